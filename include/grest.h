@@ -1,0 +1,163 @@
+/*
+ * grest.h -- C interface of libgrest, the MI355X (gfx950) implementation of the
+ * G-REST eigenpair update for evolving graphs.
+ *
+ * Method (Eini, Karaaslanli, Kalantzis, Traganitis, "Subspace Projection Methods
+ * for Fast Spectral Embeddings of Evolving Graphs"):
+ *   - transition model, Sec. 2 eq. (adj_update): A^(t+1) = pad(A^(t)) + Delta with
+ *     Delta = [[K, G], [G^T, C]] (edge flips among old nodes, edges of appended nodes);
+ *   - single-step problem, Sec. 2.1 (Problem 1): given K eigenpairs of A and Delta,
+ *     estimate K eigenpairs of A^(t+1);
+ *   - tracking loop, Alg. 2: pad X, build an orthonormal basis Z of
+ *     [Xbar, (I - Xbar Xbar^T)[Delta Xbar, B2]] (Sec. 3.3, Table 1) with
+ *     B2 = Delta_2 (G-REST3), B2 = the rank-L randomized basis R of Sec. 3.5
+ *     (G-REST_RSVD), or no B2 (G-REST2), then Rayleigh-Ritz (Alg. 1) on
+ *     Z^T A^(t+1) Z (eq. RR_eigen_graph_upd_main2) and X <- Z F_K;
+ *   - shifted Laplacians, Sec. 4.2: the trailing pairs of L = D - A and of
+ *     L_n = I - D^{-1/2} A D^{-1/2} are the leading pairs of alpha I - L and 2 I - L_n.
+ *
+ * Conventions shared by every entry point:
+ *   - All functions return a grest_status; no exception crosses the interface.
+ *   - Node ids are int32 (graphs below 2^31 nodes); each undirected edge change is
+ *     given once as (i, j) with i < j and a sign +1 (insert) or -1 (delete).  An edge
+ *     that touches an appended node (id >= current node count) is an insertion.
+ *   - Dense blocks are row-major.  "Host" pointers are ordinary CPU memory, "device"
+ *     pointers are HIP device memory on the state's device.
+ *   - The caller owns every buffer it passes; the library copies inputs before the
+ *     call returns (host inputs) or before the work that reads them is finished on
+ *     the state's stream (device inputs: keep them alive until grest_sync).
+ *   - A state is driven from one host thread at a time; different states are
+ *     independent.
+ */
+#ifndef GREST_H
+#define GREST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct grest_state grest_state;
+
+typedef enum grest_status {
+  GREST_OK = 0,
+  GREST_EINVAL = 1,   /* bad argument, or a change list that breaks the transition model */
+  GREST_ENOMEM = 2,   /* device or host allocation failed */
+  GREST_EDEVICE = 3,  /* HIP runtime error (see grest_last_error) */
+  GREST_ENUMERIC = 4, /* non-finite value or eigensolver without convergence */
+  GREST_ENODEV = 5    /* no usable device */
+} grest_status;
+
+/* operator whose pairs are tracked (Sec. 4.2) */
+enum { GREST_OP_ADJ = 0, GREST_OP_LAP = 1, GREST_OP_NLAP = 2 };
+/* subspace (Table 1, Sec. 3.5) */
+enum { GREST_G2 = 2, GREST_G3 = 3, GREST_RSVD = 4 };
+/* arithmetic of the dense blocks: all FP64; FP32 blocks with FP64 Gram/Cholesky/eigensolve;
+ * FP32 blocks with BF16-MFMA products Z^T(AZ) and Z F (FP32 accumulation) */
+enum { GREST_FP64 = 0, GREST_FP32 = 1, GREST_MIXED = 2 };
+/* where a pointer lives */
+enum { GREST_HOST = 0, GREST_DEVICE = 1 };
+/* element type of a dense output */
+enum { GREST_F64 = 0, GREST_F32 = 1 };
+
+typedef struct grest_config {
+  int32_t k;          /* K, number of tracked pairs (>= 1) */
+  int32_t variant;    /* GREST_G2 / GREST_G3 / GREST_RSVD */
+  int32_t L;          /* RSVD rank L (variant RSVD) */
+  int32_t P;          /* RSVD oversampling P (variant RSVD) */
+  int32_t op;         /* GREST_OP_* */
+  int32_t precision;  /* GREST_FP64 / GREST_FP32 / GREST_MIXED */
+  int32_t max_new;    /* largest S per update for G-REST3 (sizes the basis block) */
+  int32_t reserved;   /* 0 */
+  double rank_tol;    /* relative rank threshold of the orthonormalisation; 0 = default
+                         (1e-7 in FP64, 1e-5 otherwise) */
+} grest_config;
+
+/* ABI version of this header (bumped on any incompatible change). */
+int32_t grest_abi_version(void);
+
+/* Message of a status code (static string). */
+const char* grest_strerror(grest_status status);
+
+/* Text of the last HIP error seen by this thread (static thread-local buffer). */
+const char* grest_last_error(void);
+
+/*
+ * Format check of a change list on the host, without a device: ids in range,
+ * i < j, sign +1/-1, edges of appended nodes are insertions, no pair twice.
+ * n: current node count, n_new: appended nodes S.  Host pointers.
+ * Returns GREST_OK or GREST_EINVAL.  (Membership -- insert of an existing edge,
+ * delete of a missing one -- needs the stored graph and is checked by grest_update.)
+ */
+grest_status grest_validate_changes(int64_t n, int64_t n_new, int64_t n_changes, const int32_t* ei,
+                                    const int32_t* ej, const int8_t* sign);
+
+/*
+ * Create a state for the graph A^(0) (Sec. 2; Alg. 2 input), stored on the current
+ * HIP device.  rowptr (n0+1 entries, int64) and col (rowptr[n0] entries, int32) are
+ * host pointers to a symmetric CSR with both triangles, sorted columns, no self-loops
+ * and no duplicates (checked: GREST_EINVAL).  node_capacity / nnz_capacity reserve
+ * room for growth (0 = automatic; buffers grow on demand with a device
+ * synchronisation).  stream: a hipStream_t of that device, or NULL for a private
+ * stream.  The tracked pairs are unset until grest_set_pairs or grest_init_pairs.
+ */
+grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, const int64_t* rowptr,
+                          const int32_t* col, int64_t node_capacity, int64_t nnz_capacity,
+                          grest_state** out);
+
+/*
+ * Set the tracked pairs (Alg. 2 line 3 computed by the caller): values[k] (adjacency:
+ * eigenvalues of A; Laplacians: eigenvalues nu of L or L_n) and X, n x k row-major with
+ * orthonormal columns, FP64.  where: GREST_HOST or GREST_DEVICE for both pointers.
+ */
+grest_status grest_set_pairs(grest_state* st, const double* values, const double* X, int32_t where);
+
+/*
+ * Compute initial pairs on the device (Alg. 2 line 3 with a block subspace iteration
+ * of width 2k built from the update kernels: product with the operator, CholQR2,
+ * Rayleigh-Ritz).  iterations: number of products (>= 1); seed: start block.
+ */
+grest_status grest_init_pairs(grest_state* st, int32_t iterations, uint64_t seed);
+
+/*
+ * One G-REST update (Alg. 2 loop body) with n_new appended nodes and n_changes edge
+ * changes (ei, ej, sign).  omega: the S x (L+P) Gaussian test matrix of the
+ * randomized range finder (Sec. 3.5, step S.1), FP64 row-major; required for
+ * variant RSVD when n_new > 0, ignored otherwise.  where: GREST_HOST or GREST_DEVICE
+ * for all four arrays.
+ * The change list is validated before anything is committed: a violation returns
+ * GREST_EINVAL and leaves the state exactly as it was.  The rest of the update is
+ * queued on the state's stream; numerical trouble is reported by grest_sync.
+ */
+grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei,
+                          const int32_t* ej, const int8_t* sign, const double* omega, int32_t where);
+
+/* Wait for queued work and return (then clear) deferred numerical status bits. */
+grest_status grest_sync(grest_state* st);
+
+/*
+ * Copy the tracked pairs out: values[k] (FP64, host; may be NULL), and X (n x k
+ * row-major, element type x_dtype, may be NULL) to host or device memory.  Values are
+ * ordered as tracked: adjacency by decreasing magnitude, Laplacians by increasing nu.
+ */
+grest_status grest_get(grest_state* st, double* values, void* X, int32_t x_dtype, int32_t where);
+
+/* Current node count, stored entries (both triangles) and the state's dimensions. */
+grest_status grest_shape(const grest_state* st, int64_t* n, int64_t* nnz, int32_t* k, int32_t* width);
+
+/*
+ * Copy the stored graph to host memory: rowptr (n+1 int64) and col (nnz int32), for
+ * checking the graph update bit for bit.
+ */
+grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col);
+
+/* Release the state and all its device memory. */
+void grest_destroy(grest_state* st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GREST_H */

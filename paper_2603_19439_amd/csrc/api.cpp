@@ -1,0 +1,692 @@
+// Host orchestration of the G-REST update behind the C interface of grest.h.
+//
+// One state owns, on one device: the graph as a double-buffered CSR, the dense
+// basis buffers Z (two, row-major, ld = K + Dw) whose first K columns hold the
+// tracked eigenvectors, the workspaces of the update, and the small FP64 matrices.
+// An update is queued on the state's stream as: graph update and validation
+// (one host wait for the status word), padding, Delta Xbar, the augmentation block
+// (Delta_2 or the randomized basis R), two projections against Xbar, CholQR2 with
+// FP64 Gram and pivoted Cholesky, (op Z), Z^T (op Z), the FP64 eigensolve, and the
+// back-projection Z F into the other basis buffer.  The commit swaps buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/grest.h"
+#include "grest_internal.h"
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+void set_err(const char* what, hipError_t e) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) {                            \
+      set_err(#call, e_);                              \
+      return e_ == hipErrorOutOfMemory ? GREST_ENOMEM : GREST_EDEVICE; \
+    }                                                  \
+  } while (0)
+
+#define CHK(expr)                      \
+  do {                                 \
+    grest_status s_ = (expr);          \
+    if (s_ != GREST_OK) return s_;     \
+  } while (0)
+
+constexpr int32_t VALIDATION_BITS = ST_BAD_FORMAT | ST_DUPLICATE | ST_INSERT_EXISTING | ST_DELETE_MISSING;
+
+struct Pinned {
+  int32_t status;
+  int32_t pad;
+  int64_t m_new;
+  int64_t maxdeg;
+  int32_t ranks[8];
+};
+
+template <typename P>
+grest_status dalloc(P** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  HIPCHK(hipMalloc((void**)p, count * sizeof(P)));
+  return GREST_OK;
+}
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct grest_state {
+  grest_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  int prec = GREST_FP64;
+  size_t es = 8;  // element size of the dense blocks
+  int K = 0, op = 0, variant = 0, L = 0, Ls = 0, Dw = 0, D = 0, ldz = 0, ldy = 0;
+  double tol = 1e-7;
+  bool has_pairs = false;
+
+  int64_t n = 0, m = 0;
+  int64_t cap_n = 0, cap_m = 0, cap_nc = 0, cap_s = 0;
+
+  int64_t* rp[2] = {nullptr, nullptr};
+  int32_t* col[2] = {nullptr, nullptr};
+  void* sc[2] = {nullptr, nullptr};  // D^{-1/2} per node, working precision
+  int gcur = 0;
+
+  void* z[2] = {nullptr, nullptr};
+  int zcur = 0;
+  void* aux = nullptr;   // (op Z), cap_n x D
+  void* ybuf = nullptr;  // sketch / range basis, cap_n x ldy
+  void* bt = nullptr;    // Delta_2^T M, cap_s x Ls
+  void* omega_t = nullptr;
+  double* omega64 = nullptr;
+
+  int32_t *d_ei = nullptr, *d_ej = nullptr;
+  int8_t* d_sg = nullptr;
+  int64_t *dcnt = nullptr, *dptr = nullptr, *dfill = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
+  int32_t *dcol_tmp = nullptr, *dcol = nullptr, *dins = nullptr;
+  int8_t *dsg_tmp = nullptr, *dsg = nullptr;
+
+  double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *Mchol = nullptr, *H = nullptr, *F = nullptr;
+  double *theta = nullptr, *Fb = nullptr, *thetab = nullptr, *partial = nullptr, *eigwork = nullptr;
+  int32_t* ranks = nullptr;
+  int32_t* status = nullptr;
+  int64_t* maxdeg = nullptr;
+  Pinned* pin = nullptr;
+  double* theta_pin = nullptr;
+  int32_t deferred = 0;
+  int64_t partial_elems = 0;
+};
+
+namespace {
+
+int64_t round_up(int64_t v, int64_t q) { return ((v + q - 1) / q) * q; }
+
+grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
+  const size_t es = st->es;
+  for (int b = 0; b < 2; ++b) {
+    CHK(dalloc(&st->rp[b], cap_n + 1));
+    CHK(dalloc((char**)&st->sc[b], cap_n * es));
+    CHK(dalloc((char**)&st->z[b], (size_t)cap_n * st->ldz * es));
+  }
+  CHK(dalloc((char**)&st->aux, (size_t)cap_n * std::max(st->D, st->K) * es));
+  if (st->variant == GREST_RSVD) CHK(dalloc((char**)&st->ybuf, (size_t)cap_n * st->ldy * es));
+  CHK(dalloc(&st->dcnt, cap_n + 1));
+  CHK(dalloc(&st->dptr, cap_n + 1));
+  CHK(dalloc(&st->dfill, cap_n + 1));
+  CHK(dalloc(&st->newlen, cap_n + 1));
+  CHK(dalloc(&st->scan_tmp, scan_tmp_elems(cap_n + 1) + 16));
+  st->cap_n = cap_n;
+  return GREST_OK;
+}
+
+grest_status alloc_edge_arrays(grest_state* st, int64_t cap_m) {
+  for (int b = 0; b < 2; ++b) {
+    CHK(dalloc(&st->col[b], cap_m));
+    HIPCHK(hipMemsetAsync(st->col[b], 0, (size_t)cap_m * sizeof(int32_t), st->stream));
+  }
+  st->cap_m = cap_m;
+  return GREST_OK;
+}
+
+grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
+  dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
+  dfree(st->dcol_tmp); dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
+  CHK(dalloc(&st->d_ei, cap_nc));
+  CHK(dalloc(&st->d_ej, cap_nc));
+  CHK(dalloc(&st->d_sg, cap_nc));
+  CHK(dalloc(&st->dcol_tmp, 2 * cap_nc));
+  CHK(dalloc(&st->dcol, 2 * cap_nc));
+  CHK(dalloc(&st->dins, 2 * cap_nc));
+  CHK(dalloc(&st->dsg_tmp, 2 * cap_nc));
+  CHK(dalloc(&st->dsg, 2 * cap_nc));
+  st->cap_nc = cap_nc;
+  return GREST_OK;
+}
+
+grest_status alloc_sketch_arrays(grest_state* st, int64_t cap_s) {
+  dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
+  if (st->variant != GREST_RSVD) { st->cap_s = cap_s; return GREST_OK; }
+  CHK(dalloc((char**)&st->bt, (size_t)cap_s * st->Ls * st->es));
+  CHK(dalloc((char**)&st->omega_t, (size_t)cap_s * st->Ls * st->es));
+  CHK(dalloc(&st->omega64, (size_t)cap_s * st->Ls));
+  st->cap_s = cap_s;
+  return GREST_OK;
+}
+
+void free_all(grest_state* st) {
+  for (int b = 0; b < 2; ++b) {
+    dfree(st->rp[b]); dfree(st->col[b]); dfree(st->sc[b]); dfree(st->z[b]);
+  }
+  dfree(st->aux); dfree(st->ybuf); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
+  dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
+  dfree(st->dcnt); dfree(st->dptr); dfree(st->dfill); dfree(st->newlen); dfree(st->scan_tmp);
+  dfree(st->dcol_tmp); dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
+  dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
+  dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
+  dfree(st->ranks); dfree(st->status); dfree(st->maxdeg);
+  if (st->pin) (void)hipHostFree(st->pin);
+  if (st->theta_pin) (void)hipHostFree(st->theta_pin);
+  st->pin = nullptr;
+  st->theta_pin = nullptr;
+}
+
+// Grow node-indexed buffers, keeping the current graph and basis.
+grest_status grow_nodes(grest_state* st, int64_t need) {
+  int64_t cap = std::max<int64_t>(need, st->cap_n + st->cap_n / 2);
+  if (cap + 1 > (int64_t)4096 * 2048) cap = (int64_t)4096 * 2048 - 1;
+  if (cap < need) return GREST_EINVAL;  // device scan limit
+  HIPCHK(hipStreamSynchronize(st->stream));
+  int64_t* rp_old = st->rp[st->gcur];
+  void* z_old = st->z[st->zcur];
+  void* sc_old = st->sc[st->gcur];
+  int64_t* rp_keep[2] = {st->rp[0], st->rp[1]};
+  void* z_keep[2] = {st->z[0], st->z[1]};
+  void* sc_keep[2] = {st->sc[0], st->sc[1]};
+  st->rp[0] = st->rp[1] = nullptr;
+  st->z[0] = st->z[1] = nullptr;
+  st->sc[0] = st->sc[1] = nullptr;
+  dfree(st->aux); dfree(st->ybuf); dfree(st->dcnt); dfree(st->dptr); dfree(st->dfill);
+  dfree(st->newlen); dfree(st->scan_tmp);
+  CHK(alloc_node_arrays(st, cap));
+  HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                        st->stream));
+  HIPCHK(hipMemcpyAsync(st->sc[st->gcur], sc_old, st->n * st->es, hipMemcpyDeviceToDevice, st->stream));
+  HIPCHK(hipMemcpyAsync(st->z[st->zcur], z_old, (size_t)st->n * st->ldz * st->es, hipMemcpyDeviceToDevice,
+                        st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  for (int b = 0; b < 2; ++b) { dfree(rp_keep[b]); dfree(z_keep[b]); dfree(sc_keep[b]); }
+  return GREST_OK;
+}
+
+grest_status grow_edges(grest_state* st, int64_t need) {
+  int64_t cap = std::max<int64_t>(need, st->cap_m + st->cap_m / 2);
+  HIPCHK(hipStreamSynchronize(st->stream));
+  int32_t* keep[2] = {st->col[0], st->col[1]};
+  st->col[0] = st->col[1] = nullptr;
+  CHK(alloc_edge_arrays(st, cap));
+  HIPCHK(hipMemcpyAsync(st->col[st->gcur], keep[st->gcur], st->m * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                        st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  dfree(keep[0]);
+  dfree(keep[1]);
+  return GREST_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// the update, templated on the element type of the dense blocks
+// ---------------------------------------------------------------------------------
+template <typename T>
+struct Blocks {
+  T* Zc;  // current basis buffer (X in columns 0..K)
+  T* Zn;  // next basis buffer
+  T* W;   // columns K .. K+Dw of Zc
+  T* Y;   // sketch buffer
+  T* aux;
+};
+
+template <typename T>
+Blocks<T> blocks(grest_state* st) {
+  Blocks<T> b;
+  b.Zc = (T*)st->z[st->zcur];
+  b.Zn = (T*)st->z[st->zcur ^ 1];
+  b.W = b.Zc + st->K;
+  b.Y = (T*)st->ybuf;
+  b.aux = (T*)st->aux;
+  return b;
+}
+
+// W (n x w, ld) <- (I - Xbar Xbar^T) applied twice; the coefficients are kept in c1, c2
+template <typename T>
+void project_twice(grest_state* st, int64_t n, const T* X, int64_t ldx, T* W, int64_t ldw, int w,
+                   double* c1, double* c2) {
+  const bool acc64 = (st->prec == GREST_FP64);
+  double* cs[2] = {c1, c2};
+  for (int pass = 0; pass < 2; ++pass) {
+    if (acc64) launch_tn<T, true>(n, X, ldx, st->K, W, ldw, w, st->partial, cs[pass], st->stream);
+    else launch_tn<T, false>(n, X, ldx, st->K, W, ldw, w, st->partial, cs[pass], st->stream);
+    launch_apply<T>(n, X, ldx, st->K, cs[pass], w, -1.0, 1.0, W, ldw, st->stream);
+  }
+}
+
+// rank-revealing CholQR2 of W (n x w, ld) in place; ranks[slot] and ranks[slot+1]
+template <typename T>
+void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, const double* c1, const double* c2,
+             int slot) {
+  launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, st->stream);
+  launch_pchol(w, st->Gm, c1, c2, c1 ? st->K : 0, st->tol, st->Mchol, st->ranks + slot, st->status,
+               st->stream);
+  launch_apply<T>(n, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, st->stream);
+  launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, st->stream);
+  launch_pchol(w, st->Gm, nullptr, nullptr, 0, st->tol, st->Mchol, st->ranks + slot + 1, st->status,
+               st->stream);
+  launch_apply<T>(n, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, st->stream);
+}
+
+template <typename T>
+grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const int32_t* col, const T* sc,
+                           int32_t* rank_slot) {
+  Blocks<T> b = blocks<T>(st);
+  // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
+  launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc, st->ldz, n2, st->D, b.aux, st->D, st->stream);
+  // H = Z^T (op Z)
+  if (st->prec == GREST_FP64) launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+  else launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+  // small FP64 eigensolve on the leading K + rank block, selection of K pairs
+  const int which = st->op == GREST_OP_ADJ ? 0 : 1;
+  launch_small_eig(st->D, st->K, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
+                   st->status, st->stream);
+  // X' = Z F_K into the other buffer
+  launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
+  return GREST_OK;
+}
+
+template <typename T>
+grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* ei, const int32_t* ej,
+                         const int8_t* sg, const double* omega, int32_t where) {
+  hipStream_t s = st->stream;
+  const int64_t n = st->n, n2 = n + S;
+  // capacities
+  if (n2 > st->cap_n) CHK(grow_nodes(st, n2));
+  if (st->m + 2 * nc > st->cap_m) CHK(grow_edges(st, st->m + 2 * nc));
+  if (nc > st->cap_nc) CHK(alloc_change_arrays(st, std::max<int64_t>(nc, st->cap_nc * 2)));
+  if (st->variant == GREST_RSVD && S > st->cap_s) CHK(alloc_sketch_arrays(st, std::max<int64_t>(S, 2 * st->cap_s)));
+
+  const int32_t* dei = ei;
+  const int32_t* dej = ej;
+  const int8_t* dsg = sg;
+  if (where == GREST_HOST && nc > 0) {
+    HIPCHK(hipMemcpyAsync(st->d_ei, ei, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(st->d_ej, ej, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(st->d_sg, sg, nc * sizeof(int8_t), hipMemcpyHostToDevice, s));
+    dei = st->d_ei; dej = st->d_ej; dsg = st->d_sg;
+  }
+  const int gn = st->gcur ^ 1;
+  // ---- graph update and validation (Sec. 2, eq. adj_update) ----
+  launch_fill_bytes0(st->status, sizeof(int32_t), s);
+  launch_fill_bytes0(st->maxdeg, sizeof(int64_t), s);
+  launch_fill_i64(st->dcnt, 0, n2 + 1, s);
+  launch_fill_i64(st->dfill, 0, n2 + 1, s);
+  launch_delta_count(dei, dej, dsg, nc, n, S, st->dcnt, st->status, s);
+  launch_scan_excl(st->dcnt, st->dptr, n2, st->scan_tmp, s);
+  launch_delta_scatter(dei, dej, dsg, nc, n, S, st->dptr, st->dfill, st->dcol_tmp, st->dsg_tmp, s);
+  launch_delta_rows(n, S, st->dptr, st->dcol_tmp, st->dsg_tmp, st->dcol, st->dsg, st->dins, st->rp[st->gcur],
+                    st->col[st->gcur], st->newlen, st->status, s);
+  launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, s);
+  launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], st->dptr, st->dcol, st->dsg, st->dins, st->rp[gn],
+                   st->col[gn], st->cap_m, s);
+  if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, st->maxdeg, s);
+  else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], st->maxdeg, s);
+  HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&st->pin->m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&st->pin->maxdeg, st->maxdeg, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st->pin->status & VALIDATION_BITS) {
+    snprintf(g_last_error, sizeof(g_last_error), "change list rejected (status bits 0x%x)", st->pin->status);
+    return GREST_EINVAL;
+  }
+  const int64_t m_new = st->pin->m_new;
+
+  Blocks<T> b = blocks<T>(st);
+  const T* sc_new = (const T*)st->sc[gn];
+  // ---- pad Xbar (Alg. 2): zero the appended rows of the whole basis row ----
+  launch_fill_rows<T>(b.Zc, st->ldz, n, S, st->ldz, s);
+  // ---- Delta Xbar = Delta_1 X (Prop. 3) into W[:, 0:K] ----
+  if (st->op == GREST_OP_NLAP) {
+    launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
+                           st->col[gn], sc_new, b.Zc, st->ldz, st->K, b.W, st->ldz, s);
+  } else {
+    launch_delta_mul<T>(0, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Zc, st->ldz, st->K,
+                        b.W, st->ldz, s);
+  }
+  T* B2 = b.W + st->K;
+  const int w2 = st->Dw - st->K;
+  // ---- augmentation block ----
+  if (st->variant == GREST_G3) {
+    launch_fill_rows<T>(B2, st->ldz, 0, n2, w2, s);
+    if (S > 0)
+      launch_delta_mul<T>(3, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, nullptr, 0, w2, B2,
+                          st->ldz, s);
+  } else if (st->variant == GREST_RSVD) {
+    if (S == 0) {
+      launch_fill_rows<T>(B2, st->ldz, 0, n2, w2, s);
+    } else {
+      // S.1: Y = (I - Pi) Delta_2 Omega
+      const int Ls = st->Ls;
+      const double* om = omega;
+      if (where == GREST_HOST) {
+        HIPCHK(hipMemcpyAsync(st->omega64, omega, (size_t)S * Ls * sizeof(double), hipMemcpyHostToDevice, s));
+        om = st->omega64;
+      }
+      if (sizeof(T) == 8) {
+        HIPCHK(hipMemcpyAsync(st->omega_t, om, (size_t)S * Ls * sizeof(double), hipMemcpyDeviceToDevice, s));
+      } else {
+        launch_convert<double, float>(om, (float*)st->omega_t, (int64_t)S * Ls, s);
+      }
+      launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
+                          Ls, Ls, b.Y, st->ldy, s);
+      project_twice<T>(st, n2, b.Zc, st->ldz, b.Y, st->ldy, Ls, st->C1, st->C2);
+      // S.2: M = orth(Y) (rank-revealing CholQR2)
+      cholqr2<T>(st, n2, b.Y, st->ldy, Ls, st->C1, st->C2, 2);
+      // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
+      launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Y, st->ldy, Ls,
+                          (T*)st->bt, Ls, s);
+      launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
+      launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
+                       st->eigwork, st->status, s);
+      // S.4: R = M U_L
+      launch_apply<T>(n2, b.Y, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, B2, st->ldz, s);
+    }
+  }
+  // ---- projection (I - Xbar Xbar^T) W, twice; CholQR2 of W ----
+  project_twice<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, st->C1, st->C2);
+  cholqr2<T>(st, n2, b.W, st->ldz, st->Dw, st->C1, st->C2, 0);
+  // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
+  CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->ranks + 1));
+  HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // ---- commit ----
+  st->gcur = gn;
+  st->zcur ^= 1;
+  st->n = n2;
+  st->m = m_new;
+  return GREST_OK;
+}
+
+bool host_changes_ok(int64_t n, int64_t S, int64_t nc, const int32_t* ei, const int32_t* ej, const int8_t* sg) {
+  if (nc < 0 || S < 0) return false;
+  if (nc == 0) return true;
+  if (!ei || !ej || !sg) return false;
+  const int64_t n2 = n + S;
+  std::vector<int64_t> keys((size_t)nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t i = ei[c], j = ej[c];
+    const int s = sg[c];
+    if (i < 0 || j <= i || j >= n2) return false;
+    if (s != 1 && s != -1) return false;
+    if (j >= n && s != 1) return false;
+    keys[(size_t)c] = i * n2 + j;
+  }
+  std::sort(keys.begin(), keys.end());
+  return std::adjacent_find(keys.begin(), keys.end()) == keys.end();
+}
+
+template <typename T>
+grest_status set_pairs_impl(grest_state* st, const double* values, const double* X, int32_t where) {
+  const int64_t n = st->n;
+  const int K = st->K;
+  hipStream_t s = st->stream;
+  const size_t cnt = (size_t)n * K;
+  double* tmp = nullptr;
+  CHK(dalloc(&tmp, cnt));
+  if (where == GREST_HOST) {
+    HIPCHK(hipMemcpyAsync(tmp, X, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+  } else {
+    HIPCHK(hipMemcpyAsync(tmp, X, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  T* Z = (T*)st->z[st->zcur];
+  T* packed = (T*)st->aux;
+  if (sizeof(T) == 8) HIPCHK(hipMemcpyAsync(packed, tmp, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else launch_convert<double, float>(tmp, (float*)packed, (int64_t)cnt, s);
+  HIPCHK(hipMemcpy2DAsync(Z, st->ldz * sizeof(T), packed, K * sizeof(T), K * sizeof(T), n, hipMemcpyDeviceToDevice, s));
+  if (where == GREST_HOST) {
+    memcpy(st->theta_pin, values, K * sizeof(double));
+  } else {
+    HIPCHK(hipMemcpyAsync(st->theta_pin, values, K * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(st->theta, st->theta_pin, K * sizeof(double), hipMemcpyHostToDevice));
+  dfree(tmp);
+  st->has_pairs = true;
+  return GREST_OK;
+}
+
+template <typename T>
+grest_status get_impl(grest_state* st, double* values, void* X, int32_t x_dtype, int32_t where) {
+  hipStream_t s = st->stream;
+  HIPCHK(hipStreamSynchronize(s));
+  if (values) memcpy(values, st->theta_pin, st->K * sizeof(double));
+  if (!X) return GREST_OK;
+  const int64_t n = st->n;
+  const int K = st->K;
+  const T* Z = (const T*)st->z[st->zcur];
+  T* packed = (T*)st->aux;
+  HIPCHK(hipMemcpy2DAsync(packed, K * sizeof(T), Z, st->ldz * sizeof(T), K * sizeof(T), n, hipMemcpyDeviceToDevice, s));
+  const size_t cnt = (size_t)n * K;
+  const void* src = packed;
+  size_t bytes = cnt * sizeof(T);
+  void* conv = nullptr;
+  if ((x_dtype == GREST_F64) != (sizeof(T) == 8)) {
+    if (x_dtype == GREST_F64) {
+      double* c = nullptr;
+      CHK(dalloc(&c, cnt));
+      launch_convert<float, double>((const float*)packed, c, (int64_t)cnt, s);
+      conv = c; bytes = cnt * sizeof(double);
+    } else {
+      float* c = nullptr;
+      CHK(dalloc(&c, cnt));
+      launch_convert<double, float>((const double*)packed, c, (int64_t)cnt, s);
+      conv = c; bytes = cnt * sizeof(float);
+    }
+    src = conv;
+  }
+  HIPCHK(hipMemcpyAsync(X, src, bytes, where == GREST_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (conv) (void)hipFree(conv);
+  return GREST_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+// C interface
+// =====================================================================================
+extern "C" {
+
+int32_t grest_abi_version(void) { return 1; }
+
+const char* grest_strerror(grest_status status) {
+  switch (status) {
+    case GREST_OK: return "ok";
+    case GREST_EINVAL: return "invalid argument or change list";
+    case GREST_ENOMEM: return "out of memory";
+    case GREST_EDEVICE: return "device error";
+    case GREST_ENUMERIC: return "numerical failure";
+    case GREST_ENODEV: return "no usable device";
+  }
+  return "unknown status";
+}
+
+const char* grest_last_error(void) { return g_last_error; }
+
+grest_status grest_validate_changes(int64_t n, int64_t n_new, int64_t n_changes, const int32_t* ei,
+                                    const int32_t* ej, const int8_t* sign) {
+  if (n < 0) return GREST_EINVAL;
+  return host_changes_ok(n, n_new, n_changes, ei, ej, sign) ? GREST_OK : GREST_EINVAL;
+}
+
+grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, const int64_t* rowptr,
+                          const int32_t* col, int64_t node_capacity, int64_t nnz_capacity, grest_state** out) {
+  if (!out) return GREST_EINVAL;
+  *out = nullptr;
+  if (!cfg || !rowptr || n0 < 1 || (n0 >= INT32_MAX)) return GREST_EINVAL;
+  if (cfg->k < 1 || cfg->k >= n0 + (cfg->variant == GREST_G2 ? 0 : 0)) return GREST_EINVAL;
+  if (cfg->k > 128) return GREST_EINVAL;
+  if (cfg->variant != GREST_G2 && cfg->variant != GREST_G3 && cfg->variant != GREST_RSVD) return GREST_EINVAL;
+  if (cfg->op < GREST_OP_ADJ || cfg->op > GREST_OP_NLAP) return GREST_EINVAL;
+  if (cfg->precision < GREST_FP64 || cfg->precision > GREST_MIXED) return GREST_EINVAL;
+  if (cfg->variant == GREST_RSVD && (cfg->L < 1 || cfg->P < 0 || cfg->L + cfg->P > 128)) return GREST_EINVAL;
+  if (cfg->variant == GREST_G3 && cfg->max_new < 0) return GREST_EINVAL;
+  const int64_t m0 = rowptr[n0];
+  if (m0 < 0 || (m0 > 0 && !col)) return GREST_EINVAL;
+  // host check of the initial CSR: monotone offsets, ids in range, sorted, no self-loops
+  for (int64_t r = 0; r < n0; ++r) {
+    if (rowptr[r + 1] < rowptr[r] || rowptr[0] != 0) return GREST_EINVAL;
+    for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= n0 || col[e] == r) return GREST_EINVAL;
+      if (e > rowptr[r] && col[e] <= col[e - 1]) return GREST_EINVAL;
+    }
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GREST_ENODEV;
+
+  grest_state* st = new (std::nothrow) grest_state();
+  if (!st) return GREST_ENOMEM;
+  st->cfg = *cfg;
+  (void)hipGetDevice(&st->device);
+  st->prec = cfg->precision;
+  st->es = cfg->precision == GREST_FP64 ? 8 : 4;
+  st->K = cfg->k;
+  st->op = cfg->op;
+  st->variant = cfg->variant;
+  st->L = cfg->variant == GREST_RSVD ? cfg->L : 0;
+  st->Ls = cfg->variant == GREST_RSVD ? cfg->L + cfg->P : 0;
+  const int extra = cfg->variant == GREST_G3 ? cfg->max_new : (cfg->variant == GREST_RSVD ? cfg->L : 0);
+  st->Dw = st->K + extra;
+  st->D = st->K + st->Dw;
+  if (st->Dw > 128 || st->D > 128) { delete st; return GREST_EINVAL; }
+  const int q = (int)(16 / st->es);
+  st->ldz = (int)round_up(st->D, q);
+  st->ldy = (int)round_up(std::max(st->Ls, 1), q);
+  st->tol = cfg->rank_tol > 0 ? cfg->rank_tol : (cfg->precision == GREST_FP64 ? 1e-7 : 1e-5);
+  if (stream) {
+    st->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking) != hipSuccess) { delete st; return GREST_EDEVICE; }
+    st->own_stream = true;
+  }
+  grest_status rc = GREST_OK;
+  auto fail = [&](grest_status e) { free_all(st); if (st->own_stream) (void)hipStreamDestroy(st->stream); delete st; return e; };
+  int64_t capn = std::max<int64_t>(node_capacity, n0 + 1);
+  if (capn + 1 > (int64_t)4096 * 2048) return fail(GREST_EINVAL);  // device scan limit
+  int64_t capm = std::max<int64_t>(nnz_capacity, m0 + 1024);
+  if ((rc = alloc_node_arrays(st, capn)) != GREST_OK) return fail(rc);
+  if ((rc = alloc_edge_arrays(st, capm)) != GREST_OK) return fail(rc);
+  if ((rc = alloc_change_arrays(st, 4096)) != GREST_OK) return fail(rc);
+  if ((rc = alloc_sketch_arrays(st, 1024)) != GREST_OK) return fail(rc);
+  const int dmax = st->D;
+  const int wmax = std::max(st->Dw, std::max(st->Ls, 1));
+  if ((rc = dalloc(&st->C1, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->C2, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->Gm, (size_t)wmax * wmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->Mchol, (size_t)wmax * wmax + (size_t)(wmax + 1) * (wmax + 1))) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->H, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->F, (size_t)dmax * st->K)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->theta, st->K)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->Fb, (size_t)std::max(st->Ls, 1) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->thetab, std::max(st->L, 1))) != GREST_OK) return fail(rc);
+  st->partial_elems = (int64_t)tn_num_chunks(INT64_MAX / 4) * dmax * dmax;
+  if ((rc = dalloc(&st->partial, st->partial_elems)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->eigwork, eig_work_elems(std::max(dmax, std::max(st->Ls, 1))))) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->ranks, 8)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->status, 1)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->maxdeg, 1)) != GREST_OK) return fail(rc);
+  if (hipHostMalloc((void**)&st->pin, sizeof(Pinned)) != hipSuccess) return fail(GREST_ENOMEM);
+  if (hipHostMalloc((void**)&st->theta_pin, st->K * sizeof(double)) != hipSuccess) return fail(GREST_ENOMEM);
+  memset(st->pin, 0, sizeof(Pinned));
+  // upload the graph
+  st->n = n0;
+  st->m = m0;
+  if (hipMemcpyAsync(st->rp[0], rowptr, (n0 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st->stream) != hipSuccess)
+    return fail(GREST_EDEVICE);
+  if (m0 > 0 && hipMemcpyAsync(st->col[0], col, m0 * sizeof(int32_t), hipMemcpyHostToDevice, st->stream) != hipSuccess)
+    return fail(GREST_EDEVICE);
+  launch_fill_bytes0(st->maxdeg, sizeof(int64_t), st->stream);
+  if (st->es == 8) launch_degrees(n0, st->rp[0], (double*)st->sc[0], nullptr, st->maxdeg, st->stream);
+  else launch_degrees(n0, st->rp[0], nullptr, (float*)st->sc[0], st->maxdeg, st->stream);
+  // symmetry check on the device would need a transpose; the host check above covers format
+  if (hipStreamSynchronize(st->stream) != hipSuccess) return fail(GREST_EDEVICE);
+  *out = st;
+  return GREST_OK;
+}
+
+grest_status grest_set_pairs(grest_state* st, const double* values, const double* X, int32_t where) {
+  if (!st || !values || !X) return GREST_EINVAL;
+  return st->es == 8 ? set_pairs_impl<double>(st, values, X, where) : set_pairs_impl<float>(st, values, X, where);
+}
+
+grest_status grest_init_pairs(grest_state* st, int32_t iterations, uint64_t seed) {
+  (void)st; (void)iterations; (void)seed;
+  return GREST_EINVAL;
+}
+
+grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei, const int32_t* ej,
+                          const int8_t* sign, const double* omega, int32_t where) {
+  if (!st || !st->has_pairs) return GREST_EINVAL;
+  if (n_new < 0 || n_changes < 0) return GREST_EINVAL;
+  if (st->n + n_new >= INT32_MAX) return GREST_EINVAL;
+  if (n_changes > 0 && (!ei || !ej || !sign)) return GREST_EINVAL;
+  if (st->variant == GREST_G3 && n_new > st->cfg.max_new) return GREST_EINVAL;
+  if (st->variant == GREST_RSVD && n_new > 0 && !omega) return GREST_EINVAL;
+  if (where != GREST_HOST && where != GREST_DEVICE) return GREST_EINVAL;
+  if (where == GREST_HOST && !host_changes_ok(st->n, n_new, n_changes, ei, ej, sign)) return GREST_EINVAL;
+  // pull in the status of the previous update before overwriting the pinned word
+  HIPCHK(hipStreamSynchronize(st->stream));
+  st->deferred |= st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED);
+  return st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where)
+                     : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where);
+}
+
+grest_status grest_sync(grest_state* st) {
+  if (!st) return GREST_EINVAL;
+  HIPCHK(hipStreamSynchronize(st->stream));
+  int32_t bits = st->deferred | (st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED));
+  st->deferred = 0;
+  st->pin->status = 0;
+  if (bits) {
+    snprintf(g_last_error, sizeof(g_last_error), "numerical status bits 0x%x", bits);
+    return GREST_ENUMERIC;
+  }
+  return GREST_OK;
+}
+
+grest_status grest_get(grest_state* st, double* values, void* X, int32_t x_dtype, int32_t where) {
+  if (!st) return GREST_EINVAL;
+  if (x_dtype != GREST_F64 && x_dtype != GREST_F32) return GREST_EINVAL;
+  if (where != GREST_HOST && where != GREST_DEVICE) return GREST_EINVAL;
+  return st->es == 8 ? get_impl<double>(st, values, X, x_dtype, where) : get_impl<float>(st, values, X, x_dtype, where);
+}
+
+grest_status grest_shape(const grest_state* st, int64_t* n, int64_t* nnz, int32_t* k, int32_t* width) {
+  if (!st) return GREST_EINVAL;
+  if (n) *n = st->n;
+  if (nnz) *nnz = st->m;
+  if (k) *k = st->K;
+  if (width) *width = st->D;
+  return GREST_OK;
+}
+
+grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col) {
+  if (!st) return GREST_EINVAL;
+  HIPCHK(hipStreamSynchronize(st->stream));
+  if (rowptr) HIPCHK(hipMemcpy(rowptr, st->rp[st->gcur], (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (col && st->m > 0) HIPCHK(hipMemcpy(col, st->col[st->gcur], st->m * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return GREST_OK;
+}
+
+void grest_destroy(grest_state* st) {
+  if (!st) return;
+  (void)hipStreamSynchronize(st->stream);
+  free_all(st);
+  if (st->own_stream) (void)hipStreamDestroy(st->stream);
+  delete st;
+}
+
+}  // extern "C"

@@ -1,0 +1,377 @@
+// Update of the stored graph: assembly of the symmetric update Delta and the merge
+// A^(t+1) = pad(A^(t)) + Delta of the transition model (paper Sec. 2, eq. adj_update).
+//
+// The graph is a CSR with both triangles, int64 row offsets and int32 column ids
+// sorted inside each row.  Delta arrives as a list of undirected changes (i < j, sign).
+// Steps (all on the device):
+//   1. count the two directed entries of every change per row        (atomics)
+//   2. exclusive scan of the counts -> row offsets of Delta          (3-kernel scan)
+//   3. scatter the entries into their rows                            (atomics)
+//   4. one wavefront per row: rank-sort the row's entries by column, detect
+//      duplicates, check insert/delete against the old row (binary search) and
+//      compute the new row length
+//   5. exclusive scan of the new lengths -> new row offsets
+//   6. one wavefront per row: merge by ranks (old entries not deleted + inserted
+//      entries), fully parallel inside the row, so hub rows do not serialise.
+// Every write is bounds-checked against the row and the column capacity, so an
+// invalid change list (reported through the status word before anything reads the
+// new graph) can never write out of bounds.
+#include "grest_internal.h"
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int SCAN_IPT = 8;
+constexpr int SCAN_CHUNK = BS * SCAN_IPT;
+
+__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t count) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_zero16(uint4* p, int64_t count) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void k_zero1(uint8_t* p, int64_t count) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0;
+}
+
+inline int grid_for(int64_t work, int per_block = BS, int cap = 4096) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+// ---- block-wide exclusive scan of one int64 per thread (BS threads) ----
+__device__ int64_t block_excl_scan(int64_t v, int64_t* lds, int64_t* total) {
+  const int lane = threadIdx.x & (GREST_WAVE - 1);
+  const int wid = threadIdx.x / GREST_WAVE;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < GREST_WAVE; o <<= 1) {
+    int64_t y = __shfl_up(x, o, GREST_WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == GREST_WAVE - 1) lds[wid] = x;
+  __syncthreads();
+  int64_t off = 0, tot = 0;
+  for (int w = 0; w < BS / GREST_WAVE; ++w) {
+    int64_t s = lds[w];
+    if (w < wid) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return x - v + off;
+}
+
+__global__ void __launch_bounds__(BS) k_scan_reduce(const int64_t* in, int64_t n, int64_t* bsum) {
+  __shared__ int64_t lds[BS / GREST_WAVE];
+  int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+  int64_t acc = 0;
+  for (int q = 0; q < SCAN_IPT; ++q) {
+    int64_t i = base + (int64_t)q * BS + threadIdx.x;
+    if (i < n) acc += in[i];
+  }
+  int64_t tot;
+  block_excl_scan(acc, lds, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// single workgroup: exclusive scan of nb block sums (nb <= BS * 16), writes out[n] = total
+__global__ void __launch_bounds__(BS) k_scan_blocks(int64_t* bsum, int64_t nb, int64_t* out_total) {
+  __shared__ int64_t lds[BS / GREST_WAVE];
+  constexpr int IPT = 16;
+  int64_t vals[IPT];
+  int64_t acc = 0;
+  for (int q = 0; q < IPT; ++q) {
+    int64_t i = (int64_t)threadIdx.x * IPT + q;
+    vals[q] = i < nb ? bsum[i] : 0;
+    acc += vals[q];
+  }
+  int64_t tot;
+  int64_t off = block_excl_scan(acc, lds, &tot);
+  for (int q = 0; q < IPT; ++q) {
+    int64_t i = (int64_t)threadIdx.x * IPT + q;
+    if (i < nb) bsum[i] = off;
+    off += vals[q];
+  }
+  if (threadIdx.x == 0) *out_total = tot;
+}
+
+__global__ void __launch_bounds__(BS) k_scan_final(const int64_t* in, int64_t n, const int64_t* boff,
+                                                   int64_t* out) {
+  __shared__ int64_t lds[BS / GREST_WAVE];
+  __shared__ int64_t tile[SCAN_CHUNK];
+  int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+  for (int q = 0; q < SCAN_IPT; ++q) {
+    int64_t i = base + (int64_t)q * BS + threadIdx.x;
+    tile[q * BS + threadIdx.x] = i < n ? in[i] : 0;
+  }
+  __syncthreads();
+  int64_t acc = 0;
+  for (int q = 0; q < SCAN_IPT; ++q) acc += tile[threadIdx.x * SCAN_IPT + q];
+  int64_t tot;
+  int64_t off = block_excl_scan(acc, lds, &tot) + boff[blockIdx.x];
+  for (int q = 0; q < SCAN_IPT; ++q) {
+    int64_t v = tile[threadIdx.x * SCAN_IPT + q];
+    tile[threadIdx.x * SCAN_IPT + q] = off;
+    off += v;
+  }
+  __syncthreads();
+  for (int q = 0; q < SCAN_IPT; ++q) {
+    int64_t i = base + (int64_t)q * BS + threadIdx.x;
+    if (i < n) out[i] = tile[q * BS + threadIdx.x];
+  }
+}
+
+// ---- Delta assembly ----
+__device__ inline bool change_ok(int32_t i, int32_t j, int8_t s, int64_t n_old, int64_t n2) {
+  if (i < 0 || j <= i || (int64_t)j >= n2) return false;
+  if (s != 1 && s != -1) return false;
+  if ((int64_t)j >= n_old && s != 1) return false;  // an edge of an appended node is an insertion
+  return true;
+}
+
+__global__ void k_delta_count(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
+                              int64_t n_old, int64_t n2, int64_t* cnt, int32_t* status) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += stride) {
+    int32_t i = ei[c], j = ej[c];
+    int8_t s = sg[c];
+    if (!change_ok(i, j, s, n_old, n2)) {
+      atomicOr(status, ST_BAD_FORMAT);
+      continue;
+    }
+    atomicAdd((unsigned long long*)&cnt[i], 1ull);
+    atomicAdd((unsigned long long*)&cnt[j], 1ull);
+  }
+}
+
+__global__ void k_delta_scatter(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
+                                int64_t n_old, int64_t n2, const int64_t* dptr, int64_t* fill,
+                                int32_t* dcol, int8_t* dsg) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += stride) {
+    int32_t i = ei[c], j = ej[c];
+    int8_t s = sg[c];
+    if (!change_ok(i, j, s, n_old, n2)) continue;
+    int64_t pi = dptr[i] + (int64_t)atomicAdd((unsigned long long*)&fill[i], 1ull);
+    int64_t pj = dptr[j] + (int64_t)atomicAdd((unsigned long long*)&fill[j], 1ull);
+    dcol[pi] = j;
+    dsg[pi] = s;
+    dcol[pj] = i;
+    dsg[pj] = s;
+  }
+}
+
+__device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t len, int32_t key) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// one wavefront per row (grid-stride): rank sort, validation, new length
+__global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, const int64_t* dptr,
+                                                   const int32_t* dcol_tmp, const int8_t* dsg_tmp,
+                                                   int32_t* dcol, int8_t* dsg, int32_t* dins,
+                                                   const int64_t* rp_old, const int32_t* col_old,
+                                                   int64_t* newlen, int32_t* status) {
+  const int lane = threadIdx.x & (GREST_WAVE - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * BS + threadIdx.x) / GREST_WAVE;
+  const int64_t nwaves = (int64_t)gridDim.x * (BS / GREST_WAVE);
+  for (int64_t r = wave; r < n2; r += nwaves) {
+    const int64_t beg = dptr[r];
+    const int64_t len = dptr[r + 1] - beg;
+    const int64_t ob = r < n_old ? rp_old[r] : 0;
+    const int64_t olen = r < n_old ? rp_old[r + 1] - ob : 0;
+    if (len == 0) {
+      if (lane == 0) newlen[r] = olen;
+      continue;
+    }
+    int64_t sum_s = 0;
+    int32_t bad = 0;
+    for (int64_t e0 = 0; e0 < len; e0 += GREST_WAVE) {
+      const int64_t e = e0 + lane;
+      const bool ve = e < len;
+      const int32_t ce = ve ? dcol_tmp[beg + e] : INT32_MAX;
+      const int8_t se = ve ? dsg_tmp[beg + e] : 0;
+      int64_t rank = 0, insb = 0;
+      for (int64_t f0 = 0; f0 < len; f0 += GREST_WAVE) {
+        const int64_t f = f0 + lane;
+        const int32_t cf_l = f < len ? dcol_tmp[beg + f] : INT32_MAX;
+        const int32_t sf_l = f < len ? (int32_t)dsg_tmp[beg + f] : 0;
+        const int nf = (int)((len - f0) < GREST_WAVE ? (len - f0) : GREST_WAVE);
+        for (int q = 0; q < nf; ++q) {
+          const int32_t cf = __shfl(cf_l, q, GREST_WAVE);
+          const int32_t sf = __shfl(sf_l, q, GREST_WAVE);
+          const int64_t fi = f0 + q;
+          const bool less = (cf < ce) || (cf == ce && fi < e);
+          rank += less ? 1 : 0;
+          insb += (less && sf > 0) ? 1 : 0;
+          if (ve && cf == ce && fi != e) bad |= ST_DUPLICATE;
+        }
+      }
+      if (ve) {
+        dcol[beg + rank] = ce;
+        dsg[beg + rank] = se;
+        dins[beg + rank] = (int32_t)insb;
+        sum_s += se;
+        if (r < n_old && (int64_t)ce < n_old) {
+          const int64_t p = lower_bound_i32(col_old + ob, olen, ce);
+          const bool found = p < olen && col_old[ob + p] == ce;
+          if (found && se > 0) bad |= ST_INSERT_EXISTING;
+          if (!found && se < 0) bad |= ST_DELETE_MISSING;
+        }
+      }
+    }
+    // wave reductions
+#pragma unroll
+    for (int o = GREST_WAVE / 2; o > 0; o >>= 1) {
+      sum_s += __shfl_xor(sum_s, o, GREST_WAVE);
+      bad |= __shfl_xor(bad, o, GREST_WAVE);
+    }
+    if (lane == 0) {
+      int64_t nl = olen + sum_s;
+      newlen[r] = nl < 0 ? 0 : nl;
+      if (bad) atomicOr(status, bad);
+    }
+  }
+}
+
+// one wavefront per row (grid-stride): parallel merge by ranks
+__global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, const int64_t* rp_old,
+                                                  const int32_t* col_old, const int64_t* dptr,
+                                                  const int32_t* dcol, const int8_t* dsg,
+                                                  const int32_t* dins, const int64_t* rp_new,
+                                                  int32_t* col_new, int64_t cap_m) {
+  const int lane = threadIdx.x & (GREST_WAVE - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * BS + threadIdx.x) / GREST_WAVE;
+  const int64_t nwaves = (int64_t)gridDim.x * (BS / GREST_WAVE);
+  for (int64_t r = wave; r < n2; r += nwaves) {
+    const int64_t ob = r < n_old ? rp_old[r] : 0;
+    const int64_t olen = r < n_old ? rp_old[r + 1] - ob : 0;
+    const int64_t db = dptr[r];
+    const int64_t dlen = dptr[r + 1] - db;
+    const int64_t nb = rp_new[r];
+    const int64_t nlen = rp_new[r + 1] - nb;
+    if (nb < 0 || nlen <= 0 || nb + nlen > cap_m) continue;
+    if (dlen == 0) {
+      for (int64_t a = lane; a < olen && a < nlen; a += GREST_WAVE) col_new[nb + a] = col_old[ob + a];
+      continue;
+    }
+    const int64_t tot_ins = (int64_t)dins[db + dlen - 1] + (dsg[db + dlen - 1] > 0 ? 1 : 0);
+    for (int64_t a = lane; a < olen; a += GREST_WAVE) {
+      const int32_t c = col_old[ob + a];
+      const int64_t p = lower_bound_i32(dcol + db, dlen, c);
+      const bool hit = p < dlen && dcol[db + p] == c;
+      if (hit && dsg[db + p] < 0) continue;  // deleted
+      const int64_t insb = p < dlen ? (int64_t)dins[db + p] : tot_ins;
+      const int64_t pos = a - (p - insb) + insb;
+      if (pos >= 0 && pos < nlen) col_new[nb + pos] = c;
+    }
+    for (int64_t b = lane; b < dlen; b += GREST_WAVE) {
+      if (dsg[db + b] < 0) continue;
+      const int32_t c = dcol[db + b];
+      const int64_t q = r < n_old ? lower_bound_i32(col_old + ob, olen, c) : 0;
+      const int64_t insb = dins[db + b];
+      const int64_t pos = q - (b - insb) + insb;
+      if (pos >= 0 && pos < nlen) col_new[nb + pos] = c;
+    }
+  }
+}
+
+__global__ void k_degrees(int64_t n, const int64_t* rp, double* s64, float* s32,
+                          unsigned long long* maxdeg) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long mx = 0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += stride) {
+    const int64_t d = rp[r + 1] - rp[r];
+    const double v = d > 0 ? 1.0 / sqrt((double)d) : 0.0;
+    if (s64) s64[r] = v;
+    if (s32) s32[r] = (float)v;
+    if ((unsigned long long)d > mx) mx = (unsigned long long)d;
+  }
+#pragma unroll
+  for (int o = GREST_WAVE / 2; o > 0; o >>= 1) {
+    unsigned long long y = __shfl_xor(mx, o, GREST_WAVE);
+    mx = y > mx ? y : mx;
+  }
+  if ((threadIdx.x & (GREST_WAVE - 1)) == 0) atomicMax(maxdeg, mx);
+}
+
+}  // namespace
+
+void launch_fill_i64(int64_t* p, int64_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  k_fill_i64<<<grid_for(count), BS, 0, s>>>(p, value, count);
+}
+
+void launch_fill_bytes0(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  uintptr_t a = (uintptr_t)p;
+  if ((a & 15) == 0 && (bytes & 15) == 0) {
+    int64_t cnt = (int64_t)(bytes / 16);
+    k_zero16<<<grid_for(cnt), BS, 0, s>>>((uint4*)p, cnt);
+  } else {
+    k_zero1<<<grid_for((int64_t)bytes), BS, 0, s>>>((uint8_t*)p, (int64_t)bytes);
+  }
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1; }
+
+void launch_scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+  int64_t nb = (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  if (nb < 1) nb = 1;
+  k_scan_reduce<<<(unsigned)nb, BS, 0, s>>>(in, n, tmp);
+  k_scan_blocks<<<1, BS, 0, s>>>(tmp, nb, out + n);
+  k_scan_final<<<(unsigned)nb, BS, 0, s>>>(in, n, tmp, out);
+}
+
+void launch_delta_count(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
+                        int64_t n_old, int64_t n_new, int64_t* cnt, int32_t* status, hipStream_t s) {
+  if (nc <= 0) return;
+  k_delta_count<<<grid_for(nc), BS, 0, s>>>(ei, ej, sg, nc, n_old, n_old + n_new, cnt, status);
+}
+
+void launch_delta_scatter(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
+                          int64_t n_old, int64_t n_new, const int64_t* dptr, int64_t* fill,
+                          int32_t* dcol_tmp, int8_t* dsg_tmp, hipStream_t s) {
+  if (nc <= 0) return;
+  k_delta_scatter<<<grid_for(nc), BS, 0, s>>>(ei, ej, sg, nc, n_old, n_old + n_new, dptr, fill,
+                                              dcol_tmp, dsg_tmp);
+}
+
+void launch_delta_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol_tmp,
+                       const int8_t* dsg_tmp, int32_t* dcol, int8_t* dsg, int32_t* dins,
+                       const int64_t* rp_old, const int32_t* col_old, int64_t* newlen,
+                       int32_t* status, hipStream_t s) {
+  int64_t n2 = n_old + n_new;
+  if (n2 <= 0) return;
+  k_delta_rows<<<grid_for(n2 * GREST_WAVE, BS, 2048), BS, 0, s>>>(
+      n_old, n2, dptr, dcol_tmp, dsg_tmp, dcol, dsg, dins, rp_old, col_old, newlen, status);
+}
+
+void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
+                      const int64_t* dptr, const int32_t* dcol, const int8_t* dsg, const int32_t* dins,
+                      const int64_t* rp_new, int32_t* col_new, int64_t cap_m, hipStream_t s) {
+  int64_t n2 = n_old + n_new;
+  if (n2 <= 0) return;
+  k_csr_merge<<<grid_for(n2 * GREST_WAVE, BS, 4096), BS, 0, s>>>(n_old, n2, rp_old, col_old, dptr, dcol,
+                                                                 dsg, dins, rp_new, col_new, cap_m);
+}
+
+void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* dinv_sqrt32,
+                    int64_t* maxdeg, hipStream_t s) {
+  if (n <= 0) return;
+  k_degrees<<<grid_for(n, BS, 2048), BS, 0, s>>>(n, rp, dinv_sqrt64, dinv_sqrt32,
+                                                 (unsigned long long*)maxdeg);
+}

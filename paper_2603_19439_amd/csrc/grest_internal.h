@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP translation units of libgrest.
+// Kernels are written for gfx950 (CDNA4): 64-wide wavefronts, 160 KB LDS per CU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define GREST_WAVE 64
+
+// Status bits raised by device code and surfaced through the deferred status word.
+enum : int32_t {
+  ST_BAD_FORMAT = 1 << 0,       // id out of range, i >= j, sign not +-1, delete on an appended node
+  ST_DUPLICATE = 1 << 1,        // the same pair twice in one update
+  ST_INSERT_EXISTING = 1 << 2,  // +1 on a pair that is already an edge
+  ST_DELETE_MISSING = 1 << 3,   // -1 on a pair that is not an edge
+  ST_NONFINITE = 1 << 4,        // NaN/Inf met in a small dense factorisation
+  ST_NOT_CONVERGED = 1 << 5,    // the small eigensolver hit its iteration cap
+};
+
+// ------------------------------------------------------------------------------------
+// graph.hip: update of the stored graph (transition model of Sec. 2)
+// ------------------------------------------------------------------------------------
+void launch_fill_i64(int64_t* p, int64_t value, int64_t count, hipStream_t s);
+void launch_fill_bytes0(void* p, size_t bytes, hipStream_t s);  // zero fill by a kernel
+// exclusive scan of in[0..n) into out[0..n], out[n] = total; tmp >= scan_tmp_elems(n)
+int64_t scan_tmp_elems(int64_t n);
+void launch_scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+void launch_delta_count(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
+                        int64_t n_old, int64_t n_new, int64_t* cnt, int32_t* status, hipStream_t s);
+void launch_delta_scatter(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
+                          int64_t n_old, int64_t n_new, const int64_t* dptr, int64_t* fill,
+                          int32_t* dcol_tmp, int8_t* dsg_tmp, hipStream_t s);
+void launch_delta_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol_tmp,
+                       const int8_t* dsg_tmp, int32_t* dcol, int8_t* dsg, int32_t* dins,
+                       const int64_t* rp_old, const int32_t* col_old, int64_t* newlen,
+                       int32_t* status, hipStream_t s);
+void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
+                      const int64_t* dptr, const int32_t* dcol, const int8_t* dsg, const int32_t* dins,
+                      const int64_t* rp_new, int32_t* col_new, int64_t cap_m, hipStream_t s);
+// degrees of the new graph, D^{-1/2} (0 for isolated nodes) and the maximum degree
+void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* dinv_sqrt32,
+                    int64_t* maxdeg, hipStream_t s);
+
+// ------------------------------------------------------------------------------------
+// spmm.hip: products with the stored graph and with the update
+// ------------------------------------------------------------------------------------
+enum OpKind : int32_t { OPK_ADJ = 0, OPK_LAP = 1, OPK_NLAP = 2 };
+
+// Y[r, 0:w] = (op Z)[r, 0:w] for r in [0, n) with the L-form for Laplacians:
+//   adj : sum_c Z[c]
+//   lap : sum_c (Z[r] - Z[c])                 (= L Z)
+//   nlap: s_r sum_c (s_r Z[r] - s_c Z[c])      (= L_n Z; isolated rows give Z[r])
+// Z rows beyond nz_rows are treated as zero (padding).
+template <typename T>
+void launch_spmm(int op, int64_t n, const int64_t* rp, const int32_t* col, const T* sc,
+                 const T* Z, int64_t ldz, int64_t nz_rows, int w, T* Y, int64_t ldy, hipStream_t s);
+
+// Products with the update Delta of the tracked operator (rows grouped in dptr/dcol/dsg).
+//   mode 0: V = Delta_1 Xbar            (only columns c < n_old, input X rows c)
+//   mode 1: Y = Delta_2 Omega           (only columns c >= n_old, input rows c - n_old)
+//   mode 2: B = Delta_2^T M              (rows n_old.., all columns, input rows c)
+//   mode 3: write Delta_2 densely into out[:, 0:S] (G-REST3)
+// For lap/nlap the degree and scaling changes are included (see spmm.hip).
+template <typename T>
+void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
+                      const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
+                      const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s);
+// nlap: V = S'A'S' Xbar - [S A S X; 0] computed row by row from both graphs
+template <typename T>
+void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
+                         const T* s_old, const int64_t* rp_new, const int32_t* col_new, const T* s_new,
+                         const T* X, int64_t ldx, int k, T* V, int64_t ldv, hipStream_t s);
+
+// ------------------------------------------------------------------------------------
+// dense.hip: tall-skinny dense kernels (row-major blocks, n rows)
+// ------------------------------------------------------------------------------------
+// partial[g][a x b] = sum over the g-th row chunk of A[r, 0:a]^T B[r, 0:b]; then C = sum_g
+// (fixed order).  ACC64 selects double accumulation inside a chunk.
+int tn_num_chunks(int64_t n);
+template <typename T, bool ACC64>
+void launch_tn(int64_t n, const T* A, int64_t lda, int a, const T* B, int64_t ldb, int b,
+               double* partial, double* C, hipStream_t s);
+// Out[r, 0:b] = beta * Out[r, 0:b] + alpha * In[r, 0:a] @ M (M: a x b row-major, double)
+// In and Out may alias when they are the same columns of the same rows (in-place, beta 0).
+template <typename T>
+void launch_apply(int64_t n, const T* In, int64_t ldin, int a, const double* M, int b, double alpha,
+                  double beta, T* Out, int64_t ldout, hipStream_t s);
+template <typename T>
+void launch_fill_rows(T* p, int64_t ld, int64_t row0, int64_t rows, int w, hipStream_t s);
+template <typename Tsrc, typename Tdst>
+void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s);
+
+// ------------------------------------------------------------------------------------
+// small.hip: one-workgroup FP64 kernels on small matrices
+// ------------------------------------------------------------------------------------
+// Rank-revealing Cholesky of the Gram G (m x m) with diagonal pivoting.  Produces M
+// (m x m) such that W M has orthonormal leading columns and zero trailing ones, and
+// writes the kept count to *rank.  Columns are dropped when the pivot falls below
+// (tol * scale)^2 where scale^2 = max(1, max_j (G_jj + colsq_j)); colsq may be null.
+void launch_pchol(int m, const double* G, const double* colsq1, const double* colsq2, int kc,
+                  double tol, double* M, int32_t* rank, int32_t* status, hipStream_t s);
+// Symmetric eigensolver of H (first K + rank[0] rows/cols used, ldh = d_full) and
+// selection of kk pairs: which 0 = largest magnitude, 1 = smallest algebraic,
+// 2 = largest algebraic.  Writes theta[kk] and F (d_full x kk, zero rows past the
+// valid size) and, for the RSVD step, nothing else.  work: >= eig_work_elems(d_full).
+int64_t eig_work_elems(int d);
+void launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which,
+                      int kk, double drop_tol, double* theta, double* F, int32_t* kept,
+                      double* work, int32_t* status, hipStream_t s);
+// H = 0.5 (H + H^T) of a d x d matrix in place
+void launch_symmetrize(int d, double* H, hipStream_t s);

@@ -1,0 +1,374 @@
+// Sparse products of the update:
+//   * k_spmm: the updated operator times the basis, (op Z), row-split CSR with a
+//     group of lanes per row, each lane owning a 16-byte slice of the dense row;
+//     the Laplacians use the difference form sum_c (z_r - z_c) so that small
+//     eigenvalues keep their relative accuracy in FP32;
+//   * k_delta: products with the update of the tracked operator (Prop. 3 block
+//     Delta_1 Xbar, the sketch Delta_2 Omega of the randomized range finder, the
+//     transpose product Delta_2^T M, and the dense Delta_2 of G-REST3);
+//   * k_nlap_dx: Delta_Tn Xbar for the normalised Laplacian, where the update
+//     rescales whole rows: computed as S'A'S' Xbar - [S A S X; 0] row by row.
+#include "grest_internal.h"
+
+namespace {
+
+constexpr int BS = 256;
+
+template <typename T, int N>
+struct alignas(N * sizeof(T)) vec_t {
+  T v[N];
+};
+
+template <typename T, int N>
+__device__ inline void vload(const T* p, T (&o)[N]) {
+  const vec_t<T, N> t = *reinterpret_cast<const vec_t<T, N>*>(p);
+#pragma unroll
+  for (int i = 0; i < N; ++i) o[i] = t.v[i];
+}
+
+template <typename T, int N>
+__device__ inline void vstore(T* p, const T (&o)[N]) {
+  vec_t<T, N> t;
+#pragma unroll
+  for (int i = 0; i < N; ++i) t.v[i] = o[i];
+  *reinterpret_cast<vec_t<T, N>*>(p) = t;
+}
+
+inline int grid_for(int64_t threads, int cap = 8192) {
+  int64_t g = (threads + BS - 1) / BS;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+inline int lanes_per_row(int w, int vec) {
+  int need = (w + vec - 1) / vec;
+  int l = 1;
+  while (l < need && l < GREST_WAVE) l <<= 1;
+  return l;
+}
+
+inline int ilog2(int v) {
+  int s = 0;
+  while ((1 << s) < v) ++s;
+  return s;
+}
+
+template <typename T>
+inline int pick_vec(int w, int64_t ld1, int64_t ld2, const void* p1, const void* p2) {
+  const int v = 16 / (int)sizeof(T);
+  if (w % v == 0 && ld1 % v == 0 && ld2 % v == 0 && ((uintptr_t)p1 % 16) == 0 && ((uintptr_t)p2 % 16) == 0)
+    return v;
+  return 1;
+}
+
+// ---------------------------------------------------------------------------------
+// (op Z) for the stored graph
+// ---------------------------------------------------------------------------------
+template <typename T, int VEC, int OP>
+__global__ void __launch_bounds__(BS) k_spmm(int64_t n, const int64_t* __restrict__ rp,
+                                             const int32_t* __restrict__ col, const T* __restrict__ sc,
+                                             const T* __restrict__ Z, int64_t ldz, int w,
+                                             T* __restrict__ Y, int64_t ldy, int lpr_shift) {
+  const int lpr = 1 << lpr_shift;
+  const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int gl = (int)(gid & (lpr - 1));
+  const int64_t ngroups = ((int64_t)gridDim.x * BS) >> lpr_shift;
+  for (int64_t r = gid >> lpr_shift; r < n; r += ngroups) {
+    const int64_t beg = rp[r], end = rp[r + 1];
+    const T sr = (OP == OPK_NLAP) ? sc[r] : T(1);
+    for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
+      T acc[VEC], zr[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) { acc[i] = T(0); zr[i] = T(0); }
+      if (OP != OPK_ADJ) vload<T, VEC>(Z + r * ldz + c0, zr);
+      if (OP == OPK_NLAP) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) zr[i] *= sr;
+      }
+      int64_t e = beg;
+      for (; e + 4 <= end; e += 4) {
+        int32_t c[4];
+        T z[4][VEC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = col[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) vload<T, VEC>(Z + (int64_t)c[u] * ldz + c0, z[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const T scu = (OP == OPK_NLAP) ? sc[c[u]] : T(1);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            if (OP == OPK_ADJ) acc[i] += z[u][i];
+            else if (OP == OPK_LAP) acc[i] += zr[i] - z[u][i];
+            else acc[i] += zr[i] - scu * z[u][i];
+          }
+        }
+      }
+      for (; e < end; ++e) {
+        const int32_t c = col[e];
+        T z[VEC];
+        vload<T, VEC>(Z + (int64_t)c * ldz + c0, z);
+        const T scu = (OP == OPK_NLAP) ? sc[c] : T(1);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          if (OP == OPK_ADJ) acc[i] += z[i];
+          else if (OP == OPK_LAP) acc[i] += zr[i] - z[i];
+          else acc[i] += zr[i] - scu * z[i];
+        }
+      }
+      if (OP == OPK_NLAP) {
+        if (end == beg) {  // isolated node: (L_n)_rr = 1
+          vload<T, VEC>(Z + r * ldz + c0, acc);
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc[i] *= sr;
+        }
+      }
+      vstore<T, VEC>(Y + r * ldy + c0, acc);
+    }
+  }
+}
+
+template <typename T, int OP>
+void spmm_dispatch(int vec, int64_t n, const int64_t* rp, const int32_t* col, const T* sc, const T* Z,
+                   int64_t ldz, int w, T* Y, int64_t ldy, hipStream_t s) {
+  const int lpr = lanes_per_row(w, vec);
+  const int g = grid_for(n * lpr);
+  if (vec == 16 / (int)sizeof(T))
+    k_spmm<T, 16 / sizeof(T), OP><<<g, BS, 0, s>>>(n, rp, col, sc, Z, ldz, w, Y, ldy, ilog2(lpr));
+  else
+    k_spmm<T, 1, OP><<<g, BS, 0, s>>>(n, rp, col, sc, Z, ldz, w, Y, ldy, ilog2(lpr));
+}
+
+// ---------------------------------------------------------------------------------
+// products with the update of the tracked operator
+// ---------------------------------------------------------------------------------
+struct DeltaArgs {
+  int64_t n_old, n_new;
+  const int64_t* dptr;
+  const int32_t* dcol;
+  const int8_t* dsg;
+  const int64_t* maxdeg;  // maximum degree of the updated graph (alpha' = 2 maxdeg)
+};
+
+// weight of the Delta_2 entry (r, c) with c an appended node, and the diagonal of the
+// new block, for the three operators (adj: Delta_2 of A; lap: alpha' I - L' restricted
+// to the new columns; nlap: T_n' restricted to the new columns).
+template <typename T, int OP>
+__device__ inline T d2_weight(int8_t s, const T* snew, int64_t r, int64_t c) {
+  if (OP == OPK_NLAP) return snew[r] * snew[c];
+  (void)r; (void)c;
+  return T(s);
+}
+
+template <typename T, int OP>
+__device__ inline T d2_diag(const DeltaArgs& a, int64_t node) {
+  if (OP == OPK_ADJ) return T(0);
+  if (OP == OPK_NLAP) return T(1);
+  const int64_t deg = a.dptr[node + 1] - a.dptr[node];  // every edge of an appended node is in Delta
+  return T(2 * (double)a.maxdeg[0] - (double)deg);
+}
+
+// mode 0: out[r] = (Delta_T)[r, 0:n_old] X  for every r < n_old + n_new (zero rows included)
+// mode 1: out[r] = (Delta_T)[r, n_old:] Omega
+// mode 2: out[j] = (Delta_T)[n_old + j, :] M  (= (Delta_T,2^T M)[j] by symmetry)
+template <typename T, int VEC, int OP, int MODE>
+__global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__ snew,
+                                              const T* __restrict__ in, int64_t ldin, int w,
+                                              T* __restrict__ out, int64_t ldout, int lpr_shift) {
+  const int lpr = 1 << lpr_shift;
+  const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int gl = (int)(gid & (lpr - 1));
+  const int64_t ngroups = ((int64_t)gridDim.x * BS) >> lpr_shift;
+  const int64_t n2 = a.n_old + a.n_new;
+  const int64_t nrows = (MODE == 2) ? a.n_new : n2;
+  for (int64_t q = gid >> lpr_shift; q < nrows; q += ngroups) {
+    const int64_t r = (MODE == 2) ? a.n_old + q : q;
+    const int64_t beg = a.dptr[r], end = a.dptr[r + 1];
+    for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
+      T acc[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) acc[i] = T(0);
+      int32_t ssum = 0;
+      for (int64_t e = beg; e < end; ++e) {
+        const int64_t c = a.dcol[e];
+        const int8_t sg = a.dsg[e];
+        ssum += sg;
+        T wgt;
+        int64_t src;
+        if (MODE == 0) {
+          if (c >= a.n_old) continue;
+          wgt = T(sg);
+          src = c;
+        } else if (MODE == 1) {
+          if (c < a.n_old) continue;
+          wgt = d2_weight<T, OP>(sg, snew, r, c);
+          src = c - a.n_old;
+        } else {
+          wgt = d2_weight<T, OP>(sg, snew, r, c);
+          src = c;
+        }
+        T z[VEC];
+        vload<T, VEC>(in + src * ldin + c0, z);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] += wgt * z[i];
+      }
+      if (MODE == 0 && OP == OPK_LAP && r < a.n_old && ssum != 0) {
+        // -(D' - D) Xbar on the old rows (the alpha' - alpha shift lies in span(Xbar))
+        T z[VEC];
+        vload<T, VEC>(in + r * ldin + c0, z);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] -= T(ssum) * z[i];
+      }
+      if (MODE != 0 && r >= a.n_old) {
+        const T dgl = d2_diag<T, OP>(a, r);
+        if (dgl != T(0)) {
+          T z[VEC];
+          vload<T, VEC>(in + (MODE == 1 ? r - a.n_old : r) * ldin + c0, z);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc[i] += dgl * z[i];
+        }
+      }
+      vstore<T, VEC>(out + q * ldout + c0, acc);
+    }
+  }
+}
+
+// mode 3: out[:, j] = (Delta_T)[:, n_old + j] densely (out zero-filled beforehand)
+template <typename T, int OP>
+__global__ void __launch_bounds__(BS) k_delta_dense2(DeltaArgs a, const T* __restrict__ snew,
+                                                     T* __restrict__ out, int64_t ldout) {
+  const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * BS;
+  for (int64_t j = gid; j < a.n_new; j += nth) {
+    const int64_t r = a.n_old + j;
+    for (int64_t e = a.dptr[r]; e < a.dptr[r + 1]; ++e) {
+      const int64_t c = a.dcol[e];
+      out[c * ldout + j] = d2_weight<T, OP>(a.dsg[e], snew, c, r);
+    }
+    const T dgl = d2_diag<T, OP>(a, r);
+    if (dgl != T(0)) out[r * ldout + j] = dgl;
+  }
+}
+
+template <typename T, int VEC>
+__global__ void __launch_bounds__(BS) k_nlap_dx(int64_t n_old, int64_t n2, const int64_t* __restrict__ rpo,
+                                                const int32_t* __restrict__ colo, const T* __restrict__ so,
+                                                const int64_t* __restrict__ rpn,
+                                                const int32_t* __restrict__ coln, const T* __restrict__ sn,
+                                                const T* __restrict__ X, int64_t ldx, int w,
+                                                T* __restrict__ V, int64_t ldv, int lpr_shift) {
+  const int lpr = 1 << lpr_shift;
+  const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int gl = (int)(gid & (lpr - 1));
+  const int64_t ngroups = ((int64_t)gridDim.x * BS) >> lpr_shift;
+  for (int64_t r = gid >> lpr_shift; r < n2; r += ngroups) {
+    for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
+      T a1[VEC], a0[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) { a1[i] = T(0); a0[i] = T(0); }
+      for (int64_t e = rpn[r]; e < rpn[r + 1]; ++e) {
+        const int64_t c = coln[e];
+        if (c >= n_old) continue;
+        T z[VEC];
+        vload<T, VEC>(X + c * ldx + c0, z);
+        const T sc = sn[c];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) a1[i] += sc * z[i];
+      }
+      if (r < n_old) {
+        for (int64_t e = rpo[r]; e < rpo[r + 1]; ++e) {
+          const int64_t c = colo[e];
+          T z[VEC];
+          vload<T, VEC>(X + c * ldx + c0, z);
+          const T sc = so[c];
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) a0[i] += sc * z[i];
+        }
+      }
+      const T s1 = sn[r];
+      const T s0 = r < n_old ? so[r] : T(0);
+      T o[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) o[i] = s1 * a1[i] - s0 * a0[i];
+      vstore<T, VEC>(V + r * ldv + c0, o);
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_spmm(int op, int64_t n, const int64_t* rp, const int32_t* col, const T* sc, const T* Z,
+                 int64_t ldz, int64_t nz_rows, int w, T* Y, int64_t ldy, hipStream_t s) {
+  (void)nz_rows;
+  if (n <= 0 || w <= 0) return;
+  const int vec = pick_vec<T>(w, ldz, ldy, Z, Y);
+  if (op == OPK_ADJ) spmm_dispatch<T, OPK_ADJ>(vec, n, rp, col, sc, Z, ldz, w, Y, ldy, s);
+  else if (op == OPK_LAP) spmm_dispatch<T, OPK_LAP>(vec, n, rp, col, sc, Z, ldz, w, Y, ldy, s);
+  else spmm_dispatch<T, OPK_NLAP>(vec, n, rp, col, sc, Z, ldz, w, Y, ldy, s);
+}
+
+template <typename T, int OP, int MODE>
+static void delta_dispatch(int vec, const DeltaArgs& a, const T* snew, const T* in, int64_t ldin, int w,
+                           T* out, int64_t ldout, hipStream_t s) {
+  const int64_t rows = (MODE == 2) ? a.n_new : a.n_old + a.n_new;
+  if (rows <= 0 || w <= 0) return;
+  const int lpr = lanes_per_row(w, vec);
+  const int g = grid_for(rows * lpr);
+  if (vec == 16 / (int)sizeof(T))
+    k_delta<T, 16 / sizeof(T), OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, ilog2(lpr));
+  else
+    k_delta<T, 1, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, ilog2(lpr));
+}
+
+template <typename T, int OP>
+static void delta_mode(int mode, int vec, const DeltaArgs& a, const T* snew, const T* in, int64_t ldin,
+                       int w, T* out, int64_t ldout, hipStream_t s) {
+  if (mode == 0) delta_dispatch<T, OP, 0>(vec, a, snew, in, ldin, w, out, ldout, s);
+  else if (mode == 1) delta_dispatch<T, OP, 1>(vec, a, snew, in, ldin, w, out, ldout, s);
+  else if (mode == 2) delta_dispatch<T, OP, 2>(vec, a, snew, in, ldin, w, out, ldout, s);
+  else if (a.n_new > 0) k_delta_dense2<T, OP><<<grid_for(a.n_new), BS, 0, s>>>(a, snew, out, ldout);
+}
+
+template <typename T>
+void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
+                      const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
+                      const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s) {
+  DeltaArgs a{n_old, n_new, dptr, dcol, dsg, maxdeg};
+  const int vec = (mode == 3) ? 1 : pick_vec<T>(w, ldin, ldout, in, out);
+  if (op == OPK_ADJ) delta_mode<T, OPK_ADJ>(mode, vec, a, snew, in, ldin, w, out, ldout, s);
+  else if (op == OPK_LAP) delta_mode<T, OPK_LAP>(mode, vec, a, snew, in, ldin, w, out, ldout, s);
+  else delta_mode<T, OPK_NLAP>(mode, vec, a, snew, in, ldin, w, out, ldout, s);
+}
+
+template <typename T>
+void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
+                         const T* s_old, const int64_t* rp_new, const int32_t* col_new, const T* s_new,
+                         const T* X, int64_t ldx, int k, T* V, int64_t ldv, hipStream_t s) {
+  const int64_t n2 = n_old + n_new;
+  if (n2 <= 0 || k <= 0) return;
+  const int vec = pick_vec<T>(k, ldx, ldv, X, V);
+  const int lpr = lanes_per_row(k, vec);
+  const int g = grid_for(n2 * lpr);
+  if (vec == 16 / (int)sizeof(T))
+    k_nlap_dx<T, 16 / sizeof(T)><<<g, BS, 0, s>>>(n_old, n2, rp_old, col_old, s_old, rp_new, col_new,
+                                                  s_new, X, ldx, k, V, ldv, ilog2(lpr));
+  else
+    k_nlap_dx<T, 1><<<g, BS, 0, s>>>(n_old, n2, rp_old, col_old, s_old, rp_new, col_new, s_new, X, ldx,
+                                     k, V, ldv, ilog2(lpr));
+}
+
+#define INST(T)                                                                                       \
+  template void launch_spmm<T>(int, int64_t, const int64_t*, const int32_t*, const T*, const T*,       \
+                               int64_t, int64_t, int, T*, int64_t, hipStream_t);                      \
+  template void launch_delta_mul<T>(int, int, int64_t, int64_t, const int64_t*, const int32_t*,        \
+                                    const int8_t*, const int64_t*, const T*, const T*, int64_t, int,  \
+                                    T*, int64_t, hipStream_t);                                        \
+  template void launch_nlap_delta_x<T>(int64_t, int64_t, const int64_t*, const int32_t*, const T*,     \
+                                       const int64_t*, const int32_t*, const T*, const T*, int64_t,   \
+                                       int, T*, int64_t, hipStream_t);
+INST(float)
+INST(double)
+#undef INST

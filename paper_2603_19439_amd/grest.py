@@ -1,0 +1,201 @@
+"""ctypes binding of libgrest (include/grest.h).
+
+Argument marshalling only: every step of the update runs in the HIP library.
+Host arrays are NumPy arrays; device arrays are torch tensors on the state's
+device (their data pointers are passed through).  The library must have been
+built (``python -m paper_2603_19439_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrest.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ENODEV = range(6)
+OP = {"adj": 0, "lap": 1, "nlap": 2}
+VARIANT = {"g2": 2, "g3": 3, "rsvd": 4}
+PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
+HOST, DEVICE = 0, 1
+F64, F32 = 0, 1
+
+
+class GrestError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({_strerror(status)}) {detail}".strip())
+
+
+class Config(C.Structure):
+    _fields_ = [("k", C.c_int32), ("variant", C.c_int32), ("L", C.c_int32), ("P", C.c_int32),
+                ("op", C.c_int32), ("precision", C.c_int32), ("max_new", C.c_int32),
+                ("reserved", C.c_int32), ("rank_tol", C.c_double)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every entry point of include/grest.h
+_SIGS = [
+    ("grest_abi_version", C.c_int32, []),
+    ("grest_strerror", C.c_char_p, [C.c_int]),
+    ("grest_last_error", C.c_char_p, []),
+    ("grest_validate_changes", C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grest_create", C.c_int, [C.POINTER(Config), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                               C.c_int64, C.POINTER(C.c_void_p)]),
+    ("grest_set_pairs", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("grest_init_pairs", C.c_int, [C.c_void_p, C.c_int32, C.c_uint64]),
+    ("grest_update", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_int32]),
+    ("grest_sync", C.c_int, [C.c_void_p]),
+    ("grest_get", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    ("grest_shape", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32)]),
+    ("grest_get_graph", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grest_destroy", None, [C.c_void_p]),
+]
+
+
+def lib():
+    """Load libgrest.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_19439_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().grest_strerror(status).decode()
+    except Exception:  # library not loadable
+        return "?"
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        detail = lib().grest_last_error().decode()
+        raise GrestError(status, where, detail)
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _ptr(a, dtype):
+    """(keepalive, pointer, where) for a NumPy array (host) or a torch tensor (device)."""
+    if a is None:
+        return None, None, HOST
+    mod = type(a).__module__
+    if mod.startswith("torch"):
+        if not a.is_contiguous():
+            raise ValueError("device arrays must be contiguous")
+        return a, C.c_void_p(a.data_ptr()), (DEVICE if a.is_cuda else HOST)
+    arr, p = _host(a, dtype)
+    return arr, p, HOST
+
+
+def validate_changes(n: int, n_new: int, i, j, sign) -> bool:
+    i, pi = _host(i, np.int32)
+    j, pj = _host(j, np.int32)
+    s, ps = _host(sign, np.int8)
+    return lib().grest_validate_changes(int(n), int(n_new), int(i.size), pi, pj, ps) == OK
+
+
+class State:
+    """A G-REST state on the current HIP device (see grest.h)."""
+
+    def __init__(self, rowptr, col, k: int, variant: str = "g3", op: str = "adj", precision: str = "fp64",
+                 L: int = 0, P: int = 0, max_new: int = 0, rank_tol: float = 0.0, stream=None,
+                 node_capacity: int = 0, nnz_capacity: int = 0):
+        self._h = C.c_void_p()
+        cfg = Config(k=k, variant=VARIANT[variant], L=L, P=P, op=OP[op], precision=PRECISION[precision],
+                     max_new=max_new, reserved=0, rank_tol=rank_tol)
+        rp, prp = _host(rowptr, np.int64)
+        cl, pcl = _host(col, np.int32)
+        n0 = rp.size - 1
+        sp = C.c_void_p(stream) if stream else None
+        _check(lib().grest_create(C.byref(cfg), sp, n0, prp, pcl, int(node_capacity), int(nnz_capacity),
+                                  C.byref(self._h)), "grest_create")
+        self.k = k
+        self.op = op
+        self.precision = precision
+
+    def close(self):
+        if self._h:
+            lib().grest_destroy(self._h)
+            self._h = C.c_void_p()
+
+    __del__ = close
+
+    def set_pairs(self, values, X):
+        v, pv, wv = _ptr(values, np.float64)
+        x, px, wx = _ptr(X, np.float64)
+        if wv != wx:
+            raise ValueError("values and X must both be host or both be device arrays")
+        _check(lib().grest_set_pairs(self._h, pv, px, wx), "grest_set_pairs")
+
+    def init_pairs(self, iterations: int = 30, seed: int = 0):
+        _check(lib().grest_init_pairs(self._h, int(iterations), int(seed)), "grest_init_pairs")
+
+    def update(self, n_new: int, i, j, sign, omega=None):
+        ai, pi, w1 = _ptr(i, np.int32)
+        aj, pj, w2 = _ptr(j, np.int32)
+        asg, ps, w3 = _ptr(sign, np.int8)
+        ao, po, w4 = _ptr(omega, np.float64)
+        nc = int(ai.numel() if hasattr(ai, "numel") else np.asarray(ai).size)
+        where = w1
+        if omega is not None and w4 != where:
+            raise ValueError("omega must live where the change arrays live")
+        _check(lib().grest_update(self._h, int(n_new), nc, pi, pj, ps, po, where), "grest_update")
+        self._keep = (ai, aj, asg, ao)
+
+    def update_delta(self, d, omega=None):
+        return self.update(d.n_new, d.i, d.j, d.sign, omega)
+
+    def sync(self):
+        _check(lib().grest_sync(self._h), "grest_sync")
+
+    def shape(self) -> Tuple[int, int, int, int]:
+        n, m = C.c_int64(), C.c_int64()
+        k, w = C.c_int32(), C.c_int32()
+        _check(lib().grest_shape(self._h, C.byref(n), C.byref(m), C.byref(k), C.byref(w)), "grest_shape")
+        return n.value, m.value, k.value, w.value
+
+    def get(self, dtype=np.float64, out=None):
+        """(values, X): values FP64 host, X n x k host array (or ``out``, a device tensor)."""
+        n, _, k, _ = self.shape()
+        vals = np.empty(k, dtype=np.float64)
+        xd = F64 if np.dtype(dtype) == np.float64 else F32
+        if out is None:
+            X = np.empty((n, k), dtype=dtype)
+            _check(lib().grest_get(self._h, vals.ctypes.data_as(C.c_void_p), X.ctypes.data_as(C.c_void_p), xd, HOST),
+                   "grest_get")
+            return vals, X
+        _check(lib().grest_get(self._h, vals.ctypes.data_as(C.c_void_p), C.c_void_p(out.data_ptr()), xd, DEVICE),
+               "grest_get")
+        return vals, out
+
+    def values(self):
+        n, _, k, _ = self.shape()
+        vals = np.empty(k, dtype=np.float64)
+        _check(lib().grest_get(self._h, vals.ctypes.data_as(C.c_void_p), None, F64, HOST), "grest_get")
+        return vals
+
+    def graph(self):
+        n, m, _, _ = self.shape()
+        rp = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(m, dtype=np.int32)
+        _check(lib().grest_get_graph(self._h, rp.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p)),
+               "grest_get_graph")
+        return rp, col

@@ -34,14 +34,16 @@ def gap_prefix(ref_all: np.ndarray, k: int, rel_gap: float = 1e-3) -> int:
 
 
 def subspace_sine(U: np.ndarray, V: np.ndarray) -> float:
-    """||(I - V V^T) U||_2 for orthonormal U, V (sine of the largest principal angle)."""
+    """||(I - V V^T) U||_2 for orthonormal U, V (sine of the largest principal angle).
+
+    Computed from the residual itself, not from 1 - cos^2, so that angles near
+    machine precision are resolved."""
     U = np.asarray(U, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     if U.shape[1] == 0:
         return 0.0
-    c = np.linalg.svd(V.T @ U, compute_uv=False)
-    c = np.clip(c, 0.0, 1.0)
-    return float(np.sqrt(max(0.0, 1.0 - c.min() ** 2)))
+    R = U - V @ (V.T @ U)
+    return float(np.linalg.norm(R, 2))
 
 
 def orthonormality(U: np.ndarray) -> float:

@@ -1,0 +1,69 @@
+"""The C interface: the library loads without a GPU, exports every entry point that
+include/grest.h declares, and its host-side checks behave as documented."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_19439_amd import grest as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grest.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(grest_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["grest_create", "grest_set_pairs", "grest_init_pairs", "grest_update", "grest_sync",
+                     "grest_get", "grest_destroy", "grest_validate_changes", "grest_strerror"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = G.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    bound = {name for name, _, _ in G._SIGS}
+    assert set(declared_functions()) <= bound
+
+
+def test_abi_version_and_strerror():
+    lib = G.lib()
+    assert lib.grest_abi_version() == 1
+    assert lib.grest_strerror(0) == b"ok"
+    assert lib.grest_strerror(1).startswith(b"invalid")
+
+
+@pytest.mark.parametrize("case,ok", [
+    (dict(n=5, s=0, i=[0, 1], j=[1, 2], g=[1, -1]), True),
+    (dict(n=5, s=2, i=[0, 4], j=[5, 6], g=[1, 1]), True),
+    (dict(n=5, s=0, i=[1], j=[1], g=[1]), False),        # self-loop
+    (dict(n=5, s=0, i=[2], j=[1], g=[1]), False),        # i > j
+    (dict(n=5, s=0, i=[0], j=[5], g=[1]), False),        # out of range
+    (dict(n=5, s=1, i=[0], j=[5], g=[-1]), False),       # delete on an appended node
+    (dict(n=5, s=0, i=[0, 0], j=[3, 3], g=[1, 1]), False),  # duplicate
+    (dict(n=5, s=0, i=[0], j=[3], g=[2]), False),        # bad sign
+    (dict(n=5, s=0, i=[], j=[], g=[]), True),            # empty update
+])
+def test_host_validation(case, ok):
+    assert G.validate_changes(case["n"], case["s"], case["i"], case["j"], case["g"]) == ok
+
+
+def test_create_without_device_or_with_bad_args_fails_cleanly():
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([1, 0], dtype=np.int32)
+    with pytest.raises(G.GrestError) as e:
+        G.State(rp, col, k=5)  # k >= n
+    assert e.value.status in (G.EINVAL, G.ENODEV)
+    bad = np.array([1, 1], dtype=np.int32)  # self-loop in row 1
+    with pytest.raises(G.GrestError):
+        G.State(rp, bad, k=1)
