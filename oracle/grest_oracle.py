@@ -263,10 +263,23 @@ class StepResult:
     Delta: sp.csr_matrix     # adjacency update
     DeltaT: sp.csr_matrix    # operator update
 
+    op: str = ADJ
+
     @property
     def nu(self) -> np.ndarray:
         """Eigenvalues of L or L_n (shift - theta); for adj the Ritz values themselves."""
-        return self.shift - self.theta if self.shift else self.theta
+        return self.shift - self.theta if self.op != ADJ else self.theta
+
+    @property
+    def nu_rq(self) -> np.ndarray:
+        """nu of the Laplacians as the Laplacian quadratic form of the Ritz vectors.
+
+        For a Ritz vector x of T = shift I - L on span(Z), x^T L x = shift - theta
+        exactly (Sec. 4.2: nu = alpha - mu); evaluating it as a sum of squared edge
+        differences keeps its relative accuracy when nu is small and the shift large."""
+        if self.op == ADJ:
+            return self.theta
+        return laplacian_quadratic_form(self.A, self.X, self.op)
 
 
 def grest_step(A: sp.csr_matrix, X: np.ndarray, theta_prev: np.ndarray, n_new: int, ei, ej, sign,
@@ -320,7 +333,28 @@ def grest_step(A: sp.csr_matrix, X: np.ndarray, theta_prev: np.ndarray, n_new: i
     idx = select(th, k, which_for(op))
     Xn = normalize_signs(Z @ F[:, idx])                             # Alg. 2, Ritz vectors
     return StepResult(theta=th[idx].copy(), X=Xn, A=A_new, shift=shift, Z=Z, H=H,
-                      rank_W=Q.shape[1], Delta=Delta, DeltaT=DT)
+                      rank_W=Q.shape[1], Delta=Delta, DeltaT=DT, op=op)
+
+
+def laplacian_quadratic_form(A: sp.csr_matrix, X: np.ndarray, op: str) -> np.ndarray:
+    """x^T L x = sum over edges (x_i - x_j)^2 (lap), and x^T L_n x = sum over edges
+    (x_i/sqrt(d_i) - x_j/sqrt(d_j))^2 + sum over isolated nodes x_i^2 (nlap), per column."""
+    C = sp.triu(A, 1).tocoo()
+    i, j = C.row, C.col
+    X = np.asarray(X, dtype=np.float64)
+    if op == LAP:
+        D = X[i] - X[j]
+        return (D * D).sum(axis=0)
+    d = np.asarray(A.sum(axis=1)).ravel()
+    s = np.zeros_like(d)
+    nz = d > 0
+    s[nz] = 1.0 / np.sqrt(d[nz])
+    D = X[i] * s[i, None] - X[j] * s[j, None]
+    out = (D * D).sum(axis=0)
+    iso = ~nz
+    if iso.any():
+        out = out + (X[iso] ** 2).sum(axis=0)
+    return out
 
 
 # ------------------------------------------------------------------------------------

@@ -281,7 +281,7 @@ void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, const double*
 
 template <typename T>
 grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const int32_t* col, const T* sc,
-                           int32_t* rank_slot) {
+                           int base, int32_t* rank_slot) {
   Blocks<T> b = blocks<T>(st);
   // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
   launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc, st->ldz, n2, st->D, b.aux, st->D, st->stream);
@@ -290,7 +290,7 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   else launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
   // small FP64 eigensolve on the leading K + rank block, selection of K pairs
   const int which = st->op == GREST_OP_ADJ ? 0 : 1;
-  launch_small_eig(st->D, st->K, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
+  launch_small_eig(st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
                    st->status, st->stream);
   // X' = Z F_K into the other buffer
   launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
@@ -398,7 +398,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   project_twice<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, st->C1, st->C2);
   cholqr2<T>(st, n2, b.W, st->ldz, st->Dw, st->C1, st->C2, 0);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
-  CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->ranks + 1));
+  CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->K, st->ranks + 1));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -407,6 +407,50 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   st->zcur ^= 1;
   st->n = n2;
   st->m = m_new;
+  return GREST_OK;
+}
+
+
+// Initial pairs (Alg. 2 line 3): block subspace iteration of width b = min(2K, Dw) on the
+// tracked operator (shifted for the Laplacians so that the wanted end of the spectrum
+// dominates), CholQR2 after every product, then Rayleigh-Ritz on the final block.
+template <typename T>
+grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
+  hipStream_t s = st->stream;
+  const int64_t n = st->n;
+  int b = std::min(2 * st->K, st->Dw);
+  if (b > n) b = (int)n;
+  T* Z = (T*)st->z[st->zcur];
+  T* aux = (T*)st->aux;
+  const int64_t* rp = st->rp[st->gcur];
+  const int32_t* col = st->col[st->gcur];
+  const T* sc = (const T*)st->sc[st->gcur];
+  double shift = 0.0;
+  if (st->op == GREST_OP_LAP) {
+    int64_t md = 0;
+    HIPCHK(hipMemcpy(&md, st->maxdeg, sizeof(int64_t), hipMemcpyDeviceToHost));
+    shift = 2.0 * (double)md;
+  } else if (st->op == GREST_OP_NLAP) {
+    shift = 2.0;
+  }
+  launch_fill_bytes0(st->status, sizeof(int32_t), s);
+  launch_fill_rows<T>(Z, st->ldz, 0, n, st->ldz, s);
+  launch_fill_random<T>(Z, st->ldz, n, b, seed, s);
+  cholqr2<T>(st, n, Z, st->ldz, b, nullptr, nullptr, 0);
+  for (int it = 0; it < iters; ++it) {
+    launch_spmm<T>(st->op, n, rp, col, sc, Z, st->ldz, n, b, aux, st->D, s);
+    if (st->op != GREST_OP_ADJ) launch_axpby<T>(n, b, shift, Z, st->ldz, -1.0, aux, st->D, s);
+    HIPCHK(hipMemcpy2DAsync(Z, st->ldz * sizeof(T), aux, st->D * sizeof(T), b * sizeof(T), n,
+                            hipMemcpyDeviceToDevice, s));
+    cholqr2<T>(st, n, Z, st->ldz, b, nullptr, nullptr, 0);
+  }
+  CHK(rayleigh_ritz<T>(st, n, rp, col, sc, 0, st->ranks + 1));
+  HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  st->zcur ^= 1;
+  st->has_pairs = true;
+  if (st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED)) return GREST_ENUMERIC;
   return GREST_OK;
 }
 
@@ -623,8 +667,8 @@ grest_status grest_set_pairs(grest_state* st, const double* values, const double
 }
 
 grest_status grest_init_pairs(grest_state* st, int32_t iterations, uint64_t seed) {
-  (void)st; (void)iterations; (void)seed;
-  return GREST_EINVAL;
+  if (!st || iterations < 1) return GREST_EINVAL;
+  return st->es == 8 ? init_impl<double>(st, iterations, seed) : init_impl<float>(st, iterations, seed);
 }
 
 grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei, const int32_t* ej,

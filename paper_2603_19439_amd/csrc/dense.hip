@@ -228,3 +228,57 @@ template void launch_convert<float, double>(const float*, double*, int64_t, hipS
 template void launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
 template void launch_tn<double, false>(int64_t, const double*, int64_t, int, const double*, int64_t, int,
                                        double*, double*, hipStream_t);
+
+// ---- start block of the initial subspace iteration and a scaled update ----
+namespace {
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void k_fill_random(T* p, int64_t ld, int64_t rows, int w, uint64_t seed) {
+  const int64_t total = rows * w;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int64_t r = idx / w;
+    const int c = (int)(idx % w);
+    // uniform in (-1, 1) from a counter hash; only a generic start block is needed
+    const uint64_t h = mix64(seed ^ mix64((uint64_t)idx));
+    const double u = ((double)(h >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+    p[r * ld + c] = (T)u;
+  }
+}
+
+template <typename T>
+__global__ void k_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy) {
+  const int64_t total = rows * w;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int64_t r = idx / w;
+    const int c = (int)(idx % w);
+    Y[r * ldy + c] = (T)(a * (double)X[r * ldx + c] + b * (double)Y[r * ldy + c]);
+  }
+}
+}  // namespace
+
+template <typename T>
+void launch_fill_random(T* p, int64_t ld, int64_t rows, int w, uint64_t seed, hipStream_t s) {
+  if (rows <= 0 || w <= 0) return;
+  k_fill_random<T><<<grid_cap(rows * w), 256, 0, s>>>(p, ld, rows, w, seed);
+}
+
+template <typename T>
+void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy,
+                  hipStream_t s) {
+  if (rows <= 0 || w <= 0) return;
+  k_axpby<T><<<grid_cap(rows * w), 256, 0, s>>>(rows, w, a, X, ldx, b, Y, ldy);
+}
+
+template void launch_fill_random<float>(float*, int64_t, int64_t, int, uint64_t, hipStream_t);
+template void launch_fill_random<double>(double*, int64_t, int64_t, int, uint64_t, hipStream_t);
+template void launch_axpby<float>(int64_t, int, double, const float*, int64_t, double, float*, int64_t, hipStream_t);
+template void launch_axpby<double>(int64_t, int, double, const double*, int64_t, double, double*, int64_t,
+                                   hipStream_t);

@@ -109,3 +109,9 @@ void launch_small_eig(int d_full, int base, const int32_t* rank, const double* H
                       double* work, int32_t* status, hipStream_t s);
 // H = 0.5 (H + H^T) of a d x d matrix in place
 void launch_symmetrize(int d, double* H, hipStream_t s);
+template <typename T>
+void launch_fill_random(T* p, int64_t ld, int64_t rows, int w, uint64_t seed, hipStream_t s);
+// Y = a X + b Y on an n x w block
+template <typename T>
+void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy,
+                  hipStream_t s);

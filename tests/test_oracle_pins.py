@@ -434,3 +434,27 @@ def test_planted_lowrank_without_delta_term_is_caught(monkeypatch):
     monkeypatch.setattr(O, "operator_delta", no_delta)
     bad = O.grest_step(A, X0, th0, 2, ei, ej, sg, 3, variant=O.G3, proj=O.LOWRANK)
     assert not np.allclose(ok.theta, bad.theta, atol=1e-6)
+
+
+@pytest.mark.parametrize("op", [O.LAP, O.NLAP])
+def test_laplacian_quadratic_form_matches_dense_definition(op):
+    A, ei, ej, sg = random_case(13, n=50, s=5, p=0.1)
+    A = O.updated_adjacency(A, O.assemble_delta(A, 5, ei, ej, sg))  # may contain isolated nodes
+    X = np.random.default_rng(2).standard_normal((A.shape[0], 3))
+    d = np.asarray(A.sum(1)).ravel()
+    if op == O.LAP:
+        Lm = np.diag(d) - A.toarray()
+    else:
+        s = np.where(d > 0, 1 / np.sqrt(np.maximum(d, 1e-300)), 0.0)
+        Lm = np.eye(d.size) - np.diag(s) @ A.toarray() @ np.diag(s)
+    ref = np.einsum("ij,ij->j", X, Lm @ X)
+    assert np.allclose(O.laplacian_quadratic_form(A, X, op), ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("op", [O.LAP, O.NLAP])
+def test_ritz_nu_identity(op):
+    """For Ritz vectors of T = shift I - L, the quadratic form equals shift - theta (Sec. 4.2)."""
+    A, ei, ej, sg = random_case(5, n=60, s=6, p=0.12, connected=True)
+    th0, X0, _ = O.leading_eigenpairs(A, 6, op)
+    r = O.grest_step(A, X0, th0, 6, ei, ej, sg, 6, variant=O.G3, op=op)
+    assert np.allclose(r.nu_rq, r.nu, atol=1e-11 * max(1.0, r.shift))
