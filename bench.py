@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the G-REST eigenpair update on one MI355X.
+
+Workload: stochastic block model with n0 = 1,000,000 nodes, 32 blocks with
+Dirichlet(2) sizes, mean degree 20 (80 % intra-block), adjacency operator,
+K = 32 tracked pairs, G-REST_RSVD with L = P = 32 (subspace width 3K = 96);
+every step appends 10,000 nodes and about 50,000 edges.  Data are synthetic
+(seeded generator); the initial pairs come from the library's device subspace
+iteration.  The change lists and Gaussian test matrices are uploaded to HBM
+before the timed region, which contains exactly ``--steps`` updates bracketed by
+device synchronisations.
+
+Printed JSON line: the headline updates/s of the mixed-precision path, the plain
+FP32 path beside it, per-stage times, the roofline of the dominant kernel measured
+with HIP events around it, and the FP64 CPU oracle timed on one update of the same
+workload (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+K, L, P = 32, 32, 32
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--compare", default="fp32", help="second path timed beside the headline ('' to skip)")
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink node counts (quick runs only)")
+    ap.add_argument("--init-iters", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *msg):
+    if not args.quiet:
+        print("[bench]", *msg, file=sys.stderr, flush=True)
+
+
+def spmm_bytes(n2: int, nnz: int, width: int, elem: int) -> float:
+    """Algorithmic bytes of one product with the updated operator: column ids (4 B per
+    stored entry), row offsets (8 B per row), the basis read once and the product
+    written once (n' x width elements each)."""
+    return 4.0 * nnz + 8.0 * (n2 + 1) + 2.0 * elem * n2 * width
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the update of one graph is not "
+                                   "sharded across GPUs (see the design notes for how it would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2603_19439_amd import grest as G
+    from paper_2603_19439_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    n_steps = max(10, args.steps, args.warmup)
+    t0 = time.time()
+    wl = W.preset("sbm_n1e6", scale=args.scale, steps=n_steps)
+    log(args, f"workload generated in {time.time() - t0:.1f}s: n0={wl.n0} nnz={wl.col0.size}")
+    # device-resident inputs
+    dev_steps = []
+    for t, d in enumerate(wl.deltas):
+        om = W.omega(wl.cfg_id, 0, t + 1, d.n_new, L + P) if d.n_new > 0 else None
+        dev_steps.append((d.n_new,
+                          torch.from_numpy(d.i.astype(np.int32)).to(dev),
+                          torch.from_numpy(d.j.astype(np.int32)).to(dev),
+                          torch.from_numpy(d.sign.astype(np.int8)).to(dev),
+                          None if om is None else torch.from_numpy(om).to(dev),
+                          d.n_changes))
+    n_final = wl.n_at(n_steps)
+    nnz_cap = int(wl.col0.size + 2 * sum(s[5] for s in dev_steps) + 1024)
+    torch.cuda.synchronize()
+
+    def make_state(prec):
+        st = G.State(wl.rowptr0, wl.col0, k=K, variant="rsvd", op="adj", precision=prec, L=L, P=P,
+                     stream=torch.cuda.current_stream().cuda_stream, node_capacity=n_final + 1,
+                     nnz_capacity=nnz_cap)
+        st.init_pairs(iterations=args.init_iters, seed=7)
+        return st
+
+    def run_path(prec):
+        # warmup on its own state (same trajectory), then a fresh state for the timed steps
+        st = make_state(prec)
+        for s in dev_steps[:args.warmup]:
+            st.update(s[0], s[1], s[2], s[3], s[4])
+        st.sync()
+        st.close()
+        st = make_state(prec)
+        st.profile(True)
+        sizes = []
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for s in dev_steps[:args.steps]:
+            st.update(s[0], s[1], s[2], s[3], s[4])
+            n2, nnz, _, width = st.shape()
+            sizes.append((n2, nnz, width))
+        st.sync()
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        stages, spmm_ms, nupd = st.stage_times()
+        vals = st.values()
+        st.close()
+        elem = 8 if prec == "fp64" else 4
+        byts = sum(spmm_bytes(n2, nnz, w, elem) for n2, nnz, w in sizes)
+        return {"seconds": te - ts, "stages_ms": stages, "spmm_ms": spmm_ms, "updates": nupd,
+                "spmm_bytes": byts, "sizes": sizes, "lambda1": float(vals[0])}
+
+    log(args, f"timing {args.precision} path: warmup {args.warmup}, steps {args.steps}")
+    main_res = run_path(args.precision)
+    cmp_res = None
+    if args.compare and args.compare != args.precision:
+        log(args, f"timing {args.compare} path")
+        cmp_res = run_path(args.compare)
+
+    secs = main_res["seconds"]
+    value = args.steps / secs
+    stages = main_res["stages_ms"]
+    dominant = max(stages, key=stages.get)
+    spmm_avg_ms = main_res["spmm_ms"] / max(1, main_res["updates"])
+    achieved = main_res["spmm_bytes"] / (main_res["spmm_ms"] * 1e-3) / 1e9 if main_res["spmm_ms"] > 0 else 0.0
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args)
+
+    out = {
+        "metric": "eigen-updates/sec at n=1M,k=32 (mixed vs FP32) + p50/p99 latency @ accuracy",
+        "value": round(value, 3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * secs / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "f32+bf16", "fp32": "f32", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "SBM n0=1e6, 32 Dirichlet(2) blocks, mean degree 20, +10k nodes/+50k edges "
+                               "per step; adjacency, k=32, G-REST_RSVD L=P=32 (width 96)",
+                   "n0": wl.n0, "k": K, "L": L, "P": P, "variant": "rsvd", "precision": args.precision,
+                   "scale": args.scale},
+        "stages_ms_per_update": {k: round(v / max(1, main_res["updates"]), 4) for k, v in stages.items()},
+        "dominant_stage": dominant,
+        "roofline": {"kernel": "spmm (product with the updated operator)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_ms": round(spmm_avg_ms, 4)},
+    }
+    if cmp_res is not None:
+        cv = args.steps / cmp_res["seconds"]
+        out["compare"] = {"precision": args.compare, "value": round(cv, 3),
+                          "ms_per_step": round(1e3 * cmp_res["seconds"] / args.steps, 3),
+                          "speedup_of_headline": round(value / cv, 3),
+                          "stages_ms_per_update": {k: round(v / max(1, cmp_res["updates"]), 4)
+                                                   for k, v in cmp_res["stages_ms"].items()}}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, args):
+    """The FP64 oracle on one update of the same workload (random orthonormal start, same
+    change list and test matrix), timed on this host's cores."""
+    import numpy as np
+    from oracle import grest_oracle as O
+    from paper_2603_19439_amd import workloads as W
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max((i.get("num_threads") or 1) for i in info) if info else os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    X0 = W.random_orthonormal(wl.n0, K, 0)
+    d = wl.deltas[0]
+    om = W.omega(wl.cfg_id, 0, 1, d.n_new, L + P)
+    log(args, "timing the CPU oracle on one update")
+    t = time.perf_counter()
+    O.grest_step(A, X0, np.zeros(K), d.n_new, d.i, d.j, d.sign, K, variant=O.RSVD, L=L, Omega=om)
+    dt = time.perf_counter() - t
+    return {"value": round(1.0 / dt, 5), "unit": "updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"one update (step 1) of the same workload, n0={wl.n0}, FP64 NumPy/SciPy, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,19 @@ grest_status grest_shape(const grest_state* st, int64_t* n, int64_t* nnz, int32_
  */
 grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col);
 
+/*
+ * Stage timing with HIP events recorded on the state's stream around the stages of
+ * every update while enabled: 0 graph update and validation (with its host wait),
+ * 1 padding and Delta Xbar, 2 augmentation block, 3 projections and CholQR2,
+ * 4 product with the updated operator, 5 projected matrix Z^T (A Z), 6 small
+ * eigensolve, 7 back-projection.  grest_profile(st, 1) enables and clears the
+ * totals; grest_stage_times returns the accumulated milliseconds per stage, the
+ * milliseconds of the sparse product kernel alone, and the number of updates.
+ */
+grest_status grest_profile(grest_state* st, int32_t enable);
+grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stages, double* spmm_ms,
+                               int64_t* updates);
+
 /* Release the state and all its device memory. */
 void grest_destroy(grest_state* st);
 

@@ -112,7 +112,39 @@ struct grest_state {
   double* theta_pin = nullptr;
   int32_t deferred = 0;
   int64_t partial_elems = 0;
+
+  // optional stage timing with HIP events on the state's stream
+  static constexpr int NSTAGE = 8;
+  bool prof = false;
+  bool prof_pending = false;
+  hipEvent_t pev[NSTAGE + 1] = {};
+  hipEvent_t kev[2] = {};  // around the (op Z) product alone
+  double stage_ms[NSTAGE] = {};
+  double spmm_ms = 0.0;
+  int64_t prof_updates = 0;
+  bool marking = false;
 };
+
+namespace {
+
+void mark(grest_state* st, int i) {
+  if (st->marking) (void)hipEventRecord(st->pev[i], st->stream);
+}
+
+// add the stage times of the last completed update (its events have completed)
+void prof_collect(grest_state* st) {
+  if (!st->prof_pending) return;
+  for (int i = 0; i < grest_state::NSTAGE; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, st->pev[i], st->pev[i + 1]) == hipSuccess) st->stage_ms[i] += ms;
+  }
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, st->kev[0], st->kev[1]) == hipSuccess) st->spmm_ms += ms;
+  st->prof_updates += 1;
+  st->prof_pending = false;
+}
+
+}  // namespace
 
 namespace {
 
@@ -284,16 +316,22 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
                            int base, int32_t* rank_slot) {
   Blocks<T> b = blocks<T>(st);
   // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
+  if (st->marking) HIPCHK(hipEventRecord(st->kev[0], st->stream));
   launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc, st->ldz, n2, st->D, b.aux, st->D, st->stream);
+  if (st->marking) HIPCHK(hipEventRecord(st->kev[1], st->stream));
+  mark(st, 5);
   // H = Z^T (op Z)
   if (st->prec == GREST_FP64) launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
   else launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
   // small FP64 eigensolve on the leading K + rank block, selection of K pairs
+  mark(st, 6);
   const int which = st->op == GREST_OP_ADJ ? 0 : 1;
   launch_small_eig(st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
                    st->status, st->stream);
   // X' = Z F_K into the other buffer
+  mark(st, 7);
   launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
+  mark(st, 8);
   return GREST_OK;
 }
 
@@ -319,6 +357,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   }
   const int gn = st->gcur ^ 1;
   // ---- graph update and validation (Sec. 2, eq. adj_update) ----
+  st->marking = st->prof;
+  mark(st, 0);
   launch_fill_bytes0(st->status, sizeof(int32_t), s);
   launch_fill_bytes0(st->maxdeg, sizeof(int64_t), s);
   launch_fill_i64(st->dcnt, 0, n2 + 1, s);
@@ -338,6 +378,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   HIPCHK(hipMemcpyAsync(&st->pin->maxdeg, st->maxdeg, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (st->pin->status & VALIDATION_BITS) {
+    st->marking = false;
     snprintf(g_last_error, sizeof(g_last_error), "change list rejected (status bits 0x%x)", st->pin->status);
     return GREST_EINVAL;
   }
@@ -346,6 +387,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   Blocks<T> b = blocks<T>(st);
   const T* sc_new = (const T*)st->sc[gn];
   // ---- pad Xbar (Alg. 2): zero the appended rows of the whole basis row ----
+  mark(st, 1);
   launch_fill_rows<T>(b.Zc, st->ldz, n, S, st->ldz, s);
   // ---- Delta Xbar = Delta_1 X (Prop. 3) into W[:, 0:K] ----
   if (st->op == GREST_OP_NLAP) {
@@ -355,6 +397,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     launch_delta_mul<T>(0, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Zc, st->ldz, st->K,
                         b.W, st->ldz, s);
   }
+  mark(st, 2);
   T* B2 = b.W + st->K;
   const int w2 = st->Dw - st->K;
   // ---- augmentation block ----
@@ -394,15 +437,19 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_apply<T>(n2, b.Y, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, B2, st->ldz, s);
     }
   }
+  mark(st, 3);
   // ---- projection (I - Xbar Xbar^T) W, twice; CholQR2 of W ----
   project_twice<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, st->C1, st->C2);
   cholqr2<T>(st, n2, b.W, st->ldz, st->Dw, st->C1, st->C2, 0);
+  mark(st, 4);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
   CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->K, st->ranks + 1));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   // ---- commit ----
+  if (st->marking) st->prof_pending = true;
+  st->marking = false;
   st->gcur = gn;
   st->zcur ^= 1;
   st->n = n2;
@@ -683,6 +730,7 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
   if (where == GREST_HOST && !host_changes_ok(st->n, n_new, n_changes, ei, ej, sign)) return GREST_EINVAL;
   // pull in the status of the previous update before overwriting the pinned word
   HIPCHK(hipStreamSynchronize(st->stream));
+  prof_collect(st);
   st->deferred |= st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED);
   return st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where)
                      : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where);
@@ -691,6 +739,7 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
 grest_status grest_sync(grest_state* st) {
   if (!st) return GREST_EINVAL;
   HIPCHK(hipStreamSynchronize(st->stream));
+  prof_collect(st);
   int32_t bits = st->deferred | (st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED));
   st->deferred = 0;
   st->pin->status = 0;
@@ -725,9 +774,40 @@ grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col) {
   return GREST_OK;
 }
 
+grest_status grest_profile(grest_state* st, int32_t enable) {
+  if (!st) return GREST_EINVAL;
+  HIPCHK(hipStreamSynchronize(st->stream));
+  if (enable && !st->pev[0]) {
+    for (int i = 0; i <= grest_state::NSTAGE; ++i) HIPCHK(hipEventCreate(&st->pev[i]));
+    HIPCHK(hipEventCreate(&st->kev[0]));
+    HIPCHK(hipEventCreate(&st->kev[1]));
+  }
+  st->prof = enable != 0;
+  st->prof_pending = false;
+  for (int i = 0; i < grest_state::NSTAGE; ++i) st->stage_ms[i] = 0.0;
+  st->spmm_ms = 0.0;
+  st->prof_updates = 0;
+  return GREST_OK;
+}
+
+grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stages, double* spmm_ms,
+                               int64_t* updates) {
+  if (!st) return GREST_EINVAL;
+  HIPCHK(hipStreamSynchronize(st->stream));
+  prof_collect(st);
+  for (int i = 0; i < n_stages && i < grest_state::NSTAGE; ++i) stage_ms[i] = st->stage_ms[i];
+  if (spmm_ms) *spmm_ms = st->spmm_ms;
+  if (updates) *updates = st->prof_updates;
+  return GREST_OK;
+}
+
 void grest_destroy(grest_state* st) {
   if (!st) return;
   (void)hipStreamSynchronize(st->stream);
+  for (int i = 0; i <= grest_state::NSTAGE; ++i)
+    if (st->pev[i]) (void)hipEventDestroy(st->pev[i]);
+  if (st->kev[0]) (void)hipEventDestroy(st->kev[0]);
+  if (st->kev[1]) (void)hipEventDestroy(st->kev[1]);
   free_all(st);
   if (st->own_stream) (void)hipStreamDestroy(st->stream);
   delete st;

@@ -55,6 +55,9 @@ _SIGS = [
     ("grest_shape", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32)]),
     ("grest_get_graph", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grest_profile", C.c_int, [C.c_void_p, C.c_int32]),
+    ("grest_stage_times", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int64)]),
     ("grest_destroy", None, [C.c_void_p]),
 ]
 
@@ -65,6 +68,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_19439_amd.build`")
+        # Load torch's HIP runtime first: libgrest then binds to the same libamdhip64.so.7,
+        # so device memory and streams handed over by torch belong to one runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             f = getattr(L, name)
@@ -191,6 +200,21 @@ class State:
         vals = np.empty(k, dtype=np.float64)
         _check(lib().grest_get(self._h, vals.ctypes.data_as(C.c_void_p), None, F64, HOST), "grest_get")
         return vals
+
+    STAGES = ["graph_update", "delta_x", "augment", "project_orth", "spmm", "projected_matrix", "small_eig",
+              "back_projection"]
+
+    def profile(self, enable: bool = True):
+        _check(lib().grest_profile(self._h, int(bool(enable))), "grest_profile")
+
+    def stage_times(self):
+        """({stage: total ms}, total ms of the sparse-product kernel alone, updates timed)."""
+        ms = np.zeros(len(self.STAGES), dtype=np.float64)
+        spmm = C.c_double()
+        cnt = C.c_int64()
+        _check(lib().grest_stage_times(self._h, ms.ctypes.data_as(C.c_void_p), len(self.STAGES), C.byref(spmm),
+                                       C.byref(cnt)), "grest_stage_times")
+        return dict(zip(self.STAGES, ms.tolist())), spmm.value, cnt.value
 
     def graph(self):
         n, m, _, _ = self.shape()
