@@ -321,8 +321,14 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   if (st->marking) HIPCHK(hipEventRecord(st->kev[1], st->stream));
   mark(st, 5);
   // H = Z^T (op Z)
-  if (st->prec == GREST_FP64) launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
-  else launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+  if constexpr (sizeof(T) == 4) {
+    if (st->prec == GREST_MIXED)
+      launch_tn_bf16(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+    else
+      launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+  } else {
+    launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+  }
   // small FP64 eigensolve on the leading K + rank block, selection of K pairs
   mark(st, 6);
   const int which = st->op == GREST_OP_ADJ ? 0 : 1;
@@ -330,7 +336,14 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
                    st->status, st->stream);
   // X' = Z F_K into the other buffer
   mark(st, 7);
-  launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
+  if constexpr (sizeof(T) == 4) {
+    if (st->prec == GREST_MIXED)
+      launch_apply_bf16(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, b.Zn, st->ldz, st->stream);
+    else
+      launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
+  } else {
+    launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
+  }
   mark(st, 8);
   return GREST_OK;
 }

@@ -91,20 +91,20 @@ def test_sbm_n2000_fp64_g3_full_trajectory():
     run_trajectory(wl, 8, "g3", "adj", "fp64", 10, max_new=100)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_sbm_small_g2(prec):
     wl = W.preset("sbm_n2000", scale=0.5, steps=3)
     run_trajectory(wl, 8, "g2", "adj", prec, 3)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_sbm_large_shape_rsvd(prec):
     """Dirichlet SBM scaled to n0=20000 with RSVD (L=P=16), K=16."""
     wl = W.preset("sbm_n1e6", scale=0.02, steps=3)
     run_trajectory(wl, 16, "rsvd", "adj", prec, 3, L=16, P=16)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_chunglu_normalized_laplacian(prec):
     """Chung-Lu (gamma 2.5, mean 16) with edge churn, normalised Laplacian, K=16, G-REST2."""
     wl = W.preset("chunglu_n1e5", scale=0.05, steps=3)
