@@ -133,9 +133,13 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const Ti
                                                 int a, const Tin* __restrict__ B, int64_t ldb, int b,
                                                 double* __restrict__ partial) {
   constexpr int RB = 32;
-  // column-major staging so that a lane's eight consecutive rows are one 16-byte read
+  // column-major staging so that a lane's eight consecutive rows are one 16-byte read;
+  // every value is split into hi = bf16(x) and lo = bf16(x - hi), and the product is
+  // hi*hi + hi*lo + lo*hi (relative error ~ 2^-16 instead of 2^-8)
   __shared__ __attribute__((aligned(16))) __bf16 sA[TW][RB + 8];
   __shared__ __attribute__((aligned(16))) __bf16 sB[TW][RB + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[TW][RB + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[TW][RB + 8];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int TA = (a + 15) >> 4, TB = (b + 15) >> 4;
   int ti[MAXT], tj[MAXT];
@@ -155,16 +159,26 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const Ti
       const int rr = 2 * p + lr;
       const int64_t row = rb + rr;
       const bool ok = row < r1;
-      sA[lc][rr] = (__bf16)((ok && lc < a) ? (float)A[row * lda + lc] : 0.f);
-      sB[lc][rr] = (__bf16)((ok && lc < b) ? (float)B[row * ldb + lc] : 0.f);
+      const float xa = (ok && lc < a) ? (float)A[row * lda + lc] : 0.f;
+      const float xb = (ok && lc < b) ? (float)B[row * ldb + lc] : 0.f;
+      const __bf16 ha = (__bf16)xa, hb = (__bf16)xb;
+      sA[lc][rr] = ha;
+      sB[lc][rr] = hb;
+      sAl[lc][rr] = (__bf16)(xa - (float)ha);
+      sBl[lc][rr] = (__bf16)(xb - (float)hb);
     }
     __syncthreads();
     const int kr = 8 * (lane >> 4);
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) {
       if (ti[q] < 0) continue;
-      const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sA[ti[q] * 16 + (lane & 15)][kr]);
-      const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&sB[tj[q] * 16 + (lane & 15)][kr]);
+      const int ia = ti[q] * 16 + (lane & 15), ib = tj[q] * 16 + (lane & 15);
+      const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sA[ia][kr]);
+      const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&sB[ib][kr]);
+      const bf16x8 fal = *reinterpret_cast<const bf16x8*>(&sAl[ia][kr]);
+      const bf16x8 fbl = *reinterpret_cast<const bf16x8*>(&sBl[ib][kr]);
+      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fal, fb, acc[q], 0, 0, 0);
+      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fbl, acc[q], 0, 0, 0);
       acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[q], 0, 0, 0);
     }
   }
@@ -270,11 +284,16 @@ __global__ void __launch_bounds__(WG) k_apply_bf16(int64_t n, const float* In, i
                                                    float* Out, int64_t ldout) {
   const int KB = (a + 31) >> 5, TB = (b + 15) >> 4;
   const int kp = KB * 32;
-  // transposed: sMt[j][k], so that eight consecutive k of one column are one 16-byte read
+  // transposed: sMt[j][k], so that eight consecutive k of one column are one 16-byte read;
+  // hi/lo split of both operands as in k_tn_bf16
   __shared__ __attribute__((aligned(16))) __bf16 sMt[TW][TW + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sMl[TW][TW + 8];
   for (int idx = threadIdx.x; idx < TB * 16 * kp; idx += WG) {
     const int j = idx / kp, k = idx % kp;
-    sMt[j][k] = (__bf16)((k < a && j < b) ? (float)(alpha * Mg[(size_t)k * b + j]) : 0.f);
+    const float x = (k < a && j < b) ? (float)(alpha * Mg[(size_t)k * b + j]) : 0.f;
+    const __bf16 h = (__bf16)x;
+    sMt[j][k] = h;
+    sMl[j][k] = (__bf16)(x - (float)h);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -283,14 +302,18 @@ __global__ void __launch_bounds__(WG) k_apply_bf16(int64_t n, const float* In, i
   for (int64_t tile = (int64_t)blockIdx.x * NW + wid; tile < ntile; tile += (int64_t)gridDim.x * NW) {
     const int64_t row0 = tile * 16;
     const int64_t row = row0 + c16;
-    bf16x8 fin[4];
+    bf16x8 fin[4], finl[4];
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
       if (kb < KB) {
         const int k0 = kb * 32 + 8 * g;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          fin[kb][e] = (__bf16)((row < n && k0 + e < a) ? In[row * ldin + k0 + e] : 0.f);
+        for (int e = 0; e < 8; ++e) {
+          const float x = (row < n && k0 + e < a) ? In[row * ldin + k0 + e] : 0.f;
+          const __bf16 h = (__bf16)x;
+          fin[kb][e] = h;
+          finl[kb][e] = (__bf16)(x - (float)h);
+        }
       }
     }
     for (int jt = 0; jt < TB; ++jt) {
@@ -299,6 +322,9 @@ __global__ void __launch_bounds__(WG) k_apply_bf16(int64_t n, const float* In, i
       for (int kb = 0; kb < 4; ++kb) {
         if (kb < KB) {
           const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&sMt[jt * 16 + c16][kb * 32 + 8 * g]);
+          const bf16x8 fbl = *reinterpret_cast<const bf16x8*>(&sMl[jt * 16 + c16][kb * 32 + 8 * g]);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(finl[kb], fb, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fin[kb], fbl, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fin[kb], fb, acc, 0, 0, 0);
         }
       }

@@ -5,10 +5,12 @@
 //   * the dense symmetric eigensolver of the projected matrix (Alg. 1, small
 //     eigenproblem) and of the sketch Gram B B^T of the randomized range finder
 //     (Sec. 3.5), followed by the selection of the wanted pairs.
-// The eigensolver is Householder tridiagonalisation, explicit accumulation of the
-// orthogonal factor, and implicit symmetric QR steps with the Wilkinson shift; the
-// bulge chase runs on one lane and every lane applies the sweep's plane rotations
-// to its own row of the eigenvector matrix.  Matrices up to SMALL_LDS_D live in LDS,
+// The eigensolver is Householder tridiagonalisation (reflectors kept in place), all
+// eigenvalues of the tridiagonal by bisection on the LDL^T inertia (one lane per
+// eigenvalue), eigenvectors of the selected ones only by inverse iteration with an
+// LU factorisation with partial pivoting (clusters closer than 1e-3 ||T|| get distinct
+// shifts and reorthogonalisation on one lane), and the back-transform through the
+// reflectors with eight lanes per vector.  Matrices up to SMALL_LDS_D live in LDS,
 // larger ones in a global workspace.
 #include "grest_internal.h"
 
@@ -128,11 +130,7 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < m * m; idx += EB) {
-    int a = idx / m, j = idx % m;  // output M[a][j]
-    M[idx] = 0.0;
-    (void)a;
-  }
+  for (int idx = tid; idx < m * m; idx += EB) M[idx] = 0.0;
   __syncthreads();
   for (int idx = tid; idx < m * m; idx += EB) {
     int i = idx / m, j = idx % m;
@@ -160,21 +158,43 @@ __device__ inline bool sel_less(int which, double ta, int ia, double tb, int ib)
   return ia < ib;
 }
 
+// LDL^T inertia of T - x I: the number of eigenvalues of the tridiagonal (dg, e2 = e^2)
+// below x (Sturm count); tiny pivots are replaced by -pivmin.
+__device__ inline int sturm_count(const double* dg, const double* e2, int n, double x, double pivmin) {
+  double q = dg[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = (dg[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+__device__ inline double hash_unit(uint32_t a, uint32_t b) {
+  uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+  h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
+  return ((double)(h & 0xFFFFFF) / 16777216.0) - 0.5;
+}
+
 template <bool IN_LDS>
 __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const int32_t* rank_p,
                                                   const double* H, int which, int kk, double drop_tol,
                                                   double* theta_out, double* F, int32_t* kept_out,
                                                   double* work, int32_t* status) {
   __shared__ double sA[IN_LDS ? SMALL_LDS_D * (SMALL_LDS_D + 1) : 1];
-  __shared__ double dg[MAXD], od[MAXD], vv[MAXD], pw[MAXD], hb[MAXD];
-  __shared__ double rc[MAXD], rs[MAXD];
+  __shared__ double dg[MAXD], od[MAXD], e2[MAXD], vv[MAXD], pw[MAXD], hb[MAXD], ev[MAXD];
   __shared__ double red[EB / GREST_WAVE];
-  __shared__ int sh[4];
+  __shared__ int sel[MAXD], slot_of[MAXD], srt[MAXD];
+  __shared__ double sh_d[4];
+  __shared__ int sh_i[2];
   const int tid = threadIdx.x;
   int n = base + (rank_p ? rank_p[0] : 0);
   if (n > d_full) n = d_full;
   if (n < 0) n = 0;
   double* A = IN_LDS ? sA : work;
+  double* scratch = IN_LDS ? work : work + (size_t)(d_full + 1) * (d_full + 1);
   const int lda = n + 1;
 
   int bad = 0;
@@ -187,7 +207,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   if (bad) atomicOr(status, ST_NONFINITE);
   __syncthreads();
 
-  // ---- Householder tridiagonalisation (A = Q T Q^T) ----
+  // ---- Householder tridiagonalisation; reflector k stored below the subdiagonal ----
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     double part = 0.0;
@@ -208,7 +228,6 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
     if (tid == 0) { dg[k] = A[k * lda + k]; od[k] = ek; hb[k] = beta; }
     __syncthreads();
     if (beta != 0.0) {
-      // p = beta * A22 v
       for (int i = tid; i < m; i += EB) {
         const double* row = A + (k + 1 + i) * lda + (k + 1);
         double acc = 0.0;
@@ -219,14 +238,13 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
       double pv = 0.0;
       for (int i = tid; i < m; i += EB) pv += pw[i] * vv[i];
       const double K = 0.5 * beta * block_sum(pv, red);
-      for (int i = tid; i < m; i += EB) pw[i] -= K * vv[i];  // w
+      for (int i = tid; i < m; i += EB) pw[i] -= K * vv[i];
       __syncthreads();
       for (int idx = tid; idx < m * m; idx += EB) {
         int i = idx / m, j = idx % m;
         A[(k + 1 + i) * lda + (k + 1 + j)] -= vv[i] * pw[j] + pw[i] * vv[j];
       }
     }
-    // keep v (below its implicit leading 1) in column k
     for (int i = 1 + tid; i < m; i += EB) A[(k + 1 + i) * lda + k] = vv[i];
     __syncthreads();
   }
@@ -237,139 +255,182 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
       hb[n - 2] = 0.0;
     }
     if (n >= 1) dg[n - 1] = A[(n - 1) * lda + (n - 1)];
+    // Gershgorin interval, norm, pivot floor
+    double lo = 0.0, hi = 0.0, tn = 0.0, emax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < n ? fabs(od[i]) : 0.0);
+      lo = (i == 0) ? dg[i] - r : fmin(lo, dg[i] - r);
+      hi = (i == 0) ? dg[i] + r : fmax(hi, dg[i] + r);
+      tn = fmax(tn, fabs(dg[i]) + r);
+      if (i + 1 < n) { e2[i] = od[i] * od[i]; emax = fmax(emax, e2[i]); }
+    }
+    const double pad = 4.0 * 2.220446049250313e-16 * fmax(tn, 1e-300) + 1e-300;
+    sh_d[0] = lo - pad;
+    sh_d[1] = hi + pad;
+    sh_d[2] = tn;
+    sh_d[3] = 1e-290 * fmax(1.0, emax);
   }
   __syncthreads();
 
-  // ---- explicit Q = P_0 P_1 ... P_{n-3}, accumulated backwards in place ----
-  if (n >= 1 && tid == 0) A[(n - 1) * lda + (n - 1)] = 1.0;
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const int m = n - k - 1;
-    for (int i = tid; i < m; i += EB) vv[i] = (i == 0) ? 1.0 : A[(k + 1 + i) * lda + k];
-    __syncthreads();
-    // row k+1 and column k+1 of the block become the identity's
-    for (int j = tid; j < m; j += EB) {
-      A[(k + 1) * lda + (k + 1 + j)] = (j == 0) ? 1.0 : 0.0;
-      if (j > 0) A[(k + 1 + j) * lda + (k + 1)] = 0.0;
-    }
-    __syncthreads();
-    const double beta = hb[k];
-    if (beta != 0.0) {
-      for (int j = tid; j < m; j += EB) {
-        double acc = 0.0;
-        for (int i = 0; i < m; ++i) acc += vv[i] * A[(k + 1 + i) * lda + (k + 1 + j)];
-        pw[j] = beta * acc;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < m * m; idx += EB) {
-        int i = idx / m, j = idx % m;
-        A[(k + 1 + i) * lda + (k + 1 + j)] -= vv[i] * pw[j];
-      }
-      __syncthreads();
-    }
-  }
-  if (n >= 2) {
-    for (int j = tid; j < n; j += EB) {
-      A[0 * lda + j] = (j == 0) ? 1.0 : 0.0;
-      if (j > 0) A[j * lda + 0] = 0.0;
-    }
-    if (n == 2 && tid == 0) { A[1 * lda + 1] = 1.0; }
-  } else if (n == 1 && tid == 0) {
-    A[0] = 1.0;
-  }
-  __syncthreads();
-
-  // ---- implicit symmetric QR with the Wilkinson shift ----
+  // ---- eigenvalues: one lane per index, bisection on the inertia count ----
   const double eps = 2.220446049250313e-16;
-  int sweeps = 0;
-  const int max_sweeps = 30 * (n > 1 ? n : 1);
-  while (true) {
-    if (tid == 0) {
-      int hi = sh[1];
-      if (sweeps == 0) hi = n - 1;
-      while (hi > 0 && fabs(od[hi - 1]) <= eps * (fabs(dg[hi - 1]) + fabs(dg[hi])) + 1e-300) {
-        od[hi - 1] = 0.0;
-        --hi;
-      }
-      if (hi <= 0 || sweeps >= max_sweeps) {
-        if (hi > 0) atomicOr(status, ST_NOT_CONVERGED);
-        sh[0] = -1;
-      } else {
-        int lo = hi - 1;
-        while (lo > 0 && fabs(od[lo - 1]) > eps * (fabs(dg[lo - 1]) + fabs(dg[lo])) + 1e-300) --lo;
-        const double b = od[hi - 1];
-        const double delta = 0.5 * (dg[hi - 1] - dg[hi]);
-        const double h = hypot(delta, b);
-        const double den = delta + (delta >= 0.0 ? h : -h);
-        const double mu = (den != 0.0) ? dg[hi] - b * b / den : dg[hi];
-        double p = dg[lo] - mu, q = od[lo];
-        for (int k = lo; k < hi; ++k) {
-          double r = hypot(p, q);
-          double c = 1.0, s = 0.0;
-          if (r > 0.0) { c = p / r; s = -q / r; }
-          if (k > lo) od[k - 1] = r;
-          const double a = dg[k], bb = od[k], e2 = dg[k + 1];
-          const double cc = c * c, ss = s * s, cs = c * s;
-          dg[k] = cc * a - 2.0 * cs * bb + ss * e2;
-          dg[k + 1] = ss * a + 2.0 * cs * bb + cc * e2;
-          od[k] = cs * (a - e2) + (cc - ss) * bb;
-          if (k + 1 < hi) {
-            q = -s * od[k + 1];
-            od[k + 1] = c * od[k + 1];
-            p = od[k];
-          }
-          rc[k] = c;
-          rs[k] = s;
-        }
-        sh[0] = lo;
-        sh[1] = hi;
-      }
+  const double pivmin = sh_d[3];
+  const double tnorm = sh_d[2];
+  for (int t = tid; t < n; t += EB) {
+    double lo = sh_d[0], hi = sh_d[1];
+    for (int it = 0; it < 80; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+      if (sturm_count(dg, e2, n, mid, pivmin) > t) hi = mid; else lo = mid;
     }
-    __syncthreads();
-    const int lo = sh[0];
-    if (lo < 0) break;
-    const int hi = sh[1];
-    ++sweeps;
-    for (int i = tid; i < n; i += EB) {
-      double* row = A + i * lda;
-      double cur = row[lo];
-      for (int k = lo; k < hi; ++k) {
-        const double c = rc[k], s = rs[k];
-        const double nxt = row[k + 1];
-        row[k] = c * cur - s * nxt;
-        cur = s * cur + c * nxt;
-      }
-      row[hi] = cur;
-    }
-    __syncthreads();
+    ev[t] = 0.5 * (lo + hi);
   }
-
-  // ---- selection ----
-  if (tid == 0) sh[2] = 0;
+  for (int i = tid; i < MAXD; i += EB) { slot_of[i] = -1; }
   __syncthreads();
+
+  // ---- selection of kk pairs (ev is ascending) ----
   double tmax = 0.0;
-  for (int i = 0; i < n; ++i) tmax = fmax(tmax, dg[i]);
+  for (int i = 0; i < n; ++i) tmax = fmax(tmax, ev[i]);
   const double keep_thr = drop_tol > 0.0 ? drop_tol * drop_tol * fmax(1.0, tmax) : -INFINITY;
   for (int i = tid; i < n; i += EB) {
-    const double ti = dg[i];
     int rank = 0;
     for (int j = 0; j < n; ++j)
-      if (j != i && sel_less(which, dg[j], j, ti, i)) ++rank;
-    if (rank < kk) {
-      const bool keep = !(drop_tol > 0.0) || ti > keep_thr;
-      theta_out[rank] = keep ? ti : 0.0;
-      if (keep) atomicAdd(&sh[2], 1);
-      for (int r = 0; r < d_full; ++r)
-        F[(size_t)r * kk + rank] = (keep && r < n) ? A[r * lda + i] : 0.0;
-    }
-  }
-  // slots beyond n (fewer pairs than requested) are zero
-  for (int slot = n + tid; slot < kk; slot += EB) {
-    theta_out[slot] = 0.0;
-    for (int r = 0; r < d_full; ++r) F[(size_t)r * kk + slot] = 0.0;
+      if (j != i && sel_less(which, ev[j], j, ev[i], i)) ++rank;
+    if (rank < kk) { sel[rank] = i; slot_of[i] = rank; }
   }
   __syncthreads();
-  if (tid == 0 && kept_out) *kept_out = sh[2];
+  const int nsel = kk < n ? kk : n;
+  if (tid == 0) {  // selected indices in ascending order
+    int c = 0;
+    for (int i = 0; i < n; ++i)
+      if (slot_of[i] >= 0) srt[c++] = i;
+  }
+  __syncthreads();
+
+  // ---- eigenvectors of T by inverse iteration; a cluster (gaps below 1e-3 ||T||) is
+  //      handled by one lane with distinct shifts and reorthogonalisation ----
+  const double ortol = 1e-3 * tnorm;
+  for (int q = tid; q < nsel; q += EB) {
+    if (q > 0 && ev[srt[q]] - ev[srt[q - 1]] <= ortol) continue;  // not a cluster leader
+    double* u0 = scratch + (size_t)q * 6 * MAXD;
+    double* u1 = u0 + MAXD;
+    double* u2 = u1 + MAXD;
+    double* lm = u2 + MAXD;
+    double* x = lm + MAXD;
+    double* piv = x + MAXD;
+    double shift_prev = -INFINITY;
+    for (int p = q; p < nsel && (p == q || ev[srt[p]] - ev[srt[p - 1]] <= ortol); ++p) {
+      const int idx = srt[p];
+      const int slot = slot_of[idx];
+      double lam = ev[idx];
+      if (p > q) lam = fmax(lam, shift_prev + 10.0 * eps * fmax(tnorm, 1e-300));
+      shift_prev = lam;
+      // LU with partial pivoting of T - lam I (three upper diagonals)
+      double a = dg[0] - lam, bsup = n > 1 ? od[0] : 0.0;
+      for (int i = 0; i + 1 < n; ++i) {
+        const double c = od[i];                    // (i+1, i)
+        const double an = dg[i + 1] - lam;         // (i+1, i+1)
+        const double bn = i + 2 < n ? od[i + 1] : 0.0;  // (i+1, i+2)
+        if (fabs(a) >= fabs(c)) {
+          const double piv_a = (a == 0.0) ? pivmin : a;
+          const double l = c / piv_a;
+          u0[i] = piv_a; u1[i] = bsup; u2[i] = 0.0; lm[i] = l; piv[i] = 0.0;
+          a = an - l * bsup;
+          bsup = bn;
+        } else {
+          const double l = a / c;
+          u0[i] = c; u1[i] = an; u2[i] = bn; lm[i] = l; piv[i] = 1.0;
+          a = bsup - l * an;
+          bsup = -l * bn;
+        }
+      }
+      u0[n - 1] = (a == 0.0) ? pivmin : a;
+      for (int i = 0; i < n; ++i) x[i] = hash_unit(i, slot + 1);
+      for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i + 1 < n; ++i) {  // L^{-1} with the row interchanges
+          if (piv[i] != 0.0) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
+          x[i + 1] -= lm[i] * x[i];
+        }
+        for (int i = n - 1; i >= 0; --i) {  // U^{-1}
+          double v = x[i];
+          if (i + 1 < n) v -= u1[i] * x[i + 1];
+          if (i + 2 < n) v -= u2[i] * x[i + 2];
+          x[i] = v / u0[i];
+        }
+        for (int pp = q; pp < p; ++pp) {  // against the finished members of the cluster
+          const int sl = slot_of[srt[pp]];
+          double dot = 0.0;
+          for (int i = 0; i < n; ++i) dot += x[i] * F[(size_t)i * kk + sl];
+          for (int i = 0; i < n; ++i) x[i] -= dot * F[(size_t)i * kk + sl];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
+        nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+        for (int i = 0; i < n; ++i) x[i] *= nrm;
+      }
+      for (int i = 0; i < n; ++i) F[(size_t)i * kk + slot] = x[i];
+    }
+  }
+  __syncthreads();
+
+  // ---- back-transform x <- P_0 ... P_{n-3} x; eight lanes per vector, rows interleaved ----
+  constexpr int G = 8, RMAX = MAXD / G;
+  const int grp = tid / G, gl = tid % G;
+  for (int s0 = 0; s0 < nsel; s0 += EB / G) {
+    const int slot = s0 + grp;
+    const bool act = slot < nsel;
+    double xr[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+      const int r = gl + G * c;
+      xr[c] = (act && r < n) ? F[(size_t)r * kk + slot] : 0.0;
+    }
+    for (int k = n - 3; k >= 0; --k) {
+      const double beta = hb[k];
+      if (beta == 0.0) continue;
+      double dot = 0.0;
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) {
+        const int r = gl + G * c;
+        if (r >= k + 1 && r < n) dot += (r == k + 1 ? 1.0 : A[r * lda + k]) * xr[c];
+      }
+#pragma unroll
+      for (int o = 1; o < G; o <<= 1) dot += __shfl_xor(dot, o, G);
+      dot *= beta;
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) {
+        const int r = gl + G * c;
+        if (r >= k + 1 && r < n) xr[c] -= dot * (r == k + 1 ? 1.0 : A[r * lda + k]);
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) {
+        const int r = gl + G * c;
+        if (r < d_full) F[(size_t)r * kk + slot] = (r < n) ? xr[c] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- values, dropped columns, kept count ----
+  if (tid == 0) sh_i[0] = 0;
+  __syncthreads();
+  for (int slot = tid; slot < kk; slot += EB) {
+    if (slot < nsel) {
+      const double ti = ev[sel[slot]];
+      const bool keep = !(drop_tol > 0.0) || ti > keep_thr;
+      theta_out[slot] = keep ? ti : 0.0;
+      if (keep) atomicAdd(&sh_i[0], 1);
+      else for (int r = 0; r < d_full; ++r) F[(size_t)r * kk + slot] = 0.0;
+    } else {
+      theta_out[slot] = 0.0;
+      for (int r = 0; r < d_full; ++r) F[(size_t)r * kk + slot] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && kept_out) *kept_out = sh_i[0];
 }
 
 __global__ void k_symmetrize(int d, double* H) {
@@ -385,7 +446,7 @@ __global__ void k_symmetrize(int d, double* H) {
 
 }  // namespace
 
-int64_t eig_work_elems(int d) { return (int64_t)(d + 1) * (d + 1); }
+int64_t eig_work_elems(int d) { return (int64_t)(d + 1) * (d + 1) + (int64_t)6 * MAXD * MAXD; }
 
 void launch_pchol(int m, const double* G, const double* colsq1, const double* colsq2, int kc,
                   double tol, double* M, int32_t* rank, int32_t* status, hipStream_t s) {
