@@ -336,14 +336,8 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
                    st->status, st->stream);
   // X' = Z F_K into the other buffer
   mark(st, 7);
-  if constexpr (sizeof(T) == 4) {
-    if (st->prec == GREST_MIXED)
-      launch_apply_bf16(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, b.Zn, st->ldz, st->stream);
-    else
-      launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
-  } else {
-    launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
-  }
+  // X' = Z F on FP32 / FP64 MFMA (a memory-bound pass; FP32 keeps X orthonormal to 1e-7)
+  launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
   mark(st, 8);
   return GREST_OK;
 }

@@ -289,8 +289,9 @@ __global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, con
   }
 }
 
-__global__ void k_degrees(int64_t n, const int64_t* rp, double* s64, float* s32,
-                          unsigned long long* maxdeg) {
+__global__ void __launch_bounds__(BS) k_degrees(int64_t n, const int64_t* rp, double* s64, float* s32,
+                                                unsigned long long* maxdeg) {
+  __shared__ unsigned long long wmax[BS / GREST_WAVE];
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long mx = 0;
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += stride) {
@@ -305,7 +306,12 @@ __global__ void k_degrees(int64_t n, const int64_t* rp, double* s64, float* s32,
     unsigned long long y = __shfl_xor(mx, o, GREST_WAVE);
     mx = y > mx ? y : mx;
   }
-  if ((threadIdx.x & (GREST_WAVE - 1)) == 0) atomicMax(maxdeg, mx);
+  if ((threadIdx.x & (GREST_WAVE - 1)) == 0) wmax[threadIdx.x / GREST_WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one atomic per workgroup
+    for (int w = 1; w < BS / GREST_WAVE; ++w) mx = wmax[w] > mx ? wmax[w] : mx;
+    atomicMax(maxdeg, mx);
+  }
 }
 
 }  // namespace
@@ -372,6 +378,6 @@ void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const
 void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* dinv_sqrt32,
                     int64_t* maxdeg, hipStream_t s) {
   if (n <= 0) return;
-  k_degrees<<<grid_for(n, BS, 2048), BS, 0, s>>>(n, rp, dinv_sqrt64, dinv_sqrt32,
+  k_degrees<<<grid_for(n, BS, 1024), BS, 0, s>>>(n, rp, dinv_sqrt64, dinv_sqrt32,
                                                  (unsigned long long*)maxdeg);
 }

@@ -88,8 +88,6 @@ void launch_apply(int64_t n, const T* In, int64_t ldin, int a, const double* M, 
 // mixed precision: BF16 MFMA with FP32 accumulation (FP32 inputs)
 void launch_tn_bf16(int64_t n, const float* A, int64_t lda, int a, const float* B, int64_t ldb, int b,
                     double* partial, double* C, hipStream_t s);
-void launch_apply_bf16(int64_t n, const float* In, int64_t ldin, int a, const double* M, int b, double alpha,
-                       float* Out, int64_t ldout, hipStream_t s);
 template <typename T>
 void launch_fill_rows(T* p, int64_t ld, int64_t row0, int64_t rows, int w, hipStream_t s);
 template <typename Tsrc, typename Tdst>

@@ -1,17 +1,25 @@
-// Matrix-core (MFMA) kernels for the tall-skinny products of the update, gfx950:
-//   * k_tn_mfma : C = A^T B over n rows (A: n x a, B: n x b, a, b <= 128), per-workgroup
-//                 partial sums of 16 x 16 output tiles; FP64 MFMA (v_mfma_f64_16x16x4)
-//                 for FP64 accumulation (Gram matrices of CholQR2, FP64 projected
-//                 matrix), FP32 MFMA (v_mfma_f32_16x16x4) for FP32 accumulation, BF16
-//                 MFMA (v_mfma_f32_16x16x32_bf16) for the mixed-precision Z^T (A Z);
-//                 a symmetric mode computes only the upper tiles of a Gram matrix;
-//   * k_apply_mfma : Out = beta Out + alpha In M (M: a x b small, in LDS); same three
-//                 precisions (BF16 for the mixed back-projection Z F).
-// Rows are staged through LDS in row-major order; the contraction index of the
-// apply kernel is permuted inside each 16-wide block (lane group g feeds columns
-// 4g..4g+3 over four MFMA steps) so that every lane reads one 16-byte vector.
-// Output layouts (checked on the device): f32 and bf16 tiles give lane l, register r
-// the element (4*(l/16)+r, l%16); the f64 tile gives (l/16+4r, l%16).
+// Matrix-core (MFMA) kernels for the tall-skinny products of the update, gfx950.
+//
+//   * k_tnw    : C = A^T B over n rows (A: n x a, B: n x b, a, b <= 128) with FP32 or FP64
+//                MFMA (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64).  Every wave owns
+//                a disjoint set of 16-row blocks and keeps all output tiles of its slice
+//                in registers; each lane loads exactly the operand elements it feeds to the
+//                matrix core straight from global memory (16 rows per iteration, so that a
+//                wave has 4 (PA + PB) loads in flight).  The four waves of a workgroup are
+//                summed through LDS in a fixed order, and the workgroup partials are summed
+//                in a fixed order by k_tn_reduce, so results do not depend on scheduling.
+//                A symmetric mode (Gram matrices) computes the upper tiles only.
+//   * k_tn_bf16: the same product with split-BF16 MFMA (v_mfma_f32_16x16x32_bf16): every
+//                value is split into hi = bf16(x) and lo = bf16(x - hi) and the tile gets
+//                hi*hi + hi*lo + lo*hi with FP32 accumulation (relative error ~2^-16).  Rows
+//                are staged through LDS column-major (a lane's eight rows are one 16-byte
+//                read) and the next stage is prefetched into registers during the MFMAs.
+//   * k_apply  : Out = beta Out + alpha In M (M: a x b small, in LDS) with FP32 / FP64 MFMA;
+//                the contraction index is permuted inside each 16-wide block (lane group g
+//                feeds columns 4g..4g+3 over four MFMA steps) so every lane reads one
+//                16-byte vector; each wave keeps two 16-row tiles in flight.
+// Output layouts (checked on the device): f32 and bf16 tiles give lane l, register r the
+// element (4*(l/16)+r, l%16); the f64 tile gives (l/16+4r, l%16).
 #include "grest_internal.h"
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -23,7 +31,6 @@ namespace {
 constexpr int WG = 256;
 constexpr int NW = WG / GREST_WAVE;
 constexpr int TW = 128;      // widest operand
-constexpr int MAXT = 16;     // output tiles per wave
 constexpr int CHUNKS = 512;  // row chunks (= partial sums) of a reduction
 
 template <typename Tc>
@@ -49,128 +56,139 @@ struct Mma<double> {
 
 __device__ inline int bf16_row(int lane, int r) { return 4 * (lane >> 4) + r; }
 
-// tile t of this wave -> (ti, tj); symmetric mode enumerates ti <= tj only
-__device__ inline void decode_tile(int t, int TA, int TB, bool sym, int& ti, int& tj) {
-  if (!sym) {
-    ti = t / TB;
-    tj = t % TB;
-    if (ti >= TA) ti = -1;
-    return;
-  }
-  ti = 0;
-  while (ti < TA && t >= TB - ti) {
-    t -= TB - ti;
-    ++ti;
-  }
-  if (ti >= TA) { ti = -1; tj = -1; return; }
-  tj = ti + t;
-}
-
 // ---------------------------------------------------------------------------------
-// C = A^T B with FP32 / FP64 MFMA
+// C = A^T B, FP32 / FP64 MFMA, wave-owned rows, direct fragment loads
+// slice y covers tile-rows [y*PA, y*PA + PA); all tile-columns (< PB*16 >= b)
 // ---------------------------------------------------------------------------------
-template <typename Tin, typename Tc, bool SYM>
-__global__ void __launch_bounds__(WG) k_tn_mfma(int64_t n, int64_t rpc, const Tin* __restrict__ A, int64_t lda,
-                                                int a, const Tin* __restrict__ B, int64_t ldb, int b,
-                                                double* __restrict__ partial) {
-  constexpr int RB = 16;
-  __shared__ Tc sA[RB][TW + 4];
-  __shared__ Tc sB[SYM ? 1 : RB][TW + 4];
+template <typename Tin, typename Tc, bool SYM, int PA, int PB>
+__global__ void __launch_bounds__(WG) k_tnw(int64_t n, int64_t rpc, const Tin* __restrict__ A, int64_t lda, int a,
+                                            const Tin* __restrict__ B, int64_t ldb, int b,
+                                            double* __restrict__ partial) {
   using M = Mma<Tc>;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int TA = (a + 15) >> 4, TB = (b + 15) >> 4;
-  int ti[MAXT], tj[MAXT];
-  typename M::acc_t acc[MAXT];
+  using acc_t = typename M::acc_t;
+  extern __shared__ double red_lds[];  // PA*PB tiles of 16x16 doubles
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int ty0 = blockIdx.y * PA;
+  acc_t acc[PA][PB];
 #pragma unroll
-  for (int q = 0; q < MAXT; ++q) {
-    decode_tile(wid + NW * q, TA, TB, SYM, ti[q], tj[q]);
-    acc[q] = typename M::acc_t{0, 0, 0, 0};
-  }
+  for (int p = 0; p < PA; ++p)
+#pragma unroll
+    for (int q = 0; q < PB; ++q) acc[p][q] = acc_t{0, 0, 0, 0};
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min(n, r0 + rpc);
-  const int lr = tid >> 7, lc = tid & 127;
-  for (int64_t rb = r0; rb < r1; rb += RB) {
-    __syncthreads();
+  for (int64_t rb = r0 + 16 * wid; rb < r1; rb += 16 * NW) {
+    Tc fa[4][PA], fb[4][PB];
 #pragma unroll
-    for (int p = 0; p < RB / 2; ++p) {
-      const int rr = 2 * p + lr;
-      const int64_t row = rb + rr;
+    for (int s = 0; s < 4; ++s) {
+      const int64_t row = rb + 4 * s + g;
       const bool ok = row < r1;
-      sA[rr][lc] = (ok && lc < a) ? (Tc)A[row * lda + lc] : Tc(0);
-      if (!SYM) sB[rr][lc] = (ok && lc < b) ? (Tc)B[row * ldb + lc] : Tc(0);
-    }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < RB; kk += 4) {
-      const int kr = kk + (lane >> 4);
+      for (int q = 0; q < PB; ++q) {
+        const int col = q * 16 + c16;
+        if (SYM) fb[s][q] = (ok && col < a) ? (Tc)A[row * lda + col] : Tc(0);
+        else fb[s][q] = (ok && col < b) ? (Tc)B[row * ldb + col] : Tc(0);
+      }
 #pragma unroll
-      for (int q = 0; q < MAXT; ++q) {
-        if (ti[q] < 0) continue;
-        const Tc fa = sA[kr][ti[q] * 16 + (lane & 15)];
-        const Tc fb = SYM ? sA[kr][tj[q] * 16 + (lane & 15)] : sB[kr][tj[q] * 16 + (lane & 15)];
-        acc[q] = M::run(fa, fb, acc[q]);
+      for (int p = 0; p < PA; ++p) {
+        if (SYM) {
+          fa[s][p] = fb[s][p];  // single slice: the tile-rows are the tile-columns
+        } else {
+          const int col = (ty0 + p) * 16 + c16;
+          fa[s][p] = (ok && col < a) ? (Tc)A[row * lda + col] : Tc(0);
+        }
       }
     }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int p = 0; p < PA; ++p)
+#pragma unroll
+        for (int q = 0; q < PB; ++q)
+          if (!SYM || p <= q) acc[p][q] = M::run(fa[s][p], fb[s][q], acc[p][q]);
+  }
+  // fixed-order sum of the four waves through LDS, then one partial per workgroup
+  for (int w = 0; w < NW; ++w) {
+    if (wid == w) {
+#pragma unroll
+      for (int p = 0; p < PA; ++p)
+#pragma unroll
+        for (int q = 0; q < PB; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = ((p * PB + q) * 16 + M::row(lane, r)) * 16 + c16;
+            red_lds[e] = (w == 0) ? (double)acc[p][q][r] : red_lds[e] + (double)acc[p][q][r];
+          }
+    }
+    __syncthreads();
   }
   double* out = partial + (size_t)blockIdx.x * a * b;
-#pragma unroll
-  for (int q = 0; q < MAXT; ++q) {
-    if (ti[q] < 0) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = ti[q] * 16 + M::row(lane, r);
-      const int j = tj[q] * 16 + (lane & 15);
-      if (i < a && j < b) out[(size_t)i * b + j] = (double)acc[q][r];
-    }
+  for (int e = threadIdx.x; e < PA * PB * 256; e += WG) {
+    const int t = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    const int p = t / PB, q = t % PB;
+    if (SYM && p > q) continue;
+    const int gi = (ty0 + p) * 16 + i, gj = q * 16 + j;
+    if (gi < a && gj < b) out[(size_t)gi * b + gj] = red_lds[e];
   }
 }
 
 // ---------------------------------------------------------------------------------
-// C = A^T B with BF16 MFMA (FP32 accumulation); 32 rows per step
+// C = A^T B with split-BF16 MFMA (FP32 accumulation); 32 rows per stage, prefetched
 // ---------------------------------------------------------------------------------
-template <typename Tin>
-__global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const Tin* __restrict__ A, int64_t lda,
-                                                int a, const Tin* __restrict__ B, int64_t ldb, int b,
+constexpr int BT = 10;  // output tiles per wave (<= 40 tiles per workgroup)
+
+__global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const float* __restrict__ A, int64_t lda,
+                                                int a, const float* __restrict__ B, int64_t ldb, int b,
                                                 double* __restrict__ partial) {
   constexpr int RB = 32;
-  // column-major staging so that a lane's eight consecutive rows are one 16-byte read;
-  // every value is split into hi = bf16(x) and lo = bf16(x - hi), and the product is
-  // hi*hi + hi*lo + lo*hi (relative error ~ 2^-16 instead of 2^-8)
+  constexpr int PF = RB * TW * 2 / WG;  // prefetched values per lane (A and B panels)
   __shared__ __attribute__((aligned(16))) __bf16 sA[TW][RB + 8];
   __shared__ __attribute__((aligned(16))) __bf16 sB[TW][RB + 8];
   __shared__ __attribute__((aligned(16))) __bf16 sAl[TW][RB + 8];
   __shared__ __attribute__((aligned(16))) __bf16 sBl[TW][RB + 8];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int TA = (a + 15) >> 4, TB = (b + 15) >> 4;
-  int ti[MAXT], tj[MAXT];
-  f32x4 acc[MAXT];
+  const int ntile = TA * TB;
+  int ti[BT], tj[BT];
+  f32x4 acc[BT];
 #pragma unroll
-  for (int q = 0; q < MAXT; ++q) {
-    decode_tile(wid + NW * q, TA, TB, false, ti[q], tj[q]);
+  for (int q = 0; q < BT; ++q) {
+    const int t = wid + NW * q;
+    ti[q] = t < ntile ? t / TB : -1;
+    tj[q] = t < ntile ? t % TB : -1;
     acc[q] = f32x4{0, 0, 0, 0};
   }
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min(n, r0 + rpc);
+  // loader mapping: value v of this lane is row (v*WG + tid) / TW... rows stride 2 per pass
   const int lr = tid >> 7, lc = tid & 127;
+  float pa[PF / 2], pb[PF / 2];
+  auto fetch = [&](int64_t rb) {
+#pragma unroll
+    for (int v = 0; v < PF / 2; ++v) {
+      const int64_t row = rb + 2 * v + lr;
+      const bool ok = row < r1;
+      pa[v] = (ok && lc < a) ? A[row * lda + lc] : 0.f;
+      pb[v] = (ok && lc < b) ? B[row * ldb + lc] : 0.f;
+    }
+  };
+  if (r0 < r1) fetch(r0);
   for (int64_t rb = r0; rb < r1; rb += RB) {
     __syncthreads();
-#pragma unroll 4
-    for (int p = 0; p < RB / 2; ++p) {
-      const int rr = 2 * p + lr;
-      const int64_t row = rb + rr;
-      const bool ok = row < r1;
-      const float xa = (ok && lc < a) ? (float)A[row * lda + lc] : 0.f;
-      const float xb = (ok && lc < b) ? (float)B[row * ldb + lc] : 0.f;
-      const __bf16 ha = (__bf16)xa, hb = (__bf16)xb;
+#pragma unroll
+    for (int v = 0; v < PF / 2; ++v) {
+      const int rr = 2 * v + lr;
+      const __bf16 ha = (__bf16)pa[v], hb = (__bf16)pb[v];
       sA[lc][rr] = ha;
+      sAl[lc][rr] = (__bf16)(pa[v] - (float)ha);
       sB[lc][rr] = hb;
-      sAl[lc][rr] = (__bf16)(xa - (float)ha);
-      sBl[lc][rr] = (__bf16)(xb - (float)hb);
+      sBl[lc][rr] = (__bf16)(pb[v] - (float)hb);
     }
     __syncthreads();
+    if (rb + RB < r1) fetch(rb + RB);  // in flight during the MFMAs below
     const int kr = 8 * (lane >> 4);
 #pragma unroll
-    for (int q = 0; q < MAXT; ++q) {
+    for (int q = 0; q < BT; ++q) {
       if (ti[q] < 0) continue;
       const int ia = ti[q] * 16 + (lane & 15), ib = tj[q] * 16 + (lane & 15);
       const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sA[ia][kr]);
@@ -184,7 +202,7 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const Ti
   }
   double* out = partial + (size_t)blockIdx.x * a * b;
 #pragma unroll
-  for (int q = 0; q < MAXT; ++q) {
+  for (int q = 0; q < BT; ++q) {
     if (ti[q] < 0) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -203,13 +221,12 @@ __global__ void __launch_bounds__(WG) k_tn_reduce(int g, int a, int b, int sym, 
   const int64_t idx = (int64_t)blockIdx.x * (WG / 4) + (threadIdx.x >> 2);
   const int part = threadIdx.x & 3;
   double s = 0.0;
-  int64_t src = idx;
   if (idx < ab) {
     const int i = (int)(idx / b), j = (int)(idx % b);
+    int64_t src = idx;
     if (sym && (i >> 4) > (j >> 4)) src = (int64_t)j * b + i;
     for (int c = part; c < g; c += 4) s += partial[(size_t)c * ab + src];
   }
-  // combine the four lanes in a fixed order
   const double s1 = __shfl_xor(s, 1, 4);
   const double lo = (part & 1) ? s1 + s : s + s1;
   const double s2 = __shfl_xor(lo, 2, 4);
@@ -220,14 +237,43 @@ __global__ void __launch_bounds__(WG) k_tn_reduce(int g, int a, int b, int sym, 
 // ---------------------------------------------------------------------------------
 // Out = beta Out + alpha In M with FP32 / FP64 MFMA
 // ---------------------------------------------------------------------------------
+template <typename T, int N>
+struct alignas(N * sizeof(T)) vec_t {
+  T v[N];
+};
+
 template <typename T, typename Tc, bool VEC>
-__global__ void __launch_bounds__(WG) k_apply_mfma(int64_t n, const T* In, int64_t ldin, int a,
-                                                   const double* __restrict__ Mg, int b, double alpha,
-                                                   double beta, T* Out, int64_t ldout) {
+__device__ inline void load_frag(const T* In, int64_t ldin, int64_t row, int64_t n, int a, int KB, int g,
+                                 Tc (&fin)[8][4]) {
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    if (kb < KB) {
+      const int k0 = kb * 16 + 4 * g;
+      if (VEC && row < n && k0 + 4 <= a) {
+        constexpr int NV = 16 / sizeof(T);  // elements per 16-byte load
+#pragma unroll
+        for (int h = 0; h < 4 / NV; ++h) {
+          const vec_t<T, NV> v = *reinterpret_cast<const vec_t<T, NV>*>(In + row * ldin + k0 + h * NV);
+#pragma unroll
+          for (int m = 0; m < NV; ++m) fin[kb][h * NV + m] = (Tc)v.v[m];
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) fin[kb][m] = (row < n && k0 + m < a) ? (Tc)In[row * ldin + k0 + m] : Tc(0);
+      }
+    }
+  }
+}
+
+template <typename T, typename Tc, bool VEC>
+__global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In, int64_t ldin, int a,
+                                              const double* __restrict__ Mg, int b, double alpha, double beta,
+                                              T* Out, int64_t ldout) {
   using M = Mma<Tc>;
+  extern __shared__ double sMraw[];
+  Tc* sM = reinterpret_cast<Tc*>(sMraw);
   const int KB = (a + 15) >> 4, TB = (b + 15) >> 4;
-  const int bp = TB * 16;
-  __shared__ Tc sM[TW * TW];
+  const int bp = TB * 16 + 1;  // odd pitch: the four lane groups hit different banks
   for (int idx = threadIdx.x; idx < KB * 16 * bp; idx += WG) {
     const int k = idx / bp, j = idx % bp;
     sM[idx] = (k < a && j < b) ? (Tc)(alpha * Mg[(size_t)k * b + j]) : Tc(0);
@@ -236,103 +282,36 @@ __global__ void __launch_bounds__(WG) k_apply_mfma(int64_t n, const T* In, int64
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t ntile = (n + 15) >> 4;
-  for (int64_t tile = (int64_t)blockIdx.x * NW + wid; tile < ntile; tile += (int64_t)gridDim.x * NW) {
-    const int64_t row0 = tile * 16;
-    const int64_t row = row0 + c16;
-    Tc fin[8][4];
+  const int64_t stride = (int64_t)gridDim.x * NW * 2;
+  for (int64_t tile = ((int64_t)blockIdx.x * NW + wid) * 2; tile < ntile; tile += stride) {
+    Tc fin[2][8][4];
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      if (kb < KB) {
-        const int k0 = kb * 16 + 4 * g;
-        if (VEC && row < n && k0 + 4 <= a) {
-          const T* p = In + row * ldin + k0;
-#pragma unroll
-          for (int m = 0; m < 4; ++m) fin[kb][m] = (Tc)p[m];
-        } else {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) fin[kb][m] = (row < n && k0 + m < a) ? (Tc)In[row * ldin + k0 + m] : Tc(0);
-        }
-      }
-    }
+    for (int u = 0; u < 2; ++u)
+      load_frag<T, Tc, VEC>(In, ldin, (tile + u) * 16 + c16, n, a, KB, g, fin[u]);
     for (int jt = 0; jt < TB; ++jt) {
-      typename M::acc_t acc{0, 0, 0, 0};
 #pragma unroll
-      for (int kb = 0; kb < 8; ++kb) {
-        if (kb < KB) {
+      for (int u = 0; u < 2; ++u) {
+        const int64_t row0 = (tile + u) * 16;
+        if (row0 >= n) continue;
+        typename M::acc_t acc{0, 0, 0, 0};
 #pragma unroll
-          for (int m = 0; m < 4; ++m)
-            acc = M::run(fin[kb][m], sM[(kb * 16 + 4 * g + m) * bp + jt * 16 + c16], acc);
+        for (int kb = 0; kb < 8; ++kb) {
+          if (kb < KB) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+              acc = M::run(fin[u][kb][m], sM[(kb * 16 + 4 * g + m) * bp + jt * 16 + c16], acc);
+          }
         }
-      }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t orow = row0 + M::row(lane, r);
-        const int ocol = jt * 16 + c16;
-        if (orow < n && ocol < b) {
-          Tc v = acc[r];
-          if (beta != 0.0) v += (Tc)beta * (Tc)Out[orow * ldout + ocol];
-          Out[orow * ldout + ocol] = (T)v;
+        for (int r = 0; r < 4; ++r) {
+          const int64_t orow = row0 + M::row(lane, r);
+          const int ocol = jt * 16 + c16;
+          if (orow < n && ocol < b) {
+            Tc v = acc[r];
+            if (beta != 0.0) v += (Tc)beta * (Tc)Out[orow * ldout + ocol];
+            Out[orow * ldout + ocol] = (T)v;
+          }
         }
-      }
-    }
-  }
-}
-
-// Out = alpha In M with BF16 MFMA (FP32 accumulation), In FP32
-__global__ void __launch_bounds__(WG) k_apply_bf16(int64_t n, const float* In, int64_t ldin, int a,
-                                                   const double* __restrict__ Mg, int b, double alpha,
-                                                   float* Out, int64_t ldout) {
-  const int KB = (a + 31) >> 5, TB = (b + 15) >> 4;
-  const int kp = KB * 32;
-  // transposed: sMt[j][k], so that eight consecutive k of one column are one 16-byte read;
-  // hi/lo split of both operands as in k_tn_bf16
-  __shared__ __attribute__((aligned(16))) __bf16 sMt[TW][TW + 8];
-  __shared__ __attribute__((aligned(16))) __bf16 sMl[TW][TW + 8];
-  for (int idx = threadIdx.x; idx < TB * 16 * kp; idx += WG) {
-    const int j = idx / kp, k = idx % kp;
-    const float x = (k < a && j < b) ? (float)(alpha * Mg[(size_t)k * b + j]) : 0.f;
-    const __bf16 h = (__bf16)x;
-    sMt[j][k] = h;
-    sMl[j][k] = (__bf16)(x - (float)h);
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
-  const int64_t ntile = (n + 15) >> 4;
-  for (int64_t tile = (int64_t)blockIdx.x * NW + wid; tile < ntile; tile += (int64_t)gridDim.x * NW) {
-    const int64_t row0 = tile * 16;
-    const int64_t row = row0 + c16;
-    bf16x8 fin[4], finl[4];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      if (kb < KB) {
-        const int k0 = kb * 32 + 8 * g;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float x = (row < n && k0 + e < a) ? In[row * ldin + k0 + e] : 0.f;
-          const __bf16 h = (__bf16)x;
-          fin[kb][e] = h;
-          finl[kb][e] = (__bf16)(x - (float)h);
-        }
-      }
-    }
-    for (int jt = 0; jt < TB; ++jt) {
-      f32x4 acc{0, 0, 0, 0};
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        if (kb < KB) {
-          const bf16x8 fb = *reinterpret_cast<const bf16x8*>(&sMt[jt * 16 + c16][kb * 32 + 8 * g]);
-          const bf16x8 fbl = *reinterpret_cast<const bf16x8*>(&sMl[jt * 16 + c16][kb * 32 + 8 * g]);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(finl[kb], fb, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fin[kb], fbl, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fin[kb], fb, acc, 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t orow = row0 + bf16_row(lane, r);
-        const int ocol = jt * 16 + c16;
-        if (orow < n && ocol < b) Out[orow * ldout + ocol] = acc[r];
       }
     }
   }
@@ -340,8 +319,8 @@ __global__ void __launch_bounds__(WG) k_apply_bf16(int64_t n, const float* In, i
 
 inline int apply_grid(int64_t n) {
   int64_t tiles = (n + 15) / 16;
-  int64_t g = (tiles + NW - 1) / NW;
-  if (g > 2048) g = 2048;
+  int64_t g = (tiles + 2 * NW - 1) / (2 * NW);
+  if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -349,6 +328,38 @@ inline int apply_grid(int64_t n) {
 template <typename T>
 bool aligned16(const T* p, int64_t ld) {
   return ((uintptr_t)p % 16) == 0 && ((ld * (int64_t)sizeof(T)) % 16) == 0;
+}
+
+template <typename Tin, typename Tc, bool SYM, int PA, int PB>
+void tnw_launch(dim3 grid, hipStream_t s, int64_t n, int64_t rpc, const Tin* A, int64_t lda, int a, const Tin* B,
+                int64_t ldb, int b, double* partial) {
+  const size_t lds = (size_t)PA * PB * 256 * sizeof(double);
+  static bool attr = false;
+  if (!attr && lds > 65536) {
+    (void)hipFuncSetAttribute((const void*)k_tnw<Tin, Tc, SYM, PA, PB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  k_tnw<Tin, Tc, SYM, PA, PB><<<grid, WG, lds, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
+}
+
+// picks the register tile shape for a (TA x TB)-tile product; returns the slice count
+template <typename Tin, typename Tc>
+int tnw_dispatch(int64_t n, int g, int64_t rpc, const Tin* A, int64_t lda, int a, const Tin* B, int64_t ldb, int b,
+                 bool sym, double* partial, hipStream_t s) {
+  const int TA = (a + 15) >> 4, TB = (b + 15) >> 4;
+  const bool f64 = sizeof(Tc) == 8;
+  if (sym && TA <= 2) { tnw_launch<Tin, Tc, true, 2, 2>(dim3(g, 1), s, n, rpc, A, lda, a, B, ldb, b, partial); return 1; }
+  if (sym && TA <= 4) { tnw_launch<Tin, Tc, true, 4, 4>(dim3(g, 1), s, n, rpc, A, lda, a, B, ldb, b, partial); return 1; }
+  if (TA <= 1 && TB <= 8) { tnw_launch<Tin, Tc, false, 1, 8>(dim3(g, 1), s, n, rpc, A, lda, a, B, ldb, b, partial); return 1; }
+  if (TA <= 2 && TB <= 2) { tnw_launch<Tin, Tc, false, 2, 2>(dim3(g, 1), s, n, rpc, A, lda, a, B, ldb, b, partial); return 1; }
+  if (TA <= 2 && TB <= 4) { tnw_launch<Tin, Tc, false, 2, 4>(dim3(g, 1), s, n, rpc, A, lda, a, B, ldb, b, partial); return 1; }
+  if (TA <= 4 && TB <= 4) { tnw_launch<Tin, Tc, false, 4, 4>(dim3(g, 1), s, n, rpc, A, lda, a, B, ldb, b, partial); return 1; }
+  if (!f64 && TA <= 6 && TB <= 6) { tnw_launch<Tin, Tc, false, 6, 6>(dim3(g, 1), s, n, rpc, A, lda, a, B, ldb, b, partial); return 1; }
+  // general case: slices of two tile-rows against up to eight tile-columns
+  const int ny = (TA + 1) / 2;
+  tnw_launch<Tin, Tc, false, 2, 8>(dim3(g, ny), s, n, rpc, A, lda, a, B, ldb, b, partial);
+  return ny;
 }
 
 }  // namespace
@@ -360,7 +371,7 @@ int tn_num_chunks(int64_t n) {
   return (int)g;
 }
 
-// kind: 0 = FP32 MFMA, 1 = FP64 MFMA, 2 = BF16 MFMA
+// kind: 0 = FP32 MFMA, 1 = FP64 MFMA, 2 = split-BF16 MFMA
 template <typename T>
 static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T* B, int64_t ldb, int b,
                    double* partial, double* C, hipStream_t s) {
@@ -369,15 +380,16 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
   const int rb = kind == 2 ? 32 : 16;
   int64_t rpc = (n + g - 1) / g;
   rpc = ((rpc + rb - 1) / rb) * rb;
-  const bool sym = (A == B && lda == ldb && a == b && kind != 2);
+  if (kind == 2 && ((a + 15) >> 4) * ((b + 15) >> 4) > NW * BT) kind = 0;  // too many tiles: FP32 MFMA
+  bool sym = (A == B && lda == ldb && a == b && kind != 2);
   if (kind == 2) {
-    k_tn_bf16<T><<<g, WG, 0, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
+    k_tn_bf16<<<g, WG, 0, s>>>(n, rpc, (const float*)A, lda, a, (const float*)B, ldb, b, partial);
   } else if (kind == 1) {
-    if (sym) k_tn_mfma<T, double, true><<<g, WG, 0, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
-    else k_tn_mfma<T, double, false><<<g, WG, 0, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
+    if (sym && ((a + 15) >> 4) > 4) sym = false;  // wide Gram: full product in slices
+    tnw_dispatch<T, double>(n, g, rpc, A, lda, a, B, ldb, b, sym, partial, s);
   } else {
-    if (sym) k_tn_mfma<T, float, true><<<g, WG, 0, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
-    else k_tn_mfma<T, float, false><<<g, WG, 0, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
+    if (sym && ((a + 15) >> 4) > 4) sym = false;
+    tnw_dispatch<T, float>(n, g, rpc, A, lda, a, B, ldb, b, sym, partial, s);
   }
   const int64_t ab = (int64_t)a * b;
   k_tn_reduce<<<(unsigned)((ab + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, a, b, sym ? 1 : 0, partial, C);
@@ -394,25 +406,32 @@ void launch_tn_bf16(int64_t n, const float* A, int64_t lda, int a, const float* 
   tn_run<float>(2, n, A, lda, a, B, ldb, b, partial, C, s);
 }
 
+template <typename T, typename Tc, bool VEC>
+static void apply_launch(int64_t n, const T* In, int64_t ldin, int a, const double* M, int b, double alpha,
+                         double beta, T* Out, int64_t ldout, hipStream_t s) {
+  const int KB = (a + 15) >> 4, TB = (b + 15) >> 4;
+  const size_t lds = (size_t)KB * 16 * (TB * 16 + 1) * sizeof(Tc);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_apply<T, Tc, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)((size_t)TW * (TW + 1) * sizeof(Tc)));
+    attr = true;
+  }
+  k_apply<T, Tc, VEC><<<apply_grid(n), WG, lds, s>>>(n, In, ldin, a, M, b, alpha, beta, Out, ldout);
+}
+
 template <typename T>
 void launch_apply(int64_t n, const T* In, int64_t ldin, int a, const double* M, int b, double alpha,
                   double beta, T* Out, int64_t ldout, hipStream_t s) {
   if (n <= 0 || b <= 0) return;
-  const int g = apply_grid(n);
   const bool vec = aligned16(In, ldin);
   if (sizeof(T) == 8) {
-    if (vec) k_apply_mfma<T, double, true><<<g, WG, 0, s>>>(n, In, ldin, a, M, b, alpha, beta, Out, ldout);
-    else k_apply_mfma<T, double, false><<<g, WG, 0, s>>>(n, In, ldin, a, M, b, alpha, beta, Out, ldout);
+    if (vec) apply_launch<T, double, true>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
+    else apply_launch<T, double, false>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
   } else {
-    if (vec) k_apply_mfma<T, float, true><<<g, WG, 0, s>>>(n, In, ldin, a, M, b, alpha, beta, Out, ldout);
-    else k_apply_mfma<T, float, false><<<g, WG, 0, s>>>(n, In, ldin, a, M, b, alpha, beta, Out, ldout);
+    if (vec) apply_launch<T, float, true>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
+    else apply_launch<T, float, false>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
   }
-}
-
-void launch_apply_bf16(int64_t n, const float* In, int64_t ldin, int a, const double* M, int b, double alpha,
-                       float* Out, int64_t ldout, hipStream_t s) {
-  if (n <= 0 || b <= 0) return;
-  k_apply_bf16<<<apply_grid(n), WG, 0, s>>>(n, In, ldin, a, M, b, alpha, Out, ldout);
 }
 
 template void launch_tn<float, false>(int64_t, const float*, int64_t, int, const float*, int64_t, int, double*,
