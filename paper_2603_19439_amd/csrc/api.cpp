@@ -284,31 +284,34 @@ Blocks<T> blocks(grest_state* st) {
   return b;
 }
 
-// W (n x w, ld) <- (I - Xbar Xbar^T) applied twice; the coefficients are kept in c1, c2
+// Orthonormal basis of (I - Xbar Xbar^T) W in place (W: n x w, ld), two rounds of block
+// Gram-Schmidt with the Pythagorean Gram (CholQR2 against Xbar): each round reads
+// [Xbar W] once for C = Xbar^T W and the FP64 Gram G = W^T W, factors G - C^T C by
+// rank-revealing pivoted Cholesky in FP64, and writes W <- (W - Xbar C) M in one pass.
+// The kept column counts of the two rounds go to ranks[slot] and ranks[slot + 1].
 template <typename T>
-void project_twice(grest_state* st, int64_t n, const T* X, int64_t ldx, T* W, int64_t ldw, int w,
-                   double* c1, double* c2) {
-  const bool acc64 = (st->prec == GREST_FP64);
-  double* cs[2] = {c1, c2};
-  for (int pass = 0; pass < 2; ++pass) {
-    if (acc64) launch_tn<T, true>(n, X, ldx, st->K, W, ldw, w, st->partial, cs[pass], st->stream);
-    else launch_tn<T, false>(n, X, ldx, st->K, W, ldw, w, st->partial, cs[pass], st->stream);
-    launch_apply<T>(n, X, ldx, st->K, cs[pass], w, -1.0, 1.0, W, ldw, st->stream);
+void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, T* W, int64_t ldw, int w, int slot) {
+  hipStream_t s = st->stream;
+  for (int round = 0; round < 2; ++round) {
+    if (!launch_pip<T>(n, X, ldx, st->K, W, ldw, w, st->partial, st->C1, st->Gm, s)) {
+      if (st->prec == GREST_FP64) launch_tn<T, true>(n, X, ldx, st->K, W, ldw, w, st->partial, st->C1, s);
+      else launch_tn<T, false>(n, X, ldx, st->K, W, ldw, w, st->partial, st->C1, s);
+      launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, s);
+    }
+    launch_pchol(w, st->Gm, st->C1, st->K, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
+    launch_apply2<T>(n, X, ldx, st->K, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, s);
   }
 }
 
-// rank-revealing CholQR2 of W (n x w, ld) in place; ranks[slot] and ranks[slot+1]
+// rank-revealing CholQR2 of W (n x w, ld) in place, without a block to project against
 template <typename T>
-void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, const double* c1, const double* c2,
-             int slot) {
-  launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, st->stream);
-  launch_pchol(w, st->Gm, c1, c2, c1 ? st->K : 0, st->tol, st->Mchol, st->ranks + slot, st->status,
-               st->stream);
-  launch_apply<T>(n, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, st->stream);
-  launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, st->stream);
-  launch_pchol(w, st->Gm, nullptr, nullptr, 0, st->tol, st->Mchol, st->ranks + slot + 1, st->status,
-               st->stream);
-  launch_apply<T>(n, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, st->stream);
+void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, int slot) {
+  for (int round = 0; round < 2; ++round) {
+    launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, st->stream);
+    launch_pchol(w, st->Gm, nullptr, 0, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork,
+                 st->stream);
+    launch_apply<T>(n, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, st->stream);
+  }
 }
 
 template <typename T>
@@ -431,9 +434,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       }
       launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
                           Ls, Ls, b.Y, st->ldy, s);
-      project_twice<T>(st, n2, b.Zc, st->ldz, b.Y, st->ldy, Ls, st->C1, st->C2);
-      // S.2: M = orth(Y) (rank-revealing CholQR2)
-      cholqr2<T>(st, n2, b.Y, st->ldy, Ls, st->C1, st->C2, 2);
+      // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds
+      orth_against<T>(st, n2, b.Zc, st->ldz, b.Y, st->ldy, Ls, 2);
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
       launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Y, st->ldy, Ls,
                           (T*)st->bt, Ls, s);
@@ -446,8 +448,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   }
   mark(st, 3);
   // ---- projection (I - Xbar Xbar^T) W, twice; CholQR2 of W ----
-  project_twice<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, st->C1, st->C2);
-  cholqr2<T>(st, n2, b.W, st->ldz, st->Dw, st->C1, st->C2, 0);
+  orth_against<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, 0);
   mark(st, 4);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
   CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->K, st->ranks + 1));
@@ -490,13 +491,13 @@ grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
   launch_fill_bytes0(st->status, sizeof(int32_t), s);
   launch_fill_rows<T>(Z, st->ldz, 0, n, st->ldz, s);
   launch_fill_random<T>(Z, st->ldz, n, b, seed, s);
-  cholqr2<T>(st, n, Z, st->ldz, b, nullptr, nullptr, 0);
+  cholqr2<T>(st, n, Z, st->ldz, b, 0);
   for (int it = 0; it < iters; ++it) {
     launch_spmm<T>(st->op, n, rp, col, sc, Z, st->ldz, n, b, aux, st->D, s);
     if (st->op != GREST_OP_ADJ) launch_axpby<T>(n, b, shift, Z, st->ldz, -1.0, aux, st->D, s);
     HIPCHK(hipMemcpy2DAsync(Z, st->ldz * sizeof(T), aux, st->D * sizeof(T), b * sizeof(T), n,
                             hipMemcpyDeviceToDevice, s));
-    cholqr2<T>(st, n, Z, st->ldz, b, nullptr, nullptr, 0);
+    cholqr2<T>(st, n, Z, st->ldz, b, 0);
   }
   CHK(rayleigh_ritz<T>(st, n, rp, col, sc, 0, st->ranks + 1));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -684,7 +685,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if ((rc = dalloc(&st->C1, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->C2, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Gm, (size_t)wmax * wmax)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->Mchol, (size_t)wmax * wmax + (size_t)(wmax + 1) * (wmax + 1))) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->Mchol, (size_t)(st->K + wmax) * wmax + (size_t)(wmax + 1) * (wmax + 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->H, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->F, (size_t)dmax * st->K)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->theta, st->K)) != GREST_OK) return fail(rc);

@@ -100,8 +100,21 @@ void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s);
 // (m x m) such that W M has orthonormal leading columns and zero trailing ones, and
 // writes the kept count to *rank.  Columns are dropped when the pivot falls below
 // (tol * scale)^2 where scale^2 = max(1, max_j (G_jj + colsq_j)); colsq may be null.
-void launch_pchol(int m, const double* G, const double* colsq1, const double* colsq2, int kc,
-                  double tol, double* M, int32_t* rank, int32_t* status, hipStream_t s);
+// With C (kc x m) the factored matrix is G - C^T C, the scale comes from diag(G), and the
+// output Mout is the stacked (kc + m) x m matrix [-C M; M]; without C (kc = 0) Mout = M.
+// work: pchol_work_elems(m, kc) doubles, used when the factor does not fit in LDS.
+int64_t pchol_work_elems(int m, int kc);
+void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
+                  int32_t* status, double* work, hipStream_t s);
+// one projection round in one pass: C = X^T W (working precision) and G = W^T W (FP64);
+// returns false when the widths exceed what the kernel holds in registers
+template <typename T>
+bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw, int w, double* partial,
+                double* C, double* G, hipStream_t s);
+// Out = beta Out + alpha [In1 | In2] M  (In1: n x a1, In2: n x a2, a1 + a2 <= 128)
+template <typename T>
+void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
+                   const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s);
 // Symmetric eigensolver of H (first K + rank[0] rows/cols used, ldh = d_full) and
 // selection of kk pairs: which 0 = largest magnitude, 1 = smallest algebraic,
 // 2 = largest algebraic.  Writes theta[kk] and F (d_full x kk, zero rows past the

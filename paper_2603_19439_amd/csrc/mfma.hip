@@ -22,6 +22,8 @@
 // element (4*(l/16)+r, l%16); the f64 tile gives (l/16+4r, l%16).
 #include "grest_internal.h"
 
+#include <type_traits>
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -213,6 +215,79 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const fl
   }
 }
 
+// ---------------------------------------------------------------------------------
+// One pass over the rows for a projection round of block Gram-Schmidt with the
+// Pythagorean Gram: C = X^T W (waves 0-1) and G = W^T W, upper tiles (waves 2-3).
+// X and W are separate column blocks (any widths <= 128).  G always accumulates in
+// FP64; C in the working precision.
+// ---------------------------------------------------------------------------------
+constexpr int PT = 16;  // tiles per wave
+
+// one half of the workgroup: C = X^T W tiles (IS_C) or the upper G = W^T W tiles
+template <bool IS_C, typename T, typename Tc>
+__device__ inline void pip_part(int sub, int lane, int64_t r0, int64_t r1, const T* __restrict__ X, int64_t ldx,
+                                int kx, const T* __restrict__ W, int64_t ldw, int w, double* __restrict__ out) {
+  using M = Mma<Tc>;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int TX = (kx + 15) >> 4, TWt = (w + 15) >> 4;
+  int ti[PT], tj[PT];
+#pragma unroll
+  for (int q = 0; q < PT; ++q) {
+    int t = sub + 2 * q;
+    if (IS_C) {
+      ti[q] = t < TX * TWt ? t / TWt : -1;
+      tj[q] = t < TX * TWt ? t % TWt : -1;
+    } else {
+      int a = 0;
+      while (a < TWt && t >= TWt - a) { t -= TWt - a; ++a; }
+      ti[q] = a < TWt ? a : -1;
+      tj[q] = a < TWt ? a + t : -1;
+    }
+  }
+  typename M::acc_t acc[PT];
+#pragma unroll
+  for (int q = 0; q < PT; ++q) acc[q] = typename M::acc_t{0, 0, 0, 0};
+  const int ka = IS_C ? kx : w;
+  for (int64_t rb = r0; rb < r1; rb += 16) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t row = rb + 4 * s + g;
+      const bool ok = row < r1;
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        if (ti[q] < 0) continue;
+        const int cb = tj[q] * 16 + c16;
+        const int ca = ti[q] * 16 + c16;
+        const T vb = (ok && cb < w) ? W[row * ldw + cb] : T(0);
+        const T va = (ok && ca < ka) ? (IS_C ? X[row * ldx + ca] : W[row * ldw + ca]) : T(0);
+        acc[q] = M::run((Tc)va, (Tc)vb, acc[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PT; ++q) {
+    if (ti[q] < 0) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = ti[q] * 16 + M::row(lane, r), j = tj[q] * 16 + c16;
+      if (i < ka && j < w) out[(size_t)i * w + j] = (double)acc[q][r];
+    }
+  }
+}
+
+template <typename T, typename Tcx>
+__global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __restrict__ X, int64_t ldx, int kx,
+                                            const T* __restrict__ W, int64_t ldw, int w, double* __restrict__ partC,
+                                            double* __restrict__ partG) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  if (wid < 2)
+    pip_part<true, T, Tcx>(wid & 1, lane, r0, r1, X, ldx, kx, W, ldw, w, partC + (size_t)blockIdx.x * kx * w);
+  else
+    pip_part<false, T, double>(wid & 1, lane, r0, r1, X, ldx, kx, W, ldw, w, partG + (size_t)blockIdx.x * w * w);
+}
+
 // fixed-order sum of the chunk partials; four lanes per output, combined in order;
 // in symmetric mode the lower tiles are read from their mirror
 __global__ void __launch_bounds__(WG) k_tn_reduce(int g, int a, int b, int sym, const double* __restrict__ partial,
@@ -242,36 +317,45 @@ struct alignas(N * sizeof(T)) vec_t {
   T v[N];
 };
 
+// The input row is the concatenation [In1 row (a1 values) | In2 row (a2 values)].
 template <typename T, typename Tc, bool VEC>
-__device__ inline void load_frag(const T* In, int64_t ldin, int64_t row, int64_t n, int a, int KB, int g,
-                                 Tc (&fin)[8][4]) {
+__device__ inline void load_frag(const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a, int64_t row,
+                                 int64_t n, int KB, int g, Tc (&fin)[8][4]) {
 #pragma unroll
   for (int kb = 0; kb < 8; ++kb) {
     if (kb < KB) {
       const int k0 = kb * 16 + 4 * g;
-      if (VEC && row < n && k0 + 4 <= a) {
+      const bool in1 = k0 + 4 <= a1, in2 = k0 >= a1;
+      if (VEC && row < n && k0 + 4 <= a && (in1 || in2)) {
         constexpr int NV = 16 / sizeof(T);  // elements per 16-byte load
+        const T* p = in1 ? In1 + row * ld1 + k0 : In2 + row * ld2 + (k0 - a1);
 #pragma unroll
         for (int h = 0; h < 4 / NV; ++h) {
-          const vec_t<T, NV> v = *reinterpret_cast<const vec_t<T, NV>*>(In + row * ldin + k0 + h * NV);
+          const vec_t<T, NV> v = *reinterpret_cast<const vec_t<T, NV>*>(p + h * NV);
 #pragma unroll
           for (int m = 0; m < NV; ++m) fin[kb][h * NV + m] = (Tc)v.v[m];
         }
       } else {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) fin[kb][m] = (row < n && k0 + m < a) ? (Tc)In[row * ldin + k0 + m] : Tc(0);
+        for (int m = 0; m < 4; ++m) {
+          const int k = k0 + m;
+          T v = T(0);
+          if (row < n && k < a) v = k < a1 ? In1[row * ld1 + k] : In2[row * ld2 + (k - a1)];
+          fin[kb][m] = (Tc)v;
+        }
       }
     }
   }
 }
 
 template <typename T, typename Tc, bool VEC>
-__global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In, int64_t ldin, int a,
-                                              const double* __restrict__ Mg, int b, double alpha, double beta,
-                                              T* Out, int64_t ldout) {
+__global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2,
+                                              int64_t ld2, int a2, const double* __restrict__ Mg, int b,
+                                              double alpha, double beta, T* Out, int64_t ldout) {
   using M = Mma<Tc>;
   extern __shared__ double sMraw[];
   Tc* sM = reinterpret_cast<Tc*>(sMraw);
+  const int a = a1 + a2;
   const int KB = (a + 15) >> 4, TB = (b + 15) >> 4;
   const int bp = TB * 16 + 1;  // odd pitch: the four lane groups hit different banks
   for (int idx = threadIdx.x; idx < KB * 16 * bp; idx += WG) {
@@ -287,7 +371,7 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In, int64_t ld
     Tc fin[2][8][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
-      load_frag<T, Tc, VEC>(In, ldin, (tile + u) * 16 + c16, n, a, KB, g, fin[u]);
+      load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, (tile + u) * 16 + c16, n, KB, g, fin[u]);
     for (int jt = 0; jt < TB; ++jt) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -395,6 +479,29 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
   k_tn_reduce<<<(unsigned)((ab + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, a, b, sym ? 1 : 0, partial, C);
 }
 
+// one projection round: C = X^T W and G = W^T W (upper tiles; the reduce mirrors them)
+template <typename T>
+bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw, int w, double* partial,
+                double* C, double* G, hipStream_t s) {
+  const int TX = (kx + 15) >> 4, TWt = (w + 15) >> 4;
+  if (TX * TWt > 2 * PT || TWt * (TWt + 1) / 2 > 2 * PT) return false;
+  const int g = tn_num_chunks(n);
+  int64_t rpc = (n + g - 1) / g;
+  rpc = ((rpc + 15) / 16) * 16;
+  double* partC = partial;
+  double* partG = partial + (size_t)g * kx * w;
+  using Tcx = typename std::conditional<sizeof(T) == 8, double, float>::type;
+  k_pip<T, Tcx><<<g, WG, 0, s>>>(n, rpc, X, ldx, kx, W, ldw, w, partC, partG);
+  k_tn_reduce<<<(unsigned)(((int64_t)kx * w + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, kx, w, 0, partC, C);
+  k_tn_reduce<<<(unsigned)(((int64_t)w * w + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, w, w, 1, partG, G);
+  return true;
+}
+
+template bool launch_pip<float>(int64_t, const float*, int64_t, int, const float*, int64_t, int, double*, double*,
+                                double*, hipStream_t);
+template bool launch_pip<double>(int64_t, const double*, int64_t, int, const double*, int64_t, int, double*,
+                                 double*, double*, hipStream_t);
+
 template <typename T, bool ACC64>
 void launch_tn(int64_t n, const T* A, int64_t lda, int a, const T* B, int64_t ldb, int b, double* partial,
                double* C, hipStream_t s) {
@@ -407,9 +514,9 @@ void launch_tn_bf16(int64_t n, const float* A, int64_t lda, int a, const float* 
 }
 
 template <typename T, typename Tc, bool VEC>
-static void apply_launch(int64_t n, const T* In, int64_t ldin, int a, const double* M, int b, double alpha,
-                         double beta, T* Out, int64_t ldout, hipStream_t s) {
-  const int KB = (a + 15) >> 4, TB = (b + 15) >> 4;
+static void apply_launch(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
+                         const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s) {
+  const int KB = (a1 + a2 + 15) >> 4, TB = (b + 15) >> 4;
   const size_t lds = (size_t)KB * 16 * (TB * 16 + 1) * sizeof(Tc);
   static bool attr = false;
   if (!attr) {
@@ -417,22 +524,33 @@ static void apply_launch(int64_t n, const T* In, int64_t ldin, int a, const doub
                               (int)((size_t)TW * (TW + 1) * sizeof(Tc)));
     attr = true;
   }
-  k_apply<T, Tc, VEC><<<apply_grid(n), WG, lds, s>>>(n, In, ldin, a, M, b, alpha, beta, Out, ldout);
+  k_apply<T, Tc, VEC><<<apply_grid(n), WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout);
+}
+
+template <typename T>
+void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
+                   const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s) {
+  if (n <= 0 || b <= 0) return;
+  const bool vec = aligned16(In1, ld1) && (a2 == 0 || (aligned16(In2, ld2) && a1 % 4 == 0));
+  if (sizeof(T) == 8) {
+    if (vec) apply_launch<T, double, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+    else apply_launch<T, double, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+  } else {
+    if (vec) apply_launch<T, float, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+    else apply_launch<T, float, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+  }
 }
 
 template <typename T>
 void launch_apply(int64_t n, const T* In, int64_t ldin, int a, const double* M, int b, double alpha,
                   double beta, T* Out, int64_t ldout, hipStream_t s) {
-  if (n <= 0 || b <= 0) return;
-  const bool vec = aligned16(In, ldin);
-  if (sizeof(T) == 8) {
-    if (vec) apply_launch<T, double, true>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
-    else apply_launch<T, double, false>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
-  } else {
-    if (vec) apply_launch<T, float, true>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
-    else apply_launch<T, float, false>(n, In, ldin, a, M, b, alpha, beta, Out, ldout, s);
-  }
+  launch_apply2<T>(n, In, ldin, a, In, ldin, 0, M, b, alpha, beta, Out, ldout, s);
 }
+
+template void launch_apply2<float>(int64_t, const float*, int64_t, int, const float*, int64_t, int, const double*,
+                                   int, double, double, float*, int64_t, hipStream_t);
+template void launch_apply2<double>(int64_t, const double*, int64_t, int, const double*, int64_t, int,
+                                    const double*, int, double, double, double*, int64_t, hipStream_t);
 
 template void launch_tn<float, false>(int64_t, const float*, int64_t, int, const float*, int64_t, int, double*,
                                       double*, hipStream_t);

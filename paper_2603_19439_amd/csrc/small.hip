@@ -38,33 +38,38 @@ __device__ double block_sum(double v, double* red) {
 // pivoted Cholesky:  G(P) = R^T R  truncated at the first pivot <= (tol*scale)^2
 // M[perm[i], j] = Rinv[i, j] for i <= j < rank, every other entry 0.
 // ------------------------------------------------------------------------------------
+// With a projection coefficient block C (kc x m) the factored matrix is the Gram of the
+// projected block, G - C^T C (Pythagorean form of block Gram-Schmidt), the rank scale is
+// taken from G itself (the block before projection), and the output is the stacked
+// (kc + m) x m matrix [-C M; M], so that (W - X C) M = [X W] [-C M; M].
 template <bool IN_LDS>
-__global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const double* c1,
-                                              const double* c2, int kc, double tol, double* M,
-                                              int32_t* rank_out, int32_t* status, double* work) {
-  __shared__ double sS[IN_LDS ? (SMALL_LDS_D + 1) * (SMALL_LDS_D + 1) : 1];
+__global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const double* C, int kc, double tol,
+                                              double* Mout, int32_t* rank_out, int32_t* status, double* work) {
+  extern __shared__ double dyn[];
   __shared__ int perm[MAXD];
   __shared__ double red[EB / GREST_WAVE];
   __shared__ double sh_val[2];
   __shared__ int sh_idx;
-  double* S = IN_LDS ? sS : work;
   const int lds = m + 1;
+  double* S = IN_LDS ? dyn : work;
+  double* Cs = IN_LDS ? dyn + (size_t)lds * lds : work + (size_t)lds * lds;
+  double* M = Mout + (size_t)kc * m;  // the m x m block
   const int tid = threadIdx.x;
 
-  // load and find the scale: max_j (G_jj + |C1[:,j]|^2 + |C2[:,j]|^2)
+  for (int idx = tid; idx < kc * m; idx += EB) Cs[idx] = C[idx];
+  __syncthreads();
+  // load, subtract C^T C, and find the scale max_j G_jj
   double mx = 0.0;
   int bad = 0;
   for (int idx = tid; idx < m * m; idx += EB) {
     int i = idx / m, j = idx % m;
     double g = 0.5 * (G[(size_t)i * m + j] + G[(size_t)j * m + i]);
+    for (int l = 0; l < kc; ++l) g -= Cs[l * m + i] * Cs[l * m + j];
     if (!isfinite(g)) bad = 1;
     S[i * lds + j] = g;
   }
   for (int j = tid; j < m; j += EB) {
-    double v = G[(size_t)j * m + j];
-    if (c1) for (int i = 0; i < kc; ++i) v += c1[(size_t)i * m + j] * c1[(size_t)i * m + j];
-    if (c2) for (int i = 0; i < kc; ++i) v += c2[(size_t)i * m + j] * c2[(size_t)i * m + j];
-    mx = fmax(mx, v);
+    mx = fmax(mx, G[(size_t)j * m + j]);
     perm[j] = j;
   }
   for (int o = GREST_WAVE / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, GREST_WAVE));
@@ -135,6 +140,14 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
   for (int idx = tid; idx < m * m; idx += EB) {
     int i = idx / m, j = idx % m;
     if (i < r && j < r && i <= j) M[(size_t)perm[i] * m + j] = S[(j + 1) * lds + i];
+  }
+  // -C M: row l, column j < r sums over the pivoted rows i <= j
+  for (int idx = tid; idx < kc * m; idx += EB) {
+    const int l = idx / m, j = idx % m;
+    double acc = 0.0;
+    if (j < r)
+      for (int i = 0; i <= j; ++i) acc += Cs[l * m + perm[i]] * S[(j + 1) * lds + i];
+    Mout[idx] = -acc;
   }
   if (tid == 0) *rank_out = r;
 }
@@ -311,14 +324,34 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   // ---- eigenvectors of T by inverse iteration; a cluster (gaps below 1e-3 ||T||) is
   //      handled by one lane with distinct shifts and reorthogonalisation ----
   const double ortol = 1e-3 * tnorm;
-  for (int q = tid; q < nsel; q += EB) {
-    if (q > 0 && ev[srt[q]] - ev[srt[q - 1]] <= ortol) continue;  // not a cluster leader
-    double* u0 = scratch + (size_t)q * 6 * MAXD;
-    double* u1 = u0 + MAXD;
-    double* u2 = u1 + MAXD;
-    double* lm = u2 + MAXD;
-    double* x = lm + MAXD;
-    double* piv = x + MAXD;
+  // The reflectors move to global memory so that the LDS matrix becomes the scratch of
+  // the inverse iterations (six vectors of length n per cluster leader).
+  double* refl = work;
+  if (IN_LDS) {
+    for (int idx = tid; idx < n * lda; idx += EB) refl[idx] = A[idx];
+  }
+  __syncthreads();
+  const int per = 6 * (n > 0 ? n : 1);
+  const int cap = IN_LDS ? (SMALL_LDS_D * (SMALL_LDS_D + 1)) / per : EB;
+  int lrank = 0;  // rank of this lane's leader among the leaders
+  bool leader = false;
+  const int q = tid;
+  if (q < nsel) {
+    leader = !(q > 0 && ev[srt[q]] - ev[srt[q - 1]] <= ortol);
+    for (int qq = 1; qq < q; ++qq) lrank += !(ev[srt[qq]] - ev[srt[qq - 1]] <= ortol);
+    if (q > 0) lrank += 1;  // q == 0 is always a leader
+  }
+  const int nlead_max = nsel;  // upper bound on leaders, for the round count
+  for (int round = 0; round * cap < nlead_max; ++round) {
+   if (leader && lrank / cap == round) {
+    const int slot_l = lrank % cap;
+    double* u0 = IN_LDS ? sA + (size_t)slot_l * per : scratch + (size_t)q * 6 * MAXD;
+    const int st = IN_LDS ? n : MAXD;
+    double* u1 = u0 + st;
+    double* u2 = u1 + st;
+    double* lm = u2 + st;
+    double* x = lm + st;
+    double* piv = x + st;
     double shift_prev = -INFINITY;
     for (int p = q; p < nsel && (p == q || ev[srt[p]] - ev[srt[p - 1]] <= ortol); ++p) {
       const int idx = srt[p];
@@ -347,7 +380,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
       }
       u0[n - 1] = (a == 0.0) ? pivmin : a;
       for (int i = 0; i < n; ++i) x[i] = hash_unit(i, slot + 1);
-      for (int it = 0; it < 3; ++it) {
+      for (int it = 0; it < 2; ++it) {
         for (int i = 0; i + 1 < n; ++i) {  // L^{-1} with the row interchanges
           if (piv[i] != 0.0) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
           x[i + 1] -= lm[i] * x[i];
@@ -371,8 +404,9 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
       }
       for (int i = 0; i < n; ++i) F[(size_t)i * kk + slot] = x[i];
     }
+   }
+   __syncthreads();
   }
-  __syncthreads();
 
   // ---- back-transform x <- P_0 ... P_{n-3} x; eight lanes per vector, rows interleaved ----
   constexpr int G = 8, RMAX = MAXD / G;
@@ -393,7 +427,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
 #pragma unroll
       for (int c = 0; c < RMAX; ++c) {
         const int r = gl + G * c;
-        if (r >= k + 1 && r < n) dot += (r == k + 1 ? 1.0 : A[r * lda + k]) * xr[c];
+        if (r >= k + 1 && r < n) dot += (r == k + 1 ? 1.0 : refl[r * lda + k]) * xr[c];
       }
 #pragma unroll
       for (int o = 1; o < G; o <<= 1) dot += __shfl_xor(dot, o, G);
@@ -401,7 +435,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
 #pragma unroll
       for (int c = 0; c < RMAX; ++c) {
         const int r = gl + G * c;
-        if (r >= k + 1 && r < n) xr[c] -= dot * (r == k + 1 ? 1.0 : A[r * lda + k]);
+        if (r >= k + 1 && r < n) xr[c] -= dot * (r == k + 1 ? 1.0 : refl[r * lda + k]);
       }
     }
     if (act) {
@@ -448,15 +482,19 @@ __global__ void k_symmetrize(int d, double* H) {
 
 int64_t eig_work_elems(int d) { return (int64_t)(d + 1) * (d + 1) + (int64_t)6 * MAXD * MAXD; }
 
-void launch_pchol(int m, const double* G, const double* colsq1, const double* colsq2, int kc,
-                  double tol, double* M, int32_t* rank, int32_t* status, hipStream_t s) {
-  // the global-memory variant keeps its factor in the trailing part of M's buffer
-  if (m <= SMALL_LDS_D) {
-    k_pchol<true><<<1, EB, 0, s>>>(m, G, colsq1, colsq2, kc, tol, M, rank, status, nullptr);
-  } else {
-    k_pchol<false><<<1, EB, 0, s>>>(m, G, colsq1, colsq2, kc, tol, M, rank, status,
-                                    M + (size_t)m * m);
+int64_t pchol_work_elems(int m, int kc) { return (int64_t)(m + 1) * (m + 1) + (int64_t)kc * m; }
+
+void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
+                  int32_t* status, double* work, hipStream_t s) {
+  const size_t lds = (size_t)pchol_work_elems(m, C ? kc : 0) * sizeof(double);
+  if (!C) kc = 0;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_pchol<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    attr = true;
   }
+  if (lds <= 150 * 1024) k_pchol<true><<<1, EB, lds, s>>>(m, G, C, kc, tol, Mout, rank, status, nullptr);
+  else k_pchol<false><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status, work);
 }
 
 void launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which, int kk,
