@@ -221,71 +221,125 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const fl
 // X and W are separate column blocks (any widths <= 128).  G always accumulates in
 // FP64; C in the working precision.
 // ---------------------------------------------------------------------------------
-constexpr int PT = 16;  // tiles per wave
+// Waves 0-1 accumulate C (TXC x TWC tiles) and waves 2-3 the upper tiles of G (packed
+// triangle), each pair over alternating 16-row blocks of the workgroup's chunk; all
+// fragments of a block are loaded before its MFMAs.  The two waves of a pair are summed
+// through LDS in a fixed order.
+__host__ __device__ constexpr int tri_idx(int p, int q, int n) { return p * n - p * (p - 1) / 2 + (q - p); }
 
-// one half of the workgroup: C = X^T W tiles (IS_C) or the upper G = W^T W tiles
-template <bool IS_C, typename T, typename Tc>
-__device__ inline void pip_part(int sub, int lane, int64_t r0, int64_t r1, const T* __restrict__ X, int64_t ldx,
-                                int kx, const T* __restrict__ W, int64_t ldw, int w, double* __restrict__ out) {
-  using M = Mma<Tc>;
-  const int g = lane >> 4, c16 = lane & 15;
-  const int TX = (kx + 15) >> 4, TWt = (w + 15) >> 4;
-  int ti[PT], tj[PT];
-#pragma unroll
-  for (int q = 0; q < PT; ++q) {
-    int t = sub + 2 * q;
-    if (IS_C) {
-      ti[q] = t < TX * TWt ? t / TWt : -1;
-      tj[q] = t < TX * TWt ? t % TWt : -1;
-    } else {
-      int a = 0;
-      while (a < TWt && t >= TWt - a) { t -= TWt - a; ++a; }
-      ti[q] = a < TWt ? a : -1;
-      tj[q] = a < TWt ? a + t : -1;
-    }
-  }
-  typename M::acc_t acc[PT];
-#pragma unroll
-  for (int q = 0; q < PT; ++q) acc[q] = typename M::acc_t{0, 0, 0, 0};
-  const int ka = IS_C ? kx : w;
-  for (int64_t rb = r0; rb < r1; rb += 16) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t row = rb + 4 * s + g;
-      const bool ok = row < r1;
-#pragma unroll
-      for (int q = 0; q < PT; ++q) {
-        if (ti[q] < 0) continue;
-        const int cb = tj[q] * 16 + c16;
-        const int ca = ti[q] * 16 + c16;
-        const T vb = (ok && cb < w) ? W[row * ldw + cb] : T(0);
-        const T va = (ok && ca < ka) ? (IS_C ? X[row * ldx + ca] : W[row * ldw + ca]) : T(0);
-        acc[q] = M::run((Tc)va, (Tc)vb, acc[q]);
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < PT; ++q) {
-    if (ti[q] < 0) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = ti[q] * 16 + M::row(lane, r), j = tj[q] * 16 + c16;
-      if (i < ka && j < w) out[(size_t)i * w + j] = (double)acc[q][r];
-    }
-  }
-}
-
-template <typename T, typename Tcx>
+template <typename T, typename Tcx, int TXC, int TWC>
 __global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __restrict__ X, int64_t ldx, int kx,
                                             const T* __restrict__ W, int64_t ldw, int w, double* __restrict__ partC,
                                             double* __restrict__ partG) {
+  constexpr int NTG = TWC * (TWC + 1) / 2;
+  extern __shared__ double red_lds[];  // max(TXC*TWC, NTG) tiles of 256 doubles
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min(n, r0 + rpc);
-  if (wid < 2)
-    pip_part<true, T, Tcx>(wid & 1, lane, r0, r1, X, ldx, kx, W, ldw, w, partC + (size_t)blockIdx.x * kx * w);
-  else
-    pip_part<false, T, double>(wid & 1, lane, r0, r1, X, ldx, kx, W, ldw, w, partG + (size_t)blockIdx.x * w * w);
+  const int half = wid & 1;
+  if (wid < 2) {
+    using M = Mma<Tcx>;
+    typename M::acc_t acc[TXC][TWC];
+#pragma unroll
+    for (int p = 0; p < TXC; ++p)
+#pragma unroll
+      for (int q = 0; q < TWC; ++q) acc[p][q] = typename M::acc_t{0, 0, 0, 0};
+    for (int64_t rb = r0 + 16 * half; rb < r1; rb += 32) {
+      Tcx fx[4][TXC], fw[4][TWC];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t row = rb + 4 * s + g;
+        const bool ok = row < r1;
+#pragma unroll
+        for (int p = 0; p < TXC; ++p) {
+          const int c = p * 16 + c16;
+          fx[s][p] = (ok && c < kx) ? (Tcx)X[row * ldx + c] : Tcx(0);
+        }
+#pragma unroll
+        for (int q = 0; q < TWC; ++q) {
+          const int c = q * 16 + c16;
+          fw[s][q] = (ok && c < w) ? (Tcx)W[row * ldw + c] : Tcx(0);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int p = 0; p < TXC; ++p)
+#pragma unroll
+          for (int q = 0; q < TWC; ++q) acc[p][q] = M::run(fx[s][p], fw[s][q], acc[p][q]);
+    }
+    for (int h = 0; h < 2; ++h) {
+      if (half == h) {
+#pragma unroll
+        for (int p = 0; p < TXC; ++p)
+#pragma unroll
+          for (int q = 0; q < TWC; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int e = ((p * TWC + q) * 16 + M::row(lane, r)) * 16 + c16;
+              red_lds[e] = (h == 0) ? (double)acc[p][q][r] : red_lds[e] + (double)acc[p][q][r];
+            }
+      }
+      __builtin_amdgcn_s_barrier();  // only waves 0-1 take part in the LDS exchange order
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
+  } else {
+    using M = Mma<double>;
+    typename M::acc_t acc[NTG];
+#pragma unroll
+    for (int t = 0; t < NTG; ++t) acc[t] = typename M::acc_t{0, 0, 0, 0};
+    for (int64_t rb = r0 + 16 * half; rb < r1; rb += 32) {
+      double fw[4][TWC];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t row = rb + 4 * s + g;
+        const bool ok = row < r1;
+#pragma unroll
+        for (int q = 0; q < TWC; ++q) {
+          const int c = q * 16 + c16;
+          fw[s][q] = (ok && c < w) ? (double)W[row * ldw + c] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int p = 0; p < TWC; ++p)
+#pragma unroll
+          for (int q = p; q < TWC; ++q) acc[tri_idx(p, q, TWC)] = M::run(fw[s][p], fw[s][q], acc[tri_idx(p, q, TWC)]);
+    }
+    double* lds2 = red_lds + (size_t)TXC * TWC * 256;
+    for (int h = 0; h < 2; ++h) {
+      if (half == h) {
+#pragma unroll
+        for (int t = 0; t < NTG; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (t * 16 + M::row(lane, r)) * 16 + c16;
+            lds2[e] = (h == 0) ? acc[t][r] : lds2[e] + acc[t][r];
+          }
+      }
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    }
+  }
+  __syncthreads();
+  double* oc = partC + (size_t)blockIdx.x * kx * w;
+  double* og = partG + (size_t)blockIdx.x * w * w;
+  for (int e = threadIdx.x; e < TXC * TWC * 256; e += WG) {
+    const int t = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    const int gi = (t / TWC) * 16 + i, gj = (t % TWC) * 16 + j;
+    if (gi < kx && gj < w) oc[(size_t)gi * w + gj] = red_lds[e];
+  }
+  const double* lds2 = red_lds + (size_t)TXC * TWC * 256;
+  for (int e = threadIdx.x; e < NTG * 256; e += WG) {
+    const int t = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    int p = 0, tt = t;
+    while (tt >= TWC - p) { tt -= TWC - p; ++p; }
+    const int q = p + tt;
+    const int gi = p * 16 + i, gj = q * 16 + j;
+    if (gi < w && gj < w) og[(size_t)gi * w + gj] = lds2[e];
+  }
 }
 
 // fixed-order sum of the chunk partials; four lanes per output, combined in order;
@@ -480,18 +534,36 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
 }
 
 // one projection round: C = X^T W and G = W^T W (upper tiles; the reduce mirrors them)
+template <typename T, typename Tcx, int TXC, int TWC>
+static void pip_launch(int g, int64_t n, int64_t rpc, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw,
+                       int w, double* partC, double* partG, hipStream_t s) {
+  constexpr int NTG = TWC * (TWC + 1) / 2;
+  const size_t lds = (size_t)(TXC * TWC + NTG) * 256 * sizeof(double);
+  static bool attr = false;
+  if (!attr && lds > 65536) {
+    (void)hipFuncSetAttribute((const void*)k_pip<T, Tcx, TXC, TWC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    attr = true;
+  }
+  k_pip<T, Tcx, TXC, TWC><<<g, WG, lds, s>>>(n, rpc, X, ldx, kx, W, ldw, w, partC, partG);
+}
+
 template <typename T>
 bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw, int w, double* partial,
                 double* C, double* G, hipStream_t s) {
   const int TX = (kx + 15) >> 4, TWt = (w + 15) >> 4;
-  if (TX * TWt > 2 * PT || TWt * (TWt + 1) / 2 > 2 * PT) return false;
   const int g = tn_num_chunks(n);
   int64_t rpc = (n + g - 1) / g;
-  rpc = ((rpc + 15) / 16) * 16;
+  rpc = ((rpc + 31) / 32) * 32;
   double* partC = partial;
   double* partG = partial + (size_t)g * kx * w;
   using Tcx = typename std::conditional<sizeof(T) == 8, double, float>::type;
-  k_pip<T, Tcx><<<g, WG, 0, s>>>(n, rpc, X, ldx, kx, W, ldw, w, partC, partG);
+  if (TX == 2 && TWt == 4) pip_launch<T, Tcx, 2, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else if (TX == 2 && TWt == 2) pip_launch<T, Tcx, 2, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else if (TX == 1 && TWt == 4) pip_launch<T, Tcx, 1, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else if (TX == 1 && TWt == 2) pip_launch<T, Tcx, 1, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else if (TX == 1 && TWt == 1) pip_launch<T, Tcx, 1, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else return false;
   k_tn_reduce<<<(unsigned)(((int64_t)kx * w + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, kx, w, 0, partC, C);
   k_tn_reduce<<<(unsigned)(((int64_t)w * w + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, w, w, 1, partG, G);
   return true;

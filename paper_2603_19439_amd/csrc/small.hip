@@ -16,6 +16,24 @@
 
 #include <math.h>
 
+// Optional phase clocks for profiling builds (-DGREST_PHASE_CLOCKS): thread 0 records the
+// 100 MHz wall clock at phase boundaries of the small kernels.
+#ifdef GREST_PHASE_CLOCKS
+__device__ long long g_phase_clk[64];
+#define PHASE_MARK(slot)                                  \
+  do {                                                    \
+    __syncthreads();                                      \
+    if (threadIdx.x == 0) g_phase_clk[slot] = wall_clock64(); \
+  } while (0)
+extern "C" int grest_debug_phase_clocks(long long* out, int n) {
+  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_clk), sizeof(long long) * (n < 64 ? n : 64));
+}
+#else
+#define PHASE_MARK(slot) \
+  do {                   \
+  } while (0)
+#endif
+
 namespace {
 
 constexpr int EB = 256;           // threads per workgroup
@@ -81,6 +99,7 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
   const double thr = tol * tol * scale2;
   __syncthreads();
 
+  PHASE_MARK(10);
   int r = 0;
   for (int k = 0; k < m; ++k) {
     // pivot: largest remaining diagonal (ties to the lower position)
@@ -125,6 +144,7 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
     __syncthreads();
     r = k + 1;
   }
+  PHASE_MARK(11);
   // inverse of the leading r x r upper-triangular block, column j by thread j;
   // Rinv[i][j] is kept in row j+1 of S (below the factor) at column i
   for (int j = tid; j < r; j += EB) {
@@ -150,6 +170,7 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
     Mout[idx] = -acc;
   }
   if (tid == 0) *rank_out = r;
+  PHASE_MARK(12);
 }
 
 // ------------------------------------------------------------------------------------
@@ -220,6 +241,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   if (bad) atomicOr(status, ST_NONFINITE);
   __syncthreads();
 
+  PHASE_MARK(0);
   // ---- Householder tridiagonalisation; reflector k stored below the subdiagonal ----
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
@@ -285,6 +307,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   }
   __syncthreads();
 
+  PHASE_MARK(1);
   // ---- eigenvalues: one lane per index, bisection on the inertia count ----
   const double eps = 2.220446049250313e-16;
   const double pivmin = sh_d[3];
@@ -302,6 +325,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   for (int i = tid; i < MAXD; i += EB) { slot_of[i] = -1; }
   __syncthreads();
 
+  PHASE_MARK(2);
   // ---- selection of kk pairs (ev is ascending) ----
   double tmax = 0.0;
   for (int i = 0; i < n; ++i) tmax = fmax(tmax, ev[i]);
@@ -321,6 +345,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   }
   __syncthreads();
 
+  PHASE_MARK(3);
   // ---- eigenvectors of T by inverse iteration; a cluster (gaps below 1e-3 ||T||) is
   //      handled by one lane with distinct shifts and reorthogonalisation ----
   const double ortol = 1e-3 * tnorm;
@@ -408,6 +433,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
    __syncthreads();
   }
 
+  PHASE_MARK(4);
   // ---- back-transform x <- P_0 ... P_{n-3} x; eight lanes per vector, rows interleaved ----
   constexpr int G = 8, RMAX = MAXD / G;
   const int grp = tid / G, gl = tid % G;
@@ -448,6 +474,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   }
   __syncthreads();
 
+  PHASE_MARK(5);
   // ---- values, dropped columns, kept count ----
   if (tid == 0) sh_i[0] = 0;
   __syncthreads();
@@ -465,6 +492,7 @@ __global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const in
   }
   __syncthreads();
   if (tid == 0 && kept_out) *kept_out = sh_i[0];
+  PHASE_MARK(6);
 }
 
 __global__ void k_symmetrize(int d, double* H) {
