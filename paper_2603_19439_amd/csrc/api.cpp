@@ -335,8 +335,11 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   // small FP64 eigensolve on the leading K + rank block, selection of K pairs
   mark(st, 6);
   const int which = st->op == GREST_OP_ADJ ? 0 : 1;
-  launch_small_eig(st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
-                   st->status, st->stream);
+  if (!launch_small_eig(st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
+                        st->status, st->stream)) {
+    snprintf(g_last_error, sizeof(g_last_error), "projected order %d outside the small eigensolver's range", st->D);
+    return GREST_EINVAL;
+  }
   // X' = Z F_K into the other buffer
   mark(st, 7);
   // X' = Z F on FP32 / FP64 MFMA (a memory-bound pass; FP32 keeps X orthonormal to 1e-7)
@@ -440,8 +443,11 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Y, st->ldy, Ls,
                           (T*)st->bt, Ls, s);
       launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
-      launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
-                       st->eigwork, st->status, s);
+      if (!launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
+                            st->eigwork, st->status, s)) {
+        snprintf(g_last_error, sizeof(g_last_error), "sketch order %d outside the small eigensolver's range", Ls);
+        return GREST_EINVAL;
+      }
       // S.4: R = M U_L
       launch_apply<T>(n2, b.Y, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, B2, st->ldz, s);
     }
@@ -693,7 +699,8 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if ((rc = dalloc(&st->thetab, std::max(st->L, 1))) != GREST_OK) return fail(rc);
   st->partial_elems = (int64_t)tn_num_chunks(INT64_MAX / 4) * dmax * dmax;
   if ((rc = dalloc(&st->partial, st->partial_elems)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->eigwork, eig_work_elems(std::max(dmax, std::max(st->Ls, 1))))) != GREST_OK) return fail(rc);
+  const int64_t ework = std::max(eig_work_elems(std::max(dmax, std::max(st->Ls, 1))), pchol_work_elems(wmax, st->K));
+  if ((rc = dalloc(&st->eigwork, ework)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->ranks, 8)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->status, 1)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->maxdeg, 1)) != GREST_OK) return fail(rc);

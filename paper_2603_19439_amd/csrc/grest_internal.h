@@ -102,7 +102,8 @@ void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s);
 // (tol * scale)^2 where scale^2 = max(1, max_j (G_jj + colsq_j)); colsq may be null.
 // With C (kc x m) the factored matrix is G - C^T C, the scale comes from diag(G), and the
 // output Mout is the stacked (kc + m) x m matrix [-C M; M]; without C (kc = 0) Mout = M.
-// work: pchol_work_elems(m, kc) doubles, used when the factor does not fit in LDS.
+// The factor lives in registers and LDS (work is unused; pchol_work_elems is 0).
+// m <= 128.
 int64_t pchol_work_elems(int m, int kc);
 void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
                   int32_t* status, double* work, hipStream_t s);
@@ -115,12 +116,15 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
 template <typename T>
 void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
                    const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s);
-// Symmetric eigensolver of H (first K + rank[0] rows/cols used, ldh = d_full) and
+// Symmetric eigensolver of H (first base + rank[0] rows/cols used, ldh = d_full) and
 // selection of kk pairs: which 0 = largest magnitude, 1 = smallest algebraic,
 // 2 = largest algebraic.  Writes theta[kk] and F (d_full x kk, zero rows past the
-// valid size) and, for the RSVD step, nothing else.  work: >= eig_work_elems(d_full).
+// valid size); with drop_tol > 0 pairs whose value is at most drop_tol^2 max(1, max
+// value) get theta 0 and a zero column, and *kept receives the number of the others.
+// work: >= eig_work_elems(d_full) doubles.  Returns false (nothing launched) unless
+// 1 <= d_full <= 128 and 1 <= kk <= 128.
 int64_t eig_work_elems(int d);
-void launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which,
+bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which,
                       int kk, double drop_tol, double* theta, double* F, int32_t* kept,
                       double* work, int32_t* status, hipStream_t s);
 // H = 0.5 (H + H^T) of a d x d matrix in place

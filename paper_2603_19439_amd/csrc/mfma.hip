@@ -217,14 +217,15 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const fl
 
 // ---------------------------------------------------------------------------------
 // One pass over the rows for a projection round of block Gram-Schmidt with the
-// Pythagorean Gram: C = X^T W (waves 0-1) and G = W^T W, upper tiles (waves 2-3).
+// Pythagorean Gram: C = X^T W and G = W^T W (upper tiles).
 // X and W are separate column blocks (any widths <= 128).  G always accumulates in
 // FP64; C in the working precision.
 // ---------------------------------------------------------------------------------
-// Waves 0-1 accumulate C (TXC x TWC tiles) and waves 2-3 the upper tiles of G (packed
-// triangle), each pair over alternating 16-row blocks of the workgroup's chunk; all
-// fragments of a block are loaded before its MFMAs.  The two waves of a pair are summed
-// through LDS in a fixed order.
+// Every wave takes its own 16-row blocks of the workgroup's chunk and accumulates both
+// the C tiles (TXC x TWC, working precision) and the upper tiles of G (packed triangle,
+// FP64), so all four SIMDs share the FP64 matrix work; the fragments of the next block
+// are loaded while the MFMAs of the current one run.  The four waves are summed through
+// LDS in a fixed order.
 __host__ __device__ constexpr int tri_idx(int p, int q, int n) { return p * n - p * (p - 1) / 2 + (q - p); }
 
 template <typename T, typename Tcx, int TXC, int TWC>
@@ -232,98 +233,87 @@ __global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __r
                                             const T* __restrict__ W, int64_t ldw, int w, double* __restrict__ partC,
                                             double* __restrict__ partG) {
   constexpr int NTG = TWC * (TWC + 1) / 2;
-  extern __shared__ double red_lds[];  // max(TXC*TWC, NTG) tiles of 256 doubles
+  using MC = Mma<Tcx>;
+  using MG = Mma<double>;
+  extern __shared__ double red_lds[];  // TXC*TWC + NTG tiles of 256 doubles
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min(n, r0 + rpc);
-  const int half = wid & 1;
-  if (wid < 2) {
-    using M = Mma<Tcx>;
-    typename M::acc_t acc[TXC][TWC];
+  typename MC::acc_t ac[TXC][TWC];
+  typename MG::acc_t ag[NTG];
 #pragma unroll
-    for (int p = 0; p < TXC; ++p)
+  for (int p = 0; p < TXC; ++p)
 #pragma unroll
-      for (int q = 0; q < TWC; ++q) acc[p][q] = typename M::acc_t{0, 0, 0, 0};
-    for (int64_t rb = r0 + 16 * half; rb < r1; rb += 32) {
-      Tcx fx[4][TXC], fw[4][TWC];
+    for (int q = 0; q < TWC; ++q) ac[p][q] = typename MC::acc_t{0, 0, 0, 0};
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t row = rb + 4 * s + g;
-        const bool ok = row < r1;
+  for (int t = 0; t < NTG; ++t) ag[t] = typename MG::acc_t{0, 0, 0, 0};
+  T fx[4][TXC], fw[4][TWC];
+  auto load = [&](int64_t rb) __attribute__((always_inline)) {
 #pragma unroll
-        for (int p = 0; p < TXC; ++p) {
-          const int c = p * 16 + c16;
-          fx[s][p] = (ok && c < kx) ? (Tcx)X[row * ldx + c] : Tcx(0);
-        }
+    for (int s = 0; s < 4; ++s) {
+      const int64_t row = rb + 4 * s + g;
+      const bool ok = row < r1;
 #pragma unroll
-        for (int q = 0; q < TWC; ++q) {
-          const int c = q * 16 + c16;
-          fw[s][q] = (ok && c < w) ? (Tcx)W[row * ldw + c] : Tcx(0);
-        }
+      for (int p = 0; p < TXC; ++p) {
+        const int c = p * 16 + c16;
+        fx[s][p] = (ok && c < kx) ? X[row * ldx + c] : T(0);
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int p = 0; p < TXC; ++p)
-#pragma unroll
-          for (int q = 0; q < TWC; ++q) acc[p][q] = M::run(fx[s][p], fw[s][q], acc[p][q]);
+      for (int q = 0; q < TWC; ++q) {
+        const int c = q * 16 + c16;
+        fw[s][q] = (ok && c < w) ? W[row * ldw + c] : T(0);
+      }
     }
-    for (int h = 0; h < 2; ++h) {
-      if (half == h) {
+  };
+  int64_t rb = r0 + 16 * wid;
+  if (rb < r1) load(rb);
+  for (; rb < r1; rb += 16 * NW) {
+    T cx[4][TXC], cw[4][TWC];
 #pragma unroll
-        for (int p = 0; p < TXC; ++p)
+    for (int s = 0; s < 4; ++s) {
 #pragma unroll
-          for (int q = 0; q < TWC; ++q)
+      for (int p = 0; p < TXC; ++p) cx[s][p] = fx[s][p];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int e = ((p * TWC + q) * 16 + M::row(lane, r)) * 16 + c16;
-              red_lds[e] = (h == 0) ? (double)acc[p][q][r] : red_lds[e] + (double)acc[p][q][r];
-            }
-      }
-      __builtin_amdgcn_s_barrier();  // only waves 0-1 take part in the LDS exchange order
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      for (int q = 0; q < TWC; ++q) cw[s][q] = fw[s][q];
     }
-  } else {
-    using M = Mma<double>;
-    typename M::acc_t acc[NTG];
+    if (rb + 16 * NW < r1) load(rb + 16 * NW);  // in flight during the MFMAs below
 #pragma unroll
-    for (int t = 0; t < NTG; ++t) acc[t] = typename M::acc_t{0, 0, 0, 0};
-    for (int64_t rb = r0 + 16 * half; rb < r1; rb += 32) {
-      double fw[4][TWC];
+    for (int s = 0; s < 4; ++s) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t row = rb + 4 * s + g;
-        const bool ok = row < r1;
+      for (int p = 0; p < TXC; ++p)
 #pragma unroll
-        for (int q = 0; q < TWC; ++q) {
-          const int c = q * 16 + c16;
-          fw[s][q] = (ok && c < w) ? (double)W[row * ldw + c] : 0.0;
-        }
-      }
+        for (int q = 0; q < TWC; ++q) ac[p][q] = MC::run((Tcx)cx[s][p], (Tcx)cw[s][q], ac[p][q]);
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int p = 0; p < TWC; ++p)
 #pragma unroll
-        for (int p = 0; p < TWC; ++p)
-#pragma unroll
-          for (int q = p; q < TWC; ++q) acc[tri_idx(p, q, TWC)] = M::run(fw[s][p], fw[s][q], acc[tri_idx(p, q, TWC)]);
-    }
-    double* lds2 = red_lds + (size_t)TXC * TWC * 256;
-    for (int h = 0; h < 2; ++h) {
-      if (half == h) {
-#pragma unroll
-        for (int t = 0; t < NTG; ++t)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int e = (t * 16 + M::row(lane, r)) * 16 + c16;
-            lds2[e] = (h == 0) ? acc[t][r] : lds2[e] + acc[t][r];
-          }
-      }
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        for (int q = p; q < TWC; ++q)
+          ag[tri_idx(p, q, TWC)] = MG::run((double)cw[s][p], (double)cw[s][q], ag[tri_idx(p, q, TWC)]);
     }
   }
-  __syncthreads();
+  // fixed-order sum of the four waves
+  double* lds2 = red_lds + (size_t)TXC * TWC * 256;
+  for (int v = 0; v < NW; ++v) {
+    if (wid == v) {
+#pragma unroll
+      for (int p = 0; p < TXC; ++p)
+#pragma unroll
+        for (int q = 0; q < TWC; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = ((p * TWC + q) * 16 + MC::row(lane, r)) * 16 + c16;
+            red_lds[e] = (v == 0) ? (double)ac[p][q][r] : red_lds[e] + (double)ac[p][q][r];
+          }
+#pragma unroll
+      for (int t = 0; t < NTG; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = (t * 16 + MG::row(lane, r)) * 16 + c16;
+          lds2[e] = (v == 0) ? ag[t][r] : lds2[e] + ag[t][r];
+        }
+    }
+    __syncthreads();
+  }
   double* oc = partC + (size_t)blockIdx.x * kx * w;
   double* og = partG + (size_t)blockIdx.x * w * w;
   for (int e = threadIdx.x; e < TXC * TWC * 256; e += WG) {
@@ -331,7 +321,6 @@ __global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __r
     const int gi = (t / TWC) * 16 + i, gj = (t % TWC) * 16 + j;
     if (gi < kx && gj < w) oc[(size_t)gi * w + gj] = red_lds[e];
   }
-  const double* lds2 = red_lds + (size_t)TXC * TWC * 256;
   for (int e = threadIdx.x; e < NTG * 256; e += WG) {
     const int t = e >> 8, i = (e >> 4) & 15, j = e & 15;
     int p = 0, tt = t;

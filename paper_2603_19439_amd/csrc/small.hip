@@ -1,23 +1,30 @@
-// One-workgroup FP64 kernels on the small matrices of the update:
-//   * rank-revealing Cholesky with diagonal pivoting of a Gram matrix (the
-//     factor of CholQR2); the inverse factor is returned as the matrix M that
-//     maps W to its orthonormal basis W M;
+// FP64 kernels on the small matrices of the update:
+//   * rank-revealing Cholesky with diagonal pivoting of a Gram matrix (the factor of
+//     CholQR2); the inverse factor is returned as the matrix M that maps W to its
+//     orthonormal basis W M;
 //   * the dense symmetric eigensolver of the projected matrix (Alg. 1, small
 //     eigenproblem) and of the sketch Gram B B^T of the randomized range finder
 //     (Sec. 3.5), followed by the selection of the wanted pairs.
-// The eigensolver is Householder tridiagonalisation (reflectors kept in place), all
-// eigenvalues of the tridiagonal by bisection on the LDL^T inertia (one lane per
-// eigenvalue), eigenvectors of the selected ones only by inverse iteration with an
-// LU factorisation with partial pivoting (clusters closer than 1e-3 ||T|| get distinct
-// shifts and reorthogonalisation on one lane), and the back-transform through the
-// reflectors with eight lanes per vector.  Matrices up to SMALL_LDS_D live in LDS,
-// larger ones in a global workspace.
+// The eigensolver runs as three launches:
+//   1. one workgroup: Householder tridiagonalisation in LDS (each reflector written to a
+//      global table, zero padded to the full row);
+//   2. one wave per eigenvalue: multisection on the LDL^T inertia count, 64 probes per
+//      step (one per lane), so that an eigenvalue is found in about nine steps;
+//   3. one wave per selected pair: selection and inverse iteration with an LU
+//      factorisation with partial pivoting of T - lambda I.  Pairs closer than 1e-7 ||T||
+//      are computed one after the other by the wave of the lowest one, with
+//      reorthogonalisation against the finished members;
+//   4. one wave per selected pair: first-order symmetric orthogonalisation of the
+//      selected tridiagonal-basis vectors, y_s <- y_s - (1/2) sum_t (y_t^T y_s) y_t, which
+//      removes the eps ||T|| / gap overlap that independent inverse iterations leave
+//      between neighbours, then the back-transform through the reflectors.
+// Orders up to MAXN = 128 are supported.
 #include "grest_internal.h"
 
 #include <math.h>
 
 // Optional phase clocks for profiling builds (-DGREST_PHASE_CLOCKS): thread 0 records the
-// 100 MHz wall clock at phase boundaries of the small kernels.
+// 100 MHz wall clock at phase boundaries of the pivoted Cholesky.
 #ifdef GREST_PHASE_CLOCKS
 __device__ long long g_phase_clk[64];
 #define PHASE_MARK(slot)                                  \
@@ -28,158 +35,573 @@ __device__ long long g_phase_clk[64];
 extern "C" int grest_debug_phase_clocks(long long* out, int n) {
   return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_clk), sizeof(long long) * (n < 64 ? n : 64));
 }
+// per-section cycle accounting inside a loop (threads 0 and 64 only)
+#define SECT_DECL long long sect_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sect_t = clock64();
+#define SECT(i)                                  \
+  do {                                           \
+    const long long t_ = clock64();              \
+    sect_acc[i] += t_ - sect_t;                  \
+    sect_t = t_;                                 \
+  } while (0)
+#define SECT_WRITE(base)                                                        \
+  do {                                                                          \
+    if (threadIdx.x == 0 || threadIdx.x == 64)                                  \
+      for (int i_ = 0; i_ < 8; ++i_) g_phase_clk[(base) + (threadIdx.x ? 8 : 0) + i_] = sect_acc[i_]; \
+  } while (0)
 #else
 #define PHASE_MARK(slot) \
+  do {                   \
+  } while (0)
+#define SECT_DECL
+#define SECT(i) \
+  do {          \
+  } while (0)
+#define SECT_WRITE(base) \
   do {                   \
   } while (0)
 #endif
 
 namespace {
 
-constexpr int EB = 256;           // threads per workgroup
-constexpr int SMALL_LDS_D = 128;  // largest order kept in LDS (128 x 129 doubles = 132 KB)
-constexpr int MAXD = 256;         // largest supported order
+constexpr int EB = 256;    // threads of the one-workgroup kernels
+constexpr int NW = EB / GREST_WAVE;
+constexpr int MAXN = 128;  // largest order
+constexpr double EPS = 2.220446049250313e-16;
 
-__device__ double block_sum(double v, double* red) {
+// work layout of the eigensolver (doubles)
+constexpr int W_HDR = 0;               // n, lo, hi, ||T||, pivmin
+constexpr int W_DG = 8;                // diagonal of T
+constexpr int W_OD = W_DG + MAXN;      // off-diagonal of T
+constexpr int W_E2 = W_OD + MAXN;      // squared off-diagonal
+constexpr int W_HB = W_E2 + MAXN;      // reflector coefficients beta_k
+constexpr int W_EV = W_HB + MAXN;      // eigenvalues of T, ascending
+constexpr int W_FL = W_EV + MAXN;      // 1 for an output slot that holds a kept pair
+constexpr int W_R = 1024;              // reflector k in row k (MAXN x MAXN), v_{k+1} = 1
+constexpr int W_Y = W_R + MAXN * MAXN;  // tridiagonal-basis vectors of clustered pairs
+constexpr int W_END = W_Y + MAXN * MAXN;
+
+// ---- wave-level primitives (64 lanes, every lane active) ----
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over the wave, the same value in every lane: butterflies inside each row of 16
+// lanes (quad swaps, half-row and row mirrors), then the four row sums.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+  v = fmin(v, dpp_d<0xB1>(v));
+  v = fmin(v, dpp_d<0x4E>(v));
+  v = fmin(v, dpp_d<0x141>(v));
+  v = fmin(v, dpp_d<0x140>(v));
+  return fmin(fmin(readlane_d(v, 0), readlane_d(v, 16)), fmin(readlane_d(v, 32), readlane_d(v, 48)));
+}
+// Orders LDS traffic of one wave across lanes (a write by one lane, then a read by another).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// 1/x to full precision: hardware estimate and two Newton steps.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// ------------------------------------------------------------------------------------
+// Register-resident small matrices.  In the one-workgroup kernels below a matrix of order
+// up to M (64 or 128) lives in registers: thread (wave w, lane l) holds rows
+// i = w + 4 r (r < M / 4) at columns j = l + 64 c (c < M / 64), always addressed with
+// compile-time indices.  A column j is gathered by the lane l = j mod 64 of every wave,
+// which writes its registers at column block j / 64 to LDS; an element of a
+// lane-distributed vector that a whole wave needs is read with readlane.
+// ------------------------------------------------------------------------------------
+template <int C>
+__device__ __forceinline__ double pick(const double (&x)[C], int c) {
+  double v = x[0];
 #pragma unroll
-  for (int o = GREST_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, GREST_WAVE);
-  const int lane = threadIdx.x & (GREST_WAVE - 1), wid = threadIdx.x / GREST_WAVE;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int w = 0; w < EB / GREST_WAVE; ++w) t += red[w];
-  return t;
+  for (int q = 1; q < C; ++q) v = (c == q) ? x[q] : v;
+  return v;
+}
+// element j of a vector held as x[c] at column lane + 64 c (j uniform)
+template <int C>
+__device__ __forceinline__ double vec_elem(const double (&x)[C], int j) {
+  return readlane_d(pick<C>(x, j >> 6), j & (GREST_WAVE - 1));
+}
+// this wave's rows of column j (uniform) to buf[i]
+template <int RW, int C>
+__device__ __forceinline__ void column_to_lds(const double (&A)[RW][C], int j, int wv, int n, double* buf) {
+  const int lane = threadIdx.x & (GREST_WAVE - 1);
+  if (lane == (j & (GREST_WAVE - 1))) {
+    const int cj = j >> 6;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int i = wv + NW * r;
+      if (i < n) buf[i] = pick<C>(A[r], cj);
+    }
+  }
 }
 
 // ------------------------------------------------------------------------------------
 // pivoted Cholesky:  G(P) = R^T R  truncated at the first pivot <= (tol*scale)^2
-// M[perm[i], j] = Rinv[i, j] for i <= j < rank, every other entry 0.
+// M[perm[a], j] = Rinv[a, j] for a <= j < rank, every other entry 0.
 // ------------------------------------------------------------------------------------
 // With a projection coefficient block C (kc x m) the factored matrix is the Gram of the
 // projected block, G - C^T C (Pythagorean form of block Gram-Schmidt), the rank scale is
 // taken from G itself (the block before projection), and the output is the stacked
 // (kc + m) x m matrix [-C M; M], so that (W - X C) M = [X W] [-C M; M].
-template <bool IN_LDS>
-__global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const double* C, int kc, double tol,
-                                              double* Mout, int32_t* rank_out, int32_t* status, double* work) {
-  extern __shared__ double dyn[];
-  __shared__ int perm[MAXD];
-  __shared__ double red[EB / GREST_WAVE];
-  __shared__ double sh_val[2];
-  __shared__ int sh_idx;
-  const int lds = m + 1;
-  double* S = IN_LDS ? dyn : work;
-  double* Cs = IN_LDS ? dyn + (size_t)lds * lds : work + (size_t)lds * lds;
-  double* M = Mout + (size_t)kc * m;  // the m x m block
-  const int tid = threadIdx.x;
+// Pivoting needs no row swaps: at step k column p = perm[k] of the current Schur
+// complement (its row up to rounding) is gathered in LDS and kept there (it is
+// R[k, .] R[k, k] by original index); every wave keeps the whole
+// diagonal up to date, so all waves choose the same next pivot without an exchange, and
+// one barrier per step suffices.  The inverse factor is formed as its transpose, whose
+// rows are independent triangular solves, so that loop needs no barrier at all.
+__device__ __forceinline__ bool chosen_bit(uint64_t c0, uint64_t c1, int j) {
+  return j < 64 ? ((c0 >> j) & 1ull) : ((c1 >> (j - 64)) & 1ull);
+}
 
-  for (int idx = tid; idx < kc * m; idx += EB) Cs[idx] = C[idx];
-  __syncthreads();
-  // load, subtract C^T C, and find the scale max_j G_jj
-  double mx = 0.0;
+template <int M>
+__global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const double* Cp, int kc, double tol,
+                                              double* Mout, int32_t* rank_out, int32_t* status) {
+  constexpr int CC = M / GREST_WAVE, RW = M / NW, LP = M + 1;
+  __shared__ double Rrow[M * LP];  // pivot rows by step (pitch M + 1); later X = R^{-1}
+  __shared__ int perm[M], iperm[M];
+  __shared__ double rdg[M];
+  double* Mblk = Mout + (size_t)kc * m;  // the m x m block of the output
+  const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / GREST_WAVE);
+
+  for (int j = tid; j < M; j += EB) iperm[j] = -1;
+  // S = sym(G) - C^T C in registers and its diagonal in every wave
+  double S[RW][CC], d[CC];
   int bad = 0;
-  for (int idx = tid; idx < m * m; idx += EB) {
-    int i = idx / m, j = idx % m;
-    double g = 0.5 * (G[(size_t)i * m + j] + G[(size_t)j * m + i]);
-    for (int l = 0; l < kc; ++l) g -= Cs[l * m + i] * Cs[l * m + j];
-    if (!isfinite(g)) bad = 1;
-    S[i * lds + j] = g;
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int i = wv + NW * r;
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int j = lane + GREST_WAVE * c;
+      double g = 0.0;
+      if (i < m && j < m) {
+        g = 0.5 * (G[(size_t)i * m + j] + G[(size_t)j * m + i]);
+        for (int l = 0; l < kc; ++l) g = fma(-Cp[(size_t)l * m + i], Cp[(size_t)l * m + j], g);
+        if (!isfinite(g)) bad = 1;
+      }
+      S[r][c] = g;
+    }
   }
-  for (int j = tid; j < m; j += EB) {
-    mx = fmax(mx, G[(size_t)j * m + j]);
-    perm[j] = j;
+  double mx = 0.0;
+#pragma unroll
+  for (int c = 0; c < CC; ++c) {
+    const int j = lane + GREST_WAVE * c;
+    double g = 0.0;
+    if (j < m) {
+      mx = fmax(mx, G[(size_t)j * m + j]);
+      g = 0.5 * (G[(size_t)j * m + j] + G[(size_t)j * m + j]);
+      for (int l = 0; l < kc; ++l) g = fma(-Cp[(size_t)l * m + j], Cp[(size_t)l * m + j], g);
+    }
+    d[c] = g;
   }
-  for (int o = GREST_WAVE / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, GREST_WAVE));
-  if ((tid & (GREST_WAVE - 1)) == 0) red[tid / GREST_WAVE] = mx;
   if (bad) atomicOr(status, ST_NONFINITE);
-  __syncthreads();
-  double scale2 = 1.0;
-  for (int w = 0; w < EB / GREST_WAVE; ++w) scale2 = fmax(scale2, red[w]);
-  const double thr = tol * tol * scale2;
+  const double thr = tol * tol * fmax(1.0, wave_max_d(mx));
   __syncthreads();
 
   PHASE_MARK(10);
+  uint64_t ch0 = 0, ch1 = 0;
   int r = 0;
   for (int k = 0; k < m; ++k) {
-    // pivot: largest remaining diagonal (ties to the lower position)
-    if (tid < GREST_WAVE) {
-      double best = -1.0;
-      int bi = -1;
-      for (int j = k + tid; j < m; j += GREST_WAVE) {
-        double v = S[j * lds + j];
-        if (v > best) { best = v; bi = j; }
-      }
-      for (int o = GREST_WAVE / 2; o > 0; o >>= 1) {
-        double ob = __shfl_xor(best, o, GREST_WAVE);
-        int oi = __shfl_xor(bi, o, GREST_WAVE);
-        if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ob; bi = oi; }
-      }
-      if (tid == 0) { sh_val[0] = best; sh_idx = bi; }
+    // pivot: the largest remaining diagonal; the key keeps the value's leading bits and
+    // puts 127 - j in the last seven mantissa bits, so ties go to the lower position
+    double key = -1.0;
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int j = lane + GREST_WAVE * c;
+      if (j < m && !chosen_bit(ch0, ch1, j) && d[c] > 0.0)
+        key = fmax(key, __longlong_as_double((__double_as_longlong(d[c]) & ~0x7FLL) | (long long)(127 - j)));
     }
+    const double best = wave_max_d(key);
+    if (!(best > 0.0)) break;
+    const int p = 127 - (int)(__double_as_longlong(best) & 0x7F);
+    const double piv = vec_elem<CC>(d, p);
+    if (!(piv > thr)) break;  // also stops on NaN
+    if (p < 64) ch0 |= 1ull << p; else ch1 |= 1ull << (p - 64);
+    double* rowk = Rrow + k * LP;
+    column_to_lds<RW, CC>(S, p, wv, m, rowk);
+    if (tid == 0) { perm[k] = p; iperm[p] = k; rdg[k] = sqrt(piv); }
     __syncthreads();
-    const double piv = sh_val[0];
-    const int p = sh_idx;
-    if (!(piv > thr) || p < 0) break;  // also stops on NaN
-    if (p != k) {  // symmetric swap of rows/cols k and p
-      for (int j = tid; j < m; j += EB) {
-        double t = S[k * lds + j]; S[k * lds + j] = S[p * lds + j]; S[p * lds + j] = t;
-      }
-      __syncthreads();
-      for (int i = tid; i < m; i += EB) {
-        double t = S[i * lds + k]; S[i * lds + k] = S[i * lds + p]; S[i * lds + p] = t;
-      }
-      if (tid == 0) { int t = perm[k]; perm[k] = perm[p]; perm[p] = t; }
-      __syncthreads();
+    double rp[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int j = lane + GREST_WAVE * c;
+      rp[c] = j < m ? rowk[j] : 0.0;
     }
-    const double rkk = sqrt(piv);
-    for (int j = k + 1 + tid; j < m; j += EB) S[k * lds + j] /= rkk;
-    __syncthreads();
-    if (tid == 0) S[k * lds + k] = rkk;
-    const int t = m - k - 1;
-    for (int idx = tid; idx < t * t; idx += EB) {
-      int i = k + 1 + idx / t, j = k + 1 + idx % t;
-      S[i * lds + j] -= S[k * lds + i] * S[k * lds + j];
+    const double ip = 1.0 / piv;
+    double f[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) f[q] = rowk[wv + NW * q];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const int i = wv + NW * q;
+      const double fq = (i < m && !chosen_bit(ch0, ch1, i)) ? f[q] * ip : 0.0;
+#pragma unroll
+      for (int c = 0; c < CC; ++c) S[q][c] = fma(-fq, rp[c], S[q][c]);
     }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CC; ++c) d[c] = fma(-(rp[c] * ip), rp[c], d[c]);
     r = k + 1;
   }
   PHASE_MARK(11);
-  // inverse of the leading r x r upper-triangular block, column j by thread j;
-  // Rinv[i][j] is kept in row j+1 of S (below the factor) at column i
-  for (int j = tid; j < r; j += EB) {
-    for (int i = j; i >= 0; --i) {
-      double acc = (i == j) ? 1.0 : 0.0;
-      for (int l = i + 1; l <= j; ++l) acc -= S[i * lds + l] * S[(j + 1) * lds + l];
-      S[(j + 1) * lds + i] = acc / S[i * lds + i];
+  // Y = X^T with X = R^{-1}, R[a][b] = Rrow[a][perm[b]] / rdg[a] (upper triangular in
+  // pivot order).  Row j of Y is column j of X, an independent solve: for i descending,
+  // X[i][j] /= R[i][i], then X[a][j] -= R[a][i] X[i][j] for a < i.
+  double Y[RW][CC];
+#pragma unroll
+  for (int q = 0; q < RW; ++q)
+#pragma unroll
+    for (int c = 0; c < CC; ++c) Y[q][c] = (wv + NW * q == lane + GREST_WAVE * c && wv + NW * q < r) ? 1.0 : 0.0;
+  for (int i = r - 1; i >= 0; --i) {
+    const int pi = perm[i], li = i & (GREST_WAVE - 1), ci = i >> 6;
+    const double s = 1.0 / rdg[i];
+    double ra[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int a = lane + GREST_WAVE * c;
+      ra[c] = a < i ? Rrow[a * LP + pi] / rdg[a] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+#pragma unroll
+      for (int c = 0; c < CC; ++c) Y[q][c] = (c == ci && lane == li) ? Y[q][c] * s : Y[q][c];
+      const double yi = vec_elem<CC>(Y[q], i);
+#pragma unroll
+      for (int c = 0; c < CC; ++c) Y[q][c] = fma(-ra[c], yi, Y[q][c]);
     }
   }
-  __syncthreads();
-  for (int idx = tid; idx < m * m; idx += EB) M[idx] = 0.0;
-  __syncthreads();
-  for (int idx = tid; idx < m * m; idx += EB) {
-    int i = idx / m, j = idx % m;
-    if (i < r && j < r && i <= j) M[(size_t)perm[i] * m + j] = S[(j + 1) * lds + i];
+  PHASE_MARK(13);
+  __syncthreads();  // every read of Rrow is done; it now receives X
+#pragma unroll
+  for (int q = 0; q < RW; ++q) {
+    const int j = wv + NW * q;
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int a = lane + GREST_WAVE * c;
+      if (a < r && j < m) {
+        Rrow[a * LP + j] = Y[q][c];
+        Mblk[(size_t)perm[a] * m + j] = Y[q][c];  // M[perm[a]][j] = X[a][j]
+      }
+    }
+    if (j < m && iperm[j] < 0)  // rows of dropped columns are zero
+      for (int t = lane; t < m; t += GREST_WAVE) Mblk[(size_t)j * m + t] = 0.0;
   }
-  // -C M: row l, column j < r sums over the pivoted rows i <= j
-  for (int idx = tid; idx < kc * m; idx += EB) {
-    const int l = idx / m, j = idx % m;
-    double acc = 0.0;
-    if (j < r)
-      for (int i = 0; i <= j; ++i) acc += Cs[l * m + perm[i]] * S[(j + 1) * lds + i];
-    Mout[idx] = -acc;
+  __syncthreads();
+  // -C M = -(C P) X: wave w takes rows l = l0 + 8 w + t of C (t < 8), lanes the columns;
+  // X[a][j] is zero for a > j, so the sum runs over every a < r
+  constexpr int LT = 8;
+  for (int l0 = 0; l0 < kc; l0 += NW * LT) {
+    const int lb = l0 + LT * wv;
+    double acc[LT][CC];
+#pragma unroll
+    for (int t = 0; t < LT; ++t)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) acc[t][c] = 0.0;
+    for (int a = 0; a < r; ++a) {
+      const int pa = __builtin_amdgcn_readfirstlane(perm[a]);
+      double xa[CC];
+#pragma unroll
+      for (int c = 0; c < CC; ++c) xa[c] = Rrow[a * LP + lane + GREST_WAVE * c];
+#pragma unroll
+      for (int t = 0; t < LT; ++t) {
+        const double cv = (lb + t < kc) ? Cp[(size_t)(lb + t) * m + pa] : 0.0;
+#pragma unroll
+        for (int c = 0; c < CC; ++c) acc[t][c] = fma(cv, xa[c], acc[t][c]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < LT; ++t)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) {
+        const int j = lane + GREST_WAVE * c;
+        if (lb + t < kc && j < m) Mout[(size_t)(lb + t) * m + j] = -acc[t][c];
+      }
   }
   if (tid == 0) *rank_out = r;
   PHASE_MARK(12);
 }
 
 // ------------------------------------------------------------------------------------
-// symmetric eigensolver + selection
+// 1. tridiagonalisation T = Q^T A Q, Q = P_0 ... P_{n-3}, P_k = I - beta_k v_k v_k^T
 // ------------------------------------------------------------------------------------
-__device__ inline bool sel_less(int which, double ta, int ia, double tb, int ib) {
+// A lives in registers (see above).  Iteration k:
+//   every wave reads column k (gathered in LDS at the end of the previous iteration) and
+//   forms the reflector itself (identical arithmetic in every wave, so nothing needs to
+//   be published); v is zero outside rows k+1 .. n-1, so the full-width updates below
+//   leave the rest of A unchanged;
+//   p = beta A v: each wave sums over its rows (symmetry turns row sums into column
+//   sums), the four partial vectors meet in LDS;
+//   w = p - (beta p^T v / 2) v;  A <- A - v w^T - w v^T in registers;
+//   column k+1 of the updated A goes to LDS for the next iteration.
+// Two barriers per iteration.
+template <int M>
+__global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int32_t* rank_p, const double* H,
+                                                double* work, int32_t* status) {
+  constexpr int C = M / GREST_WAVE, RW = M / NW;
+  __shared__ double pw4[NW][M];
+  __shared__ double colb[2][M];
+  __shared__ double vwb[NW][2][M];  // each wave's own copy of v and w
+  __shared__ double sdg[M], sod[M], shb[M];
+  const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / GREST_WAVE);
+  int n = base + (rank_p ? rank_p[0] : 0);
+  if (n > d_full) n = d_full;
+  if (n > M) n = M;
+  if (n < 0) n = 0;
+  double* R = work + W_R;
+
+  double A[RW][C];
+  int bad = 0;
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int i = wv + NW * r;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = lane + GREST_WAVE * c;
+      double h = 0.0;
+      if (i < n && j < n) {
+        h = 0.5 * (H[(size_t)i * d_full + j] + H[(size_t)j * d_full + i]);
+        if (!isfinite(h)) { bad = 1; h = 0.0; }
+      }
+      A[r][c] = h;
+    }
+  }
+  if (bad) atomicOr(status, ST_NONFINITE);
+  if (n >= 1) column_to_lds<RW, C>(A, 0, wv, n, colb[0]);
+  __syncthreads();
+  PHASE_MARK(0);
+  SECT_DECL
+
+  for (int k = 0; k + 2 < n; ++k) {
+    const double* col = colb[k & 1];
+    // reflector annihilating column k below k+1
+    double x[C];
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = lane + GREST_WAVE * c;
+      x[c] = (j > k + 1 && j < n) ? col[j] : 0.0;
+      s2 = fma(x[c], x[c], s2);
+    }
+    const double x0 = col[k + 1];
+    const double sigma = wave_sum_d(s2);
+    double beta = 0.0, v0 = 1.0, ek = x0;
+    if (sigma > 0.0) {
+      const double mu = sqrt(x0 * x0 + sigma);
+      v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma / (x0 + mu));
+      beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+      ek = mu;
+    }
+    const double inv = 1.0 / v0;
+    SECT(0);
+    double v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = lane + GREST_WAVE * c;
+      v[c] = (j == k + 1) ? 1.0 : x[c] * inv;
+    }
+    if (wv == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) R[(size_t)k * MAXN + lane + GREST_WAVE * c] = v[c];
+      if (C == 1) R[(size_t)k * MAXN + lane + GREST_WAVE] = 0.0;
+      if (lane == 0) { sdg[k] = col[k]; sod[k] = ek; shb[k] = beta; }
+    }
+    // column blocks entirely inside the finished part (j <= k) take no part
+    const int c0 = (k + 1) / GREST_WAVE;
+    double vr[RW];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) vwb[wv][0][lane + GREST_WAVE * c] = v[c];
+      wave_lds_fence();
+#pragma unroll
+      for (int r = 0; r < RW; ++r) vr[r] = vwb[wv][0][wv + NW * r];
+      double pp[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) pp[c] = 0.0;
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        if (wv + NW * r > k) {
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (c >= c0) pp[c] = fma(A[r][c], vr[r], pp[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) pw4[wv][lane + GREST_WAVE * c] = pp[c];
+    }
+    SECT(1);
+    __syncthreads();
+    SECT(2);
+    if (beta != 0.0) {
+      double p[C], w[C];
+      double pv = 0.0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int j = lane + GREST_WAVE * c;
+        p[c] = (j > k && j < n) ? beta * ((pw4[0][j] + pw4[1][j]) + (pw4[2][j] + pw4[3][j])) : 0.0;
+        pv = fma(p[c], v[c], pv);
+      }
+      const double Kc = 0.5 * beta * wave_sum_d(pv);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        w[c] = fma(-Kc, v[c], p[c]);
+        vwb[wv][1][lane + GREST_WAVE * c] = w[c];
+      }
+      wave_lds_fence();
+      SECT(3);
+      double wr[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) wr[r] = vwb[wv][1][wv + NW * r];
+      // v and w vanish outside rows/cols k+1 .. n-1, so the update leaves the rest as is
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        if (wv + NW * r > k) {
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            if (c >= c0) A[r][c] = fma(-vr[r], w[c], fma(-wr[r], v[c], A[r][c]));
+        }
+      }
+    }
+    SECT(4);
+    column_to_lds<RW, C>(A, k + 1, wv, n, colb[(k + 1) & 1]);
+    SECT(5);
+    __syncthreads();
+    SECT(6);
+  }
+  SECT_WRITE(20);
+  PHASE_MARK(1);
+  // the last two diagonal entries and the last off-diagonal one: column n-2 is in LDS
+  // (n >= 3) or is gathered here, then column n-1
+  if (n >= 2) {
+    if (n == 2) {
+      column_to_lds<RW, C>(A, 0, wv, n, colb[0]);
+      __syncthreads();
+    }
+    if (tid == 0) { sdg[n - 2] = colb[n & 1][n - 2]; sod[n - 2] = colb[n & 1][n - 1]; shb[n - 2] = 0.0; }
+    __syncthreads();
+    column_to_lds<RW, C>(A, n - 1, wv, n, colb[(n - 1) & 1]);
+    __syncthreads();
+    if (tid == 0) { sdg[n - 1] = colb[(n - 1) & 1][n - 1]; sod[n - 1] = 0.0; shb[n - 1] = 0.0; }
+  } else if (n == 1) {
+    if (tid == 0) { sdg[0] = colb[0][0]; sod[0] = 0.0; shb[0] = 0.0; }
+  }
+  __syncthreads();
+  if (wv == 0) {
+    // Gershgorin interval, norm, pivot floor; T to global memory
+    double lo = INFINITY, hi = -INFINITY, tn = 0.0, emax = 0.0;
+    for (int i = lane; i < MAXN; i += GREST_WAVE) {
+      if (i < n) {
+        const double r = (i > 0 ? fabs(sod[i - 1]) : 0.0) + (i + 1 < n ? fabs(sod[i]) : 0.0);
+        lo = fmin(lo, sdg[i] - r);
+        hi = fmax(hi, sdg[i] + r);
+        tn = fmax(tn, fabs(sdg[i]) + r);
+        const double e2 = (i + 1 < n) ? sod[i] * sod[i] : 0.0;
+        emax = fmax(emax, e2);
+        work[W_DG + i] = sdg[i];
+        work[W_OD + i] = (i + 1 < n) ? sod[i] : 0.0;
+        work[W_E2 + i] = e2;
+        work[W_HB + i] = shb[i];
+      }
+    }
+    lo = wave_min_d(lo);
+    hi = wave_max_d(hi);
+    tn = wave_max_d(tn);
+    emax = wave_max_d(emax);
+    if (lane == 0) {
+      if (n == 0) { lo = 0.0; hi = 0.0; }
+      const double pad = 4.0 * EPS * fmax(tn, 1e-300) + 1e-300;
+      work[W_HDR + 0] = (double)n;
+      work[W_HDR + 1] = lo - pad;
+      work[W_HDR + 2] = hi + pad;
+      work[W_HDR + 3] = tn;
+      work[W_HDR + 4] = 1e-290 * fmax(1.0, emax);
+    }
+  }
+  PHASE_MARK(2);
+}
+
+// ------------------------------------------------------------------------------------
+// 2. eigenvalues: one wave per index t, 64-way multisection on the inertia count
+// ------------------------------------------------------------------------------------
+// Number of eigenvalues of the tridiagonal (dg, e2 = off-diagonal squared) below x, from
+// the pivots of the LDL^T factorisation of T - x I; tiny pivots become -pivmin.
+__device__ __forceinline__ int sturm_count(const double* dg, const double* e2, int n, double x, double pivmin) {
+  double q = dg[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q < 0.0;
+#pragma unroll 4
+  for (int i = 1; i < n; ++i) {
+    q = fma(-e2[i - 1], recip(q), dg[i] - x);
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+__device__ __forceinline__ double probe_at(double lo, double w, int s) { return lo + w * ((double)s * (1.0 / 65.0)); }
+
+__global__ void __launch_bounds__(GREST_WAVE) k_bisect(double* work) {
+  __shared__ double sdg[MAXN], se2[MAXN];
+  const int t = blockIdx.x, lane = threadIdx.x;
+  const int n = (int)work[W_HDR];
+  if (t >= n) return;
+  for (int i = lane; i < n; i += GREST_WAVE) { sdg[i] = work[W_DG + i]; se2[i] = work[W_E2 + i]; }
+  __syncthreads();
+  double lo = work[W_HDR + 1], hi = work[W_HDR + 2];
+  const double tnorm = work[W_HDR + 3], pivmin = work[W_HDR + 4];
+  const double atol = fmax(EPS * tnorm, pivmin);
+  for (int it = 0; it < 24; ++it) {
+    const double w = hi - lo;
+    if (!(w > fmax(atol, 2.0 * EPS * fmax(fabs(lo), fabs(hi))))) break;
+    // probe s = lane + 1; the first probe whose count exceeds t closes the bracket
+    const int c = sturm_count(sdg, se2, n, probe_at(lo, w, lane + 1), pivmin);
+    const unsigned long long above = __ballot(c > t);
+    const int a = above ? __builtin_ctzll(above) : GREST_WAVE;  // probes 1..a have count <= t
+    const double nlo = a == 0 ? lo : probe_at(lo, w, a);
+    const double nhi = a == GREST_WAVE ? hi : probe_at(lo, w, a + 1);
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) work[W_EV + t] = 0.5 * (lo + hi);
+}
+
+// ------------------------------------------------------------------------------------
+// 3. selection, inverse iteration and back-transform: one wave per output slot
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ bool sel_less(int which, double ta, int ia, double tb, int ib) {
   // true if (ta, ia) comes before (tb, ib) in output order
   if (which == 0) {  // largest magnitude, then larger algebraic, then lower index
-    double aa = fabs(ta), ab = fabs(tb);
+    const double aa = fabs(ta), ab = fabs(tb);
     if (aa != ab) return aa > ab;
     if (ta != tb) return ta > tb;
     return ia < ib;
@@ -192,307 +614,197 @@ __device__ inline bool sel_less(int which, double ta, int ia, double tb, int ib)
   return ia < ib;
 }
 
-// LDL^T inertia of T - x I: the number of eigenvalues of the tridiagonal (dg, e2 = e^2)
-// below x (Sturm count); tiny pivots are replaced by -pivmin.
-__device__ inline int sturm_count(const double* dg, const double* e2, int n, double x, double pivmin) {
-  double q = dg[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int c = q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    q = (dg[i] - x) - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    c += q < 0.0;
-  }
-  return c;
-}
-
-__device__ inline double hash_unit(uint32_t a, uint32_t b) {
+__device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
   uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
   h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
   return ((double)(h & 0xFFFFFF) / 16777216.0) - 0.5;
 }
 
-template <bool IN_LDS>
-__global__ void __launch_bounds__(EB) k_small_eig(int d_full, int base, const int32_t* rank_p,
-                                                  const double* H, int which, int kk, double drop_tol,
-                                                  double* theta_out, double* F, int32_t* kept_out,
-                                                  double* work, int32_t* status) {
-  __shared__ double sA[IN_LDS ? SMALL_LDS_D * (SMALL_LDS_D + 1) : 1];
-  __shared__ double dg[MAXD], od[MAXD], e2[MAXD], vv[MAXD], pw[MAXD], hb[MAXD], ev[MAXD];
-  __shared__ double red[EB / GREST_WAVE];
-  __shared__ int sel[MAXD], slot_of[MAXD], srt[MAXD];
-  __shared__ double sh_d[4];
-  __shared__ int sh_i[2];
-  const int tid = threadIdx.x;
-  int n = base + (rank_p ? rank_p[0] : 0);
-  if (n > d_full) n = d_full;
-  if (n < 0) n = 0;
-  double* A = IN_LDS ? sA : work;
-  double* scratch = IN_LDS ? work : work + (size_t)(d_full + 1) * (d_full + 1);
-  const int lda = n + 1;
-
-  int bad = 0;
-  for (int idx = tid; idx < n * n; idx += EB) {
-    int i = idx / n, j = idx % n;
-    double h = 0.5 * (H[(size_t)i * d_full + j] + H[(size_t)j * d_full + i]);
-    if (!isfinite(h)) { bad = 1; h = 0.0; }
-    A[i * lda + j] = h;
-  }
-  if (bad) atomicOr(status, ST_NONFINITE);
-  __syncthreads();
-
-  PHASE_MARK(0);
-  // ---- Householder tridiagonalisation; reflector k stored below the subdiagonal ----
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += EB) {
-      double x = A[(k + 1 + i) * lda + k];
-      part += x * x;
-    }
-    const double sigma = block_sum(part, red);
-    const double x0 = A[(k + 1) * lda + k];
-    double beta = 0.0, v0 = 1.0, ek = x0;
-    if (sigma > 0.0) {
-      const double mu = sqrt(x0 * x0 + sigma);
-      v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma / (x0 + mu));
-      beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
-      ek = mu;
-    }
-    for (int i = tid; i < m; i += EB) vv[i] = (i == 0) ? 1.0 : A[(k + 1 + i) * lda + k] / v0;
-    if (tid == 0) { dg[k] = A[k * lda + k]; od[k] = ek; hb[k] = beta; }
-    __syncthreads();
-    if (beta != 0.0) {
-      for (int i = tid; i < m; i += EB) {
-        const double* row = A + (k + 1 + i) * lda + (k + 1);
-        double acc = 0.0;
-        for (int j = 0; j < m; ++j) acc += row[j] * vv[j];
-        pw[i] = beta * acc;
-      }
-      __syncthreads();
-      double pv = 0.0;
-      for (int i = tid; i < m; i += EB) pv += pw[i] * vv[i];
-      const double K = 0.5 * beta * block_sum(pv, red);
-      for (int i = tid; i < m; i += EB) pw[i] -= K * vv[i];
-      __syncthreads();
-      for (int idx = tid; idx < m * m; idx += EB) {
-        int i = idx / m, j = idx % m;
-        A[(k + 1 + i) * lda + (k + 1 + j)] -= vv[i] * pw[j] + pw[i] * vv[j];
-      }
-    }
-    for (int i = 1 + tid; i < m; i += EB) A[(k + 1 + i) * lda + k] = vv[i];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (n >= 2) {
-      dg[n - 2] = A[(n - 2) * lda + (n - 2)];
-      od[n - 2] = A[(n - 1) * lda + (n - 2)];
-      hb[n - 2] = 0.0;
-    }
-    if (n >= 1) dg[n - 1] = A[(n - 1) * lda + (n - 1)];
-    // Gershgorin interval, norm, pivot floor
-    double lo = 0.0, hi = 0.0, tn = 0.0, emax = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < n ? fabs(od[i]) : 0.0);
-      lo = (i == 0) ? dg[i] - r : fmin(lo, dg[i] - r);
-      hi = (i == 0) ? dg[i] + r : fmax(hi, dg[i] + r);
-      tn = fmax(tn, fabs(dg[i]) + r);
-      if (i + 1 < n) { e2[i] = od[i] * od[i]; emax = fmax(emax, e2[i]); }
-    }
-    const double pad = 4.0 * 2.220446049250313e-16 * fmax(tn, 1e-300) + 1e-300;
-    sh_d[0] = lo - pad;
-    sh_d[1] = hi + pad;
-    sh_d[2] = tn;
-    sh_d[3] = 1e-290 * fmax(1.0, emax);
+__global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, int kk, double drop_tol,
+                                                       double* work, double* theta_out, double* F,
+                                                       int32_t* kept_out, int32_t* status) {
+  __shared__ double sev[MAXN], sdg[MAXN], sod[MAXN];
+  __shared__ double u0i[MAXN], u1[MAXN], u2[MAXN], lm[MAXN], yv[MAXN];
+  __shared__ unsigned char pv[MAXN];
+  __shared__ int ssel[MAXN], sslot[MAXN], mslot[MAXN];
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  const int n = (int)work[W_HDR];
+  const double tnorm = work[W_HDR + 3];
+  double* Yb = work + W_Y;
+  for (int i = lane; i < MAXN; i += GREST_WAVE) ssel[i] = 0;
+  for (int i = lane; i < n; i += GREST_WAVE) {
+    sev[i] = work[W_EV + i];
+    sdg[i] = work[W_DG + i];
+    sod[i] = work[W_OD + i];
   }
   __syncthreads();
-
-  PHASE_MARK(1);
-  // ---- eigenvalues: one lane per index, bisection on the inertia count ----
-  const double eps = 2.220446049250313e-16;
-  const double pivmin = sh_d[3];
-  const double tnorm = sh_d[2];
-  for (int t = tid; t < n; t += EB) {
-    double lo = sh_d[0], hi = sh_d[1];
-    for (int it = 0; it < 80; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-      if (sturm_count(dg, e2, n, mid, pivmin) > t) hi = mid; else lo = mid;
-    }
-    ev[t] = 0.5 * (lo + hi);
+  // rank of every eigenvalue in output order
+  for (int i = lane; i < n; i += GREST_WAVE) {
+    int rk = 0;
+    const double ti = sev[i];
+    for (int j = 0; j < n; ++j) rk += (j != i) && sel_less(which, sev[j], j, ti, i);
+    sslot[i] = rk < kk ? rk : -1;
+    if (rk < kk) ssel[rk] = i;
   }
-  for (int i = tid; i < MAXD; i += EB) { slot_of[i] = -1; }
-  __syncthreads();
-
-  PHASE_MARK(2);
-  // ---- selection of kk pairs (ev is ascending) ----
-  double tmax = 0.0;
-  for (int i = 0; i < n; ++i) tmax = fmax(tmax, ev[i]);
-  const double keep_thr = drop_tol > 0.0 ? drop_tol * drop_tol * fmax(1.0, tmax) : -INFINITY;
-  for (int i = tid; i < n; i += EB) {
-    int rank = 0;
-    for (int j = 0; j < n; ++j)
-      if (j != i && sel_less(which, ev[j], j, ev[i], i)) ++rank;
-    if (rank < kk) { sel[rank] = i; slot_of[i] = rank; }
-  }
+  double tmax = -INFINITY;
+  for (int i = lane; i < n; i += GREST_WAVE) tmax = fmax(tmax, sev[i]);
+  tmax = wave_max_d(tmax);
   __syncthreads();
   const int nsel = kk < n ? kk : n;
-  if (tid == 0) {  // selected indices in ascending order
+  const double keep_thr = drop_tol > 0.0 ? drop_tol * drop_tol * fmax(1.0, tmax) : -INFINITY;
+  // a selected index is kept unless its value falls below the drop threshold
+  auto kept_idx = [&](int i) { return sslot[i] >= 0 && !(sev[i] <= keep_thr); };
+  if (slot == 0 && lane == 0 && kept_out) {
     int c = 0;
-    for (int i = 0; i < n; ++i)
-      if (slot_of[i] >= 0) srt[c++] = i;
+    for (int s = 0; s < nsel; ++s) c += kept_idx(ssel[s]);
+    *kept_out = c;
   }
-  __syncthreads();
+  auto zero_column = [&](int s) {
+    for (int r = lane; r < d_full; r += GREST_WAVE) F[(size_t)r * kk + s] = 0.0;
+    if (lane == 0) { theta_out[s] = 0.0; work[W_FL + s] = 0.0; }
+  };
+  if (slot >= nsel) { zero_column(slot); return; }
+  const int idx = ssel[slot];
+  if (!kept_idx(idx)) { zero_column(slot); return; }
+  if (lane == 0) work[W_FL + slot] = 1.0;
+  // cluster: consecutive kept selected indices (ascending eigenvalue order) whose gaps are
+  // at most ortol; the lowest member computes the whole cluster
+  const double ortol = 1e-7 * tnorm;
+  int prev = -1;
+  for (int j = idx - 1; j >= 0; --j)
+    if (kept_idx(j)) { prev = j; break; }
+  if (prev >= 0 && sev[idx] - sev[prev] <= ortol) return;
 
-  PHASE_MARK(3);
-  // ---- eigenvectors of T by inverse iteration; a cluster (gaps below 1e-3 ||T||) is
-  //      handled by one lane with distinct shifts and reorthogonalisation ----
-  const double ortol = 1e-3 * tnorm;
-  // The reflectors move to global memory so that the LDS matrix becomes the scratch of
-  // the inverse iterations (six vectors of length n per cluster leader).
-  double* refl = work;
-  if (IN_LDS) {
-    for (int idx = tid; idx < n * lda; idx += EB) refl[idx] = A[idx];
-  }
-  __syncthreads();
-  const int per = 6 * (n > 0 ? n : 1);
-  const int cap = IN_LDS ? (SMALL_LDS_D * (SMALL_LDS_D + 1)) / per : EB;
-  int lrank = 0;  // rank of this lane's leader among the leaders
-  bool leader = false;
-  const int q = tid;
-  if (q < nsel) {
-    leader = !(q > 0 && ev[srt[q]] - ev[srt[q - 1]] <= ortol);
-    for (int qq = 1; qq < q; ++qq) lrank += !(ev[srt[qq]] - ev[srt[qq - 1]] <= ortol);
-    if (q > 0) lrank += 1;  // q == 0 is always a leader
-  }
-  const int nlead_max = nsel;  // upper bound on leaders, for the round count
-  for (int round = 0; round * cap < nlead_max; ++round) {
-   if (leader && lrank / cap == round) {
-    const int slot_l = lrank % cap;
-    double* u0 = IN_LDS ? sA + (size_t)slot_l * per : scratch + (size_t)q * 6 * MAXD;
-    const int st = IN_LDS ? n : MAXD;
-    double* u1 = u0 + st;
-    double* u2 = u1 + st;
-    double* lm = u2 + st;
-    double* x = lm + st;
-    double* piv = x + st;
-    double shift_prev = -INFINITY;
-    for (int p = q; p < nsel && (p == q || ev[srt[p]] - ev[srt[p - 1]] <= ortol); ++p) {
-      const int idx = srt[p];
-      const int slot = slot_of[idx];
-      double lam = ev[idx];
-      if (p > q) lam = fmax(lam, shift_prev + 10.0 * eps * fmax(tnorm, 1e-300));
-      shift_prev = lam;
-      // LU with partial pivoting of T - lam I (three upper diagonals)
-      double a = dg[0] - lam, bsup = n > 1 ? od[0] : 0.0;
+  const double tiny = fmax(EPS * tnorm, 1e-290);
+  const double y_eps = 10.0 * EPS * fmax(tnorm, 1e-300);
+  double shift_prev = -INFINITY;
+  int nmem = 0;
+  int cur = idx;
+  while (cur >= 0) {
+    const int cslot = sslot[cur];
+    double lam = sev[cur];
+    if (nmem > 0) lam = fmax(lam, shift_prev + y_eps);
+    shift_prev = lam;
+    // LU with partial pivoting of T - lam I (U has three diagonals; 1/U_ii is stored),
+    // pivots below tiny are raised to tiny
+    if (lane == 0) {
+      double a = sdg[0] - lam, bsup = n > 1 ? sod[0] : 0.0;
       for (int i = 0; i + 1 < n; ++i) {
-        const double c = od[i];                    // (i+1, i)
-        const double an = dg[i + 1] - lam;         // (i+1, i+1)
-        const double bn = i + 2 < n ? od[i + 1] : 0.0;  // (i+1, i+2)
+        const double c = sod[i];
+        const double an = sdg[i + 1] - lam;
+        const double bn = i + 2 < n ? sod[i + 1] : 0.0;
         if (fabs(a) >= fabs(c)) {
-          const double piv_a = (a == 0.0) ? pivmin : a;
-          const double l = c / piv_a;
-          u0[i] = piv_a; u1[i] = bsup; u2[i] = 0.0; lm[i] = l; piv[i] = 0.0;
-          a = an - l * bsup;
+          const double pa = fabs(a) < tiny ? (a < 0.0 ? -tiny : tiny) : a;
+          const double ia = recip(pa);
+          const double l = c * ia;
+          u0i[i] = ia; u1[i] = bsup; u2[i] = 0.0; lm[i] = l; pv[i] = 0;
+          a = fma(-l, bsup, an);
           bsup = bn;
         } else {
-          const double l = a / c;
-          u0[i] = c; u1[i] = an; u2[i] = bn; lm[i] = l; piv[i] = 1.0;
-          a = bsup - l * an;
+          const double ic = recip(c);
+          const double l = a * ic;
+          u0i[i] = ic; u1[i] = an; u2[i] = bn; lm[i] = l; pv[i] = 1;
+          a = fma(-l, an, bsup);
           bsup = -l * bn;
         }
       }
-      u0[n - 1] = (a == 0.0) ? pivmin : a;
-      for (int i = 0; i < n; ++i) x[i] = hash_unit(i, slot + 1);
-      for (int it = 0; it < 2; ++it) {
+      const double pa = fabs(a) < tiny ? (a < 0.0 ? -tiny : tiny) : a;
+      u0i[n - 1] = recip(pa);
+    }
+    for (int i = lane; i < n; i += GREST_WAVE) yv[i] = hash_unit(i, cslot + 1);
+    __syncthreads();
+    for (int it = 0; it < 2; ++it) {
+      if (lane == 0) {
+        double x = yv[0];
         for (int i = 0; i + 1 < n; ++i) {  // L^{-1} with the row interchanges
-          if (piv[i] != 0.0) { const double t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
-          x[i + 1] -= lm[i] * x[i];
+          double xn = yv[i + 1];
+          if (pv[i]) { const double t = x; x = xn; xn = t; }
+          yv[i] = x;
+          x = fma(-lm[i], x, xn);
         }
-        for (int i = n - 1; i >= 0; --i) {  // U^{-1}
-          double v = x[i];
-          if (i + 1 < n) v -= u1[i] * x[i + 1];
-          if (i + 2 < n) v -= u2[i] * x[i + 2];
-          x[i] = v / u0[i];
+        yv[n - 1] = x;
+        double x1 = 0.0, x2 = 0.0;  // U^{-1}
+        for (int i = n - 1; i >= 0; --i) {
+          const double v = fma(-u2[i], x2, fma(-u1[i], x1, yv[i])) * u0i[i];
+          yv[i] = v;
+          x2 = x1;
+          x1 = v;
         }
-        for (int pp = q; pp < p; ++pp) {  // against the finished members of the cluster
-          const int sl = slot_of[srt[pp]];
-          double dot = 0.0;
-          for (int i = 0; i < n; ++i) dot += x[i] * F[(size_t)i * kk + sl];
-          for (int i = 0; i < n; ++i) x[i] -= dot * F[(size_t)i * kk + sl];
-        }
-        double nrm = 0.0;
-        for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
-        nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-        for (int i = 0; i < n; ++i) x[i] *= nrm;
       }
-      for (int i = 0; i < n; ++i) F[(size_t)i * kk + slot] = x[i];
+      __syncthreads();
+      double y0 = lane < n ? yv[lane] : 0.0;
+      double y1 = lane + GREST_WAVE < n ? yv[lane + GREST_WAVE] : 0.0;
+      // classical Gram-Schmidt, twice, against the finished members of the cluster
+      for (int pass = 0; pass < (nmem > 0 ? 2 : 0); ++pass) {
+        for (int q = 0; q < nmem; ++q) {
+          const double* yq = Yb + (size_t)mslot[q] * MAXN;
+          const double d = wave_sum_d(y0 * yq[lane] + y1 * yq[lane + GREST_WAVE]);
+          y0 = fma(-d, yq[lane], y0);
+          y1 = fma(-d, yq[lane + GREST_WAVE], y1);
+        }
+      }
+      const double nrm2 = wave_sum_d(y0 * y0 + y1 * y1);
+      double s = (nrm2 > 0.0 && isfinite(nrm2)) ? 1.0 / sqrt(nrm2) : 0.0;
+      if (s == 0.0) {  // breakdown: fall back to the unit vector of the index
+        if (lane == 0) atomicOr(status, ST_NOT_CONVERGED);
+        y0 = (lane == cur) ? 1.0 : 0.0;
+        y1 = (lane + GREST_WAVE == cur) ? 1.0 : 0.0;
+        s = 1.0;
+      }
+      y0 *= s;
+      y1 *= s;
+      if (lane < n) yv[lane] = y0;
+      if (lane + GREST_WAVE < n) yv[lane + GREST_WAVE] = y1;
+      __syncthreads();
     }
-   }
-   __syncthreads();
+    double y0 = lane < n ? yv[lane] : 0.0;
+    double y1 = lane + GREST_WAVE < n ? yv[lane + GREST_WAVE] : 0.0;
+    // next member of the cluster, if any
+    int nxt = -1;
+    for (int j = cur + 1; j < n; ++j)
+      if (kept_idx(j)) { nxt = j; break; }
+    if (nxt >= 0 && !(sev[nxt] - sev[cur] <= ortol)) nxt = -1;
+    // the tridiagonal-basis vector, for the later members and for the last launch
+    double* yq = Yb + (size_t)cslot * MAXN;
+    yq[lane] = y0;
+    yq[lane + GREST_WAVE] = y1;
+    if (lane == 0) { mslot[nmem] = cslot; theta_out[cslot] = sev[cur]; }
+    __threadfence_block();
+    ++nmem;
+    cur = nxt;
+    __syncthreads();
   }
+}
 
-  PHASE_MARK(4);
-  // ---- back-transform x <- P_0 ... P_{n-3} x; eight lanes per vector, rows interleaved ----
-  constexpr int G = 8, RMAX = MAXD / G;
-  const int grp = tid / G, gl = tid % G;
-  for (int s0 = 0; s0 < nsel; s0 += EB / G) {
-    const int slot = s0 + grp;
-    const bool act = slot < nsel;
-    double xr[RMAX];
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) {
-      const int r = gl + G * c;
-      xr[c] = (act && r < n) ? F[(size_t)r * kk + slot] : 0.0;
-    }
-    for (int k = n - 3; k >= 0; --k) {
-      const double beta = hb[k];
-      if (beta == 0.0) continue;
-      double dot = 0.0;
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        const int r = gl + G * c;
-        if (r >= k + 1 && r < n) dot += (r == k + 1 ? 1.0 : refl[r * lda + k]) * xr[c];
-      }
-#pragma unroll
-      for (int o = 1; o < G; o <<= 1) dot += __shfl_xor(dot, o, G);
-      dot *= beta;
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        const int r = gl + G * c;
-        if (r >= k + 1 && r < n) xr[c] -= dot * (r == k + 1 ? 1.0 : refl[r * lda + k]);
-      }
-    }
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        const int r = gl + G * c;
-        if (r < d_full) F[(size_t)r * kk + slot] = (r < n) ? xr[c] : 0.0;
-      }
-    }
+__global__ void __launch_bounds__(GREST_WAVE) k_backtr(int d_full, int kk, const double* work, double* F) {
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  if (work[W_FL + slot] == 0.0) return;
+  const int n = (int)work[W_HDR];
+  const double* R = work + W_R;
+  const double* hb = work + W_HB;
+  const double* Yb = work + W_Y;
+  const double ys0 = Yb[(size_t)slot * MAXN + lane], ys1 = Yb[(size_t)slot * MAXN + lane + GREST_WAVE];
+  double c0 = 0.0, c1 = 0.0;
+  for (int t = 0; t < kk; ++t) {
+    if (t == slot || work[W_FL + t] == 0.0) continue;
+    const double yt0 = Yb[(size_t)t * MAXN + lane], yt1 = Yb[(size_t)t * MAXN + lane + GREST_WAVE];
+    const double e = wave_sum_d(fma(yt0, ys0, yt1 * ys1));
+    c0 = fma(e, yt0, c0);
+    c1 = fma(e, yt1, c1);
   }
-  __syncthreads();
-
-  PHASE_MARK(5);
-  // ---- values, dropped columns, kept count ----
-  if (tid == 0) sh_i[0] = 0;
-  __syncthreads();
-  for (int slot = tid; slot < kk; slot += EB) {
-    if (slot < nsel) {
-      const double ti = ev[sel[slot]];
-      const bool keep = !(drop_tol > 0.0) || ti > keep_thr;
-      theta_out[slot] = keep ? ti : 0.0;
-      if (keep) atomicAdd(&sh_i[0], 1);
-      else for (int r = 0; r < d_full; ++r) F[(size_t)r * kk + slot] = 0.0;
-    } else {
-      theta_out[slot] = 0.0;
-      for (int r = 0; r < d_full; ++r) F[(size_t)r * kk + slot] = 0.0;
-    }
+  double y0 = fma(-0.5, c0, ys0), y1 = fma(-0.5, c1, ys1);
+  // back-transform y <- P_0 ... P_{n-3} y
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = hb[k];
+    const double r0 = R[(size_t)k * MAXN + lane], r1 = R[(size_t)k * MAXN + lane + GREST_WAVE];
+    const double d = beta * wave_sum_d(fma(r0, y0, r1 * y1));
+    y0 = fma(-d, r0, y0);
+    y1 = fma(-d, r1, y1);
   }
-  __syncthreads();
-  if (tid == 0 && kept_out) *kept_out = sh_i[0];
-  PHASE_MARK(6);
+  for (int r = lane; r < d_full; r += GREST_WAVE) {
+    const double v = r < GREST_WAVE ? y0 : y1;
+    F[(size_t)r * kk + slot] = r < n ? v : 0.0;
+  }
 }
 
 __global__ void k_symmetrize(int d, double* H) {
@@ -508,33 +820,27 @@ __global__ void k_symmetrize(int d, double* H) {
 
 }  // namespace
 
-int64_t eig_work_elems(int d) { return (int64_t)(d + 1) * (d + 1) + (int64_t)6 * MAXD * MAXD; }
+int64_t eig_work_elems(int d) { return d <= MAXN ? (int64_t)W_END : 0; }
 
-int64_t pchol_work_elems(int m, int kc) { return (int64_t)(m + 1) * (m + 1) + (int64_t)kc * m; }
+int64_t pchol_work_elems(int, int) { return 0; }
 
 void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
-                  int32_t* status, double* work, hipStream_t s) {
-  const size_t lds = (size_t)pchol_work_elems(m, C ? kc : 0) * sizeof(double);
+                  int32_t* status, double*, hipStream_t s) {
   if (!C) kc = 0;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_pchol<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    attr = true;
-  }
-  if (lds <= 150 * 1024) k_pchol<true><<<1, EB, lds, s>>>(m, G, C, kc, tol, Mout, rank, status, nullptr);
-  else k_pchol<false><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status, work);
+  if (m <= 64) k_pchol<64><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
+  else k_pchol<128><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
 }
 
-void launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which, int kk,
+bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which, int kk,
                       double drop_tol, double* theta, double* F, int32_t* kept, double* work,
                       int32_t* status, hipStream_t s) {
-  if (d_full <= SMALL_LDS_D) {
-    k_small_eig<true><<<1, EB, 0, s>>>(d_full, base, rank, H, which, kk, drop_tol, theta, F, kept,
-                                       work, status);
-  } else {
-    k_small_eig<false><<<1, EB, 0, s>>>(d_full, base, rank, H, which, kk, drop_tol, theta, F, kept,
-                                        work, status);
-  }
+  if (d_full < 1 || d_full > MAXN || kk < 1 || kk > MAXN) return false;
+  if (d_full <= 64) k_tridiag<64><<<1, EB, 0, s>>>(d_full, base, rank, H, work, status);
+  else k_tridiag<128><<<1, EB, 0, s>>>(d_full, base, rank, H, work, status);
+  k_bisect<<<d_full, GREST_WAVE, 0, s>>>(work);
+  k_eigvec<<<kk, GREST_WAVE, 0, s>>>(d_full, which, kk, drop_tol, work, theta, F, kept, status);
+  k_backtr<<<kk, GREST_WAVE, 0, s>>>(d_full, kk, work, F);
+  return true;
 }
 
 void launch_symmetrize(int d, double* H, hipStream_t s) {

@@ -139,10 +139,11 @@ class State:
         self.k = k
         self.op = op
         self.precision = precision
+        self._lib = lib()  # kept for the destructor, which may run during interpreter exit
 
     def close(self):
-        if self._h:
-            lib().grest_destroy(self._h)
+        if getattr(self, "_h", None):
+            self._lib.grest_destroy(self._h)
             self._h = C.c_void_p()
 
     __del__ = close
