@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink node counts (quick runs only)")
     ap.add_argument("--init-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a reference kernel of "
+                         "known traffic for hardware byte counters)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -75,6 +78,15 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(args, f"reference copy: {args.calib_copy_mib} MiB read and {args.calib_copy_mib} MiB written")
+        del src, dst
     n_steps = max(10, args.steps, args.warmup)
     t0 = time.time()
     wl = W.preset("sbm_n1e6", scale=args.scale, steps=n_steps)
@@ -166,7 +178,9 @@ def main():
         "dominant_stage": dominant,
         "roofline": {"kernel": "spmm (product with the updated operator)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "traffic_unit": "GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+                     "algorithmic_gb_per_launch": round(main_res["spmm_bytes"] / max(1, len(main_res["sizes"])) / 1e9, 4),
                      "avg_launch_ms": round(spmm_avg_ms, 4)},
     }
     if cmp_res is not None:
@@ -194,15 +208,40 @@ def cpu_baseline(wl, args):
     except Exception:
         cores = os.cpu_count()
     A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
-    X0 = W.random_orthonormal(wl.n0, K, 0)
-    d = wl.deltas[0]
-    om = W.omega(wl.cfg_id, 0, 1, d.n_new, L + P)
-    log(args, "timing the CPU oracle on one update")
+    X = W.random_orthonormal(wl.n0, K, 0)
+    theta = np.zeros(K)
+    steps = 2
+    log(args, f"timing the CPU oracle on {steps} updates")
     t = time.perf_counter()
-    O.grest_step(A, X0, np.zeros(K), d.n_new, d.i, d.j, d.sign, K, variant=O.RSVD, L=L, Omega=om)
+    for s in range(steps):
+        d = wl.deltas[s]
+        om = W.omega(wl.cfg_id, 0, s + 1, d.n_new, L + P)
+        r = O.grest_step(A, X, theta, d.n_new, d.i, d.j, d.sign, K, variant=O.RSVD, L=L, Omega=om)
+        A, X, theta = r.A, r.X, r.theta
     dt = time.perf_counter() - t
-    return {"value": round(1.0 / dt, 5), "unit": "updates/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"one update (step 1) of the same workload, n0={wl.n0}, FP64 NumPy/SciPy, {dt:.1f} s"}
+    return {"value": round(steps / dt, 5), "unit": "updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"the first {steps} updates of the same workload from a random orthonormal start, "
+                      f"n0={wl.n0}, FP64 NumPy/SciPy, {dt:.1f} s"}
+
+
+def measured_traffic():
+    """HBM bytes per launch of the product kernel at this workload, from the committed
+    byte-counter summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "spmm_traffic_sbm_n1e6_k32.txt")
+    src = os.path.join(ROOT, "paper_2603_19439_amd", "csrc", "spmm.hip")
+    try:
+        rec = {}
+        for line in open(path):
+            if "=" in line and not line.startswith(" "):
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.split()[0]
+        cur = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+        if rec.get("kernel_source_sha1") != cur:
+            return None
+        return float(rec["traffic_gb_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 if __name__ == "__main__":

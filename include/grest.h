@@ -47,7 +47,8 @@ typedef enum grest_status {
   GREST_ENOMEM = 2,   /* device or host allocation failed */
   GREST_EDEVICE = 3,  /* HIP runtime error (see grest_last_error) */
   GREST_ENUMERIC = 4, /* non-finite value or eigensolver without convergence */
-  GREST_ENODEV = 5    /* no usable device */
+  GREST_ENODEV = 5,   /* no usable device */
+  GREST_EAGAIN = 6    /* server queue full or device-memory budget exceeded; retry later */
 } grest_status;
 
 /* operator whose pairs are tracked (Sec. 4.2) */
@@ -168,6 +169,67 @@ grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stag
 
 /* Release the state and all its device memory. */
 void grest_destroy(grest_state* st);
+
+/* Rebinds the state to another HIP stream (NULL: a stream of its own).  Waits for the
+ * work already queued on the old stream first.  EINVAL on a NULL state. */
+grest_status grest_set_stream(grest_state* st, void* stream);
+
+/* Device memory held by the state, in bytes (its current capacities). */
+grest_status grest_memory(const grest_state* st, int64_t* device_bytes);
+
+/* ------------------------------------------------------------------------------------
+ * Batched execution of many graphs (serving).  This is not part of the method: it runs
+ * the single-graph update of Alg. 2 for many independent graphs on one device.
+ *
+ * A server owns `lanes` worker lanes, each a host thread with its own HIP stream.  A
+ * state attached to the server is pinned to one lane (graph ids are assigned in attach
+ * order, lane = id mod lanes) and driven only by that lane until the server is
+ * destroyed, so the updates of one graph run in submission order and one at a time;
+ * lanes overlap on the device.  Every update of a graph runs the same kernels with the
+ * same reduction orders whatever else is queued, so its result does not depend on the
+ * mix of graphs.
+ *
+ * Admission: attach fails with GREST_EAGAIN when the device memory of the attached
+ * states would exceed hbm_budget_bytes (0: no limit); submit fails with GREST_EAGAIN
+ * when `max_queue` requests are pending.
+ * Time stamps are nanoseconds of the monotonic clock that grest_now_ns reads.
+ * While attached, a state must not be used directly (no update, get or sync) except
+ * after grest_server_drain has returned; the server restores the state's original
+ * stream when it is destroyed.  Requests for one graph are submitted from one host
+ * thread (their order is the submission order).
+ * ------------------------------------------------------------------------------------ */
+typedef struct grest_server grest_server;
+
+int64_t grest_now_ns(void);
+
+/* lanes in [1, 64]; max_queue >= 1. */
+grest_status grest_server_create(int64_t hbm_budget_bytes, int32_t lanes, int32_t max_queue,
+                                 grest_server** out);
+
+/* Attaches a state that already holds its pairs; *graph_id receives its id. */
+grest_status grest_server_attach(grest_server* sv, grest_state* st, int32_t* graph_id);
+
+/* Queues one update of graph `graph_id` (host arrays, copied before return; arguments as
+ * for grest_update with where = GREST_HOST).  The change list's format is checked here
+ * against the node count the graph will have once its queued requests have run
+ * (EINVAL, nothing queued); checks that need the graph itself (an insertion of an
+ * existing edge, a deletion of a missing one) surface in the request's completion
+ * status, with that graph left unchanged.  `tag` is returned by grest_poll. */
+grest_status grest_submit(grest_server* sv, int32_t graph_id, int64_t n_new, int64_t n_changes, const int32_t* ei,
+                          const int32_t* ej, const int8_t* sign, const double* omega, uint64_t tag);
+
+/* Copies up to `max` finished requests in completion order and removes them from the
+ * server: tag, final status, submission and completion times.  Returns the count
+ * (never blocks). */
+int32_t grest_poll(grest_server* sv, int32_t max, uint64_t* tags, int32_t* status, int64_t* t_submit_ns,
+                   int64_t* t_done_ns);
+
+/* Blocks until every queued request has finished (they stay available to grest_poll). */
+grest_status grest_server_drain(grest_server* sv);
+
+/* Drains, stops the lanes, restores every attached state's stream.  The states stay
+ * owned by the caller. */
+void grest_server_destroy(grest_server* sv);
 
 #ifdef __cplusplus
 }

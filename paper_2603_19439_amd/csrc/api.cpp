@@ -202,6 +202,24 @@ grest_status alloc_sketch_arrays(grest_state* st, int64_t cap_s) {
   return GREST_OK;
 }
 
+// device bytes of every buffer of the state (the same list free_all releases)
+int64_t device_bytes(const grest_state* st) {
+  int64_t total = 0;
+  auto add = [&](const void* p) {
+    size_t sz = 0;
+    if (p && hipMemPtrGetInfo(const_cast<void*>(p), &sz) == hipSuccess) total += (int64_t)sz;
+  };
+  for (int b = 0; b < 2; ++b) { add(st->rp[b]); add(st->col[b]); add(st->sc[b]); add(st->z[b]); }
+  add(st->aux); add(st->ybuf); add(st->bt); add(st->omega_t); add(st->omega64);
+  add(st->d_ei); add(st->d_ej); add(st->d_sg);
+  add(st->dcnt); add(st->dptr); add(st->dfill); add(st->newlen); add(st->scan_tmp);
+  add(st->dcol_tmp); add(st->dcol); add(st->dins); add(st->dsg_tmp); add(st->dsg);
+  add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F);
+  add(st->theta); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
+  add(st->ranks); add(st->status); add(st->maxdeg);
+  return total;
+}
+
 void free_all(grest_state* st) {
   for (int b = 0; b < 2; ++b) {
     dfree(st->rp[b]); dfree(st->col[b]); dfree(st->sc[b]); dfree(st->z[b]);
@@ -600,6 +618,9 @@ grest_status get_impl(grest_state* st, double* values, void* X, int32_t x_dtype,
 
 }  // namespace
 
+void* state_user_stream(const grest_state* st) { return st->own_stream ? nullptr : (void*)st->stream; }
+int64_t state_sketch_cols(const grest_state* st) { return st->variant == GREST_RSVD ? st->Ls : 0; }
+
 // =====================================================================================
 // C interface
 // =====================================================================================
@@ -615,6 +636,7 @@ const char* grest_strerror(grest_status status) {
     case GREST_EDEVICE: return "device error";
     case GREST_ENUMERIC: return "numerical failure";
     case GREST_ENODEV: return "no usable device";
+    case GREST_EAGAIN: return "queue full or memory budget exceeded";
   }
   return "unknown status";
 }
@@ -786,6 +808,28 @@ grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col) {
   HIPCHK(hipStreamSynchronize(st->stream));
   if (rowptr) HIPCHK(hipMemcpy(rowptr, st->rp[st->gcur], (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
   if (col && st->m > 0) HIPCHK(hipMemcpy(col, st->col[st->gcur], st->m * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return GREST_OK;
+}
+
+grest_status grest_set_stream(grest_state* st, void* stream) {
+  if (!st) return GREST_EINVAL;
+  HIPCHK(hipStreamSynchronize(st->stream));
+  if (stream) {
+    if (st->own_stream) (void)hipStreamDestroy(st->stream);
+    st->own_stream = false;
+    st->stream = (hipStream_t)stream;
+  } else if (!st->own_stream) {
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    st->stream = s;
+    st->own_stream = true;
+  }
+  return GREST_OK;
+}
+
+grest_status grest_memory(const grest_state* st, int64_t* bytes) {
+  if (!st || !bytes) return GREST_EINVAL;
+  *bytes = device_bytes(st);
   return GREST_OK;
 }
 

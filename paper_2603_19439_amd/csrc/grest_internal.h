@@ -135,3 +135,12 @@ void launch_fill_random(T* p, int64_t ld, int64_t rows, int w, uint64_t seed, hi
 template <typename T>
 void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy,
                   hipStream_t s);
+
+// ------------------------------------------------------------------------------------
+// api.cpp: state accessors used by the server
+// ------------------------------------------------------------------------------------
+struct grest_state;
+// the caller's stream the state is bound to, or null when the state uses its own
+void* state_user_stream(const grest_state* st);
+// columns of the Gaussian test matrix an update needs (L + P for RSVD, else 0)
+int64_t state_sketch_cols(const grest_state* st);

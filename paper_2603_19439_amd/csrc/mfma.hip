@@ -461,11 +461,13 @@ template <typename Tin, typename Tc, bool SYM, int PA, int PB>
 void tnw_launch(dim3 grid, hipStream_t s, int64_t n, int64_t rpc, const Tin* A, int64_t lda, int a, const Tin* B,
                 int64_t ldb, int b, double* partial) {
   const size_t lds = (size_t)PA * PB * 256 * sizeof(double);
-  static bool attr = false;
-  if (!attr && lds > 65536) {
-    (void)hipFuncSetAttribute((const void*)k_tnw<Tin, Tc, SYM, PA, PB>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr = true;
+  if (lds > 65536) {  // once per instance; function-local statics initialise thread-safely
+    static const bool attr = [lds] {
+      (void)hipFuncSetAttribute((const void*)k_tnw<Tin, Tc, SYM, PA, PB>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      return true;
+    }();
+    (void)attr;
   }
   k_tnw<Tin, Tc, SYM, PA, PB><<<grid, WG, lds, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
 }
@@ -528,11 +530,13 @@ static void pip_launch(int g, int64_t n, int64_t rpc, const T* X, int64_t ldx, i
                        int w, double* partC, double* partG, hipStream_t s) {
   constexpr int NTG = TWC * (TWC + 1) / 2;
   const size_t lds = (size_t)(TXC * TWC + NTG) * 256 * sizeof(double);
-  static bool attr = false;
-  if (!attr && lds > 65536) {
-    (void)hipFuncSetAttribute((const void*)k_pip<T, Tcx, TXC, TWC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    attr = true;
+  if (lds > 65536) {
+    static const bool attr = [lds] {
+      (void)hipFuncSetAttribute((const void*)k_pip<T, Tcx, TXC, TWC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      return true;
+    }();
+    (void)attr;
   }
   k_pip<T, Tcx, TXC, TWC><<<g, WG, lds, s>>>(n, rpc, X, ldx, kx, W, ldw, w, partC, partG);
 }
@@ -579,12 +583,12 @@ static void apply_launch(int64_t n, const T* In1, int64_t ld1, int a1, const T* 
                          const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s) {
   const int KB = (a1 + a2 + 15) >> 4, TB = (b + 15) >> 4;
   const size_t lds = (size_t)KB * 16 * (TB * 16 + 1) * sizeof(Tc);
-  static bool attr = false;
-  if (!attr) {
+  static const bool attr = [] {
     (void)hipFuncSetAttribute((const void*)k_apply<T, Tc, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)((size_t)TW * (TW + 1) * sizeof(Tc)));
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   k_apply<T, Tc, VEC><<<apply_grid(n), WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout);
 }
 

@@ -1,0 +1,232 @@
+// Batched execution of many independent graphs on one device (the serving loop).
+//
+// A server runs `lanes` worker threads, each with its own HIP stream (default priority).
+// Attached graphs are pinned to lane id mod lanes; a lane takes its requests in
+// submission order and runs each one as a complete single-graph update (grest_update,
+// then grest_sync for the deferred status), so one graph's updates stay ordered and
+// never overlap, while the lanes overlap on the device.  Requests own copies of their
+// change lists.  Completions are kept until grest_poll hands them out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/grest.h"
+#include "grest_internal.h"
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Request {
+  int32_t gid = 0;
+  uint64_t tag = 0;
+  int64_t n_new = 0;
+  std::vector<int32_t> ei, ej;
+  std::vector<int8_t> sg;
+  std::vector<double> omega;
+  bool has_omega = false;
+  int64_t t_submit = 0;
+};
+
+struct Done {
+  uint64_t tag;
+  int32_t status;
+  int64_t t_submit, t_done;
+};
+
+struct Graph {
+  grest_state* st;
+  void* user_stream;  // restored on destroy (null: the state had its own stream)
+  int64_t bytes;
+  int64_t sketch_cols;  // L + P of an RSVD state, else 0
+  int64_t n_proj;       // node count once every queued request of the graph has run
+};
+
+}  // namespace
+
+struct grest_server {
+  int device = 0;
+  int64_t budget = 0, used = 0;
+  int32_t nlanes = 0, max_queue = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<std::deque<Request>> queues;
+  std::vector<std::thread> workers;
+  std::vector<Graph> graphs;
+  std::deque<Done> done;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_idle;
+  int64_t pending = 0;  // queued or running
+  bool stop = false;
+};
+
+namespace {
+
+void worker(grest_server* sv, int lane) {
+  (void)hipSetDevice(sv->device);
+  for (;;) {
+    Request rq;
+    grest_state* st = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queues[lane].empty(); });
+      if (sv->queues[lane].empty()) return;  // stop requested and nothing left
+      rq = std::move(sv->queues[lane].front());
+      sv->queues[lane].pop_front();
+      st = sv->graphs[rq.gid].st;  // read under the lock: attach may grow the table
+    }
+    const int64_t nc = (int64_t)rq.ei.size();
+    grest_status rc = grest_update(st, rq.n_new, nc, nc ? rq.ei.data() : nullptr, nc ? rq.ej.data() : nullptr,
+                                   nc ? rq.sg.data() : nullptr, rq.has_omega ? rq.omega.data() : nullptr,
+                                   GREST_HOST);
+    const grest_status rs = grest_sync(st);  // waits for the update and reads its status
+    if (rc == GREST_OK) rc = rs;
+    const int64_t t_done = now_ns();
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      if (rc != GREST_OK) sv->graphs[rq.gid].n_proj -= rq.n_new;  // the graph did not grow
+      sv->done.push_back(Done{rq.tag, (int32_t)rc, rq.t_submit, t_done});
+      --sv->pending;
+    }
+    sv->cv_idle.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t grest_now_ns(void) { return now_ns(); }
+
+grest_status grest_server_create(int64_t hbm_budget_bytes, int32_t lanes, int32_t max_queue, grest_server** out) {
+  if (!out) return GREST_EINVAL;
+  *out = nullptr;
+  if (lanes < 1 || lanes > 64 || max_queue < 1 || hbm_budget_bytes < 0) return GREST_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GREST_ENODEV;
+  grest_server* sv = new (std::nothrow) grest_server();
+  if (!sv) return GREST_ENOMEM;
+  (void)hipGetDevice(&sv->device);
+  sv->budget = hbm_budget_bytes;
+  sv->nlanes = lanes;
+  sv->max_queue = max_queue;
+  sv->queues.resize(lanes);
+  for (int l = 0; l < lanes; ++l) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t t : sv->streams) (void)hipStreamDestroy(t);
+      delete sv;
+      return GREST_EDEVICE;
+    }
+    sv->streams.push_back(s);
+  }
+  for (int l = 0; l < lanes; ++l) sv->workers.emplace_back(worker, sv, l);
+  *out = sv;
+  return GREST_OK;
+}
+
+grest_status grest_server_attach(grest_server* sv, grest_state* st, int32_t* graph_id) {
+  if (!sv || !st || !graph_id) return GREST_EINVAL;
+  int64_t bytes = 0;
+  grest_status rc = grest_memory(st, &bytes);
+  if (rc != GREST_OK) return rc;
+  int64_t n = 0;
+  int32_t k = 0, width = 0;
+  if ((rc = grest_shape(st, &n, nullptr, &k, &width)) != GREST_OK) return rc;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  for (const Graph& g : sv->graphs)
+    if (g.st == st) return GREST_EINVAL;  // already attached
+  if (sv->budget > 0 && sv->used + bytes > sv->budget) return GREST_EAGAIN;
+  const int32_t id = (int32_t)sv->graphs.size();
+  void* user = state_user_stream(st);
+  if ((rc = grest_set_stream(st, sv->streams[id % sv->nlanes])) != GREST_OK) return rc;
+  sv->graphs.push_back(Graph{st, user, bytes, state_sketch_cols(st), n});
+  sv->used += bytes;
+  *graph_id = id;
+  return GREST_OK;
+}
+
+grest_status grest_submit(grest_server* sv, int32_t graph_id, int64_t n_new, int64_t n_changes, const int32_t* ei,
+                          const int32_t* ej, const int8_t* sign, const double* omega, uint64_t tag) {
+  if (!sv || n_new < 0 || n_changes < 0) return GREST_EINVAL;
+  if (n_changes > 0 && (!ei || !ej || !sign)) return GREST_EINVAL;
+  Graph g;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (graph_id < 0 || graph_id >= (int32_t)sv->graphs.size()) return GREST_EINVAL;
+    g = sv->graphs[graph_id];
+  }
+  if (g.sketch_cols > 0 && n_new > 0 && !omega) return GREST_EINVAL;
+  // format, id ranges, no duplicates: against the size the graph will have when this runs
+  if (grest_validate_changes(g.n_proj, n_new, n_changes, ei, ej, sign) != GREST_OK) return GREST_EINVAL;
+  Request rq;
+  rq.gid = graph_id;
+  rq.tag = tag;
+  rq.n_new = n_new;
+  rq.ei.assign(ei, ei + n_changes);
+  rq.ej.assign(ej, ej + n_changes);
+  rq.sg.assign(sign, sign + n_changes);
+  if (omega && g.sketch_cols > 0 && n_new > 0) {
+    rq.omega.assign(omega, omega + (size_t)n_new * (size_t)g.sketch_cols);
+    rq.has_omega = true;
+  }
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->pending >= sv->max_queue) return GREST_EAGAIN;
+    sv->graphs[graph_id].n_proj += n_new;
+    rq.t_submit = now_ns();
+    sv->queues[graph_id % sv->nlanes].push_back(std::move(rq));
+    ++sv->pending;
+  }
+  sv->cv_work.notify_all();
+  return GREST_OK;
+}
+
+int32_t grest_poll(grest_server* sv, int32_t max, uint64_t* tags, int32_t* status, int64_t* t_submit_ns,
+                   int64_t* t_done_ns) {
+  if (!sv || max <= 0) return 0;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  int32_t c = 0;
+  while (c < max && !sv->done.empty()) {
+    const Done& d = sv->done.front();
+    if (tags) tags[c] = d.tag;
+    if (status) status[c] = d.status;
+    if (t_submit_ns) t_submit_ns[c] = d.t_submit;
+    if (t_done_ns) t_done_ns[c] = d.t_done;
+    sv->done.pop_front();
+    ++c;
+  }
+  return c;
+}
+
+grest_status grest_server_drain(grest_server* sv) {
+  if (!sv) return GREST_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  sv->cv_idle.wait(lk, [&] { return sv->pending == 0; });
+  return GREST_OK;
+}
+
+void grest_server_destroy(grest_server* sv) {
+  if (!sv) return;
+  (void)grest_server_drain(sv);
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  for (std::thread& t : sv->workers) t.join();
+  for (const Graph& g : sv->graphs) (void)grest_set_stream(g.st, g.user_stream);
+  for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+  delete sv;
+}
+
+}  // extern "C"

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgrest.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ENODEV = range(6)
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ENODEV, EAGAIN = range(7)
 OP = {"adj": 0, "lap": 1, "nlap": 2}
 VARIANT = {"g2": 2, "g3": 3, "rsvd": 4}
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
@@ -59,6 +59,16 @@ _SIGS = [
     ("grest_stage_times", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_int64)]),
     ("grest_destroy", None, [C.c_void_p]),
+    ("grest_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("grest_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("grest_now_ns", C.c_int64, []),
+    ("grest_server_create", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    ("grest_server_attach", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    ("grest_submit", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_uint64]),
+    ("grest_poll", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grest_server_drain", C.c_int, [C.c_void_p]),
+    ("grest_server_destroy", None, [C.c_void_p]),
 ]
 
 
@@ -205,6 +215,15 @@ class State:
     STAGES = ["graph_update", "delta_x", "augment", "project_orth", "spmm", "projected_matrix", "small_eig",
               "back_projection"]
 
+    def memory(self) -> int:
+        """Device bytes held by the state."""
+        b = C.c_int64()
+        _check(lib().grest_memory(self._h, C.byref(b)), "grest_memory")
+        return int(b.value)
+
+    def set_stream(self, stream: Optional[int]):
+        _check(lib().grest_set_stream(self._h, C.c_void_p(stream) if stream else None), "grest_set_stream")
+
     def profile(self, enable: bool = True):
         _check(lib().grest_profile(self._h, int(bool(enable))), "grest_profile")
 
@@ -224,3 +243,55 @@ class State:
         _check(lib().grest_get_graph(self._h, rp.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p)),
                "grest_get_graph")
         return rp, col
+
+
+def now_ns() -> int:
+    """The monotonic clock of the server's time stamps, in nanoseconds."""
+    return int(lib().grest_now_ns())
+
+
+class Server:
+    """Batched execution of many graphs on the current device (grest_server_* in grest.h)."""
+
+    def __init__(self, lanes: int = 4, max_queue: int = 1 << 16, hbm_budget_bytes: int = 0):
+        self._lib = lib()
+        self._h = C.c_void_p()
+        _check(self._lib.grest_server_create(int(hbm_budget_bytes), int(lanes), int(max_queue),
+                                             C.byref(self._h)), "grest_server_create")
+        self._states = []
+
+    def attach(self, state: "State") -> int:
+        gid = C.c_int32()
+        _check(self._lib.grest_server_attach(self._h, state._h, C.byref(gid)), "grest_server_attach")
+        self._states.append(state)
+        return int(gid.value)
+
+    def submit(self, graph_id: int, n_new: int, i, j, sign, omega=None, tag: int = 0) -> int:
+        """Queues one update (host arrays); returns the status (OK, EAGAIN or EINVAL)."""
+        i, pi = _host(i, np.int32)
+        j, pj = _host(j, np.int32)
+        sg, ps = _host(sign, np.int8)
+        om, po = (None, None) if omega is None else _host(omega, np.float64)
+        return int(self._lib.grest_submit(self._h, int(graph_id), int(n_new), int(i.size), pi, pj, ps, po,
+                                          C.c_uint64(int(tag))))
+
+    def poll(self, max_items: int = 4096):
+        """Finished requests: arrays (tag, status, t_submit_ns, t_done_ns)."""
+        tags = np.empty(max_items, np.uint64)
+        st = np.empty(max_items, np.int32)
+        ts = np.empty(max_items, np.int64)
+        td = np.empty(max_items, np.int64)
+        c = int(self._lib.grest_poll(self._h, int(max_items), tags.ctypes.data_as(C.c_void_p),
+                                     st.ctypes.data_as(C.c_void_p), ts.ctypes.data_as(C.c_void_p),
+                                     td.ctypes.data_as(C.c_void_p)))
+        return tags[:c], st[:c], ts[:c], td[:c]
+
+    def drain(self):
+        _check(self._lib.grest_server_drain(self._h), "grest_server_drain")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.grest_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    __del__ = close

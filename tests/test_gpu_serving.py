@@ -1,0 +1,172 @@
+"""Batched execution of many graphs through the serving entry points (grest_server_*).
+
+The server runs the single-graph update for several graphs on several lanes (host
+threads with their own streams).  What it must guarantee, and what is checked here:
+a graph's result does not depend on the other graphs in the mix or on the lane
+interleaving (bitwise equal to the same updates run alone), per-graph order is kept,
+an invalid request fails alone and leaves its graph unchanged, admission limits are
+enforced, and completion records carry consistent time stamps.  The numerical quality
+of each update is the parity suite's business; one graph here is also checked
+against the FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import grest_oracle as O
+from paper_2603_19439_amd import grest as G
+from paper_2603_19439_amd import metrics as M
+from paper_2603_19439_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def banner(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _graphs(count, n0=600, steps=4, new=20):
+    """Small SBM graphs with different seeds and K, with the exact initial pairs."""
+    out = []
+    for g in range(count):
+        wl = W.sbm_small(n0=n0 + 40 * g, new_per_step=new, insertions=60, deletions=20, steps=steps, cfg_id=1,
+                         graph_id=10 + g)
+        k = (4, 6, 8)[g % 3]
+        A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+        th, X, _ = O.leading_eigenpairs(A, k)
+        out.append((wl, k, th, X))
+    return out
+
+
+def _new_state(wl, k, th, X, prec):
+    st = G.State(wl.rowptr0, wl.col0, k=k, variant="rsvd", precision=prec, L=k, P=k)
+    st.set_pairs(th, X)
+    return st
+
+
+def _omega(wl, g, t, d, k):
+    return W.omega(wl.cfg_id, g, t + 1, d.n_new, 2 * k) if d.n_new > 0 else None
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_results_do_not_depend_on_the_mix(prec):
+    graphs = _graphs(3)
+    # reference: every graph alone, updates driven directly
+    ref = []
+    for g, (wl, k, th, X) in enumerate(graphs):
+        banner(f"serving reference graph {g} prec={prec} n0={wl.n0} k={k}")
+        st = _new_state(wl, k, th, X, prec)
+        for t, d in enumerate(wl.deltas):
+            st.update_delta(d, _omega(wl, g, t, d, k))
+        st.sync()
+        ref.append(st.get())
+        st.close()
+    # the same updates interleaved over two lanes
+    banner(f"serving mix prec={prec}")
+    sv = G.Server(lanes=2)
+    states = [_new_state(wl, k, th, X, prec) for (wl, k, th, X) in graphs]
+    ids = [sv.attach(st) for st in states]
+    tag = 0
+    steps = len(graphs[0][0].deltas)
+    for t in range(steps):
+        for g, (wl, k, th, X) in enumerate(graphs):
+            d = wl.deltas[t]
+            rc = sv.submit(ids[g], d.n_new, d.i, d.j, d.sign, _omega(wl, g, t, d, k), tag=1000 * g + t)
+            assert rc == G.OK, rc
+            tag += 1
+    sv.drain()
+    tags, status, ts, td = sv.poll(1024)
+    assert tags.size == tag and np.all(status == G.OK), (tags, status)
+    assert np.all(td >= ts)
+    # per-graph completion order follows submission order
+    for g in range(len(graphs)):
+        mine = [int(x) % 1000 for x in tags if int(x) // 1000 == g]
+        assert mine == sorted(mine), mine
+    sv.close()
+    for g, st in enumerate(states):
+        vals, X = st.get()
+        assert np.array_equal(vals, ref[g][0]) and np.array_equal(X, ref[g][1]), f"graph {g} differs"
+        st.close()
+
+
+def test_served_graph_matches_oracle():
+    (wl, k, th, X), = _graphs(1)
+    banner(f"serving vs oracle n0={wl.n0} k={k}")
+    sv = G.Server(lanes=3)
+    st = _new_state(wl, k, th, X, "fp64")
+    gid = sv.attach(st)
+    for t, d in enumerate(wl.deltas):
+        assert sv.submit(gid, d.n_new, d.i, d.j, d.sign, _omega(wl, 0, t, d, k), tag=t) == G.OK
+    sv.drain()
+    _, status, _, _ = sv.poll(64)
+    assert np.all(status == G.OK)
+    sv.close()
+    A, Xo, tho = O.adjacency_from_csr(wl.rowptr0, wl.col0), X, th
+    for t, d in enumerate(wl.deltas):
+        r = O.grest_step(A, Xo, tho, d.n_new, d.i, d.j, d.sign, k, variant=O.RSVD, L=k,
+                         Omega=_omega(wl, 0, t, d, k))
+        A, Xo, tho = r.A, r.X, r.theta
+    vals, Xg = st.get()
+    kk = M.gap_prefix(np.abs(tho), k, 1e-3)
+    assert M.eig_rel_error(vals[:kk], tho[:kk]) <= 1e-10
+    if kk > 0:
+        assert M.subspace_sine(Xg[:, :kk], Xo[:, :kk]) <= 1e-8
+    st.close()
+
+
+def test_invalid_request_fails_alone():
+    (wl, k, th, X), = _graphs(1)
+    banner("serving invalid request")
+    # reference: only the valid first update
+    st_ref = _new_state(wl, k, th, X, "fp64")
+    d0 = wl.deltas[0]
+    st_ref.update_delta(d0, _omega(wl, 0, 0, d0, k))
+    st_ref.sync()
+    ref = st_ref.get()
+    st_ref.close()
+    sv = G.Server(lanes=1)
+    st = _new_state(wl, k, th, X, "fp64")
+    gid = sv.attach(st)
+    # an insertion of an existing edge passes the host checks and fails on the device
+    i0 = int(np.repeat(np.arange(wl.n0), np.diff(wl.rowptr0))[0])
+    j0 = int(wl.col0[0])
+    a, b = min(i0, j0), max(i0, j0)
+    assert sv.submit(gid, 0, np.array([a]), np.array([b]), np.array([1], np.int8), None, tag=1) == G.OK
+    assert sv.submit(gid, d0.n_new, d0.i, d0.j, d0.sign, _omega(wl, 0, 0, d0, k), tag=2) == G.OK
+    # a host-detectable error is refused at submission
+    assert sv.submit(gid, 0, np.array([3]), np.array([3]), np.array([1], np.int8), None, tag=3) == G.EINVAL
+    sv.drain()
+    tags, status, _, _ = sv.poll(16)
+    assert list(tags) == [1, 2] and status[0] == G.EINVAL and status[1] == G.OK, (tags, status)
+    sv.close()
+    vals, Xg = st.get()
+    assert np.array_equal(vals, ref[0]) and np.array_equal(Xg, ref[1])
+    st.close()
+
+
+def test_admission_limits():
+    (wl, k, th, X), = _graphs(1)
+    banner("serving admission")
+    st = _new_state(wl, k, th, X, "fp64")
+    assert st.memory() > 0
+    sv = G.Server(lanes=1, hbm_budget_bytes=1)
+    with pytest.raises(G.GrestError) as e:
+        sv.attach(st)
+    assert e.value.status == G.EAGAIN
+    sv.close()
+    sv = G.Server(lanes=1, max_queue=1)
+    gid = sv.attach(st)
+    d0, d1 = wl.deltas[0], wl.deltas[1]
+    assert sv.submit(gid, d0.n_new, d0.i, d0.j, d0.sign, _omega(wl, 0, 0, d0, k), tag=1) == G.OK
+    # the first update takes milliseconds; this submission comes microseconds later
+    assert sv.submit(gid, d1.n_new, d1.i, d1.j, d1.sign, _omega(wl, 0, 1, d1, k), tag=2) == G.EAGAIN
+    sv.drain()
+    tags, status, _, _ = sv.poll(16)
+    assert list(tags) == [1] and status[0] == G.OK
+    sv.close()
+    # the state is usable directly again after the server is gone
+    st.update_delta(d1, _omega(wl, 0, 1, d1, k))
+    st.sync()
+    st.close()
