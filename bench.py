@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink node counts (quick runs only)")
     ap.add_argument("--init-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-graphs", type=int, default=32,
+                    help="graphs in the many-graph serving leg (0 skips it; the full mix has 256)")
+    ap.add_argument("--serving-rates", default="100,400", help="Poisson arrival rates, requests/s")
+    ap.add_argument("--serving-requests", default="300,800", help="requests per rate")
+    ap.add_argument("--serving-lanes", type=int, default=4)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference kernel of "
                          "known traffic for hardware byte counters)")
@@ -156,6 +161,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args)
+    n0_main = wl.n0
+    del wl, dev_steps
+    serve = serving_leg(args) if args.serving_graphs > 0 else None
 
     out = {
         "metric": "eigen-updates/sec at n=1M,k=32 (mixed vs FP32) + p50/p99 latency @ accuracy",
@@ -172,7 +180,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "SBM n0=1e6, 32 Dirichlet(2) blocks, mean degree 20, +10k nodes/+50k edges "
                                "per step; adjacency, k=32, G-REST_RSVD L=P=32 (width 96)",
-                   "n0": wl.n0, "k": K, "L": L, "P": P, "variant": "rsvd", "precision": args.precision,
+                   "n0": n0_main, "k": K, "L": L, "P": P, "variant": "rsvd", "precision": args.precision,
                    "scale": args.scale},
         "stages_ms_per_update": {k: round(v / max(1, main_res["updates"]), 4) for k, v in stages.items()},
         "dominant_stage": dominant,
@@ -190,9 +198,117 @@ def main():
                           "speedup_of_headline": round(value / cv, 3),
                           "stages_ms_per_update": {k: round(v / max(1, cmp_res["updates"]), 4)
                                                    for k, v in cmp_res["stages_ms"].items()}}
+    if serve is not None:
+        out["serving"] = serve
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def serving_leg(args):
+    """Update latency of many graphs served together: Poisson arrivals with uniform target
+    graphs, each request one update of its graph (G-REST_RSVD, L = P = K), run by the
+    library's server.  Latency = completion time - scheduled arrival time.  Two probe
+    graphs (the smallest) start from the oracle's exact pairs and their whole request
+    sequences are replayed through the FP64 oracle afterwards (accuracy gate)."""
+    import numpy as np
+    import torch
+    from oracle import grest_oracle as O
+    from paper_2603_19439_amd import grest as G
+    from paper_2603_19439_amd import metrics as M
+    from paper_2603_19439_amd import workloads as W
+
+    rates = [float(x) for x in args.serving_rates.split(",")]
+    counts = [int(x) for x in args.serving_requests.split(",")]
+    ng = args.serving_graphs
+    per_graph = int(np.ceil(sum(counts) / ng * 1.6)) + 8
+    t0 = time.time()
+    graphs = [W.serving_graph(g, per_graph) for g in range(ng)]
+    log(args, f"serving: {ng} graphs generated in {time.time() - t0:.1f}s "
+              f"(n0 {min(g.workload.n0 for g in graphs)}..{max(g.workload.n0 for g in graphs)})")
+    probes = sorted(range(ng), key=lambda g: graphs[g].workload.n0)[:2]
+    states, exact0 = [], {}
+    for g, sg in enumerate(graphs):
+        wl = sg.workload
+        n_fin = wl.n0 + sum(d.n_new for d in wl.deltas) + 1
+        nnz = int(wl.col0.size + 2 * sum(d.n_changes for d in wl.deltas) + 1024)
+        st = G.State(wl.rowptr0, wl.col0, k=sg.k, variant="rsvd", op="adj", precision=args.precision, L=sg.k,
+                     P=sg.k, node_capacity=n_fin, nnz_capacity=nnz)
+        if g in probes:
+            th, X, _ = O.leading_eigenpairs(O.adjacency_from_csr(wl.rowptr0, wl.col0), sg.k)
+            st.set_pairs(th, X)
+            exact0[g] = (th, X)
+        else:
+            st.init_pairs(iterations=20, seed=g)
+        states.append(st)
+    torch.cuda.synchronize()
+    sv = G.Server(lanes=args.serving_lanes, max_queue=1 << 16)
+    ids = [sv.attach(st) for st in states]
+    nxt = [0] * ng
+    results = []
+    for seg, (rate, count) in enumerate(zip(rates, counts)):
+        t_arr, tgt = W.arrivals(rate, count, ng, seed=seg)
+        reqs = []
+        for q in range(count):
+            g = int(tgt[q])
+            for _ in range(ng):  # a graph whose requests are used up passes to the next one
+                if nxt[g] < per_graph:
+                    break
+                g = (g + 1) % ng
+            d = graphs[g].workload.deltas[nxt[g]]
+            om = W.omega(4, g, nxt[g] + 1, d.n_new, 2 * graphs[g].k) if d.n_new > 0 else None
+            reqs.append((g, d.n_new, d.i.astype(np.int32), d.j.astype(np.int32), d.sign, om))
+            nxt[g] += 1
+        start = G.now_ns() + 20_000_000
+        arr_ns = start + (t_arr * 1e9).astype(np.int64)
+        retries = 0
+        for q, (g, s_new, i, j, sg_, om) in enumerate(reqs):
+            wait = (arr_ns[q] - G.now_ns()) / 1e9
+            if wait > 2e-4:
+                time.sleep(wait - 2e-4)
+            while G.now_ns() < arr_ns[q]:
+                pass
+            while sv.submit(ids[g], s_new, i, j, sg_, om, tag=q) == G.EAGAIN:
+                retries += 1
+                time.sleep(1e-4)
+        sv.drain()
+        tags, status, ts, td = sv.poll(count + 16)
+        if tags.size != count or np.any(status != G.OK):
+            raise RuntimeError(f"serving: {tags.size}/{count} completions, statuses {np.unique(status)}")
+        lat_ms = (td - arr_ns[tags.astype(np.int64)]) / 1e6
+        makespan = (td.max() - start) / 1e9
+        results.append({"rate_req_s": rate, "requests": count, "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                        "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                        "mean_ms": round(float(lat_ms.mean()), 3),
+                        "throughput_req_s": round(count / makespan, 1), "queue_full_retries": retries})
+        log(args, f"serving at {rate:g} req/s: p50 {results[-1]['p50_ms']} ms, p99 {results[-1]['p99_ms']} ms")
+    sv.close()
+    # accuracy of the probe graphs over all the requests they received
+    acc = []
+    for g in probes:
+        wl, k = graphs[g].workload, graphs[g].k
+        A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+        th, X = exact0[g]
+        for t in range(nxt[g]):
+            d = wl.deltas[t]
+            om = W.omega(4, g, t + 1, d.n_new, 2 * k) if d.n_new > 0 else None
+            r = O.grest_step(A, X, th, d.n_new, d.i, d.j, d.sign, k, variant=O.RSVD, L=k, Omega=om)
+            A, X, th = r.A, r.X, r.theta
+        vals, Xg = states[g].get()
+        kk = M.gap_prefix(np.abs(th), k, 1e-3)
+        e = float(M.eig_rel_error(vals[:kk], th[:kk])) if kk else 0.0
+        sine = float(M.subspace_sine(Xg[:, :kk], X[:, :kk])) if kk else 0.0
+        acc.append({"graph": g, "n0": wl.n0, "k": k, "updates": nxt[g], "k_gated": kk,
+                    "e_lambda": e, "sine": sine})
+    for st in states:
+        st.close()
+    tol = {"fp64": 1e-10, "fp32": 1e-5, "mixed": 1e-3}[args.precision]
+    passed = all(a["e_lambda"] <= tol and a["sine"] <= 1e-3 for a in acc)
+    return {"workload": f"{ng} graphs (SBM or Chung-Lu, n0 {min(g.workload.n0 for g in graphs)}.."
+                        f"{max(g.workload.n0 for g in graphs)}, mean degree 8-32, K in {{8,16,32}}, "
+                        f"G-REST_RSVD L=P=K), requests of 0.1-1 % new nodes + 0.1-1 % insertions",
+            "lanes": args.serving_lanes, "precision": args.precision, "rates": results,
+            "accuracy_probes": acc, "accuracy_gate_passed": passed}
 
 
 def cpu_baseline(wl, args):

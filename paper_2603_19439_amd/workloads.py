@@ -420,6 +420,129 @@ def chung_lu(n0=100_000, gamma=2.5, mean=16.0, cap=2000.0, steps=20, ins_frac=0.
     return Workload("chung_lu", cfg_id, n0, rowptr0, col0, deltas, keys)
 
 
+# --------------------------------------------------------------------------------------
+# many independent graphs with a stream of update requests (serving)
+# --------------------------------------------------------------------------------------
+@dataclasses.dataclass
+class ServingGraph:
+    graph_id: int
+    family: str  # "sbm" or "chunglu"
+    k: int
+    workload: Workload  # the initial graph and its requests, in order
+
+
+class _EdgeSet:
+    """Membership of canonical keys: a sorted base array plus recent additions, merged
+    from time to time (insert-only streams)."""
+
+    def __init__(self, keys):
+        self.base = np.sort(keys)
+        self.extra = []
+        self.count = int(self.base.size)
+
+    def contains(self, k):
+        pos = np.searchsorted(self.base, k)
+        hit = (pos < self.base.size) & (self.base[np.minimum(pos, self.base.size - 1)] == k)
+        for e in self.extra:
+            hit |= np.isin(k, e)
+        return hit
+
+    def add(self, k):
+        self.extra.append(np.asarray(k, dtype=np.int64))
+        self.count += int(k.size)
+        if len(self.extra) >= 8:
+            self.base = np.union1d(self.base, np.concatenate(self.extra))
+            self.extra = []
+
+
+def serving_graph(graph_id: int, requests: int, scale: float = 1.0, cfg_id: int = 4) -> ServingGraph:
+    """One graph of the many-graph serving mix and ``requests`` updates for it.
+
+    Family Bernoulli(1/2): SBM (8-32 blocks, Dirichlet(2) proportions, 80 % of the edges
+    inside blocks) or Chung-Lu (pdf exponent 2.5).  Mean degree uniform in 8..32,
+    n0 ~ LogNormal(ln 5e4, 1) clipped to [1e4, 5e5] (times ``scale``), K uniform in
+    {8, 16, 32}.  Each request appends round(U[0.1, 1] % of n) nodes, wired per family
+    (SBM: Poisson(d/2) partners, 80 % in the node's own block; Chung-Lu: max(1,
+    Poisson(w)) partners proportional to the weights), plus round(U[0.1, 1] % of the
+    edge count) uniform insertions among non-adjacent existing pairs."""
+    rng = rng_for(cfg_id, graph_id, 0, _GRAPH)
+    family = "sbm" if rng.random() < 0.5 else "chunglu"
+    n0 = int(np.clip(np.exp(rng.normal(np.log(5e4), 1.0)), 1e4, 5e5) * scale)
+    n0 = max(n0, 64)
+    d = int(rng.integers(8, 33))
+    k = int(rng.choice([8, 16, 32]))
+    if family == "sbm":
+        blocks = int(rng.integers(8, 33))
+        pi = rng.dirichlet(np.full(blocks, 2.0))
+        sizes = rng.multinomial(n0, pi).astype(np.int64)
+        offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        ssq = float(np.sum(sizes.astype(np.float64) ** 2))
+        p_in = 0.8 * d * n0 / ssq
+        p_out = 0.2 * d * n0 / max(float(n0) ** 2 - ssq, 1.0)
+        a, b = _sbm_edges_by_counts(rng, sizes, offsets, p_in, p_out)
+        perm = rng.permutation(n0)
+        labels = np.empty(n0, dtype=np.int64)
+        labels[perm] = np.repeat(np.arange(blocks), sizes)
+        keys = _dedupe_pairs(perm[a], perm[b])
+        w = None
+    else:
+        cap = float(np.sqrt(d * n0))
+        w, xm = pareto_weights(rng, n0, 2.5, float(d), cap)
+        keys = _connect(rng, n0, _chung_lu_keys(rng, w), w)
+        labels = None
+    rowptr0, col0 = csr_from_keys(n0, keys)
+    es = _EdgeSet(keys)
+    deltas = []
+    n = n0
+    for t in range(1, requests + 1):
+        r = rng_for(cfg_id, graph_id, t, _DELTA)
+        s = max(1, int(round(r.uniform(0.001, 0.01) * n)))
+        n_ins = int(round(r.uniform(0.001, 0.01) * es.count))
+        if family == "sbm":
+            lab_new = r.choice(pi.size, size=s, p=pi)
+            all_lab = np.concatenate([labels, lab_new])
+            order = np.argsort(all_lab, kind="stable")
+            cnt = np.bincount(all_lab, minlength=pi.size)
+            start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+            deg = r.poisson(d / 2.0, s)
+            src = np.repeat(np.arange(n, n + s), deg)
+            own = np.repeat(lab_new, deg)
+            intra = r.random(src.size) < 0.8
+            tgt = r.integers(0, n + s, src.size)
+            pos = (r.random(src.size) * cnt[own]).astype(np.int64)
+            tgt[intra] = order[start[own[intra]] + pos[intra]]
+            labels = all_lab
+        else:
+            wn = np.minimum(xm * (1.0 - r.random(s)) ** (-1.0 / 1.5), cap)
+            deg = np.maximum(1, r.poisson(wn))
+            src = np.repeat(np.arange(n, n + s), deg)
+            cdf = np.cumsum(w / w.sum())
+            cdf[-1] = 1.0
+            tgt = np.searchsorted(cdf, r.random(src.size), side="right").astype(np.int64)
+            w = np.concatenate([w, wn])
+        ins_new = _dedupe_pairs(src, tgt)
+        u = r.integers(0, n, 2 * n_ins + 16)
+        v = r.integers(0, n, u.size)
+        ko = _dedupe_pairs(u, v)
+        ko = ko[~es.contains(ko)]
+        r.shuffle(ko)
+        ko = ko[:n_ins]
+        dl = _delta_from_keys(n, s, np.concatenate([ins_new, ko]), np.empty(0, np.int64))
+        deltas.append(dl)
+        es.add(_keys(dl.i, dl.j))
+        n += s
+    wl = Workload(f"serving_{family}", cfg_id, n0, rowptr0, col0, deltas)
+    return ServingGraph(graph_id, family, k, wl)
+
+
+def arrivals(rate: float, count: int, graphs: int, seed: int, cfg_id: int = 4):
+    """Poisson arrival times (seconds from the start) and uniform target graphs."""
+    r = rng_for(cfg_id, seed, 0, _ARRIVAL)
+    t = np.cumsum(r.exponential(1.0 / rate, count))
+    g = r.integers(0, graphs, count)
+    return t, g
+
+
 def omega(cfg_id: int, graph_id: int, step: int, rows: int, cols: int) -> np.ndarray:
     """The Gaussian test matrix of the randomized range finder, i.i.d. N(0,1), FP64,
     ``rows x cols`` row-major.  Passed to both the oracle and the GPU path."""
