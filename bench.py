@@ -268,13 +268,19 @@ def serving_leg(args):
                 time.sleep(wait - 2e-4)
             while G.now_ns() < arr_ns[q]:
                 pass
-            while sv.submit(ids[g], s_new, i, j, sg_, om, tag=q) == G.EAGAIN:
+            while True:
+                rc = sv.submit(ids[g], s_new, i, j, sg_, om, tag=q)
+                if rc != G.EAGAIN:
+                    break
                 retries += 1
                 time.sleep(1e-4)
+            if rc != G.OK:
+                raise RuntimeError(f"serving: request {q} (graph {g}) refused with status {rc}")
         sv.drain()
         tags, status, ts, td = sv.poll(count + 16)
         if tags.size != count or np.any(status != G.OK):
-            raise RuntimeError(f"serving: {tags.size}/{count} completions, statuses {np.unique(status)}")
+            bad = [(int(t), reqs[int(t)][0], int(st_)) for t, st_ in zip(tags, status) if st_ != G.OK]
+            raise RuntimeError(f"serving: {tags.size}/{count} completions; failed (tag, graph, status): {bad[:20]}")
         lat_ms = (td - arr_ns[tags.astype(np.int64)]) / 1e6
         makespan = (td.max() - start) / 1e9
         results.append({"rate_req_s": rate, "requests": count, "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),

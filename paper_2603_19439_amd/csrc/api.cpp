@@ -99,8 +99,11 @@ struct grest_state {
 
   int32_t *d_ei = nullptr, *d_ej = nullptr;
   int8_t* d_sg = nullptr;
-  int64_t *dcnt = nullptr, *dptr = nullptr, *dfill = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
-  int32_t *dcol_tmp = nullptr, *dcol = nullptr, *dins = nullptr;
+  int64_t *dcnt = nullptr, *dptr = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
+  uint64_t *dkey_in = nullptr, *dkey_out = nullptr;  // packed (row, column) keys of Delta
+  char* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  int32_t *dcol = nullptr, *dins = nullptr;
   int8_t *dsg_tmp = nullptr, *dsg = nullptr;
 
   double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *Mchol = nullptr, *H = nullptr, *F = nullptr;
@@ -161,7 +164,6 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   if (st->variant == GREST_RSVD) CHK(dalloc((char**)&st->ybuf, (size_t)cap_n * st->ldy * es));
   CHK(dalloc(&st->dcnt, cap_n + 1));
   CHK(dalloc(&st->dptr, cap_n + 1));
-  CHK(dalloc(&st->dfill, cap_n + 1));
   CHK(dalloc(&st->newlen, cap_n + 1));
   CHK(dalloc(&st->scan_tmp, scan_tmp_elems(cap_n + 1) + 16));
   st->cap_n = cap_n;
@@ -179,11 +181,15 @@ grest_status alloc_edge_arrays(grest_state* st, int64_t cap_m) {
 
 grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
-  dfree(st->dcol_tmp); dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
+  dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
+  dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
   CHK(dalloc(&st->d_ei, cap_nc));
   CHK(dalloc(&st->d_ej, cap_nc));
   CHK(dalloc(&st->d_sg, cap_nc));
-  CHK(dalloc(&st->dcol_tmp, 2 * cap_nc));
+  CHK(dalloc(&st->dkey_in, 2 * cap_nc));
+  CHK(dalloc(&st->dkey_out, 2 * cap_nc));
+  st->sort_tmp_bytes = delta_sort_temp_bytes(2 * cap_nc);
+  CHK(dalloc(&st->sort_tmp, st->sort_tmp_bytes));
   CHK(dalloc(&st->dcol, 2 * cap_nc));
   CHK(dalloc(&st->dins, 2 * cap_nc));
   CHK(dalloc(&st->dsg_tmp, 2 * cap_nc));
@@ -212,8 +218,9 @@ int64_t device_bytes(const grest_state* st) {
   for (int b = 0; b < 2; ++b) { add(st->rp[b]); add(st->col[b]); add(st->sc[b]); add(st->z[b]); }
   add(st->aux); add(st->ybuf); add(st->bt); add(st->omega_t); add(st->omega64);
   add(st->d_ei); add(st->d_ej); add(st->d_sg);
-  add(st->dcnt); add(st->dptr); add(st->dfill); add(st->newlen); add(st->scan_tmp);
-  add(st->dcol_tmp); add(st->dcol); add(st->dins); add(st->dsg_tmp); add(st->dsg);
+  add(st->dcnt); add(st->dptr); add(st->newlen); add(st->scan_tmp);
+  add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp);
+  add(st->dcol); add(st->dins); add(st->dsg_tmp); add(st->dsg);
   add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F);
   add(st->theta); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
   add(st->ranks); add(st->status); add(st->maxdeg);
@@ -226,8 +233,9 @@ void free_all(grest_state* st) {
   }
   dfree(st->aux); dfree(st->ybuf); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
-  dfree(st->dcnt); dfree(st->dptr); dfree(st->dfill); dfree(st->newlen); dfree(st->scan_tmp);
-  dfree(st->dcol_tmp); dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
+  dfree(st->dcnt); dfree(st->dptr); dfree(st->newlen); dfree(st->scan_tmp);
+  dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
+  dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
   dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
   dfree(st->ranks); dfree(st->status); dfree(st->maxdeg);
@@ -252,7 +260,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   st->rp[0] = st->rp[1] = nullptr;
   st->z[0] = st->z[1] = nullptr;
   st->sc[0] = st->sc[1] = nullptr;
-  dfree(st->aux); dfree(st->ybuf); dfree(st->dcnt); dfree(st->dptr); dfree(st->dfill);
+  dfree(st->aux); dfree(st->ybuf); dfree(st->dcnt); dfree(st->dptr);
   dfree(st->newlen); dfree(st->scan_tmp);
   CHK(alloc_node_arrays(st, cap));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
@@ -393,12 +401,17 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   launch_fill_bytes0(st->status, sizeof(int32_t), s);
   launch_fill_bytes0(st->maxdeg, sizeof(int64_t), s);
   launch_fill_i64(st->dcnt, 0, n2 + 1, s);
-  launch_fill_i64(st->dfill, 0, n2 + 1, s);
-  launch_delta_count(dei, dej, dsg, nc, n, S, st->dcnt, st->status, s);
+  const int kshift = delta_key_shift(n2);
+  launch_delta_keys(dei, dej, dsg, nc, n, S, kshift, st->dkey_in, st->dsg_tmp, st->dcnt, st->status, s);
   launch_scan_excl(st->dcnt, st->dptr, n2, st->scan_tmp, s);
-  launch_delta_scatter(dei, dej, dsg, nc, n, S, st->dptr, st->dfill, st->dcol_tmp, st->dsg_tmp, s);
-  launch_delta_rows(n, S, st->dptr, st->dcol_tmp, st->dsg_tmp, st->dcol, st->dsg, st->dins, st->rp[st->gcur],
-                    st->col[st->gcur], st->newlen, st->status, s);
+  if (!launch_delta_sort(st->dkey_in, st->dkey_out, st->dsg_tmp, st->dsg, 2 * nc, 2 * kshift, st->sort_tmp,
+                         st->sort_tmp_bytes, s)) {
+    snprintf(g_last_error, sizeof(g_last_error), "radix sort of the update could not be launched");
+    return GREST_EDEVICE;
+  }
+  launch_delta_extract(st->dkey_out, 2 * nc, st->dptr + n2, kshift, st->dcol, s);
+  launch_delta_rows(n, S, st->dptr, st->dcol, st->dsg, st->dins, st->rp[st->gcur], st->col[st->gcur], st->newlen,
+                    st->status, s);
   launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, s);
   launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], st->dptr, st->dcol, st->dsg, st->dins, st->rp[gn],
                    st->col[gn], st->cap_m, s);
@@ -529,7 +542,7 @@ grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
   HIPCHK(hipStreamSynchronize(s));
   st->zcur ^= 1;
   st->has_pairs = true;
-  if (st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED)) return GREST_ENUMERIC;
+  if (st->pin->status & ST_NUMERIC) return GREST_ENUMERIC;
   return GREST_OK;
 }
 
@@ -768,7 +781,7 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
   // pull in the status of the previous update before overwriting the pinned word
   HIPCHK(hipStreamSynchronize(st->stream));
   prof_collect(st);
-  st->deferred |= st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED);
+  st->deferred |= st->pin->status & ST_NUMERIC;
   return st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where)
                      : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where);
 }
@@ -777,7 +790,7 @@ grest_status grest_sync(grest_state* st) {
   if (!st) return GREST_EINVAL;
   HIPCHK(hipStreamSynchronize(st->stream));
   prof_collect(st);
-  int32_t bits = st->deferred | (st->pin->status & (ST_NONFINITE | ST_NOT_CONVERGED));
+  int32_t bits = st->deferred | (st->pin->status & ST_NUMERIC);
   st->deferred = 0;
   st->pin->status = 0;
   if (bits) {

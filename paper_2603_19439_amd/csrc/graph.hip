@@ -4,12 +4,14 @@
 // The graph is a CSR with both triangles, int64 row offsets and int32 column ids
 // sorted inside each row.  Delta arrives as a list of undirected changes (i < j, sign).
 // Steps (all on the device):
-//   1. count the two directed entries of every change per row        (atomics)
+//   1. the two directed entries of every change become keys (row, column) packed in
+//      64 bits; the entries per row are counted                      (atomics)
 //   2. exclusive scan of the counts -> row offsets of Delta          (3-kernel scan)
-//   3. scatter the entries into their rows                            (atomics)
-//   4. one wavefront per row: rank-sort the row's entries by column, detect
-//      duplicates, check insert/delete against the old row (binary search) and
-//      compute the new row length
+//   3. stable radix sort of the keys (signs carried along), so every row of Delta is
+//      contiguous and sorted by column whatever its length
+//   4. one wavefront per row, linear in the row: duplicates, insert/delete checks
+//      against the old row (binary search), per-row prefix counts of insertions and
+//      the new row length
 //   5. exclusive scan of the new lengths -> new row offsets
 //   6. one wavefront per row: merge by ranks (old entries not deleted + inserted
 //      entries), fully parallel inside the row, so hub rows do not serialise.
@@ -17,6 +19,8 @@
 // invalid change list (reported through the status word before anything reads the
 // new graph) can never write out of bounds.
 #include "grest_internal.h"
+
+#include <hipcub/hipcub.hpp>
 
 namespace {
 
@@ -138,36 +142,39 @@ __device__ inline bool change_ok(int32_t i, int32_t j, int8_t s, int64_t n_old, 
   return true;
 }
 
-__global__ void k_delta_count(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
-                              int64_t n_old, int64_t n2, int64_t* cnt, int32_t* status) {
+// keys of the directed entries: (row << shift) | column; an invalid change gets all-ones
+// keys, which sort after every valid one and are never read
+__global__ void k_delta_keys(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc, int64_t n_old,
+                             int64_t n2, int shift, uint64_t* keys, int8_t* vals, int64_t* cnt, int32_t* status) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += stride) {
-    int32_t i = ei[c], j = ej[c];
-    int8_t s = sg[c];
+    const int32_t i = ei[c], j = ej[c];
+    const int8_t s = sg[c];
     if (!change_ok(i, j, s, n_old, n2)) {
       atomicOr(status, ST_BAD_FORMAT);
+      keys[2 * c] = ~0ull;
+      keys[2 * c + 1] = ~0ull;
+      vals[2 * c] = 0;
+      vals[2 * c + 1] = 0;
       continue;
     }
+    keys[2 * c] = ((uint64_t)i << shift) | (uint64_t)j;
+    keys[2 * c + 1] = ((uint64_t)j << shift) | (uint64_t)i;
+    vals[2 * c] = s;
+    vals[2 * c + 1] = s;
     atomicAdd((unsigned long long*)&cnt[i], 1ull);
     atomicAdd((unsigned long long*)&cnt[j], 1ull);
   }
 }
 
-__global__ void k_delta_scatter(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
-                                int64_t n_old, int64_t n2, const int64_t* dptr, int64_t* fill,
-                                int32_t* dcol, int8_t* dsg) {
+// column ids of the sorted valid entries (the first dptr[n2] keys)
+__global__ void k_delta_extract(const uint64_t* keys, int64_t items, const int64_t* total, int shift,
+                                int32_t* dcol) {
+  const int64_t lim = min(items, *total);
+  const uint64_t mask = (1ull << shift) - 1ull;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += stride) {
-    int32_t i = ei[c], j = ej[c];
-    int8_t s = sg[c];
-    if (!change_ok(i, j, s, n_old, n2)) continue;
-    int64_t pi = dptr[i] + (int64_t)atomicAdd((unsigned long long*)&fill[i], 1ull);
-    int64_t pj = dptr[j] + (int64_t)atomicAdd((unsigned long long*)&fill[j], 1ull);
-    dcol[pi] = j;
-    dsg[pi] = s;
-    dcol[pj] = i;
-    dsg[pj] = s;
-  }
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < lim; p += stride)
+    dcol[p] = (int32_t)(keys[p] & mask);
 }
 
 __device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t len, int32_t key) {
@@ -179,10 +186,10 @@ __device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t len, int32_t
   return lo;
 }
 
-// one wavefront per row (grid-stride): rank sort, validation, new length
+// one wavefront per row (grid-stride) over the sorted row: duplicates, validation,
+// dins[p] = insertions before p in the row, new length
 __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, const int64_t* dptr,
-                                                   const int32_t* dcol_tmp, const int8_t* dsg_tmp,
-                                                   int32_t* dcol, int8_t* dsg, int32_t* dins,
+                                                   const int32_t* dcol, const int8_t* dsg, int32_t* dins,
                                                    const int64_t* rp_old, const int32_t* col_old,
                                                    int64_t* newlen, int32_t* status) {
   const int lane = threadIdx.x & (GREST_WAVE - 1);
@@ -199,31 +206,22 @@ __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, co
     }
     int64_t sum_s = 0;
     int32_t bad = 0;
+    int32_t carry = 0;  // insertions in the earlier chunks of the row
     for (int64_t e0 = 0; e0 < len; e0 += GREST_WAVE) {
       const int64_t e = e0 + lane;
       const bool ve = e < len;
-      const int32_t ce = ve ? dcol_tmp[beg + e] : INT32_MAX;
-      const int8_t se = ve ? dsg_tmp[beg + e] : 0;
-      int64_t rank = 0, insb = 0;
-      for (int64_t f0 = 0; f0 < len; f0 += GREST_WAVE) {
-        const int64_t f = f0 + lane;
-        const int32_t cf_l = f < len ? dcol_tmp[beg + f] : INT32_MAX;
-        const int32_t sf_l = f < len ? (int32_t)dsg_tmp[beg + f] : 0;
-        const int nf = (int)((len - f0) < GREST_WAVE ? (len - f0) : GREST_WAVE);
-        for (int q = 0; q < nf; ++q) {
-          const int32_t cf = __shfl(cf_l, q, GREST_WAVE);
-          const int32_t sf = __shfl(sf_l, q, GREST_WAVE);
-          const int64_t fi = f0 + q;
-          const bool less = (cf < ce) || (cf == ce && fi < e);
-          rank += less ? 1 : 0;
-          insb += (less && sf > 0) ? 1 : 0;
-          if (ve && cf == ce && fi != e) bad |= ST_DUPLICATE;
-        }
+      const int32_t ce = ve ? dcol[beg + e] : 0;
+      const int8_t se = ve ? dsg[beg + e] : 0;
+      if (ve && e > 0 && dcol[beg + e - 1] == ce) bad |= ST_DUPLICATE;
+      const int32_t ins = (ve && se > 0) ? 1 : 0;
+      int32_t incl = ins;  // inclusive prefix sum over the lanes
+#pragma unroll
+      for (int o = 1; o < GREST_WAVE; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, GREST_WAVE);
+        if (lane >= o) incl += y;
       }
       if (ve) {
-        dcol[beg + rank] = ce;
-        dsg[beg + rank] = se;
-        dins[beg + rank] = (int32_t)insb;
+        dins[beg + e] = carry + incl - ins;
         sum_s += se;
         if (r < n_old && (int64_t)ce < n_old) {
           const int64_t p = lower_bound_i32(col_old + ob, olen, ce);
@@ -232,8 +230,8 @@ __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, co
           if (!found && se < 0) bad |= ST_DELETE_MISSING;
         }
       }
+      carry += __shfl(incl, GREST_WAVE - 1, GREST_WAVE);
     }
-    // wave reductions
 #pragma unroll
     for (int o = GREST_WAVE / 2; o > 0; o >>= 1) {
       sum_s += __shfl_xor(sum_s, o, GREST_WAVE);
@@ -342,28 +340,51 @@ void launch_scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, 
   k_scan_final<<<(unsigned)nb, BS, 0, s>>>(in, n, tmp, out);
 }
 
-void launch_delta_count(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
-                        int64_t n_old, int64_t n_new, int64_t* cnt, int32_t* status, hipStream_t s) {
-  if (nc <= 0) return;
-  k_delta_count<<<grid_for(nc), BS, 0, s>>>(ei, ej, sg, nc, n_old, n_old + n_new, cnt, status);
+int delta_key_shift(int64_t n2) {
+  int b = 1;
+  while (b < 31 && ((int64_t)1 << b) < n2) ++b;
+  return b;
 }
 
-void launch_delta_scatter(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
-                          int64_t n_old, int64_t n_new, const int64_t* dptr, int64_t* fill,
-                          int32_t* dcol_tmp, int8_t* dsg_tmp, hipStream_t s) {
+void launch_delta_keys(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc, int64_t n_old,
+                       int64_t n_new, int shift, uint64_t* keys, int8_t* vals, int64_t* cnt, int32_t* status,
+                       hipStream_t s) {
   if (nc <= 0) return;
-  k_delta_scatter<<<grid_for(nc), BS, 0, s>>>(ei, ej, sg, nc, n_old, n_old + n_new, dptr, fill,
-                                              dcol_tmp, dsg_tmp);
+  k_delta_keys<<<grid_for(nc), BS, 0, s>>>(ei, ej, sg, nc, n_old, n_old + n_new, shift, keys, vals, cnt, status);
 }
 
-void launch_delta_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol_tmp,
-                       const int8_t* dsg_tmp, int32_t* dcol, int8_t* dsg, int32_t* dins,
-                       const int64_t* rp_old, const int32_t* col_old, int64_t* newlen,
+size_t delta_sort_temp_bytes(int64_t items) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (const int8_t*)nullptr, (int8_t*)nullptr, (int)items, 0, 64);
+  return bytes;
+}
+
+bool launch_delta_sort(const uint64_t* kin, uint64_t* kout, const int8_t* vin, int8_t* vout, int64_t items,
+                       int end_bit, void* tmp, size_t tmp_bytes, hipStream_t s) {
+  if (items <= 0) return true;
+  size_t need = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)items, 0, end_bit, s) !=
+          hipSuccess ||
+      need > tmp_bytes)
+    return false;
+  return hipcub::DeviceRadixSort::SortPairs(tmp, need, kin, kout, vin, vout, (int)items, 0, end_bit, s) ==
+         hipSuccess;
+}
+
+void launch_delta_extract(const uint64_t* keys, int64_t items, const int64_t* total, int shift, int32_t* dcol,
+                          hipStream_t s) {
+  if (items <= 0) return;
+  k_delta_extract<<<grid_for(items), BS, 0, s>>>(keys, items, total, shift, dcol);
+}
+
+void launch_delta_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, const int8_t* dsg,
+                       int32_t* dins, const int64_t* rp_old, const int32_t* col_old, int64_t* newlen,
                        int32_t* status, hipStream_t s) {
   int64_t n2 = n_old + n_new;
   if (n2 <= 0) return;
-  k_delta_rows<<<grid_for(n2 * GREST_WAVE, BS, 2048), BS, 0, s>>>(
-      n_old, n2, dptr, dcol_tmp, dsg_tmp, dcol, dsg, dins, rp_old, col_old, newlen, status);
+  k_delta_rows<<<grid_for(n2 * GREST_WAVE, BS, 2048), BS, 0, s>>>(n_old, n2, dptr, dcol, dsg, dins, rp_old,
+                                                                   col_old, newlen, status);
 }
 
 void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,

@@ -13,8 +13,10 @@ enum : int32_t {
   ST_DUPLICATE = 1 << 1,        // the same pair twice in one update
   ST_INSERT_EXISTING = 1 << 2,  // +1 on a pair that is already an edge
   ST_DELETE_MISSING = 1 << 3,   // -1 on a pair that is not an edge
-  ST_NONFINITE = 1 << 4,        // NaN/Inf met in a small dense factorisation
-  ST_NOT_CONVERGED = 1 << 5,    // the small eigensolver hit its iteration cap
+  ST_NONFINITE = 1 << 4,        // NaN/Inf in the Gram matrix of an orthonormalisation
+  ST_NOT_CONVERGED = 1 << 5,    // inverse iteration of the small eigensolver broke down
+  ST_NONFINITE_H = 1 << 6,      // NaN/Inf in a matrix given to the small eigensolver
+  ST_NUMERIC = ST_NONFINITE | ST_NOT_CONVERGED | ST_NONFINITE_H,
 };
 
 // ------------------------------------------------------------------------------------
@@ -25,14 +27,23 @@ void launch_fill_bytes0(void* p, size_t bytes, hipStream_t s);  // zero fill by 
 // exclusive scan of in[0..n) into out[0..n], out[n] = total; tmp >= scan_tmp_elems(n)
 int64_t scan_tmp_elems(int64_t n);
 void launch_scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
-void launch_delta_count(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
-                        int64_t n_old, int64_t n_new, int64_t* cnt, int32_t* status, hipStream_t s);
-void launch_delta_scatter(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc,
-                          int64_t n_old, int64_t n_new, const int64_t* dptr, int64_t* fill,
-                          int32_t* dcol_tmp, int8_t* dsg_tmp, hipStream_t s);
-void launch_delta_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol_tmp,
-                       const int8_t* dsg_tmp, int32_t* dcol, int8_t* dsg, int32_t* dins,
-                       const int64_t* rp_old, const int32_t* col_old, int64_t* newlen,
+// bits of a node id in the packed (row, column) keys of Delta
+int delta_key_shift(int64_t n2);
+// keys and signs of the two directed entries of every change (invalid: all-ones key and
+// ST_BAD_FORMAT), and the per-row entry counts (cnt zeroed by the caller)
+void launch_delta_keys(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc, int64_t n_old,
+                       int64_t n_new, int shift, uint64_t* keys, int8_t* vals, int64_t* cnt, int32_t* status,
+                       hipStream_t s);
+// stable radix sort of items keys (bits [0, end_bit)) with their signs; false when the
+// temporary storage is too small or the sort cannot be launched
+size_t delta_sort_temp_bytes(int64_t items);
+bool launch_delta_sort(const uint64_t* kin, uint64_t* kout, const int8_t* vin, int8_t* vout, int64_t items,
+                       int end_bit, void* tmp, size_t tmp_bytes, hipStream_t s);
+// column ids of the first *total sorted keys
+void launch_delta_extract(const uint64_t* keys, int64_t items, const int64_t* total, int shift, int32_t* dcol,
+                          hipStream_t s);
+void launch_delta_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, const int8_t* dsg,
+                       int32_t* dins, const int64_t* rp_old, const int32_t* col_old, int64_t* newlen,
                        int32_t* status, hipStream_t s);
 void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
                       const int64_t* dptr, const int32_t* dcol, const int8_t* dsg, const int32_t* dins,

@@ -17,7 +17,8 @@
 //   * k_apply  : Out = beta Out + alpha In M (M: a x b small, in LDS) with FP32 / FP64 MFMA;
 //                the contraction index is permuted inside each 16-wide block (lane group g
 //                feeds columns 4g..4g+3 over four MFMA steps) so every lane reads one
-//                16-byte vector; each wave keeps two 16-row tiles in flight.
+//                16-byte vector; each wave works on one 16-row tile while the next
+//                tile's fragments are loading.
 // Output layouts (checked on the device): f32 and bf16 tiles give lane l, register r the
 // element (4*(l/16)+r, l%16); the f64 tile gives (l/16+4r, l%16).
 #include "grest_internal.h"
@@ -331,25 +332,36 @@ __global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __r
   }
 }
 
-// fixed-order sum of the chunk partials; four lanes per output, combined in order;
-// in symmetric mode the lower tiles are read from their mirror
+// fixed-order sum of the chunk partials: a workgroup owns 64 consecutive outputs, wave w
+// sums the partials c = w, w + 4, ... with four independent accumulators (so that many
+// loads are in flight), and the four wave sums are combined in a fixed order.  In
+// symmetric mode the lower tiles are read from their mirror.
 __global__ void __launch_bounds__(WG) k_tn_reduce(int g, int a, int b, int sym, const double* __restrict__ partial,
                                                   double* __restrict__ C) {
+  __shared__ double red[NW][64];
   const int64_t ab = (int64_t)a * b;
-  const int64_t idx = (int64_t)blockIdx.x * (WG / 4) + (threadIdx.x >> 2);
-  const int part = threadIdx.x & 3;
-  double s = 0.0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (idx < ab) {
-    const int i = (int)(idx / b), j = (int)(idx % b);
     int64_t src = idx;
-    if (sym && (i >> 4) > (j >> 4)) src = (int64_t)j * b + i;
-    for (int c = part; c < g; c += 4) s += partial[(size_t)c * ab + src];
+    if (sym) {
+      const int i = (int)(idx / b), j = (int)(idx % b);
+      if ((i >> 4) > (j >> 4)) src = (int64_t)j * b + i;
+    }
+    const double* p = partial + src;
+    int c = w;
+    for (; c + 3 * NW < g; c += 4 * NW) {
+      s0 += p[(size_t)c * ab];
+      s1 += p[(size_t)(c + NW) * ab];
+      s2 += p[(size_t)(c + 2 * NW) * ab];
+      s3 += p[(size_t)(c + 3 * NW) * ab];
+    }
+    for (; c < g; c += NW) s0 += p[(size_t)c * ab];
   }
-  const double s1 = __shfl_xor(s, 1, 4);
-  const double lo = (part & 1) ? s1 + s : s + s1;
-  const double s2 = __shfl_xor(lo, 2, 4);
-  const double tot = (part & 2) ? s2 + lo : lo + s2;
-  if (idx < ab && part == 0) C[idx] = tot;
+  red[w][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (w == 0 && idx < ab) C[idx] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // ---------------------------------------------------------------------------------
@@ -409,35 +421,38 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t ntile = (n + 15) >> 4;
-  const int64_t stride = (int64_t)gridDim.x * NW * 2;
-  for (int64_t tile = ((int64_t)blockIdx.x * NW + wid) * 2; tile < ntile; tile += stride) {
-    Tc fin[2][8][4];
+  const int64_t stride = (int64_t)gridDim.x * NW;
+  // one 16-row tile at a time; the next tile's fragments are in flight during its MFMAs
+  int64_t tile = (int64_t)blockIdx.x * NW + wid;
+  Tc nxt[8][4];
+  if (tile < ntile) load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, tile * 16 + c16, n, KB, g, nxt);
+  for (; tile < ntile; tile += stride) {
+    Tc fin[8][4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-      load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, (tile + u) * 16 + c16, n, KB, g, fin[u]);
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) fin[kb][m] = nxt[kb][m];
+    if (tile + stride < ntile)
+      load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, (tile + stride) * 16 + c16, n, KB, g, nxt);
+    const int64_t row0 = tile * 16;
     for (int jt = 0; jt < TB; ++jt) {
+      typename M::acc_t acc{0, 0, 0, 0};
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int64_t row0 = (tile + u) * 16;
-        if (row0 >= n) continue;
-        typename M::acc_t acc{0, 0, 0, 0};
+      for (int kb = 0; kb < 8; ++kb) {
+        if (kb < KB) {
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) {
-          if (kb < KB) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-              acc = M::run(fin[u][kb][m], sM[(kb * 16 + 4 * g + m) * bp + jt * 16 + c16], acc);
-          }
+          for (int m = 0; m < 4; ++m)
+            acc = M::run(fin[kb][m], sM[(kb * 16 + 4 * g + m) * bp + jt * 16 + c16], acc);
         }
+      }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t orow = row0 + M::row(lane, r);
-          const int ocol = jt * 16 + c16;
-          if (orow < n && ocol < b) {
-            Tc v = acc[r];
-            if (beta != 0.0) v += (Tc)beta * (Tc)Out[orow * ldout + ocol];
-            Out[orow * ldout + ocol] = (T)v;
-          }
+      for (int r = 0; r < 4; ++r) {
+        const int64_t orow = row0 + M::row(lane, r);
+        const int ocol = jt * 16 + c16;
+        if (orow < n && ocol < b) {
+          Tc v = acc[r];
+          if (beta != 0.0) v += (Tc)beta * (Tc)Out[orow * ldout + ocol];
+          Out[orow * ldout + ocol] = (T)v;
         }
       }
     }
@@ -446,7 +461,7 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
 
 inline int apply_grid(int64_t n) {
   int64_t tiles = (n + 15) / 16;
-  int64_t g = (tiles + 2 * NW - 1) / (2 * NW);
+  int64_t g = (tiles + 4 * NW - 1) / (4 * NW);  // about four tiles per wave
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   return (int)g;
@@ -521,7 +536,7 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
     tnw_dispatch<T, float>(n, g, rpc, A, lda, a, B, ldb, b, sym, partial, s);
   }
   const int64_t ab = (int64_t)a * b;
-  k_tn_reduce<<<(unsigned)((ab + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, a, b, sym ? 1 : 0, partial, C);
+  k_tn_reduce<<<(unsigned)((ab + 63) / 64), WG, 0, s>>>(g, a, b, sym ? 1 : 0, partial, C);
 }
 
 // one projection round: C = X^T W and G = W^T W (upper tiles; the reduce mirrors them)
@@ -557,8 +572,8 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
   else if (TX == 1 && TWt == 2) pip_launch<T, Tcx, 1, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else if (TX == 1 && TWt == 1) pip_launch<T, Tcx, 1, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else return false;
-  k_tn_reduce<<<(unsigned)(((int64_t)kx * w + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, kx, w, 0, partC, C);
-  k_tn_reduce<<<(unsigned)(((int64_t)w * w + WG / 4 - 1) / (WG / 4)), WG, 0, s>>>(g, w, w, 1, partG, G);
+  k_tn_reduce<<<(unsigned)(((int64_t)kx * w + 63) / 64), WG, 0, s>>>(g, kx, w, 0, partC, C);
+  k_tn_reduce<<<(unsigned)(((int64_t)w * w + 63) / 64), WG, 0, s>>>(g, w, w, 1, partG, G);
   return true;
 }
 

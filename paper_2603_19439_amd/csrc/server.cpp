@@ -85,15 +85,17 @@ void worker(grest_server* sv, int lane) {
       st = sv->graphs[rq.gid].st;  // read under the lock: attach may grow the table
     }
     const int64_t nc = (int64_t)rq.ei.size();
-    grest_status rc = grest_update(st, rq.n_new, nc, nc ? rq.ei.data() : nullptr, nc ? rq.ej.data() : nullptr,
-                                   nc ? rq.sg.data() : nullptr, rq.has_omega ? rq.omega.data() : nullptr,
-                                   GREST_HOST);
-    const grest_status rs = grest_sync(st);  // waits for the update and reads its status
-    if (rc == GREST_OK) rc = rs;
+    const grest_status ru = grest_update(st, rq.n_new, nc, nc ? rq.ei.data() : nullptr,
+                                         nc ? rq.ej.data() : nullptr, nc ? rq.sg.data() : nullptr,
+                                         rq.has_omega ? rq.omega.data() : nullptr, GREST_HOST);
+    // waits for the update and reads its deferred numerical status (the update has
+    // committed even when that status is not OK)
+    const grest_status rs = grest_sync(st);
+    const grest_status rc = ru != GREST_OK ? ru : rs;
     const int64_t t_done = now_ns();
     {
       std::lock_guard<std::mutex> lk(sv->mu);
-      if (rc != GREST_OK) sv->graphs[rq.gid].n_proj -= rq.n_new;  // the graph did not grow
+      if (ru != GREST_OK) sv->graphs[rq.gid].n_proj -= rq.n_new;  // rejected: the graph did not grow
       sv->done.push_back(Done{rq.tag, (int32_t)rc, rq.t_submit, t_done});
       --sv->pending;
     }

@@ -35,6 +35,11 @@ __device__ long long g_phase_clk[64];
 extern "C" int grest_debug_phase_clocks(long long* out, int n) {
   return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_clk), sizeof(long long) * (n < 64 ? n : 64));
 }
+// the last inverse-iteration breakdown: [n, cur, lam, tnorm, nrm2, it, nmem, which, dg[128], od[128], ev[128]]
+__device__ double g_dbg_eig[8 + 3 * 128];
+extern "C" int grest_debug_eig(double* out) {
+  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_dbg_eig), sizeof(double) * (8 + 3 * 128));
+}
 // per-section cycle accounting inside a loop (threads 0 and 64 only)
 #define SECT_DECL long long sect_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sect_t = clock64();
 #define SECT(i)                                  \
@@ -183,18 +188,24 @@ __device__ __forceinline__ bool chosen_bit(uint64_t c0, uint64_t c1, int j) {
   return j < 64 ? ((c0 >> j) & 1ull) : ((c1 >> (j - 64)) & 1ull);
 }
 
-template <int M>
-__global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const double* Cp, int kc, double tol,
+template <int M, bool CL>
+__global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const double* Cg, int kc, double tol,
                                               double* Mout, int32_t* rank_out, int32_t* status) {
   constexpr int CC = M / GREST_WAVE, RW = M / NW, LP = M + 1;
   __shared__ double Rrow[M * LP];  // pivot rows by step (pitch M + 1); later X = R^{-1}
   __shared__ int perm[M], iperm[M];
   __shared__ double rdg[M];
+  extern __shared__ double cdyn[];  // with CL: the coefficient block C (kc x m)
   double* Mblk = Mout + (size_t)kc * m;  // the m x m block of the output
   const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid / GREST_WAVE);
 
   for (int j = tid; j < M; j += EB) iperm[j] = -1;
+  if (CL) {
+    for (int idx = tid; idx < kc * m; idx += EB) cdyn[idx] = Cg[idx];
+    __syncthreads();
+  }
+  const double* Cp = CL ? cdyn : Cg;
   // S = sym(G) - C^T C in registers and its diagonal in every wave
   double S[RW][CC], d[CC];
   int bad = 0;
@@ -396,7 +407,7 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
       A[r][c] = h;
     }
   }
-  if (bad) atomicOr(status, ST_NONFINITE);
+  if (bad) atomicOr(status, ST_NONFINITE_H);
   if (n >= 1) column_to_lds<RW, C>(A, 0, wv, n, colb[0]);
   __syncthreads();
   PHASE_MARK(0);
@@ -710,6 +721,8 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
       }
       const double pa = fabs(a) < tiny ? (a < 0.0 ? -tiny : tiny) : a;
       u0i[n - 1] = recip(pa);
+      u1[n - 1] = 0.0;  // read (times zero) by the back-substitution
+      u2[n - 1] = 0.0;
     }
     for (int i = lane; i < n; i += GREST_WAVE) yv[i] = hash_unit(i, cslot + 1);
     __syncthreads();
@@ -723,9 +736,15 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
           x = fma(-lm[i], x, xn);
         }
         yv[n - 1] = x;
-        double x1 = 0.0, x2 = 0.0;  // U^{-1}
+        double x1 = 0.0, x2 = 0.0;  // U^{-1}; rescaled when it grows (tiny pivots)
         for (int i = n - 1; i >= 0; --i) {
-          const double v = fma(-u2[i], x2, fma(-u1[i], x1, yv[i])) * u0i[i];
+          double v = fma(-u2[i], x2, fma(-u1[i], x1, yv[i])) * u0i[i];
+          if (fabs(v) > 1e150) {  // scale the whole system: solved part and the rest
+            for (int q = 0; q < n; ++q) yv[q] *= 1e-150;
+            x1 *= 1e-150;
+            x2 *= 1e-150;
+            v = fma(-u2[i], x2, fma(-u1[i], x1, yv[i])) * u0i[i];
+          }
           yv[i] = v;
           x2 = x1;
           x1 = v;
@@ -747,6 +766,13 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
       double s = (nrm2 > 0.0 && isfinite(nrm2)) ? 1.0 / sqrt(nrm2) : 0.0;
       if (s == 0.0) {  // breakdown: fall back to the unit vector of the index
         if (lane == 0) atomicOr(status, ST_NOT_CONVERGED);
+#ifdef GREST_PHASE_CLOCKS
+        if (lane == 0) {
+          g_dbg_eig[0] = n; g_dbg_eig[1] = cur; g_dbg_eig[2] = lam; g_dbg_eig[3] = tnorm;
+          g_dbg_eig[4] = nrm2; g_dbg_eig[5] = it; g_dbg_eig[6] = nmem; g_dbg_eig[7] = which;
+          for (int q = 0; q < n; ++q) { g_dbg_eig[8 + q] = sdg[q]; g_dbg_eig[136 + q] = sod[q]; g_dbg_eig[264 + q] = sev[q]; }
+        }
+#endif
         y0 = (lane == cur) ? 1.0 : 0.0;
         y1 = (lane + GREST_WAVE == cur) ? 1.0 : 0.0;
         s = 1.0;
@@ -824,11 +850,28 @@ int64_t eig_work_elems(int d) { return d <= MAXN ? (int64_t)W_END : 0; }
 
 int64_t pchol_work_elems(int, int) { return 0; }
 
+// the coefficient block goes to LDS when it fits beside the static arrays
+template <int M>
+void pchol_launch(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
+                  int32_t* status, hipStream_t s) {
+  constexpr size_t kStatic = (size_t)M * (M + 1) * 8 + (size_t)M * 16;
+  constexpr size_t kDynMax = 160 * 1024 - kStatic - 1024;
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)k_pchol<M, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kDynMax);
+    return true;
+  }();
+  (void)attr;
+  const size_t dyn = (size_t)kc * m * sizeof(double);
+  if (kc > 0 && dyn <= kDynMax) k_pchol<M, true><<<1, EB, dyn, s>>>(m, G, C, kc, tol, Mout, rank, status);
+  else k_pchol<M, false><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
+}
+
 void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
                   int32_t* status, double*, hipStream_t s) {
   if (!C) kc = 0;
-  if (m <= 64) k_pchol<64><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
-  else k_pchol<128><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
+  if (m <= 64) pchol_launch<64>(m, G, C, kc, tol, Mout, rank, status, s);
+  else pchol_launch<128>(m, G, C, kc, tol, Mout, rank, status, s);
 }
 
 bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which, int kk,

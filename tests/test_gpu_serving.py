@@ -170,3 +170,24 @@ def test_admission_limits():
     st.update_delta(d1, _omega(wl, 0, 1, d1, k))
     st.sync()
     st.close()
+
+
+@pytest.mark.parametrize("graph_id,requests", [(16, 4), (14, 20)])
+def test_serving_graph_updates_report_no_numerical_status(graph_id, requests):
+    """Graphs of the serving mix on which the small eigensolver once read an unset entry
+    of its LU factor (regression): every update must finish with status OK."""
+    sg = W.serving_graph(graph_id, requests)
+    wl = sg.workload
+    banner(f"serving graph {graph_id} ({sg.family}, n0={wl.n0}, k={sg.k}) for {requests} requests")
+    n_fin = wl.n0 + sum(d.n_new for d in wl.deltas) + 1
+    nnz = int(wl.col0.size + 2 * sum(d.n_changes for d in wl.deltas) + 1024)
+    st = G.State(wl.rowptr0, wl.col0, k=sg.k, variant="rsvd", precision="mixed", L=sg.k, P=sg.k,
+                 node_capacity=n_fin, nnz_capacity=nnz)
+    st.init_pairs(iterations=20, seed=graph_id)
+    for t, d in enumerate(wl.deltas):
+        st.update_delta(d, W.omega(4, graph_id, t + 1, d.n_new, 2 * sg.k) if d.n_new > 0 else None)
+        st.sync()  # raises on a non-OK status
+    vals, X = st.get()
+    assert np.all(np.isfinite(vals)) and np.all(np.isfinite(X))
+    assert M.orthonormality(X) <= 1e-5
+    st.close()
