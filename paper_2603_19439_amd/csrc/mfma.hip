@@ -332,13 +332,16 @@ __global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __r
   }
 }
 
-// fixed-order sum of the chunk partials: a workgroup owns 64 consecutive outputs, wave w
-// sums the partials c = w, w + 4, ... with four independent accumulators (so that many
-// loads are in flight), and the four wave sums are combined in a fixed order.  In
-// symmetric mode the lower tiles are read from their mirror.
-__global__ void __launch_bounds__(WG) k_tn_reduce(int g, int a, int b, int sym, const double* __restrict__ partial,
-                                                  double* __restrict__ C) {
-  __shared__ double red[NW][64];
+// fixed-order sum of the chunk partials: a workgroup of RWV waves owns 64 consecutive
+// outputs, wave w sums the partials c = w, w + RWV, ... with four independent
+// accumulators (many loads in flight), and the wave sums are combined in a fixed order.
+// In symmetric mode the lower tiles are read from their mirror.
+constexpr int RWV = 16;
+
+__global__ void __launch_bounds__(RWV * 64) k_tn_reduce(int g, int a, int b, int sym,
+                                                        const double* __restrict__ partial,
+                                                        double* __restrict__ C) {
+  __shared__ double red[RWV][64];
   const int64_t ab = (int64_t)a * b;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
@@ -351,17 +354,22 @@ __global__ void __launch_bounds__(WG) k_tn_reduce(int g, int a, int b, int sym, 
     }
     const double* p = partial + src;
     int c = w;
-    for (; c + 3 * NW < g; c += 4 * NW) {
+    for (; c + 3 * RWV < g; c += 4 * RWV) {
       s0 += p[(size_t)c * ab];
-      s1 += p[(size_t)(c + NW) * ab];
-      s2 += p[(size_t)(c + 2 * NW) * ab];
-      s3 += p[(size_t)(c + 3 * NW) * ab];
+      s1 += p[(size_t)(c + RWV) * ab];
+      s2 += p[(size_t)(c + 2 * RWV) * ab];
+      s3 += p[(size_t)(c + 3 * RWV) * ab];
     }
-    for (; c < g; c += NW) s0 += p[(size_t)c * ab];
+    for (; c < g; c += RWV) s0 += p[(size_t)c * ab];
   }
   red[w][lane] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (w == 0 && idx < ab) C[idx] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (w == 0 && idx < ab) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < RWV; ++q) t += red[q][lane];
+    C[idx] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -536,7 +544,7 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
     tnw_dispatch<T, float>(n, g, rpc, A, lda, a, B, ldb, b, sym, partial, s);
   }
   const int64_t ab = (int64_t)a * b;
-  k_tn_reduce<<<(unsigned)((ab + 63) / 64), WG, 0, s>>>(g, a, b, sym ? 1 : 0, partial, C);
+  k_tn_reduce<<<(unsigned)((ab + 63) / 64), RWV * 64, 0, s>>>(g, a, b, sym ? 1 : 0, partial, C);
 }
 
 // one projection round: C = X^T W and G = W^T W (upper tiles; the reduce mirrors them)
@@ -572,8 +580,8 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
   else if (TX == 1 && TWt == 2) pip_launch<T, Tcx, 1, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else if (TX == 1 && TWt == 1) pip_launch<T, Tcx, 1, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else return false;
-  k_tn_reduce<<<(unsigned)(((int64_t)kx * w + 63) / 64), WG, 0, s>>>(g, kx, w, 0, partC, C);
-  k_tn_reduce<<<(unsigned)(((int64_t)w * w + 63) / 64), WG, 0, s>>>(g, w, w, 1, partG, G);
+  k_tn_reduce<<<(unsigned)(((int64_t)kx * w + 63) / 64), RWV * 64, 0, s>>>(g, kx, w, 0, partC, C);
+  k_tn_reduce<<<(unsigned)(((int64_t)w * w + 63) / 64), RWV * 64, 0, s>>>(g, w, w, 1, partG, G);
   return true;
 }
 

@@ -68,7 +68,7 @@ extern "C" int grest_debug_eig(double* out) {
 
 namespace {
 
-constexpr int EB = 256;    // threads of the one-workgroup kernels
+constexpr int EB = 1024;   // threads of the one-workgroup kernels (four waves per SIMD)
 constexpr int NW = EB / GREST_WAVE;
 constexpr int MAXN = 128;  // largest order
 constexpr double EPS = 2.220446049250313e-16;
@@ -194,12 +194,13 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
   constexpr int CC = M / GREST_WAVE, RW = M / NW, LP = M + 1;
   __shared__ double Rrow[M * LP];  // pivot rows by step (pitch M + 1); later X = R^{-1}
   __shared__ int perm[M], iperm[M];
-  __shared__ double rdg[M];
+  __shared__ double rdg[M], rdi[M];
   extern __shared__ double cdyn[];  // with CL: the coefficient block C (kc x m)
   double* Mblk = Mout + (size_t)kc * m;  // the m x m block of the output
   const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid / GREST_WAVE);
 
+  PHASE_MARK(9);
   for (int j = tid; j < M; j += EB) iperm[j] = -1;
   if (CL) {
     for (int idx = tid; idx < kc * m; idx += EB) cdyn[idx] = Cg[idx];
@@ -285,48 +286,53 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
     r = k + 1;
   }
   PHASE_MARK(11);
-  // Y = X^T with X = R^{-1}, R[a][b] = Rrow[a][perm[b]] / rdg[a] (upper triangular in
-  // pivot order).  Row j of Y is column j of X, an independent solve: for i descending,
-  // X[i][j] /= R[i][i], then X[a][j] -= R[a][i] X[i][j] for a < i.
-  double Y[RW][CC];
+  // X = R^{-1}, R[a][b] = Rrow[a][perm[b]] / rdg[a] (upper triangular in pivot order).
+  // Column j of X is an independent solve: for i descending, X[i][j] /= R[i][i], then
+  // X[a][j] -= R[a][i] X[i][j] for a < i.
+  for (int a = tid; a < M; a += EB) rdi[a] = a < r ? 1.0 / rdg[a] : 0.0;
+  __syncthreads();
+  {
+    // Y = X^T in the distributed layout: row j of Y is column j of X, an independent solve
+    double Y[RW][CC];
 #pragma unroll
-  for (int q = 0; q < RW; ++q)
+    for (int q = 0; q < RW; ++q)
 #pragma unroll
-    for (int c = 0; c < CC; ++c) Y[q][c] = (wv + NW * q == lane + GREST_WAVE * c && wv + NW * q < r) ? 1.0 : 0.0;
-  for (int i = r - 1; i >= 0; --i) {
-    const int pi = perm[i], li = i & (GREST_WAVE - 1), ci = i >> 6;
-    const double s = 1.0 / rdg[i];
-    double ra[CC];
+      for (int c = 0; c < CC; ++c) Y[q][c] = (wv + NW * q == lane + GREST_WAVE * c && wv + NW * q < r) ? 1.0 : 0.0;
+    for (int i = r - 1; i >= 0; --i) {
+      const int pi = perm[i], li = i & (GREST_WAVE - 1), ci = i >> 6;
+      const double s = rdi[i];
+      double ra[CC];
 #pragma unroll
-    for (int c = 0; c < CC; ++c) {
-      const int a = lane + GREST_WAVE * c;
-      ra[c] = a < i ? Rrow[a * LP + pi] / rdg[a] : 0.0;
+      for (int c = 0; c < CC; ++c) {
+        const int a = lane + GREST_WAVE * c;
+        ra[c] = a < i ? Rrow[a * LP + pi] * rdi[a] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < RW; ++q) {
+#pragma unroll
+        for (int c = 0; c < CC; ++c) Y[q][c] = (c == ci && lane == li) ? Y[q][c] * s : Y[q][c];
+        const double yi = vec_elem<CC>(Y[q], i);
+#pragma unroll
+        for (int c = 0; c < CC; ++c) Y[q][c] = fma(-ra[c], yi, Y[q][c]);
+      }
     }
+    __syncthreads();  // every read of Rrow is done; it now receives X
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
+      const int j = wv + NW * q;
 #pragma unroll
-      for (int c = 0; c < CC; ++c) Y[q][c] = (c == ci && lane == li) ? Y[q][c] * s : Y[q][c];
-      const double yi = vec_elem<CC>(Y[q], i);
-#pragma unroll
-      for (int c = 0; c < CC; ++c) Y[q][c] = fma(-ra[c], yi, Y[q][c]);
+      for (int c = 0; c < CC; ++c) {
+        const int a = lane + GREST_WAVE * c;
+        if (a < r && j < m) {
+          Rrow[a * LP + j] = Y[q][c];
+          Mblk[(size_t)perm[a] * m + j] = Y[q][c];  // M[perm[a]][j] = X[a][j]
+        }
+      }
+      if (j < m && iperm[j] < 0)  // rows of dropped columns are zero
+        for (int t = lane; t < m; t += GREST_WAVE) Mblk[(size_t)j * m + t] = 0.0;
     }
   }
   PHASE_MARK(13);
-  __syncthreads();  // every read of Rrow is done; it now receives X
-#pragma unroll
-  for (int q = 0; q < RW; ++q) {
-    const int j = wv + NW * q;
-#pragma unroll
-    for (int c = 0; c < CC; ++c) {
-      const int a = lane + GREST_WAVE * c;
-      if (a < r && j < m) {
-        Rrow[a * LP + j] = Y[q][c];
-        Mblk[(size_t)perm[a] * m + j] = Y[q][c];  // M[perm[a]][j] = X[a][j]
-      }
-    }
-    if (j < m && iperm[j] < 0)  // rows of dropped columns are zero
-      for (int t = lane; t < m; t += GREST_WAVE) Mblk[(size_t)j * m + t] = 0.0;
-  }
   __syncthreads();
   // -C M = -(C P) X: wave w takes rows l = l0 + 8 w + t of C (t < 8), lanes the columns;
   // X[a][j] is zero for a > j, so the sum runs over every a < r
@@ -371,7 +377,7 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
 //   be published); v is zero outside rows k+1 .. n-1, so the full-width updates below
 //   leave the rest of A unchanged;
 //   p = beta A v: each wave sums over its rows (symmetry turns row sums into column
-//   sums), the four partial vectors meet in LDS;
+//   sums), the per-wave partial vectors meet in LDS and are summed in a fixed order;
 //   w = p - (beta p^T v / 2) v;  A <- A - v w^T - w v^T in registers;
 //   column k+1 of the updated A goes to LDS for the next iteration.
 // Two barriers per iteration.
@@ -379,7 +385,7 @@ template <int M>
 __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int32_t* rank_p, const double* H,
                                                 double* work, int32_t* status) {
   constexpr int C = M / GREST_WAVE, RW = M / NW;
-  __shared__ double pw4[NW][M];
+  __shared__ double pwv[NW][M];
   __shared__ double colb[2][M];
   __shared__ double vwb[NW][2][M];  // each wave's own copy of v and w
   __shared__ double sdg[M], sod[M], shb[M];
@@ -447,8 +453,6 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
       if (C == 1) R[(size_t)k * MAXN + lane + GREST_WAVE] = 0.0;
       if (lane == 0) { sdg[k] = col[k]; sod[k] = ek; shb[k] = beta; }
     }
-    // column blocks entirely inside the finished part (j <= k) take no part
-    const int c0 = (k + 1) / GREST_WAVE;
     double vr[RW];
     if (beta != 0.0) {
 #pragma unroll
@@ -459,16 +463,13 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
       double pp[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) pp[c] = 0.0;
+      // rows and columns outside the active block have v = 0: no branches needed
 #pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        if (wv + NW * r > k) {
+      for (int r = 0; r < RW; ++r)
 #pragma unroll
-          for (int c = 0; c < C; ++c)
-            if (c >= c0) pp[c] = fma(A[r][c], vr[r], pp[c]);
-        }
-      }
+        for (int c = 0; c < C; ++c) pp[c] = fma(A[r][c], vr[r], pp[c]);
 #pragma unroll
-      for (int c = 0; c < C; ++c) pw4[wv][lane + GREST_WAVE * c] = pp[c];
+      for (int c = 0; c < C; ++c) pwv[wv][lane + GREST_WAVE * c] = pp[c];
     }
     SECT(1);
     __syncthreads();
@@ -479,7 +480,10 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const int j = lane + GREST_WAVE * c;
-        p[c] = (j > k && j < n) ? beta * ((pw4[0][j] + pw4[1][j]) + (pw4[2][j] + pw4[3][j])) : 0.0;
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sum += pwv[q][j];
+        p[c] = (j > k && j < n) ? beta * sum : 0.0;
         pv = fma(p[c], v[c], pv);
       }
       const double Kc = 0.5 * beta * wave_sum_d(pv);
@@ -495,13 +499,9 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
       for (int r = 0; r < RW; ++r) wr[r] = vwb[wv][1][wv + NW * r];
       // v and w vanish outside rows/cols k+1 .. n-1, so the update leaves the rest as is
 #pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        if (wv + NW * r > k) {
+      for (int r = 0; r < RW; ++r)
 #pragma unroll
-          for (int c = 0; c < C; ++c)
-            if (c >= c0) A[r][c] = fma(-vr[r], w[c], fma(-wr[r], v[c], A[r][c]));
-        }
-      }
+        for (int c = 0; c < C; ++c) A[r][c] = fma(-vr[r], w[c], fma(-wr[r], v[c], A[r][c]));
     }
     SECT(4);
     column_to_lds<RW, C>(A, k + 1, wv, n, colb[(k + 1) & 1]);
@@ -854,7 +854,7 @@ int64_t pchol_work_elems(int, int) { return 0; }
 template <int M>
 void pchol_launch(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
                   int32_t* status, hipStream_t s) {
-  constexpr size_t kStatic = (size_t)M * (M + 1) * 8 + (size_t)M * 16;
+  constexpr size_t kStatic = (size_t)M * (M + 1) * 8 + (size_t)M * 24;
   constexpr size_t kDynMax = 160 * 1024 - kStatic - 1024;
   static const bool attr = [] {
     (void)hipFuncSetAttribute((const void*)k_pchol<M, true>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -245,7 +245,9 @@ def _sbm_edges_by_counts(rng, sizes, offsets, p_in, p_out):
 
 def sbm_large(n0=1_000_000, blocks=32, dirichlet=2.0, deg_in=16.0, deg_out=4.0, steps=10,
               new_per_step=10_000, new_deg=4.0, old_insertions=10_000, intra_frac=0.8,
-              cfg_id=3, graph_id=0) -> Workload:
+              cfg_id=3, graph_id=0, permute=True) -> Workload:
+    """O(m) SBM; ``permute=False`` keeps the initial ids sorted by block (a locality
+    reference: the same graph with neighbours close in id space)."""
     rng = rng_for(cfg_id, graph_id, 0, _GRAPH)
     pi = rng.dirichlet(np.full(blocks, dirichlet))
     sizes = rng.multinomial(n0, pi).astype(np.int64)
@@ -256,6 +258,8 @@ def sbm_large(n0=1_000_000, blocks=32, dirichlet=2.0, deg_in=16.0, deg_out=4.0, 
     a, b = _sbm_edges_by_counts(rng, sizes, offsets, p_in, p_out)
     lab_sorted = np.repeat(np.arange(blocks), sizes)
     perm = rng.permutation(n0)
+    if not permute:
+        perm = np.arange(n0)
     labels = np.empty(n0, dtype=np.int64)
     labels[perm] = lab_sorted
     keys = _dedupe_pairs(perm[a], perm[b])
