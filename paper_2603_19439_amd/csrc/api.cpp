@@ -46,8 +46,8 @@ void set_err(const char* what, hipError_t e) {
 constexpr int32_t VALIDATION_BITS = ST_BAD_FORMAT | ST_DUPLICATE | ST_INSERT_EXISTING | ST_DELETE_MISSING;
 
 struct Pinned {
-  int32_t status;
-  int32_t pad;
+  int32_t status;   // numerical status of the last update (copied at its end)
+  int32_t vstatus;  // validation status of the update in progress
   int64_t m_new;
   int64_t maxdeg;
   int32_t ranks[8];
@@ -113,15 +113,19 @@ struct grest_state {
   int64_t* maxdeg = nullptr;
   Pinned* pin = nullptr;
   double* theta_pin = nullptr;
+  hipEvent_t vev = nullptr;  // recorded once the validation result is on its way to the host
   int32_t deferred = 0;
   int64_t partial_elems = 0;
 
-  // optional stage timing with HIP events on the state's stream
+  // optional stage timing with HIP events on the state's stream; two sets of events, used
+  // by alternate updates, so that an update's events are read (at the next update's
+  // validation wait, when they have completed) before they are recorded again
   static constexpr int NSTAGE = 8;
   bool prof = false;
-  bool prof_pending = false;
-  hipEvent_t pev[NSTAGE + 1] = {};
-  hipEvent_t kev[2] = {};  // around the (op Z) product alone
+  int pslot = 0;
+  bool prof_pending[2] = {false, false};
+  hipEvent_t pev[2][NSTAGE + 1] = {};
+  hipEvent_t kev[2][2] = {};  // around the (op Z) product alone
   double stage_ms[NSTAGE] = {};
   double spmm_ms = 0.0;
   int64_t prof_updates = 0;
@@ -131,20 +135,30 @@ struct grest_state {
 namespace {
 
 void mark(grest_state* st, int i) {
-  if (st->marking) (void)hipEventRecord(st->pev[i], st->stream);
+  if (st->marking) (void)hipEventRecord(st->pev[st->pslot][i], st->stream);
 }
 
-// add the stage times of the last completed update (its events have completed)
-void prof_collect(grest_state* st) {
-  if (!st->prof_pending) return;
+void mark_spmm(grest_state* st, int i) {
+  if (st->marking) (void)hipEventRecord(st->kev[st->pslot][i], st->stream);
+}
+
+// add the stage times of the update that used event set `slot` (its events have completed)
+void prof_collect_slot(grest_state* st, int slot) {
+  if (!st->prof_pending[slot]) return;
   for (int i = 0; i < grest_state::NSTAGE; ++i) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, st->pev[i], st->pev[i + 1]) == hipSuccess) st->stage_ms[i] += ms;
+    if (hipEventElapsedTime(&ms, st->pev[slot][i], st->pev[slot][i + 1]) == hipSuccess) st->stage_ms[i] += ms;
   }
   float ms = 0.f;
-  if (hipEventElapsedTime(&ms, st->kev[0], st->kev[1]) == hipSuccess) st->spmm_ms += ms;
+  if (hipEventElapsedTime(&ms, st->kev[slot][0], st->kev[slot][1]) == hipSuccess) st->spmm_ms += ms;
   st->prof_updates += 1;
-  st->prof_pending = false;
+  st->prof_pending[slot] = false;
+}
+
+// after a full wait on the stream
+void prof_collect(grest_state* st) {
+  prof_collect_slot(st, st->pslot ^ 1);
+  prof_collect_slot(st, st->pslot);
 }
 
 }  // namespace
@@ -180,6 +194,7 @@ grest_status alloc_edge_arrays(grest_state* st, int64_t cap_m) {
 }
 
 grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
+  HIPCHK(hipStreamSynchronize(st->stream));  // queued work may still read the old arrays
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
   dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
@@ -199,6 +214,7 @@ grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
 }
 
 grest_status alloc_sketch_arrays(grest_state* st, int64_t cap_s) {
+  HIPCHK(hipStreamSynchronize(st->stream));  // queued work may still read the old arrays
   dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   if (st->variant != GREST_RSVD) { st->cap_s = cap_s; return GREST_OK; }
   CHK(dalloc((char**)&st->bt, (size_t)cap_s * st->Ls * st->es));
@@ -239,6 +255,8 @@ void free_all(grest_state* st) {
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
   dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
   dfree(st->ranks); dfree(st->status); dfree(st->maxdeg);
+  if (st->vev) (void)hipEventDestroy(st->vev);
+  st->vev = nullptr;
   if (st->pin) (void)hipHostFree(st->pin);
   if (st->theta_pin) (void)hipHostFree(st->theta_pin);
   st->pin = nullptr;
@@ -345,9 +363,9 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
                            int base, int32_t* rank_slot) {
   Blocks<T> b = blocks<T>(st);
   // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
-  if (st->marking) HIPCHK(hipEventRecord(st->kev[0], st->stream));
+  mark_spmm(st, 0);
   launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc, st->ldz, n2, st->D, b.aux, st->D, st->stream);
-  if (st->marking) HIPCHK(hipEventRecord(st->kev[1], st->stream));
+  mark_spmm(st, 1);
   mark(st, 5);
   // H = Z^T (op Z)
   if constexpr (sizeof(T) == 4) {
@@ -417,34 +435,32 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
                    st->col[gn], st->cap_m, s);
   if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, st->maxdeg, s);
   else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], st->maxdeg, s);
-  HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&st->pin->vstatus, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->maxdeg, st->maxdeg, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (st->pin->status & VALIDATION_BITS) {
-    st->marking = false;
-    snprintf(g_last_error, sizeof(g_last_error), "change list rejected (status bits 0x%x)", st->pin->status);
-    return GREST_EINVAL;
-  }
-  const int64_t m_new = st->pin->m_new;
+  HIPCHK(hipEventRecord(st->vev, s));
 
+  // The host needs the validation result before it commits.  Work that reads only the
+  // update's own arrays (whose column ids are in range whatever the validation finds,
+  // since out-of-range entries never enter them) and the current basis, and writes only
+  // scratch blocks, is queued before the host waits for the validation event, so the
+  // device keeps running meanwhile; a rejected update leaves nothing but scratch behind.
+  // What reads the merged graph (the normalised Laplacian's Delta Xbar and the Rayleigh-
+  // Ritz product) is queued after the wait.
   Blocks<T> b = blocks<T>(st);
   const T* sc_new = (const T*)st->sc[gn];
+  const bool nlap = st->op == GREST_OP_NLAP;
   // ---- pad Xbar (Alg. 2): zero the appended rows of the whole basis row ----
   mark(st, 1);
   launch_fill_rows<T>(b.Zc, st->ldz, n, S, st->ldz, s);
   // ---- Delta Xbar = Delta_1 X (Prop. 3) into W[:, 0:K] ----
-  if (st->op == GREST_OP_NLAP) {
-    launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
-                           st->col[gn], sc_new, b.Zc, st->ldz, st->K, b.W, st->ldz, s);
-  } else {
+  if (!nlap)
     launch_delta_mul<T>(0, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Zc, st->ldz, st->K,
                         b.W, st->ldz, s);
-  }
   mark(st, 2);
+  // ---- augmentation block ----
   T* B2 = b.W + st->K;
   const int w2 = st->Dw - st->K;
-  // ---- augmentation block ----
   if (st->variant == GREST_G3) {
     launch_fill_rows<T>(B2, st->ldz, 0, n2, w2, s);
     if (S > 0)
@@ -476,6 +492,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
       if (!launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
                             st->eigwork, st->status, s)) {
+        (void)hipEventSynchronize(st->vev);
+        st->marking = false;
         snprintf(g_last_error, sizeof(g_last_error), "sketch order %d outside the small eigensolver's range", Ls);
         return GREST_EINVAL;
       }
@@ -485,7 +503,26 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   }
   mark(st, 3);
   // ---- projection (I - Xbar Xbar^T) W, twice; CholQR2 of W ----
-  orth_against<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, 0);
+  if (!nlap) orth_against<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, 0);
+
+  HIPCHK(hipEventSynchronize(st->vev));
+  // every earlier update has finished: collect the numerical status and the stage times
+  // of the last one
+  st->deferred |= st->pin->status & ST_NUMERIC;
+  st->pin->status = 0;
+  prof_collect_slot(st, st->pslot ^ 1);
+  if (st->pin->vstatus & VALIDATION_BITS) {
+    st->marking = false;
+    snprintf(g_last_error, sizeof(g_last_error), "change list rejected (status bits 0x%x)", st->pin->vstatus);
+    return GREST_EINVAL;
+  }
+  const int64_t m_new = st->pin->m_new;
+
+  if (nlap) {
+    launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
+                           st->col[gn], sc_new, b.Zc, st->ldz, st->K, b.W, st->ldz, s);
+    orth_against<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, 0);
+  }
   mark(st, 4);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
   CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->K, st->ranks + 1));
@@ -493,7 +530,10 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   // ---- commit ----
-  if (st->marking) st->prof_pending = true;
+  if (st->marking) {  // the next update records into the other set
+    st->prof_pending[st->pslot] = true;
+    st->pslot ^= 1;
+  }
   st->marking = false;
   st->gcur = gn;
   st->zcur ^= 1;
@@ -742,6 +782,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if (hipHostMalloc((void**)&st->pin, sizeof(Pinned)) != hipSuccess) return fail(GREST_ENOMEM);
   if (hipHostMalloc((void**)&st->theta_pin, st->K * sizeof(double)) != hipSuccess) return fail(GREST_ENOMEM);
   memset(st->pin, 0, sizeof(Pinned));
+  if (hipEventCreateWithFlags(&st->vev, hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
   // upload the graph
   st->n = n0;
   st->m = m0;
@@ -778,10 +819,8 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
   if (st->variant == GREST_RSVD && n_new > 0 && !omega) return GREST_EINVAL;
   if (where != GREST_HOST && where != GREST_DEVICE) return GREST_EINVAL;
   if (where == GREST_HOST && !host_changes_ok(st->n, n_new, n_changes, ei, ej, sign)) return GREST_EINVAL;
-  // pull in the status of the previous update before overwriting the pinned word
-  HIPCHK(hipStreamSynchronize(st->stream));
-  prof_collect(st);
-  st->deferred |= st->pin->status & ST_NUMERIC;
+  // the previous update may still run on the device: its status (and stage times) are
+  // collected at this update's validation wait
   return st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where)
                      : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where);
 }
@@ -849,13 +888,15 @@ grest_status grest_memory(const grest_state* st, int64_t* bytes) {
 grest_status grest_profile(grest_state* st, int32_t enable) {
   if (!st) return GREST_EINVAL;
   HIPCHK(hipStreamSynchronize(st->stream));
-  if (enable && !st->pev[0]) {
-    for (int i = 0; i <= grest_state::NSTAGE; ++i) HIPCHK(hipEventCreate(&st->pev[i]));
-    HIPCHK(hipEventCreate(&st->kev[0]));
-    HIPCHK(hipEventCreate(&st->kev[1]));
+  if (enable && !st->pev[0][0]) {
+    for (int b = 0; b < 2; ++b) {
+      for (int i = 0; i <= grest_state::NSTAGE; ++i) HIPCHK(hipEventCreate(&st->pev[b][i]));
+      HIPCHK(hipEventCreate(&st->kev[b][0]));
+      HIPCHK(hipEventCreate(&st->kev[b][1]));
+    }
   }
   st->prof = enable != 0;
-  st->prof_pending = false;
+  st->prof_pending[0] = st->prof_pending[1] = false;
   for (int i = 0; i < grest_state::NSTAGE; ++i) st->stage_ms[i] = 0.0;
   st->spmm_ms = 0.0;
   st->prof_updates = 0;
@@ -876,10 +917,12 @@ grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stag
 void grest_destroy(grest_state* st) {
   if (!st) return;
   (void)hipStreamSynchronize(st->stream);
-  for (int i = 0; i <= grest_state::NSTAGE; ++i)
-    if (st->pev[i]) (void)hipEventDestroy(st->pev[i]);
-  if (st->kev[0]) (void)hipEventDestroy(st->kev[0]);
-  if (st->kev[1]) (void)hipEventDestroy(st->kev[1]);
+  for (int b = 0; b < 2; ++b) {
+    for (int i = 0; i <= grest_state::NSTAGE; ++i)
+      if (st->pev[b][i]) (void)hipEventDestroy(st->pev[b][i]);
+    if (st->kev[b][0]) (void)hipEventDestroy(st->kev[b][0]);
+    if (st->kev[b][1]) (void)hipEventDestroy(st->kev[b][1]);
+  }
   free_all(st);
   if (st->own_stream) (void)hipStreamDestroy(st->stream);
   delete st;

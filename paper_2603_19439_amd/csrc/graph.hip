@@ -9,11 +9,11 @@
 //   2. exclusive scan of the counts -> row offsets of Delta          (3-kernel scan)
 //   3. stable radix sort of the keys (signs carried along), so every row of Delta is
 //      contiguous and sorted by column whatever its length
-//   4. one wavefront per row, linear in the row: duplicates, insert/delete checks
+//   4. a group of lanes per row, linear in the row: duplicates, insert/delete checks
 //      against the old row (binary search), per-row prefix counts of insertions and
 //      the new row length
 //   5. exclusive scan of the new lengths -> new row offsets
-//   6. one wavefront per row: merge by ranks (old entries not deleted + inserted
+//   6. a group of lanes per row: merge by ranks (old entries not deleted + inserted
 //      entries), fully parallel inside the row, so hub rows do not serialise.
 // Every write is bounds-checked against the row and the column capacity, so an
 // invalid change list (reported through the status word before anything reads the
@@ -186,39 +186,40 @@ __device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t len, int32_t
   return lo;
 }
 
-// one wavefront per row (grid-stride) over the sorted row: duplicates, validation,
+// a group of LPR lanes per row (grid-stride) over the sorted row: duplicates, validation,
 // dins[p] = insertions before p in the row, new length
+template <int LPR>
 __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, const int64_t* dptr,
                                                    const int32_t* dcol, const int8_t* dsg, int32_t* dins,
                                                    const int64_t* rp_old, const int32_t* col_old,
                                                    int64_t* newlen, int32_t* status) {
-  const int lane = threadIdx.x & (GREST_WAVE - 1);
-  const int64_t wave = ((int64_t)blockIdx.x * BS + threadIdx.x) / GREST_WAVE;
-  const int64_t nwaves = (int64_t)gridDim.x * (BS / GREST_WAVE);
-  for (int64_t r = wave; r < n2; r += nwaves) {
+  const int sl = threadIdx.x & (LPR - 1);  // lane within the row group
+  const int64_t grp = ((int64_t)blockIdx.x * BS + threadIdx.x) / LPR;
+  const int64_t ngrp = (int64_t)gridDim.x * (BS / LPR);
+  for (int64_t r = grp; r < n2; r += ngrp) {
     const int64_t beg = dptr[r];
     const int64_t len = dptr[r + 1] - beg;
     const int64_t ob = r < n_old ? rp_old[r] : 0;
     const int64_t olen = r < n_old ? rp_old[r + 1] - ob : 0;
     if (len == 0) {
-      if (lane == 0) newlen[r] = olen;
+      if (sl == 0) newlen[r] = olen;
       continue;
     }
     int64_t sum_s = 0;
     int32_t bad = 0;
     int32_t carry = 0;  // insertions in the earlier chunks of the row
-    for (int64_t e0 = 0; e0 < len; e0 += GREST_WAVE) {
-      const int64_t e = e0 + lane;
+    for (int64_t e0 = 0; e0 < len; e0 += LPR) {
+      const int64_t e = e0 + sl;
       const bool ve = e < len;
       const int32_t ce = ve ? dcol[beg + e] : 0;
       const int8_t se = ve ? dsg[beg + e] : 0;
       if (ve && e > 0 && dcol[beg + e - 1] == ce) bad |= ST_DUPLICATE;
       const int32_t ins = (ve && se > 0) ? 1 : 0;
-      int32_t incl = ins;  // inclusive prefix sum over the lanes
+      int32_t incl = ins;  // inclusive prefix sum over the group
 #pragma unroll
-      for (int o = 1; o < GREST_WAVE; o <<= 1) {
-        const int32_t y = __shfl_up(incl, o, GREST_WAVE);
-        if (lane >= o) incl += y;
+      for (int o = 1; o < LPR; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, LPR);
+        if (sl >= o) incl += y;
       }
       if (ve) {
         dins[beg + e] = carry + incl - ins;
@@ -230,14 +231,14 @@ __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, co
           if (!found && se < 0) bad |= ST_DELETE_MISSING;
         }
       }
-      carry += __shfl(incl, GREST_WAVE - 1, GREST_WAVE);
+      carry += __shfl(incl, LPR - 1, LPR);
     }
 #pragma unroll
-    for (int o = GREST_WAVE / 2; o > 0; o >>= 1) {
-      sum_s += __shfl_xor(sum_s, o, GREST_WAVE);
-      bad |= __shfl_xor(bad, o, GREST_WAVE);
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+      sum_s += __shfl_xor(sum_s, o, LPR);
+      bad |= __shfl_xor(bad, o, LPR);
     }
-    if (lane == 0) {
+    if (sl == 0) {
       int64_t nl = olen + sum_s;
       newlen[r] = nl < 0 ? 0 : nl;
       if (bad) atomicOr(status, bad);
@@ -245,16 +246,18 @@ __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, co
   }
 }
 
-// one wavefront per row (grid-stride): parallel merge by ranks
+// a group of LPR lanes per row (grid-stride): untouched rows are shifted copies, touched
+// rows a parallel merge by ranks
+template <int LPR>
 __global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, const int64_t* rp_old,
                                                   const int32_t* col_old, const int64_t* dptr,
                                                   const int32_t* dcol, const int8_t* dsg,
                                                   const int32_t* dins, const int64_t* rp_new,
                                                   int32_t* col_new, int64_t cap_m) {
-  const int lane = threadIdx.x & (GREST_WAVE - 1);
-  const int64_t wave = ((int64_t)blockIdx.x * BS + threadIdx.x) / GREST_WAVE;
-  const int64_t nwaves = (int64_t)gridDim.x * (BS / GREST_WAVE);
-  for (int64_t r = wave; r < n2; r += nwaves) {
+  const int sl = threadIdx.x & (LPR - 1);
+  const int64_t grp = ((int64_t)blockIdx.x * BS + threadIdx.x) / LPR;
+  const int64_t ngrp = (int64_t)gridDim.x * (BS / LPR);
+  for (int64_t r = grp; r < n2; r += ngrp) {
     const int64_t ob = r < n_old ? rp_old[r] : 0;
     const int64_t olen = r < n_old ? rp_old[r + 1] - ob : 0;
     const int64_t db = dptr[r];
@@ -263,11 +266,11 @@ __global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, con
     const int64_t nlen = rp_new[r + 1] - nb;
     if (nb < 0 || nlen <= 0 || nb + nlen > cap_m) continue;
     if (dlen == 0) {
-      for (int64_t a = lane; a < olen && a < nlen; a += GREST_WAVE) col_new[nb + a] = col_old[ob + a];
+      for (int64_t a = sl; a < olen && a < nlen; a += LPR) col_new[nb + a] = col_old[ob + a];
       continue;
     }
     const int64_t tot_ins = (int64_t)dins[db + dlen - 1] + (dsg[db + dlen - 1] > 0 ? 1 : 0);
-    for (int64_t a = lane; a < olen; a += GREST_WAVE) {
+    for (int64_t a = sl; a < olen; a += LPR) {
       const int32_t c = col_old[ob + a];
       const int64_t p = lower_bound_i32(dcol + db, dlen, c);
       const bool hit = p < dlen && dcol[db + p] == c;
@@ -276,7 +279,7 @@ __global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, con
       const int64_t pos = a - (p - insb) + insb;
       if (pos >= 0 && pos < nlen) col_new[nb + pos] = c;
     }
-    for (int64_t b = lane; b < dlen; b += GREST_WAVE) {
+    for (int64_t b = sl; b < dlen; b += LPR) {
       if (dsg[db + b] < 0) continue;
       const int32_t c = dcol[db + b];
       const int64_t q = r < n_old ? lower_bound_i32(col_old + ob, olen, c) : 0;
@@ -383,8 +386,9 @@ void launch_delta_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const 
                        int32_t* status, hipStream_t s) {
   int64_t n2 = n_old + n_new;
   if (n2 <= 0) return;
-  k_delta_rows<<<grid_for(n2 * GREST_WAVE, BS, 2048), BS, 0, s>>>(n_old, n2, dptr, dcol, dsg, dins, rp_old,
-                                                                   col_old, newlen, status);
+  constexpr int LPR = 8;  // touched rows carry a few changes each
+  k_delta_rows<LPR><<<grid_for(n2 * LPR, BS, 1 << 15), BS, 0, s>>>(n_old, n2, dptr, dcol, dsg, dins, rp_old, col_old,
+                                                                   newlen, status);
 }
 
 void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
@@ -392,8 +396,9 @@ void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const
                       const int64_t* rp_new, int32_t* col_new, int64_t cap_m, hipStream_t s) {
   int64_t n2 = n_old + n_new;
   if (n2 <= 0) return;
-  k_csr_merge<<<grid_for(n2 * GREST_WAVE, BS, 4096), BS, 0, s>>>(n_old, n2, rp_old, col_old, dptr, dcol,
-                                                                 dsg, dins, rp_new, col_new, cap_m);
+  constexpr int LPR = 16;  // about one pass over a row of mean length
+  k_csr_merge<LPR><<<grid_for(n2 * LPR, BS, 1 << 15), BS, 0, s>>>(n_old, n2, rp_old, col_old, dptr, dcol, dsg, dins,
+                                                                  rp_new, col_new, cap_m);
 }
 
 void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* dinv_sqrt32,

@@ -8,7 +8,8 @@
 //                wave has 4 (PA + PB) loads in flight).  The four waves of a workgroup are
 //                summed through LDS in a fixed order, and the workgroup partials are summed
 //                in a fixed order by k_tn_reduce, so results do not depend on scheduling.
-//                A symmetric mode (Gram matrices) computes the upper tiles only.
+//                A symmetric mode (Gram matrices) computes the upper tiles only and writes
+//                the lower ones as their mirrors.
 //   * k_tn_bf16: the same product with split-BF16 MFMA (v_mfma_f32_16x16x32_bf16): every
 //                value is split into hi = bf16(x) and lo = bf16(x - hi) and the tile gets
 //                hi*hi + hi*lo + lo*hi with FP32 accumulation (relative error ~2^-16).  Rows
@@ -129,9 +130,11 @@ __global__ void __launch_bounds__(WG) k_tnw(int64_t n, int64_t rpc, const Tin* _
   for (int e = threadIdx.x; e < PA * PB * 256; e += WG) {
     const int t = e >> 8, i = (e >> 4) & 15, j = e & 15;
     const int p = t / PB, q = t % PB;
-    if (SYM && p > q) continue;
+    // symmetric mode: a lower tile is the transpose of its mirror, so the partial is full
+    // and the reduction reads it row by row
+    const double v = (SYM && p > q) ? red_lds[((q * PB + p) * 16 + j) * 16 + i] : red_lds[e];
     const int gi = (ty0 + p) * 16 + i, gj = q * 16 + j;
-    if (gi < a && gj < b) out[(size_t)gi * b + gj] = red_lds[e];
+    if (gi < a && gj < b) out[(size_t)gi * b + gj] = v;
   }
 }
 
@@ -322,47 +325,52 @@ __global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __r
     const int gi = (t / TWC) * 16 + i, gj = (t % TWC) * 16 + j;
     if (gi < kx && gj < w) oc[(size_t)gi * w + gj] = red_lds[e];
   }
-  for (int e = threadIdx.x; e < NTG * 256; e += WG) {
+  // G in full (lower tiles from their mirrors), so that the reduction reads rows
+  for (int e = threadIdx.x; e < TWC * TWC * 256; e += WG) {
     const int t = e >> 8, i = (e >> 4) & 15, j = e & 15;
-    int p = 0, tt = t;
-    while (tt >= TWC - p) { tt -= TWC - p; ++p; }
-    const int q = p + tt;
+    const int p = t / TWC, q = t % TWC;
+    const double v = p <= q ? lds2[(tri_idx(p, q, TWC) * 16 + i) * 16 + j] : lds2[(tri_idx(q, p, TWC) * 16 + j) * 16 + i];
     const int gi = p * 16 + i, gj = q * 16 + j;
-    if (gi < w && gj < w) og[(size_t)gi * w + gj] = lds2[e];
+    if (gi < w && gj < w) og[(size_t)gi * w + gj] = v;
   }
 }
 
 // fixed-order sum of the chunk partials: a workgroup of RWV waves owns 64 consecutive
-// outputs, wave w sums the partials c = w, w + RWV, ... with four independent
-// accumulators (many loads in flight), and the wave sums are combined in a fixed order.
-// In symmetric mode the lower tiles are read from their mirror.
+// outputs, wave w sums the partials c = w, w + RWV, ... (all of its loads are issued
+// before the first add, so the reduction costs one memory latency), and the wave sums are
+// combined in a fixed order.  One launch serves up to two products (the two outputs of a
+// projection round).
 constexpr int RWV = 16;
+constexpr int RLD = CHUNKS / RWV;  // partials per lane
+static_assert(RLD * RWV == CHUNKS, "every chunk has a wave");
 
-__global__ void __launch_bounds__(RWV * 64) k_tn_reduce(int g, int a, int b, int sym,
-                                                        const double* __restrict__ partial,
-                                                        double* __restrict__ C) {
+struct RedJob {
+  const double* partial;
+  double* C;
+  int a, b, blocks;
+};
+
+__global__ void __launch_bounds__(RWV * 64) k_tn_reduce(int g, RedJob j0, RedJob j1) {
   __shared__ double red[RWV][64];
+  const bool second = (int)blockIdx.x >= j0.blocks;
+  const double* partial = second ? j1.partial : j0.partial;
+  double* C = second ? j1.C : j0.C;
+  const int a = second ? j1.a : j0.a, b = second ? j1.b : j0.b;
+  const int64_t blk = second ? (int64_t)blockIdx.x - j0.blocks : (int64_t)blockIdx.x;
   const int64_t ab = (int64_t)a * b;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  if (idx < ab) {
-    int64_t src = idx;
-    if (sym) {
-      const int i = (int)(idx / b), j = (int)(idx % b);
-      if ((i >> 4) > (j >> 4)) src = (int64_t)j * b + i;
-    }
-    const double* p = partial + src;
-    int c = w;
-    for (; c + 3 * RWV < g; c += 4 * RWV) {
-      s0 += p[(size_t)c * ab];
-      s1 += p[(size_t)(c + RWV) * ab];
-      s2 += p[(size_t)(c + 2 * RWV) * ab];
-      s3 += p[(size_t)(c + 3 * RWV) * ab];
-    }
-    for (; c < g; c += RWV) s0 += p[(size_t)c * ab];
+  const int64_t idx = blk * 64 + lane;
+  double v[RLD];
+#pragma unroll
+  for (int q = 0; q < RLD; ++q) {
+    const int c = w + RWV * q;
+    v[q] = (idx < ab && c < g) ? partial[(size_t)c * ab + idx] : 0.0;
   }
-  red[w][lane] = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int h = RLD / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int q = 0; q < h; ++q) v[q] += v[q + h];
+  red[w][lane] = v[0];
   __syncthreads();
   if (w == 0 && idx < ab) {
     double t = 0.0;
@@ -370,6 +378,15 @@ __global__ void __launch_bounds__(RWV * 64) k_tn_reduce(int g, int a, int b, int
     for (int q = 0; q < RWV; ++q) t += red[q][lane];
     C[idx] = t;
   }
+}
+
+inline RedJob red_job(const double* partial, double* C, int a, int b) {
+  return RedJob{partial, C, a, b, (int)(((int64_t)a * b + 63) / 64)};
+}
+
+inline void launch_reduce(int g, const RedJob& j0, const RedJob& j1, hipStream_t s) {
+  const int nb = j0.blocks + j1.blocks;
+  if (nb > 0) k_tn_reduce<<<nb, RWV * 64, 0, s>>>(g, j0, j1);
 }
 
 // ---------------------------------------------------------------------------------
@@ -543,8 +560,7 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
     if (sym && ((a + 15) >> 4) > 4) sym = false;
     tnw_dispatch<T, float>(n, g, rpc, A, lda, a, B, ldb, b, sym, partial, s);
   }
-  const int64_t ab = (int64_t)a * b;
-  k_tn_reduce<<<(unsigned)((ab + 63) / 64), RWV * 64, 0, s>>>(g, a, b, sym ? 1 : 0, partial, C);
+  launch_reduce(g, red_job(partial, C, a, b), RedJob{nullptr, nullptr, 0, 0, 0}, s);
 }
 
 // one projection round: C = X^T W and G = W^T W (upper tiles; the reduce mirrors them)
@@ -580,8 +596,7 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
   else if (TX == 1 && TWt == 2) pip_launch<T, Tcx, 1, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else if (TX == 1 && TWt == 1) pip_launch<T, Tcx, 1, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else return false;
-  k_tn_reduce<<<(unsigned)(((int64_t)kx * w + 63) / 64), RWV * 64, 0, s>>>(g, kx, w, 0, partC, C);
-  k_tn_reduce<<<(unsigned)(((int64_t)w * w + 63) / 64), RWV * 64, 0, s>>>(g, w, w, 1, partG, G);
+  launch_reduce(g, red_job(partC, C, kx, w), red_job(partG, G, w, w), s);
   return true;
 }
 
