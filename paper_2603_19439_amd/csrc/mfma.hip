@@ -24,6 +24,8 @@
 // element (4*(l/16)+r, l%16); the f64 tile gives (l/16+4r, l%16).
 #include "grest_internal.h"
 
+#include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -233,7 +235,7 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const fl
 __host__ __device__ constexpr int tri_idx(int p, int q, int n) { return p * n - p * (p - 1) / 2 + (q - p); }
 
 template <typename T, typename Tcx, int TXC, int TWC>
-__global__ void __launch_bounds__(WG) k_pip(int64_t n, int64_t rpc, const T* __restrict__ X, int64_t ldx, int kx,
+__global__ void __launch_bounds__(WG, sizeof(T) == 4 ? 2 : 1) k_pip(int64_t n, int64_t rpc, const T* __restrict__ X, int64_t ldx, int kx,
                                             const T* __restrict__ W, int64_t ldw, int w, double* __restrict__ partC,
                                             double* __restrict__ partG) {
   constexpr int NTG = TWC * (TWC + 1) / 2;
@@ -484,6 +486,172 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
   }
 }
 
+// FP32 blocks: the tile is computed transposed, D = M^T In^T, so that lane (g, c) of the
+// wave reads four consecutive input columns of row c (one 16-byte load per 16 columns)
+// and ends up holding four consecutive output columns of row c (one 16-byte store).  M is
+// staged in LDS as float4 groups [kb][jt][g][c] of the four coefficients a lane feeds in
+// the four MFMA steps of a 16-wide k block, so each lane reads one 16-byte vector per
+// (kb, jt).  KB = ceil(a / 16) is a template parameter so the fragment arrays are exact;
+// two output tiles are accumulated side by side.  Every row's inputs are read before its
+// outputs are written, so Out may alias In2 (in-place update of a column block).
+template <int KB, bool VEC>
+__global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, int64_t ld1, int a1,
+                                                  const float* In2, int64_t ld2, int a2,
+                                                  const double* __restrict__ Mg, int b, double alpha, double beta,
+                                                  float* Out, int64_t ldout) {
+  extern __shared__ double sMraw[];
+  f32x4* sM = reinterpret_cast<f32x4*>(sMraw);
+  const int a = a1 + a2;
+  const int TB = (b + 15) >> 4;
+  for (int idx = threadIdx.x; idx < KB * TB * 64; idx += WG) {
+    const int c = idx & 15, g = (idx >> 4) & 3, t = idx >> 6;
+    const int kb = t / TB, jt = t % TB;
+    const int j = jt * 16 + c;
+    f32x4 v;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = kb * 16 + 4 * g + m;
+      v[m] = (k < a && j < b) ? (float)(alpha * Mg[(size_t)k * b + j]) : 0.f;
+    }
+    sM[idx] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int64_t ntile = (n + 15) >> 4;
+  const int64_t stride = (int64_t)gridDim.x * NW;
+  // VEC: a1, a and b are multiples of four and every row start is 16-byte aligned, so a
+  // lane's four columns are either all inside one input block or all past the end
+  auto load = [&](int64_t t, f32x4(&f)[KB]) __attribute__((always_inline)) {
+    const int64_t row = t * 16 + c16;
+    if (VEC) {
+      const float* b1 = In1 + row * ld1;
+      const float* b2 = In2 + row * ld2 - a1;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const int k0 = kb * 16 + 4 * g;
+        f[kb] = (row < n && k0 < a) ? *reinterpret_cast<const f32x4*>((k0 < a1 ? b1 : b2) + k0)
+                                    : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int k = kb * 16 + 4 * g + m;
+          float v = 0.f;
+          if (row < n && k < a) v = k < a1 ? In1[row * ld1 + k] : In2[row * ld2 + (k - a1)];
+          f[kb][m] = v;
+        }
+      }
+    }
+  };
+  auto store = [&](int64_t row, int jt, f32x4 acc) __attribute__((always_inline)) {
+    const int col0 = jt * 16 + 4 * g;
+    if (row >= n || jt >= TB) return;
+    float* o = Out + row * ldout + col0;
+    if (VEC) {
+      if (col0 >= b) return;
+      if (beta != 0.0) {
+        const f32x4 old = *reinterpret_cast<const f32x4*>(o);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] += (float)beta * old[r];
+      }
+      *reinterpret_cast<f32x4*>(o) = acc;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (col0 + r < b) {
+          float v = acc[r];
+          if (beta != 0.0) v += (float)beta * o[r];
+          o[r] = v;
+        }
+      }
+    }
+  };
+  int64_t tile = (int64_t)blockIdx.x * NW + wid;
+  f32x4 nxt[KB];
+  if (tile < ntile) load(tile, nxt);
+  for (; tile < ntile; tile += stride) {
+    f32x4 fin[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) fin[kb] = nxt[kb];
+    if (tile + stride < ntile) load(tile + stride, nxt);  // in flight during the MFMAs below
+    const int64_t row = tile * 16 + c16;
+    for (int jt = 0; jt < TB; jt += 2) {
+      const bool two = jt + 1 < TB;
+      f32x4 acc0{0.f, 0.f, 0.f, 0.f}, acc1{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const f32x4 m0 = sM[(kb * TB + jt) * 64 + lane];
+        const f32x4 m1 = two ? sM[(kb * TB + jt + 1) * 64 + lane] : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(m0[m], fin[kb][m], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(m1[m], fin[kb][m], acc1, 0, 0, 0);
+        }
+      }
+      store(row, jt, acc0);
+      store(row, jt + 1, acc1);
+    }
+  }
+}
+
+int device_cus() {
+  static const int cus = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || v <= 0)
+      v = 256;
+    return v;
+  }();
+  return cus;
+}
+
+template <int KB, bool VEC>
+void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
+                      const double* M, int b, double alpha, double beta, float* Out, int64_t ldout, hipStream_t s) {
+  const int TB = (b + 15) >> 4;
+  const size_t lds = (size_t)KB * TB * 64 * sizeof(f32x4);
+  // resident workgroups per CU for this LDS size (queried once per size; a persistent
+  // grid of that many workgroups per CU takes the tiles round-robin)
+  static std::atomic<int> occ_cache[8];
+  int occ = occ_cache[TB - 1].load(std::memory_order_relaxed);
+  if (occ <= 0) {
+    static const bool attr = [] {
+      (void)hipFuncSetAttribute((const void*)k_apply_f32<KB, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(KB * 8 * 64 * sizeof(f32x4)));
+      return true;
+    }();
+    (void)attr;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_apply_f32<KB, VEC>, WG, lds) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    occ = nb;
+    occ_cache[TB - 1].store(occ, std::memory_order_relaxed);
+  }
+  const int64_t tiles = (n + 15) / 16;
+  int64_t g = std::min<int64_t>((tiles + NW - 1) / NW, (int64_t)device_cus() * occ);
+  if (g < 1) g = 1;
+  k_apply_f32<KB, VEC><<<(unsigned)g, WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout);
+}
+
+template <bool VEC>
+void apply_f32_dispatch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
+                        const double* M, int b, double alpha, double beta, float* Out, int64_t ldout, hipStream_t s) {
+  switch ((a1 + a2 + 15) >> 4) {
+    case 1: apply_f32_launch<1, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    case 2: apply_f32_launch<2, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    case 3: apply_f32_launch<3, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    case 4: apply_f32_launch<4, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    case 5: apply_f32_launch<5, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    case 6: apply_f32_launch<6, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    case 7: apply_f32_launch<7, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    default: apply_f32_launch<8, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+  }
+}
+
 inline int apply_grid(int64_t n) {
   int64_t tiles = (n + 15) / 16;
   int64_t g = (tiles + 4 * NW - 1) / (4 * NW);  // about four tiles per wave
@@ -635,12 +803,14 @@ void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, i
                    const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s) {
   if (n <= 0 || b <= 0) return;
   const bool vec = aligned16(In1, ld1) && (a2 == 0 || (aligned16(In2, ld2) && a1 % 4 == 0));
-  if (sizeof(T) == 8) {
+  if constexpr (sizeof(T) == 8) {
     if (vec) apply_launch<T, double, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
     else apply_launch<T, double, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
   } else {
-    if (vec) apply_launch<T, float, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
-    else apply_launch<T, float, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+    if (vec && aligned16(Out, ldout) && a1 % 4 == 0 && (a1 + a2) % 4 == 0 && b % 4 == 0)
+      apply_f32_dispatch<true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+    else
+      apply_f32_dispatch<false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
   }
 }
 
