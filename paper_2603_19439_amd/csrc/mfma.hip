@@ -222,6 +222,125 @@ __global__ void __launch_bounds__(WG) k_tn_bf16(int64_t n, int64_t rpc, const fl
 }
 
 // ---------------------------------------------------------------------------------
+// C = A^T B with split-BF16 MFMA, FP32 rows staged transposed in LDS (the form used when
+// the widths are multiples of four and the rows 16-byte aligned).  A stage is 32 rows:
+// each loader thread takes four adjacent columns of eight consecutive rows (eight
+// 16-byte loads), and writes each of its four columns' eight values as two 16-byte LDS
+// stores into a column-major buffer (pitch 36 floats, which keeps the 16-lane phases of
+// the 16-byte fragment reads on disjoint banks).  The next stage's loads are in flight
+// during the MFMAs.  Wave w owns a TT x TT block of output tiles (tile rows from w / 2,
+// tile columns from w % 2); each lane reads its eight k values of a fragment as two
+// 16-byte vectors and splits them into hi = bf16(x) and lo = bf16(x - hi) in registers,
+// and every tile gets lo*hi + hi*lo + hi*hi with FP32 accumulation.
+// ---------------------------------------------------------------------------------
+constexpr int TP = 36;  // LDS pitch (floats) of one staged column of 32 rows
+
+template <int TT>
+__global__ void __launch_bounds__(WG) k_tn_bf16t(int64_t n, int64_t rpc, const float* __restrict__ A, int64_t lda,
+                                                 int a, const float* __restrict__ B, int64_t ldb, int b,
+                                                 double* __restrict__ partial) {
+  extern __shared__ double tsm_raw[];
+  float* S = reinterpret_cast<float*>(tsm_raw);  // (a + b) columns x TP
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int ncg = (a + b) >> 2;  // column groups of four
+  const int items = ncg * 4;     // x four row groups of eight rows
+  const int64_t r0 = (int64_t)blockIdx.x * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  // loader item of this thread: column group cg, row group rg
+  const bool loader = tid < items;
+  const int cg = tid >> 2, rg = tid & 3;
+  const int gc = 4 * cg;  // first concatenated column
+  const float* src = gc < a ? A + gc : B + (gc - a);
+  const int64_t ld = gc < a ? lda : ldb;
+  f32x4 pre[8];
+  auto fetch = [&](int64_t rb) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t row = rb + 8 * rg + e;
+      pre[e] = (loader && row < r1) ? *reinterpret_cast<const f32x4*>(src + row * ld) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  const int ti0 = (wid >> 1) * TT, tj0 = (wid & 1) * TT;
+  f32x4 acc[TT][TT];
+#pragma unroll
+  for (int p = 0; p < TT; ++p)
+#pragma unroll
+    for (int q = 0; q < TT; ++q) acc[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto frag = [&](int col, bool ok, bf16x8& hi, bf16x8& lo) __attribute__((always_inline)) {
+    f32x4 u0{0.f, 0.f, 0.f, 0.f}, u1{0.f, 0.f, 0.f, 0.f};
+    if (ok) {
+      u0 = *reinterpret_cast<const f32x4*>(S + col * TP + 8 * g);
+      u1 = *reinterpret_cast<const f32x4*>(S + col * TP + 8 * g + 4);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float x = e < 4 ? u0[e] : u1[e - 4];
+      const __bf16 h = (__bf16)x;
+      hi[e] = h;
+      lo[e] = (__bf16)(x - (float)h);
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t rb = r0; rb < r1; rb += 32) {
+    __syncthreads();  // the previous stage's fragments have been read
+    if (loader) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float* d = S + (gc + q) * TP + 8 * rg;
+        *reinterpret_cast<f32x4*>(d) = f32x4{pre[0][q], pre[1][q], pre[2][q], pre[3][q]};
+        *reinterpret_cast<f32x4*>(d + 4) = f32x4{pre[4][q], pre[5][q], pre[6][q], pre[7][q]};
+      }
+    }
+    __syncthreads();
+    if (rb + 32 < r1) fetch(rb + 32);  // in flight during the MFMAs below
+    bf16x8 ahi[TT], alo[TT], bhi[TT], blo[TT];
+#pragma unroll
+    for (int p = 0; p < TT; ++p) {
+      const int ca = (ti0 + p) * 16 + c16;
+      frag(ca, ca < a, ahi[p], alo[p]);
+    }
+#pragma unroll
+    for (int q = 0; q < TT; ++q) {
+      const int cb = (tj0 + q) * 16 + c16;
+      frag(a + cb, cb < b, bhi[q], blo[q]);
+    }
+#pragma unroll
+    for (int p = 0; p < TT; ++p)
+#pragma unroll
+      for (int q = 0; q < TT; ++q) {
+        acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[p], bhi[q], acc[p][q], 0, 0, 0);
+        acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[p], blo[q], acc[p][q], 0, 0, 0);
+        acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[p], bhi[q], acc[p][q], 0, 0, 0);
+      }
+  }
+  double* out = partial + (size_t)blockIdx.x * a * b;
+#pragma unroll
+  for (int p = 0; p < TT; ++p)
+#pragma unroll
+    for (int q = 0; q < TT; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = (ti0 + p) * 16 + bf16_row(lane, r);
+        const int j = (tj0 + q) * 16 + c16;
+        if (i < a && j < b) out[(size_t)i * b + j] = (double)acc[p][q][r];
+      }
+}
+
+template <int TT>
+void tn_bf16t_launch(int g, int64_t n, int64_t rpc, const float* A, int64_t lda, int a, const float* B, int64_t ldb,
+                     int b, double* partial, hipStream_t s) {
+  const size_t lds = (size_t)(a + b) * TP * sizeof(float);
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)k_tn_bf16t<TT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(2 * TW * TP * sizeof(float)));
+    return true;
+  }();
+  (void)attr;
+  k_tn_bf16t<TT><<<g, WG, lds, s>>>(n, rpc, A, lda, a, B, ldb, b, partial);
+}
+
+// ---------------------------------------------------------------------------------
 // One pass over the rows for a projection round of block Gram-Schmidt with the
 // Pythagorean Gram: C = X^T W and G = W^T W (upper tiles).
 // X and W are separate column blocks (any widths <= 128).  G always accumulates in
@@ -720,7 +839,15 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
   if (kind == 2 && ((a + 15) >> 4) * ((b + 15) >> 4) > NW * BT) kind = 0;  // too many tiles: FP32 MFMA
   bool sym = (A == B && lda == ldb && a == b && kind != 2);
   if (kind == 2) {
-    k_tn_bf16<<<g, WG, 0, s>>>(n, rpc, (const float*)A, lda, a, (const float*)B, ldb, b, partial);
+    const int tt = std::max((((a + 15) >> 4) + 1) / 2, (((b + 15) >> 4) + 1) / 2);
+    const bool staged = a % 4 == 0 && b % 4 == 0 && aligned16(A, lda) && aligned16(B, ldb);
+    const float* fA = (const float*)A;
+    const float* fB = (const float*)B;
+    if (staged && tt <= 1) tn_bf16t_launch<1>(g, n, rpc, fA, lda, a, fB, ldb, b, partial, s);
+    else if (staged && tt == 2) tn_bf16t_launch<2>(g, n, rpc, fA, lda, a, fB, ldb, b, partial, s);
+    else if (staged && tt == 3) tn_bf16t_launch<3>(g, n, rpc, fA, lda, a, fB, ldb, b, partial, s);
+    else if (staged && tt == 4) tn_bf16t_launch<4>(g, n, rpc, fA, lda, a, fB, ldb, b, partial, s);
+    else k_tn_bf16<<<g, WG, 0, s>>>(n, rpc, fA, lda, a, fB, ldb, b, partial);
   } else if (kind == 1) {
     if (sym && ((a + 15) >> 4) > 4) sym = false;  // wide Gram: full product in slices
     tnw_dispatch<T, double>(n, g, rpc, A, lda, a, B, ldb, b, sym, partial, s);

@@ -106,6 +106,14 @@ def test_sbm_large_shape_rsvd(prec):
     run_trajectory(wl, 16, "rsvd", "adj", prec, 3, L=16, P=16)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_sbm_headline_width_rsvd_k32(prec):
+    """The headline's shape at n0=20000: Dirichlet SBM, K=32, RSVD with L=P=32, so the
+    basis is 96 wide (the widths the large runs use in every product kernel)."""
+    wl = W.preset("sbm_n1e6", scale=0.02, steps=2)
+    run_trajectory(wl, 32, "rsvd", "adj", prec, 2, L=32, P=32)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_chunglu_normalized_laplacian(prec):
     """Chung-Lu (gamma 2.5, mean 16) with edge churn, normalised Laplacian, K=16, G-REST2."""
