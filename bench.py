@@ -136,13 +136,16 @@ def main():
         st.sync()
         torch.cuda.synchronize()
         te = time.perf_counter()
-        stages, spmm_ms, nupd = st.stage_times()
+        stages, spmm_ms, nupd, spmm_cols = st.stage_times()
         vals = st.values()
         st.close()
         elem = 8 if prec == "fp64" else 4
-        byts = sum(spmm_bytes(n2, nnz, w, elem) for n2, nnz, w in sizes)
+        # the product multiplies every column of Z, or only the new ones when the kept A X
+        # is reused; the bytes follow the width actually multiplied
+        width = spmm_cols / max(1, nupd)
+        byts = sum(spmm_bytes(n2, nnz, width, elem) for n2, nnz, _ in sizes)
         return {"seconds": te - ts, "stages_ms": stages, "spmm_ms": spmm_ms, "updates": nupd,
-                "spmm_bytes": byts, "sizes": sizes, "lambda1": float(vals[0])}
+                "spmm_bytes": byts, "spmm_width": width, "sizes": sizes, "lambda1": float(vals[0])}
 
     log(args, f"timing {args.precision} path: warmup {args.warmup}, steps {args.steps}")
     main_res = run_path(args.precision)
@@ -186,10 +189,12 @@ def main():
         "dominant_stage": dominant,
         "roofline": {"kernel": "spmm (product with the updated operator)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(main_res["spmm_width"]),
                      "traffic_unit": "GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                      "algorithmic_gb_per_launch": round(main_res["spmm_bytes"] / max(1, len(main_res["sizes"])) / 1e9, 4),
-                     "avg_launch_ms": round(spmm_avg_ms, 4)},
+                     "avg_launch_ms": round(spmm_avg_ms, 4),
+                     "width": round(main_res["spmm_width"], 2)},
     }
     if cmp_res is not None:
         cv = args.steps / cmp_res["seconds"]
@@ -346,9 +351,10 @@ def cpu_baseline(wl, args):
                       f"n0={wl.n0}, FP64 NumPy/SciPy, {dt:.1f} s"}
 
 
-def measured_traffic():
+def measured_traffic(width):
     """HBM bytes per launch of the product kernel at this workload, from the committed
-    byte-counter summary, or None when the kernel source changed since it was taken."""
+    byte-counter summary, or None when the kernel source changed since it was taken or the
+    summary was taken at another product width."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "spmm_traffic_sbm_n1e6_k32.txt")
     src = os.path.join(ROOT, "paper_2603_19439_amd", "csrc", "spmm.hip")
@@ -359,7 +365,7 @@ def measured_traffic():
                 k, v = line.split("=", 1)
                 rec[k.strip()] = v.split()[0]
         cur = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
-        if rec.get("kernel_source_sha1") != cur:
+        if rec.get("kernel_source_sha1") != cur or abs(float(rec.get("spmm_width", -1)) - width) > 0.5:
             return None
         return float(rec["traffic_gb_per_launch"])
     except (OSError, KeyError, ValueError):

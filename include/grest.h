@@ -161,11 +161,14 @@ grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col);
  * 4 product with the updated operator, 5 projected matrix Z^T (A Z), 6 small
  * eigensolve, 7 back-projection.  grest_profile(st, 1) enables and clears the
  * totals; grest_stage_times returns the accumulated milliseconds per stage, the
- * milliseconds of the sparse product kernel alone, and the number of updates.
+ * milliseconds of the sparse product kernel alone, the number of updates, and the sum
+ * over those updates of the sparse product's width (the columns of Z it multiplied:
+ * all of them, or only the new ones when the kept adjacency product A X is reused).
+ * Any output pointer may be null.
  */
 grest_status grest_profile(grest_state* st, int32_t enable);
 grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stages, double* spmm_ms,
-                               int64_t* updates);
+                               int64_t* updates, int64_t* spmm_cols);
 
 /* Release the state and all its device memory. */
 void grest_destroy(grest_state* st);

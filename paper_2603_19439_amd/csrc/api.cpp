@@ -116,6 +116,10 @@ struct grest_state {
   hipEvent_t vev = nullptr;  // recorded once the validation result is on its way to the host
   int32_t deferred = 0;
   int64_t partial_elems = 0;
+  // adjacency only: aux[:, 0:K] holds A X for the current graph and tracked block (kept
+  // from the last back-projection), so the next update multiplies only the new columns
+  bool ax_valid = false;
+  int32_t ax_age = 0;  // updates since the last full-width product
 
   // optional stage timing with HIP events on the state's stream; two sets of events, used
   // by alternate updates, so that an update's events are read (at the next update's
@@ -128,6 +132,8 @@ struct grest_state {
   hipEvent_t kev[2][2] = {};  // around the (op Z) product alone
   double stage_ms[NSTAGE] = {};
   double spmm_ms = 0.0;
+  int64_t spmm_cols[2] = {0, 0};  // width of the (op Z) product per event set
+  int64_t prof_spmm_cols = 0;
   int64_t prof_updates = 0;
   bool marking = false;
 };
@@ -151,6 +157,7 @@ void prof_collect_slot(grest_state* st, int slot) {
   }
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, st->kev[slot][0], st->kev[slot][1]) == hipSuccess) st->spmm_ms += ms;
+  st->prof_spmm_cols += st->spmm_cols[slot];
   st->prof_updates += 1;
   st->prof_pending[slot] = false;
 }
@@ -269,6 +276,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   if (cap + 1 > (int64_t)4096 * 2048) cap = (int64_t)4096 * 2048 - 1;
   if (cap < need) return GREST_EINVAL;  // device scan limit
   HIPCHK(hipStreamSynchronize(st->stream));
+  st->ax_valid = false;  // the product buffer is reallocated below
   int64_t* rp_old = st->rp[st->gcur];
   void* z_old = st->z[st->zcur];
   void* sc_old = st->sc[st->gcur];
@@ -358,14 +366,19 @@ void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, int slot) {
   }
 }
 
+// With reuse, aux[:, 0:K] already holds (op) Xbar for the updated operator (the kept
+// product of the old operator with X plus Delta_1 X, added during the Delta Xbar stage),
+// and only the other columns of Z go through the sparse product.
 template <typename T>
 grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const int32_t* col, const T* sc,
-                           int base, int32_t* rank_slot) {
+                           int base, int32_t* rank_slot, bool reuse) {
   Blocks<T> b = blocks<T>(st);
   // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
+  const int c0 = reuse ? st->K : 0;
   mark_spmm(st, 0);
-  launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc, st->ldz, n2, st->D, b.aux, st->D, st->stream);
+  launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc + c0, st->ldz, n2, st->D - c0, b.aux + c0, st->D, st->stream);
   mark_spmm(st, 1);
+  st->spmm_cols[st->pslot] = st->D - c0;
   mark(st, 5);
   // H = Z^T (op Z)
   if constexpr (sizeof(T) == 4) {
@@ -388,6 +401,10 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   mark(st, 7);
   // X' = Z F on FP32 / FP64 MFMA (a memory-bound pass; FP32 keeps X orthonormal to 1e-7)
   launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
+  // A X' = (A Z) F, kept in aux[:, 0:K] for the next update (in place: every row of aux is
+  // read before its first K entries are written)
+  if (st->op == GREST_OP_ADJ)
+    launch_apply<T>(n2, b.aux, st->D, st->D, st->F, st->K, 1.0, 0.0, b.aux, st->D, st->stream);
   mark(st, 8);
   return GREST_OK;
 }
@@ -402,6 +419,10 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   if (st->m + 2 * nc > st->cap_m) CHK(grow_edges(st, st->m + 2 * nc));
   if (nc > st->cap_nc) CHK(alloc_change_arrays(st, std::max<int64_t>(nc, st->cap_nc * 2)));
   if (st->variant == GREST_RSVD && S > st->cap_s) CHK(alloc_sketch_arrays(st, std::max<int64_t>(S, 2 * st->cap_s)));
+  // reuse of the kept A X (adjacency), with a full-width product every kAxRefresh updates
+  // so that the rounding carried along by the recurrence stays bounded
+  constexpr int kAxRefresh = 16;
+  const bool reuse = st->op == GREST_OP_ADJ && st->ax_valid && st->ax_age + 1 < kAxRefresh;
 
   const int32_t* dei = ei;
   const int32_t* dej = ej;
@@ -456,7 +477,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // ---- Delta Xbar = Delta_1 X (Prop. 3) into W[:, 0:K] ----
   if (!nlap)
     launch_delta_mul<T>(0, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Zc, st->ldz, st->K,
-                        b.W, st->ldz, s);
+                        b.W, st->ldz, s, reuse ? b.aux : nullptr, st->D);
+  st->ax_valid = false;  // valid again only once this update commits
   mark(st, 2);
   // ---- augmentation block ----
   T* B2 = b.W + st->K;
@@ -525,7 +547,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   }
   mark(st, 4);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
-  CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->K, st->ranks + 1));
+  CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->K, st->ranks + 1, reuse));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -539,6 +561,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   st->zcur ^= 1;
   st->n = n2;
   st->m = m_new;
+  st->ax_valid = st->op == GREST_OP_ADJ;
+  st->ax_age = reuse ? st->ax_age + 1 : 0;
   return GREST_OK;
 }
 
@@ -576,12 +600,14 @@ grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
                             hipMemcpyDeviceToDevice, s));
     cholqr2<T>(st, n, Z, st->ldz, b, 0);
   }
-  CHK(rayleigh_ritz<T>(st, n, rp, col, sc, 0, st->ranks + 1));
+  CHK(rayleigh_ritz<T>(st, n, rp, col, sc, 0, st->ranks + 1, false));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   st->zcur ^= 1;
   st->has_pairs = true;
+  st->ax_valid = st->op == GREST_OP_ADJ;
+  st->ax_age = 0;
   if (st->pin->status & ST_NUMERIC) return GREST_ENUMERIC;
   return GREST_OK;
 }
@@ -618,7 +644,7 @@ grest_status set_pairs_impl(grest_state* st, const double* values, const double*
     HIPCHK(hipMemcpyAsync(tmp, X, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   T* Z = (T*)st->z[st->zcur];
-  T* packed = (T*)st->aux;
+  T* packed = (T*)st->z[st->zcur ^ 1];  // the other basis buffer is scratch between updates
   if (sizeof(T) == 8) HIPCHK(hipMemcpyAsync(packed, tmp, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
   else launch_convert<double, float>(tmp, (float*)packed, (int64_t)cnt, s);
   HIPCHK(hipMemcpy2DAsync(Z, st->ldz * sizeof(T), packed, K * sizeof(T), K * sizeof(T), n, hipMemcpyDeviceToDevice, s));
@@ -631,6 +657,7 @@ grest_status set_pairs_impl(grest_state* st, const double* values, const double*
   HIPCHK(hipMemcpy(st->theta, st->theta_pin, K * sizeof(double), hipMemcpyHostToDevice));
   dfree(tmp);
   st->has_pairs = true;
+  st->ax_valid = false;
   return GREST_OK;
 }
 
@@ -643,7 +670,7 @@ grest_status get_impl(grest_state* st, double* values, void* X, int32_t x_dtype,
   const int64_t n = st->n;
   const int K = st->K;
   const T* Z = (const T*)st->z[st->zcur];
-  T* packed = (T*)st->aux;
+  T* packed = (T*)st->z[st->zcur ^ 1];  // scratch between updates (the product buffer is kept)
   HIPCHK(hipMemcpy2DAsync(packed, K * sizeof(T), Z, st->ldz * sizeof(T), K * sizeof(T), n, hipMemcpyDeviceToDevice, s));
   const size_t cnt = (size_t)n * K;
   const void* src = packed;
@@ -899,18 +926,21 @@ grest_status grest_profile(grest_state* st, int32_t enable) {
   st->prof_pending[0] = st->prof_pending[1] = false;
   for (int i = 0; i < grest_state::NSTAGE; ++i) st->stage_ms[i] = 0.0;
   st->spmm_ms = 0.0;
+  st->prof_spmm_cols = 0;
   st->prof_updates = 0;
   return GREST_OK;
 }
 
 grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stages, double* spmm_ms,
-                               int64_t* updates) {
+                               int64_t* updates, int64_t* spmm_cols) {
   if (!st) return GREST_EINVAL;
   HIPCHK(hipStreamSynchronize(st->stream));
   prof_collect(st);
-  for (int i = 0; i < n_stages && i < grest_state::NSTAGE; ++i) stage_ms[i] = st->stage_ms[i];
+  if (stage_ms)
+    for (int i = 0; i < n_stages && i < grest_state::NSTAGE; ++i) stage_ms[i] = st->stage_ms[i];
   if (spmm_ms) *spmm_ms = st->spmm_ms;
   if (updates) *updates = st->prof_updates;
+  if (spmm_cols) *spmm_cols = st->prof_spmm_cols;
   return GREST_OK;
 }
 

@@ -72,10 +72,14 @@ void launch_spmm(int op, int64_t n, const int64_t* rp, const int32_t* col, const
 //   mode 2: B = Delta_2^T M              (rows n_old.., all columns, input rows c)
 //   mode 3: write Delta_2 densely into out[:, 0:S] (G-REST3)
 // For lap/nlap the degree and scaling changes are included (see spmm.hip).
+// Mode 0 with acc_io: also acc_io[r] += V[r] on old rows with entries, acc_io[r] = V[r] on
+// appended rows (turns a kept product of the old operator with X into the updated
+// operator's product with the padded block).
 template <typename T>
 void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
                       const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
-                      const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s);
+                      const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s,
+                      T* acc_io = nullptr, int64_t ldacc = 0);
 // nlap: V = S'A'S' Xbar - [S A S X; 0] computed row by row from both graphs
 template <typename T>
 void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,

@@ -170,13 +170,17 @@ __device__ inline T d2_diag(const DeltaArgs& a, int64_t node) {
   return T(2 * (double)a.maxdeg[0] - (double)deg);
 }
 
-// mode 0: out[r] = (Delta_T)[r, 0:n_old] X  for every r < n_old + n_new (zero rows included)
+// mode 0: out[r] = (Delta_T)[r, 0:n_old] X  for every r < n_old + n_new (zero rows included);
+//         with acc set, also acc[r] += out[r] on the old rows that have entries and
+//         acc[r] = out[r] on the appended rows (the product of the updated operator with the
+//         padded block, from the old operator's product kept in acc)
 // mode 1: out[r] = (Delta_T)[r, n_old:] Omega
 // mode 2: out[j] = (Delta_T)[n_old + j, :] M  (= (Delta_T,2^T M)[j] by symmetry)
 template <typename T, int VEC, int OP, int MODE>
 __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__ snew,
                                               const T* __restrict__ in, int64_t ldin, int w,
-                                              T* __restrict__ out, int64_t ldout, int lpr_shift) {
+                                              T* __restrict__ out, int64_t ldout, T* __restrict__ acc_io,
+                                              int64_t ldacc, int lpr_shift) {
   const int lpr = 1 << lpr_shift;
   const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int gl = (int)(gid & (lpr - 1));
@@ -231,6 +235,18 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
         }
       }
       vstore<T, VEC>(out + q * ldout + c0, acc);
+      if (MODE == 0 && acc_io) {
+        T* pa = acc_io + r * ldacc + c0;
+        if (r >= a.n_old) {
+          vstore<T, VEC>(pa, acc);
+        } else if (end > beg) {
+          T old[VEC];
+          vload<T, VEC>(pa, old);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) old[i] += acc[i];
+          vstore<T, VEC>(pa, old);
+        }
+      }
     }
   }
 }
@@ -312,35 +328,38 @@ void launch_spmm(int op, int64_t n, const int64_t* rp, const int32_t* col, const
 
 template <typename T, int OP, int MODE>
 static void delta_dispatch(int vec, const DeltaArgs& a, const T* snew, const T* in, int64_t ldin, int w,
-                           T* out, int64_t ldout, hipStream_t s) {
+                           T* out, int64_t ldout, T* acc_io, int64_t ldacc, hipStream_t s) {
   const int64_t rows = (MODE == 2) ? a.n_new : a.n_old + a.n_new;
   if (rows <= 0 || w <= 0) return;
   const int lpr = lanes_per_row(w, vec);
   const int g = grid_for(rows * lpr);
   if (vec == 16 / (int)sizeof(T))
-    k_delta<T, 16 / sizeof(T), OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, ilog2(lpr));
+    k_delta<T, 16 / sizeof(T), OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc,
+                                                          ilog2(lpr));
   else
-    k_delta<T, 1, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, ilog2(lpr));
+    k_delta<T, 1, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc, ilog2(lpr));
 }
 
 template <typename T, int OP>
 static void delta_mode(int mode, int vec, const DeltaArgs& a, const T* snew, const T* in, int64_t ldin,
-                       int w, T* out, int64_t ldout, hipStream_t s) {
-  if (mode == 0) delta_dispatch<T, OP, 0>(vec, a, snew, in, ldin, w, out, ldout, s);
-  else if (mode == 1) delta_dispatch<T, OP, 1>(vec, a, snew, in, ldin, w, out, ldout, s);
-  else if (mode == 2) delta_dispatch<T, OP, 2>(vec, a, snew, in, ldin, w, out, ldout, s);
+                       int w, T* out, int64_t ldout, T* acc_io, int64_t ldacc, hipStream_t s) {
+  if (mode == 0) delta_dispatch<T, OP, 0>(vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s);
+  else if (mode == 1) delta_dispatch<T, OP, 1>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s);
+  else if (mode == 2) delta_dispatch<T, OP, 2>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s);
   else if (a.n_new > 0) k_delta_dense2<T, OP><<<grid_for(a.n_new), BS, 0, s>>>(a, snew, out, ldout);
 }
 
 template <typename T>
 void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
                       const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
-                      const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s) {
+                      const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s, T* acc_io,
+                      int64_t ldacc) {
   DeltaArgs a{n_old, n_new, dptr, dcol, dsg, maxdeg};
-  const int vec = (mode == 3) ? 1 : pick_vec<T>(w, ldin, ldout, in, out);
-  if (op == OPK_ADJ) delta_mode<T, OPK_ADJ>(mode, vec, a, snew, in, ldin, w, out, ldout, s);
-  else if (op == OPK_LAP) delta_mode<T, OPK_LAP>(mode, vec, a, snew, in, ldin, w, out, ldout, s);
-  else delta_mode<T, OPK_NLAP>(mode, vec, a, snew, in, ldin, w, out, ldout, s);
+  int vec = (mode == 3) ? 1 : pick_vec<T>(w, ldin, ldout, in, out);
+  if (acc_io && vec > 1 && (ldacc % vec != 0 || ((uintptr_t)acc_io % 16) != 0)) vec = 1;
+  if (op == OPK_ADJ) delta_mode<T, OPK_ADJ>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s);
+  else if (op == OPK_LAP) delta_mode<T, OPK_LAP>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s);
+  else delta_mode<T, OPK_NLAP>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s);
 }
 
 template <typename T>
@@ -365,7 +384,7 @@ void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, co
                                int64_t, int64_t, int, T*, int64_t, hipStream_t);                      \
   template void launch_delta_mul<T>(int, int, int64_t, int64_t, const int64_t*, const int32_t*,        \
                                     const int8_t*, const int64_t*, const T*, const T*, int64_t, int,  \
-                                    T*, int64_t, hipStream_t);                                        \
+                                    T*, int64_t, hipStream_t, T*, int64_t);                           \
   template void launch_nlap_delta_x<T>(int64_t, int64_t, const int64_t*, const int32_t*, const T*,     \
                                        const int64_t*, const int32_t*, const T*, const T*, int64_t,   \
                                        int, T*, int64_t, hipStream_t);

@@ -57,7 +57,7 @@ _SIGS = [
     ("grest_get_graph", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("grest_profile", C.c_int, [C.c_void_p, C.c_int32]),
     ("grest_stage_times", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
-                                    C.POINTER(C.c_int64)]),
+                                    C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("grest_destroy", None, [C.c_void_p]),
     ("grest_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
     ("grest_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -228,13 +228,15 @@ class State:
         _check(lib().grest_profile(self._h, int(bool(enable))), "grest_profile")
 
     def stage_times(self):
-        """({stage: total ms}, total ms of the sparse-product kernel alone, updates timed)."""
+        """({stage: total ms}, total ms of the sparse-product kernel alone, updates timed,
+        summed width of those sparse products)."""
         ms = np.zeros(len(self.STAGES), dtype=np.float64)
         spmm = C.c_double()
         cnt = C.c_int64()
+        cols = C.c_int64()
         _check(lib().grest_stage_times(self._h, ms.ctypes.data_as(C.c_void_p), len(self.STAGES), C.byref(spmm),
-                                       C.byref(cnt)), "grest_stage_times")
-        return dict(zip(self.STAGES, ms.tolist())), spmm.value, cnt.value
+                                       C.byref(cnt), C.byref(cols)), "grest_stage_times")
+        return dict(zip(self.STAGES, ms.tolist())), spmm.value, cnt.value, cols.value
 
     def graph(self):
         n, m, _, _ = self.shape()

@@ -129,6 +129,39 @@ def test_laplacians_with_growth_fp64(op):
     run_trajectory(wl, 8, "rsvd", op, "fp64", 2, L=8, P=8)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kept_adjacency_product_matches_direct_product(prec):
+    """For the adjacency the product A X of the tracked block is kept from the last
+    back-projection and updated by Delta_1 X, so the sparse product only multiplies the new
+    columns (with a full-width product every 16 updates).  Against a second state that is
+    re-seeded with its own pairs before every update (which forces the full product) the
+    trajectories agree to rounding over 20 updates, across the refresh."""
+    wl = W.preset("sbm_n2000", scale=0.5, steps=20)
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, _ = O.leading_eigenpairs(A, 8, "adj")
+    sa = G.State(wl.rowptr0, wl.col0, k=8, variant="rsvd", precision=prec, L=8, P=8)
+    sb = G.State(wl.rowptr0, wl.col0, k=8, variant="rsvd", precision=prec, L=8, P=8)
+    sa.set_pairs(th0, X0)
+    sb.set_pairs(th0, X0)
+    tol_v, tol_s = (1e-11, 1e-9) if prec == "fp64" else (1e-5, 1e-3)
+    for t, d in enumerate(wl.deltas):
+        banner(f"kept product step {t + 1} prec={prec}")
+        om = W.omega(wl.cfg_id, 0, t + 1, d.n_new, 16) if d.n_new > 0 else None
+        sa.update_delta(d, om)
+        sa.sync()
+        sb.update_delta(d, om)
+        sb.sync()
+        va, Xa = sa.get()
+        vb, Xb = sb.get()
+        kk = M.gap_prefix(np.abs(vb), 8, 1e-3)
+        assert M.eig_rel_error(va, vb) <= tol_v, (t, M.eig_rel_error(va, vb))
+        if kk > 0:
+            assert M.subspace_sine(Xa[:, :kk], Xb[:, :kk]) <= tol_s
+        sb.set_pairs(vb, Xb)  # drops the kept product: the next update multiplies all columns
+    sa.close()
+    sb.close()
+
+
 # ------------------------------------------------------------------------------------
 # edge cases
 # ------------------------------------------------------------------------------------
