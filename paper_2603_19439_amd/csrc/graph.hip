@@ -13,8 +13,9 @@
 //      against the old row (binary search), per-row prefix counts of insertions and
 //      the new row length
 //   5. exclusive scan of the new lengths -> new row offsets
-//   6. a group of lanes per row: merge by ranks (old entries not deleted + inserted
-//      entries), fully parallel inside the row, so hub rows do not serialise.
+//   6. blocks of rows: rows without changes are copied as one coalesced range per block;
+//      rows with changes are merged by ranks (old entries not deleted + inserted
+//      entries) by a group of lanes, fully parallel inside the row.
 // Every write is bounds-checked against the row and the column capacity, so an
 // invalid change list (reported through the status word before anything reads the
 // new graph) can never write out of bounds.
@@ -246,47 +247,82 @@ __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, co
   }
 }
 
-// a group of LPR lanes per row (grid-stride): untouched rows are shifted copies, touched
-// rows a parallel merge by ranks
+// The merge works on blocks of BS consecutive rows.  Rows without changes are shifted
+// copies: the block's old column ids are one contiguous range, which the workgroup copies
+// element by element (coalesced), finding each element's row by a binary search over the
+// block's row starts in LDS.  Rows with changes are collected in LDS and merged by ranks
+// by groups of LPR lanes (fully parallel inside the row, so hub rows do not serialise).
 template <int LPR>
 __global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, const int64_t* rp_old,
                                                   const int32_t* col_old, const int64_t* dptr,
                                                   const int32_t* dcol, const int8_t* dsg,
                                                   const int32_t* dins, const int64_t* rp_new,
                                                   int32_t* col_new, int64_t cap_m) {
-  const int sl = threadIdx.x & (LPR - 1);
-  const int64_t grp = ((int64_t)blockIdx.x * BS + threadIdx.x) / LPR;
-  const int64_t ngrp = (int64_t)gridDim.x * (BS / LPR);
-  for (int64_t r = grp; r < n2; r += ngrp) {
-    const int64_t ob = r < n_old ? rp_old[r] : 0;
-    const int64_t olen = r < n_old ? rp_old[r + 1] - ob : 0;
-    const int64_t db = dptr[r];
-    const int64_t dlen = dptr[r + 1] - db;
-    const int64_t nb = rp_new[r];
-    const int64_t nlen = rp_new[r + 1] - nb;
-    if (nb < 0 || nlen <= 0 || nb + nlen > cap_m) continue;
-    if (dlen == 0) {
-      for (int64_t a = sl; a < olen && a < nlen; a += LPR) col_new[nb + a] = col_old[ob + a];
-      continue;
+  __shared__ int64_t s_ob[BS + 1];  // old row starts of the block (rows >= n_old: empty)
+  __shared__ int64_t s_shift[BS];   // new start - old start
+  __shared__ int s_list[BS];        // rows with changes (block offsets)
+  __shared__ int s_cnt;
+  const int t = threadIdx.x;
+  const int sl = t & (LPR - 1), grp = t / LPR;
+  const int64_t old_end = rp_old[n_old];
+  for (int64_t r0 = (int64_t)blockIdx.x * BS; r0 < n2; r0 += (int64_t)gridDim.x * BS) {
+    if (t == 0) s_cnt = 0;
+    const int64_t r = r0 + t;
+    s_ob[t] = r < n_old ? rp_old[r] : old_end;
+    if (t == BS - 1) s_ob[BS] = r + 1 < n_old ? rp_old[r + 1] : old_end;
+    __syncthreads();
+    if (r < n2) {
+      s_shift[t] = rp_new[r] - s_ob[t];
+      if (dptr[r + 1] > dptr[r]) s_list[atomicAdd(&s_cnt, 1)] = t;
+    } else {
+      s_shift[t] = -1;
     }
-    const int64_t tot_ins = (int64_t)dins[db + dlen - 1] + (dsg[db + dlen - 1] > 0 ? 1 : 0);
-    for (int64_t a = sl; a < olen; a += LPR) {
-      const int32_t c = col_old[ob + a];
-      const int64_t p = lower_bound_i32(dcol + db, dlen, c);
-      const bool hit = p < dlen && dcol[db + p] == c;
-      if (hit && dsg[db + p] < 0) continue;  // deleted
-      const int64_t insb = p < dlen ? (int64_t)dins[db + p] : tot_ins;
-      const int64_t pos = a - (p - insb) + insb;
-      if (pos >= 0 && pos < nlen) col_new[nb + pos] = c;
+    __syncthreads();
+    // shifted copies of the rows without changes
+    const int64_t e0 = s_ob[0], e1 = s_ob[BS];
+    for (int64_t e = e0 + t; e < e1; e += BS) {
+      int lo = 0, hi = BS;  // last row whose start is <= e
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_ob[mid] <= e) lo = mid; else hi = mid;
+      }
+      const int64_t rr = r0 + lo;
+      if (rr < n2 && dptr[rr + 1] == dptr[rr]) {
+        const int64_t dst = e + s_shift[lo];
+        if (dst >= 0 && dst < cap_m) col_new[dst] = col_old[e];
+      }
     }
-    for (int64_t b = sl; b < dlen; b += LPR) {
-      if (dsg[db + b] < 0) continue;
-      const int32_t c = dcol[db + b];
-      const int64_t q = r < n_old ? lower_bound_i32(col_old + ob, olen, c) : 0;
-      const int64_t insb = dins[db + b];
-      const int64_t pos = q - (b - insb) + insb;
-      if (pos >= 0 && pos < nlen) col_new[nb + pos] = c;
+    // rows with changes: merge by ranks
+    const int cnt = s_cnt;
+    for (int li = grp; li < cnt; li += BS / LPR) {
+      const int64_t rr = r0 + s_list[li];
+      const int64_t ob = s_ob[s_list[li]];
+      const int64_t olen = (rr < n_old ? s_ob[s_list[li] + 1] : ob) - ob;
+      const int64_t db = dptr[rr];
+      const int64_t dlen = dptr[rr + 1] - db;
+      const int64_t nb = rp_new[rr];
+      const int64_t nlen = rp_new[rr + 1] - nb;
+      if (nb < 0 || nlen <= 0 || nb + nlen > cap_m) continue;
+      const int64_t tot_ins = (int64_t)dins[db + dlen - 1] + (dsg[db + dlen - 1] > 0 ? 1 : 0);
+      for (int64_t a = sl; a < olen; a += LPR) {
+        const int32_t c = col_old[ob + a];
+        const int64_t p = lower_bound_i32(dcol + db, dlen, c);
+        const bool hit = p < dlen && dcol[db + p] == c;
+        if (hit && dsg[db + p] < 0) continue;  // deleted
+        const int64_t insb = p < dlen ? (int64_t)dins[db + p] : tot_ins;
+        const int64_t pos = a - (p - insb) + insb;
+        if (pos >= 0 && pos < nlen) col_new[nb + pos] = c;
+      }
+      for (int64_t b = sl; b < dlen; b += LPR) {
+        if (dsg[db + b] < 0) continue;
+        const int32_t c = dcol[db + b];
+        const int64_t q = rr < n_old ? lower_bound_i32(col_old + ob, olen, c) : 0;
+        const int64_t insb = dins[db + b];
+        const int64_t pos = q - (b - insb) + insb;
+        if (pos >= 0 && pos < nlen) col_new[nb + pos] = c;
+      }
     }
+    __syncthreads();  // the block's LDS is reused by the next block
   }
 }
 
@@ -396,9 +432,9 @@ void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const
                       const int64_t* rp_new, int32_t* col_new, int64_t cap_m, hipStream_t s) {
   int64_t n2 = n_old + n_new;
   if (n2 <= 0) return;
-  constexpr int LPR = 16;  // about one pass over a row of mean length
-  k_csr_merge<LPR><<<grid_for(n2 * LPR, BS, 1 << 15), BS, 0, s>>>(n_old, n2, rp_old, col_old, dptr, dcol, dsg, dins,
-                                                                  rp_new, col_new, cap_m);
+  constexpr int LPR = 16;  // about one pass over a changed row of mean length
+  k_csr_merge<LPR><<<grid_for(n2, BS, 1 << 16), BS, 0, s>>>(n_old, n2, rp_old, col_old, dptr, dcol, dsg, dins,
+                                                            rp_new, col_new, cap_m);
 }
 
 void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* dinv_sqrt32,

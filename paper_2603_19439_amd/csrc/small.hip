@@ -68,8 +68,8 @@ extern "C" int grest_debug_eig(double* out) {
 
 namespace {
 
-constexpr int EB = 1024;   // threads of the one-workgroup kernels (four waves per SIMD)
-constexpr int NW = EB / GREST_WAVE;
+constexpr int TRI_WAVES = 8;  // waves of the tridiagonalisation workgroup (two per SIMD)
+constexpr int PCH_WAVES = 16;  // waves of the pivoted Cholesky workgroup
 constexpr int MAXN = 128;  // largest order
 constexpr double EPS = 2.220446049250313e-16;
 
@@ -157,14 +157,14 @@ __device__ __forceinline__ double vec_elem(const double (&x)[C], int j) {
   return readlane_d(pick<C>(x, j >> 6), j & (GREST_WAVE - 1));
 }
 // this wave's rows of column j (uniform) to buf[i]
-template <int RW, int C>
+template <int RW, int C, int NWV>
 __device__ __forceinline__ void column_to_lds(const double (&A)[RW][C], int j, int wv, int n, double* buf) {
   const int lane = threadIdx.x & (GREST_WAVE - 1);
   if (lane == (j & (GREST_WAVE - 1))) {
     const int cj = j >> 6;
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
-      const int i = wv + NW * r;
+      const int i = wv + NWV * r;
       if (i < n) buf[i] = pick<C>(A[r], cj);
     }
   }
@@ -189,8 +189,9 @@ __device__ __forceinline__ bool chosen_bit(uint64_t c0, uint64_t c1, int j) {
 }
 
 template <int M, bool CL>
-__global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const double* Cg, int kc, double tol,
+__global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const double* G, const double* Cg, int kc, double tol,
                                               double* Mout, int32_t* rank_out, int32_t* status) {
+  constexpr int NW = PCH_WAVES, EB = PCH_WAVES * GREST_WAVE;
   constexpr int CC = M / GREST_WAVE, RW = M / NW, LP = M + 1;
   __shared__ double Rrow[M * LP];  // pivot rows by step (pitch M + 1); later X = R^{-1}
   __shared__ int perm[M], iperm[M];
@@ -261,8 +262,8 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
     if (!(piv > thr)) break;  // also stops on NaN
     if (p < 64) ch0 |= 1ull << p; else ch1 |= 1ull << (p - 64);
     double* rowk = Rrow + k * LP;
-    column_to_lds<RW, CC>(S, p, wv, m, rowk);
-    if (tid == 0) { perm[k] = p; iperm[p] = k; rdg[k] = sqrt(piv); }
+    column_to_lds<RW, CC, NW>(S, p, wv, m, rowk);
+    if (tid == 0) { perm[k] = p; iperm[p] = k; rdg[k] = piv; }  // square roots after the loop
     __syncthreads();
     double rp[CC];
 #pragma unroll
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
       const int j = lane + GREST_WAVE * c;
       rp[c] = j < m ? rowk[j] : 0.0;
     }
-    const double ip = 1.0 / piv;
+    const double ip = recip(piv);
     double f[RW];
 #pragma unroll
     for (int q = 0; q < RW; ++q) f[q] = rowk[wv + NW * q];
@@ -286,10 +287,10 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
     r = k + 1;
   }
   PHASE_MARK(11);
-  // X = R^{-1}, R[a][b] = Rrow[a][perm[b]] / rdg[a] (upper triangular in pivot order).
-  // Column j of X is an independent solve: for i descending, X[i][j] /= R[i][i], then
-  // X[a][j] -= R[a][i] X[i][j] for a < i.
-  for (int a = tid; a < M; a += EB) rdi[a] = a < r ? 1.0 / rdg[a] : 0.0;
+  // X = R^{-1}, R[a][b] = Rrow[a][perm[b]] / sqrt(piv_a) (upper triangular in pivot
+  // order).  Column j of X is an independent solve: for i descending, X[i][j] /= R[i][i],
+  // then X[a][j] -= R[a][i] X[i][j] for a < i.
+  for (int a = tid; a < M; a += EB) rdi[a] = a < r ? 1.0 / sqrt(rdg[a]) : 0.0;
   __syncthreads();
   {
     // Y = X^T in the distributed layout: row j of Y is column j of X, an independent solve
@@ -372,20 +373,22 @@ __global__ void __launch_bounds__(EB) k_pchol(int m, const double* G, const doub
 // 1. tridiagonalisation T = Q^T A Q, Q = P_0 ... P_{n-3}, P_k = I - beta_k v_k v_k^T
 // ------------------------------------------------------------------------------------
 // A lives in registers (see above).  Iteration k:
-//   every wave reads column k (gathered in LDS at the end of the previous iteration) and
-//   forms the reflector itself (identical arithmetic in every wave, so nothing needs to
-//   be published); v is zero outside rows k+1 .. n-1, so the full-width updates below
+//   every wave holds column k in registers and forms the reflector itself (identical
+//   arithmetic in every wave, so nothing needs to be published); v is zero outside rows
+//   k+1 .. n-1, so the full-width updates below
 //   leave the rest of A unchanged;
 //   p = beta A v: each wave sums over its rows (symmetry turns row sums into column
 //   sums), the per-wave partial vectors meet in LDS and are summed in a fixed order;
 //   w = p - (beta p^T v / 2) v;  A <- A - v w^T - w v^T in registers;
-//   column k+1 of the updated A goes to LDS for the next iteration.
-// Two barriers per iteration.
+//   column k+1 of A before the reflection is published with the partial sums, and every
+//   wave forms the reflected column k+1 from it and v, w itself.
+// One barrier per iteration (the LDS buffers alternate with k).
 template <int M>
-__global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int32_t* rank_p, const double* H,
+__global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, int base, const int32_t* rank_p, const double* H,
                                                 double* work, int32_t* status) {
+  constexpr int NW = TRI_WAVES;
   constexpr int C = M / GREST_WAVE, RW = M / NW;
-  __shared__ double pwv[NW][M];
+  __shared__ double pwv[2][NW][M];
   __shared__ double colb[2][M];
   __shared__ double vwb[NW][2][M];  // each wave's own copy of v and w
   __shared__ double sdg[M], sod[M], shb[M];
@@ -414,44 +417,52 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
     }
   }
   if (bad) atomicOr(status, ST_NONFINITE_H);
-  if (n >= 1) column_to_lds<RW, C>(A, 0, wv, n, colb[0]);
+  // column k of the current matrix is kept in registers by every wave (colk); column 0 is
+  // gathered through LDS once
+  if (n >= 1) column_to_lds<RW, C, NW>(A, 0, wv, n, colb[1]);
   __syncthreads();
+  double colk[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int j = lane + GREST_WAVE * c;
+    colk[c] = j < n ? colb[1][j] : 0.0;
+  }
   PHASE_MARK(0);
   SECT_DECL
 
   for (int k = 0; k + 2 < n; ++k) {
-    const double* col = colb[k & 1];
+    const int pb = k & 1;
     // reflector annihilating column k below k+1
-    double x[C];
     double s2 = 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int j = lane + GREST_WAVE * c;
-      x[c] = (j > k + 1 && j < n) ? col[j] : 0.0;
-      s2 = fma(x[c], x[c], s2);
+      const double xc = (j > k + 1 && j < n) ? colk[c] : 0.0;
+      s2 = fma(xc, xc, s2);
     }
-    const double x0 = col[k + 1];
+    const double x0 = vec_elem<C>(colk, k + 1);
     const double sigma = wave_sum_d(s2);
     double beta = 0.0, v0 = 1.0, ek = x0;
     if (sigma > 0.0) {
       const double mu = sqrt(x0 * x0 + sigma);
-      v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma / (x0 + mu));
-      beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+      v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma * recip(x0 + mu));
+      beta = 2.0 * v0 * v0 * recip(sigma + v0 * v0);
       ek = mu;
     }
-    const double inv = 1.0 / v0;
+    const double inv = recip(v0);
     SECT(0);
     double v[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int j = lane + GREST_WAVE * c;
-      v[c] = (j == k + 1) ? 1.0 : x[c] * inv;
+      v[c] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < n) ? colk[c] * inv : 0.0);
     }
     if (wv == 0) {
+      const double dk = vec_elem<C>(colk, k);
 #pragma unroll
       for (int c = 0; c < C; ++c) R[(size_t)k * MAXN + lane + GREST_WAVE * c] = v[c];
       if (C == 1) R[(size_t)k * MAXN + lane + GREST_WAVE] = 0.0;
-      if (lane == 0) { sdg[k] = col[k]; sod[k] = ek; shb[k] = beta; }
+      if (lane == 0) { sdg[k] = dk; sod[k] = ek; shb[k] = beta; }
     }
     double vr[RW];
     if (beta != 0.0) {
@@ -469,27 +480,29 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
 #pragma unroll
         for (int c = 0; c < C; ++c) pp[c] = fma(A[r][c], vr[r], pp[c]);
 #pragma unroll
-      for (int c = 0; c < C; ++c) pwv[wv][lane + GREST_WAVE * c] = pp[c];
+      for (int c = 0; c < C; ++c) pwv[pb][wv][lane + GREST_WAVE * c] = pp[c];
     }
+    // column k+1 before this reflection, for the next reflector
+    column_to_lds<RW, C, NW>(A, k + 1, wv, n, colb[pb]);
     SECT(1);
-    __syncthreads();
+    __syncthreads();  // the only barrier of the step (buffers alternate with k)
     SECT(2);
     if (beta != 0.0) {
-      double p[C], w[C];
+      double w[C];  // first p = beta A v, then w = p - K v
       double pv = 0.0;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const int j = lane + GREST_WAVE * c;
         double sum = 0.0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) sum += pwv[q][j];
-        p[c] = (j > k && j < n) ? beta * sum : 0.0;
-        pv = fma(p[c], v[c], pv);
+        for (int q = 0; q < NW; ++q) sum += pwv[pb][q][j];
+        w[c] = (j > k && j < n) ? beta * sum : 0.0;
+        pv = fma(w[c], v[c], pv);
       }
       const double Kc = 0.5 * beta * wave_sum_d(pv);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        w[c] = fma(-Kc, v[c], p[c]);
+        w[c] = fma(-Kc, v[c], w[c]);
         vwb[wv][1][lane + GREST_WAVE * c] = w[c];
       }
       wave_lds_fence();
@@ -502,29 +515,36 @@ __global__ void __launch_bounds__(EB) k_tridiag(int d_full, int base, const int3
       for (int r = 0; r < RW; ++r)
 #pragma unroll
         for (int c = 0; c < C; ++c) A[r][c] = fma(-vr[r], w[c], fma(-wr[r], v[c], A[r][c]));
+      // the next column after the reflection: a[:, k+1] - v w[k+1] - w (v[k+1] = 1)
+      const double wk1 = vec_elem<C>(w, k + 1);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int j = lane + GREST_WAVE * c;
+        colk[c] = j < n ? colb[pb][j] - fma(v[c], wk1, w[c]) : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int j = lane + GREST_WAVE * c;
+        colk[c] = j < n ? colb[pb][j] : 0.0;
+      }
     }
     SECT(4);
-    column_to_lds<RW, C>(A, k + 1, wv, n, colb[(k + 1) & 1]);
-    SECT(5);
-    __syncthreads();
-    SECT(6);
   }
   SECT_WRITE(20);
   PHASE_MARK(1);
-  // the last two diagonal entries and the last off-diagonal one: column n-2 is in LDS
-  // (n >= 3) or is gathered here, then column n-1
+  // the last two diagonal entries and the last off-diagonal one: column n-2 is colk, then
+  // column n-1 is gathered
+  __syncthreads();  // every read of colb in the loop is done
   if (n >= 2) {
-    if (n == 2) {
-      column_to_lds<RW, C>(A, 0, wv, n, colb[0]);
-      __syncthreads();
-    }
-    if (tid == 0) { sdg[n - 2] = colb[n & 1][n - 2]; sod[n - 2] = colb[n & 1][n - 1]; shb[n - 2] = 0.0; }
+    const double d2 = vec_elem<C>(colk, n - 2), e2 = vec_elem<C>(colk, n - 1);
+    if (tid == 0) { sdg[n - 2] = d2; sod[n - 2] = e2; shb[n - 2] = 0.0; }
+    column_to_lds<RW, C, NW>(A, n - 1, wv, n, colb[0]);
     __syncthreads();
-    column_to_lds<RW, C>(A, n - 1, wv, n, colb[(n - 1) & 1]);
-    __syncthreads();
-    if (tid == 0) { sdg[n - 1] = colb[(n - 1) & 1][n - 1]; sod[n - 1] = 0.0; shb[n - 1] = 0.0; }
+    if (tid == 0) { sdg[n - 1] = colb[0][n - 1]; sod[n - 1] = 0.0; shb[n - 1] = 0.0; }
   } else if (n == 1) {
-    if (tid == 0) { sdg[0] = colb[0][0]; sod[0] = 0.0; shb[0] = 0.0; }
+    const double d0 = vec_elem<C>(colk, 0);
+    if (tid == 0) { sdg[0] = d0; sod[0] = 0.0; shb[0] = 0.0; }
   }
   __syncthreads();
   if (wv == 0) {
@@ -863,8 +883,8 @@ void pchol_launch(int m, const double* G, const double* C, int kc, double tol, d
   }();
   (void)attr;
   const size_t dyn = (size_t)kc * m * sizeof(double);
-  if (kc > 0 && dyn <= kDynMax) k_pchol<M, true><<<1, EB, dyn, s>>>(m, G, C, kc, tol, Mout, rank, status);
-  else k_pchol<M, false><<<1, EB, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
+  if (kc > 0 && dyn <= kDynMax) k_pchol<M, true><<<1, PCH_WAVES * GREST_WAVE, dyn, s>>>(m, G, C, kc, tol, Mout, rank, status);
+  else k_pchol<M, false><<<1, PCH_WAVES * GREST_WAVE, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
 }
 
 void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
@@ -878,8 +898,8 @@ bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H
                       double drop_tol, double* theta, double* F, int32_t* kept, double* work,
                       int32_t* status, hipStream_t s) {
   if (d_full < 1 || d_full > MAXN || kk < 1 || kk > MAXN) return false;
-  if (d_full <= 64) k_tridiag<64><<<1, EB, 0, s>>>(d_full, base, rank, H, work, status);
-  else k_tridiag<128><<<1, EB, 0, s>>>(d_full, base, rank, H, work, status);
+  if (d_full <= 64) k_tridiag<64><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, H, work, status);
+  else k_tridiag<128><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, H, work, status);
   k_bisect<<<d_full, GREST_WAVE, 0, s>>>(work);
   k_eigvec<<<kk, GREST_WAVE, 0, s>>>(d_full, which, kk, drop_tol, work, theta, F, kept, status);
   k_backtr<<<kk, GREST_WAVE, 0, s>>>(d_full, kk, work, F);
