@@ -34,7 +34,7 @@ K, L, P = 32, 32, 32
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--compare", default="fp32", help="second path timed beside the headline ('' to skip)")
@@ -92,7 +92,7 @@ def main():
         torch.cuda.synchronize()
         log(args, f"reference copy: {args.calib_copy_mib} MiB read and {args.calib_copy_mib} MiB written")
         del src, dst
-    n_steps = max(10, args.steps, args.warmup)
+    n_steps = max(16, args.steps, args.warmup)
     t0 = time.time()
     wl = W.preset("sbm_n1e6", scale=args.scale, steps=n_steps)
     log(args, f"workload generated in {time.time() - t0:.1f}s: n0={wl.n0} nnz={wl.col0.size}")
@@ -353,8 +353,11 @@ def cpu_baseline(wl, args):
 
 def measured_traffic(width):
     """HBM bytes per launch of the product kernel at this workload, from the committed
-    byte-counter summary, or None when the kernel source changed since it was taken or the
-    summary was taken at another product width."""
+    byte-counter summary: measured at the 64-column (kept A X) and 96-column (full) widths,
+    and linear in the width in between (a fixed part for the graph, a per-column part for
+    the gathered rows), so the mean width of the timed updates picks its point on that
+    line.  None when the kernel source changed since the counters were taken or the width
+    lies outside the measured range."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "spmm_traffic_sbm_n1e6_k32.txt")
     src = os.path.join(ROOT, "paper_2603_19439_amd", "csrc", "spmm.hip")
@@ -365,10 +368,16 @@ def measured_traffic(width):
                 k, v = line.split("=", 1)
                 rec[k.strip()] = v.split()[0]
         cur = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
-        if rec.get("kernel_source_sha1") != cur or abs(float(rec.get("spmm_width", -1)) - width) > 0.5:
+        if rec.get("kernel_source_sha1") != cur:
             return None
-        return float(rec["traffic_gb_per_launch"])
-    except (OSError, KeyError, ValueError):
+        pts = sorted((float(w), float(t)) for w, t in (p.split(":") for p in rec["traffic_points"].split(",")))
+        (w0, t0), (w1, t1) = pts[0], pts[-1]
+        if not (w0 - 0.5 <= width <= w1 + 0.5):
+            return None
+        if w1 == w0:
+            return t0
+        return round(t0 + (t1 - t0) * (width - w0) / (w1 - w0), 4)
+    except (OSError, KeyError, ValueError, IndexError):
         return None
 
 
