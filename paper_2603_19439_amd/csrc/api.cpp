@@ -342,16 +342,16 @@ Blocks<T> blocks(grest_state* st) {
 // rank-revealing pivoted Cholesky in FP64, and writes W <- (W - Xbar C) M in one pass.
 // The kept column counts of the two rounds go to ranks[slot] and ranks[slot + 1].
 template <typename T>
-void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, T* W, int64_t ldw, int w, int slot) {
+void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T* W, int64_t ldw, int w, int slot) {
   hipStream_t s = st->stream;
   for (int round = 0; round < 2; ++round) {
-    if (!launch_pip<T>(n, X, ldx, st->K, W, ldw, w, st->partial, st->C1, st->Gm, s)) {
-      if (st->prec == GREST_FP64) launch_tn<T, true>(n, X, ldx, st->K, W, ldw, w, st->partial, st->C1, s);
-      else launch_tn<T, false>(n, X, ldx, st->K, W, ldw, w, st->partial, st->C1, s);
+    if (!launch_pip<T>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s)) {
+      if (st->prec == GREST_FP64) launch_tn<T, true>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
+      else launch_tn<T, false>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
       launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, s);
     }
-    launch_pchol(w, st->Gm, st->C1, st->K, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
-    launch_apply2<T>(n, X, ldx, st->K, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, s);
+    launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
+    launch_apply2<T>(n, X, ldx, kx, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, s);
   }
 }
 
@@ -369,9 +369,12 @@ void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, int slot) {
 // With reuse, aux[:, 0:K] already holds (op) Xbar for the updated operator (the kept
 // product of the old operator with X plus Delta_1 X, added during the Delta Xbar stage),
 // and only the other columns of Z go through the sparse product.
+// The basis may hold two packed blocks with dropped columns between them: the small
+// eigensolve then works on the kept columns [0, base + *rank_slot) and
+// [seg2, seg2 + *rank2).
 template <typename T>
 grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const int32_t* col, const T* sc,
-                           int base, int32_t* rank_slot, bool reuse) {
+                           int base, int32_t* rank_slot, bool reuse, int seg2 = 0, const int32_t* rank2 = nullptr) {
   Blocks<T> b = blocks<T>(st);
   // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
   const int c0 = reuse ? st->K : 0;
@@ -393,7 +396,7 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   mark(st, 6);
   const int which = st->op == GREST_OP_ADJ ? 0 : 1;
   if (!launch_small_eig(st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
-                        st->status, st->stream)) {
+                        st->status, st->stream, seg2, rank2)) {
     snprintf(g_last_error, sizeof(g_last_error), "projected order %d outside the small eigensolver's range", st->D);
     return GREST_EINVAL;
   }
@@ -471,26 +474,41 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   Blocks<T> b = blocks<T>(st);
   const T* sc_new = (const T*)st->sc[gn];
   const bool nlap = st->op == GREST_OP_NLAP;
+  const bool rsvd = st->variant == GREST_RSVD;
+  const int K = st->K;
+  // Basis layout.  G-REST2/3: Z = [Xbar | Delta Xbar | augmentation], the last two
+  // projected against Xbar and orthonormalised together.  RSVD: Z = [Xbar | R | Delta
+  // Xbar]; the sketch basis R = M U_L is orthonormal and orthogonal to Xbar by
+  // construction (M comes out of two projections and CholQR2, U_L is orthonormal), so
+  // only Delta Xbar is projected, against [Xbar R], which spans the same subspace as
+  // projecting [Delta Xbar, R] against Xbar (Sec. 3.5) with a third of the Gram work.
+  T* dX = rsvd ? b.Zc + K + st->L : b.W;  // Delta Xbar
+  T* Rb = b.Zc + K;                        // R (RSVD)
+  auto project = [&]() {
+    if (rsvd) orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0);
+    else orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0);
+  };
   // ---- pad Xbar (Alg. 2): zero the appended rows of the whole basis row ----
   mark(st, 1);
   launch_fill_rows<T>(b.Zc, st->ldz, n, S, st->ldz, s);
-  // ---- Delta Xbar = Delta_1 X (Prop. 3) into W[:, 0:K] ----
+  // ---- Delta Xbar = Delta_1 X (Prop. 3) ----
   if (!nlap)
-    launch_delta_mul<T>(0, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Zc, st->ldz, st->K,
-                        b.W, st->ldz, s, reuse ? b.aux : nullptr, st->D);
+    launch_delta_mul<T>(0, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Zc, st->ldz, K, dX,
+                        st->ldz, s, reuse ? b.aux : nullptr, st->D);
   st->ax_valid = false;  // valid again only once this update commits
   mark(st, 2);
   // ---- augmentation block ----
-  T* B2 = b.W + st->K;
-  const int w2 = st->Dw - st->K;
   if (st->variant == GREST_G3) {
+    T* B2 = b.W + K;
+    const int w2 = st->Dw - K;
     launch_fill_rows<T>(B2, st->ldz, 0, n2, w2, s);
     if (S > 0)
       launch_delta_mul<T>(3, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, nullptr, 0, w2, B2,
                           st->ldz, s);
-  } else if (st->variant == GREST_RSVD) {
+  } else if (rsvd) {
     if (S == 0) {
-      launch_fill_rows<T>(B2, st->ldz, 0, n2, w2, s);
+      launch_fill_rows<T>(Rb, st->ldz, 0, n2, st->L, s);
+      launch_fill_bytes0(st->ranks + 4, sizeof(int32_t), s);  // no sketch columns kept
     } else {
       // S.1: Y = (I - Pi) Delta_2 Omega
       const int Ls = st->Ls;
@@ -507,7 +525,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
                           Ls, Ls, b.Y, st->ldy, s);
       // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds
-      orth_against<T>(st, n2, b.Zc, st->ldz, b.Y, st->ldy, Ls, 2);
+      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2);
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
       launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Y, st->ldy, Ls,
                           (T*)st->bt, Ls, s);
@@ -519,13 +537,13 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
         snprintf(g_last_error, sizeof(g_last_error), "sketch order %d outside the small eigensolver's range", Ls);
         return GREST_EINVAL;
       }
-      // S.4: R = M U_L
-      launch_apply<T>(n2, b.Y, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, B2, st->ldz, s);
+      // S.4: R = M U_L (its kept columns first, the dropped ones zero)
+      launch_apply<T>(n2, b.Y, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, Rb, st->ldz, s);
     }
   }
   mark(st, 3);
-  // ---- projection (I - Xbar Xbar^T) W, twice; CholQR2 of W ----
-  if (!nlap) orth_against<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, 0);
+  // ---- projection (I - Pi) twice and CholQR2 ----
+  if (!nlap) project();
 
   HIPCHK(hipEventSynchronize(st->vev));
   // every earlier update has finished: collect the numerical status and the stage times
@@ -542,12 +560,15 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
 
   if (nlap) {
     launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
-                           st->col[gn], sc_new, b.Zc, st->ldz, st->K, b.W, st->ldz, s);
-    orth_against<T>(st, n2, b.Zc, st->ldz, b.W, st->ldz, st->Dw, 0);
+                           st->col[gn], sc_new, b.Zc, st->ldz, K, dX, st->ldz, s);
+    project();
   }
   mark(st, 4);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
-  CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, st->K, st->ranks + 1, reuse));
+  if (rsvd)  // kept columns: [0, K + r_R) and [K + L, K + L + r_dX)
+    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 4, reuse, K + st->L, st->ranks + 1));
+  else
+    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 1, reuse));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));

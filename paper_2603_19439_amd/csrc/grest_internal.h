@@ -138,10 +138,14 @@ void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, i
 // value) get theta 0 and a zero column, and *kept receives the number of the others.
 // work: >= eig_work_elems(d_full) doubles.  Returns false (nothing launched) unless
 // 1 <= d_full <= 128 and 1 <= kk <= 128.
+// With rank2 the matrix is H restricted to the indices [0, base + *rank) followed by
+// [seg2, seg2 + *rank2) (a basis of two packed blocks with dropped columns in between);
+// F rows follow the same indices and the other rows are zero.
 int64_t eig_work_elems(int d);
 bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which,
                       int kk, double drop_tol, double* theta, double* F, int32_t* kept,
-                      double* work, int32_t* status, hipStream_t s);
+                      double* work, int32_t* status, hipStream_t s, int seg2 = 0,
+                      const int32_t* rank2 = nullptr);
 // H = 0.5 (H + H^T) of a d x d matrix in place
 void launch_symmetrize(int d, double* H, hipStream_t s);
 template <typename T>

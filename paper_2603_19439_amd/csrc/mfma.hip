@@ -886,6 +886,9 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
   double* partG = partial + (size_t)g * kx * w;
   using Tcx = typename std::conditional<sizeof(T) == 8, double, float>::type;
   if (TX == 2 && TWt == 4) pip_launch<T, Tcx, 2, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else if (TX == 4 && TWt == 2) pip_launch<T, Tcx, 4, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else if (TX == 3 && TWt == 2) pip_launch<T, Tcx, 3, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  else if (TX == 2 && TWt == 1) pip_launch<T, Tcx, 2, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else if (TX == 2 && TWt == 2) pip_launch<T, Tcx, 2, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else if (TX == 1 && TWt == 4) pip_launch<T, Tcx, 1, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
   else if (TX == 1 && TWt == 2) pip_launch<T, Tcx, 1, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);

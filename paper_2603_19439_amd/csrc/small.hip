@@ -74,7 +74,7 @@ constexpr int MAXN = 128;  // largest order
 constexpr double EPS = 2.220446049250313e-16;
 
 // work layout of the eigensolver (doubles)
-constexpr int W_HDR = 0;               // n, lo, hi, ||T||, pivmin
+constexpr int W_HDR = 0;               // n, lo, hi, ||T||, pivmin, s1, seg2 (the index map)
 constexpr int W_DG = 8;                // diagonal of T
 constexpr int W_OD = W_DG + MAXN;      // off-diagonal of T
 constexpr int W_E2 = W_OD + MAXN;      // squared off-diagonal
@@ -383,9 +383,15 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
 //   column k+1 of A before the reflection is published with the partial sums, and every
 //   wave forms the reflected column k+1 from it and v, w itself.
 // One barrier per iteration (the LDS buffers alternate with k).
+// The matrix reduced is H restricted to the index set [0, s1) + [seg2, seg2 + r2) with
+// s1 = base + rank_p[0] and r2 = rank2_p[0] (the kept columns of a basis made of two
+// packed blocks); index i of the reduced matrix is H index i for i < s1, else
+// seg2 + i - s1.  The back-transform writes F through the same map.
 template <int M>
-__global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, int base, const int32_t* rank_p, const double* H,
-                                                double* work, int32_t* status) {
+__global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, int base, const int32_t* rank_p,
+                                                                    int seg2, const int32_t* rank2_p,
+                                                                    const double* H, double* work,
+                                                                    int32_t* status) {
   constexpr int NW = TRI_WAVES;
   constexpr int C = M / GREST_WAVE, RW = M / NW;
   __shared__ double pwv[2][NW][M];
@@ -394,10 +400,15 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
   __shared__ double sdg[M], sod[M], shb[M];
   const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid / GREST_WAVE);
-  int n = base + (rank_p ? rank_p[0] : 0);
-  if (n > d_full) n = d_full;
+  int s1 = base + (rank_p ? rank_p[0] : 0);
+  s1 = s1 < 0 ? 0 : (s1 > d_full ? d_full : s1);
+  int r2 = rank2_p ? rank2_p[0] : 0;
+  if (!rank2_p) seg2 = s1;
+  if (seg2 < s1) seg2 = s1;
+  r2 = r2 < 0 ? 0 : (r2 > d_full - seg2 ? d_full - seg2 : r2);
+  int n = s1 + r2;
   if (n > M) n = M;
-  if (n < 0) n = 0;
+  auto mp = [&](int i) { return i < s1 ? i : seg2 + (i - s1); };
   double* R = work + W_R;
 
   double A[RW][C];
@@ -410,7 +421,8 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
       const int j = lane + GREST_WAVE * c;
       double h = 0.0;
       if (i < n && j < n) {
-        h = 0.5 * (H[(size_t)i * d_full + j] + H[(size_t)j * d_full + i]);
+        const int mi = mp(i), mj = mp(j);
+        h = 0.5 * (H[(size_t)mi * d_full + mj] + H[(size_t)mj * d_full + mi]);
         if (!isfinite(h)) { bad = 1; h = 0.0; }
       }
       A[r][c] = h;
@@ -576,6 +588,8 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
       work[W_HDR + 2] = hi + pad;
       work[W_HDR + 3] = tn;
       work[W_HDR + 4] = 1e-290 * fmax(1.0, emax);
+      work[W_HDR + 5] = (double)s1;
+      work[W_HDR + 6] = (double)seg2;
     }
   }
   PHASE_MARK(2);
@@ -823,9 +837,11 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
 }
 
 __global__ void __launch_bounds__(GREST_WAVE) k_backtr(int d_full, int kk, const double* work, double* F) {
+  __shared__ double ysh[MAXN];
   const int slot = blockIdx.x, lane = threadIdx.x;
   if (work[W_FL + slot] == 0.0) return;
   const int n = (int)work[W_HDR];
+  const int s1 = (int)work[W_HDR + 5], seg2 = (int)work[W_HDR + 6];
   const double* R = work + W_R;
   const double* hb = work + W_HB;
   const double* Yb = work + W_Y;
@@ -847,9 +863,13 @@ __global__ void __launch_bounds__(GREST_WAVE) k_backtr(int d_full, int kk, const
     y0 = fma(-d, r0, y0);
     y1 = fma(-d, r1, y1);
   }
+  // F row of reduced index i is mp(i); the rows outside the map are zero
+  ysh[lane] = y0;
+  ysh[lane + GREST_WAVE] = y1;
+  wave_lds_fence();
   for (int r = lane; r < d_full; r += GREST_WAVE) {
-    const double v = r < GREST_WAVE ? y0 : y1;
-    F[(size_t)r * kk + slot] = r < n ? v : 0.0;
+    const int i = r < s1 ? r : ((r >= seg2 && r - seg2 < n - s1) ? s1 + (r - seg2) : -1);
+    F[(size_t)r * kk + slot] = i >= 0 ? ysh[i] : 0.0;
   }
 }
 
@@ -896,10 +916,13 @@ void launch_pchol(int m, const double* G, const double* C, int kc, double tol, d
 
 bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which, int kk,
                       double drop_tol, double* theta, double* F, int32_t* kept, double* work,
-                      int32_t* status, hipStream_t s) {
+                      int32_t* status, hipStream_t s, int seg2, const int32_t* rank2) {
   if (d_full < 1 || d_full > MAXN || kk < 1 || kk > MAXN) return false;
-  if (d_full <= 64) k_tridiag<64><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, H, work, status);
-  else k_tridiag<128><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, H, work, status);
+  if (rank2 && (seg2 < base || seg2 > d_full)) return false;
+  if (d_full <= 64)
+    k_tridiag<64><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, seg2, rank2, H, work, status);
+  else
+    k_tridiag<128><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, seg2, rank2, H, work, status);
   k_bisect<<<d_full, GREST_WAVE, 0, s>>>(work);
   k_eigvec<<<kk, GREST_WAVE, 0, s>>>(d_full, which, kk, drop_tol, work, theta, F, kept, status);
   k_backtr<<<kk, GREST_WAVE, 0, s>>>(d_full, kk, work, F);
