@@ -130,6 +130,32 @@ def test_laplacians_with_growth_fp64(op):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rsvd_sketch_rank_below_L(prec):
+    """Fewer new nodes than L: the sketch keeps fewer than L columns, so the basis
+    [X | R | Delta X] has dropped columns between its two packed blocks (the small
+    eigensolver's index map)."""
+    wl = W.sbm_small(n0=800, new_per_step=3, insertions=40, deletions=10, steps=3, cfg_id=1, graph_id=31)
+    run_trajectory(wl, 8, "rsvd", "adj", prec, 3, L=8, P=8)
+
+
+def test_rsvd_single_edge_without_new_nodes():
+    """RSVD with no new node and one changed edge: R is empty and Delta X has rank <= 2."""
+    banner("rsvd single edge flip")
+    wl = W.preset("sbm_n2000", scale=0.05, steps=1)
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, _ = O.leading_eigenpairs(A, 4)
+    st = G.State(wl.rowptr0, wl.col0, k=4, variant="rsvd", precision="fp64", L=4, P=4)
+    st.set_pairs(th0, X0)
+    Ad = A.toarray()
+    i, j = map(int, np.argwhere(np.triu(Ad == 0, 1))[7])
+    st.update(0, [i], [j], np.array([1], np.int8))
+    st.sync()
+    r = O.grest_step(A, X0, th0, 0, [i], [j], [1], 4, variant=O.RSVD, L=4)
+    check_step(st, r, "adj", "fp64", 4, "rsvd single edge")
+    st.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_kept_adjacency_product_matches_direct_product(prec):
     """For the adjacency the product A X of the tracked block is kept from the last
     back-projection and updated by Delta_1 X, so the sparse product only multiplies the new
