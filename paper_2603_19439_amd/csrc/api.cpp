@@ -341,11 +341,16 @@ Blocks<T> blocks(grest_state* st) {
 // [Xbar W] once for C = Xbar^T W and the FP64 Gram G = W^T W, factors G - C^T C by
 // rank-revealing pivoted Cholesky in FP64, and writes W <- (W - Xbar C) M in one pass.
 // The kept column counts of the two rounds go to ranks[slot] and ranks[slot + 1].
+// With rows (a device list of at most rows_bound rows, count in *nrows) W is zero outside
+// those rows, and the first round's read pass covers them only.
 template <typename T>
-void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T* W, int64_t ldw, int w, int slot) {
+void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T* W, int64_t ldw, int w, int slot,
+                  const int32_t* rows = nullptr, const int64_t* nrows = nullptr, int64_t rows_bound = 0) {
   hipStream_t s = st->stream;
   for (int round = 0; round < 2; ++round) {
-    if (!launch_pip<T>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s)) {
+    const bool sparse = round == 0 && rows;
+    if (!(sparse ? launch_pip<T>(rows_bound, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s, rows, nrows)
+                 : launch_pip<T>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s))) {
       if (st->prec == GREST_FP64) launch_tn<T, true>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
       else launch_tn<T, false>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
       launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, s);
@@ -524,8 +529,12 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       }
       launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
                           Ls, Ls, b.Y, st->ldy, s);
-      // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds
-      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2);
+      // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds; Y is
+      // zero except on the rows of Delta with an entry in an appended column, and the first
+      // round's read pass covers those rows only
+      launch_sketch_rows(n, S, st->dptr, st->dcol, st->dcnt, st->newlen, st->scan_tmp, st->dins, s);
+      const int64_t bound = std::min<int64_t>(n2, 2 * nc);
+      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->dins, st->newlen + n2, bound);
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
       launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Y, st->ldy, Ls,
                           (T*)st->bt, Ls, s);

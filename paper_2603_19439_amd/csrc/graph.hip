@@ -326,6 +326,22 @@ __global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, con
   }
 }
 
+// rows of Delta with an entry in an appended column (its columns are sorted, so the last
+// entry decides): the rows where Delta_2 Omega is not zero
+__global__ void __launch_bounds__(BS) k_sketch_flags(int64_t n_old, int64_t n2, const int64_t* dptr,
+                                                     const int32_t* dcol, int64_t* flag) {
+  for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n2; r += (int64_t)gridDim.x * BS) {
+    const int64_t e = dptr[r + 1];
+    flag[r] = (e > dptr[r] && (int64_t)dcol[e - 1] >= n_old) ? 1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(BS) k_compact_rows(int64_t n2, const int64_t* flag, const int64_t* pos,
+                                                     int32_t* rows) {
+  for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n2; r += (int64_t)gridDim.x * BS)
+    if (flag[r]) rows[pos[r]] = (int32_t)r;
+}
+
 __global__ void __launch_bounds__(BS) k_degrees(int64_t n, const int64_t* rp, double* s64, float* s32,
                                                 unsigned long long* maxdeg) {
   __shared__ unsigned long long wmax[BS / GREST_WAVE];
@@ -435,6 +451,15 @@ void launch_csr_merge(int64_t n_old, int64_t n_new, const int64_t* rp_old, const
   constexpr int LPR = 16;  // about one pass over a changed row of mean length
   k_csr_merge<LPR><<<grid_for(n2, BS, 1 << 16), BS, 0, s>>>(n_old, n2, rp_old, col_old, dptr, dcol, dsg, dins,
                                                             rp_new, col_new, cap_m);
+}
+
+void launch_sketch_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, int64_t* flag,
+                        int64_t* pos, int64_t* scan_tmp, int32_t* rows, hipStream_t s) {
+  const int64_t n2 = n_old + n_new;
+  if (n2 <= 0) return;
+  k_sketch_flags<<<grid_for(n2), BS, 0, s>>>(n_old, n2, dptr, dcol, flag);
+  launch_scan_excl(flag, pos, n2, scan_tmp, s);
+  k_compact_rows<<<grid_for(n2), BS, 0, s>>>(n2, flag, pos, rows);
 }
 
 void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* dinv_sqrt32,

@@ -27,6 +27,11 @@ void launch_fill_bytes0(void* p, size_t bytes, hipStream_t s);  // zero fill by 
 // exclusive scan of in[0..n) into out[0..n], out[n] = total; tmp >= scan_tmp_elems(n)
 int64_t scan_tmp_elems(int64_t n);
 void launch_scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// rows[0 .. pos[n_old + n_new]) = the rows of Delta with an entry in an appended column,
+// ascending (the rows where Delta_2 Omega is not zero); flag and pos hold n_old + n_new + 1
+// entries, rows at most that many
+void launch_sketch_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, int64_t* flag,
+                        int64_t* pos, int64_t* scan_tmp, int32_t* rows, hipStream_t s);
 // bits of a node id in the packed (row, column) keys of Delta
 int delta_key_shift(int64_t n2);
 // keys and signs of the two directed entries of every change (invalid: all-ones key and
@@ -123,10 +128,13 @@ int64_t pchol_work_elems(int m, int kc);
 void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
                   int32_t* status, double* work, hipStream_t s);
 // one projection round in one pass: C = X^T W (working precision) and G = W^T W (FP64);
-// returns false when the widths exceed what the kernel holds in registers
+// returns false when the widths exceed what the kernel holds in registers.  With rows the
+// pass covers rows[0 .. min(n, *nrows)) only (device count, n an upper bound), which is
+// exact when W is zero on every other row.
 template <typename T>
 bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw, int w, double* partial,
-                double* C, double* G, hipStream_t s);
+                double* C, double* G, hipStream_t s, const int32_t* rows = nullptr,
+                const int64_t* nrows = nullptr);
 // Out = beta Out + alpha [In1 | In2] M  (In1: n x a1, In2: n x a2, a1 + a2 <= 128)
 template <typename T>
 void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,

@@ -353,16 +353,20 @@ void tn_bf16t_launch(int g, int64_t n, int64_t rpc, const float* A, int64_t lda,
 // LDS in a fixed order.
 __host__ __device__ constexpr int tri_idx(int p, int q, int n) { return p * n - p * (p - 1) / 2 + (q - p); }
 
+// With a row list (rows, *nrows on the device) the pass runs over those rows only: the
+// rows left out must be zero in W (the products are then the same).
 template <typename T, typename Tcx, int TXC, int TWC>
 __global__ void __launch_bounds__(WG, sizeof(T) == 4 ? 2 : 1) k_pip(int64_t n, int64_t rpc, const T* __restrict__ X, int64_t ldx, int kx,
                                             const T* __restrict__ W, int64_t ldw, int w, double* __restrict__ partC,
-                                            double* __restrict__ partG) {
+                                            double* __restrict__ partG, const int32_t* __restrict__ rows,
+                                            const int64_t* __restrict__ nrows) {
   constexpr int NTG = TWC * (TWC + 1) / 2;
   using MC = Mma<Tcx>;
   using MG = Mma<double>;
   extern __shared__ double red_lds[];  // TXC*TWC + NTG tiles of 256 doubles
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
+  if (rows) n = min(n, *nrows);
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min(n, r0 + rpc);
   typename MC::acc_t ac[TXC][TWC];
@@ -377,8 +381,9 @@ __global__ void __launch_bounds__(WG, sizeof(T) == 4 ? 2 : 1) k_pip(int64_t n, i
   auto load = [&](int64_t rb) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int64_t row = rb + 4 * s + g;
-      const bool ok = row < r1;
+      const int64_t idx = rb + 4 * s + g;
+      const bool ok = idx < r1;
+      const int64_t row = (rows && ok) ? (int64_t)rows[idx] : idx;
 #pragma unroll
       for (int p = 0; p < TXC; ++p) {
         const int c = p * 16 + c16;
@@ -861,7 +866,8 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
 // one projection round: C = X^T W and G = W^T W (upper tiles; the reduce mirrors them)
 template <typename T, typename Tcx, int TXC, int TWC>
 static void pip_launch(int g, int64_t n, int64_t rpc, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw,
-                       int w, double* partC, double* partG, hipStream_t s) {
+                       int w, double* partC, double* partG, const int32_t* rows, const int64_t* nrows,
+                       hipStream_t s) {
   constexpr int NTG = TWC * (TWC + 1) / 2;
   const size_t lds = (size_t)(TXC * TWC + NTG) * 256 * sizeof(double);
   if (lds > 65536) {
@@ -872,12 +878,13 @@ static void pip_launch(int g, int64_t n, int64_t rpc, const T* X, int64_t ldx, i
     }();
     (void)attr;
   }
-  k_pip<T, Tcx, TXC, TWC><<<g, WG, lds, s>>>(n, rpc, X, ldx, kx, W, ldw, w, partC, partG);
+  k_pip<T, Tcx, TXC, TWC><<<g, WG, lds, s>>>(n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows);
 }
 
 template <typename T>
 bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw, int w, double* partial,
-                double* C, double* G, hipStream_t s) {
+                double* C, double* G, hipStream_t s, const int32_t* rows, const int64_t* nrows) {
+  if (!rows) nrows = nullptr;
   const int TX = (kx + 15) >> 4, TWt = (w + 15) >> 4;
   const int g = tn_num_chunks(n);
   int64_t rpc = (n + g - 1) / g;
@@ -885,23 +892,23 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
   double* partC = partial;
   double* partG = partial + (size_t)g * kx * w;
   using Tcx = typename std::conditional<sizeof(T) == 8, double, float>::type;
-  if (TX == 2 && TWt == 4) pip_launch<T, Tcx, 2, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
-  else if (TX == 4 && TWt == 2) pip_launch<T, Tcx, 4, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
-  else if (TX == 3 && TWt == 2) pip_launch<T, Tcx, 3, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
-  else if (TX == 2 && TWt == 1) pip_launch<T, Tcx, 2, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
-  else if (TX == 2 && TWt == 2) pip_launch<T, Tcx, 2, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
-  else if (TX == 1 && TWt == 4) pip_launch<T, Tcx, 1, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
-  else if (TX == 1 && TWt == 2) pip_launch<T, Tcx, 1, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
-  else if (TX == 1 && TWt == 1) pip_launch<T, Tcx, 1, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, s);
+  if (TX == 2 && TWt == 4) pip_launch<T, Tcx, 2, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
+  else if (TX == 4 && TWt == 2) pip_launch<T, Tcx, 4, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
+  else if (TX == 3 && TWt == 2) pip_launch<T, Tcx, 3, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
+  else if (TX == 2 && TWt == 1) pip_launch<T, Tcx, 2, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
+  else if (TX == 2 && TWt == 2) pip_launch<T, Tcx, 2, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
+  else if (TX == 1 && TWt == 4) pip_launch<T, Tcx, 1, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
+  else if (TX == 1 && TWt == 2) pip_launch<T, Tcx, 1, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
+  else if (TX == 1 && TWt == 1) pip_launch<T, Tcx, 1, 1>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
   else return false;
   launch_reduce(g, red_job(partC, C, kx, w), red_job(partG, G, w, w), s);
   return true;
 }
 
 template bool launch_pip<float>(int64_t, const float*, int64_t, int, const float*, int64_t, int, double*, double*,
-                                double*, hipStream_t);
+                                double*, hipStream_t, const int32_t*, const int64_t*);
 template bool launch_pip<double>(int64_t, const double*, int64_t, int, const double*, int64_t, int, double*,
-                                 double*, double*, hipStream_t);
+                                 double*, double*, hipStream_t, const int32_t*, const int64_t*);
 
 template <typename T, bool ACC64>
 void launch_tn(int64_t n, const T* A, int64_t lda, int a, const T* B, int64_t ldb, int b, double* partial,
