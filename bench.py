@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--serving-rates", default="100,400", help="Poisson arrival rates, requests/s")
     ap.add_argument("--serving-requests", default="300,800", help="requests per rate")
     ap.add_argument("--serving-lanes", type=int, default=4)
+    ap.add_argument("--serving-burst", type=int, default=256,
+                    help="requests of the saturation burst (served path vs plain FP32 per-graph path)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a reference kernel of "
                          "known traffic for hardware byte counters)")
@@ -226,7 +228,7 @@ def serving_leg(args):
     rates = [float(x) for x in args.serving_rates.split(",")]
     counts = [int(x) for x in args.serving_requests.split(",")]
     ng = args.serving_graphs
-    per_graph = int(np.ceil(sum(counts) / ng * 1.6)) + 8
+    per_graph = int(np.ceil((sum(counts) + args.serving_burst) / ng * 1.6)) + 8
     t0 = time.time()
     graphs = [W.serving_graph(g, per_graph) for g in range(ng)]
     log(args, f"serving: {ng} graphs generated in {time.time() - t0:.1f}s "
@@ -293,6 +295,58 @@ def serving_leg(args):
                         "mean_ms": round(float(lat_ms.mean()), 3),
                         "throughput_req_s": round(count / makespan, 1), "queue_full_retries": retries})
         log(args, f"serving at {rate:g} req/s: p50 {results[-1]['p50_ms']} ms, p99 {results[-1]['p99_ms']} ms")
+    # saturation: a burst of requests (all due at once) on the served path, against the same
+    # number of requests run one after another on plain FP32 per-graph states
+    burst = []
+    for q in range(args.serving_burst):
+        g = q % ng
+        if nxt[g] >= per_graph:
+            continue
+        d = graphs[g].workload.deltas[nxt[g]]
+        om = W.omega(4, g, nxt[g] + 1, d.n_new, 2 * graphs[g].k) if d.n_new > 0 else None
+        burst.append((g, d.n_new, d.i.astype(np.int32), d.j.astype(np.int32), d.sign, om))
+        nxt[g] += 1
+    sat = None
+    if burst:
+        t0_ns = G.now_ns()
+        for q, (g, s_new, i, j, sg_, om) in enumerate(burst):
+            rc = sv.submit(ids[g], s_new, i, j, sg_, om, tag=q)
+            if rc != G.OK:
+                raise RuntimeError(f"serving burst: request {q} refused with status {rc}")
+        sv.drain()
+        tags, status, ts, td = sv.poll(len(burst) + 16)
+        if tags.size != len(burst) or np.any(status != G.OK):
+            raise RuntimeError("serving burst: missing or failed completions")
+        served = len(burst) / ((td.max() - t0_ns) / 1e9)
+        # plain path: FP32 states of the same graphs, each request an update and a wait
+        plain_states = []
+        for g in range(ng):
+            wl = graphs[g].workload
+            n_fin = wl.n0 + sum(d.n_new for d in wl.deltas) + 1
+            nnz = int(wl.col0.size + 2 * sum(d.n_changes for d in wl.deltas) + 1024)
+            ps = G.State(wl.rowptr0, wl.col0, k=graphs[g].k, variant="rsvd", op="adj", precision="fp32",
+                         L=graphs[g].k, P=graphs[g].k, node_capacity=n_fin, nnz_capacity=nnz)
+            ps.init_pairs(iterations=20, seed=g)
+            plain_states.append(ps)
+        pn = [0] * ng
+        plain_reqs = []
+        for (g, *_rest) in burst:
+            d = graphs[g].workload.deltas[pn[g]]
+            om = W.omega(4, g, pn[g] + 1, d.n_new, 2 * graphs[g].k) if d.n_new > 0 else None
+            plain_reqs.append((g, d, om))
+            pn[g] += 1
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for g, d, om in plain_reqs:
+            plain_states[g].update_delta(d, om)
+            plain_states[g].sync()
+        plain = len(plain_reqs) / (time.perf_counter() - tp)
+        for ps in plain_states:
+            ps.close()
+        sat = {"requests": len(burst), "served_req_s": round(served, 1), "plain_fp32_per_graph_req_s": round(plain, 1),
+               "speedup": round(served / plain, 2)}
+        log(args, f"serving burst of {len(burst)}: {served:.0f} req/s served ({args.precision}, "
+                  f"{args.serving_lanes} lanes) vs {plain:.0f} req/s plain FP32 per graph")
     sv.close()
     # accuracy of the probe graphs over all the requests they received
     acc = []
@@ -318,7 +372,7 @@ def serving_leg(args):
     return {"workload": f"{ng} graphs (SBM or Chung-Lu, n0 {min(g.workload.n0 for g in graphs)}.."
                         f"{max(g.workload.n0 for g in graphs)}, mean degree 8-32, K in {{8,16,32}}, "
                         f"G-REST_RSVD L=P=K), requests of 0.1-1 % new nodes + 0.1-1 % insertions",
-            "lanes": args.serving_lanes, "precision": args.precision, "rates": results,
+            "lanes": args.serving_lanes, "precision": args.precision, "rates": results, "saturation": sat,
             "accuracy_probes": acc, "accuracy_gate_passed": passed}
 
 
