@@ -45,7 +45,7 @@ def parse():
                     help="graphs in the many-graph serving leg (0 skips it; the full mix has 256)")
     ap.add_argument("--serving-rates", default="100,400", help="Poisson arrival rates, requests/s")
     ap.add_argument("--serving-requests", default="300,800", help="requests per rate")
-    ap.add_argument("--serving-lanes", type=int, default=4)
+    ap.add_argument("--serving-lanes", type=int, default=8)
     ap.add_argument("--serving-burst", type=int, default=256,
                     help="requests of the saturation burst (served path vs plain FP32 per-graph path)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
