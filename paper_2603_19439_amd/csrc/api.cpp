@@ -100,6 +100,7 @@ struct grest_state {
   int32_t *d_ei = nullptr, *d_ej = nullptr;
   int8_t* d_sg = nullptr;
   int64_t *dcnt = nullptr, *dptr = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
+  int32_t* srows = nullptr;  // rows where the sketch Delta_2 Omega can be nonzero
   uint64_t *dkey_in = nullptr, *dkey_out = nullptr;  // packed (row, column) keys of Delta
   char* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
@@ -186,6 +187,7 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   CHK(dalloc(&st->dcnt, cap_n + 1));
   CHK(dalloc(&st->dptr, cap_n + 1));
   CHK(dalloc(&st->newlen, cap_n + 1));
+  CHK(dalloc(&st->srows, cap_n + 1));
   CHK(dalloc(&st->scan_tmp, scan_tmp_elems(cap_n + 1) + 16));
   st->cap_n = cap_n;
   return GREST_OK;
@@ -241,7 +243,7 @@ int64_t device_bytes(const grest_state* st) {
   for (int b = 0; b < 2; ++b) { add(st->rp[b]); add(st->col[b]); add(st->sc[b]); add(st->z[b]); }
   add(st->aux); add(st->ybuf); add(st->bt); add(st->omega_t); add(st->omega64);
   add(st->d_ei); add(st->d_ej); add(st->d_sg);
-  add(st->dcnt); add(st->dptr); add(st->newlen); add(st->scan_tmp);
+  add(st->dcnt); add(st->dptr); add(st->newlen); add(st->scan_tmp); add(st->srows);
   add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp);
   add(st->dcol); add(st->dins); add(st->dsg_tmp); add(st->dsg);
   add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F);
@@ -256,7 +258,7 @@ void free_all(grest_state* st) {
   }
   dfree(st->aux); dfree(st->ybuf); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
-  dfree(st->dcnt); dfree(st->dptr); dfree(st->newlen); dfree(st->scan_tmp);
+  dfree(st->dcnt); dfree(st->dptr); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
   dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
@@ -287,7 +289,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   st->z[0] = st->z[1] = nullptr;
   st->sc[0] = st->sc[1] = nullptr;
   dfree(st->aux); dfree(st->ybuf); dfree(st->dcnt); dfree(st->dptr);
-  dfree(st->newlen); dfree(st->scan_tmp);
+  dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows);
   CHK(alloc_node_arrays(st, cap));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
                         st->stream));
@@ -530,11 +532,11 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
                           Ls, Ls, b.Y, st->ldy, s);
       // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds; Y is
-      // zero except on the rows of Delta with an entry in an appended column, and the first
-      // round's read pass covers those rows only
-      launch_sketch_rows(n, S, st->dptr, st->dcol, st->dcnt, st->newlen, st->scan_tmp, st->dins, s);
-      const int64_t bound = std::min<int64_t>(n2, 2 * nc);
-      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->dins, st->newlen + n2, bound);
+      // zero except on the appended rows and the rows of Delta with an entry in an appended
+      // column, and the first round's read pass covers those rows only
+      launch_sketch_rows(n, S, st->dptr, st->dcol, st->dcnt, st->newlen, st->scan_tmp, st->srows, s);
+      const int64_t bound = std::min<int64_t>(n2, S + 2 * nc);
+      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->srows, st->newlen + n2, bound);
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
       launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Y, st->ldy, Ls,
                           (T*)st->bt, Ls, s);

@@ -326,13 +326,14 @@ __global__ void __launch_bounds__(BS) k_csr_merge(int64_t n_old, int64_t n2, con
   }
 }
 
-// rows of Delta with an entry in an appended column (its columns are sorted, so the last
-// entry decides): the rows where Delta_2 Omega is not zero
+// the rows where Delta_2 Omega can be nonzero: the appended rows (for the Laplacians the
+// diagonal of the new block reaches every one of them) and the old rows of Delta with an
+// entry in an appended column (its columns are sorted, so the last entry decides)
 __global__ void __launch_bounds__(BS) k_sketch_flags(int64_t n_old, int64_t n2, const int64_t* dptr,
                                                      const int32_t* dcol, int64_t* flag) {
   for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n2; r += (int64_t)gridDim.x * BS) {
     const int64_t e = dptr[r + 1];
-    flag[r] = (e > dptr[r] && (int64_t)dcol[e - 1] >= n_old) ? 1 : 0;
+    flag[r] = (r >= n_old || (e > dptr[r] && (int64_t)dcol[e - 1] >= n_old)) ? 1 : 0;
   }
 }
 

@@ -27,9 +27,9 @@ void launch_fill_bytes0(void* p, size_t bytes, hipStream_t s);  // zero fill by 
 // exclusive scan of in[0..n) into out[0..n], out[n] = total; tmp >= scan_tmp_elems(n)
 int64_t scan_tmp_elems(int64_t n);
 void launch_scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
-// rows[0 .. pos[n_old + n_new]) = the rows of Delta with an entry in an appended column,
-// ascending (the rows where Delta_2 Omega is not zero); flag and pos hold n_old + n_new + 1
-// entries, rows at most that many
+// rows[0 .. pos[n_old + n_new]) = the appended rows and the old rows of Delta with an entry
+// in an appended column, ascending (every row where Delta_2 Omega can be nonzero); flag
+// and pos hold n_old + n_new + 1 entries, rows at most min(n_old + n_new, n_new + 2 nnz)
 void launch_sketch_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, int64_t* flag,
                         int64_t* pos, int64_t* scan_tmp, int32_t* rows, hipStream_t s);
 // bits of a node id in the packed (row, column) keys of Delta

@@ -243,6 +243,7 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
   __syncthreads();
 
   PHASE_MARK(10);
+  SECT_DECL
   uint64_t ch0 = 0, ch1 = 0;
   int r = 0;
   for (int k = 0; k < m; ++k) {
@@ -259,12 +260,15 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
     if (!(best > 0.0)) break;
     const int p = 127 - (int)(__double_as_longlong(best) & 0x7F);
     const double piv = vec_elem<CC>(d, p);
+    SECT(0);
     if (!(piv > thr)) break;  // also stops on NaN
     if (p < 64) ch0 |= 1ull << p; else ch1 |= 1ull << (p - 64);
     double* rowk = Rrow + k * LP;
     column_to_lds<RW, CC, NW>(S, p, wv, m, rowk);
     if (tid == 0) { perm[k] = p; iperm[p] = k; rdg[k] = piv; }  // square roots after the loop
+    SECT(1);
     __syncthreads();
+    SECT(2);
     double rp[CC];
 #pragma unroll
     for (int c = 0; c < CC; ++c) {
@@ -285,7 +289,9 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
 #pragma unroll
     for (int c = 0; c < CC; ++c) d[c] = fma(-(rp[c] * ip), rp[c], d[c]);
     r = k + 1;
+    SECT(3);
   }
+  SECT_WRITE(40);
   PHASE_MARK(11);
   // X = R^{-1}, R[a][b] = Rrow[a][perm[b]] / sqrt(piv_a) (upper triangular in pivot
   // order).  Column j of X is an independent solve: for i descending, X[i][j] /= R[i][i],
