@@ -316,3 +316,35 @@ def test_device_init_pairs_match_exact_leading_pairs():
     th, Xe, _ = O.leading_eigenpairs(A, 4)
     assert M.eig_rel_error(vals[:1], th[:1]) < 1e-10
     assert M.eig_rel_error(vals, th) < 1e-3
+
+
+# ------------------------------------------------------------------------------------
+# full size: the headline workload in the launch configuration the benchmark times
+# ------------------------------------------------------------------------------------
+def test_full_size_single_step_parity():
+    """n0 = 1e6 SBM, K = 32, RSVD with L = P = 32 (the benchmark's workload and kernel
+    shapes): one update from the same start on the GPU (mixed and FP32) and in the oracle.
+    The start is a few block power iterations on the host (no exact eigensolve at this
+    size); parity is the agreement of the two updates on the same inputs."""
+    wl = W.preset("sbm_n1e6", scale=1.0, steps=1)
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    X = W.random_orthonormal(wl.n0, 32, 5)
+    for _ in range(6):  # block power iteration with Cholesky QR (host, FP64)
+        Y = A @ X
+        R = np.linalg.cholesky(Y.T @ Y).T
+        X = np.linalg.solve(R.T, Y.T).T
+    th = np.einsum("ij,ij->j", X, A @ X)
+    d = wl.deltas[0]
+    om = W.omega(wl.cfg_id, 0, 1, d.n_new, 64)
+    banner(f"full size: oracle step n0={wl.n0} nnz={A.nnz}")
+    r = O.grest_step(A, X, th, d.n_new, d.i, d.j, d.sign, 32, variant=O.RSVD, L=32, Omega=om)
+    for prec in ("mixed", "fp32"):
+        banner(f"full size: GPU step prec={prec}")
+        n_fin = wl.n0 + d.n_new + 1
+        st = G.State(wl.rowptr0, wl.col0, k=32, variant="rsvd", precision=prec, L=32, P=32, node_capacity=n_fin,
+                     nnz_capacity=int(wl.col0.size + 2 * d.n_changes + 1024))
+        st.set_pairs(th, X)
+        st.update_delta(d, om)
+        st.sync()
+        check_step(st, r, "adj", prec, 32, f"full size {prec}")
+        st.close()
