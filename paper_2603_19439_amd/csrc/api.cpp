@@ -92,7 +92,11 @@ struct grest_state {
   void* z[2] = {nullptr, nullptr};
   int zcur = 0;
   void* aux = nullptr;   // (op Z), cap_n x D
-  void* ybuf = nullptr;  // sketch / range basis, cap_n x ldy
+  void* ybuf = nullptr;  // sketch Y = Delta_2 Omega, cap_n x ldy, zero outside the listed rows
+  void* mbuf = nullptr;  // its orthonormal basis M, cap_n x ldy
+  bool y_clean = false;  // ybuf is zero outside srows[0 .. *srows_cnt)
+  int64_t* srows_cnt = nullptr;  // device count of the last sketch row list
+  int64_t srows_bound = 0;       // host upper bound of that count
   void* bt = nullptr;    // Delta_2^T M, cap_s x Ls
   void* omega_t = nullptr;
   double* omega64 = nullptr;
@@ -183,7 +187,11 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
     CHK(dalloc((char**)&st->z[b], (size_t)cap_n * st->ldz * es));
   }
   CHK(dalloc((char**)&st->aux, (size_t)cap_n * std::max(st->D, st->K) * es));
-  if (st->variant == GREST_RSVD) CHK(dalloc((char**)&st->ybuf, (size_t)cap_n * st->ldy * es));
+  if (st->variant == GREST_RSVD) {
+    CHK(dalloc((char**)&st->ybuf, (size_t)cap_n * st->ldy * es));
+    CHK(dalloc((char**)&st->mbuf, (size_t)cap_n * st->ldy * es));
+  }
+  st->y_clean = false;
   CHK(dalloc(&st->dcnt, cap_n + 1));
   CHK(dalloc(&st->dptr, cap_n + 1));
   CHK(dalloc(&st->newlen, cap_n + 1));
@@ -241,7 +249,7 @@ int64_t device_bytes(const grest_state* st) {
     if (p && hipMemPtrGetInfo(const_cast<void*>(p), &sz) == hipSuccess) total += (int64_t)sz;
   };
   for (int b = 0; b < 2; ++b) { add(st->rp[b]); add(st->col[b]); add(st->sc[b]); add(st->z[b]); }
-  add(st->aux); add(st->ybuf); add(st->bt); add(st->omega_t); add(st->omega64);
+  add(st->aux); add(st->ybuf); add(st->mbuf); add(st->srows_cnt); add(st->bt); add(st->omega_t); add(st->omega64);
   add(st->d_ei); add(st->d_ej); add(st->d_sg);
   add(st->dcnt); add(st->dptr); add(st->newlen); add(st->scan_tmp); add(st->srows);
   add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp);
@@ -256,7 +264,7 @@ void free_all(grest_state* st) {
   for (int b = 0; b < 2; ++b) {
     dfree(st->rp[b]); dfree(st->col[b]); dfree(st->sc[b]); dfree(st->z[b]);
   }
-  dfree(st->aux); dfree(st->ybuf); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
+  dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->srows_cnt); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
   dfree(st->dcnt); dfree(st->dptr); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
@@ -288,7 +296,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   st->rp[0] = st->rp[1] = nullptr;
   st->z[0] = st->z[1] = nullptr;
   st->sc[0] = st->sc[1] = nullptr;
-  dfree(st->aux); dfree(st->ybuf); dfree(st->dcnt); dfree(st->dptr);
+  dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->dcnt); dfree(st->dptr);
   dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows);
   CHK(alloc_node_arrays(st, cap));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
@@ -345,20 +353,27 @@ Blocks<T> blocks(grest_state* st) {
 // The kept column counts of the two rounds go to ranks[slot] and ranks[slot + 1].
 // With rows (a device list of at most rows_bound rows, count in *nrows) W is zero outside
 // those rows, and the first round's read pass covers them only.
+// With Wout the first round reads W and writes Wout (same leading dimension), and the
+// second round works on Wout in place; flag2 (with rows) marks the rows of W that can be
+// nonzero, so the first round's apply does not read the others.
 template <typename T>
 void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T* W, int64_t ldw, int w, int slot,
-                  const int32_t* rows = nullptr, const int64_t* nrows = nullptr, int64_t rows_bound = 0) {
+                  const int32_t* rows = nullptr, const int64_t* nrows = nullptr, int64_t rows_bound = 0,
+                  T* Wout = nullptr, const int64_t* flag2 = nullptr) {
   hipStream_t s = st->stream;
   for (int round = 0; round < 2; ++round) {
     const bool sparse = round == 0 && rows;
-    if (!(sparse ? launch_pip<T>(rows_bound, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s, rows, nrows)
-                 : launch_pip<T>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s))) {
-      if (st->prec == GREST_FP64) launch_tn<T, true>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
-      else launch_tn<T, false>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
-      launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, s);
+    T* Win = (round == 1 && Wout) ? Wout : W;
+    T* Wo = Wout ? Wout : W;
+    if (!(sparse ? launch_pip<T>(rows_bound, X, ldx, kx, Win, ldw, w, st->partial, st->C1, st->Gm, s, rows, nrows)
+                 : launch_pip<T>(n, X, ldx, kx, Win, ldw, w, st->partial, st->C1, st->Gm, s))) {
+      if (st->prec == GREST_FP64) launch_tn<T, true>(n, X, ldx, kx, Win, ldw, w, st->partial, st->C1, s);
+      else launch_tn<T, false>(n, X, ldx, kx, Win, ldw, w, st->partial, st->C1, s);
+      launch_tn<T, true>(n, Win, ldw, w, Win, ldw, w, st->partial, st->Gm, s);
     }
     launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
-    launch_apply2<T>(n, X, ldx, kx, W, ldw, w, st->Mchol, w, 1.0, 0.0, W, ldw, s);
+    launch_apply2<T>(n, X, ldx, kx, Win, ldw, w, st->Mchol, w, 1.0, 0.0, Wo, ldw, s,
+                     round == 0 ? flag2 : nullptr);
   }
 }
 
@@ -529,16 +544,28 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       } else {
         launch_convert<double, float>(om, (float*)st->omega_t, (int64_t)S * Ls, s);
       }
-      launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
-                          Ls, Ls, b.Y, st->ldy, s);
-      // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds; Y is
-      // zero except on the appended rows and the rows of Delta with an entry in an appended
-      // column, and the first round's read pass covers those rows only
+      // Y is zero except on the appended rows and the rows of Delta with an entry in an
+      // appended column (the row list).  The buffer is kept that way: the rows of the
+      // previous list are cleared (all of Y after a reallocation) and the product writes
+      // the rows of the new list only.
+      T* Mb = (T*)st->mbuf;
+      if (st->y_clean)
+        launch_zero_listed_rows<T>(b.Y, st->ldy, Ls, st->srows, st->srows_cnt, st->srows_bound, s);
+      else
+        launch_fill_rows<T>(b.Y, st->ldy, 0, n2, Ls, s);
       launch_sketch_rows(n, S, st->dptr, st->dcol, st->dcnt, st->newlen, st->scan_tmp, st->srows, s);
       const int64_t bound = std::min<int64_t>(n2, S + 2 * nc);
-      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->srows, st->newlen + n2, bound);
+      launch_copy_i64(st->newlen + n2, st->srows_cnt, s);
+      st->srows_bound = bound;
+      st->y_clean = true;
+      launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
+                          Ls, Ls, b.Y, st->ldy, s);
+      // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds; the first
+      // round's read passes cover the listed rows of Y only, and M goes to its own buffer
+      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->srows, st->newlen + n2, bound, Mb,
+                      st->dcnt);
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
-      launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Y, st->ldy, Ls,
+      launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, Mb, st->ldy, Ls,
                           (T*)st->bt, Ls, s);
       launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
       if (!launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
@@ -549,7 +576,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
         return GREST_EINVAL;
       }
       // S.4: R = M U_L (its kept columns first, the dropped ones zero)
-      launch_apply<T>(n2, b.Y, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, Rb, st->ldz, s);
+      launch_apply<T>(n2, Mb, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, Rb, st->ldz, s);
     }
   }
   mark(st, 3);
@@ -838,6 +865,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if ((rc = dalloc(&st->ranks, 8)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->status, 1)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->maxdeg, 1)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->srows_cnt, 1)) != GREST_OK) return fail(rc);
   if (hipHostMalloc((void**)&st->pin, sizeof(Pinned)) != hipSuccess) return fail(GREST_ENOMEM);
   if (hipHostMalloc((void**)&st->theta_pin, st->K * sizeof(double)) != hipSuccess) return fail(GREST_ENOMEM);
   memset(st->pin, 0, sizeof(Pinned));

@@ -16,6 +16,19 @@ __global__ void k_fill_rows(T* p, int64_t ld, int64_t row0, int64_t rows, int w)
   }
 }
 
+// zero the listed rows (rows[0 .. *count)) of a row-major block of width w
+template <typename T>
+__global__ void k_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const int64_t* count) {
+  const int64_t total = *count * w;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride)
+    p[(int64_t)rows[idx / w] * ld + idx % w] = T(0);
+}
+
+__global__ void k_copy_i64(const int64_t* src, int64_t* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
 template <typename Ts, typename Td>
 __global__ void k_convert(const Ts* s, Td* d, int64_t count) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -37,6 +50,15 @@ void launch_fill_rows(T* p, int64_t ld, int64_t row0, int64_t rows, int w, hipSt
   k_fill_rows<T><<<grid_cap(rows * w), 256, 0, s>>>(p, ld, row0, rows, w);
 }
 
+template <typename T>
+void launch_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const int64_t* count, int64_t bound,
+                             hipStream_t s) {
+  if (bound <= 0 || w <= 0) return;
+  k_zero_listed_rows<T><<<grid_cap(bound * w), 256, 0, s>>>(p, ld, w, rows, count);
+}
+
+void launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s) { k_copy_i64<<<1, 64, 0, s>>>(src, dst); }
+
 template <typename Tsrc, typename Tdst>
 void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s) {
   if (count <= 0) return;
@@ -45,6 +67,10 @@ void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s) {
 
 template void launch_fill_rows<float>(float*, int64_t, int64_t, int64_t, int, hipStream_t);
 template void launch_fill_rows<double>(double*, int64_t, int64_t, int64_t, int, hipStream_t);
+template void launch_zero_listed_rows<float>(float*, int64_t, int, const int32_t*, const int64_t*, int64_t,
+                                             hipStream_t);
+template void launch_zero_listed_rows<double>(double*, int64_t, int, const int32_t*, const int64_t*, int64_t,
+                                              hipStream_t);
 template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
 template void launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);

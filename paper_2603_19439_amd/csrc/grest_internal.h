@@ -73,7 +73,8 @@ void launch_spmm(int op, int64_t n, const int64_t* rp, const int32_t* col, const
 
 // Products with the update Delta of the tracked operator (rows grouped in dptr/dcol/dsg).
 //   mode 0: V = Delta_1 Xbar            (only columns c < n_old, input X rows c)
-//   mode 1: Y = Delta_2 Omega           (only columns c >= n_old, input rows c - n_old)
+//   mode 1: Y = Delta_2 Omega           (only columns c >= n_old, input rows c - n_old; only
+//           the rows that can be nonzero are written, the others must be zero already)
 //   mode 2: B = Delta_2^T M              (rows n_old.., all columns, input rows c)
 //   mode 3: write Delta_2 densely into out[:, 0:S] (G-REST3)
 // For lap/nlap the degree and scaling changes are included (see spmm.hip).
@@ -110,6 +111,12 @@ void launch_tn_bf16(int64_t n, const float* A, int64_t lda, int a, const float* 
                     double* partial, double* C, hipStream_t s);
 template <typename T>
 void launch_fill_rows(T* p, int64_t ld, int64_t row0, int64_t rows, int w, hipStream_t s);
+// zero rows[0 .. *count) of a row-major block (bound: an upper bound of *count, sizes the grid)
+template <typename T>
+void launch_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const int64_t* count, int64_t bound,
+                             hipStream_t s);
+// *dst = *src on the device
+void launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
 template <typename Tsrc, typename Tdst>
 void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s);
 
@@ -135,10 +142,12 @@ template <typename T>
 bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw, int w, double* partial,
                 double* C, double* G, hipStream_t s, const int32_t* rows = nullptr,
                 const int64_t* nrows = nullptr);
-// Out = beta Out + alpha [In1 | In2] M  (In1: n x a1, In2: n x a2, a1 + a2 <= 128)
+// Out = beta Out + alpha [In1 | In2] M  (In1: n x a1, In2: n x a2, a1 + a2 <= 128).  With
+// flag2 the rows r with flag2[r] == 0 of In2 must be zero (they are then not read).
 template <typename T>
 void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
-                   const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s);
+                   const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s,
+                   const int64_t* flag2 = nullptr);
 // Symmetric eigensolver of H (first base + rank[0] rows/cols used, ldh = d_full) and
 // selection of kk pairs: which 0 = largest magnitude, 1 = smallest algebraic,
 // 2 = largest algebraic.  Writes theta[kk] and F (d_full x kk, zero rows past the

@@ -618,11 +618,12 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
 // (kb, jt).  KB = ceil(a / 16) is a template parameter so the fragment arrays are exact;
 // two output tiles are accumulated side by side.  Every row's inputs are read before its
 // outputs are written, so Out may alias In2 (in-place update of a column block).
+// With flag2, the In2 part of row r is read only where flag2[r] != 0 (zero elsewhere).
 template <int KB, bool VEC>
 __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, int64_t ld1, int a1,
                                                   const float* In2, int64_t ld2, int a2,
                                                   const double* __restrict__ Mg, int b, double alpha, double beta,
-                                                  float* Out, int64_t ldout) {
+                                                  float* Out, int64_t ldout, const int64_t* __restrict__ flag2) {
   extern __shared__ double sMraw[];
   f32x4* sM = reinterpret_cast<f32x4*>(sMraw);
   const int a = a1 + a2;
@@ -648,14 +649,16 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
   // lane's four columns are either all inside one input block or all past the end
   auto load = [&](int64_t t, f32x4(&f)[KB]) __attribute__((always_inline)) {
     const int64_t row = t * 16 + c16;
+    const bool use2 = row < n && (!flag2 || flag2[row] != 0);
     if (VEC) {
       const float* b1 = In1 + row * ld1;
       const float* b2 = In2 + row * ld2 - a1;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         const int k0 = kb * 16 + 4 * g;
-        f[kb] = (row < n && k0 < a) ? *reinterpret_cast<const f32x4*>((k0 < a1 ? b1 : b2) + k0)
-                                    : f32x4{0.f, 0.f, 0.f, 0.f};
+        f[kb] = (row < n && k0 < a && (k0 < a1 || use2))
+                    ? *reinterpret_cast<const f32x4*>((k0 < a1 ? b1 : b2) + k0)
+                    : f32x4{0.f, 0.f, 0.f, 0.f};
       }
     } else {
 #pragma unroll
@@ -664,7 +667,10 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
         for (int m = 0; m < 4; ++m) {
           const int k = kb * 16 + 4 * g + m;
           float v = 0.f;
-          if (row < n && k < a) v = k < a1 ? In1[row * ld1 + k] : In2[row * ld2 + (k - a1)];
+          if (row < n && k < a) {
+            if (k < a1) v = In1[row * ld1 + k];
+            else if (use2) v = In2[row * ld2 + (k - a1)];
+          }
           f[kb][m] = v;
         }
       }
@@ -734,7 +740,8 @@ int device_cus() {
 
 template <int KB, bool VEC>
 void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
-                      const double* M, int b, double alpha, double beta, float* Out, int64_t ldout, hipStream_t s) {
+                      const double* M, int b, double alpha, double beta, float* Out, int64_t ldout,
+                      const int64_t* flag2, hipStream_t s) {
   const int TB = (b + 15) >> 4;
   const size_t lds = (size_t)KB * TB * 64 * sizeof(f32x4);
   // resident workgroups per CU for this LDS size (queried once per size; a persistent
@@ -758,21 +765,23 @@ void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const fl
   const int64_t tiles = (n + 15) / 16;
   int64_t g = std::min<int64_t>((tiles + NW - 1) / NW, (int64_t)device_cus() * occ);
   if (g < 1) g = 1;
-  k_apply_f32<KB, VEC><<<(unsigned)g, WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout);
+  k_apply_f32<KB, VEC><<<(unsigned)g, WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout,
+                                                     flag2);
 }
 
 template <bool VEC>
 void apply_f32_dispatch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
-                        const double* M, int b, double alpha, double beta, float* Out, int64_t ldout, hipStream_t s) {
+                        const double* M, int b, double alpha, double beta, float* Out, int64_t ldout,
+                        const int64_t* flag2, hipStream_t s) {
   switch ((a1 + a2 + 15) >> 4) {
-    case 1: apply_f32_launch<1, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
-    case 2: apply_f32_launch<2, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
-    case 3: apply_f32_launch<3, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
-    case 4: apply_f32_launch<4, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
-    case 5: apply_f32_launch<5, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
-    case 6: apply_f32_launch<6, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
-    case 7: apply_f32_launch<7, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
-    default: apply_f32_launch<8, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s); break;
+    case 1: apply_f32_launch<1, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    case 2: apply_f32_launch<2, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    case 3: apply_f32_launch<3, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    case 4: apply_f32_launch<4, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    case 5: apply_f32_launch<5, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    case 6: apply_f32_launch<6, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    case 7: apply_f32_launch<7, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    default: apply_f32_launch<8, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
   }
 }
 
@@ -937,7 +946,8 @@ static void apply_launch(int64_t n, const T* In1, int64_t ld1, int a1, const T* 
 
 template <typename T>
 void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
-                   const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s) {
+                   const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s,
+                   const int64_t* flag2) {
   if (n <= 0 || b <= 0) return;
   const bool vec = aligned16(In1, ld1) && (a2 == 0 || (aligned16(In2, ld2) && a1 % 4 == 0));
   if constexpr (sizeof(T) == 8) {
@@ -945,9 +955,9 @@ void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, i
     else apply_launch<T, double, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
   } else {
     if (vec && aligned16(Out, ldout) && a1 % 4 == 0 && (a1 + a2) % 4 == 0 && b % 4 == 0)
-      apply_f32_dispatch<true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+      apply_f32_dispatch<true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s);
     else
-      apply_f32_dispatch<false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+      apply_f32_dispatch<false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s);
   }
 }
 
@@ -958,9 +968,10 @@ void launch_apply(int64_t n, const T* In, int64_t ldin, int a, const double* M, 
 }
 
 template void launch_apply2<float>(int64_t, const float*, int64_t, int, const float*, int64_t, int, const double*,
-                                   int, double, double, float*, int64_t, hipStream_t);
+                                   int, double, double, float*, int64_t, hipStream_t, const int64_t*);
 template void launch_apply2<double>(int64_t, const double*, int64_t, int, const double*, int64_t, int,
-                                    const double*, int, double, double, double*, int64_t, hipStream_t);
+                                    const double*, int, double, double, double*, int64_t, hipStream_t,
+                                    const int64_t*);
 
 template void launch_tn<float, false>(int64_t, const float*, int64_t, int, const float*, int64_t, int, double*,
                                       double*, hipStream_t);

@@ -174,7 +174,9 @@ __device__ inline T d2_diag(const DeltaArgs& a, int64_t node) {
 //         with acc set, also acc[r] += out[r] on the old rows that have entries and
 //         acc[r] = out[r] on the appended rows (the product of the updated operator with the
 //         padded block, from the old operator's product kept in acc)
-// mode 1: out[r] = (Delta_T)[r, n_old:] Omega
+// mode 1: out[r] = (Delta_T)[r, n_old:] Omega, written only on the appended rows and the
+//         rows with an entry in an appended column (every other row is zero and is left
+//         as it is: the caller keeps those rows zero)
 // mode 2: out[j] = (Delta_T)[n_old + j, :] M  (= (Delta_T,2^T M)[j] by symmetry)
 template <typename T, int VEC, int OP, int MODE>
 __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__ snew,
@@ -195,6 +197,7 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
 #pragma unroll
       for (int i = 0; i < VEC; ++i) acc[i] = T(0);
       int32_t ssum = 0;
+      bool any_new = false;  // mode 1: an entry in an appended column
       for (int64_t e = beg; e < end; ++e) {
         const int64_t c = a.dcol[e];
         const int8_t sg = a.dsg[e];
@@ -207,6 +210,7 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
           src = c;
         } else if (MODE == 1) {
           if (c < a.n_old) continue;
+          any_new = true;
           wgt = d2_weight<T, OP>(sg, snew, r, c);
           src = c - a.n_old;
         } else {
@@ -234,7 +238,9 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
           for (int i = 0; i < VEC; ++i) acc[i] += dgl * z[i];
         }
       }
-      vstore<T, VEC>(out + q * ldout + c0, acc);
+      // mode 1 leaves the old rows without an entry in an appended column alone: they are
+      // zero, and the caller keeps them zero
+      if (MODE != 1 || r >= a.n_old || any_new) vstore<T, VEC>(out + q * ldout + c0, acc);
       if (MODE == 0 && acc_io) {
         T* pa = acc_io + r * ldacc + c0;
         if (r >= a.n_old) {
