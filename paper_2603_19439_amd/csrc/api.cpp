@@ -105,6 +105,7 @@ struct grest_state {
   int8_t* d_sg = nullptr;
   int64_t *dcnt = nullptr, *dptr = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
   int32_t* srows = nullptr;  // rows where the sketch Delta_2 Omega can be nonzero
+  int32_t* drows = nullptr;  // rows where Delta_1 X can be nonzero
   uint64_t *dkey_in = nullptr, *dkey_out = nullptr;  // packed (row, column) keys of Delta
   char* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
@@ -196,6 +197,7 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   CHK(dalloc(&st->dptr, cap_n + 1));
   CHK(dalloc(&st->newlen, cap_n + 1));
   CHK(dalloc(&st->srows, cap_n + 1));
+  CHK(dalloc(&st->drows, cap_n + 1));
   CHK(dalloc(&st->scan_tmp, scan_tmp_elems(cap_n + 1) + 16));
   st->cap_n = cap_n;
   return GREST_OK;
@@ -251,7 +253,7 @@ int64_t device_bytes(const grest_state* st) {
   for (int b = 0; b < 2; ++b) { add(st->rp[b]); add(st->col[b]); add(st->sc[b]); add(st->z[b]); }
   add(st->aux); add(st->ybuf); add(st->mbuf); add(st->srows_cnt); add(st->bt); add(st->omega_t); add(st->omega64);
   add(st->d_ei); add(st->d_ej); add(st->d_sg);
-  add(st->dcnt); add(st->dptr); add(st->newlen); add(st->scan_tmp); add(st->srows);
+  add(st->dcnt); add(st->dptr); add(st->newlen); add(st->scan_tmp); add(st->srows); add(st->drows);
   add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp);
   add(st->dcol); add(st->dins); add(st->dsg_tmp); add(st->dsg);
   add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F);
@@ -267,6 +269,7 @@ void free_all(grest_state* st) {
   dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->srows_cnt); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
   dfree(st->dcnt); dfree(st->dptr); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows);
+  dfree(st->drows);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
   dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
@@ -297,7 +300,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   st->z[0] = st->z[1] = nullptr;
   st->sc[0] = st->sc[1] = nullptr;
   dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->dcnt); dfree(st->dptr);
-  dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows);
+  dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows); dfree(st->drows);
   CHK(alloc_node_arrays(st, cap));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
                         st->stream));
@@ -506,9 +509,25 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // projecting [Delta Xbar, R] against Xbar (Sec. 3.5) with a third of the Gram work.
   T* dX = rsvd ? b.Zc + K + st->L : b.W;  // Delta Xbar
   T* Rb = b.Zc + K;                        // R (RSVD)
+  // Delta Xbar is zero except on the rows of Delta with an entry in an old column (for the
+  // adjacency and the Laplacian's form; the normalised Laplacian's form changes whole
+  // rows), so the first projection round of a block made of it alone covers those rows
   auto project = [&]() {
-    if (rsvd) orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0);
-    else orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0);
+    const bool sparse_dx = !nlap && (rsvd || st->variant == GREST_G2);
+    if (sparse_dx) {
+      launch_delta1_rows(n, S, st->dptr, st->dcol, st->dcnt, st->newlen, st->scan_tmp, st->drows, s);
+      const int64_t bound = std::min<int64_t>(n2, 2 * nc);
+      if (rsvd)
+        orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0, st->drows, st->newlen + n2, bound,
+                        nullptr, st->dcnt);
+      else
+        orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0, st->drows, st->newlen + n2, bound,
+                        nullptr, st->dcnt);
+    } else if (rsvd) {
+      orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0);
+    } else {
+      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0);
+    }
   };
   // ---- pad Xbar (Alg. 2): zero the appended rows of the whole basis row ----
   mark(st, 1);

@@ -337,6 +337,13 @@ __global__ void __launch_bounds__(BS) k_sketch_flags(int64_t n_old, int64_t n2, 
   }
 }
 
+// the rows of Delta with any entry: the rows where Delta_1 X can be nonzero (an entry in
+// an old column, or for the unnormalised Laplacian a degree change on an old row)
+__global__ void __launch_bounds__(BS) k_delta1_flags(int64_t n2, const int64_t* dptr, int64_t* flag) {
+  for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n2; r += (int64_t)gridDim.x * BS)
+    flag[r] = dptr[r + 1] > dptr[r] ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(BS) k_compact_rows(int64_t n2, const int64_t* flag, const int64_t* pos,
                                                      int32_t* rows) {
   for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n2; r += (int64_t)gridDim.x * BS)
@@ -459,6 +466,16 @@ void launch_sketch_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const
   const int64_t n2 = n_old + n_new;
   if (n2 <= 0) return;
   k_sketch_flags<<<grid_for(n2), BS, 0, s>>>(n_old, n2, dptr, dcol, flag);
+  launch_scan_excl(flag, pos, n2, scan_tmp, s);
+  k_compact_rows<<<grid_for(n2), BS, 0, s>>>(n2, flag, pos, rows);
+}
+
+void launch_delta1_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, int64_t* flag,
+                        int64_t* pos, int64_t* scan_tmp, int32_t* rows, hipStream_t s) {
+  const int64_t n2 = n_old + n_new;
+  if (n2 <= 0) return;
+  (void)dcol;
+  k_delta1_flags<<<grid_for(n2), BS, 0, s>>>(n2, dptr, flag);
   launch_scan_excl(flag, pos, n2, scan_tmp, s);
   k_compact_rows<<<grid_for(n2), BS, 0, s>>>(n2, flag, pos, rows);
 }

@@ -32,6 +32,10 @@ void launch_scan_excl(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, 
 // and pos hold n_old + n_new + 1 entries, rows at most min(n_old + n_new, n_new + 2 nnz)
 void launch_sketch_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, int64_t* flag,
                         int64_t* pos, int64_t* scan_tmp, int32_t* rows, hipStream_t s);
+// the same for the rows of Delta with any entry (where Delta_1 X can be nonzero); rows at
+// most min(n_old + n_new, 2 nnz) entries
+void launch_delta1_rows(int64_t n_old, int64_t n_new, const int64_t* dptr, const int32_t* dcol, int64_t* flag,
+                        int64_t* pos, int64_t* scan_tmp, int32_t* rows, hipStream_t s);
 // bits of a node id in the packed (row, column) keys of Delta
 int delta_key_shift(int64_t n2);
 // keys and signs of the two directed entries of every change (invalid: all-ones key and
