@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--compare", default="fp32", help="second path timed beside the headline ('' to skip)")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink node counts (quick runs only)")
     ap.add_argument("--init-iters", type=int, default=40)
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run each update's graph stage on the state's stream (no second stream)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-graphs", type=int, default=32,
                     help="graphs in the many-graph serving leg (0 skips it; the full mix has 256)")
@@ -117,6 +119,7 @@ def main():
                      stream=torch.cuda.current_stream().cuda_stream, node_capacity=n_final + 1,
                      nnz_capacity=nnz_cap)
         st.init_pairs(iterations=args.init_iters, seed=7)
+        st.set_overlap(not args.no_overlap)
         return st
 
     def run_path(prec):
@@ -186,7 +189,7 @@ def main():
         "config": {"workload": "SBM n0=1e6, 32 Dirichlet(2) blocks, mean degree 20, +10k nodes/+50k edges "
                                "per step; adjacency, k=32, G-REST_RSVD L=P=32 (width 96)",
                    "n0": n0_main, "k": K, "L": L, "P": P, "variant": "rsvd", "precision": args.precision,
-                   "scale": args.scale},
+                   "scale": args.scale, "graph_stage_overlap": not args.no_overlap},
         "stages_ms_per_update": {k: round(v / max(1, main_res["updates"]), 4) for k, v in stages.items()},
         "dominant_stage": dominant,
         "roofline": {"kernel": "spmm (product with the updated operator)", "bound": "hbm",

@@ -177,6 +177,19 @@ void grest_destroy(grest_state* st);
  * work already queued on the old stream first.  EINVAL on a NULL state. */
 grest_status grest_set_stream(grest_state* st, void* stream);
 
+/*
+ * Overlap mode (enable = 1): the graph stage of each update -- the change list turned
+ * into Delta's CSR, its validation, the merge into the new CSR (Sec. 2, eq. adj_update)
+ * -- runs on a second stream owned by the state, so that it proceeds while the device
+ * still finishes the previous update; the rest of the update stays on the state's stream
+ * and waits for it with an event.  Results are the same as without it.  Contract: with
+ * where = GREST_DEVICE the change arrays given to grest_update must be complete when it
+ * is called (the graph stage no longer waits for earlier work of the state's stream);
+ * omega is still read on the state's stream.  enable = 0 returns to one stream.  Waits
+ * for the queued work first.  EINVAL on a NULL state, EDEVICE if no stream can be made.
+ */
+grest_status grest_set_overlap(grest_state* st, int32_t enable);
+
 /* Device memory held by the state, in bytes (its current capacities). */
 grest_status grest_memory(const grest_state* st, int64_t* device_bytes);
 

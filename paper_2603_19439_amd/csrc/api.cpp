@@ -46,11 +46,12 @@ void set_err(const char* what, hipError_t e) {
 constexpr int32_t VALIDATION_BITS = ST_BAD_FORMAT | ST_DUPLICATE | ST_INSERT_EXISTING | ST_DELETE_MISSING;
 
 struct Pinned {
-  int32_t status;   // numerical status of the last update (copied at its end)
-  int32_t vstatus;  // validation status of the update in progress
-  int64_t m_new;
-  int64_t maxdeg;
+  int32_t status;  // numerical status of the last update (copied at its end)
   int32_t ranks[8];
+  struct {
+    int32_t vstatus;  // validation status of the update that used this slot
+    int64_t m_new;
+  } g[2];
 };
 
 template <typename P>
@@ -101,25 +102,43 @@ struct grest_state {
   void* omega_t = nullptr;
   double* omega64 = nullptr;
 
+  // Graph stage of an update (change list sorted into Delta, validation, merge into the
+  // other CSR buffer).  It runs on gstream, which is the state's stream unless the
+  // overlap mode gives it a stream of its own, so that it runs while the device finishes
+  // the previous update.  What the rest of the update reads (Delta's CSR, the status word
+  // of the validation) comes in two slots used by alternate updates; the arrays only
+  // the graph stage touches are single.
+  hipStream_t gstream = nullptr;
+  bool overlap = false;
+  int dslot = 0;               // slot of the update in progress
+  bool prev_rejected = false;  // the last update call failed its validation
+  hipEvent_t gev[2] = {};      // graph stage of the slot's update done (results on the host)
+  hipEvent_t endev[2] = {};    // every kernel of the slot's update done
+  bool end_recorded[2] = {false, false};
   int32_t *d_ei = nullptr, *d_ej = nullptr;
   int8_t* d_sg = nullptr;
-  int64_t *dcnt = nullptr, *dptr = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
-  int32_t* srows = nullptr;  // rows where the sketch Delta_2 Omega can be nonzero
-  int32_t* drows = nullptr;  // rows where Delta_1 X can be nonzero
+  int64_t *dcnt = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
+  int64_t* dptr[2] = {nullptr, nullptr};
+  int32_t* dcol[2] = {nullptr, nullptr};
+  int8_t* dsg[2] = {nullptr, nullptr};
+  int32_t* vstat[2] = {nullptr, nullptr};  // validation bits per slot
   uint64_t *dkey_in = nullptr, *dkey_out = nullptr;  // packed (row, column) keys of Delta
   char* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
-  int32_t *dcol = nullptr, *dins = nullptr;
-  int8_t *dsg_tmp = nullptr, *dsg = nullptr;
+  int32_t* dins = nullptr;
+  int8_t* dsg_tmp = nullptr;
+  // row lists of the sparse projection rounds (flags, positions, scan workspace)
+  int64_t *rflag = nullptr, *rpos = nullptr, *rscan_tmp = nullptr;
+  int32_t* srows = nullptr;  // rows where the sketch Delta_2 Omega can be nonzero
+  int32_t* drows = nullptr;  // rows where Delta_1 X can be nonzero
 
   double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *Mchol = nullptr, *H = nullptr, *F = nullptr;
   double *theta = nullptr, *Fb = nullptr, *thetab = nullptr, *partial = nullptr, *eigwork = nullptr;
   int32_t* ranks = nullptr;
   int32_t* status = nullptr;
-  int64_t* maxdeg = nullptr;
+  int64_t* maxdeg[2] = {nullptr, nullptr};  // largest degree of CSR buffer b
   Pinned* pin = nullptr;
   double* theta_pin = nullptr;
-  hipEvent_t vev = nullptr;  // recorded once the validation result is on its way to the host
   int32_t deferred = 0;
   int64_t partial_elems = 0;
   // adjacency only: aux[:, 0:K] holds A X for the current graph and tracked block (kept
@@ -135,6 +154,7 @@ struct grest_state {
   int pslot = 0;
   bool prof_pending[2] = {false, false};
   hipEvent_t pev[2][NSTAGE + 1] = {};
+  hipEvent_t gend[2] = {};    // end of the graph stage (on gstream)
   hipEvent_t kev[2][2] = {};  // around the (op Z) product alone
   double stage_ms[NSTAGE] = {};
   double spmm_ms = 0.0;
@@ -147,7 +167,7 @@ struct grest_state {
 namespace {
 
 void mark(grest_state* st, int i) {
-  if (st->marking) (void)hipEventRecord(st->pev[st->pslot][i], st->stream);
+  if (st->marking) (void)hipEventRecord(st->pev[st->pslot][i], i == 0 ? st->gstream : st->stream);
 }
 
 void mark_spmm(grest_state* st, int i) {
@@ -159,7 +179,8 @@ void prof_collect_slot(grest_state* st, int slot) {
   if (!st->prof_pending[slot]) return;
   for (int i = 0; i < grest_state::NSTAGE; ++i) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, st->pev[slot][i], st->pev[slot][i + 1]) == hipSuccess) st->stage_ms[i] += ms;
+    hipEvent_t e1 = i == 0 ? st->gend[slot] : st->pev[slot][i + 1];
+    if (hipEventElapsedTime(&ms, st->pev[slot][i], e1) == hipSuccess) st->stage_ms[i] += ms;
   }
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, st->kev[slot][0], st->kev[slot][1]) == hipSuccess) st->spmm_ms += ms;
@@ -180,6 +201,13 @@ namespace {
 
 int64_t round_up(int64_t v, int64_t q) { return ((v + q - 1) / q) * q; }
 
+// wait for everything queued on the state's streams
+grest_status sync_all(grest_state* st) {
+  HIPCHK(hipStreamSynchronize(st->stream));
+  if (st->gstream && st->gstream != st->stream) HIPCHK(hipStreamSynchronize(st->gstream));
+  return GREST_OK;
+}
+
 grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   const size_t es = st->es;
   for (int b = 0; b < 2; ++b) {
@@ -194,11 +222,15 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   }
   st->y_clean = false;
   CHK(dalloc(&st->dcnt, cap_n + 1));
-  CHK(dalloc(&st->dptr, cap_n + 1));
+  CHK(dalloc(&st->dptr[0], cap_n + 1));
+  CHK(dalloc(&st->dptr[1], cap_n + 1));
   CHK(dalloc(&st->newlen, cap_n + 1));
+  CHK(dalloc(&st->scan_tmp, scan_tmp_elems(cap_n + 1) + 16));
+  CHK(dalloc(&st->rflag, cap_n + 1));
+  CHK(dalloc(&st->rpos, cap_n + 1));
+  CHK(dalloc(&st->rscan_tmp, scan_tmp_elems(cap_n + 1) + 16));
   CHK(dalloc(&st->srows, cap_n + 1));
   CHK(dalloc(&st->drows, cap_n + 1));
-  CHK(dalloc(&st->scan_tmp, scan_tmp_elems(cap_n + 1) + 16));
   st->cap_n = cap_n;
   return GREST_OK;
 }
@@ -213,10 +245,10 @@ grest_status alloc_edge_arrays(grest_state* st, int64_t cap_m) {
 }
 
 grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
-  HIPCHK(hipStreamSynchronize(st->stream));  // queued work may still read the old arrays
+  CHK(sync_all(st));  // queued work may still read the old arrays
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
-  dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
+  dfree(st->dcol[0]); dfree(st->dcol[1]); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg[0]); dfree(st->dsg[1]);
   CHK(dalloc(&st->d_ei, cap_nc));
   CHK(dalloc(&st->d_ej, cap_nc));
   CHK(dalloc(&st->d_sg, cap_nc));
@@ -224,16 +256,18 @@ grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
   CHK(dalloc(&st->dkey_out, 2 * cap_nc));
   st->sort_tmp_bytes = delta_sort_temp_bytes(2 * cap_nc);
   CHK(dalloc(&st->sort_tmp, st->sort_tmp_bytes));
-  CHK(dalloc(&st->dcol, 2 * cap_nc));
+  for (int b = 0; b < 2; ++b) {
+    CHK(dalloc(&st->dcol[b], 2 * cap_nc));
+    CHK(dalloc(&st->dsg[b], 2 * cap_nc));
+  }
   CHK(dalloc(&st->dins, 2 * cap_nc));
   CHK(dalloc(&st->dsg_tmp, 2 * cap_nc));
-  CHK(dalloc(&st->dsg, 2 * cap_nc));
   st->cap_nc = cap_nc;
   return GREST_OK;
 }
 
 grest_status alloc_sketch_arrays(grest_state* st, int64_t cap_s) {
-  HIPCHK(hipStreamSynchronize(st->stream));  // queued work may still read the old arrays
+  CHK(sync_all(st));  // queued work may still read the old arrays
   dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   if (st->variant != GREST_RSVD) { st->cap_s = cap_s; return GREST_OK; }
   CHK(dalloc((char**)&st->bt, (size_t)cap_s * st->Ls * st->es));
@@ -253,12 +287,15 @@ int64_t device_bytes(const grest_state* st) {
   for (int b = 0; b < 2; ++b) { add(st->rp[b]); add(st->col[b]); add(st->sc[b]); add(st->z[b]); }
   add(st->aux); add(st->ybuf); add(st->mbuf); add(st->srows_cnt); add(st->bt); add(st->omega_t); add(st->omega64);
   add(st->d_ei); add(st->d_ej); add(st->d_sg);
-  add(st->dcnt); add(st->dptr); add(st->newlen); add(st->scan_tmp); add(st->srows); add(st->drows);
-  add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp);
-  add(st->dcol); add(st->dins); add(st->dsg_tmp); add(st->dsg);
+  add(st->dcnt); add(st->newlen); add(st->scan_tmp); add(st->srows); add(st->drows);
+  add(st->rflag); add(st->rpos); add(st->rscan_tmp);
+  add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp); add(st->dins); add(st->dsg_tmp);
+  for (int b = 0; b < 2; ++b) {
+    add(st->dptr[b]); add(st->dcol[b]); add(st->dsg[b]); add(st->vstat[b]); add(st->maxdeg[b]);
+  }
   add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F);
   add(st->theta); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
-  add(st->ranks); add(st->status); add(st->maxdeg);
+  add(st->ranks); add(st->status);
   return total;
 }
 
@@ -268,15 +305,18 @@ void free_all(grest_state* st) {
   }
   dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->srows_cnt); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
-  dfree(st->dcnt); dfree(st->dptr); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows);
-  dfree(st->drows);
-  dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
-  dfree(st->dcol); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg);
+  dfree(st->dcnt); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows); dfree(st->drows);
+  dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp);
+  dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp); dfree(st->dins); dfree(st->dsg_tmp);
+  for (int b = 0; b < 2; ++b) {
+    dfree(st->dptr[b]); dfree(st->dcol[b]); dfree(st->dsg[b]); dfree(st->vstat[b]); dfree(st->maxdeg[b]);
+    if (st->gev[b]) (void)hipEventDestroy(st->gev[b]);
+    if (st->endev[b]) (void)hipEventDestroy(st->endev[b]);
+    st->gev[b] = st->endev[b] = nullptr;
+  }
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
   dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
-  dfree(st->ranks); dfree(st->status); dfree(st->maxdeg);
-  if (st->vev) (void)hipEventDestroy(st->vev);
-  st->vev = nullptr;
+  dfree(st->ranks); dfree(st->status);
   if (st->pin) (void)hipHostFree(st->pin);
   if (st->theta_pin) (void)hipHostFree(st->theta_pin);
   st->pin = nullptr;
@@ -288,7 +328,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   int64_t cap = std::max<int64_t>(need, st->cap_n + st->cap_n / 2);
   if (cap + 1 > (int64_t)4096 * 2048) cap = (int64_t)4096 * 2048 - 1;
   if (cap < need) return GREST_EINVAL;  // device scan limit
-  HIPCHK(hipStreamSynchronize(st->stream));
+  CHK(sync_all(st));
   st->ax_valid = false;  // the product buffer is reallocated below
   int64_t* rp_old = st->rp[st->gcur];
   void* z_old = st->z[st->zcur];
@@ -299,8 +339,9 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   st->rp[0] = st->rp[1] = nullptr;
   st->z[0] = st->z[1] = nullptr;
   st->sc[0] = st->sc[1] = nullptr;
-  dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->dcnt); dfree(st->dptr);
-  dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows); dfree(st->drows);
+  dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->dcnt); dfree(st->dptr[0]); dfree(st->dptr[1]);
+  dfree(st->newlen); dfree(st->scan_tmp); dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp);
+  dfree(st->srows); dfree(st->drows);
   CHK(alloc_node_arrays(st, cap));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
                         st->stream));
@@ -314,7 +355,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
 
 grest_status grow_edges(grest_state* st, int64_t need) {
   int64_t cap = std::max<int64_t>(need, st->cap_m + st->cap_m / 2);
-  HIPCHK(hipStreamSynchronize(st->stream));
+  CHK(sync_all(st));
   int32_t* keep[2] = {st->col[0], st->col[1]};
   st->col[0] = st->col[1] = nullptr;
   CHK(alloc_edge_arrays(st, cap));
@@ -452,42 +493,72 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   constexpr int kAxRefresh = 16;
   const bool reuse = st->op == GREST_OP_ADJ && st->ax_valid && st->ax_age + 1 < kAxRefresh;
 
+  const int gn = st->gcur ^ 1;
+  const int ds = st->dslot;
+  // ---- graph update and validation (Sec. 2, eq. adj_update) on the graph stream ----
+  // It writes CSR buffer gn and Delta slot ds.  Without the overlap mode it simply
+  // follows the earlier work on the one stream.  With it, it waits only for the last
+  // readers of what it overwrites: the update two calls back, which used slot ds and
+  // read buffer gn as its new graph; and the previous update as well when that one read
+  // buffer gn too (the normalised Laplacian's Delta Xbar reads the old graph, and a
+  // rejected update's queued work reads the scales of buffer gn).
+  hipStream_t gs = st->gstream;
+  if (gs != s) {
+    if (st->end_recorded[ds]) HIPCHK(hipStreamWaitEvent(gs, st->endev[ds], 0));
+    if ((st->op == GREST_OP_NLAP || st->prev_rejected) && st->end_recorded[ds ^ 1])
+      HIPCHK(hipStreamWaitEvent(gs, st->endev[ds ^ 1], 0));
+  }
   const int32_t* dei = ei;
   const int32_t* dej = ej;
-  const int8_t* dsg = sg;
+  const int8_t* dsgn = sg;
   if (where == GREST_HOST && nc > 0) {
-    HIPCHK(hipMemcpyAsync(st->d_ei, ei, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(st->d_ej, ej, nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(st->d_sg, sg, nc * sizeof(int8_t), hipMemcpyHostToDevice, s));
-    dei = st->d_ei; dej = st->d_ej; dsg = st->d_sg;
+    HIPCHK(hipMemcpyAsync(st->d_ei, ei, nc * sizeof(int32_t), hipMemcpyHostToDevice, gs));
+    HIPCHK(hipMemcpyAsync(st->d_ej, ej, nc * sizeof(int32_t), hipMemcpyHostToDevice, gs));
+    HIPCHK(hipMemcpyAsync(st->d_sg, sg, nc * sizeof(int8_t), hipMemcpyHostToDevice, gs));
+    dei = st->d_ei; dej = st->d_ej; dsgn = st->d_sg;
   }
-  const int gn = st->gcur ^ 1;
-  // ---- graph update and validation (Sec. 2, eq. adj_update) ----
+  int64_t* dptr = st->dptr[ds];
+  int32_t* dcol = st->dcol[ds];
+  int8_t* dsg = st->dsg[ds];
+  int64_t* maxdeg = st->maxdeg[gn];
   st->marking = st->prof;
   mark(st, 0);
-  launch_fill_bytes0(st->status, sizeof(int32_t), s);
-  launch_fill_bytes0(st->maxdeg, sizeof(int64_t), s);
-  launch_fill_i64(st->dcnt, 0, n2 + 1, s);
+  launch_fill_bytes0(st->vstat[ds], sizeof(int32_t), gs);
+  launch_fill_bytes0(maxdeg, sizeof(int64_t), gs);
+  launch_fill_i64(st->dcnt, 0, n2 + 1, gs);
   const int kshift = delta_key_shift(n2);
-  launch_delta_keys(dei, dej, dsg, nc, n, S, kshift, st->dkey_in, st->dsg_tmp, st->dcnt, st->status, s);
-  launch_scan_excl(st->dcnt, st->dptr, n2, st->scan_tmp, s);
-  if (!launch_delta_sort(st->dkey_in, st->dkey_out, st->dsg_tmp, st->dsg, 2 * nc, 2 * kshift, st->sort_tmp,
-                         st->sort_tmp_bytes, s)) {
+  launch_delta_keys(dei, dej, dsgn, nc, n, S, kshift, st->dkey_in, st->dsg_tmp, st->dcnt, st->vstat[ds], gs);
+  launch_scan_excl(st->dcnt, dptr, n2, st->scan_tmp, gs);
+  if (!launch_delta_sort(st->dkey_in, st->dkey_out, st->dsg_tmp, dsg, 2 * nc, 2 * kshift, st->sort_tmp,
+                         st->sort_tmp_bytes, gs)) {
     snprintf(g_last_error, sizeof(g_last_error), "radix sort of the update could not be launched");
     return GREST_EDEVICE;
   }
-  launch_delta_extract(st->dkey_out, 2 * nc, st->dptr + n2, kshift, st->dcol, s);
-  launch_delta_rows(n, S, st->dptr, st->dcol, st->dsg, st->dins, st->rp[st->gcur], st->col[st->gcur], st->newlen,
-                    st->status, s);
-  launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, s);
-  launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], st->dptr, st->dcol, st->dsg, st->dins, st->rp[gn],
-                   st->col[gn], st->cap_m, s);
-  if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, st->maxdeg, s);
-  else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], st->maxdeg, s);
-  HIPCHK(hipMemcpyAsync(&st->pin->vstatus, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&st->pin->m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&st->pin->maxdeg, st->maxdeg, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(st->vev, s));
+  launch_delta_extract(st->dkey_out, 2 * nc, dptr + n2, kshift, dcol, gs);
+  launch_delta_rows(n, S, dptr, dcol, dsg, st->dins, st->rp[st->gcur], st->col[st->gcur], st->newlen, st->vstat[ds],
+                    gs);
+  launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, gs);
+  launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, st->dins, st->rp[gn], st->col[gn],
+                   st->cap_m, gs);
+  if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, maxdeg, gs);
+  else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], maxdeg, gs);
+  HIPCHK(hipMemcpyAsync(&st->pin->g[ds].vstatus, st->vstat[ds], sizeof(int32_t), hipMemcpyDeviceToHost, gs));
+  HIPCHK(hipMemcpyAsync(&st->pin->g[ds].m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, gs));
+  if (st->marking) (void)hipEventRecord(st->gend[st->pslot], gs);
+  HIPCHK(hipEventRecord(st->gev[ds], gs));
+  st->dslot ^= 1;
+  // the rest of the update follows the graph stage; the numerical status word is cleared
+  // for it (the previous update's word has been copied out by then, on this stream)
+  if (gs != s) HIPCHK(hipStreamWaitEvent(s, st->gev[ds], 0));
+  launch_fill_bytes0(st->status, sizeof(int32_t), s);
+  // every return below records the end of this update's kernels (they read slot ds)
+  struct EndMark {
+    grest_state* st;
+    int slot;
+    ~EndMark() {
+      if (hipEventRecord(st->endev[slot], st->stream) == hipSuccess) st->end_recorded[slot] = true;
+    }
+  } end_mark{st, ds};
 
   // The host needs the validation result before it commits.  Work that reads only the
   // update's own arrays (whose column ids are in range whatever the validation finds,
@@ -515,14 +586,14 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   auto project = [&]() {
     const bool sparse_dx = !nlap && (rsvd || st->variant == GREST_G2);
     if (sparse_dx) {
-      launch_delta1_rows(n, S, st->dptr, st->dcol, st->dcnt, st->newlen, st->scan_tmp, st->drows, s);
+      launch_delta1_rows(n, S, dptr, dcol, st->rflag, st->rpos, st->rscan_tmp, st->drows, s);
       const int64_t bound = std::min<int64_t>(n2, 2 * nc);
       if (rsvd)
-        orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0, st->drows, st->newlen + n2, bound,
-                        nullptr, st->dcnt);
+        orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0, st->drows, st->rpos + n2, bound,
+                        nullptr, st->rflag);
       else
-        orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0, st->drows, st->newlen + n2, bound,
-                        nullptr, st->dcnt);
+        orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0, st->drows, st->rpos + n2, bound,
+                        nullptr, st->rflag);
     } else if (rsvd) {
       orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0);
     } else {
@@ -534,7 +605,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   launch_fill_rows<T>(b.Zc, st->ldz, n, S, st->ldz, s);
   // ---- Delta Xbar = Delta_1 X (Prop. 3) ----
   if (!nlap)
-    launch_delta_mul<T>(0, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, b.Zc, st->ldz, K, dX,
+    launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX,
                         st->ldz, s, reuse ? b.aux : nullptr, st->D);
   st->ax_valid = false;  // valid again only once this update commits
   mark(st, 2);
@@ -544,7 +615,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     const int w2 = st->Dw - K;
     launch_fill_rows<T>(B2, st->ldz, 0, n2, w2, s);
     if (S > 0)
-      launch_delta_mul<T>(3, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, nullptr, 0, w2, B2,
+      launch_delta_mul<T>(3, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, nullptr, 0, w2, B2,
                           st->ldz, s);
   } else if (rsvd) {
     if (S == 0) {
@@ -572,24 +643,25 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
         launch_zero_listed_rows<T>(b.Y, st->ldy, Ls, st->srows, st->srows_cnt, st->srows_bound, s);
       else
         launch_fill_rows<T>(b.Y, st->ldy, 0, n2, Ls, s);
-      launch_sketch_rows(n, S, st->dptr, st->dcol, st->dcnt, st->newlen, st->scan_tmp, st->srows, s);
+      launch_sketch_rows(n, S, dptr, dcol, st->rflag, st->rpos, st->rscan_tmp, st->srows, s);
       const int64_t bound = std::min<int64_t>(n2, S + 2 * nc);
-      launch_copy_i64(st->newlen + n2, st->srows_cnt, s);
+      launch_copy_i64(st->rpos + n2, st->srows_cnt, s);
       st->srows_bound = bound;
       st->y_clean = true;
-      launch_delta_mul<T>(1, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, (const T*)st->omega_t,
+      launch_delta_mul<T>(1, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, (const T*)st->omega_t,
                           Ls, Ls, b.Y, st->ldy, s);
       // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds; the first
       // round's read passes cover the listed rows of Y only, and M goes to its own buffer
-      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->srows, st->newlen + n2, bound, Mb,
-                      st->dcnt);
+      orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->srows, st->rpos + n2, bound, Mb,
+                      st->rflag);
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
-      launch_delta_mul<T>(2, st->op, n, S, st->dptr, st->dcol, st->dsg, st->maxdeg, sc_new, Mb, st->ldy, Ls,
+      launch_delta_mul<T>(2, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, Mb, st->ldy, Ls,
                           (T*)st->bt, Ls, s);
       launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
       if (!launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
                             st->eigwork, st->status, s)) {
-        (void)hipEventSynchronize(st->vev);
+        (void)hipEventSynchronize(st->gev[ds]);
+        st->prev_rejected = true;  // nothing committed; queued work may still read slot ds
         st->marking = false;
         snprintf(g_last_error, sizeof(g_last_error), "sketch order %d outside the small eigensolver's range", Ls);
         return GREST_EINVAL;
@@ -602,18 +674,21 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // ---- projection (I - Pi) twice and CholQR2 ----
   if (!nlap) project();
 
-  HIPCHK(hipEventSynchronize(st->vev));
-  // every earlier update has finished: collect the numerical status and the stage times
-  // of the last one
+  HIPCHK(hipEventSynchronize(st->gev[ds]));
+  // every earlier update has finished (with the overlap mode, once the previous update's
+  // end event has passed): collect the numerical status and the stage times of the last one
+  if (gs != s && st->end_recorded[ds ^ 1]) HIPCHK(hipEventSynchronize(st->endev[ds ^ 1]));
   st->deferred |= st->pin->status & ST_NUMERIC;
   st->pin->status = 0;
   prof_collect_slot(st, st->pslot ^ 1);
-  if (st->pin->vstatus & VALIDATION_BITS) {
+  const int32_t vbits = st->pin->g[ds].vstatus;
+  st->prev_rejected = (vbits & VALIDATION_BITS) != 0;
+  if (st->prev_rejected) {
     st->marking = false;
-    snprintf(g_last_error, sizeof(g_last_error), "change list rejected (status bits 0x%x)", st->pin->vstatus);
+    snprintf(g_last_error, sizeof(g_last_error), "change list rejected (status bits 0x%x)", vbits);
     return GREST_EINVAL;
   }
-  const int64_t m_new = st->pin->m_new;
+  const int64_t m_new = st->pin->g[ds].m_new;
 
   if (nlap) {
     launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
@@ -662,7 +737,7 @@ grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
   double shift = 0.0;
   if (st->op == GREST_OP_LAP) {
     int64_t md = 0;
-    HIPCHK(hipMemcpy(&md, st->maxdeg, sizeof(int64_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&md, st->maxdeg[st->gcur], sizeof(int64_t), hipMemcpyDeviceToHost));
     shift = 2.0 * (double)md;
   } else if (st->op == GREST_OP_NLAP) {
     shift = 2.0;
@@ -857,6 +932,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
     if (hipStreamCreateWithFlags(&st->stream, hipStreamNonBlocking) != hipSuccess) { delete st; return GREST_EDEVICE; }
     st->own_stream = true;
   }
+  st->gstream = st->stream;
   grest_status rc = GREST_OK;
   auto fail = [&](grest_status e) { free_all(st); if (st->own_stream) (void)hipStreamDestroy(st->stream); delete st; return e; };
   int64_t capn = std::max<int64_t>(node_capacity, n0 + 1);
@@ -883,12 +959,16 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if ((rc = dalloc(&st->eigwork, ework)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->ranks, 8)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->status, 1)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->maxdeg, 1)) != GREST_OK) return fail(rc);
+  for (int b = 0; b < 2; ++b) {
+    if ((rc = dalloc(&st->maxdeg[b], 1)) != GREST_OK) return fail(rc);
+    if ((rc = dalloc(&st->vstat[b], 1)) != GREST_OK) return fail(rc);
+    if (hipEventCreateWithFlags(&st->gev[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
+    if (hipEventCreateWithFlags(&st->endev[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
+  }
   if ((rc = dalloc(&st->srows_cnt, 1)) != GREST_OK) return fail(rc);
   if (hipHostMalloc((void**)&st->pin, sizeof(Pinned)) != hipSuccess) return fail(GREST_ENOMEM);
   if (hipHostMalloc((void**)&st->theta_pin, st->K * sizeof(double)) != hipSuccess) return fail(GREST_ENOMEM);
   memset(st->pin, 0, sizeof(Pinned));
-  if (hipEventCreateWithFlags(&st->vev, hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
   // upload the graph
   st->n = n0;
   st->m = m0;
@@ -896,9 +976,9 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
     return fail(GREST_EDEVICE);
   if (m0 > 0 && hipMemcpyAsync(st->col[0], col, m0 * sizeof(int32_t), hipMemcpyHostToDevice, st->stream) != hipSuccess)
     return fail(GREST_EDEVICE);
-  launch_fill_bytes0(st->maxdeg, sizeof(int64_t), st->stream);
-  if (st->es == 8) launch_degrees(n0, st->rp[0], (double*)st->sc[0], nullptr, st->maxdeg, st->stream);
-  else launch_degrees(n0, st->rp[0], nullptr, (float*)st->sc[0], st->maxdeg, st->stream);
+  launch_fill_bytes0(st->maxdeg[0], sizeof(int64_t), st->stream);
+  if (st->es == 8) launch_degrees(n0, st->rp[0], (double*)st->sc[0], nullptr, st->maxdeg[0], st->stream);
+  else launch_degrees(n0, st->rp[0], nullptr, (float*)st->sc[0], st->maxdeg[0], st->stream);
   // symmetry check on the device would need a transpose; the host check above covers format
   if (hipStreamSynchronize(st->stream) != hipSuccess) return fail(GREST_EDEVICE);
   *out = st;
@@ -933,7 +1013,7 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
 
 grest_status grest_sync(grest_state* st) {
   if (!st) return GREST_EINVAL;
-  HIPCHK(hipStreamSynchronize(st->stream));
+  CHK(sync_all(st));
   prof_collect(st);
   int32_t bits = st->deferred | (st->pin->status & ST_NUMERIC);
   st->deferred = 0;
@@ -963,7 +1043,7 @@ grest_status grest_shape(const grest_state* st, int64_t* n, int64_t* nnz, int32_
 
 grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col) {
   if (!st) return GREST_EINVAL;
-  HIPCHK(hipStreamSynchronize(st->stream));
+  CHK(sync_all(st));
   if (rowptr) HIPCHK(hipMemcpy(rowptr, st->rp[st->gcur], (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
   if (col && st->m > 0) HIPCHK(hipMemcpy(col, st->col[st->gcur], st->m * sizeof(int32_t), hipMemcpyDeviceToHost));
   return GREST_OK;
@@ -971,7 +1051,7 @@ grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col) {
 
 grest_status grest_set_stream(grest_state* st, void* stream) {
   if (!st) return GREST_EINVAL;
-  HIPCHK(hipStreamSynchronize(st->stream));
+  CHK(sync_all(st));
   if (stream) {
     if (st->own_stream) (void)hipStreamDestroy(st->stream);
     st->own_stream = false;
@@ -981,6 +1061,23 @@ grest_status grest_set_stream(grest_state* st, void* stream) {
     HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     st->stream = s;
     st->own_stream = true;
+  }
+  if (!st->overlap) st->gstream = st->stream;
+  return GREST_OK;
+}
+
+grest_status grest_set_overlap(grest_state* st, int32_t enable) {
+  if (!st) return GREST_EINVAL;
+  CHK(sync_all(st));
+  if (enable && !st->overlap) {
+    hipStream_t g = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&g, hipStreamNonBlocking));
+    st->gstream = g;
+    st->overlap = true;
+  } else if (!enable && st->overlap) {
+    (void)hipStreamDestroy(st->gstream);
+    st->gstream = st->stream;
+    st->overlap = false;
   }
   return GREST_OK;
 }
@@ -993,10 +1090,11 @@ grest_status grest_memory(const grest_state* st, int64_t* bytes) {
 
 grest_status grest_profile(grest_state* st, int32_t enable) {
   if (!st) return GREST_EINVAL;
-  HIPCHK(hipStreamSynchronize(st->stream));
+  CHK(sync_all(st));
   if (enable && !st->pev[0][0]) {
     for (int b = 0; b < 2; ++b) {
       for (int i = 0; i <= grest_state::NSTAGE; ++i) HIPCHK(hipEventCreate(&st->pev[b][i]));
+      HIPCHK(hipEventCreate(&st->gend[b]));
       HIPCHK(hipEventCreate(&st->kev[b][0]));
       HIPCHK(hipEventCreate(&st->kev[b][1]));
     }
@@ -1013,7 +1111,7 @@ grest_status grest_profile(grest_state* st, int32_t enable) {
 grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stages, double* spmm_ms,
                                int64_t* updates, int64_t* spmm_cols) {
   if (!st) return GREST_EINVAL;
-  HIPCHK(hipStreamSynchronize(st->stream));
+  CHK(sync_all(st));
   prof_collect(st);
   if (stage_ms)
     for (int i = 0; i < n_stages && i < grest_state::NSTAGE; ++i) stage_ms[i] = st->stage_ms[i];
@@ -1025,8 +1123,10 @@ grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stag
 
 void grest_destroy(grest_state* st) {
   if (!st) return;
-  (void)hipStreamSynchronize(st->stream);
+  (void)sync_all(st);
+  if (st->overlap) (void)hipStreamDestroy(st->gstream);
   for (int b = 0; b < 2; ++b) {
+    if (st->gend[b]) (void)hipEventDestroy(st->gend[b]);
     for (int i = 0; i <= grest_state::NSTAGE; ++i)
       if (st->pev[b][i]) (void)hipEventDestroy(st->pev[b][i]);
     if (st->kev[b][0]) (void)hipEventDestroy(st->kev[b][0]);

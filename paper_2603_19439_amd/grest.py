@@ -60,6 +60,7 @@ _SIGS = [
                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("grest_destroy", None, [C.c_void_p]),
     ("grest_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("grest_set_overlap", C.c_int, [C.c_void_p, C.c_int32]),
     ("grest_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("grest_now_ns", C.c_int64, []),
     ("grest_server_create", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
@@ -223,6 +224,10 @@ class State:
 
     def set_stream(self, stream: Optional[int]):
         _check(lib().grest_set_stream(self._h, C.c_void_p(stream) if stream else None), "grest_set_stream")
+
+    def set_overlap(self, enable: bool = True):
+        """Run each update's graph stage on a second stream, overlapping the previous update."""
+        _check(lib().grest_set_overlap(self._h, int(bool(enable))), "grest_set_overlap")
 
     def profile(self, enable: bool = True):
         _check(lib().grest_profile(self._h, int(bool(enable))), "grest_profile")

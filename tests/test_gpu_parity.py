@@ -306,6 +306,68 @@ def test_deterministic_bitwise():
     assert np.array_equal(outs[0][1], outs[1][1])
 
 
+def _device_updates(wl, variant, L, P):
+    import torch
+    dev = torch.device("cuda")
+    ups = []
+    for t, d in enumerate(wl.deltas):
+        om = None
+        if variant == "rsvd" and d.n_new > 0:
+            om = torch.tensor(W.omega(wl.cfg_id, 0, t + 1, d.n_new, L + P), dtype=torch.float64, device=dev)
+        ups.append((d.n_new, torch.tensor(d.i, dtype=torch.int32, device=dev),
+                    torch.tensor(d.j, dtype=torch.int32, device=dev),
+                    torch.tensor(d.sign, dtype=torch.int8, device=dev), om))
+    torch.cuda.synchronize()
+    return ups
+
+
+@pytest.mark.parametrize("case", ["sbm_adj_rsvd_fp32", "sbm_adj_rsvd_fp64", "chunglu_nlap_g2_fp64",
+                                  "chunglu_lap_g3_mixed"])
+def test_overlap_mode_matches_one_stream(case):
+    """With the graph stage of each update on a second stream (grest_set_overlap), the
+    updates give the same bits as on one stream: device-resident change lists queued back
+    to back without a wait, the kept adjacency product, appended nodes, and a change list
+    that the device rejects between two updates (the next update still waits for the
+    rejected one's queued work)."""
+    import torch
+    wl_name, op, variant, prec = case.split("_")
+    if wl_name == "sbm":
+        wl = W.preset("sbm_n1e6", scale=0.01, steps=6)
+    else:
+        wl = W.preset("chunglu_n4e6", scale=0.002, steps=4)
+    k, L, P = 8, 8, 8
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, shift0 = O.leading_eigenpairs(A, k, op)
+    vals0 = th0 if op == "adj" else shift0 - th0
+    ups = _device_updates(wl, variant, L, P)
+    # an insertion of an edge that every graph of the run holds (the runs only insert
+    # edges, or delete few): rejected on the device as an existing edge
+    r0 = int(np.argmax(np.diff(wl.rowptr0) > 0))
+    c0 = int(wl.col0[wl.rowptr0[r0]:wl.rowptr0[r0 + 1]].max())
+    keep = all((d.sign > 0).all() for d in wl.deltas)
+    dev = torch.device("cuda")
+    bad = (torch.tensor([min(r0, c0)], dtype=torch.int32, device=dev),
+           torch.tensor([max(r0, c0)], dtype=torch.int32, device=dev),
+           torch.tensor([1], dtype=torch.int8, device=dev))
+    outs = []
+    for overlap in (False, True):
+        banner(f"overlap={overlap} {case}")
+        st = G.State(wl.rowptr0, wl.col0, k=k, variant=variant, op=op, precision=prec, L=L, P=P, max_new=96)
+        st.set_pairs(vals0, X0)
+        st.set_overlap(overlap)
+        for t, (S, i, j, g, om) in enumerate(ups):
+            st.update(S, i, j, g, om)
+            if t == 1 and keep:
+                with pytest.raises(G.GrestError) as e:
+                    st.update(0, *bad)
+                assert e.value.status == G.EINVAL
+        st.sync()
+        outs.append(st.get(np.float64) + st.graph())
+        st.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
 def test_device_init_pairs_match_exact_leading_pairs():
     banner("device initial eigensolver")
     wl = W.preset("sbm_n2000", steps=0)
