@@ -114,7 +114,8 @@ struct grest_state {
   bool prev_rejected = false;  // the last update call failed its validation
   hipEvent_t gev[2] = {};      // graph stage of the slot's update done (results on the host)
   hipEvent_t endev[2] = {};    // every kernel of the slot's update done
-  bool end_recorded[2] = {false, false};
+  hipEvent_t gate[2] = {};     // the slot's update has reached its small eigensolve
+  bool end_recorded[2] = {false, false}, gate_recorded[2] = {false, false};
   int32_t *d_ei = nullptr, *d_ej = nullptr;
   int8_t* d_sg = nullptr;
   int64_t *dcnt = nullptr, *newlen = nullptr, *scan_tmp = nullptr;
@@ -312,7 +313,8 @@ void free_all(grest_state* st) {
     dfree(st->dptr[b]); dfree(st->dcol[b]); dfree(st->dsg[b]); dfree(st->vstat[b]); dfree(st->maxdeg[b]);
     if (st->gev[b]) (void)hipEventDestroy(st->gev[b]);
     if (st->endev[b]) (void)hipEventDestroy(st->endev[b]);
-    st->gev[b] = st->endev[b] = nullptr;
+    if (st->gate[b]) (void)hipEventDestroy(st->gate[b]);
+    st->gev[b] = st->endev[b] = st->gate[b] = nullptr;
   }
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
   dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
@@ -440,7 +442,8 @@ void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, int slot) {
 // [seg2, seg2 + *rank2).
 template <typename T>
 grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const int32_t* col, const T* sc,
-                           int base, int32_t* rank_slot, bool reuse, int seg2 = 0, const int32_t* rank2 = nullptr) {
+                           int base, int32_t* rank_slot, bool reuse, int seg2 = 0, const int32_t* rank2 = nullptr,
+                           int gate_slot = -1) {
   Blocks<T> b = blocks<T>(st);
   // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
   const int c0 = reuse ? st->K : 0;
@@ -460,6 +463,10 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   }
   // small FP64 eigensolve on the leading K + rank block, selection of K pairs
   mark(st, 6);
+  // with the overlap mode the next update's graph stage starts here: the one-workgroup
+  // eigensolve leaves the rest of the device free for it
+  if (gate_slot >= 0 && st->overlap && hipEventRecord(st->gate[gate_slot], st->stream) == hipSuccess)
+    st->gate_recorded[gate_slot] = true;
   const int which = st->op == GREST_OP_ADJ ? 0 : 1;
   if (!launch_small_eig(st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
                         st->status, st->stream, seg2, rank2)) {
@@ -501,12 +508,16 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // readers of what it overwrites: the update two calls back, which used slot ds and
   // read buffer gn as its new graph; and the previous update as well when that one read
   // buffer gn too (the normalised Laplacian's Delta Xbar reads the old graph, and a
-  // rejected update's queued work reads the scales of buffer gn).
+  // rejected update's queued work reads the scales of buffer gn).  It also starts no
+  // earlier than the previous update's small eigensolve, so that its many short kernels
+  // do not queue behind the wide ones before it.
   hipStream_t gs = st->gstream;
   if (gs != s) {
     if (st->end_recorded[ds]) HIPCHK(hipStreamWaitEvent(gs, st->endev[ds], 0));
     if ((st->op == GREST_OP_NLAP || st->prev_rejected) && st->end_recorded[ds ^ 1])
       HIPCHK(hipStreamWaitEvent(gs, st->endev[ds ^ 1], 0));
+    else if (st->gate_recorded[ds ^ 1])
+      HIPCHK(hipStreamWaitEvent(gs, st->gate[ds ^ 1], 0));
   }
   const int32_t* dei = ei;
   const int32_t* dej = ej;
@@ -698,9 +709,10 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   mark(st, 4);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
   if (rsvd)  // kept columns: [0, K + r_R) and [K + L, K + L + r_dX)
-    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 4, reuse, K + st->L, st->ranks + 1));
+    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 4, reuse, K + st->L, st->ranks + 1,
+                         ds));
   else
-    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 1, reuse));
+    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 1, reuse, 0, nullptr, ds));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -964,6 +976,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
     if ((rc = dalloc(&st->vstat[b], 1)) != GREST_OK) return fail(rc);
     if (hipEventCreateWithFlags(&st->gev[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
     if (hipEventCreateWithFlags(&st->endev[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
+    if (hipEventCreateWithFlags(&st->gate[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
   }
   if ((rc = dalloc(&st->srows_cnt, 1)) != GREST_OK) return fail(rc);
   if (hipHostMalloc((void**)&st->pin, sizeof(Pinned)) != hipSuccess) return fail(GREST_ENOMEM);
