@@ -134,6 +134,7 @@ struct grest_state {
   int32_t* drows = nullptr;  // rows where Delta_1 X can be nonzero
 
   double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *Mchol = nullptr, *H = nullptr, *F = nullptr;
+  double* Msk = nullptr;  // coefficients of R = [Xbar Y1] (Mchol U_L), (K + Ls) x L
   double *theta = nullptr, *Fb = nullptr, *thetab = nullptr, *partial = nullptr, *eigwork = nullptr;
   int32_t* ranks = nullptr;
   int32_t* status = nullptr;
@@ -294,7 +295,7 @@ int64_t device_bytes(const grest_state* st) {
   for (int b = 0; b < 2; ++b) {
     add(st->dptr[b]); add(st->dcol[b]); add(st->dsg[b]); add(st->vstat[b]); add(st->maxdeg[b]);
   }
-  add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F);
+  add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F); add(st->Msk);
   add(st->theta); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
   add(st->ranks); add(st->status);
   return total;
@@ -316,7 +317,7 @@ void free_all(grest_state* st) {
     if (st->gate[b]) (void)hipEventDestroy(st->gate[b]);
     st->gev[b] = st->endev[b] = st->gate[b] = nullptr;
   }
-  dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F);
+  dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F); dfree(st->Msk);
   dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
   dfree(st->ranks); dfree(st->status);
   if (st->pin) (void)hipHostFree(st->pin);
@@ -402,10 +403,12 @@ Blocks<T> blocks(grest_state* st) {
 // With Wout the first round reads W and writes Wout (same leading dimension), and the
 // second round works on Wout in place; flag2 (with rows) marks the rows of W that can be
 // nonzero, so the first round's apply does not read the others.
+// Without last_apply the second round stops at its factor: the basis is then
+// [X Wout] Mchol, which the caller applies itself.
 template <typename T>
 void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T* W, int64_t ldw, int w, int slot,
                   const int32_t* rows = nullptr, const int64_t* nrows = nullptr, int64_t rows_bound = 0,
-                  T* Wout = nullptr, const int64_t* flag2 = nullptr) {
+                  T* Wout = nullptr, const int64_t* flag2 = nullptr, bool last_apply = true) {
   hipStream_t s = st->stream;
   for (int round = 0; round < 2; ++round) {
     const bool sparse = round == 0 && rows;
@@ -418,6 +421,7 @@ void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T
       launch_tn<T, true>(n, Win, ldw, w, Win, ldw, w, st->partial, st->Gm, s);
     }
     launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
+    if (round == 1 && !last_apply) break;
     launch_apply2<T>(n, X, ldx, kx, Win, ldw, w, st->Mchol, w, 1.0, 0.0, Wo, ldw, s,
                      round == 0 ? flag2 : nullptr);
   }
@@ -662,11 +666,18 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_delta_mul<T>(1, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, (const T*)st->omega_t,
                           Ls, Ls, b.Y, st->ldy, s);
       // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds; the first
-      // round's read passes cover the listed rows of Y only, and M goes to its own buffer
+      // round's read passes cover the listed rows of Y only, and its output Y1 goes to its
+      // own buffer.  M = [Xbar Y1] Mchol is needed in full only through R = M U_L, so the
+      // second round stops at its factor: M is formed on the listed rows alone (all that
+      // Delta_2^T M reads; into Y's rows, which keeps Y zero elsewhere), and R comes out of
+      // one pass over [Xbar Y1] with the coefficients Mchol U_L.
       orth_against<T>(st, n2, b.Zc, st->ldz, K, b.Y, st->ldy, Ls, 2, st->srows, st->rpos + n2, bound, Mb,
-                      st->rflag);
+                      st->rflag, false);
+      launch_apply2<T>(bound, b.Zc, st->ldz, K, Mb, st->ldy, Ls, st->Mchol, Ls, 1.0, 0.0, b.Y, st->ldy, s, nullptr,
+                       st->srows, st->srows_cnt);
+      const T* Mrows = b.Y;
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
-      launch_delta_mul<T>(2, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, Mb, st->ldy, Ls,
+      launch_delta_mul<T>(2, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, Mrows, st->ldy, Ls,
                           (T*)st->bt, Ls, s);
       launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
       if (!launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
@@ -678,7 +689,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
         return GREST_EINVAL;
       }
       // S.4: R = M U_L (its kept columns first, the dropped ones zero)
-      launch_apply<T>(n2, Mb, st->ldy, Ls, st->Fb, st->L, 1.0, 0.0, Rb, st->ldz, s);
+      launch_small_gemm(K + Ls, Ls, st->L, st->Mchol, st->Fb, st->Msk, s);
+      launch_apply2<T>(n2, b.Zc, st->ldz, K, Mb, st->ldy, Ls, st->Msk, st->L, 1.0, 0.0, Rb, st->ldz, s);
     }
   }
   mark(st, 3);
@@ -961,6 +973,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if ((rc = dalloc(&st->Gm, (size_t)wmax * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Mchol, (size_t)(st->K + wmax) * wmax + (size_t)(wmax + 1) * (wmax + 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->H, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->Msk, (size_t)(st->K + wmax) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->F, (size_t)dmax * st->K)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->theta, st->K)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Fb, (size_t)std::max(st->Ls, 1) * std::max(st->L, 1))) != GREST_OK) return fail(rc);

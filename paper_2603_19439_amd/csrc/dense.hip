@@ -35,6 +35,18 @@ __global__ void k_convert(const Ts* s, Td* d, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) d[i] = (Td)s[i];
 }
 
+// C (m x q) = A (m x p) B (p x q), row-major FP64, one output per thread
+__global__ void __launch_bounds__(256) k_small_gemm(int m, int p, int q, const double* __restrict__ A,
+                                                    const double* __restrict__ B, double* __restrict__ C) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * q) return;
+  const int i = idx / q, j = idx % q;
+  double acc = 0.0;
+#pragma unroll 16
+  for (int k = 0; k < p; ++k) acc = fma(A[(size_t)i * p + k], B[(size_t)k * q + j], acc);
+  C[idx] = acc;
+}
+
 inline int grid_cap(int64_t work, int cap = 4096) {
   int64_t g = (work + 255) / 256;
   if (g < 1) g = 1;
@@ -58,6 +70,11 @@ void launch_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const
 }
 
 void launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s) { k_copy_i64<<<1, 64, 0, s>>>(src, dst); }
+
+void launch_small_gemm(int m, int p, int q, const double* A, const double* B, double* C, hipStream_t s) {
+  if (m <= 0 || q <= 0) return;
+  k_small_gemm<<<(m * q + 255) / 256, 256, 0, s>>>(m, p, q, A, B, C);
+}
 
 template <typename Tsrc, typename Tdst>
 void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s) {

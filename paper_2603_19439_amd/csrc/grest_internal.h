@@ -121,6 +121,8 @@ void launch_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const
                              hipStream_t s);
 // *dst = *src on the device
 void launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
+// C (m x q) = A (m x p) B (p x q), row-major FP64
+void launch_small_gemm(int m, int p, int q, const double* A, const double* B, double* C, hipStream_t s);
 template <typename Tsrc, typename Tdst>
 void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s);
 
@@ -147,11 +149,12 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
                 double* C, double* G, hipStream_t s, const int32_t* rows = nullptr,
                 const int64_t* nrows = nullptr);
 // Out = beta Out + alpha [In1 | In2] M  (In1: n x a1, In2: n x a2, a1 + a2 <= 128).  With
-// flag2 the rows r with flag2[r] == 0 of In2 must be zero (they are then not read).
+// flag2 the rows r with flag2[r] == 0 of In2 must be zero (they are then not read).  With
+// rows (a device list, count in *nrows <= n) only the listed rows are computed.
 template <typename T>
 void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
                    const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s,
-                   const int64_t* flag2 = nullptr);
+                   const int64_t* flag2 = nullptr, const int32_t* rows = nullptr, const int64_t* nrows = nullptr);
 // Symmetric eigensolver of H (first base + rank[0] rows/cols used, ldh = d_full) and
 // selection of kk pairs: which 0 = largest magnitude, 1 = smallest algebraic,
 // 2 = largest algebraic.  Writes theta[kk] and F (d_full x kk, zero rows past the

@@ -554,10 +554,13 @@ __device__ inline void load_frag(const T* In1, int64_t ld1, int a1, const T* In2
   }
 }
 
+// With rows, the kernel covers the listed rows rows[0 .. min(n, *nrows)) only (n is then a
+// bound of the count); row idx of the tiles is matrix row rows[idx].
 template <typename T, typename Tc, bool VEC>
 __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2,
                                               int64_t ld2, int a2, const double* __restrict__ Mg, int b,
-                                              double alpha, double beta, T* Out, int64_t ldout) {
+                                              double alpha, double beta, T* Out, int64_t ldout,
+                                              const int32_t* __restrict__ rows, const int64_t* nrows) {
   using M = Mma<Tc>;
   extern __shared__ double sMraw[];
   Tc* sM = reinterpret_cast<Tc*>(sMraw);
@@ -571,20 +574,30 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
-  const int64_t ntile = (n + 15) >> 4;
+  const int64_t nl = rows ? (n < *nrows ? n : *nrows) : n;
+  const int64_t ntile = (nl + 15) >> 4;
   const int64_t stride = (int64_t)gridDim.x * NW;
+  // tile row idx -> matrix row, and the bound load_frag checks it against
+  auto load_t = [&](int64_t t, Tc(&f)[8][4]) __attribute__((always_inline)) {
+    const int64_t idx = t * 16 + c16;
+    if (!rows) {
+      load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, idx, n, KB, g, f);
+    } else {
+      const int64_t row = idx < nl ? (int64_t)rows[idx] : 0;
+      load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, row, idx < nl ? row + 1 : 0, KB, g, f);
+    }
+  };
   // one 16-row tile at a time; the next tile's fragments are in flight during its MFMAs
   int64_t tile = (int64_t)blockIdx.x * NW + wid;
   Tc nxt[8][4];
-  if (tile < ntile) load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, tile * 16 + c16, n, KB, g, nxt);
+  if (tile < ntile) load_t(tile, nxt);
   for (; tile < ntile; tile += stride) {
     Tc fin[8][4];
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
       for (int m = 0; m < 4; ++m) fin[kb][m] = nxt[kb][m];
-    if (tile + stride < ntile)
-      load_frag<T, Tc, VEC>(In1, ld1, a1, In2, ld2, a, (tile + stride) * 16 + c16, n, KB, g, nxt);
+    if (tile + stride < ntile) load_t(tile + stride, nxt);
     const int64_t row0 = tile * 16;
     for (int jt = 0; jt < TB; ++jt) {
       typename M::acc_t acc{0, 0, 0, 0};
@@ -598,9 +611,10 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t orow = row0 + M::row(lane, r);
+        const int64_t oidx = row0 + M::row(lane, r);
         const int ocol = jt * 16 + c16;
-        if (orow < n && ocol < b) {
+        if (oidx < nl && ocol < b) {
+          const int64_t orow = rows ? (int64_t)rows[oidx] : oidx;
           Tc v = acc[r];
           if (beta != 0.0) v += (Tc)beta * (Tc)Out[orow * ldout + ocol];
           Out[orow * ldout + ocol] = (T)v;
@@ -619,11 +633,13 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
 // two output tiles are accumulated side by side.  Every row's inputs are read before its
 // outputs are written, so Out may alias In2 (in-place update of a column block).
 // With flag2, the In2 part of row r is read only where flag2[r] != 0 (zero elsewhere).
+// With rows, only the listed rows rows[0 .. min(n, *nrows)) are covered.
 template <int KB, bool VEC>
 __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, int64_t ld1, int a1,
                                                   const float* In2, int64_t ld2, int a2,
                                                   const double* __restrict__ Mg, int b, double alpha, double beta,
-                                                  float* Out, int64_t ldout, const int64_t* __restrict__ flag2) {
+                                                  float* Out, int64_t ldout, const int64_t* __restrict__ flag2,
+                                                  const int32_t* __restrict__ rows, const int64_t* nrows) {
   extern __shared__ double sMraw[];
   f32x4* sM = reinterpret_cast<f32x4*>(sMraw);
   const int a = a1 + a2;
@@ -643,20 +659,26 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
-  const int64_t ntile = (n + 15) >> 4;
+  const int64_t nl = rows ? (n < *nrows ? n : *nrows) : n;
+  const int64_t ntile = (nl + 15) >> 4;
   const int64_t stride = (int64_t)gridDim.x * NW;
+  auto row_of = [&](int64_t idx) __attribute__((always_inline)) {
+    return rows ? (idx < nl ? (int64_t)rows[idx] : (int64_t)0) : idx;
+  };
   // VEC: a1, a and b are multiples of four and every row start is 16-byte aligned, so a
   // lane's four columns are either all inside one input block or all past the end
   auto load = [&](int64_t t, f32x4(&f)[KB]) __attribute__((always_inline)) {
-    const int64_t row = t * 16 + c16;
-    const bool use2 = row < n && (!flag2 || flag2[row] != 0);
+    const int64_t idx = t * 16 + c16;
+    const bool ok = idx < nl;
+    const int64_t row = row_of(idx);
+    const bool use2 = ok && (!flag2 || flag2[row] != 0);
     if (VEC) {
       const float* b1 = In1 + row * ld1;
       const float* b2 = In2 + row * ld2 - a1;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         const int k0 = kb * 16 + 4 * g;
-        f[kb] = (row < n && k0 < a && (k0 < a1 || use2))
+        f[kb] = (ok && k0 < a && (k0 < a1 || use2))
                     ? *reinterpret_cast<const f32x4*>((k0 < a1 ? b1 : b2) + k0)
                     : f32x4{0.f, 0.f, 0.f, 0.f};
       }
@@ -667,7 +689,7 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
         for (int m = 0; m < 4; ++m) {
           const int k = kb * 16 + 4 * g + m;
           float v = 0.f;
-          if (row < n && k < a) {
+          if (ok && k < a) {
             if (k < a1) v = In1[row * ld1 + k];
             else if (use2) v = In2[row * ld2 + (k - a1)];
           }
@@ -676,9 +698,9 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
       }
     }
   };
-  auto store = [&](int64_t row, int jt, f32x4 acc) __attribute__((always_inline)) {
+  auto store = [&](int64_t row, bool ok, int jt, f32x4 acc) __attribute__((always_inline)) {
     const int col0 = jt * 16 + 4 * g;
-    if (row >= n || jt >= TB) return;
+    if (!ok || jt >= TB) return;
     float* o = Out + row * ldout + col0;
     if (VEC) {
       if (col0 >= b) return;
@@ -707,7 +729,9 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) fin[kb] = nxt[kb];
     if (tile + stride < ntile) load(tile + stride, nxt);  // in flight during the MFMAs below
-    const int64_t row = tile * 16 + c16;
+    const int64_t ridx = tile * 16 + c16;
+    const bool rok = ridx < nl;
+    const int64_t row = row_of(ridx);
     for (int jt = 0; jt < TB; jt += 2) {
       const bool two = jt + 1 < TB;
       f32x4 acc0{0.f, 0.f, 0.f, 0.f}, acc1{0.f, 0.f, 0.f, 0.f};
@@ -721,8 +745,8 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
           acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(m1[m], fin[kb][m], acc1, 0, 0, 0);
         }
       }
-      store(row, jt, acc0);
-      store(row, jt + 1, acc1);
+      store(row, rok, jt, acc0);
+      store(row, rok, jt + 1, acc1);
     }
   }
 }
@@ -741,7 +765,7 @@ int device_cus() {
 template <int KB, bool VEC>
 void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
                       const double* M, int b, double alpha, double beta, float* Out, int64_t ldout,
-                      const int64_t* flag2, hipStream_t s) {
+                      const int64_t* flag2, const int32_t* rows, const int64_t* nrows, hipStream_t s) {
   const int TB = (b + 15) >> 4;
   const size_t lds = (size_t)KB * TB * 64 * sizeof(f32x4);
   // resident workgroups per CU for this LDS size (queried once per size; a persistent
@@ -766,22 +790,22 @@ void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const fl
   int64_t g = std::min<int64_t>((tiles + NW - 1) / NW, (int64_t)device_cus() * occ);
   if (g < 1) g = 1;
   k_apply_f32<KB, VEC><<<(unsigned)g, WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout,
-                                                     flag2);
+                                                     flag2, rows, nrows);
 }
 
 template <bool VEC>
 void apply_f32_dispatch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
                         const double* M, int b, double alpha, double beta, float* Out, int64_t ldout,
-                        const int64_t* flag2, hipStream_t s) {
+                        const int64_t* flag2, const int32_t* rows, const int64_t* nrows, hipStream_t s) {
   switch ((a1 + a2 + 15) >> 4) {
-    case 1: apply_f32_launch<1, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
-    case 2: apply_f32_launch<2, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
-    case 3: apply_f32_launch<3, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
-    case 4: apply_f32_launch<4, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
-    case 5: apply_f32_launch<5, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
-    case 6: apply_f32_launch<6, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
-    case 7: apply_f32_launch<7, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
-    default: apply_f32_launch<8, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s); break;
+    case 1: apply_f32_launch<1, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 2: apply_f32_launch<2, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 3: apply_f32_launch<3, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 4: apply_f32_launch<4, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 5: apply_f32_launch<5, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 6: apply_f32_launch<6, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 7: apply_f32_launch<7, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    default: apply_f32_launch<8, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
   }
 }
 
@@ -932,7 +956,8 @@ void launch_tn_bf16(int64_t n, const float* A, int64_t lda, int a, const float* 
 
 template <typename T, typename Tc, bool VEC>
 static void apply_launch(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
-                         const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s) {
+                         const double* M, int b, double alpha, double beta, T* Out, int64_t ldout,
+                         const int32_t* rows, const int64_t* nrows, hipStream_t s) {
   const int KB = (a1 + a2 + 15) >> 4, TB = (b + 15) >> 4;
   const size_t lds = (size_t)KB * 16 * (TB * 16 + 1) * sizeof(Tc);
   static const bool attr = [] {
@@ -941,23 +966,25 @@ static void apply_launch(int64_t n, const T* In1, int64_t ld1, int a1, const T* 
     return true;
   }();
   (void)attr;
-  k_apply<T, Tc, VEC><<<apply_grid(n), WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout);
+  k_apply<T, Tc, VEC><<<apply_grid(n), WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout,
+                                                     rows, nrows);
 }
 
 template <typename T>
 void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
                    const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s,
-                   const int64_t* flag2) {
+                   const int64_t* flag2, const int32_t* rows, const int64_t* nrows) {
   if (n <= 0 || b <= 0) return;
+  if (!rows) nrows = nullptr;
   const bool vec = aligned16(In1, ld1) && (a2 == 0 || (aligned16(In2, ld2) && a1 % 4 == 0));
   if constexpr (sizeof(T) == 8) {
-    if (vec) apply_launch<T, double, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
-    else apply_launch<T, double, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s);
+    if (vec) apply_launch<T, double, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, rows, nrows, s);
+    else apply_launch<T, double, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, rows, nrows, s);
   } else {
     if (vec && aligned16(Out, ldout) && a1 % 4 == 0 && (a1 + a2) % 4 == 0 && b % 4 == 0)
-      apply_f32_dispatch<true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s);
+      apply_f32_dispatch<true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
     else
-      apply_f32_dispatch<false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, s);
+      apply_f32_dispatch<false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
   }
 }
 
@@ -968,10 +995,11 @@ void launch_apply(int64_t n, const T* In, int64_t ldin, int a, const double* M, 
 }
 
 template void launch_apply2<float>(int64_t, const float*, int64_t, int, const float*, int64_t, int, const double*,
-                                   int, double, double, float*, int64_t, hipStream_t, const int64_t*);
+                                   int, double, double, float*, int64_t, hipStream_t, const int64_t*,
+                                   const int32_t*, const int64_t*);
 template void launch_apply2<double>(int64_t, const double*, int64_t, int, const double*, int64_t, int,
                                     const double*, int, double, double, double*, int64_t, hipStream_t,
-                                    const int64_t*);
+                                    const int64_t*, const int32_t*, const int64_t*);
 
 template void launch_tn<float, false>(int64_t, const float*, int64_t, int, const float*, int64_t, int, double*,
                                       double*, hipStream_t);
