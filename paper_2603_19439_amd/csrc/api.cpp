@@ -135,6 +135,7 @@ struct grest_state {
 
   double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *Mchol = nullptr, *H = nullptr, *F = nullptr;
   double* Msk = nullptr;  // coefficients of R = [Xbar Y1] (Mchol U_L), (K + Ls) x L
+  double* M1buf = nullptr;  // first-round factor of a fused CholQR2 (same shape as Mchol)
   double *theta = nullptr, *Fb = nullptr, *thetab = nullptr, *partial = nullptr, *eigwork = nullptr;
   int32_t* ranks = nullptr;
   int32_t* status = nullptr;
@@ -295,7 +296,7 @@ int64_t device_bytes(const grest_state* st) {
   for (int b = 0; b < 2; ++b) {
     add(st->dptr[b]); add(st->dcol[b]); add(st->dsg[b]); add(st->vstat[b]); add(st->maxdeg[b]);
   }
-  add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F); add(st->Msk);
+  add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F); add(st->Msk); add(st->M1buf);
   add(st->theta); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
   add(st->ranks); add(st->status);
   return total;
@@ -317,7 +318,7 @@ void free_all(grest_state* st) {
     if (st->gate[b]) (void)hipEventDestroy(st->gate[b]);
     st->gev[b] = st->endev[b] = st->gate[b] = nullptr;
   }
-  dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F); dfree(st->Msk);
+  dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F); dfree(st->Msk); dfree(st->M1buf);
   dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
   dfree(st->ranks); dfree(st->status);
   if (st->pin) (void)hipHostFree(st->pin);
@@ -405,11 +406,29 @@ Blocks<T> blocks(grest_state* st) {
 // nonzero, so the first round's apply does not read the others.
 // Without last_apply the second round stops at its factor: the basis is then
 // [X Wout] Mchol, which the caller applies itself.
+// FP32 blocks of the covered shapes fuse the first round's apply with the second round's
+// read pass (launch_apply_pip): W1 is written and its Gram products are formed from the
+// registers that hold it, which saves reading it back.
 template <typename T>
 void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T* W, int64_t ldw, int w, int slot,
                   const int32_t* rows = nullptr, const int64_t* nrows = nullptr, int64_t rows_bound = 0,
                   T* Wout = nullptr, const int64_t* flag2 = nullptr, bool last_apply = true) {
   hipStream_t s = st->stream;
+  if constexpr (sizeof(T) == 4) {
+    T* Wo = Wout ? Wout : W;
+    if (apply_pip_ok(X, ldx, kx, W, ldw, w, Wo, ldw)) {
+      if (!(rows ? launch_pip<T>(rows_bound, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s, rows, nrows)
+                 : launch_pip<T>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, st->Gm, s))) {
+        launch_tn<T, false>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
+        launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, s);
+      }
+      launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->M1buf, st->ranks + slot, st->status, st->eigwork, s);
+      launch_apply_pip(n, X, ldx, kx, W, ldw, w, flag2, st->M1buf, Wo, ldw, st->partial, st->C1, st->Gm, s);
+      launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + 1, st->status, st->eigwork, s);
+      if (last_apply) launch_apply2<T>(n, X, ldx, kx, Wo, ldw, w, st->Mchol, w, 1.0, 0.0, Wo, ldw, s);
+      return;
+    }
+  }
   for (int round = 0; round < 2; ++round) {
     const bool sparse = round == 0 && rows;
     T* Win = (round == 1 && Wout) ? Wout : W;
@@ -422,8 +441,16 @@ void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T
     }
     launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
     if (round == 1 && !last_apply) break;
-    launch_apply2<T>(n, X, ldx, kx, Win, ldw, w, st->Mchol, w, 1.0, 0.0, Wo, ldw, s,
-                     round == 0 ? flag2 : nullptr);
+    if (round == 0 && rows && Wout) {
+      // W is zero off the listed rows and goes to another buffer: Wout = X (-C M) over
+      // every row, then Wout += W M on the listed rows alone
+      launch_apply2<T>(n, X, ldx, kx, X, ldx, 0, st->Mchol, w, 1.0, 0.0, Wo, ldw, s);
+      launch_apply2<T>(rows_bound, W, ldw, w, W, ldw, 0, st->Mchol + (size_t)kx * w, w, 1.0, 1.0, Wo, ldw, s,
+                       nullptr, rows, nrows);
+    } else {
+      launch_apply2<T>(n, X, ldx, kx, Win, ldw, w, st->Mchol, w, 1.0, 0.0, Wo, ldw, s,
+                       round == 0 ? flag2 : nullptr);
+    }
   }
 }
 
@@ -972,6 +999,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if ((rc = dalloc(&st->C2, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Gm, (size_t)wmax * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Mchol, (size_t)(st->K + wmax) * wmax + (size_t)(wmax + 1) * (wmax + 1))) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->M1buf, (size_t)(st->D + wmax) * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->H, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Msk, (size_t)(st->K + wmax) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->F, (size_t)dmax * st->K)) != GREST_OK) return fail(rc);

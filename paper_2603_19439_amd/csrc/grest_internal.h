@@ -121,6 +121,15 @@ void launch_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const
                              hipStream_t s);
 // *dst = *src on the device
 void launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s);
+// First CholQR round's apply fused with the second round's read pass (FP32 blocks):
+// Out = W1 = [X | W] M1 (M1 (kx + w) x w; Out may be W), C = X^T W1 and G = W1^T W1 (FP64
+// results).  kx, w multiples of 16 of the covered shapes, 16-byte aligned rows; false (and
+// nothing queued) otherwise.  flag2 (optional) marks the rows where W can be nonzero.
+bool apply_pip_ok(const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w, const float* Out,
+                  int64_t ldout);
+bool launch_apply_pip(int64_t n, const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w,
+                      const int64_t* flag2, const double* M1, float* Out, int64_t ldout, double* partial, double* C,
+                      double* G, hipStream_t s);
 // C (m x q) = A (m x p) B (p x q), row-major FP64
 void launch_small_gemm(int m, int p, int q, const double* A, const double* B, double* C, hipStream_t s);
 template <typename Tsrc, typename Tdst>

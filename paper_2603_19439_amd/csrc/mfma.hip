@@ -1013,3 +1013,218 @@ template void launch_apply<float>(int64_t, const float*, int64_t, int, const dou
                                   int64_t, hipStream_t);
 template void launch_apply<double>(int64_t, const double*, int64_t, int, const double*, int, double, double,
                                    double*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------------
+// The first CholQR round's apply fused with the second round's read pass, on FP32 blocks:
+// W1 = [X | W] M1 for a 16-row tile as k_apply_f32 computes it (lane (g, c) holds row c,
+// columns 16 jt + 4 g .. + 3), written to Out (which may be W: a row is read before it is
+// written), and the tile's contributions to C = X^T W1 (FP32 MFMA) and G = W1^T W1 (FP64
+// MFMA, upper tiles, mirrored on output), as k_pip accumulates them.  X and W1 reach the
+// four-rows-per-step layout of those products through a per-wave LDS tile.  kx = 16 KBX,
+// w = 16 NWB; W's blocks are skipped on a tile where flag2 marks no row (W is zero there).
+// Each workgroup writes its partials for the fixed-order reduction.
+// ---------------------------------------------------------------------------------
+namespace {
+
+template <int KBX, int NWB>
+__global__ void __launch_bounds__(WG, 2) k_apply_pip(int64_t n, const float* __restrict__ X, int64_t ldx,
+                                                  const float* W, int64_t ldw, const int64_t* __restrict__ flag2,
+                                                  const double* __restrict__ M1, float* Out, int64_t ldout,
+                                                  double* __restrict__ partC, double* __restrict__ partG) {
+  constexpr int KB1 = KBX + NWB;
+  constexpr int kx = 16 * KBX, w = 16 * NWB;
+  constexpr int PT = kx + w + 4;  // pitch of the transposition tile (floats)
+  constexpr int NTG = NWB * (NWB + 1) / 2;
+  extern __shared__ double lds_raw[];
+  f32x4* sM1 = reinterpret_cast<f32x4*>(lds_raw);
+  float* tiles = reinterpret_cast<float*>(sM1 + KB1 * NWB * 64);
+  // coefficients in the fragment order of k_apply_f32: [kb][jt][g][c] -> M1[16 kb + 4 g + m][16 jt + c]
+  for (int idx = threadIdx.x; idx < KB1 * NWB * 64; idx += WG) {
+    const int c = idx & 15, g = (idx >> 4) & 3, t = idx >> 6;
+    const int kb = t / NWB, jt = t % NWB;
+    f32x4 v;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = (float)M1[(size_t)(kb * 16 + 4 * g + m) * w + jt * 16 + c];
+    sM1[idx] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int64_t ntile = (n + 15) >> 4;
+  const int64_t stride = (int64_t)gridDim.x * NW;
+  // fragments of [X | W] for row c16 of tile t; returns whether any row of the tile has W
+  auto load = [&](int64_t t, f32x4(&f)[KB1]) __attribute__((always_inline)) {
+    const int64_t row = t * 16 + c16;
+    const bool ok = row < n;
+    const bool use2 = ok && (!flag2 || flag2[row] != 0);
+#pragma unroll
+    for (int kb = 0; kb < KBX; ++kb)
+      f[kb] = ok ? *reinterpret_cast<const f32x4*>(X + row * ldx + kb * 16 + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < NWB; ++kb)
+      f[KBX + kb] = use2 ? *reinterpret_cast<const f32x4*>(W + row * ldw + kb * 16 + 4 * g)
+                         : f32x4{0.f, 0.f, 0.f, 0.f};
+    return __builtin_amdgcn_ballot_w64(use2) != 0;
+  };
+  typename Mma<float>::acc_t ac[KBX][NWB];
+  typename Mma<double>::acc_t ag[NTG];
+#pragma unroll
+  for (int p = 0; p < KBX; ++p)
+#pragma unroll
+    for (int q = 0; q < NWB; ++q) ac[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < NTG; ++t) ag[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  float* tile = tiles + wid * 16 * PT;
+  int64_t t = (int64_t)blockIdx.x * NW + wid;
+  f32x4 fin[KB1];
+  bool any2 = false;
+  if (t < ntile) any2 = load(t, fin);
+  for (; t < ntile; t += stride) {
+    // X to the wave's tile (row c16)
+#pragma unroll
+    for (int kb = 0; kb < KBX; ++kb) *reinterpret_cast<f32x4*>(tile + c16 * PT + kb * 16 + 4 * g) = fin[kb];
+    // W1 = [X | W] M1
+    f32x4 w1[NWB];
+#pragma unroll
+    for (int jt = 0; jt < NWB; ++jt) w1[jt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb) {
+      if (kb >= KBX && !any2) break;
+#pragma unroll
+      for (int jt = 0; jt < NWB; ++jt) {
+        const f32x4 mv = sM1[(kb * NWB + jt) * 64 + lane];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) w1[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[m], fin[kb][m], w1[jt], 0, 0, 0);
+      }
+    }
+    const int64_t row = t * 16 + c16;
+    // the next tile's fragments go into the same registers, in flight during the products
+    if (t + stride < ntile) any2 = load(t + stride, fin);
+    if (row < n) {
+#pragma unroll
+      for (int jt = 0; jt < NWB; ++jt) *reinterpret_cast<f32x4*>(Out + row * ldout + jt * 16 + 4 * g) = w1[jt];
+    }
+#pragma unroll
+    for (int jt = 0; jt < NWB; ++jt) *reinterpret_cast<f32x4*>(tile + c16 * PT + kx + jt * 16 + 4 * g) = w1[jt];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+    for (int s = 0; s < 4; ++s) {
+      const float* tr = tile + (4 * s + g) * PT;
+      float cx[KBX], cw[NWB];
+#pragma unroll
+      for (int p = 0; p < KBX; ++p) cx[p] = tr[p * 16 + c16];
+#pragma unroll
+      for (int q = 0; q < NWB; ++q) cw[q] = tr[kx + q * 16 + c16];
+#pragma unroll
+      for (int p = 0; p < KBX; ++p)
+#pragma unroll
+        for (int q = 0; q < NWB; ++q) ac[p][q] = Mma<float>::run(cx[p], cw[q], ac[p][q]);
+#pragma unroll
+      for (int p = 0; p < NWB; ++p)
+#pragma unroll
+        for (int q = p; q < NWB; ++q)
+          ag[tri_idx(p, q, NWB)] = Mma<double>::run((double)cw[p], (double)cw[q], ag[tri_idx(p, q, NWB)]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  // fixed-order sum of the four waves, then this workgroup's partials (the LDS of the
+  // coefficients and tiles is reused once every wave is past its loop)
+  __syncthreads();
+  double* red = lds_raw;
+  double* red2 = red + (size_t)KBX * NWB * 256;
+  for (int v = 0; v < NW; ++v) {
+    if (wid == v) {
+#pragma unroll
+      for (int p = 0; p < KBX; ++p)
+#pragma unroll
+        for (int q = 0; q < NWB; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = ((p * NWB + q) * 16 + Mma<float>::row(lane, r)) * 16 + c16;
+            red[e] = (v == 0) ? (double)ac[p][q][r] : red[e] + (double)ac[p][q][r];
+          }
+#pragma unroll
+      for (int tt = 0; tt < NTG; ++tt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = (tt * 16 + Mma<double>::row(lane, r)) * 16 + c16;
+          red2[e] = (v == 0) ? ag[tt][r] : red2[e] + ag[tt][r];
+        }
+    }
+    __syncthreads();
+  }
+  double* oc = partC + (size_t)blockIdx.x * kx * w;
+  double* og = partG + (size_t)blockIdx.x * w * w;
+  for (int e = threadIdx.x; e < KBX * NWB * 256; e += WG) {
+    const int tt = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    oc[(size_t)((tt / NWB) * 16 + i) * w + (tt % NWB) * 16 + j] = red[e];
+  }
+  for (int e = threadIdx.x; e < NWB * NWB * 256; e += WG) {
+    const int tt = e >> 8, i = (e >> 4) & 15, j = e & 15;
+    const int p = tt / NWB, q = tt % NWB;
+    const double v = p <= q ? red2[(tri_idx(p, q, NWB) * 16 + i) * 16 + j] : red2[(tri_idx(q, p, NWB) * 16 + j) * 16 + i];
+    og[(size_t)(p * 16 + i) * w + q * 16 + j] = v;
+  }
+}
+
+template <int KBX, int NWB>
+void apply_pip_launch(int64_t n, const float* X, int64_t ldx, const float* W, int64_t ldw, const int64_t* flag2,
+                      const double* M1, float* Out, int64_t ldout, double* partC, double* partG, int* grid_out,
+                      hipStream_t s) {
+  constexpr int KB1 = KBX + NWB;
+  const size_t coef = (size_t)KB1 * NWB * 64 * 16;
+  const size_t tiles = (size_t)NW * 16 * (16 * KB1 + 4) * sizeof(float);
+  const size_t red = ((size_t)KBX * NWB + NWB * (NWB + 1) / 2) * 256 * sizeof(double);
+  const size_t lds = std::max(coef + tiles, red);
+  static std::atomic<int> occ_cache{0};
+  int occ = occ_cache.load(std::memory_order_relaxed);
+  if (occ <= 0) {
+    (void)hipFuncSetAttribute((const void*)k_apply_pip<KBX, NWB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_apply_pip<KBX, NWB>, WG, lds) !=
+            hipSuccess || nb < 1)
+      nb = 1;
+    occ = nb;
+    occ_cache.store(occ, std::memory_order_relaxed);
+  }
+  const int64_t ntiles = (n + 15) / 16;
+  int64_t g = std::min<int64_t>((ntiles + NW - 1) / NW, (int64_t)device_cus() * occ);
+  if (g > CHUNKS) g = CHUNKS;  // one partial per workgroup
+  if (g < 1) g = 1;
+  *grid_out = (int)g;
+  k_apply_pip<KBX, NWB><<<(unsigned)g, WG, lds, s>>>(n, X, ldx, W, ldw, flag2, M1, Out, ldout, partC, partG);
+}
+
+bool apply_pip_shape(int kxb, int wb) {
+  return (kxb == 2 && wb == 4) || (kxb == 4 && wb == 2) || (kxb == 1 && wb == 2) || (kxb == 2 && wb == 1) ||
+         (kxb == 1 && wb == 1) || (kxb == 2 && wb == 2) || (kxb == 1 && wb == 4) || (kxb == 4 && wb == 1);
+}
+
+}  // namespace
+
+bool apply_pip_ok(const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w, const float* Out,
+                  int64_t ldout) {
+  return kx > 0 && w > 0 && kx % 16 == 0 && w % 16 == 0 && apply_pip_shape(kx / 16, w / 16) && aligned16(X, ldx) &&
+         aligned16(W, ldw) && aligned16(Out, ldout);
+}
+
+bool launch_apply_pip(int64_t n, const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w,
+                      const int64_t* flag2, const double* M1, float* Out, int64_t ldout, double* partial, double* C,
+                      double* G, hipStream_t s) {
+  if (!apply_pip_ok(X, ldx, kx, W, ldw, w, Out, ldout) || n <= 0) return false;
+  double* partC = partial;
+  double* partG = partial + (size_t)CHUNKS * kx * w;
+  int g = 0;
+  const int a = kx / 16, b = w / 16;
+#define GREST_AP(A, B)                                                                                  \
+  if (a == A && b == B) apply_pip_launch<A, B>(n, X, ldx, W, ldw, flag2, M1, Out, ldout, partC, partG, &g, s); \
+  else
+  GREST_AP(2, 4) GREST_AP(4, 2) GREST_AP(1, 2) GREST_AP(2, 1) GREST_AP(1, 1) GREST_AP(2, 2) GREST_AP(1, 4)
+  GREST_AP(4, 1) return false;
+#undef GREST_AP
+  launch_reduce(g, red_job(partC, C, kx, w), red_job(partG, G, w, w), s);
+  return true;
+}
