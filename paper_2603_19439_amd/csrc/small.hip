@@ -190,8 +190,10 @@ __device__ __forceinline__ bool chosen_bit(uint64_t c0, uint64_t c1, int j) {
 
 template <int M, bool CL>
 __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const double* G, const double* Cg, int kc, double tol,
-                                              double* Mout, int32_t* rank_out, int32_t* status) {
+                                              double* Mout, int32_t* rank_out, int32_t* status,
+                                              const int32_t* done) {
   constexpr int NW = PCH_WAVES, EB = PCH_WAVES * GREST_WAVE;
+  if (done && *done) return;  // the factor is already there (k_chol_np)
   constexpr int CC = M / GREST_WAVE, RW = M / NW, LP = M + 1;
   __shared__ double Rrow[M * LP];  // pivot rows by step (pitch M + 1); later X = R^{-1}
   __shared__ int perm[M], iperm[M];
@@ -373,6 +375,229 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
   }
   if (tid == 0) *rank_out = r;
   PHASE_MARK(12);
+}
+
+// ------------------------------------------------------------------------------------
+// Cholesky factor without pivoting, for the second CholQR round, whose Gram matrix is
+// close to the identity on the columns the first round kept (they come first) and zero on
+// the others.  Same output as k_pchol with the identity permutation: S = G - C^T C =
+// R^T R truncated at the first pivot <= thr, M = R^{-1} on the leading rank x rank block
+// (zero elsewhere), preceded by the rows of -C M.  *done is set when this factor is valid:
+// every pivot before the truncation is above thr and every diagonal entry left after it
+// is at most thr (the truncation rule of the pivoted factor holds); otherwise it is
+// cleared and the pivoted kernel runs.  S lives in LDS (upper triangle updated in place,
+// one barrier per column), the inverse is formed row by row from the bottom (one barrier
+// per row).
+// ------------------------------------------------------------------------------------
+constexpr int CNP_M = 64, CNP_T = 256, CNP_P = CNP_M + 1;
+constexpr size_t kCnpDynMax = (size_t)CNP_M * CNP_M * sizeof(double);  // the block C (kc <= 64)
+
+__global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restrict__ G, const double* __restrict__ Cg,
+                                                  int kc, double tol, double* __restrict__ Mout,
+                                                  int32_t* rank_out, int32_t* done) {
+  constexpr int NB = CNP_M / 16;  // a thread's rows (and columns) on a 16 x 16 thread grid
+  // Each thread keeps its 4 x 4 entries (rows ty + 16 a, columns tx + 16 b) of S, later of
+  // X = R^{-1}, in registers; what the other threads need goes through LDS one row at a
+  // time: row j of the Schur complement at step j (Rr[j] = R[j][.] R[j][j]), and the
+  // finished rows of X (Xr).
+  __shared__ double Rr[CNP_M * CNP_P];
+  __shared__ double Xr[CNP_M * CNP_P];
+  __shared__ double rdi[CNP_M];
+  __shared__ double red[CNP_T / GREST_WAVE];
+  __shared__ int s_bad;
+  extern __shared__ double Cs[];  // C (kc x m)
+  const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1), wv = tid / GREST_WAVE;
+  const int ty = tid >> 4, tx = tid & 15;
+  if (m == CNP_M) PHASE_MARK(2);
+  if (tid == 0) s_bad = 0;
+  for (int idx = tid; idx < kc * m; idx += CNP_T) Cs[idx] = Cg[idx];
+  __syncthreads();
+  // S = sym(G) - C^T C
+  double v[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ty + 16 * a, j = tx + 16 * b;
+      v[a][b] = (i < m && j < m) ? 0.5 * (G[(size_t)i * m + j] + G[(size_t)j * m + i]) : 0.0;
+    }
+  for (int l = 0; l < kc; ++l) {
+    double ci[NB], cj[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      ci[a] = Cs[l * m + (ty + 16 * a < m ? ty + 16 * a : 0)];
+      cj[a] = Cs[l * m + (tx + 16 * a < m ? tx + 16 * a : 0)];
+      ci[a] = ty + 16 * a < m ? ci[a] : 0.0;
+      cj[a] = tx + 16 * a < m ? cj[a] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v[a][b] = fma(-ci[a], cj[b], v[a][b]);
+  }
+  {
+    int bad = 0;
+    double mx = 0.0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = ty + 16 * a, j = tx + 16 * b;
+        if (i < m && j < m) {
+          if (!isfinite(v[a][b])) bad = 1;
+          if (i == j) mx = fmax(mx, G[(size_t)i * m + i]);
+        }
+      }
+    mx = wave_max_d(mx);
+    if (lane == 0) red[wv] = mx;
+    if (bad) s_bad = 1;
+    if (ty == 0)  // row 0
+#pragma unroll
+      for (int b = 0; b < NB; ++b) Rr[tx + 16 * b] = v[0][b];
+  }
+  __syncthreads();
+  double gmx = 0.0;
+  for (int q = 0; q < CNP_T / GREST_WAVE; ++q) gmx = fmax(gmx, red[q]);
+  const double thr = tol * tol * fmax(1.0, gmx);
+  if (s_bad) {  // leave the non-finite report to the pivoted kernel
+    if (tid == 0) *done = 0;
+    return;
+  }
+  // right-looking factor: step j subtracts S[i][j] S[j][k] / S[j][j] (i, k > j), with
+  // S[i][j] = S[j][i] read from row j
+  if (m == CNP_M) PHASE_MARK(3);
+  int r = m;
+  for (int j = 0; j < m; ++j) {
+    const double* rj = Rr + j * CNP_P;
+    const double d = rj[j];
+    if (!(d > thr)) { r = j; break; }
+    const double inv = recip(d);
+    double f[NB], g[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int i = ty + 16 * a, k = tx + 16 * a;
+      f[a] = rj[i];
+      g[a] = rj[k];
+      f[a] = (i > j && i < m) ? f[a] * inv : 0.0;
+      g[a] = (k > j && k < m) ? g[a] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f[a], g[b], v[a][b]);
+    // row j + 1 for the next step
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (ty + 16 * a == j + 1)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Rr[(j + 1) * CNP_P + tx + 16 * b] = v[a][b];
+    __syncthreads();
+  }
+  // valid only if every diagonal entry left is at most thr
+  if (m == CNP_M) PHASE_MARK(4);
+  for (int j = tid; j < r; j += CNP_T) rdi[j] = 1.0 / sqrt(Rr[j * CNP_P + j]);
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ty + 16 * a;
+      if (i == tx + 16 * b && i >= r && i < m && v[a][b] > thr) ok = false;
+    }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (!ok) s_bad = 1;
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) *done = 0;
+    return;
+  }
+  // X = R^{-1} by rows from the bottom.  X starts as I; at step k row k has all its terms,
+  // X[k][c] = B[k][c] / R[k][k], and every row i < k subtracts R[i][k] X[k][c]; the
+  // division of each row by its R[i][i] comes at the end.
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[a][b] = (ty + 16 * a == tx + 16 * b) ? 1.0 : 0.0;
+  if (r > 0) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (ty + 16 * a == r - 1)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Xr[(r - 1) * CNP_P + tx + 16 * b] = v[a][b];
+  }
+  __syncthreads();
+  for (int k = r - 1; k > 0; --k) {
+    const double rk = rdi[k];
+    double f[NB], xk[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int i = ty + 16 * a, c = tx + 16 * a;
+      f[a] = Rr[(i < k ? i : 0) * CNP_P + k] * rdi[i < k ? i : 0];
+      xk[a] = Xr[k * CNP_P + c];
+      f[a] = i < k ? f[a] * rk : 0.0;
+      xk[a] = (c >= k && c < r) ? xk[a] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f[a], xk[b], v[a][b]);
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (ty + 16 * a == k - 1)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Xr[(k - 1) * CNP_P + tx + 16 * b] = v[a][b];
+    __syncthreads();
+  }
+  // output: rows of -C M, then M (zero outside the leading r x r upper triangle)
+  if (m == CNP_M) PHASE_MARK(5);
+  double* Mblk = Mout + (size_t)kc * m;
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const int i = ty + 16 * a;
+    const double ri = i < r ? rdi[i] : 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = tx + 16 * b;
+      if (i < m && j < m) Mblk[(size_t)i * m + j] = (i <= j && j < r) ? v[a][b] * ri : 0.0;
+    }
+  }
+  for (int l0 = 0; l0 < kc; l0 += CNP_M) {
+    double acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < r; ++q) {
+      const double rq = rdi[q];
+      double cl[NB], xq[NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int l = l0 + ty + 16 * a, j = tx + 16 * a;
+        cl[a] = Cs[(l < kc ? l : 0) * m + q];
+        xq[a] = Xr[q * CNP_P + j];
+        cl[a] = l < kc ? cl[a] : 0.0;
+        xq[a] = (j >= q && j < r) ? xq[a] * rq : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = fma(cl[a], xq[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int l = l0 + ty + 16 * a, j = tx + 16 * b;
+        if (l < kc && j < m) Mout[(size_t)l * m + j] = -acc[a][b];
+      }
+  }
+  if (tid == 0) {
+    *rank_out = r;
+    *done = 1;
+  }
+  if (m == CNP_M) PHASE_MARK(6);
 }
 
 // ------------------------------------------------------------------------------------
@@ -899,7 +1124,7 @@ int64_t pchol_work_elems(int, int) { return 0; }
 // the coefficient block goes to LDS when it fits beside the static arrays
 template <int M>
 void pchol_launch(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
-                  int32_t* status, hipStream_t s) {
+                  int32_t* status, hipStream_t s, const int32_t* done = nullptr) {
   constexpr size_t kStatic = (size_t)M * (M + 1) * 8 + (size_t)M * 24;
   constexpr size_t kDynMax = 160 * 1024 - kStatic - 1024;
   static const bool attr = [] {
@@ -909,8 +1134,10 @@ void pchol_launch(int m, const double* G, const double* C, int kc, double tol, d
   }();
   (void)attr;
   const size_t dyn = (size_t)kc * m * sizeof(double);
-  if (kc > 0 && dyn <= kDynMax) k_pchol<M, true><<<1, PCH_WAVES * GREST_WAVE, dyn, s>>>(m, G, C, kc, tol, Mout, rank, status);
-  else k_pchol<M, false><<<1, PCH_WAVES * GREST_WAVE, 0, s>>>(m, G, C, kc, tol, Mout, rank, status);
+  if (kc > 0 && dyn <= kDynMax)
+    k_pchol<M, true><<<1, PCH_WAVES * GREST_WAVE, dyn, s>>>(m, G, C, kc, tol, Mout, rank, status, done);
+  else
+    k_pchol<M, false><<<1, PCH_WAVES * GREST_WAVE, 0, s>>>(m, G, C, kc, tol, Mout, rank, status, done);
 }
 
 void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
@@ -918,6 +1145,27 @@ void launch_pchol(int m, const double* G, const double* C, int kc, double tol, d
   if (!C) kc = 0;
   if (m <= 64) pchol_launch<64>(m, G, C, kc, tol, Mout, rank, status, s);
   else pchol_launch<128>(m, G, C, kc, tol, Mout, rank, status, s);
+}
+
+// Second-round factor: the Cholesky factor without pivoting first (k_chol_np); where it
+// cannot stand in for the pivoted one, the pivoted kernel runs as before.
+void launch_pchol2(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
+                   int32_t* status, double* work, hipStream_t s) {
+  if (!C) kc = 0;
+  int32_t* done = reinterpret_cast<int32_t*>(work);
+  const size_t dyn = (size_t)kc * CNP_M * sizeof(double);
+  if (m > CNP_M || dyn > kCnpDynMax) {
+    launch_pchol(m, G, C, kc, tol, Mout, rank, status, work, s);
+    return;
+  }
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)k_chol_np, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCnpDynMax);
+    return true;
+  }();
+  (void)attr;
+  k_chol_np<<<1, CNP_T, dyn, s>>>(m, G, C, kc, tol, Mout, rank, done);
+  if (m <= 64) pchol_launch<64>(m, G, C, kc, tol, Mout, rank, status, s, done);
+  else pchol_launch<128>(m, G, C, kc, tol, Mout, rank, status, s, done);
 }
 
 bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which, int kk,
