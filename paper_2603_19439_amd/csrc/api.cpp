@@ -422,7 +422,7 @@ void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T
         launch_tn<T, false>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
         launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, s);
       }
-      launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->M1buf, st->ranks + slot, st->status, st->eigwork, s);
+      launch_pchol2(w, st->Gm, st->C1, kx, st->tol, st->M1buf, st->ranks + slot, st->status, st->eigwork, s);
       launch_apply_pip(n, X, ldx, kx, W, ldw, w, flag2, st->M1buf, Wo, ldw, st->partial, st->C1, st->Gm, s);
       launch_pchol2(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + 1, st->status, st->eigwork, s);
       if (last_apply) launch_apply2<T>(n, X, ldx, kx, Wo, ldw, w, st->Mchol, w, 1.0, 0.0, Wo, ldw, s);
@@ -439,10 +439,7 @@ void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T
       else launch_tn<T, false>(n, X, ldx, kx, Win, ldw, w, st->partial, st->C1, s);
       launch_tn<T, true>(n, Win, ldw, w, Win, ldw, w, st->partial, st->Gm, s);
     }
-    if (round == 0)
-      launch_pchol(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot, st->status, st->eigwork, s);
-    else
-      launch_pchol2(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + 1, st->status, st->eigwork, s);
+    launch_pchol2(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
     if (round == 1 && !last_apply) break;
     if (round == 0 && rows && Wout) {
       // W is zero off the listed rows and goes to another buffer: Wout = X (-C M) over

@@ -149,8 +149,8 @@ void launch_convert(const Tsrc* src, Tdst* dst, int64_t count, hipStream_t s);
 int64_t pchol_work_elems(int m, int kc);
 void launch_pchol(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
                   int32_t* status, double* work, hipStream_t s);
-// the same factor for a second CholQR round (Gram close to the identity on its leading
-// columns): without pivoting where that gives the same kept columns; work holds a flag
+// the same factor, without pivoting where that satisfies the truncation rule (pivoted
+// otherwise); work holds a flag
 void launch_pchol2(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
                   int32_t* status, double* work, hipStream_t s);
 // one projection round in one pass: C = X^T W (working precision) and G = W^T W (FP64);

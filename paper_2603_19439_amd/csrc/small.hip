@@ -378,9 +378,11 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
 }
 
 // ------------------------------------------------------------------------------------
-// Cholesky factor without pivoting, for the second CholQR round, whose Gram matrix is
-// close to the identity on the columns the first round kept (they come first) and zero on
-// the others.  Same output as k_pchol with the identity permutation: S = G - C^T C =
+// Cholesky factor without pivoting, tried first in every CholQR round: the Gram matrix of
+// a full-rank block (and of the second round, close to the identity on the columns the
+// first round kept, which come first, and zero on the others) needs no pivoting for the
+// factor itself; pivoting only decides the rank.  Same output as k_pchol with the
+// identity permutation: S = G - C^T C =
 // R^T R truncated at the first pivot <= thr, M = R^{-1} on the leading rank x rank block
 // (zero elsewhere), preceded by the rows of -C M.  *done is set when this factor is valid:
 // every pivot before the truncation is above thr and every diagonal entry left after it
@@ -1147,8 +1149,8 @@ void launch_pchol(int m, const double* G, const double* C, int kc, double tol, d
   else pchol_launch<128>(m, G, C, kc, tol, Mout, rank, status, s);
 }
 
-// Second-round factor: the Cholesky factor without pivoting first (k_chol_np); where it
-// cannot stand in for the pivoted one, the pivoted kernel runs as before.
+// The factor of a CholQR round: without pivoting first (k_chol_np); where that does not
+// satisfy the truncation rule (a rank-deficient block), the pivoted kernel runs.
 void launch_pchol2(int m, const double* G, const double* C, int kc, double tol, double* Mout, int32_t* rank,
                    int32_t* status, double* work, hipStream_t s) {
   if (!C) kc = 0;
