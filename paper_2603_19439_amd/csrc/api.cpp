@@ -128,8 +128,10 @@ struct grest_state {
   size_t sort_tmp_bytes = 0;
   int32_t* dins = nullptr;
   int8_t* dsg_tmp = nullptr;
-  // row lists of the sparse projection rounds (flags, positions, scan workspace)
+  // row lists of the sparse projection rounds (flags, positions, scan workspace): the
+  // sketch's (r*) and Delta_1 X's (d*)
   int64_t *rflag = nullptr, *rpos = nullptr, *rscan_tmp = nullptr;
+  int64_t *dflag = nullptr, *dpos = nullptr, *dscan_tmp = nullptr;
   int32_t* srows = nullptr;  // rows where the sketch Delta_2 Omega can be nonzero
   int32_t* drows = nullptr;  // rows where Delta_1 X can be nonzero
 
@@ -232,6 +234,9 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   CHK(dalloc(&st->rflag, cap_n + 1));
   CHK(dalloc(&st->rpos, cap_n + 1));
   CHK(dalloc(&st->rscan_tmp, scan_tmp_elems(cap_n + 1) + 16));
+  CHK(dalloc(&st->dflag, cap_n + 1));
+  CHK(dalloc(&st->dpos, cap_n + 1));
+  CHK(dalloc(&st->dscan_tmp, scan_tmp_elems(cap_n + 1) + 16));
   CHK(dalloc(&st->srows, cap_n + 1));
   CHK(dalloc(&st->drows, cap_n + 1));
   st->cap_n = cap_n;
@@ -291,7 +296,7 @@ int64_t device_bytes(const grest_state* st) {
   add(st->aux); add(st->ybuf); add(st->mbuf); add(st->srows_cnt); add(st->bt); add(st->omega_t); add(st->omega64);
   add(st->d_ei); add(st->d_ej); add(st->d_sg);
   add(st->dcnt); add(st->newlen); add(st->scan_tmp); add(st->srows); add(st->drows);
-  add(st->rflag); add(st->rpos); add(st->rscan_tmp);
+  add(st->rflag); add(st->rpos); add(st->rscan_tmp); add(st->dflag); add(st->dpos); add(st->dscan_tmp);
   add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp); add(st->dins); add(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
     add(st->dptr[b]); add(st->dcol[b]); add(st->dsg[b]); add(st->vstat[b]); add(st->maxdeg[b]);
@@ -309,7 +314,7 @@ void free_all(grest_state* st) {
   dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->srows_cnt); dfree(st->bt); dfree(st->omega_t); dfree(st->omega64);
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
   dfree(st->dcnt); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows); dfree(st->drows);
-  dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp);
+  dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp); dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp); dfree(st->dins); dfree(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
     dfree(st->dptr[b]); dfree(st->dcol[b]); dfree(st->dsg[b]); dfree(st->vstat[b]); dfree(st->maxdeg[b]);
@@ -345,6 +350,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   st->sc[0] = st->sc[1] = nullptr;
   dfree(st->aux); dfree(st->ybuf); dfree(st->mbuf); dfree(st->dcnt); dfree(st->dptr[0]); dfree(st->dptr[1]);
   dfree(st->newlen); dfree(st->scan_tmp); dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp);
+  dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
   dfree(st->srows); dfree(st->drows);
   CHK(alloc_node_arrays(st, cap));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
@@ -580,10 +586,49 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   launch_delta_rows(n, S, dptr, dcol, dsg, st->dins, st->rp[st->gcur], st->col[st->gcur], st->newlen, st->vstat[ds],
                     gs);
   launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, gs);
-  launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, st->dins, st->rp[gn], st->col[gn],
-                   st->cap_m, gs);
   if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, maxdeg, gs);
   else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], maxdeg, gs);
+  // ---- the work of the update that reads only Delta, the new graph's scales and Omega,
+  // and writes only scratch (the sketch and the row lists), goes on the same stream, its
+  // short kernels before the merge, which streams the whole graph ----
+  const T* sc_new = (const T*)st->sc[gn];
+  const bool nlap = st->op == GREST_OP_NLAP;
+  const bool rsvd = st->variant == GREST_RSVD;
+  const bool sparse_dx = !nlap && (rsvd || st->variant == GREST_G2);
+  const int64_t sk_bound = std::min<int64_t>(n2, S + 2 * nc);
+  if (rsvd && S > 0) {
+    // S.1 (first half): Y = Delta_2 Omega; the projection comes with the orthonormalisation
+    const int Ls = st->Ls;
+    T* Y = (T*)st->ybuf;
+    const double* om = omega;
+    if (where == GREST_HOST) {
+      HIPCHK(hipMemcpyAsync(st->omega64, omega, (size_t)S * Ls * sizeof(double), hipMemcpyHostToDevice, gs));
+      om = st->omega64;
+    }
+    if (sizeof(T) == 8) {
+      HIPCHK(hipMemcpyAsync(st->omega_t, om, (size_t)S * Ls * sizeof(double), hipMemcpyDeviceToDevice, gs));
+    } else {
+      launch_convert<double, float>(om, (float*)st->omega_t, (int64_t)S * Ls, gs);
+    }
+    // Y is zero except on the appended rows and the rows of Delta with an entry in an
+    // appended column (the row list).  The buffer is kept that way: the rows of the
+    // previous list are cleared (all of Y after a reallocation) and the product writes
+    // the rows of the new list only.
+    if (st->y_clean)
+      launch_zero_listed_rows<T>(Y, st->ldy, Ls, st->srows, st->srows_cnt, st->srows_bound, gs);
+    else
+      launch_fill_rows<T>(Y, st->ldy, 0, n2, Ls, gs);
+    launch_sketch_rows(n, S, dptr, dcol, st->rflag, st->rpos, st->rscan_tmp, st->srows, gs);
+    launch_copy_i64(st->rpos + n2, st->srows_cnt, gs);
+    st->srows_bound = sk_bound;
+    st->y_clean = true;
+    launch_delta_mul<T>(1, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, (const T*)st->omega_t, Ls, Ls, Y,
+                        st->ldy, gs);
+  }
+  // rows where Delta_1 X can be nonzero (the adjacency's and the Laplacian's form)
+  if (sparse_dx) launch_delta1_rows(n, S, dptr, dcol, st->dflag, st->dpos, st->dscan_tmp, st->drows, gs);
+  launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, st->dins, st->rp[gn], st->col[gn],
+                   st->cap_m, gs);
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].vstatus, st->vstat[ds], sizeof(int32_t), hipMemcpyDeviceToHost, gs));
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, gs));
   if (st->marking) (void)hipEventRecord(st->gend[st->pslot], gs);
@@ -610,9 +655,6 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // What reads the merged graph (the normalised Laplacian's Delta Xbar and the Rayleigh-
   // Ritz product) is queued after the wait.
   Blocks<T> b = blocks<T>(st);
-  const T* sc_new = (const T*)st->sc[gn];
-  const bool nlap = st->op == GREST_OP_NLAP;
-  const bool rsvd = st->variant == GREST_RSVD;
   const int K = st->K;
   // Basis layout.  G-REST2/3: Z = [Xbar | Delta Xbar | augmentation], the last two
   // projected against Xbar and orthonormalised together.  RSVD: Z = [Xbar | R | Delta
@@ -626,16 +668,14 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // adjacency and the Laplacian's form; the normalised Laplacian's form changes whole
   // rows), so the first projection round of a block made of it alone covers those rows
   auto project = [&]() {
-    const bool sparse_dx = !nlap && (rsvd || st->variant == GREST_G2);
-    if (sparse_dx) {
-      launch_delta1_rows(n, S, dptr, dcol, st->rflag, st->rpos, st->rscan_tmp, st->drows, s);
+    if (sparse_dx) {  // the row list came with the graph stage
       const int64_t bound = std::min<int64_t>(n2, 2 * nc);
       if (rsvd)
-        orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0, st->drows, st->rpos + n2, bound,
-                        nullptr, st->rflag);
+        orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0, st->drows, st->dpos + n2, bound,
+                        nullptr, st->dflag);
       else
-        orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0, st->drows, st->rpos + n2, bound,
-                        nullptr, st->rflag);
+        orth_against<T>(st, n2, b.Zc, st->ldz, K, b.W, st->ldz, st->Dw, 0, st->drows, st->dpos + n2, bound,
+                        nullptr, st->dflag);
     } else if (rsvd) {
       orth_against<T>(st, n2, b.Zc, st->ldz, K + st->L, dX, st->ldz, K, 0);
     } else {
@@ -664,34 +704,11 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_fill_rows<T>(Rb, st->ldz, 0, n2, st->L, s);
       launch_fill_bytes0(st->ranks + 4, sizeof(int32_t), s);  // no sketch columns kept
     } else {
-      // S.1: Y = (I - Pi) Delta_2 Omega
+      // S.1: Y = (I - Pi) Delta_2 Omega; Delta_2 Omega and its row list came with the
+      // graph stage
       const int Ls = st->Ls;
-      const double* om = omega;
-      if (where == GREST_HOST) {
-        HIPCHK(hipMemcpyAsync(st->omega64, omega, (size_t)S * Ls * sizeof(double), hipMemcpyHostToDevice, s));
-        om = st->omega64;
-      }
-      if (sizeof(T) == 8) {
-        HIPCHK(hipMemcpyAsync(st->omega_t, om, (size_t)S * Ls * sizeof(double), hipMemcpyDeviceToDevice, s));
-      } else {
-        launch_convert<double, float>(om, (float*)st->omega_t, (int64_t)S * Ls, s);
-      }
-      // Y is zero except on the appended rows and the rows of Delta with an entry in an
-      // appended column (the row list).  The buffer is kept that way: the rows of the
-      // previous list are cleared (all of Y after a reallocation) and the product writes
-      // the rows of the new list only.
       T* Mb = (T*)st->mbuf;
-      if (st->y_clean)
-        launch_zero_listed_rows<T>(b.Y, st->ldy, Ls, st->srows, st->srows_cnt, st->srows_bound, s);
-      else
-        launch_fill_rows<T>(b.Y, st->ldy, 0, n2, Ls, s);
-      launch_sketch_rows(n, S, dptr, dcol, st->rflag, st->rpos, st->rscan_tmp, st->srows, s);
-      const int64_t bound = std::min<int64_t>(n2, S + 2 * nc);
-      launch_copy_i64(st->rpos + n2, st->srows_cnt, s);
-      st->srows_bound = bound;
-      st->y_clean = true;
-      launch_delta_mul<T>(1, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, (const T*)st->omega_t,
-                          Ls, Ls, b.Y, st->ldy, s);
+      const int64_t bound = sk_bound;
       // (I - Pi) applied twice and S.2: M = orth(Y), in the same two fused rounds; the first
       // round's read passes cover the listed rows of Y only, and its output Y1 goes to its
       // own buffer.  M = [Xbar Y1] Mchol is needed in full only through R = M U_L, so the
