@@ -160,7 +160,10 @@ grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col);
  * 1 padding and Delta Xbar, 2 augmentation block, 3 projections and CholQR2,
  * 4 product with the updated operator, 5 projected matrix Z^T (A Z), 6 small
  * eigensolve, 7 back-projection.  grest_profile(st, 1) enables and clears the
- * totals; grest_stage_times returns the accumulated milliseconds per stage, the
+ * totals; grest_profile(st, 2) records only the two events around the sparse product
+ * (each timing event between two kernels costs the stream a few microseconds; the
+ * stage times then read zero); 0 disables; other values: EINVAL.
+ * grest_stage_times returns the accumulated milliseconds per stage, the
  * milliseconds of the sparse product kernel alone, the number of updates, and the sum
  * over those updates of the sparse product's width (the columns of Z it multiplied:
  * all of them, or only the new ones when the kept adjacency product A X is reused).

@@ -167,12 +167,14 @@ struct grest_state {
   int64_t prof_spmm_cols = 0;
   int64_t prof_updates = 0;
   bool marking = false;
+  bool stage_marks = true;  // false: only the events around the sparse product
 };
 
 namespace {
 
 void mark(grest_state* st, int i) {
-  if (st->marking) (void)hipEventRecord(st->pev[st->pslot][i], i == 0 ? st->gstream : st->stream);
+  if (st->marking && st->stage_marks)
+    (void)hipEventRecord(st->pev[st->pslot][i], i == 0 ? st->gstream : st->stream);
 }
 
 void mark_spmm(grest_state* st, int i) {
@@ -182,7 +184,7 @@ void mark_spmm(grest_state* st, int i) {
 // add the stage times of the update that used event set `slot` (its events have completed)
 void prof_collect_slot(grest_state* st, int slot) {
   if (!st->prof_pending[slot]) return;
-  for (int i = 0; i < grest_state::NSTAGE; ++i) {
+  for (int i = 0; i < grest_state::NSTAGE && st->stage_marks; ++i) {
     float ms = 0.f;
     hipEvent_t e1 = i == 0 ? st->gend[slot] : st->pev[slot][i + 1];
     if (hipEventElapsedTime(&ms, st->pev[slot][i], e1) == hipSuccess) st->stage_ms[i] += ms;
@@ -631,7 +633,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
                    st->cap_m, gs);
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].vstatus, st->vstat[ds], sizeof(int32_t), hipMemcpyDeviceToHost, gs));
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, gs));
-  if (st->marking) (void)hipEventRecord(st->gend[st->pslot], gs);
+  if (st->marking && st->stage_marks) (void)hipEventRecord(st->gend[st->pslot], gs);
   HIPCHK(hipEventRecord(st->gev[ds], gs));
   st->dslot ^= 1;
   // the rest of the update follows the graph stage; the numerical status word is cleared
@@ -1170,7 +1172,9 @@ grest_status grest_profile(grest_state* st, int32_t enable) {
       HIPCHK(hipEventCreate(&st->kev[b][1]));
     }
   }
+  if (enable < 0 || enable > 2) return GREST_EINVAL;
   st->prof = enable != 0;
+  st->stage_marks = enable == 1;
   st->prof_pending[0] = st->prof_pending[1] = false;
   for (int i = 0; i < grest_state::NSTAGE; ++i) st->stage_ms[i] = 0.0;
   st->spmm_ms = 0.0;

@@ -229,8 +229,9 @@ class State:
         """Run each update's graph stage on a second stream, overlapping the previous update."""
         _check(lib().grest_set_overlap(self._h, int(bool(enable))), "grest_set_overlap")
 
-    def profile(self, enable: bool = True):
-        _check(lib().grest_profile(self._h, int(bool(enable))), "grest_profile")
+    def profile(self, enable=True):
+        """True/1: every stage's events; 2: only those around the sparse product; False/0: off."""
+        _check(lib().grest_profile(self._h, int(enable)), "grest_profile")
 
     def stage_times(self):
         """({stage: total ms}, total ms of the sparse-product kernel alone, updates timed,
