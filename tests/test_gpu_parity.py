@@ -129,6 +129,16 @@ def test_laplacians_with_growth_fp64(op):
     run_trajectory(wl, 8, "rsvd", op, "fp64", 2, L=8, P=8)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_laplacian_k64_width_128(prec):
+    """The large-graph form's shape at n0 = 2000: Chung-Lu (exponent 2.2) with 1 % node
+    growth per step, combinatorial Laplacian, K = 64 smallest pairs, G-REST2, so the basis
+    is 128 wide (the widest the kernels take: 128-column applies and products, the
+    64-wide CholQR2 factor, the 128 template of the small eigensolver)."""
+    wl = W.preset("chunglu_n4e6", scale=0.0005, steps=2)
+    run_trajectory(wl, 64, "g2", "lap", prec, 2)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_rsvd_sketch_rank_below_L(prec):
     """Fewer new nodes than L: the sketch keeps fewer than L columns, so the basis
