@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--compare", default="fp32", help="second path timed beside the headline ('' to skip)")
+    ap.add_argument("--no-lowrank", action="store_true",
+                    help="skip timing the low-rank projected matrix (eq. ..._main3) beside the headline")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink node counts (quick runs only)")
     ap.add_argument("--init-iters", type=int, default=40)
     ap.add_argument("--no-overlap", action="store_true",
@@ -114,26 +116,26 @@ def main():
     nnz_cap = int(wl.col0.size + 2 * sum(s[5] for s in dev_steps) + 1024)
     torch.cuda.synchronize()
 
-    def make_state(prec):
+    def make_state(prec, proj="exact"):
         st = G.State(wl.rowptr0, wl.col0, k=K, variant="rsvd", op="adj", precision=prec, L=L, P=P,
                      stream=torch.cuda.current_stream().cuda_stream, node_capacity=n_final + 1,
-                     nnz_capacity=nnz_cap)
+                     nnz_capacity=nnz_cap, proj=proj)
         st.init_pairs(iterations=args.init_iters, seed=7)
         st.set_overlap(not args.no_overlap)
         return st
 
-    def run_path(prec):
+    def run_path(prec, proj="exact"):
         # warmup on its own state (same trajectory), then a fresh state for the timed steps
         # the warm-up updates carry every stage's timing events; the timed ones only the two
         # around the sparse product (each event between two kernels costs a few microseconds)
-        st = make_state(prec)
+        st = make_state(prec, proj)
         st.profile(True)
         for s in dev_steps[:args.warmup]:
             st.update(s[0], s[1], s[2], s[3], s[4])
         st.sync()
         stages, _, stage_n, _ = st.stage_times()
         st.close()
-        st = make_state(prec)
+        st = make_state(prec, proj)
         st.profile(2)
         sizes = []
         torch.cuda.synchronize()
@@ -162,6 +164,10 @@ def main():
     if args.compare and args.compare != args.precision:
         log(args, f"timing {args.compare} path")
         cmp_res = run_path(args.compare)
+    lr_res = None
+    if not args.no_lowrank:
+        log(args, f"timing the {args.precision} path with the low-rank projected matrix")
+        lr_res = run_path(args.precision, "lowrank")
 
     secs = main_res["seconds"]
     value = args.steps / secs
@@ -213,6 +219,14 @@ def main():
                           "speedup_of_headline": round(value / cv, 3),
                           "stages_ms_per_update": {k: round(v / max(1, cmp_res["stage_updates"]), 4)
                                                    for k, v in cmp_res["stages_ms"].items()}}
+    if lr_res is not None:
+        lv = args.steps / lr_res["seconds"]
+        out["lowrank"] = {"note": "same workload and precision, H = Z^T (Xbar Theta Xbar^T + Delta) Z (eq. "
+                                  "RR_eigen_graph_upd_main3) instead of the product with the stored graph",
+                          "value": round(lv, 3), "ms_per_step": round(1e3 * lr_res["seconds"] / args.steps, 3),
+                          "speedup_of_headline": round(lv / value, 3),
+                          "stages_ms_per_update": {k: round(v / max(1, lr_res["stage_updates"]), 4)
+                                                   for k, v in lr_res["stages_ms"].items()}}
     if serve is not None:
         out["serving"] = serve
     if cpu is not None:

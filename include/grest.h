@@ -62,6 +62,11 @@ enum { GREST_FP64 = 0, GREST_FP32 = 1, GREST_MIXED = 2 };
 enum { GREST_HOST = 0, GREST_DEVICE = 1 };
 /* element type of a dense output */
 enum { GREST_F64 = 0, GREST_F32 = 1 };
+/* projected matrix of the Rayleigh-Ritz step: EXACT, H = Z^T A' Z with the stored updated
+ * graph (eq. RR_eigen_graph_upd_main2); LOWRANK, H = Z^T (Xbar Theta Xbar^T + Delta) Z
+ * with the previous Ritz values Theta (eq. RR_eigen_graph_upd_main3, the form of Alg. 2),
+ * which needs no product with the whole graph (adjacency only) */
+enum { GREST_PROJ_EXACT = 0, GREST_PROJ_LOWRANK = 1 };
 
 typedef struct grest_config {
   int32_t k;          /* K, number of tracked pairs (>= 1) */
@@ -71,7 +76,7 @@ typedef struct grest_config {
   int32_t op;         /* GREST_OP_* */
   int32_t precision;  /* GREST_FP64 / GREST_FP32 / GREST_MIXED */
   int32_t max_new;    /* largest S per update for G-REST3 (sizes the basis block) */
-  int32_t reserved;   /* 0 */
+  int32_t proj;       /* GREST_PROJ_EXACT (0) or GREST_PROJ_LOWRANK (op GREST_OP_ADJ only) */
   double rank_tol;    /* relative rank threshold of the orthonormalisation; 0 = default
                          (1e-7 in FP64, 1e-5 otherwise) */
 } grest_config;

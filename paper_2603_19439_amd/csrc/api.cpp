@@ -138,6 +138,12 @@ struct grest_state {
   double *C1 = nullptr, *C2 = nullptr, *Gm = nullptr, *Mchol = nullptr, *H = nullptr, *F = nullptr;
   double* Msk = nullptr;  // coefficients of R = [Xbar Y1] (Mchol U_L), (K + Ls) x L
   double* M1buf = nullptr;  // first-round factor of a fused CholQR2 (same shape as Mchol)
+  // low-rank projection: the listed rows of Z and of Delta Z (2 cap_nc x D each), and
+  // C = Z^T Xbar (D x K)
+  int proj = GREST_PROJ_EXACT;
+  void* zg = nullptr;
+  void* dz = nullptr;
+  double* Clr = nullptr;
   double *theta = nullptr, *Fb = nullptr, *thetab = nullptr, *partial = nullptr, *eigwork = nullptr;
   int32_t* ranks = nullptr;
   int32_t* status = nullptr;
@@ -272,6 +278,11 @@ grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
   }
   CHK(dalloc(&st->dins, 2 * cap_nc));
   CHK(dalloc(&st->dsg_tmp, 2 * cap_nc));
+  dfree(st->zg); dfree(st->dz);
+  if (st->proj == GREST_PROJ_LOWRANK) {
+    CHK(dalloc((char**)&st->zg, (size_t)2 * cap_nc * st->D * st->es));
+    CHK(dalloc((char**)&st->dz, (size_t)2 * cap_nc * st->D * st->es));
+  }
   st->cap_nc = cap_nc;
   return GREST_OK;
 }
@@ -304,6 +315,7 @@ int64_t device_bytes(const grest_state* st) {
     add(st->dptr[b]); add(st->dcol[b]); add(st->dsg[b]); add(st->vstat[b]); add(st->maxdeg[b]);
   }
   add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F); add(st->Msk); add(st->M1buf);
+  add(st->zg); add(st->dz); add(st->Clr);
   add(st->theta); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
   add(st->ranks); add(st->status);
   return total;
@@ -326,6 +338,7 @@ void free_all(grest_state* st) {
     st->gev[b] = st->endev[b] = st->gate[b] = nullptr;
   }
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F); dfree(st->Msk); dfree(st->M1buf);
+  dfree(st->zg); dfree(st->dz); dfree(st->Clr);
   dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
   dfree(st->ranks); dfree(st->status);
   if (st->pin) (void)hipHostFree(st->pin);
@@ -479,26 +492,58 @@ void cholqr2(grest_state* st, int64_t n, T* W, int64_t ldw, int w, int slot) {
 // The basis may hold two packed blocks with dropped columns between them: the small
 // eigensolve then works on the kept columns [0, base + *rank_slot) and
 // [seg2, seg2 + *rank2).
+struct LowRankIn {  // Delta's CSR and the list of its nonempty rows (count on the device)
+  const int64_t* dptr;
+  const int32_t* dcol;
+  const int8_t* dsg;
+  const int32_t* rows;
+  const int64_t* count;
+  int64_t bound;
+};
+
 template <typename T>
 grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const int32_t* col, const T* sc,
                            int base, int32_t* rank_slot, bool reuse, int seg2 = 0, const int32_t* rank2 = nullptr,
-                           int gate_slot = -1) {
+                           int gate_slot = -1, const LowRankIn* lr = nullptr) {
   Blocks<T> b = blocks<T>(st);
-  // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
-  const int c0 = reuse ? st->K : 0;
-  mark_spmm(st, 0);
-  launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc + c0, st->ldz, n2, st->D - c0, b.aux + c0, st->D, st->stream);
-  mark_spmm(st, 1);
-  st->spmm_cols[st->pslot] = st->D - c0;
-  mark(st, 5);
-  // H = Z^T (op Z)
-  if constexpr (sizeof(T) == 4) {
-    if (st->prec == GREST_MIXED)
-      launch_tn_bf16(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
-    else
-      launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+  if (lr) {
+    // low-rank projected matrix (eq. RR_eigen_graph_upd_main3): H = C Theta C^T + Z^T Delta Z
+    // with C = Z^T Xbar and the previous Ritz values Theta; Delta Z is nonzero only on the
+    // rows of Delta with an entry, so Z^T Delta Z is a product over those rows, gathered
+    T* Zg = (T*)st->zg;
+    T* Dz = (T*)st->dz;
+    mark_spmm(st, 0);  // no sparse product with the whole graph
+    mark_spmm(st, 1);
+    st->spmm_cols[st->pslot] = 0;
+    mark(st, 5);
+    // FP32 blocks accumulate on FP32 MFMA, as the exact form's FP32 product does
+    constexpr bool acc64 = sizeof(T) == 8;
+    launch_tn<T, acc64>(n2, b.Zc, st->ldz, st->D, b.Zc, st->ldz, st->K, st->partial, st->Clr, st->stream);
+    launch_delta_gather<T>(lr->bound, lr->rows, lr->count, lr->dptr, lr->dcol, lr->dsg, b.Zc, st->ldz, st->D, Zg,
+                           Dz, st->stream);
+    if (lr->bound > 0) {
+      launch_tn<T, acc64>(lr->bound, Zg, st->D, st->D, Dz, st->D, st->D, st->partial, st->H, st->stream);
+    } else {
+      launch_fill_rows<double>(st->H, st->D, 0, st->D, st->D, st->stream);
+    }
+    launch_lowrank_h(st->D, st->K, st->Clr, st->theta, st->H, st->stream);
   } else {
-    launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+    // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
+    const int c0 = reuse ? st->K : 0;
+    mark_spmm(st, 0);
+    launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc + c0, st->ldz, n2, st->D - c0, b.aux + c0, st->D, st->stream);
+    mark_spmm(st, 1);
+    st->spmm_cols[st->pslot] = st->D - c0;
+    mark(st, 5);
+    // H = Z^T (op Z)
+    if constexpr (sizeof(T) == 4) {
+      if (st->prec == GREST_MIXED)
+        launch_tn_bf16(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+      else
+        launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+    } else {
+      launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+    }
   }
   // small FP64 eigensolve on the leading K + rank block, selection of K pairs
   mark(st, 6);
@@ -518,7 +563,7 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   launch_apply<T>(n2, b.Zc, st->ldz, st->D, st->F, st->K, 1.0, 0.0, b.Zn, st->ldz, st->stream);
   // A X' = (A Z) F, kept in aux[:, 0:K] for the next update (in place: every row of aux is
   // read before its first K entries are written)
-  if (st->op == GREST_OP_ADJ)
+  if (st->op == GREST_OP_ADJ && !lr)
     launch_apply<T>(n2, b.aux, st->D, st->D, st->F, st->K, 1.0, 0.0, b.aux, st->D, st->stream);
   mark(st, 8);
   return GREST_OK;
@@ -537,7 +582,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // reuse of the kept A X (adjacency), with a full-width product every kAxRefresh updates
   // so that the rounding carried along by the recurrence stays bounded
   constexpr int kAxRefresh = 16;
-  const bool reuse = st->op == GREST_OP_ADJ && st->ax_valid && st->ax_age + 1 < kAxRefresh;
+  const bool lowrank = st->proj == GREST_PROJ_LOWRANK;
+  const bool reuse = st->op == GREST_OP_ADJ && !lowrank && st->ax_valid && st->ax_age + 1 < kAxRefresh;
 
   const int gn = st->gcur ^ 1;
   const int ds = st->dslot;
@@ -628,7 +674,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
                         st->ldy, gs);
   }
   // rows where Delta_1 X can be nonzero (the adjacency's and the Laplacian's form)
-  if (sparse_dx) launch_delta1_rows(n, S, dptr, dcol, st->dflag, st->dpos, st->dscan_tmp, st->drows, gs);
+  if (sparse_dx || lowrank)
+    launch_delta1_rows(n, S, dptr, dcol, st->dflag, st->dpos, st->dscan_tmp, st->drows, gs);
   launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, st->dins, st->rp[gn], st->col[gn],
                    st->cap_m, gs);
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].vstatus, st->vstat[ds], sizeof(int32_t), hipMemcpyDeviceToHost, gs));
@@ -766,11 +813,13 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   }
   mark(st, 4);
   // ---- Rayleigh-Ritz on Z = [Xbar, Q] and back-projection ----
+  const LowRankIn lr_in{dptr, dcol, dsg, st->drows, st->dpos + n2, std::min<int64_t>(n2, 2 * nc)};
+  const LowRankIn* lr = lowrank ? &lr_in : nullptr;
   if (rsvd)  // kept columns: [0, K + r_R) and [K + L, K + L + r_dX)
     CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 4, reuse, K + st->L, st->ranks + 1,
-                         ds));
+                         ds, lr));
   else
-    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 1, reuse, 0, nullptr, ds));
+    CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 1, reuse, 0, nullptr, ds, lr));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -784,7 +833,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   st->zcur ^= 1;
   st->n = n2;
   st->m = m_new;
-  st->ax_valid = st->op == GREST_OP_ADJ;
+  st->ax_valid = st->op == GREST_OP_ADJ && !lowrank;
   st->ax_age = reuse ? st->ax_age + 1 : 0;
   return GREST_OK;
 }
@@ -964,6 +1013,8 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if (cfg->precision < GREST_FP64 || cfg->precision > GREST_MIXED) return GREST_EINVAL;
   if (cfg->variant == GREST_RSVD && (cfg->L < 1 || cfg->P < 0 || cfg->L + cfg->P > 128)) return GREST_EINVAL;
   if (cfg->variant == GREST_G3 && cfg->max_new < 0) return GREST_EINVAL;
+  if (cfg->proj != GREST_PROJ_EXACT && cfg->proj != GREST_PROJ_LOWRANK) return GREST_EINVAL;
+  if (cfg->proj == GREST_PROJ_LOWRANK && cfg->op != GREST_OP_ADJ) return GREST_EINVAL;
   const int64_t m0 = rowptr[n0];
   if (m0 < 0 || (m0 > 0 && !col)) return GREST_EINVAL;
   // host check of the initial CSR: monotone offsets, ids in range, sorted, no self-loops
@@ -982,6 +1033,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   st->cfg = *cfg;
   (void)hipGetDevice(&st->device);
   st->prec = cfg->precision;
+  st->proj = cfg->proj;
   st->es = cfg->precision == GREST_FP64 ? 8 : 4;
   st->K = cfg->k;
   st->op = cfg->op;
@@ -1019,6 +1071,7 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if ((rc = dalloc(&st->Gm, (size_t)wmax * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Mchol, (size_t)(st->K + wmax) * wmax + (size_t)(wmax + 1) * (wmax + 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->M1buf, (size_t)(st->D + wmax) * wmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->Clr, (size_t)st->D * st->K)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->H, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Msk, (size_t)(st->K + wmax) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->F, (size_t)dmax * st->K)) != GREST_OK) return fail(rc);

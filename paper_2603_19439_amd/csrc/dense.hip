@@ -35,6 +35,18 @@ __global__ void k_convert(const Ts* s, Td* d, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) d[i] = (Td)s[i];
 }
 
+// H (d x d) += C diag(theta) C^T, C d x k row-major (the low-rank term of the projected
+// matrix), one entry per thread
+__global__ void __launch_bounds__(256) k_lowrank_h(int d, int k, const double* __restrict__ Cm,
+                                                   const double* __restrict__ theta, double* __restrict__ H) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * d) return;
+  const int i = idx / d, j = idx % d;
+  double acc = H[idx];
+  for (int q = 0; q < k; ++q) acc = fma(Cm[(size_t)i * k + q] * theta[q], Cm[(size_t)j * k + q], acc);
+  H[idx] = acc;
+}
+
 // C (m x q) = A (m x p) B (p x q), row-major FP64, one output per thread
 __global__ void __launch_bounds__(256) k_small_gemm(int m, int p, int q, const double* __restrict__ A,
                                                     const double* __restrict__ B, double* __restrict__ C) {
@@ -70,6 +82,11 @@ void launch_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const
 }
 
 void launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s) { k_copy_i64<<<1, 64, 0, s>>>(src, dst); }
+
+void launch_lowrank_h(int d, int k, const double* Cm, const double* theta, double* H, hipStream_t s) {
+  if (d <= 0) return;
+  k_lowrank_h<<<(d * d + 255) / 256, 256, 0, s>>>(d, k, Cm, theta, H);
+}
 
 void launch_small_gemm(int m, int p, int q, const double* A, const double* B, double* C, hipStream_t s) {
   if (m <= 0 || q <= 0) return;

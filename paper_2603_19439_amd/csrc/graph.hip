@@ -486,3 +486,48 @@ void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* di
   k_degrees<<<grid_for(n, BS, 1024), BS, 0, s>>>(n, rp, dinv_sqrt64, dinv_sqrt32,
                                                  (unsigned long long*)maxdeg);
 }
+
+// The rows of Delta Z that the low-rank projected matrix needs, gathered: for the listed
+// rows r = rows[i] (slots i < *count), Zg[i] = Z[r] and Dz[i] = (Delta Z)[r], the sum over
+// the entries e of row r of Delta of sign_e Z[col_e] (FP64 accumulation); slots from the
+// count up to bound get zeros, so that a dense product over bound rows sees only the
+// listed ones.  One wave per slot, lanes over the w <= 128 columns.
+namespace {
+template <typename T>
+__global__ void __launch_bounds__(256) k_delta_gather(int64_t bound, const int32_t* __restrict__ rows,
+                                                      const int64_t* count, const int64_t* __restrict__ dptr,
+                                                      const int32_t* __restrict__ dcol,
+                                                      const int8_t* __restrict__ dsg, const T* __restrict__ Z,
+                                                      int64_t ldz, int w, T* __restrict__ Zg, T* __restrict__ Dz) {
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (slot >= bound) return;
+  const int64_t cnt = *count;
+  for (int c = lane; c < w; c += 64) {
+    T zg = T(0), dz = T(0);
+    if (slot < cnt) {
+      const int64_t r = rows[slot];
+      double acc = 0.0;
+      for (int64_t e = dptr[r]; e < dptr[r + 1]; ++e) acc += (double)dsg[e] * (double)Z[(int64_t)dcol[e] * ldz + c];
+      zg = Z[r * ldz + c];
+      dz = (T)acc;
+    }
+    Zg[slot * w + c] = zg;
+    Dz[slot * w + c] = dz;
+  }
+}
+}  // namespace
+
+template <typename T>
+void launch_delta_gather(int64_t bound, const int32_t* rows, const int64_t* count, const int64_t* dptr,
+                         const int32_t* dcol, const int8_t* dsg, const T* Z, int64_t ldz, int w, T* Zg, T* Dz,
+                         hipStream_t s) {
+  if (bound <= 0 || w <= 0) return;
+  k_delta_gather<T><<<(unsigned)((bound + 3) / 4), 256, 0, s>>>(bound, rows, count, dptr, dcol, dsg, Z, ldz, w, Zg,
+                                                                 Dz);
+}
+
+template void launch_delta_gather<float>(int64_t, const int32_t*, const int64_t*, const int64_t*, const int32_t*,
+                                        const int8_t*, const float*, int64_t, int, float*, float*, hipStream_t);
+template void launch_delta_gather<double>(int64_t, const int32_t*, const int64_t*, const int64_t*, const int32_t*,
+                                         const int8_t*, const double*, int64_t, int, double*, double*, hipStream_t);

@@ -130,6 +130,14 @@ bool apply_pip_ok(const float* X, int64_t ldx, int kx, const float* W, int64_t l
 bool launch_apply_pip(int64_t n, const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w,
                       const int64_t* flag2, const double* M1, float* Out, int64_t ldout, double* partial, double* C,
                       double* G, hipStream_t s);
+// H (d x d) += C diag(theta) C^T, C d x k row-major FP64
+void launch_lowrank_h(int d, int k, const double* Cm, const double* theta, double* H, hipStream_t s);
+// Zg[i] = Z[rows[i]], Dz[i] = (Delta Z)[rows[i]] for slots i < *count, zero rows up to bound
+// (outputs bound x w, row-major, ld w)
+template <typename T>
+void launch_delta_gather(int64_t bound, const int32_t* rows, const int64_t* count, const int64_t* dptr,
+                         const int32_t* dcol, const int8_t* dsg, const T* Z, int64_t ldz, int w, T* Zg, T* Dz,
+                         hipStream_t s);
 // C (m x q) = A (m x p) B (p x q), row-major FP64
 void launch_small_gemm(int m, int p, int q, const double* A, const double* B, double* C, hipStream_t s);
 template <typename Tsrc, typename Tdst>

@@ -33,7 +33,7 @@ class GrestError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("k", C.c_int32), ("variant", C.c_int32), ("L", C.c_int32), ("P", C.c_int32),
                 ("op", C.c_int32), ("precision", C.c_int32), ("max_new", C.c_int32),
-                ("reserved", C.c_int32), ("rank_tol", C.c_double)]
+                ("proj", C.c_int32), ("rank_tol", C.c_double)]
 
 
 _lib = None
@@ -137,10 +137,10 @@ class State:
 
     def __init__(self, rowptr, col, k: int, variant: str = "g3", op: str = "adj", precision: str = "fp64",
                  L: int = 0, P: int = 0, max_new: int = 0, rank_tol: float = 0.0, stream=None,
-                 node_capacity: int = 0, nnz_capacity: int = 0):
+                 node_capacity: int = 0, nnz_capacity: int = 0, proj: str = "exact"):
         self._h = C.c_void_p()
         cfg = Config(k=k, variant=VARIANT[variant], L=L, P=P, op=OP[op], precision=PRECISION[precision],
-                     max_new=max_new, reserved=0, rank_tol=rank_tol)
+                     max_new=max_new, proj={"exact": 0, "lowrank": 1}[proj], rank_tol=rank_tol)
         rp, prp = _host(rowptr, np.int64)
         cl, pcl = _host(col, np.int32)
         n0 = rp.size - 1

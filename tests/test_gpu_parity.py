@@ -58,11 +58,13 @@ def check_step(st, r, op, prec, k, label):
     return vals, X
 
 
-def run_trajectory(wl, k, variant, op, prec, steps, L=0, P=0, max_new=0, single_step=False, check_graph=True):
+def run_trajectory(wl, k, variant, op, prec, steps, L=0, P=0, max_new=0, single_step=False, check_graph=True,
+                   proj="exact"):
     A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
     th0, X0, shift0 = O.leading_eigenpairs(A, k, op)
     vals0 = th0 if op == "adj" else shift0 - th0
-    st = G.State(wl.rowptr0, wl.col0, k=k, variant=variant, op=op, precision=prec, L=L, P=P, max_new=max_new)
+    st = G.State(wl.rowptr0, wl.col0, k=k, variant=variant, op=op, precision=prec, L=L, P=P, max_new=max_new,
+                 proj=proj)
     st.set_pairs(vals0, X0)
     Xo, tho = X0, th0
     for t, d in enumerate(wl.deltas[:steps]):
@@ -71,7 +73,8 @@ def run_trajectory(wl, k, variant, op, prec, steps, L=0, P=0, max_new=0, single_
                f"changes={d.n_changes}")
         st.update_delta(d, om)
         st.sync()
-        r = O.grest_step(A, Xo, tho, d.n_new, d.i, d.j, d.sign, k, variant=variant, op=op, L=L or None, Omega=om)
+        r = O.grest_step(A, Xo, tho, d.n_new, d.i, d.j, d.sign, k, variant=variant, op=op, L=L or None, Omega=om,
+                         proj=proj)
         if check_graph:
             rp, col = st.graph()
             assert np.array_equal(rp, r.A.indptr) and np.array_equal(col, r.A.indices), "graph update differs"
@@ -127,6 +130,30 @@ def test_laplacians_with_growth_fp64(op):
     wl = W.preset("chunglu_n4e6", scale=0.001, steps=2)
     run_trajectory(wl, 8, "g3", op, "fp64", 2, max_new=64)
     run_trajectory(wl, 8, "rsvd", op, "fp64", 2, L=8, P=8)
+
+
+def test_lowrank_projection_sbm_n2000_fp64_g3():
+    """The paper's own form of the projected matrix (eq. RR_eigen_graph_upd_main3):
+    H = Z^T Xbar Theta Xbar^T Z + Z^T Delta Z with the previous Ritz values, no product with
+    the whole graph.  SBM n0 = 2000, K = 8, G-REST3, 5 steps, against the oracle's lowrank
+    form on the same inputs."""
+    wl = W.preset("sbm_n2000", steps=5)
+    run_trajectory(wl, 8, "g3", "adj", "fp64", 5, max_new=100, proj="lowrank")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_lowrank_projection_sbm_large_shape_rsvd(prec):
+    """The low-rank form with RSVD on the n = 1e6 SBM shape at 2 % scale (K = 16, L = P = 16)."""
+    wl = W.preset("sbm_n1e6", scale=0.02, steps=3)
+    run_trajectory(wl, 16, "rsvd", "adj", prec, 3, L=16, P=16, proj="lowrank")
+
+
+def test_lowrank_projection_needs_the_adjacency():
+    banner("lowrank with a Laplacian")
+    wl = W.preset("sbm_n2000", scale=0.05, steps=1)
+    with pytest.raises(G.GrestError) as e:
+        G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="lap", proj="lowrank")
+    assert e.value.status == G.EINVAL
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
