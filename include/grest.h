@@ -198,6 +198,21 @@ grest_status grest_set_stream(grest_state* st, void* stream);
  */
 grest_status grest_set_overlap(grest_state* st, int32_t enable);
 
+/*
+ * Low-rank states only (proj = GREST_PROJ_LOWRANK): release the stored graph.  The
+ * low-rank projected matrix needs only Delta and the previous pairs (eq.
+ * RR_eigen_graph_upd_main3, Alg. 2), so the state then keeps its basis, Delta and its
+ * scratch; the two CSR column buffers and the (op Z) buffer are freed.  Afterwards each
+ * update still sorts its change list into Delta's CSR and rejects out-of-range ids, i >= j,
+ * signs other than +1/-1 and pairs listed twice, but it can no longer check an insertion
+ * against an existing edge or a deletion against a missing one: the caller vouches for
+ * those (the results of an update that breaks them are undefined, not an error).
+ * grest_init_pairs and grest_get_graph then return EINVAL and grest_shape reports nnz = -1.
+ * Waits for the queued work first.  EINVAL on a NULL state or one with the exact
+ * projection; calling it again is a no-op.
+ */
+grest_status grest_release_graph(grest_state* st);
+
 /* Device memory held by the state, in bytes (its current capacities). */
 grest_status grest_memory(const grest_state* st, int64_t* device_bytes);
 

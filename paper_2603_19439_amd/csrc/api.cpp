@@ -155,6 +155,9 @@ struct grest_state {
   // adjacency only: aux[:, 0:K] holds A X for the current graph and tracked block (kept
   // from the last back-projection), so the next update multiplies only the new columns
   bool ax_valid = false;
+  // low-rank states only: the stored graph has been released (grest_release_graph); updates
+  // keep Delta alone, and the checks that need the old graph are not made
+  bool graph_free = false;
   int32_t ax_age = 0;  // updates since the last full-width product
 
   // optional stage timing with HIP events on the state's stream; two sets of events, used
@@ -228,7 +231,7 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
     CHK(dalloc((char**)&st->sc[b], cap_n * es));
     CHK(dalloc((char**)&st->z[b], (size_t)cap_n * st->ldz * es));
   }
-  CHK(dalloc((char**)&st->aux, (size_t)cap_n * std::max(st->D, st->K) * es));
+  if (!st->graph_free) CHK(dalloc((char**)&st->aux, (size_t)cap_n * std::max(st->D, st->K) * es));
   if (st->variant == GREST_RSVD) {
     CHK(dalloc((char**)&st->ybuf, (size_t)cap_n * st->ldy * es));
     CHK(dalloc((char**)&st->mbuf, (size_t)cap_n * st->ldy * es));
@@ -516,13 +519,23 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
     mark_spmm(st, 1);
     st->spmm_cols[st->pslot] = 0;
     mark(st, 5);
-    // FP32 blocks accumulate on FP32 MFMA, as the exact form's FP32 product does
-    constexpr bool acc64 = sizeof(T) == 8;
-    launch_tn<T, acc64>(n2, b.Zc, st->ldz, st->D, b.Zc, st->ldz, st->K, st->partial, st->Clr, st->stream);
+    // the products take the precision of the exact form's H: split BF16 in the mixed mode,
+    // FP32 MFMA for FP32 blocks, FP64 MFMA for FP64 blocks
+    auto product = [&](int64_t rows, const T* A, int64_t lda, int a, const T* B, int64_t ldb, int bw, double* out) {
+      if constexpr (sizeof(T) == 4) {
+        if (st->prec == GREST_MIXED)
+          launch_tn_bf16(rows, A, lda, a, B, ldb, bw, st->partial, out, st->stream);
+        else
+          launch_tn<T, false>(rows, A, lda, a, B, ldb, bw, st->partial, out, st->stream);
+      } else {
+        launch_tn<T, true>(rows, A, lda, a, B, ldb, bw, st->partial, out, st->stream);
+      }
+    };
+    product(n2, b.Zc, st->ldz, st->D, b.Zc, st->ldz, st->K, st->Clr);
     launch_delta_gather<T>(lr->bound, lr->rows, lr->count, lr->dptr, lr->dcol, lr->dsg, b.Zc, st->ldz, st->D, Zg,
                            Dz, st->stream);
     if (lr->bound > 0) {
-      launch_tn<T, acc64>(lr->bound, Zg, st->D, st->D, Dz, st->D, st->D, st->partial, st->H, st->stream);
+      product(lr->bound, Zg, st->D, st->D, Dz, st->D, st->D, st->H);
     } else {
       launch_fill_rows<double>(st->H, st->D, 0, st->D, st->D, st->stream);
     }
@@ -576,7 +589,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   const int64_t n = st->n, n2 = n + S;
   // capacities
   if (n2 > st->cap_n) CHK(grow_nodes(st, n2));
-  if (st->m + 2 * nc > st->cap_m) CHK(grow_edges(st, st->m + 2 * nc));
+  if (!st->graph_free && st->m + 2 * nc > st->cap_m) CHK(grow_edges(st, st->m + 2 * nc));
   if (nc > st->cap_nc) CHK(alloc_change_arrays(st, std::max<int64_t>(nc, st->cap_nc * 2)));
   if (st->variant == GREST_RSVD && S > st->cap_s) CHK(alloc_sketch_arrays(st, std::max<int64_t>(S, 2 * st->cap_s)));
   // reuse of the kept A X (adjacency), with a full-width product every kAxRefresh updates
@@ -631,11 +644,14 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     return GREST_EDEVICE;
   }
   launch_delta_extract(st->dkey_out, 2 * nc, dptr + n2, kshift, dcol, gs);
-  launch_delta_rows(n, S, dptr, dcol, dsg, st->dins, st->rp[st->gcur], st->col[st->gcur], st->newlen, st->vstat[ds],
-                    gs);
-  launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, gs);
-  if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, maxdeg, gs);
-  else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], maxdeg, gs);
+  const bool gfree = st->graph_free;
+  launch_delta_rows(n, S, dptr, dcol, dsg, st->dins, gfree ? nullptr : st->rp[st->gcur],
+                    gfree ? nullptr : st->col[st->gcur], st->newlen, st->vstat[ds], gs);
+  if (!gfree) {
+    launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, gs);
+    if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, maxdeg, gs);
+    else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], maxdeg, gs);
+  }
   // ---- the work of the update that reads only Delta, the new graph's scales and Omega,
   // and writes only scratch (the sketch and the row lists), goes on the same stream, its
   // short kernels before the merge, which streams the whole graph ----
@@ -676,10 +692,12 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // rows where Delta_1 X can be nonzero (the adjacency's and the Laplacian's form)
   if (sparse_dx || lowrank)
     launch_delta1_rows(n, S, dptr, dcol, st->dflag, st->dpos, st->dscan_tmp, st->drows, gs);
-  launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, st->dins, st->rp[gn], st->col[gn],
-                   st->cap_m, gs);
+  if (!gfree)
+    launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, st->dins, st->rp[gn], st->col[gn],
+                     st->cap_m, gs);
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].vstatus, st->vstat[ds], sizeof(int32_t), hipMemcpyDeviceToHost, gs));
-  HIPCHK(hipMemcpyAsync(&st->pin->g[ds].m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, gs));
+  if (!gfree)
+    HIPCHK(hipMemcpyAsync(&st->pin->g[ds].m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, gs));
   if (st->marking && st->stage_marks) (void)hipEventRecord(st->gend[st->pslot], gs);
   HIPCHK(hipEventRecord(st->gev[ds], gs));
   st->dslot ^= 1;
@@ -804,7 +822,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     snprintf(g_last_error, sizeof(g_last_error), "change list rejected (status bits 0x%x)", vbits);
     return GREST_EINVAL;
   }
-  const int64_t m_new = st->pin->g[ds].m_new;
+  const int64_t m_new = gfree ? -1 : st->pin->g[ds].m_new;
 
   if (nlap) {
     launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
@@ -1117,7 +1135,7 @@ grest_status grest_set_pairs(grest_state* st, const double* values, const double
 }
 
 grest_status grest_init_pairs(grest_state* st, int32_t iterations, uint64_t seed) {
-  if (!st || iterations < 1) return GREST_EINVAL;
+  if (!st || iterations < 1 || st->graph_free) return GREST_EINVAL;
   return st->es == 8 ? init_impl<double>(st, iterations, seed) : init_impl<float>(st, iterations, seed);
 }
 
@@ -1168,7 +1186,7 @@ grest_status grest_shape(const grest_state* st, int64_t* n, int64_t* nnz, int32_
 }
 
 grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col) {
-  if (!st) return GREST_EINVAL;
+  if (!st || st->graph_free) return GREST_EINVAL;
   CHK(sync_all(st));
   if (rowptr) HIPCHK(hipMemcpy(rowptr, st->rp[st->gcur], (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
   if (col && st->m > 0) HIPCHK(hipMemcpy(col, st->col[st->gcur], st->m * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1205,6 +1223,25 @@ grest_status grest_set_overlap(grest_state* st, int32_t enable) {
     st->gstream = st->stream;
     st->overlap = false;
   }
+  return GREST_OK;
+}
+
+grest_status grest_release_graph(grest_state* st) {
+  if (!st) return GREST_EINVAL;
+  if (st->proj != GREST_PROJ_LOWRANK) {
+    snprintf(g_last_error, sizeof(g_last_error), "only a state with the low-rank projection can drop its graph");
+    return GREST_EINVAL;
+  }
+  if (st->graph_free) return GREST_OK;
+  CHK(sync_all(st));
+  // the two CSR column buffers and the product buffer (op Z); the row offsets and the
+  // scales are node-sized and stay (unused)
+  dfree(st->col[0]);
+  dfree(st->col[1]);
+  dfree(st->aux);
+  st->cap_m = 0;
+  st->m = -1;
+  st->graph_free = true;
   return GREST_OK;
 }
 

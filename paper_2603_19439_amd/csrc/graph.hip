@@ -200,8 +200,9 @@ __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, co
   for (int64_t r = grp; r < n2; r += ngrp) {
     const int64_t beg = dptr[r];
     const int64_t len = dptr[r + 1] - beg;
-    const int64_t ob = r < n_old ? rp_old[r] : 0;
-    const int64_t olen = r < n_old ? rp_old[r + 1] - ob : 0;
+    const bool old_row = rp_old != nullptr && r < n_old;  // no old graph: membership unchecked
+    const int64_t ob = old_row ? rp_old[r] : 0;
+    const int64_t olen = old_row ? rp_old[r + 1] - ob : 0;
     if (len == 0) {
       if (sl == 0) newlen[r] = olen;
       continue;
@@ -225,7 +226,7 @@ __global__ void __launch_bounds__(BS) k_delta_rows(int64_t n_old, int64_t n2, co
       if (ve) {
         dins[beg + e] = carry + incl - ins;
         sum_s += se;
-        if (r < n_old && (int64_t)ce < n_old) {
+        if (old_row && (int64_t)ce < n_old) {
           const int64_t p = lower_bound_i32(col_old + ob, olen, ce);
           const bool found = p < olen && col_old[ob + p] == ce;
           if (found && se > 0) bad |= ST_INSERT_EXISTING;

@@ -62,6 +62,7 @@ _SIGS = [
     ("grest_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
     ("grest_set_overlap", C.c_int, [C.c_void_p, C.c_int32]),
     ("grest_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("grest_release_graph", C.c_int, [C.c_void_p]),
     ("grest_now_ns", C.c_int64, []),
     ("grest_server_create", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
     ("grest_server_attach", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -222,6 +223,10 @@ class State:
         _check(lib().grest_memory(self._h, C.byref(b)), "grest_memory")
         return int(b.value)
 
+    def release_graph(self):
+        """Low-rank states: free the stored graph; updates then keep Delta alone."""
+        _check(lib().grest_release_graph(self._h), "grest_release_graph")
+
     def set_stream(self, stream: Optional[int]):
         _check(lib().grest_set_stream(self._h, C.c_void_p(stream) if stream else None), "grest_set_stream")
 
@@ -246,6 +251,8 @@ class State:
 
     def graph(self):
         n, m, _, _ = self.shape()
+        if m < 0:  # no stored graph: the library refuses
+            _check(lib().grest_get_graph(self._h, None, None), "grest_get_graph")
         rp = np.empty(n + 1, dtype=np.int64)
         col = np.empty(m, dtype=np.int32)
         _check(lib().grest_get_graph(self._h, rp.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p)),

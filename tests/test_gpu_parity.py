@@ -148,12 +148,69 @@ def test_lowrank_projection_sbm_large_shape_rsvd(prec):
     run_trajectory(wl, 16, "rsvd", "adj", prec, 3, L=16, P=16, proj="lowrank")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lowrank_without_stored_graph(prec):
+    """A low-rank state that has released its graph keeps Delta alone (the memory of
+    eq. RR_eigen_graph_upd_main3's form): its pairs equal, bit for bit, those of a low-rank
+    state that keeps the graph; it holds less device memory; the calls that need the
+    graph refuse; a pair listed twice is still rejected, the state unchanged."""
+    import torch
+    wl = W.preset("sbm_n1e6", scale=0.02, steps=3)
+    k, L, P = 16, 16, 16
+    banner(f"lowrank without stored graph prec={prec}")
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, _ = O.leading_eigenpairs(A, k, "adj")
+    keep, free = [G.State(wl.rowptr0, wl.col0, k=k, variant="rsvd", op="adj", precision=prec, L=L, P=P,
+                          proj="lowrank") for _ in range(2)]
+    for st in (keep, free):
+        st.set_pairs(th0, X0)
+    before = free.memory()
+    free.release_graph()
+    free.release_graph()  # a second call is a no-op
+    m0 = int(wl.rowptr0[-1])
+    assert free.memory() <= before - 2 * 4 * m0, (before, free.memory())
+    assert free.shape()[1] == -1
+    with pytest.raises(G.GrestError) as e:
+        free.graph()
+    assert e.value.status == G.EINVAL
+    with pytest.raises(G.GrestError) as e:
+        free.init_pairs(2)
+    assert e.value.status == G.EINVAL
+    d0 = wl.deltas[0]
+    dev = torch.device("cuda:0")
+    with pytest.raises(G.GrestError) as e:  # the first change listed twice, caught on the device
+        free.update(0, torch.tensor(np.r_[d0.i[:3], d0.i[:1]], dtype=torch.int32, device=dev),
+                    torch.tensor(np.r_[d0.j[:3], d0.j[:1]], dtype=torch.int32, device=dev),
+                    torch.tensor(np.r_[d0.sign[:3], d0.sign[:1]], dtype=torch.int8, device=dev))
+    assert e.value.status == G.EINVAL
+    Xo, tho = X0, th0
+    for t, d in enumerate(wl.deltas[:3]):
+        om = W.omega(wl.cfg_id, 0, t + 1, d.n_new, L + P) if d.n_new > 0 else None
+        for st in (keep, free):
+            st.update_delta(d, om)
+            st.sync()
+        vk, Xk = keep.get()
+        vf, Xf = free.get()
+        assert np.array_equal(vk, vf) and np.array_equal(Xk, Xf), f"step {t + 1}: results differ"
+        r = O.grest_step(A, Xo, tho, d.n_new, d.i, d.j, d.sign, k, variant="rsvd", op="adj", L=L, Omega=om,
+                         proj="lowrank")
+        check_step(free, r, "adj", prec, k, f"step {t + 1}")
+        A, Xo, tho = r.A, r.X, r.theta
+    keep.close()
+    free.close()
+
+
 def test_lowrank_projection_needs_the_adjacency():
     banner("lowrank with a Laplacian")
     wl = W.preset("sbm_n2000", scale=0.05, steps=1)
     with pytest.raises(G.GrestError) as e:
         G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="lap", proj="lowrank")
     assert e.value.status == G.EINVAL
+    st = G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="adj")
+    with pytest.raises(G.GrestError) as e:  # the exact form needs its graph
+        st.release_graph()
+    assert e.value.status == G.EINVAL
+    st.close()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
