@@ -358,6 +358,39 @@ def laplacian_quadratic_form(A: sp.csr_matrix, X: np.ndarray, op: str) -> np.nda
 
 
 # ------------------------------------------------------------------------------------
+# drift of tracked pairs (the error proxy behind a restart)
+# ------------------------------------------------------------------------------------
+def drift_metrics(A: sp.csr_matrix, X: np.ndarray, values: np.ndarray, op: str = ADJ):
+    """How far tracked pairs have drifted from eigenpairs of the current graph: the
+    measure that decides when to recompute them from scratch, as TIMERS does when its
+    accumulated error grows (Sec. 2.2, prior art), with a minimum number of updates
+    between recomputations (the setup of Sec. 5).
+
+    orth  = max_ij |(X^T X - I)_ij|
+    resid = max_j ||M x_j - values_j x_j||_2 / scale, where M is the matrix whose values
+            are reported: A (adj), L (lap), L_n (nlap); scale = max_j |values_j| for the
+            adjacency (its norm when the largest-magnitude pair is tracked), and the
+            shift of Sec. 4.2 for the Laplacians (2 d_max >= ||L||_2, 2 >= ||L_n||_2).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    values = np.asarray(values, dtype=np.float64)
+    k = X.shape[1]
+    orth = float(np.abs(X.T @ X - np.eye(k)).max()) if k else 0.0
+    T, shift = operator_matrix(A, op)
+    if op == ADJ:
+        M = T
+        scale = float(np.abs(values).max()) if k else 1.0
+    else:
+        M = shift * sp.identity(A.shape[0]) - T
+        scale = shift
+    if scale <= 0.0:
+        scale = 1.0
+    R = M @ X - X * values[None, :]
+    resid = float(np.sqrt((R * R).sum(axis=0)).max()) / scale if k else 0.0
+    return orth, resid
+
+
+# ------------------------------------------------------------------------------------
 # exact eigenpairs (for method-quality reports and brute-force pins)
 # ------------------------------------------------------------------------------------
 def leading_eigenpairs(A: sp.csr_matrix, k: int, op: str = ADJ, dense_limit: int = 5000):

@@ -458,3 +458,64 @@ def test_ritz_nu_identity(op):
     th0, X0, _ = O.leading_eigenpairs(A, 6, op)
     r = O.grest_step(A, X0, th0, 6, ei, ej, sg, 6, variant=O.G3, op=op)
     assert np.allclose(r.nu_rq, r.nu, atol=1e-11 * max(1.0, r.shift))
+
+
+# ------------------------------------------------------------------------------------
+# drift of tracked pairs (the restart measure): pinned by exact pairs from a dense
+# eigensolver of matrices built here, and by closed forms of a scaled and a rotated pair
+# ------------------------------------------------------------------------------------
+def _small_graph(seed, n=60, p=0.12):
+    rng = np.random.default_rng(seed)
+    U = np.triu((rng.random((n, n)) < p).astype(np.float64), 1)
+    Ad = U + U.T
+    return Ad, sp.csr_matrix(Ad)
+
+
+def _dense_reported_matrix(Ad, op):
+    """A, L = D - A or L_n = I - D^-1/2 A D^-1/2 (identity rows for isolated nodes), built
+    directly from their definitions."""
+    d = Ad.sum(axis=1)
+    if op == "adj":
+        return Ad
+    if op == "lap":
+        return np.diag(d) - Ad
+    s = np.where(d > 0, 1.0 / np.sqrt(np.where(d > 0, d, 1.0)), 0.0)
+    return np.eye(len(d)) - s[:, None] * Ad * s[None, :]
+
+
+@pytest.mark.parametrize("op", ["adj", "lap", "nlap"])
+def test_drift_is_zero_on_exact_pairs(op):
+    Ad, A = _small_graph(11)
+    w, V = np.linalg.eigh(_dense_reported_matrix(Ad, op))
+    idx = np.argsort(-np.abs(w))[:6] if op == "adj" else np.arange(6)
+    orth, resid = O.drift_metrics(A, V[:, idx], w[idx], op)
+    assert orth <= 1e-13 and resid <= 1e-13, (orth, resid)
+
+
+def test_drift_of_scaled_pairs_is_orthonormality_only():
+    Ad, A = _small_graph(12)
+    w, V = np.linalg.eigh(Ad)
+    idx = np.argsort(-np.abs(w))[:5]
+    eps = 1e-3
+    orth, resid = O.drift_metrics(A, (1 + eps) * V[:, idx], w[idx], "adj")
+    assert abs(orth - (2 * eps + eps * eps)) <= 1e-12, orth
+    assert resid <= 1e-13, resid
+
+
+@pytest.mark.parametrize("op", ["adj", "lap"])
+def test_drift_of_rotated_pair_is_sine_times_gap(op):
+    """x_1 = cos(phi) u_a + sin(phi) u_b reported with value lambda_a: its residual is
+    |sin(phi)| |lambda_b - lambda_a|, divided by the scale (max |values| for the
+    adjacency, 2 d_max for the Laplacian); orthonormality is untouched."""
+    Ad, A = _small_graph(13)
+    w, V = np.linalg.eigh(_dense_reported_matrix(Ad, op))
+    order = np.argsort(-np.abs(w)) if op == "adj" else np.arange(len(w))
+    keep, b = order[:4], order[10]
+    phi = 0.2
+    X = V[:, keep].copy()
+    X[:, 0] = np.cos(phi) * V[:, keep[0]] + np.sin(phi) * V[:, b]
+    orth, resid = O.drift_metrics(A, X, w[keep], op)
+    scale = np.abs(w[keep]).max() if op == "adj" else 2.0 * Ad.sum(axis=1).max()
+    expect = abs(np.sin(phi)) * abs(w[b] - w[keep[0]]) / scale
+    assert orth <= 1e-13, orth
+    assert abs(resid - expect) <= 1e-12 * max(1.0, expect), (resid, expect)
