@@ -208,10 +208,39 @@ grest_status grest_set_overlap(grest_state* st, int32_t enable);
  * against an existing edge or a deletion against a missing one: the caller vouches for
  * those (the results of an update that breaks them are undefined, not an error).
  * grest_init_pairs and grest_get_graph then return EINVAL and grest_shape reports nnz = -1.
- * Waits for the queued work first.  EINVAL on a NULL state or one with the exact
- * projection; calling it again is a no-op.
+ * Waits for the queued work first.  EINVAL on a NULL state, one with the exact
+ * projection or one with a restart policy; calling it again is a no-op.
  */
 grest_status grest_release_graph(grest_state* st);
+
+/*
+ * Drift of the tracked pairs, the measure a restart is decided on (the recomputation of
+ * TIMERS when its accumulated error grows, Sec. 2.2): orth = max_ij |(U^T U - I)_ij| and
+ * resid = max_j ||M u_j - lambda_j u_j||_2 / scale, where M is the matrix whose values
+ * are reported (A, L or L_n) and scale = max_j |lambda_j| for the adjacency, 2 d_max for
+ * L and 2 for L_n (bounds on their norms, Sec. 4.2).  Computed on the device now (one
+ * product with the graph and two Gram passes, FP64 accumulation); waits for queued work.
+ * resid is NaN for a state without its graph.  Either pointer may be NULL.  EINVAL on a
+ * NULL state or one without pairs.
+ */
+grest_status grest_drift(grest_state* st, double* orth, double* resid);
+
+/*
+ * Restart policy: after every check_every-th update (0 disables) the drift is measured
+ * (that call of grest_update then waits for the update); when resid > tol_resid or
+ * orth > tol_orth, and at least min_gap updates have passed since the pairs were last
+ * set, initialised or recomputed (Sec. 5 keeps at least 5 updates between
+ * recomputations), the pairs are recomputed from scratch by grest_init_pairs with the
+ * given iterations and seed + (number of restarts so far).  A restart inside grest_update
+ * returns that call's status.  EINVAL on a NULL state, negative counts, iterations < 1
+ * or a negative or NaN tolerance when enabled, or a state without its graph.
+ */
+grest_status grest_set_restart(grest_state* st, double tol_resid, double tol_orth, int32_t check_every,
+                               int32_t min_gap, int32_t iterations, uint64_t seed);
+
+/* Restarts so far and the last drift measured by the policy (-1 before the first);
+ * any pointer may be NULL. */
+grest_status grest_restart_stats(const grest_state* st, int64_t* restarts, double* last_orth, double* last_resid);
 
 /* Device memory held by the state, in bytes (its current capacities). */
 grest_status grest_memory(const grest_state* st, int64_t* device_bytes);

@@ -158,6 +158,14 @@ struct grest_state {
   // low-rank states only: the stored graph has been released (grest_release_graph); updates
   // keep Delta alone, and the checks that need the old graph are not made
   bool graph_free = false;
+  // restart policy (grest_set_restart): every rs_every updates the drift of the pairs is
+  // measured; past a threshold, and at least rs_gap updates after the last (re)start,
+  // the pairs are recomputed from scratch by the initial eigensolver
+  double rs_tol_resid = 0.0, rs_tol_orth = 0.0;
+  int rs_every = 0, rs_gap = 0, rs_iters = 0;
+  uint64_t rs_seed = 0;
+  int64_t rs_since_check = 0, rs_since_start = 0, rs_count = 0;
+  double rs_last_orth = -1.0, rs_last_resid = -1.0;
   int32_t ax_age = 0;  // updates since the last full-width product
 
   // optional stage timing with HIP events on the state's stream; two sets of events, used
@@ -898,7 +906,56 @@ grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
   st->has_pairs = true;
   st->ax_valid = st->op == GREST_OP_ADJ;
   st->ax_age = 0;
+  st->rs_since_check = st->rs_since_start = 0;
   if (st->pin->status & ST_NUMERIC) return GREST_ENUMERIC;
+  return GREST_OK;
+}
+
+// Drift of the tracked pairs (the measure a restart is decided on): orth = max |U^T U - I|
+// and resid = max_j ||M u_j - lambda_j u_j||_2 / scale, with M the matrix whose values are
+// reported (A, L or L_n) and scale = max_j |lambda_j| (adjacency), 2 d_max (L) or 2 (L_n),
+// the bounds on their norms of Sec. 4.2.  Gram and residual norms accumulate in FP64; the
+// residual block M U - U diag(lambda) is formed in the other basis buffer, which is scratch
+// between updates.  Without a stored graph resid is NaN.
+template <typename T>
+grest_status drift_impl(grest_state* st, double* orth, double* resid) {
+  CHK(sync_all(st));
+  hipStream_t s = st->stream;
+  const int64_t n = st->n;
+  const int K = st->K;
+  const T* U = (const T*)st->z[st->zcur];
+  T* R = (T*)st->z[st->zcur ^ 1];
+  launch_tn<T, true>(n, U, st->ldz, K, U, st->ldz, K, st->partial, st->Gm, s);
+  std::vector<double> G((size_t)K * K), RR((size_t)K * K);
+  HIPCHK(hipMemcpyAsync(G.data(), st->Gm, G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  int64_t md = 0;
+  if (!st->graph_free) {
+    launch_spmm<T>(st->op, n, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], U, st->ldz, n, K, R,
+                   st->ldz, s);
+    launch_sub_scaled_cols<T>(n, K, st->theta, U, st->ldz, R, st->ldz, s);
+    launch_tn<T, true>(n, R, st->ldz, K, R, st->ldz, K, st->partial, st->H, s);
+    HIPCHK(hipMemcpyAsync(RR.data(), st->H, RR.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&md, st->maxdeg[st->gcur], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  double o = 0.0;
+  for (int i = 0; i < K; ++i)
+    for (int j = 0; j < K; ++j) o = std::max(o, std::fabs(G[(size_t)i * K + j] - (i == j ? 1.0 : 0.0)));
+  double r = std::nan("");
+  if (!st->graph_free) {
+    double scale = 0.0;
+    if (st->op == GREST_OP_ADJ) {
+      for (int j = 0; j < K; ++j) scale = std::max(scale, std::fabs(st->theta_pin[j]));
+    } else {
+      scale = st->op == GREST_OP_LAP ? 2.0 * (double)md : 2.0;
+    }
+    if (!(scale > 0.0)) scale = 1.0;
+    double m2 = 0.0;
+    for (int j = 0; j < K; ++j) m2 = std::max(m2, RR[(size_t)j * K + j]);
+    r = std::sqrt(m2) / scale;
+  }
+  if (orth) *orth = o;
+  if (resid) *resid = r;
   return GREST_OK;
 }
 
@@ -948,6 +1005,7 @@ grest_status set_pairs_impl(grest_state* st, const double* values, const double*
   dfree(tmp);
   st->has_pairs = true;
   st->ax_valid = false;
+  st->rs_since_check = st->rs_since_start = 0;
   return GREST_OK;
 }
 
@@ -1151,8 +1209,57 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
   if (where == GREST_HOST && !host_changes_ok(st->n, n_new, n_changes, ei, ej, sign)) return GREST_EINVAL;
   // the previous update may still run on the device: its status (and stage times) are
   // collected at this update's validation wait
-  return st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where)
-                     : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where);
+  grest_status rc = st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where)
+                                : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where);
+  if (rc != GREST_OK || st->rs_every <= 0) return rc;
+  // restart policy: the drift is measured once every rs_every updates (this call then
+  // waits for the update); past a threshold the pairs are recomputed from scratch, at
+  // most once every rs_gap updates
+  ++st->rs_since_check;
+  ++st->rs_since_start;
+  if (st->rs_since_check < st->rs_every) return GREST_OK;
+  st->rs_since_check = 0;
+  double o = 0.0, r = 0.0;
+  CHK(st->es == 8 ? drift_impl<double>(st, &o, &r) : drift_impl<float>(st, &o, &r));
+  st->rs_last_orth = o;
+  st->rs_last_resid = r;
+  if ((r > st->rs_tol_resid || o > st->rs_tol_orth) && st->rs_since_start >= st->rs_gap) {
+    // keep the update's numerical status for grest_sync: the restart reuses the word
+    st->deferred |= st->pin->status & ST_NUMERIC;
+    st->pin->status = 0;
+    const uint64_t seed = st->rs_seed + (uint64_t)st->rs_count;
+    ++st->rs_count;
+    return st->es == 8 ? init_impl<double>(st, st->rs_iters, seed) : init_impl<float>(st, st->rs_iters, seed);
+  }
+  return GREST_OK;
+}
+
+grest_status grest_drift(grest_state* st, double* orth, double* resid) {
+  if (!st || !st->has_pairs) return GREST_EINVAL;
+  return st->es == 8 ? drift_impl<double>(st, orth, resid) : drift_impl<float>(st, orth, resid);
+}
+
+grest_status grest_set_restart(grest_state* st, double tol_resid, double tol_orth, int32_t check_every,
+                               int32_t min_gap, int32_t iterations, uint64_t seed) {
+  if (!st || check_every < 0 || min_gap < 0) return GREST_EINVAL;
+  if (check_every > 0 && (iterations < 1 || st->graph_free || !(tol_resid >= 0.0) || !(tol_orth >= 0.0)))
+    return GREST_EINVAL;
+  st->rs_every = check_every;
+  st->rs_gap = min_gap;
+  st->rs_iters = iterations;
+  st->rs_tol_resid = tol_resid;
+  st->rs_tol_orth = tol_orth;
+  st->rs_seed = seed;
+  st->rs_since_check = 0;
+  return GREST_OK;
+}
+
+grest_status grest_restart_stats(const grest_state* st, int64_t* restarts, double* last_orth, double* last_resid) {
+  if (!st) return GREST_EINVAL;
+  if (restarts) *restarts = st->rs_count;
+  if (last_orth) *last_orth = st->rs_last_orth;
+  if (last_resid) *last_resid = st->rs_last_resid;
+  return GREST_OK;
 }
 
 grest_status grest_sync(grest_state* st) {
@@ -1233,6 +1340,10 @@ grest_status grest_release_graph(grest_state* st) {
     return GREST_EINVAL;
   }
   if (st->graph_free) return GREST_OK;
+  if (st->rs_every > 0) {
+    snprintf(g_last_error, sizeof(g_last_error), "a state with a restart policy needs its graph");
+    return GREST_EINVAL;
+  }
   CHK(sync_all(st));
   // the two CSR column buffers and the product buffer (op Z); the row offsets and the
   // scales are node-sized and stay (unused)

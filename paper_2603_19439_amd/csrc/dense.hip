@@ -142,7 +142,31 @@ __global__ void k_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, 
     Y[r * ldy + c] = (T)(a * (double)X[r * ldx + c] + b * (double)Y[r * ldy + c]);
   }
 }
+
+// residual block of tracked pairs: R[:, c] -= values[c] U[:, c] (FP64 arithmetic)
+template <typename T>
+__global__ void k_sub_scaled_cols(int64_t rows, int w, const double* __restrict__ values, const T* __restrict__ U,
+                                  int64_t ldu, T* __restrict__ R, int64_t ldr) {
+  const int64_t total = rows * w;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int64_t r = idx / w;
+    const int c = (int)(idx % w);
+    R[r * ldr + c] = (T)((double)R[r * ldr + c] - values[c] * (double)U[r * ldu + c]);
+  }
+}
 }  // namespace
+
+template <typename T>
+void launch_sub_scaled_cols(int64_t rows, int w, const double* values, const T* U, int64_t ldu, T* R, int64_t ldr,
+                            hipStream_t s) {
+  if (rows <= 0 || w <= 0) return;
+  k_sub_scaled_cols<T><<<grid_cap(rows * w), 256, 0, s>>>(rows, w, values, U, ldu, R, ldr);
+}
+template void launch_sub_scaled_cols<float>(int64_t, int, const double*, const float*, int64_t, float*, int64_t,
+                                            hipStream_t);
+template void launch_sub_scaled_cols<double>(int64_t, int, const double*, const double*, int64_t, double*, int64_t,
+                                             hipStream_t);
 
 template <typename T>
 void launch_fill_random(T* p, int64_t ld, int64_t rows, int w, uint64_t seed, hipStream_t s) {

@@ -195,6 +195,10 @@ bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H
 void launch_symmetrize(int d, double* H, hipStream_t s);
 template <typename T>
 void launch_fill_random(T* p, int64_t ld, int64_t rows, int w, uint64_t seed, hipStream_t s);
+// R[:, c] -= values[c] U[:, c] on an n x w block (the residual of tracked pairs)
+template <typename T>
+void launch_sub_scaled_cols(int64_t rows, int w, const double* values, const T* U, int64_t ldu, T* R, int64_t ldr,
+                            hipStream_t s);
 // Y = a X + b Y on an n x w block
 template <typename T>
 void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy,

@@ -63,6 +63,11 @@ _SIGS = [
     ("grest_set_overlap", C.c_int, [C.c_void_p, C.c_int32]),
     ("grest_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("grest_release_graph", C.c_int, [C.c_void_p]),
+    ("grest_drift", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("grest_set_restart", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_uint64]),
+    ("grest_restart_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
     ("grest_now_ns", C.c_int64, []),
     ("grest_server_create", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
     ("grest_server_attach", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
@@ -226,6 +231,24 @@ class State:
     def release_graph(self):
         """Low-rank states: free the stored graph; updates then keep Delta alone."""
         _check(lib().grest_release_graph(self._h), "grest_release_graph")
+
+    def drift(self) -> Tuple[float, float]:
+        """(max |U^T U - I|, max_j ||M u_j - lambda_j u_j|| / scale), measured on the device now."""
+        o, r = C.c_double(), C.c_double()
+        _check(lib().grest_drift(self._h, C.byref(o), C.byref(r)), "grest_drift")
+        return o.value, r.value
+
+    def set_restart(self, tol_resid: float, tol_orth: float, check_every: int = 1, min_gap: int = 5,
+                    iterations: int = 30, seed: int = 0):
+        """Recompute the pairs from scratch when their drift passes a threshold (check_every = 0: off)."""
+        _check(lib().grest_set_restart(self._h, float(tol_resid), float(tol_orth), int(check_every), int(min_gap),
+                                       int(iterations), int(seed)), "grest_set_restart")
+
+    def restart_stats(self) -> Tuple[int, float, float]:
+        """(restarts so far, last orth, last resid measured by the restart policy)."""
+        c, o, r = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().grest_restart_stats(self._h, C.byref(c), C.byref(o), C.byref(r)), "grest_restart_stats")
+        return c.value, o.value, r.value
 
     def set_stream(self, stream: Optional[int]):
         _check(lib().grest_set_stream(self._h, C.c_void_p(stream) if stream else None), "grest_set_stream")

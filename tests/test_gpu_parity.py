@@ -200,6 +200,96 @@ def test_lowrank_without_stored_graph(prec):
     free.close()
 
 
+@pytest.mark.parametrize("op,prec", [("adj", "fp64"), ("adj", "fp32"), ("lap", "mixed"), ("nlap", "fp64")])
+def test_drift_matches_oracle_definition(op, prec):
+    """The device's drift measure (orthonormality, scaled residual) against the oracle's
+    definition evaluated on the same pairs and the oracle's graph, after three updates."""
+    wl = W.preset("sbm_n2000", scale=0.5, steps=3)
+    k = 8
+    banner(f"drift op={op} prec={prec}")
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, shift0 = O.leading_eigenpairs(A, k, op)
+    vals0 = th0 if op == "adj" else shift0 - th0
+    st = G.State(wl.rowptr0, wl.col0, k=k, variant="g2", op=op, precision=prec)
+    st.set_pairs(vals0, X0)
+    for d in wl.deltas[:3]:
+        st.update_delta(d)
+        A = O.updated_adjacency(A, O.assemble_delta(A, d.n_new, d.i, d.j, d.sign))
+    st.sync()
+    vals, X = st.get()
+    orth, resid = st.drift()
+    o_ref, r_ref = O.drift_metrics(A, X, vals, op)
+    banner(f"  orth {orth:.3e} (oracle {o_ref:.3e}), resid {resid:.3e} (oracle {r_ref:.3e})")
+    assert abs(orth - o_ref) <= 1e-12, (orth, o_ref)
+    assert abs(resid - r_ref) <= (1e-11 if prec == "fp64" else 1e-5), (resid, r_ref)
+    st.close()
+
+
+def test_restart_policy_recomputes_like_init_pairs():
+    """With zero thresholds every check finds drift, so the pairs are recomputed right
+    after the fifth update (min_gap = 5) and not at the sixth or seventh: the state then
+    equals, bit for bit, a state without the policy that called grest_init_pairs with the
+    same iterations and seed at that point.  Thresholds that are never reached leave the
+    results bitwise those of a state without the policy."""
+    wl = W.preset("sbm_n2000", scale=0.5, steps=7)
+    k, iters, seed = 8, 40, 123
+    banner("restart policy")
+    mk = lambda: G.State(wl.rowptr0, wl.col0, k=k, variant="g2", op="adj", precision="fp64")
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, _ = O.leading_eigenpairs(A, k, "adj")
+    pol, ref, lax = mk(), mk(), mk()
+    for st in (pol, ref, lax):
+        st.set_pairs(th0, X0)
+    pol.set_restart(0.0, 0.0, check_every=1, min_gap=5, iterations=iters, seed=seed)
+    lax.set_restart(1e30, 1e30, check_every=2, min_gap=0, iterations=iters, seed=seed)
+    for t, d in enumerate(wl.deltas[:7]):
+        for st in (pol, ref, lax):
+            st.update_delta(d)
+        if t == 4:
+            ref.init_pairs(iters, seed)
+        n_rs, lo, lr = pol.restart_stats()
+        assert n_rs == (0 if t < 4 else 1), (t, n_rs)
+        assert lo >= 0.0 and lr >= 0.0
+    for st in (pol, ref, lax):
+        st.sync()
+    vp, Xp = pol.get()
+    vr, Xr = ref.get()
+    assert np.array_equal(vp, vr) and np.array_equal(Xp, Xr), "restart differs from init_pairs"
+    assert lax.restart_stats()[0] == 0
+    plain = mk()
+    plain.set_pairs(th0, X0)
+    for d in wl.deltas[:7]:
+        plain.update_delta(d)
+    plain.sync()
+    vl, Xl = lax.get()
+    v0, X0g = plain.get()
+    assert np.array_equal(vl, v0) and np.array_equal(Xl, X0g), "the drift checks changed the results"
+    for st in (pol, ref, lax, plain):
+        st.close()
+
+
+def test_restart_policy_argument_checks():
+    banner("restart policy arguments")
+    wl = W.preset("sbm_n2000", scale=0.25, steps=1)
+    st = G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="adj", proj="lowrank")
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, _ = O.leading_eigenpairs(A, 4, "adj")
+    st.set_pairs(th0, X0)
+    for bad in [dict(check_every=-1), dict(min_gap=-1), dict(iterations=0)]:
+        args = dict(tol_resid=1e-3, tol_orth=1e-3, check_every=1, min_gap=5, iterations=10)
+        args.update(bad)
+        with pytest.raises(G.GrestError) as e:
+            st.set_restart(**args)
+        assert e.value.status == G.EINVAL
+    st.release_graph()
+    with pytest.raises(G.GrestError) as e:  # a recomputation needs the graph
+        st.set_restart(1e-3, 1e-3)
+    assert e.value.status == G.EINVAL
+    orth, resid = st.drift()
+    assert orth <= 1e-12 and np.isnan(resid)
+    st.close()
+
+
 def test_lowrank_projection_needs_the_adjacency():
     banner("lowrank with a Laplacian")
     wl = W.preset("sbm_n2000", scale=0.05, steps=1)
