@@ -26,6 +26,10 @@ the method is measured on):
   attached by one edge.  Updates either insert/delete a fraction of the edges
   or append nodes whose partners are drawn proportional to the weights.
 
+* ``sbm_expansion``: a Bernoulli SBM on all N nodes (uniform random clusters),
+  revealed by expansion only: the subgraph induced by n0 random nodes, then
+  batches of further random nodes with all their edges; returns the clusters
+  too, for the spectral-clustering check.
 Node ids are randomly permuted at t=0 so that neighbouring ids carry no block
 locality; appended nodes take the next ids.
 """
@@ -218,6 +222,86 @@ def sbm_small(n0=2000, blocks=4, p_in=0.05, p_out=0.005, steps=10, new_per_step=
         labels = all_lab
         n += new_per_step
     return Workload("sbm_small", cfg_id, n0, rowptr0, col0, deltas, keys)
+
+
+# --------------------------------------------------------------------------------------
+# SBM revealed by graph expansion, with its ground-truth clusters
+# --------------------------------------------------------------------------------------
+def _distinct_pairs(rng, cnt, na, nb, same):
+    """cnt distinct pairs drawn uniformly: unordered pairs inside one group of na nodes
+    (same) or pairs across groups of na and nb nodes, as flat indices a * (na or nb) + b.
+    Uniform draws are merged until cnt distinct ones exist, then cnt of them are kept at
+    random: a uniformly random cnt-subset, so that with a binomial cnt every pair is an
+    edge independently (a Bernoulli graph)."""
+    width = na if same else nb
+    got = np.empty(0, np.int64)
+    while got.size < cnt:
+        m = int((cnt - got.size) * 1.2) + 16
+        a = rng.integers(0, na, m)
+        b = rng.integers(0, width, m)
+        if same:
+            keep = a != b
+            a, b = np.minimum(a[keep], b[keep]), np.maximum(a[keep], b[keep])
+        got = np.unique(np.concatenate([got, a.astype(np.int64) * width + b]))
+    if got.size > cnt:
+        got = rng.choice(got, cnt, replace=False)
+    return got, width
+
+
+@dataclasses.dataclass
+class ClusteredWorkload:
+    workload: Workload
+    labels: np.ndarray  # cluster of every node of the final graph, by node id
+
+
+def sbm_expansion(N=10_000, clusters=4, p_in=0.05, p_out=0.005, n0=9_500, steps=10, new_per_step=50,
+                  cfg_id=6, graph_id=0) -> ClusteredWorkload:
+    """An SBM on N nodes (each node in a uniformly random cluster; a pair is an edge with
+    probability p_in inside a cluster and p_out across), revealed by expansion: the graph
+    at t = 0 is the subgraph induced by n0 random nodes, and every step adds new_per_step
+    further random nodes with all their edges to the nodes present (updates are
+    insertions touching new nodes only).  Node ids follow the order of arrival."""
+    rng = rng_for(cfg_id, graph_id, 0, _GRAPH)
+    lab = rng.integers(0, clusters, N)
+    sizes = np.bincount(lab, minlength=clusters).astype(np.int64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    gi, gj = [], []  # edges in the numbering where clusters are contiguous
+    for b in range(clusters):
+        sb = int(sizes[b])
+        if sb >= 2:
+            idx, w = _distinct_pairs(rng, rng.binomial(sb * (sb - 1) // 2, p_in), sb, sb, True)
+            gi.append(idx // w + offsets[b])
+            gj.append(idx % w + offsets[b])
+        for c in range(b + 1, clusters):
+            sc = int(sizes[c])
+            if sb == 0 or sc == 0:
+                continue
+            idx, w = _distinct_pairs(rng, rng.binomial(sb * sc, p_out), sb, sc, False)
+            gi.append(idx // w + offsets[b])
+            gj.append(idx % w + offsets[c])
+    gi = np.concatenate(gi) if gi else np.empty(0, np.int64)
+    gj = np.concatenate(gj) if gj else np.empty(0, np.int64)
+    arrival = rng.permutation(N)  # node g of the contiguous numbering gets id arrival[g]
+    labels = np.empty(N, dtype=np.int64)
+    labels[arrival] = np.repeat(np.arange(clusters), sizes)
+    ei, ej = arrival[gi], arrival[gj]
+    lo, hi = np.minimum(ei, ej), np.maximum(ei, ej)
+    first = hi < n0
+    keys = np.unique(_keys(lo[first], hi[first]))
+    rowptr0, col0 = csr_from_keys(n0, keys)
+    deltas = []
+    n = n0
+    for _ in range(steps):
+        s = min(new_per_step, N - n)
+        if s <= 0:
+            break
+        m = (hi >= n) & (hi < n + s)
+        d = _delta_from_keys(n, s, _keys(lo[m], hi[m]), np.empty(0, np.int64))
+        deltas.append(d)
+        keys = apply_delta_keys(keys, d)
+        n += s
+    wl = Workload("sbm_expansion", cfg_id, n0, rowptr0, col0, deltas, keys)
+    return ClusteredWorkload(wl, labels[:n])
 
 
 # --------------------------------------------------------------------------------------

@@ -63,3 +63,30 @@ def test_omega_is_standard_normal_and_seeded():
     a = W.omega(3, 0, 1, 2000, 64)
     assert np.array_equal(a, W.omega(3, 0, 1, 2000, 64))
     assert abs(a.mean()) < 0.01 and abs(a.std() - 1) < 0.01
+
+
+def test_sbm_expansion_structure():
+    """The expansion SBM: the graph at t = 0 is induced by the first n0 ids, every update
+    appends new_per_step nodes with insertions that touch a new node only, and the final
+    graph's edge densities inside and across clusters match p_in and p_out."""
+    N, k, p_in, p_out = 2000, 4, 0.05, 0.01
+    cw = W.sbm_expansion(N=N, clusters=k, p_in=p_in, p_out=p_out, n0=1900, steps=10, new_per_step=10, graph_id=3)
+    wl, lab = cw.workload, cw.labels
+    assert wl.rowptr0.shape[0] == 1901 and lab.shape == (N,)
+    n = 1900
+    for d in wl.deltas:
+        assert d.n_old == n and d.n_new == 10
+        assert np.all(d.sign == 1) and np.all(d.i < d.j) and np.all(d.j >= n) and np.all(d.j < n + 10)
+        n += 10
+    keys = wl.keys_final
+    i, j = keys // W.KEY_BASE, keys % W.KEY_BASE
+    same = lab[i] == lab[j]
+    sizes = np.bincount(lab, minlength=k)
+    pairs_in = int((sizes * (sizes - 1) // 2).sum())
+    pairs_out = N * (N - 1) // 2 - pairs_in
+    for cnt, pairs, p in [(int(same.sum()), pairs_in, p_in), (int((~same).sum()), pairs_out, p_out)]:
+        sd = np.sqrt(pairs * p * (1 - p))
+        assert abs(cnt - pairs * p) <= 5 * sd, (cnt, pairs * p)
+    # same seed, same stream
+    again = W.sbm_expansion(N=N, clusters=k, p_in=p_in, p_out=p_out, n0=1900, steps=10, new_per_step=10, graph_id=3)
+    assert np.array_equal(again.workload.keys_final, keys) and np.array_equal(again.labels, lab)
