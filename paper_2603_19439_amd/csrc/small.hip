@@ -453,9 +453,9 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
     mx = wave_max_d(mx);
     if (lane == 0) red[wv] = mx;
     if (bad) s_bad = 1;
-    if (ty == 0)  // row 0
+    if (ty < 2)  // rows 0 and 1, the first pair's
 #pragma unroll
-      for (int b = 0; b < NB; ++b) Rr[tx + 16 * b] = v[0][b];
+      for (int b = 0; b < NB; ++b) Rr[ty * CNP_P + tx + 16 * b] = v[0][b];
   }
   __syncthreads();
   double gmx = 0.0;
@@ -466,35 +466,64 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
     return;
   }
   // right-looking factor: step j subtracts S[i][j] S[j][k] / S[j][j] (i, k > j), with
-  // S[i][j] = S[j][i] read from row j
+  // S[i][j] = S[j][i] read from row j.  Two steps per barrier: rows j and j + 1 of the
+  // Schur complement before step j are in LDS, and every thread forms row j + 1 after
+  // step j itself (the same fma as the update), so the pair applies both rank-1 updates
+  // in the order and rounding of two single steps.  Row j + 1's final values (its factor
+  // row) stay in the registers of its owners and go to LDS after the loop: no later step
+  // changes them, and writing them during the pair would race with its readers.
   if (m == CNP_M) PHASE_MARK(3);
   int r = m;
-  for (int j = 0; j < m; ++j) {
-    const double* rj = Rr + j * CNP_P;
-    const double d = rj[j];
-    if (!(d > thr)) { r = j; break; }
-    const double inv = recip(d);
-    double f[NB], g[NB];
+  for (int j = 0; j < m; j += 2) {
+    const double* r0 = Rr + j * CNP_P;
+    const double d0 = r0[j];
+    if (!(d0 > thr)) { r = j; break; }
+    const double inv0 = recip(d0);
+    const bool has1 = j + 1 < m;
+    const double* r1 = Rr + (has1 ? j + 1 : j) * CNP_P;
+    const double c10 = has1 ? r0[j + 1] * inv0 : 0.0;
+    const double d1 = has1 ? fma(-c10, r0[j + 1], r1[j + 1]) : 0.0;
+    const bool two = has1 && d1 > thr;
+    const double inv1 = two ? recip(d1) : 0.0;
+    double f0[NB], g0[NB], f1[NB], g1[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
       const int i = ty + 16 * a, k = tx + 16 * a;
-      f[a] = rj[i];
-      g[a] = rj[k];
-      f[a] = (i > j && i < m) ? f[a] * inv : 0.0;
-      g[a] = (k > j && k < m) ? g[a] : 0.0;
+      const double a0i = r0[i], a0k = r0[k], a1i = r1[i], a1k = r1[k];
+      f0[a] = (i > j && i < m) ? a0i * inv0 : 0.0;
+      g0[a] = (k > j && k < m) ? a0k : 0.0;
+      f1[a] = (two && i > j + 1 && i < m) ? fma(-c10, a0i, a1i) * inv1 : 0.0;
+      g1[a] = (two && k > j + 1 && k < m) ? fma(-c10, a0k, a1k) : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f[a], g[b], v[a][b]);
-    // row j + 1 for the next step
+      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f0[a], g0[b], v[a][b]);
 #pragma unroll
     for (int a = 0; a < NB; ++a)
-      if (ty + 16 * a == j + 1)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) Rr[(j + 1) * CNP_P + tx + 16 * b] = v[a][b];
+      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f1[a], g1[b], v[a][b]);
+    // rows j + 2 and j + 3 for the next pair (not read by this one)
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (ty + 16 * a == j + 2 || ty + 16 * a == j + 3)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Rr[(ty + 16 * a) * CNP_P + tx + 16 * b] = v[a][b];
     __syncthreads();
+    if (!two) {  // row j + 1 fails the rank rule (or there is none)
+      if (has1) r = j + 1;
+      break;
+    }
   }
+  // the second rows of the pairs: their factor rows from the registers
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const int q = ty + 16 * a;
+    if ((q & 1) && q < r)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) Rr[q * CNP_P + tx + 16 * b] = v[a][b];
+  }
+  __syncthreads();
   // valid only if every diagonal entry left is at most thr
   if (m == CNP_M) PHASE_MARK(4);
   for (int j = tid; j < r; j += CNP_T) rdi[j] = 1.0 / sqrt(Rr[j * CNP_P + j]);
@@ -517,40 +546,62 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
   // X = R^{-1} by rows from the bottom.  X starts as I; at step k row k has all its terms,
   // X[k][c] = B[k][c] / R[k][k], and every row i < k subtracts R[i][k] X[k][c]; the
   // division of each row by its R[i][i] comes at the end.
+  // Two steps per barrier, as in the factor: rows k and k - 1 of X before step k are in
+  // LDS, every thread forms row k - 1 after step k itself, and the final values of the
+  // pairs' second rows go to LDS after the loop.
 #pragma unroll
   for (int a = 0; a < NB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) v[a][b] = (ty + 16 * a == tx + 16 * b) ? 1.0 : 0.0;
-  if (r > 0) {
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
-      if (ty + 16 * a == r - 1)
+  for (int a = 0; a < NB; ++a)
+    if (ty + 16 * a < r && ty + 16 * a >= r - 2)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) Xr[(r - 1) * CNP_P + tx + 16 * b] = v[a][b];
-  }
+      for (int b = 0; b < NB; ++b) Xr[(ty + 16 * a) * CNP_P + tx + 16 * b] = v[a][b];
   __syncthreads();
-  for (int k = r - 1; k > 0; --k) {
+  for (int k = r - 1; k > 0; k -= 2) {
+    const bool has1 = k > 1;  // step k - 1 (rows below k - 1) exists
     const double rk = rdi[k];
-    double f[NB], xk[NB];
+    const double rk1 = rdi[k - 1];
+    const double fkk1 = Rr[(k - 1) * CNP_P + k] * rdi[k - 1] * rk;  // row k - 1's multiplier in step k
+    double f0[NB], x0[NB], f1[NB], x1[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
       const int i = ty + 16 * a, c = tx + 16 * a;
-      f[a] = Rr[(i < k ? i : 0) * CNP_P + k] * rdi[i < k ? i : 0];
-      xk[a] = Xr[k * CNP_P + c];
-      f[a] = i < k ? f[a] * rk : 0.0;
-      xk[a] = (c >= k && c < r) ? xk[a] : 0.0;
+      const int i0 = i < k ? i : 0, i1 = i < k - 1 ? i : 0;
+      f0[a] = Rr[i0 * CNP_P + k] * rdi[i0];
+      f1[a] = Rr[i1 * CNP_P + k - 1] * rdi[i1];
+      const double xkc = Xr[k * CNP_P + c], xk1c = Xr[(k - 1) * CNP_P + c];
+      f0[a] = i < k ? f0[a] * rk : 0.0;
+      x0[a] = (c >= k && c < r) ? xkc : 0.0;
+      f1[a] = (has1 && i < k - 1) ? f1[a] * rk1 : 0.0;
+      x1[a] = (has1 && c >= k - 1 && c < r) ? fma(-fkk1, x0[a], xk1c) : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f[a], xk[b], v[a][b]);
+      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f0[a], x0[b], v[a][b]);
 #pragma unroll
     for (int a = 0; a < NB; ++a)
-      if (ty + 16 * a == k - 1)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) Xr[(k - 1) * CNP_P + tx + 16 * b] = v[a][b];
+      for (int b = 0; b < NB; ++b) v[a][b] = fma(-f1[a], x1[b], v[a][b]);
+    // rows k - 2 and k - 3 for the next pair (not read by this one)
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (ty + 16 * a == k - 2 || ty + 16 * a == k - 3)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Xr[(ty + 16 * a) * CNP_P + tx + 16 * b] = v[a][b];
     __syncthreads();
   }
+  // the pairs' second rows k - 1 (rows r - 2, r - 4, ...): final from the registers
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const int q = ty + 16 * a;
+    if (q <= r - 2 && ((r - q) & 1) == 0)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) Xr[q * CNP_P + tx + 16 * b] = v[a][b];
+  }
+  __syncthreads();
   // output: rows of -C M, then M (zero outside the leading r x r upper triangle)
   if (m == CNP_M) PHASE_MARK(5);
   double* Mblk = Mout + (size_t)kc * m;
