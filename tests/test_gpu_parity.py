@@ -148,6 +148,32 @@ def test_lowrank_projection_sbm_large_shape_rsvd(prec):
     run_trajectory(wl, 16, "rsvd", "adj", prec, 3, L=16, P=16, proj="lowrank")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_lowrank_headline_width_graph_free(prec):
+    """The low-rank form at the headline's width (K = 32, L = P = 32: a 96-wide basis) on
+    the n = 1e6 SBM shape at 2 % scale, by a state that has released its graph and runs in
+    the overlap mode, against the oracle's low-rank trajectory."""
+    wl = W.preset("sbm_n1e6", scale=0.02, steps=2)
+    k, L, P = 32, 32, 32
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    th0, X0, _ = O.leading_eigenpairs(A, k, "adj")
+    st = G.State(wl.rowptr0, wl.col0, k=k, variant="rsvd", op="adj", precision=prec, L=L, P=P, proj="lowrank")
+    st.set_pairs(th0, X0)
+    st.release_graph()
+    st.set_overlap(True)
+    Xo, tho = X0, th0
+    for t, d in enumerate(wl.deltas[:2]):
+        om = W.omega(wl.cfg_id, 0, t + 1, d.n_new, L + P) if d.n_new > 0 else None
+        banner(f"lowrank headline width step {t + 1} prec={prec} S={d.n_new} changes={d.n_changes}")
+        st.update_delta(d, om)
+        st.sync()
+        r = O.grest_step(A, Xo, tho, d.n_new, d.i, d.j, d.sign, k, variant="rsvd", op="adj", L=L, Omega=om,
+                         proj="lowrank")
+        check_step(st, r, "adj", prec, k, f"step {t + 1}")
+        A, Xo, tho = r.A, r.X, r.theta
+    st.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_lowrank_without_stored_graph(prec):
     """A low-rank state that has released its graph keeps Delta alone (the memory of
