@@ -178,6 +178,34 @@ grest_status grest_profile(grest_state* st, int32_t enable);
 grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stages, double* spmm_ms,
                                int64_t* updates, int64_t* spmm_cols);
 
+/*
+ * Checkpoint (Alg. 2's state between two time steps): the configuration, the capacities,
+ * the stored graph (unless released), the tracked pairs and the kept adjacency product
+ * A X with its refresh age, as one self-contained host buffer.  buf == NULL: *bytes
+ * receives the size needed.  Otherwise *bytes is the buffer's size; if it is too small,
+ * EINVAL with the size needed in *bytes.  Waits for the queued work.  The restart policy,
+ * the overlap mode, the stream and the stage timing are not part of a checkpoint.
+ */
+grest_status grest_save(grest_state* st, void* buf, size_t* bytes);
+
+/*
+ * Resume: a new state on the current HIP device (stream as for grest_create) equal to
+ * the one saved, so that its updates give bit for bit the results the saved state would
+ * have given.  bytes must be the checkpoint's exact size.  EINVAL on a buffer that is not
+ * a checkpoint of this ABI version or is truncated; device errors as for grest_create.
+ */
+grest_status grest_load(const void* buf, size_t bytes, void* stream, grest_state** out);
+
+/*
+ * Borrowed view of the tracked block without a copy: *X is the device address of the
+ * basis buffer whose first k columns are X (row-major, leading dimension *ld elements,
+ * element type *dtype: GREST_F64 or GREST_F32), *n its rows.  Valid until the next call
+ * that changes the state (update, set or init of pairs, destroy); its contents are final
+ * after grest_sync, or for work ordered after the update on the state's stream.  Any
+ * output pointer may be NULL.  EINVAL on a NULL state or one without pairs.
+ */
+grest_status grest_view(grest_state* st, const void** X, int64_t* n, int64_t* ld, int32_t* dtype);
+
 /* Release the state and all its device memory. */
 void grest_destroy(grest_state* st);
 

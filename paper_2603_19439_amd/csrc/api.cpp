@@ -1077,8 +1077,12 @@ grest_status grest_validate_changes(int64_t n, int64_t n_new, int64_t n_changes,
   return host_changes_ok(n, n_new, n_changes, ei, ej, sign) ? GREST_OK : GREST_EINVAL;
 }
 
-grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, const int64_t* rowptr,
-                          const int32_t* col, int64_t node_capacity, int64_t nnz_capacity, grest_state** out) {
+namespace {
+// exact_caps: the capacities are taken as given (a resumed checkpoint, whose later growth
+// must happen at the same updates as the saved state's); otherwise they are lower bounds
+grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, const int64_t* rowptr,
+                         const int32_t* col, int64_t node_capacity, int64_t nnz_capacity, bool exact_caps,
+                         grest_state** out) {
   if (!out) return GREST_EINVAL;
   *out = nullptr;
   if (!cfg || !rowptr || n0 < 1 || (n0 >= INT32_MAX)) return GREST_EINVAL;
@@ -1133,9 +1137,10 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   st->gstream = st->stream;
   grest_status rc = GREST_OK;
   auto fail = [&](grest_status e) { free_all(st); if (st->own_stream) (void)hipStreamDestroy(st->stream); delete st; return e; };
-  int64_t capn = std::max<int64_t>(node_capacity, n0 + 1);
-  if (capn + 1 > (int64_t)4096 * 2048) return fail(GREST_EINVAL);  // device scan limit
-  int64_t capm = std::max<int64_t>(nnz_capacity, m0 + 1024);
+  int64_t capn = exact_caps ? node_capacity : std::max<int64_t>(node_capacity, n0 + 1);
+  if (capn < n0 || capn + 1 > (int64_t)4096 * 2048) return fail(GREST_EINVAL);  // device scan limit
+  int64_t capm = exact_caps ? std::max<int64_t>(nnz_capacity, 1) : std::max<int64_t>(nnz_capacity, m0 + 1024);
+  if (capm < m0) return fail(GREST_EINVAL);
   if ((rc = alloc_node_arrays(st, capn)) != GREST_OK) return fail(rc);
   if ((rc = alloc_edge_arrays(st, capm)) != GREST_OK) return fail(rc);
   if ((rc = alloc_change_arrays(st, 4096)) != GREST_OK) return fail(rc);
@@ -1185,6 +1190,12 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
   if (hipStreamSynchronize(st->stream) != hipSuccess) return fail(GREST_EDEVICE);
   *out = st;
   return GREST_OK;
+}
+}  // namespace
+
+grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, const int64_t* rowptr,
+                          const int32_t* col, int64_t node_capacity, int64_t nnz_capacity, grest_state** out) {
+  return create_impl(cfg, stream, n0, rowptr, col, node_capacity, nnz_capacity, false, out);
 }
 
 grest_status grest_set_pairs(grest_state* st, const double* values, const double* X, int32_t where) {
@@ -1394,6 +1405,136 @@ grest_status grest_stage_times(grest_state* st, double* stage_ms, int32_t n_stag
   if (spmm_ms) *spmm_ms = st->spmm_ms;
   if (updates) *updates = st->prof_updates;
   if (spmm_cols) *spmm_cols = st->prof_spmm_cols;
+  return GREST_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// checkpoint / resume and the borrowed view of the tracked block
+// ---------------------------------------------------------------------------------
+namespace {
+struct CheckpointHeader {
+  char magic[8];
+  int32_t abi, es;
+  grest_config cfg;
+  int64_t n, m, cap_n, cap_m;
+  int32_t has_pairs, graph_free, ax_valid, ax_age;
+};
+constexpr char kCheckpointMagic[8] = {'G', 'R', 'E', 'S', 'T', 'C', 'K', '1'};
+
+// layout after the header: rowptr (n + 1 int64) and col (m int32) unless the graph was
+// released; values (K f64) and X (n x K f64, row-major) with pairs; the kept product
+// A X (n x K of the state's element type) when valid
+size_t checkpoint_bytes(const CheckpointHeader& h) {
+  size_t b = sizeof(CheckpointHeader);
+  if (!h.graph_free) b += (size_t)(h.n + 1) * sizeof(int64_t) + (size_t)h.m * sizeof(int32_t);
+  if (h.has_pairs) b += (size_t)h.cfg.k * sizeof(double) + (size_t)h.n * h.cfg.k * sizeof(double);
+  if (h.ax_valid) b += (size_t)h.n * h.cfg.k * h.es;
+  return b;
+}
+}  // namespace
+
+grest_status grest_save(grest_state* st, void* buf, size_t* bytes) {
+  if (!st || !bytes) return GREST_EINVAL;
+  CHK(sync_all(st));
+  CheckpointHeader h;
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, kCheckpointMagic, sizeof(h.magic));
+  h.abi = grest_abi_version();
+  h.es = st->es;
+  h.cfg = st->cfg;
+  h.n = st->n;
+  h.m = st->graph_free ? 0 : st->m;
+  h.cap_n = st->cap_n;
+  h.cap_m = st->cap_m;
+  h.has_pairs = st->has_pairs ? 1 : 0;
+  h.graph_free = st->graph_free ? 1 : 0;
+  h.ax_valid = (st->ax_valid && st->has_pairs) ? 1 : 0;
+  h.ax_age = st->ax_age;
+  const size_t need = checkpoint_bytes(h);
+  if (!buf || *bytes < need) {
+    const bool query = !buf;
+    *bytes = need;
+    return query ? GREST_OK : GREST_EINVAL;
+  }
+  char* p = (char*)buf;
+  memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  if (!h.graph_free) {
+    HIPCHK(hipMemcpy(p, st->rp[st->gcur], (h.n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    p += (h.n + 1) * sizeof(int64_t);
+    if (h.m > 0) HIPCHK(hipMemcpy(p, st->col[st->gcur], h.m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    p += h.m * sizeof(int32_t);
+  }
+  if (h.has_pairs) {
+    double* vals = (double*)p;
+    double* X = vals + h.cfg.k;
+    CHK(grest_get(st, vals, X, GREST_F64, GREST_HOST));
+    p += (size_t)h.cfg.k * sizeof(double) + (size_t)h.n * h.cfg.k * sizeof(double);
+  }
+  if (h.ax_valid) {
+    HIPCHK(hipMemcpy2D(p, (size_t)h.cfg.k * h.es, st->aux, (size_t)st->D * h.es, (size_t)h.cfg.k * h.es, h.n,
+                       hipMemcpyDeviceToHost));
+  }
+  *bytes = need;
+  return GREST_OK;
+}
+
+grest_status grest_load(const void* buf, size_t bytes, void* stream, grest_state** out) {
+  if (!out) return GREST_EINVAL;
+  *out = nullptr;
+  if (!buf || bytes < sizeof(CheckpointHeader)) return GREST_EINVAL;
+  CheckpointHeader h;
+  memcpy(&h, buf, sizeof(h));
+  if (memcmp(h.magic, kCheckpointMagic, sizeof(h.magic)) != 0 || h.abi != grest_abi_version()) return GREST_EINVAL;
+  if ((h.es != 4 && h.es != 8) || h.n < 1 || h.m < 0 || h.cfg.k < 1 || h.cfg.k > 128) return GREST_EINVAL;
+  if (checkpoint_bytes(h) != bytes) return GREST_EINVAL;
+  const char* p = (const char*)buf + sizeof(h);
+  std::vector<int64_t> empty_rp;
+  const int64_t* rp = nullptr;
+  const int32_t* col = nullptr;
+  if (h.graph_free) {  // the released graph is not stored: an empty one of n nodes stands in
+    empty_rp.assign((size_t)h.n + 1, 0);
+    rp = empty_rp.data();
+  } else {
+    rp = (const int64_t*)p;
+    p += (h.n + 1) * sizeof(int64_t);
+    col = (const int32_t*)p;
+    p += h.m * sizeof(int32_t);
+    if (rp[h.n] != h.m) return GREST_EINVAL;
+  }
+  grest_state* st = nullptr;
+  CHK(create_impl(&h.cfg, stream, h.n, rp, col, h.cap_n, h.graph_free ? 1 : h.cap_m, true, &st));
+  grest_status rc = GREST_OK;
+  if (h.graph_free) rc = grest_release_graph(st);
+  if (rc == GREST_OK && h.has_pairs) {
+    const double* vals = (const double*)p;
+    const double* X = vals + h.cfg.k;
+    rc = grest_set_pairs(st, vals, X, GREST_HOST);
+    p += (size_t)h.cfg.k * sizeof(double) + (size_t)h.n * h.cfg.k * sizeof(double);
+  }
+  if (rc == GREST_OK && h.ax_valid) {
+    if (hipMemcpy2D(st->aux, (size_t)st->D * h.es, p, (size_t)h.cfg.k * h.es, (size_t)h.cfg.k * h.es, h.n,
+                    hipMemcpyHostToDevice) != hipSuccess) {
+      rc = GREST_EDEVICE;
+    } else {
+      st->ax_valid = true;
+      st->ax_age = h.ax_age;
+    }
+  }
+  if (rc != GREST_OK) {
+    grest_destroy(st);
+    return rc;
+  }
+  *out = st;
+  return GREST_OK;
+}
+
+grest_status grest_view(grest_state* st, const void** X, int64_t* n, int64_t* ld, int32_t* dtype) {
+  if (!st || !st->has_pairs) return GREST_EINVAL;
+  if (X) *X = st->z[st->zcur];
+  if (n) *n = st->n;
+  if (ld) *ld = st->ldz;
+  if (dtype) *dtype = st->es == 8 ? GREST_F64 : GREST_F32;
   return GREST_OK;
 }
 

@@ -63,6 +63,10 @@ _SIGS = [
     ("grest_set_overlap", C.c_int, [C.c_void_p, C.c_int32]),
     ("grest_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("grest_release_graph", C.c_int, [C.c_void_p]),
+    ("grest_save", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    ("grest_load", C.c_int, [C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("grest_view", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                             C.POINTER(C.c_int32)]),
     ("grest_drift", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("grest_set_restart", C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_uint64]),
@@ -157,6 +161,38 @@ class State:
         self.op = op
         self.precision = precision
         self._lib = lib()  # kept for the destructor, which may run during interpreter exit
+
+    def save(self) -> bytes:
+        """Checkpoint of the state (graph, capacities, pairs, kept product) as bytes."""
+        size = C.c_size_t(0)
+        _check(lib().grest_save(self._h, None, C.byref(size)), "grest_save")
+        buf = C.create_string_buffer(size.value)
+        _check(lib().grest_save(self._h, buf, C.byref(size)), "grest_save")
+        return buf.raw[:size.value]
+
+    @classmethod
+    def load(cls, blob: bytes, stream=None) -> "State":
+        """A new state resumed from a checkpoint made by save()."""
+        import struct
+        self = cls.__new__(cls)
+        self._h = C.c_void_p()
+        buf = C.create_string_buffer(blob, len(blob))
+        sp = C.c_void_p(stream) if stream else None
+        _check(lib().grest_load(buf, len(blob), sp, C.byref(self._h)), "grest_load")
+        # header: magic, abi, element size, then the config's k, variant, L, P, op, precision
+        k, _, _, _, op, prec = struct.unpack_from("<6i", blob, 16)
+        self.k = k
+        self.op = {v: n for n, v in OP.items()}[op]
+        self.precision = {v: n for n, v in PRECISION.items()}[prec]
+        self._lib = lib()
+        return self
+
+    def view(self) -> Tuple[int, int, int, int]:
+        """(device address, rows, leading dimension, dtype code) of the basis buffer whose
+        first k columns are the tracked block (borrowed: valid until the state changes)."""
+        x, n, ld, dt = C.c_void_p(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().grest_view(self._h, C.byref(x), C.byref(n), C.byref(ld), C.byref(dt)), "grest_view")
+        return int(x.value or 0), n.value, ld.value, dt.value
 
     def close(self):
         if getattr(self, "_h", None):
