@@ -904,7 +904,7 @@ grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
   HIPCHK(hipStreamSynchronize(s));
   st->zcur ^= 1;
   st->has_pairs = true;
-  st->ax_valid = st->op == GREST_OP_ADJ;
+  st->ax_valid = st->op == GREST_OP_ADJ && st->proj == GREST_PROJ_EXACT;
   st->ax_age = 0;
   st->rs_since_check = st->rs_since_start = 0;
   if (st->pin->status & ST_NUMERIC) return GREST_ENUMERIC;
@@ -1448,7 +1448,8 @@ grest_status grest_save(grest_state* st, void* buf, size_t* bytes) {
   h.cap_m = st->cap_m;
   h.has_pairs = st->has_pairs ? 1 : 0;
   h.graph_free = st->graph_free ? 1 : 0;
-  h.ax_valid = (st->ax_valid && st->has_pairs) ? 1 : 0;
+  h.ax_valid = (st->ax_valid && st->has_pairs && !st->graph_free && st->op == GREST_OP_ADJ &&
+                st->proj == GREST_PROJ_EXACT) ? 1 : 0;
   h.ax_age = st->ax_age;
   const size_t need = checkpoint_bytes(h);
   if (!buf || *bytes < need) {
@@ -1486,7 +1487,15 @@ grest_status grest_load(const void* buf, size_t bytes, void* stream, grest_state
   CheckpointHeader h;
   memcpy(&h, buf, sizeof(h));
   if (memcmp(h.magic, kCheckpointMagic, sizeof(h.magic)) != 0 || h.abi != grest_abi_version()) return GREST_EINVAL;
-  if ((h.es != 4 && h.es != 8) || h.n < 1 || h.m < 0 || h.cfg.k < 1 || h.cfg.k > 128) return GREST_EINVAL;
+  // everything the sizes and the device copies below depend on is checked before use
+  if (h.es != (h.cfg.precision == GREST_FP64 ? 8 : 4)) return GREST_EINVAL;
+  if (h.n < 1 || h.n >= INT32_MAX || h.m < 0 || h.m > ((int64_t)1 << 40) || h.cfg.k < 1 || h.cfg.k > 128)
+    return GREST_EINVAL;
+  if ((h.has_pairs | h.graph_free | h.ax_valid) & ~1) return GREST_EINVAL;
+  if (h.graph_free && (h.m != 0 || h.cfg.proj != GREST_PROJ_LOWRANK)) return GREST_EINVAL;
+  // the kept product exists only for the exact adjacency form with pairs and a graph
+  if (h.ax_valid && (!h.has_pairs || h.graph_free || h.cfg.op != GREST_OP_ADJ || h.cfg.proj != GREST_PROJ_EXACT))
+    return GREST_EINVAL;
   if (checkpoint_bytes(h) != bytes) return GREST_EINVAL;
   const char* p = (const char*)buf + sizeof(h);
   std::vector<int64_t> empty_rp;

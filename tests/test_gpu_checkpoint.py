@@ -83,7 +83,12 @@ def test_malformed_checkpoints_are_rejected():
     st = G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="adj")
     st.set_pairs(th0, X0)
     blob = st.save()
-    for bad in [blob[:-8], blob + b"\0" * 8, b"X" + blob[1:]]:
+    import struct
+    wrong_es = bytearray(blob)
+    struct.pack_into("<i", wrong_es, 12, 4)  # FP32 elements claimed for an FP64 state
+    released = bytearray(blob)
+    struct.pack_into("<i", released, 92, 1)  # a released graph claimed for the exact form
+    for bad in [blob[:-8], blob + b"\0" * 8, b"X" + blob[1:], bytes(wrong_es), bytes(released)]:
         with pytest.raises(G.GrestError) as e:
             G.State.load(bad)
         assert e.value.status == G.EINVAL
@@ -114,3 +119,23 @@ def test_view_holds_the_tracked_block(prec):
     assert hip.hipMemcpy(host.ctypes.data, ptr, host.nbytes, 2) == 0  # device to host
     assert np.array_equal(host[:, :8].astype(np.float64), X)
     st.close()
+
+
+def test_lowrank_state_initialised_on_device_round_trips():
+    """A low-rank state whose pairs come from the device initialisation keeps no product
+    with the graph, so its checkpoint carries none and loads back."""
+    banner("low-rank state after device init")
+    wl = W.preset("sbm_n2000", scale=0.5, steps=2)
+    st = G.State(wl.rowptr0, wl.col0, k=8, variant="g2", op="adj", precision="fp64", proj="lowrank")
+    st.init_pairs(30, 5)
+    rs = G.State.load(st.save())
+    for d in wl.deltas[:2]:
+        st.update_delta(d)
+        rs.update_delta(d)
+    st.sync()
+    rs.sync()
+    v0, X0 = st.get()
+    v1, X1 = rs.get()
+    assert np.array_equal(v0, v1) and np.array_equal(X0, X1)
+    st.close()
+    rs.close()
