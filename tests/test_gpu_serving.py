@@ -191,3 +191,43 @@ def test_serving_graph_updates_report_no_numerical_status(graph_id, requests):
     assert np.all(np.isfinite(vals)) and np.all(np.isfinite(X))
     assert M.orthonormality(X) <= 1e-5
     st.close()
+
+
+def test_restart_policy_inside_served_updates():
+    """States with a restart policy served over two lanes: the recomputations happen inside
+    the lanes' updates, after the same updates as when each graph is driven alone, and
+    the results are bitwise those of the graph alone."""
+    graphs = _graphs(3, steps=4)
+
+    def policy_state(g, wl, k, th, X):
+        st = _new_state(wl, k, th, X, "fp64")
+        st.set_restart(0.0, 0.0, check_every=1, min_gap=2, iterations=20, seed=7 + g)
+        return st
+
+    ref = []
+    for g, (wl, k, th, X) in enumerate(graphs):
+        banner(f"restart policy alone graph {g}")
+        st = policy_state(g, wl, k, th, X)
+        for t, d in enumerate(wl.deltas):
+            st.update_delta(d, _omega(wl, g, t, d, k))
+        st.sync()
+        ref.append((st.get(), st.restart_stats()[0]))
+        st.close()
+    banner("restart policy served")
+    sv = G.Server(lanes=2)
+    states = [policy_state(g, wl, k, th, X) for g, (wl, k, th, X) in enumerate(graphs)]
+    ids = [sv.attach(st) for st in states]
+    for t in range(4):
+        for g, (wl, k, th, X) in enumerate(graphs):
+            d = wl.deltas[t]
+            assert sv.submit(ids[g], d.n_new, d.i, d.j, d.sign, _omega(wl, g, t, d, k), tag=1000 * g + t) == G.OK
+    sv.drain()
+    tags, status, _, _ = sv.poll(1024)
+    assert tags.size == 12 and np.all(status == G.OK), status
+    sv.close()
+    for g, st in enumerate(states):
+        (vr, Xr), nr = ref[g]
+        vals, X = st.get()
+        assert nr == 2 and st.restart_stats()[0] == nr
+        assert np.array_equal(vals, vr) and np.array_equal(X, Xr), f"graph {g} differs"
+        st.close()
