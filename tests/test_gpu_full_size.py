@@ -1,0 +1,87 @@
+"""The HIP path at the workloads' full sizes, checked through properties that hold at any
+size (the oracle cannot compute the exact pairs of these graphs):
+
+* the graph after the updates is, entry for entry, the oracle's A^(t+1) = pad(A^(t)) + Delta
+  (eq. adj_update);
+* every returned value is the Rayleigh quotient of its returned vector on the oracle's
+  updated operator (u^T A u for the adjacency, u^T L u for the Laplacian), to the mixed
+  precision's eigenvalue tolerance 1e-3 (Alg. 1: Ritz values are Rayleigh quotients of
+  Ritz vectors);
+* the tracked block is orthonormal to 1e-5.
+
+The initial pairs come from the device initialisation, as in the benchmark.  Generating
+the two workloads on the host takes about half a minute.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import grest_oracle as O
+from paper_2603_19439_amd import grest as G
+from paper_2603_19439_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def banner(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _check(st, A, op, steps_label):
+    vals, X = st.get()
+    rp, col = st.graph()
+    assert np.array_equal(rp, A.indptr) and np.array_equal(col, A.indices), "graph update differs"
+    k = X.shape[1]
+    G_ = X.T @ X
+    orth = float(np.abs(G_ - np.eye(k)).max())
+    T, alpha = O.operator_matrix(A, op)
+    TX = T @ X
+    tq = (X * TX).sum(axis=0)
+    rq = tq if op == "adj" else alpha - tq  # u^T A u, or u^T L u = alpha - u^T T u
+    scale = np.maximum(np.abs(rq), 1e-8 * np.abs(rq).max())
+    e = float((np.abs(vals - rq) / scale).max())
+    banner(f"  {steps_label}: orth {orth:.2e}, max |value - Rayleigh quotient| / |quotient| {e:.2e}")
+    assert orth <= 1e-5, orth
+    assert e <= 1e-3, e
+
+
+def _run(wl, k, variant, op, L, P, steps, init_iters):
+    t0 = time.time()
+    n_final = wl.n_at(steps)
+    nnz_cap = int(wl.col0.size + 2 * sum(d.n_changes for d in wl.deltas[:steps]) + 1024)
+    st = G.State(wl.rowptr0, wl.col0, k=k, variant=variant, op=op, precision="mixed", L=L, P=P,
+                 node_capacity=n_final + 1, nnz_capacity=nnz_cap)
+    st.set_overlap(True)
+    st.init_pairs(iterations=init_iters, seed=7)
+    banner(f"  initial pairs on the device ({time.time() - t0:.1f} s)")
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    for t, d in enumerate(wl.deltas[:steps]):
+        om = W.omega(wl.cfg_id, 0, t + 1, d.n_new, L + P) if variant == "rsvd" and d.n_new > 0 else None
+        st.update_delta(d, om)
+        A = O.updated_adjacency(A, O.assemble_delta(A, d.n_new, d.i, d.j, d.sign))
+        banner(f"  step {t + 1}: n={A.shape[0]} nnz={A.nnz}")
+    st.sync()
+    _check(st, A, op, f"after {steps} updates")
+    st.close()
+
+
+def test_sbm_n1e6_k32_rsvd_mixed_full_size():
+    """The benchmark's workload at full size: SBM n0 = 1e6, 32 Dirichlet blocks, mean degree
+    20, 10,000 new nodes and 10,000 insertions per step; K = 32, G-REST_RSVD L = P = 32,
+    mixed precision, overlap mode; 4 updates."""
+    t0 = time.time()
+    wl = W.preset("sbm_n1e6", steps=4)
+    banner(f"sbm n1e6 generated in {time.time() - t0:.1f} s")
+    _run(wl, 32, "rsvd", "adj", 32, 32, 4, 40)
+
+
+def test_chunglu_n4e6_laplacian_k64_full_size():
+    """Chung-Lu n0 = 4e6, mean degree 16, exponent 2.2, combinatorial Laplacian, K = 64
+    smallest, G-REST2 (a 128-wide basis), mixed precision; 2 updates of 1 % node growth."""
+    t0 = time.time()
+    wl = W.preset("chunglu_n4e6", steps=2)
+    banner(f"chung-lu n4e6 generated in {time.time() - t0:.1f} s")
+    _run(wl, 64, "g2", "lap", 0, 0, 2, 20)
