@@ -109,6 +109,14 @@ def test_sbm_large_shape_rsvd(prec):
     run_trajectory(wl, 16, "rsvd", "adj", prec, 3, L=16, P=16)
 
 
+def test_chunglu_n1e5_normalized_laplacian_k32_fp32_full_size():
+    """The normalised-Laplacian workload at its full size: Chung-Lu n0 = 1e5 (Pareto
+    exponent 2.5, mean 16, cap 2000), K = 32, 20 steps of 0.5 % insertions and 0.2 %
+    deletions, FP32, step by step against the oracle's trajectory (graph and pairs)."""
+    wl = W.preset("chunglu_n1e5", steps=20)
+    run_trajectory(wl, 32, "g2", "nlap", "fp32", 20)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
 def test_sbm_headline_width_rsvd_k32(prec):
     """The headline's shape at n0=20000: Dirichlet SBM, K=32, RSVD with L=P=32, so the
