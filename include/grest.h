@@ -277,11 +277,12 @@ grest_status grest_memory(const grest_state* st, int64_t* device_bytes);
  * Batched execution of many graphs (serving).  This is not part of the method: it runs
  * the single-graph update of Alg. 2 for many independent graphs on one device.
  *
- * A server owns `lanes` worker lanes, each a host thread with its own HIP stream.  A
- * state attached to the server is pinned to one lane (graph ids are assigned in attach
- * order, lane = id mod lanes) and driven only by that lane until the server is
- * destroyed, so the updates of one graph run in submission order and one at a time;
- * lanes overlap on the device.  Every update of a graph runs the same kernels with the
+ * A server owns `lanes` worker lanes, each a host thread with its own HIP stream.
+ * Requests wait in one queue in submission order; a free lane takes the oldest request
+ * whose graph no other lane is updating and runs it on its own stream (the graph's state
+ * is moved there while idle).  So the updates of one graph run in submission order and
+ * one at a time, a request never waits behind another graph's update while a lane is
+ * free, and lanes overlap on the device.  Every update of a graph runs the same kernels with the
  * same reduction orders whatever else is queued, so its result does not depend on the
  * mix of graphs.
  *

@@ -1048,6 +1048,10 @@ grest_status get_impl(grest_state* st, double* values, void* X, int32_t x_dtype,
 
 void* state_user_stream(const grest_state* st) { return st->own_stream ? nullptr : (void*)st->stream; }
 int64_t state_sketch_cols(const grest_state* st) { return st->variant == GREST_RSVD ? st->Ls : 0; }
+void state_rebind_stream(grest_state* st, void* stream) {
+  st->stream = (hipStream_t)stream;
+  if (!st->overlap) st->gstream = st->stream;
+}
 
 // =====================================================================================
 // C interface

@@ -212,3 +212,7 @@ struct grest_state;
 void* state_user_stream(const grest_state* st);
 // columns of the Gaussian test matrix an update needs (L + P for RSVD, else 0)
 int64_t state_sketch_cols(const grest_state* st);
+// Moves an idle state (nothing queued on its streams, e.g. right after grest_sync) onto
+// another stream without waiting on the old one, which another state may be using.
+// The state must not own its stream (attach has replaced an owned stream already).
+void state_rebind_stream(grest_state* st, void* stream);

@@ -1,11 +1,14 @@
 // Batched execution of many independent graphs on one device (the serving loop).
 //
 // A server runs `lanes` worker threads, each with its own HIP stream (default priority).
-// Attached graphs are pinned to lane id mod lanes; a lane takes its requests in
-// submission order and runs each one as a complete single-graph update (grest_update,
-// then grest_sync for the deferred status), so one graph's updates stay ordered and
-// never overlap, while the lanes overlap on the device.  Requests own copies of their
-// change lists.  Completions are kept until grest_poll hands them out.
+// Requests wait in one queue in submission order.  A free lane takes the oldest request
+// whose graph is not being updated by another lane, moves that graph's state onto its
+// own stream (the state is idle then, so the move costs no wait) and runs the request as
+// a complete single-graph update (grest_update, then grest_sync for the deferred status).
+// So one graph's updates stay ordered and never overlap, no lane idles while a runnable
+// request waits behind a long update of another graph, and the lanes overlap on the
+// device.  Requests own copies of their change lists.  Completions are kept until
+// grest_poll hands them out.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,6 +53,8 @@ struct Graph {
   int64_t bytes;
   int64_t sketch_cols;  // L + P of an RSVD state, else 0
   int64_t n_proj;       // node count once every queued request of the graph has run
+  int32_t lane;         // lane whose stream the state is on
+  bool running;         // a lane is updating it
 };
 
 }  // namespace
@@ -59,7 +64,7 @@ struct grest_server {
   int64_t budget = 0, used = 0;
   int32_t nlanes = 0, max_queue = 0;
   std::vector<hipStream_t> streams;
-  std::vector<std::deque<Request>> queues;
+  std::deque<Request> queue;  // submission order
   std::vector<std::thread> workers;
   std::vector<Graph> graphs;
   std::deque<Done> done;
@@ -76,14 +81,29 @@ void worker(grest_server* sv, int lane) {
   for (;;) {
     Request rq;
     grest_state* st = nullptr;
+    bool move = false;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queues[lane].empty(); });
-      if (sv->queues[lane].empty()) return;  // stop requested and nothing left
-      rq = std::move(sv->queues[lane].front());
-      sv->queues[lane].pop_front();
-      st = sv->graphs[rq.gid].st;  // read under the lock: attach may grow the table
+      // the oldest request whose graph is idle (the graph's own requests are in order)
+      auto runnable = [&] {
+        for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
+          if (!sv->graphs[it->gid].running) return it;
+        return sv->queue.end();
+      };
+      auto it = sv->queue.end();
+      sv->cv_work.wait(lk, [&] { return (it = runnable()) != sv->queue.end() || (sv->stop && sv->queue.empty()); });
+      if (it == sv->queue.end()) return;  // stop requested and nothing left
+      rq = std::move(*it);
+      sv->queue.erase(it);
+      Graph& g = sv->graphs[rq.gid];  // under the lock: attach may grow the table
+      g.running = true;
+      st = g.st;
+      move = g.lane != lane;
+      g.lane = lane;
     }
+    // the state is idle (its last update ended with grest_sync), while its old stream may
+    // be running another graph's update: no wait on that stream
+    if (move) state_rebind_stream(st, sv->streams[lane]);
     const int64_t nc = (int64_t)rq.ei.size();
     const grest_status ru = grest_update(st, rq.n_new, nc, nc ? rq.ei.data() : nullptr,
                                          nc ? rq.ej.data() : nullptr, nc ? rq.sg.data() : nullptr,
@@ -96,10 +116,12 @@ void worker(grest_server* sv, int lane) {
     {
       std::lock_guard<std::mutex> lk(sv->mu);
       if (ru != GREST_OK) sv->graphs[rq.gid].n_proj -= rq.n_new;  // rejected: the graph did not grow
+      sv->graphs[rq.gid].running = false;
       sv->done.push_back(Done{rq.tag, (int32_t)rc, rq.t_submit, t_done});
       --sv->pending;
     }
     sv->cv_idle.notify_all();
+    sv->cv_work.notify_all();  // the graph's next request may be runnable now
   }
 }
 
@@ -121,7 +143,6 @@ grest_status grest_server_create(int64_t hbm_budget_bytes, int32_t lanes, int32_
   sv->budget = hbm_budget_bytes;
   sv->nlanes = lanes;
   sv->max_queue = max_queue;
-  sv->queues.resize(lanes);
   for (int l = 0; l < lanes; ++l) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
@@ -151,7 +172,7 @@ grest_status grest_server_attach(grest_server* sv, grest_state* st, int32_t* gra
   const int32_t id = (int32_t)sv->graphs.size();
   void* user = state_user_stream(st);
   if ((rc = grest_set_stream(st, sv->streams[id % sv->nlanes])) != GREST_OK) return rc;
-  sv->graphs.push_back(Graph{st, user, bytes, state_sketch_cols(st), n});
+  sv->graphs.push_back(Graph{st, user, bytes, state_sketch_cols(st), n, id % sv->nlanes, false});
   sv->used += bytes;
   *graph_id = id;
   return GREST_OK;
@@ -186,7 +207,7 @@ grest_status grest_submit(grest_server* sv, int32_t graph_id, int64_t n_new, int
     if (sv->pending >= sv->max_queue) return GREST_EAGAIN;
     sv->graphs[graph_id].n_proj += n_new;
     rq.t_submit = now_ns();
-    sv->queues[graph_id % sv->nlanes].push_back(std::move(rq));
+    sv->queue.push_back(std::move(rq));
     ++sv->pending;
   }
   sv->cv_work.notify_all();
