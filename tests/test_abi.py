@@ -67,3 +67,44 @@ def test_create_without_device_or_with_bad_args_fails_cleanly():
     bad = np.array([1, 1], dtype=np.int32)  # self-loop in row 1
     with pytest.raises(G.GrestError):
         G.State(rp, bad, k=1)
+
+
+def _checkpoint(es=8, prec=0, proj=0, has_pairs=0, graph_free=0, ax_valid=0, magic=b"GRESTCK1", n=3, m=2,
+                truncate=0):
+    """A checkpoint buffer of the layout grest_save writes (header, then the CSR), for a
+    3-node graph with one edge and no pairs."""
+    import struct
+    cfg = struct.pack("<8id", 1, 2, 0, 0, 0, prec, 0, proj, 0.0)  # k=1, G-REST2, adjacency
+    head = struct.pack("<8sii", magic, 1, es) + cfg + struct.pack("<qqqq", n, m, n + 1, m + 1024) + \
+        struct.pack("<iiii", has_pairs, graph_free, ax_valid, 0)
+    body = b""
+    if not graph_free:
+        body = np.array([0, 1, 2, 2], dtype=np.int64).tobytes() + np.array([1, 0], dtype=np.int32).tobytes()
+    buf = head + body
+    return buf[:len(buf) - truncate] if truncate else buf
+
+
+@pytest.mark.parametrize("kw,valid", [
+    (dict(), True),
+    (dict(es=4), False),                      # FP32 elements for an FP64 configuration
+    (dict(magic=b"GRESTCKX"), False),         # not a checkpoint
+    (dict(truncate=4), False),                # truncated
+    (dict(graph_free=1), False),              # a released graph for the exact form
+    (dict(ax_valid=1), False),                # a kept product without pairs
+    (dict(proj=1, ax_valid=0, graph_free=0), True),
+])
+def test_checkpoint_header_checks_on_the_host(kw, valid):
+    """grest_load checks a checkpoint on the host before any device call: malformed buffers
+    are EINVAL; a well-formed one reaches the device (ENODEV without a GPU)."""
+    import ctypes as C
+    lib = G.lib()
+    buf = _checkpoint(**kw)
+    cbuf = C.create_string_buffer(buf, len(buf))
+    out = C.c_void_p()
+    rc = lib.grest_load(cbuf, len(buf), None, C.byref(out))
+    if valid:
+        assert rc in (G.OK, G.ENODEV), rc
+        if rc == G.OK:
+            lib.grest_destroy(out)
+    else:
+        assert rc == G.EINVAL, rc
