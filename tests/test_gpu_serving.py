@@ -231,3 +231,44 @@ def test_restart_policy_inside_served_updates():
         assert nr == 2 and st.restart_stats()[0] == nr
         assert np.array_equal(vals, vr) and np.array_equal(X, Xr), f"graph {g} differs"
         st.close()
+
+
+def test_graph_free_lowrank_states_served():
+    """Low-rank states that released their graphs (the truncated form keeps Delta alone)
+    are admitted with the footprint they have after the release and served with results
+    bitwise those of each graph alone."""
+    graphs = _graphs(3, steps=3)
+
+    def lowrank_state(wl, k, th, X):
+        st = G.State(wl.rowptr0, wl.col0, k=k, variant="rsvd", precision="mixed", L=k, P=k, proj="lowrank")
+        st.set_pairs(th, X)
+        before = st.memory()
+        st.release_graph()
+        assert st.memory() < before
+        return st
+
+    ref = []
+    for g, (wl, k, th, X) in enumerate(graphs):
+        banner(f"graph-free low-rank alone graph {g}")
+        st = lowrank_state(wl, k, th, X)
+        for t, d in enumerate(wl.deltas):
+            st.update_delta(d, _omega(wl, g, t, d, k))
+        st.sync()
+        ref.append(st.get())
+        st.close()
+    banner("graph-free low-rank served")
+    states = [lowrank_state(wl, k, th, X) for (wl, k, th, X) in graphs]
+    sv = G.Server(lanes=2, hbm_budget_bytes=sum(st.memory() for st in states))
+    ids = [sv.attach(st) for st in states]
+    for t in range(3):
+        for g, (wl, k, th, X) in enumerate(graphs):
+            d = wl.deltas[t]
+            assert sv.submit(ids[g], d.n_new, d.i, d.j, d.sign, _omega(wl, g, t, d, k), tag=1000 * g + t) == G.OK
+    sv.drain()
+    tags, status, _, _ = sv.poll(1024)
+    assert tags.size == 9 and np.all(status == G.OK), status
+    sv.close()
+    for g, st in enumerate(states):
+        vals, X = st.get()
+        assert np.array_equal(vals, ref[g][0]) and np.array_equal(X, ref[g][1]), f"graph {g} differs"
+        st.close()
