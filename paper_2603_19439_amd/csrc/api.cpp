@@ -271,6 +271,19 @@ grest_status alloc_edge_arrays(grest_state* st, int64_t cap_m) {
   return GREST_OK;
 }
 
+// The low-rank form's gathered rows of Z and Delta Z: one per row of Delta with an entry,
+// at most min(n', 2 x changes) <= min(node capacity, 2 x change capacity); reallocated
+// when either capacity grows (both callers have synchronised the state)
+grest_status alloc_gather_arrays(grest_state* st) {
+  dfree(st->zg);
+  dfree(st->dz);
+  if (st->proj != GREST_PROJ_LOWRANK) return GREST_OK;
+  const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(2 * st->cap_nc, st->cap_n));
+  CHK(dalloc((char**)&st->zg, (size_t)rows * st->D * st->es));
+  CHK(dalloc((char**)&st->dz, (size_t)rows * st->D * st->es));
+  return GREST_OK;
+}
+
 grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
   CHK(sync_all(st));  // queued work may still read the old arrays
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
@@ -289,13 +302,8 @@ grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
   }
   CHK(dalloc(&st->dins, 2 * cap_nc));
   CHK(dalloc(&st->dsg_tmp, 2 * cap_nc));
-  dfree(st->zg); dfree(st->dz);
-  if (st->proj == GREST_PROJ_LOWRANK) {
-    CHK(dalloc((char**)&st->zg, (size_t)2 * cap_nc * st->D * st->es));
-    CHK(dalloc((char**)&st->dz, (size_t)2 * cap_nc * st->D * st->es));
-  }
   st->cap_nc = cap_nc;
-  return GREST_OK;
+  return alloc_gather_arrays(st);
 }
 
 grest_status alloc_sketch_arrays(grest_state* st, int64_t cap_s) {
@@ -379,6 +387,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
   dfree(st->srows); dfree(st->drows);
   CHK(alloc_node_arrays(st, cap));
+  CHK(alloc_gather_arrays(st));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
                         st->stream));
   HIPCHK(hipMemcpyAsync(st->sc[st->gcur], sc_old, st->n * st->es, hipMemcpyDeviceToDevice, st->stream));
