@@ -11,9 +11,11 @@ before the timed region, which contains exactly ``--steps`` updates bracketed by
 device synchronisations.
 
 Printed JSON line: the headline updates/s of the mixed-precision path, the plain
-FP32 path beside it, per-stage times, the roofline of the dominant kernel measured
-with HIP events around it, and the FP64 CPU oracle timed on one update of the same
-workload (``cpu_baseline``).
+FP32 path and the truncated low-rank form beside it, each with its accuracy gate
+(graph, Rayleigh quotients, orthonormality after the timed updates), per-stage times,
+the roofline of the dominant kernel measured with HIP events around it, the serving
+latencies of many graphs, and the FP64 CPU oracle timed on the first updates of the
+same workload (``cpu_baseline``, the only part that runs the oracle).
 """
 from __future__ import annotations
 
