@@ -150,12 +150,14 @@ grest_status grest_sync(grest_state* st);
  */
 grest_status grest_get(grest_state* st, double* values, void* X, int32_t x_dtype, int32_t where);
 
-/* Current node count, stored entries (both triangles) and the state's dimensions. */
+/* Current node count, stored entries (both triangles; -1 once the graph is released)
+ * and the state's dimensions.  Any output pointer may be NULL. */
 grest_status grest_shape(const grest_state* st, int64_t* n, int64_t* nnz, int32_t* k, int32_t* width);
 
 /*
  * Copy the stored graph to host memory: rowptr (n+1 int64) and col (nnz int32), for
- * checking the graph update bit for bit.
+ * checking the graph update bit for bit.  Waits for queued work.  EINVAL on a NULL state
+ * or one that released its graph.
  */
 grest_status grest_get_graph(grest_state* st, int64_t* rowptr, int32_t* col);
 
