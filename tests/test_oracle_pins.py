@@ -519,3 +519,35 @@ def test_drift_of_rotated_pair_is_sine_times_gap(op):
     expect = abs(np.sin(phi)) * abs(w[b] - w[keep[0]]) / scale
     assert orth <= 1e-13, orth
     assert abs(resid - expect) <= 1e-12 * max(1.0, expect), (resid, expect)
+
+
+# ------------------------------------------------------------------------------------
+# the truncated form (eq. RR_eigen_graph_upd_main3) against the exact one: when the old
+# adjacency has rank K and its K nonzero pairs are tracked exactly, A = Xbar Theta Xbar^T,
+# so both forms project the same matrix and must agree for any update
+# ------------------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", ["g2", "g3", "rsvd"])
+def test_lowrank_equals_exact_on_a_rank_k_graph(variant):
+    a, b = 5, 7  # complete bipartite K_{5,7}: rank 2, eigenvalues +-sqrt(35), the rest 0
+    n = a + b
+    Ad = np.zeros((n, n))
+    Ad[:a, a:] = 1.0
+    Ad[a:, :a] = 1.0
+    A = sp.csr_matrix(Ad)
+    w, V = np.linalg.eigh(Ad)
+    idx = np.argsort(-np.abs(w))[:2]
+    th0, X0 = w[idx], V[:, idx]
+    assert np.allclose(np.abs(th0), np.sqrt(a * b), atol=1e-12)
+    # an update: two appended nodes, one insertion inside a side, one deletion across
+    s_new = 2
+    ei = np.array([0, 1, 3, 6, 2], dtype=np.int64)
+    ej = np.array([1, 12, 13, 13, 9], dtype=np.int64)
+    sg = np.array([1, 1, 1, 1, -1], dtype=np.int8)
+    L = 2 if variant == "rsvd" else None
+    om = np.random.default_rng(3).standard_normal((s_new, 4)) if variant == "rsvd" else None
+    kw = dict(variant=variant, L=L, Omega=om)
+    ex = O.grest_step(A, X0, th0, s_new, ei, ej, sg, 2, proj=O.EXACT, **kw)
+    lr = O.grest_step(A, X0, th0, s_new, ei, ej, sg, 2, proj=O.LOWRANK, **kw)
+    assert np.allclose(lr.theta, ex.theta, atol=1e-12, rtol=0), (lr.theta, ex.theta)
+    # same Ritz subspace (signs aside)
+    assert np.abs(np.abs(np.diag(lr.X.T @ ex.X)) - 1.0).max() <= 1e-10
