@@ -16,6 +16,13 @@
  *   - shifted Laplacians, Sec. 4.2: the trailing pairs of L = D - A and of
  *     L_n = I - D^{-1/2} A D^{-1/2} are the leading pairs of alpha I - L and 2 I - L_n.
  *
+ * Groups of entry points: a state's life (create, set or init pairs, update, sync,
+ * get, shape, destroy); the truncated projection of eq. RR_eigen_graph_upd_main3 with a
+ * released graph (GREST_PROJ_LOWRANK, grest_release_graph); drift and recomputation
+ * (grest_drift, grest_set_restart); checkpoint, resume and the borrowed view (grest_save,
+ * grest_load, grest_view); streams, overlap, memory and stage timing; and the server
+ * that runs many graphs' updates together (grest_server_*, grest_submit, grest_poll).
+ *
  * Conventions shared by every entry point:
  *   - All functions return a grest_status; no exception crosses the interface.
  *   - Node ids are int32 (graphs below 2^31 nodes); each undirected edge change is
