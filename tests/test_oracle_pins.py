@@ -10,6 +10,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 from oracle import grest_oracle as O
@@ -196,6 +197,72 @@ def test_rsvd_truncates_when_rank_exceeds_L():
     rr = O.grest_step(A, X0, th0, 12, ei, ej, sg, k, variant=O.RSVD, L=L, Omega=Om)
     r3 = O.grest_step(A, X0, th0, 12, ei, ej, sg, k, variant=O.G3)
     assert rr.Z.shape[1] <= 2 * k + L < r3.Z.shape[1]
+
+
+def _rsvd_truncation_case(seed):
+    """An update whose projected trailing block has rank r with L < r < L + P, and the
+    dense leading-L left singular subspace of that block computed directly."""
+    A, ei, ej, sg = random_case(seed, n=80, s=8, p=0.08, n_ins=6, n_del=4)
+    k, L, P, s = 4, 3, 8, 8
+    n = A.shape[0]
+    _, X0, _ = O.leading_eigenpairs(A, k)
+    Xb = np.vstack([X0, np.zeros((s, k))])
+    # Delta_2 straight from the change list: the appended nodes' columns of Delta
+    D2 = np.zeros((n + s, s))
+    for a, b, g in zip(ei, ej, sg):
+        if b >= n:
+            D2[a, b - n] += g
+            if a >= n:
+                D2[b, a - n] += g
+    P_perp = np.eye(n + s) - Xb @ Xb.T
+    # SciPy's SVD (not NumPy's, which the planted-mistake tests replace inside the oracle)
+    U, sig, _ = sla.svd(P_perp @ D2, full_matrices=False)
+    r = int(np.count_nonzero(sig > 1e-10 * sig[0]))
+    Om = np.random.default_rng(500 + seed).standard_normal((s, L + P))
+    return A, Xb, ei, ej, sg, n, s, L, P, U[:, :L], sig, r, Om
+
+
+def _rsvd_truncation_sine(seed):
+    A, Xb, ei, ej, sg, n, s, L, P, UL, sig, r, Om = _rsvd_truncation_case(seed)
+    D = O.assemble_delta(A, s, ei, ej, sg)
+    _, DT, _, _ = O.operator_delta(A, O.updated_adjacency(A, D), O.ADJ)
+    R = O.rsvd_basis(Xb, DT[:, n:].tocsr(), Om, L)
+    if R.shape[1] != L:
+        return np.inf
+    # sine of the largest principal angle = ||U_L U_L^T - R R^T||_2 for orthonormal blocks
+    return float(np.linalg.norm(UL @ UL.T - R @ R.T, 2))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rsvd_truncation_keeps_leading_left_singular_subspace(seed):
+    """Sec. 3.5, S.2-S.4: when L < rank((I - Pi) Delta_2) < L + P the Gaussian sketch spans
+    the whole range (probability 1), so M U_L is exactly the span of the L leading left
+    singular vectors of the dense (I - Pi) Delta_2."""
+    _, _, _, _, _, _, _, L, P, _, sig, r, _ = _rsvd_truncation_case(seed)
+    assert L < r < L + P
+    assert (sig[L - 1] - sig[L]) / sig[0] > 0.02  # a gap that makes the subspace well defined
+    assert _rsvd_truncation_sine(seed) < 1e-12
+
+
+def test_planted_trailing_singular_vectors_are_caught(monkeypatch):
+    real = np.linalg.svd
+
+    def trailing_first(a, full_matrices=True, compute_uv=True, **kw):
+        U, s, Vt = real(a, full_matrices=full_matrices, compute_uv=True, **kw)
+        return U[:, ::-1], s[::-1], Vt[::-1]
+    assert _rsvd_truncation_sine(1) < 1e-12
+    monkeypatch.setattr(O.np.linalg, "svd", trailing_first)
+    assert _rsvd_truncation_sine(1) > 1e-3
+
+
+def test_planted_right_for_left_singular_vectors_is_caught(monkeypatch):
+    real = np.linalg.svd
+
+    def right_for_left(a, full_matrices=True, compute_uv=True, **kw):
+        U, s, Vt = real(a, full_matrices=full_matrices, compute_uv=True, **kw)
+        return Vt.T[: U.shape[0], : U.shape[1]], s, Vt
+    monkeypatch.setattr(O.np.linalg, "svd", right_for_left)
+    assert _rsvd_truncation_sine(1) > 1e-3
 
 
 # ------------------------------------------------------------------------------------
