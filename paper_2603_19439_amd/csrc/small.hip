@@ -23,49 +23,6 @@
 
 #include <math.h>
 
-// Optional phase clocks for profiling builds (-DGREST_PHASE_CLOCKS): thread 0 records the
-// 100 MHz wall clock at phase boundaries of the pivoted Cholesky.
-#ifdef GREST_PHASE_CLOCKS
-__device__ long long g_phase_clk[64];
-#define PHASE_MARK(slot)                                  \
-  do {                                                    \
-    __syncthreads();                                      \
-    if (threadIdx.x == 0) g_phase_clk[slot] = wall_clock64(); \
-  } while (0)
-extern "C" int grest_debug_phase_clocks(long long* out, int n) {
-  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_clk), sizeof(long long) * (n < 64 ? n : 64));
-}
-// the last inverse-iteration breakdown: [n, cur, lam, tnorm, nrm2, it, nmem, which, dg[128], od[128], ev[128]]
-__device__ double g_dbg_eig[8 + 3 * 128];
-extern "C" int grest_debug_eig(double* out) {
-  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(g_dbg_eig), sizeof(double) * (8 + 3 * 128));
-}
-// per-section cycle accounting inside a loop (threads 0 and 64 only)
-#define SECT_DECL long long sect_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sect_t = clock64();
-#define SECT(i)                                  \
-  do {                                           \
-    const long long t_ = clock64();              \
-    sect_acc[i] += t_ - sect_t;                  \
-    sect_t = t_;                                 \
-  } while (0)
-#define SECT_WRITE(base)                                                        \
-  do {                                                                          \
-    if (threadIdx.x == 0 || threadIdx.x == 64)                                  \
-      for (int i_ = 0; i_ < 8; ++i_) g_phase_clk[(base) + (threadIdx.x ? 8 : 0) + i_] = sect_acc[i_]; \
-  } while (0)
-#else
-#define PHASE_MARK(slot) \
-  do {                   \
-  } while (0)
-#define SECT_DECL
-#define SECT(i) \
-  do {          \
-  } while (0)
-#define SECT_WRITE(base) \
-  do {                   \
-  } while (0)
-#endif
-
 namespace {
 
 constexpr int TRI_WAVES = 8;  // waves of the tridiagonalisation workgroup (two per SIMD)
@@ -203,7 +160,6 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
   const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid / GREST_WAVE);
 
-  PHASE_MARK(9);
   for (int j = tid; j < M; j += EB) iperm[j] = -1;
   if (CL) {
     for (int idx = tid; idx < kc * m; idx += EB) cdyn[idx] = Cg[idx];
@@ -244,8 +200,6 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
   const double thr = tol * tol * fmax(1.0, wave_max_d(mx));
   __syncthreads();
 
-  PHASE_MARK(10);
-  SECT_DECL
   uint64_t ch0 = 0, ch1 = 0;
   int r = 0;
   for (int k = 0; k < m; ++k) {
@@ -262,15 +216,12 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
     if (!(best > 0.0)) break;
     const int p = 127 - (int)(__double_as_longlong(best) & 0x7F);
     const double piv = vec_elem<CC>(d, p);
-    SECT(0);
     if (!(piv > thr)) break;  // also stops on NaN
     if (p < 64) ch0 |= 1ull << p; else ch1 |= 1ull << (p - 64);
     double* rowk = Rrow + k * LP;
     column_to_lds<RW, CC, NW>(S, p, wv, m, rowk);
     if (tid == 0) { perm[k] = p; iperm[p] = k; rdg[k] = piv; }  // square roots after the loop
-    SECT(1);
     __syncthreads();
-    SECT(2);
     double rp[CC];
 #pragma unroll
     for (int c = 0; c < CC; ++c) {
@@ -291,10 +242,7 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
 #pragma unroll
     for (int c = 0; c < CC; ++c) d[c] = fma(-(rp[c] * ip), rp[c], d[c]);
     r = k + 1;
-    SECT(3);
   }
-  SECT_WRITE(40);
-  PHASE_MARK(11);
   // X = R^{-1}, R[a][b] = Rrow[a][perm[b]] / sqrt(piv_a) (upper triangular in pivot
   // order).  Column j of X is an independent solve: for i descending, X[i][j] /= R[i][i],
   // then X[a][j] -= R[a][i] X[i][j] for a < i.
@@ -341,7 +289,6 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
         for (int t = lane; t < m; t += GREST_WAVE) Mblk[(size_t)j * m + t] = 0.0;
     }
   }
-  PHASE_MARK(13);
   __syncthreads();
   // -C M = -(C P) X: wave w takes rows l = l0 + 8 w + t of C (t < 8), lanes the columns;
   // X[a][j] is zero for a > j, so the sum runs over every a < r
@@ -374,7 +321,6 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
       }
   }
   if (tid == 0) *rank_out = r;
-  PHASE_MARK(12);
 }
 
 // ------------------------------------------------------------------------------------
@@ -410,7 +356,6 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
   extern __shared__ double Cs[];  // C (kc x m)
   const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1), wv = tid / GREST_WAVE;
   const int ty = tid >> 4, tx = tid & 15;
-  if (m == CNP_M) PHASE_MARK(2);
   if (tid == 0) s_bad = 0;
   for (int idx = tid; idx < kc * m; idx += CNP_T) Cs[idx] = Cg[idx];
   __syncthreads();
@@ -472,7 +417,6 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
   // in the order and rounding of two single steps.  Row j + 1's final values (its factor
   // row) stay in the registers of its owners and go to LDS after the loop: no later step
   // changes them, and writing them during the pair would race with its readers.
-  if (m == CNP_M) PHASE_MARK(3);
   int r = m;
   for (int j = 0; j < m; j += 2) {
     const double* r0 = Rr + j * CNP_P;
@@ -525,7 +469,6 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
   }
   __syncthreads();
   // valid only if every diagonal entry left is at most thr
-  if (m == CNP_M) PHASE_MARK(4);
   for (int j = tid; j < r; j += CNP_T) rdi[j] = 1.0 / sqrt(Rr[j * CNP_P + j]);
   bool ok = true;
 #pragma unroll
@@ -603,7 +546,6 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
   }
   __syncthreads();
   // output: rows of -C M, then M (zero outside the leading r x r upper triangle)
-  if (m == CNP_M) PHASE_MARK(5);
   double* Mblk = Mout + (size_t)kc * m;
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
@@ -650,7 +592,6 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
     *rank_out = r;
     *done = 1;
   }
-  if (m == CNP_M) PHASE_MARK(6);
 }
 
 // ------------------------------------------------------------------------------------
@@ -723,8 +664,6 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
     const int j = lane + GREST_WAVE * c;
     colk[c] = j < n ? colb[1][j] : 0.0;
   }
-  PHASE_MARK(0);
-  SECT_DECL
 
   for (int k = 0; k + 2 < n; ++k) {
     const int pb = k & 1;
@@ -746,7 +685,6 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
       ek = mu;
     }
     const double inv = recip(v0);
-    SECT(0);
     double v[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -780,9 +718,7 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
     }
     // column k+1 before this reflection, for the next reflector
     column_to_lds<RW, C, NW>(A, k + 1, wv, n, colb[pb]);
-    SECT(1);
     __syncthreads();  // the only barrier of the step (buffers alternate with k)
-    SECT(2);
     if (beta != 0.0) {
       double w[C];  // first p = beta A v, then w = p - K v
       double pv = 0.0;
@@ -802,7 +738,6 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
         vwb[wv][1][lane + GREST_WAVE * c] = w[c];
       }
       wave_lds_fence();
-      SECT(3);
       double wr[RW];
 #pragma unroll
       for (int r = 0; r < RW; ++r) wr[r] = vwb[wv][1][wv + NW * r];
@@ -825,10 +760,7 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
         colk[c] = j < n ? colb[pb][j] : 0.0;
       }
     }
-    SECT(4);
   }
-  SECT_WRITE(20);
-  PHASE_MARK(1);
   // the last two diagonal entries and the last off-diagonal one: column n-2 is colk, then
   // column n-1 is gathered
   __syncthreads();  // every read of colb in the loop is done
@@ -876,7 +808,6 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
       work[W_HDR + 6] = (double)seg2;
     }
   }
-  PHASE_MARK(2);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1084,13 +1015,6 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
       double s = (nrm2 > 0.0 && isfinite(nrm2)) ? 1.0 / sqrt(nrm2) : 0.0;
       if (s == 0.0) {  // breakdown: fall back to the unit vector of the index
         if (lane == 0) atomicOr(status, ST_NOT_CONVERGED);
-#ifdef GREST_PHASE_CLOCKS
-        if (lane == 0) {
-          g_dbg_eig[0] = n; g_dbg_eig[1] = cur; g_dbg_eig[2] = lam; g_dbg_eig[3] = tnorm;
-          g_dbg_eig[4] = nrm2; g_dbg_eig[5] = it; g_dbg_eig[6] = nmem; g_dbg_eig[7] = which;
-          for (int q = 0; q < n; ++q) { g_dbg_eig[8 + q] = sdg[q]; g_dbg_eig[136 + q] = sod[q]; g_dbg_eig[264 + q] = sev[q]; }
-        }
-#endif
         y0 = (lane == cur) ? 1.0 : 0.0;
         y1 = (lane + GREST_WAVE == cur) ? 1.0 : 0.0;
         s = 1.0;
