@@ -147,6 +147,30 @@ grest_status grest_init_pairs(grest_state* st, int32_t iterations, uint64_t seed
 grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei,
                           const int32_t* ej, const int8_t* sign, const double* omega, int32_t where);
 
+/*
+ * The same update as grest_update, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): it calls
+ * no hipMalloc, hipFree or allocating library routine.  Arguments, validation and results
+ * are those of grest_update (bitwise the same results, by the same kernels), except:
+ *   - nothing grows: the update must fit the state's current capacities (node count,
+ *     stored entries, appended nodes of the sketch, the low-rank gather rows), which
+ *     grest_create's node_capacity / nnz_capacity or earlier grest_update calls set;
+ *   - n_changes <= 262,144 (2^18).  The buffers sized by the change list (its device
+ *     copy, Delta's packed keys, their radix sort, the merge ranks, Delta's columns and
+ *     signs) live in one static device array of 28 MiB that every device the library
+ *     runs on holds until the process ends;
+ *   - the change list's format is checked on the device only (the state is still left
+ *     unchanged by a violation, with GREST_EINVAL);
+ *   - the restart policy of grest_set_restart is not applied by this call.
+ * A size beyond these limits returns GREST_EINVAL (grest_last_error names the limit) with
+ * nothing queued.  Every call on one device shares that device's array, which keeps the
+ * last call's contents: calls that overlap on one device race, so before a no-allocation
+ * update of another state on the same device, wait for the previous one (grest_sync).
+ * A state's own successive calls are ordered by its streams and do not race.
+ */
+grest_status grest_update_noalloc(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei,
+                                  const int32_t* ej, const int8_t* sign, const double* omega, int32_t where);
+
 /* Wait for queued work and return (then clear) deferred numerical status bits. */
 grest_status grest_sync(grest_state* st);
 

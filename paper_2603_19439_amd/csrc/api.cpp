@@ -599,16 +599,49 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   return GREST_OK;
 }
 
+// The buffers an update sizes by its change list: the device copies of the change arrays,
+// the packed keys of Delta before and after the sort, the sort's temporary storage, the
+// insertion ranks of the merge, the unsorted signs and the two slots of Delta's columns
+// and signs.  grest_update uses the state's own (grown on demand), grest_update_noalloc
+// those carved from the static device workspace.
+struct ChangeBufs {
+  int32_t *ei = nullptr, *ej = nullptr;
+  int8_t* sg = nullptr;
+  uint64_t *kin = nullptr, *kout = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_bytes = 0;
+  int32_t* dcol[2] = {nullptr, nullptr};
+  int8_t* dsg[2] = {nullptr, nullptr};
+  int32_t* dins = nullptr;
+  int8_t* sg_tmp = nullptr;
+};
+
+ChangeBufs state_change_bufs(const grest_state* st) {
+  ChangeBufs b;
+  b.ei = st->d_ei; b.ej = st->d_ej; b.sg = st->d_sg;
+  b.kin = st->dkey_in; b.kout = st->dkey_out;
+  b.sort_tmp = st->sort_tmp; b.sort_bytes = st->sort_tmp_bytes;
+  for (int k = 0; k < 2; ++k) { b.dcol[k] = st->dcol[k]; b.dsg[k] = st->dsg[k]; }
+  b.dins = st->dins; b.sg_tmp = st->dsg_tmp;
+  return b;
+}
+
+// With ext the change-list buffers come from ext and nothing is allocated: the caller has
+// checked every capacity the update needs.
 template <typename T>
 grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* ei, const int32_t* ej,
-                         const int8_t* sg, const double* omega, int32_t where) {
+                         const int8_t* sg, const double* omega, int32_t where, const ChangeBufs* ext = nullptr) {
   hipStream_t s = st->stream;
   const int64_t n = st->n, n2 = n + S;
   // capacities
-  if (n2 > st->cap_n) CHK(grow_nodes(st, n2));
-  if (!st->graph_free && st->m + 2 * nc > st->cap_m) CHK(grow_edges(st, st->m + 2 * nc));
-  if (nc > st->cap_nc) CHK(alloc_change_arrays(st, std::max<int64_t>(nc, st->cap_nc * 2)));
-  if (st->variant == GREST_RSVD && S > st->cap_s) CHK(alloc_sketch_arrays(st, std::max<int64_t>(S, 2 * st->cap_s)));
+  if (!ext) {
+    if (n2 > st->cap_n) CHK(grow_nodes(st, n2));
+    if (!st->graph_free && st->m + 2 * nc > st->cap_m) CHK(grow_edges(st, st->m + 2 * nc));
+    if (nc > st->cap_nc) CHK(alloc_change_arrays(st, std::max<int64_t>(nc, st->cap_nc * 2)));
+    if (st->variant == GREST_RSVD && S > st->cap_s)
+      CHK(alloc_sketch_arrays(st, std::max<int64_t>(S, 2 * st->cap_s)));
+  }
+  const ChangeBufs cb = ext ? *ext : state_change_bufs(st);
   // reuse of the kept A X (adjacency), with a full-width product every kAxRefresh updates
   // so that the rounding carried along by the recurrence stays bounded
   constexpr int kAxRefresh = 16;
@@ -638,14 +671,14 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   const int32_t* dej = ej;
   const int8_t* dsgn = sg;
   if (where == GREST_HOST && nc > 0) {
-    HIPCHK(hipMemcpyAsync(st->d_ei, ei, nc * sizeof(int32_t), hipMemcpyHostToDevice, gs));
-    HIPCHK(hipMemcpyAsync(st->d_ej, ej, nc * sizeof(int32_t), hipMemcpyHostToDevice, gs));
-    HIPCHK(hipMemcpyAsync(st->d_sg, sg, nc * sizeof(int8_t), hipMemcpyHostToDevice, gs));
-    dei = st->d_ei; dej = st->d_ej; dsgn = st->d_sg;
+    HIPCHK(hipMemcpyAsync(cb.ei, ei, nc * sizeof(int32_t), hipMemcpyHostToDevice, gs));
+    HIPCHK(hipMemcpyAsync(cb.ej, ej, nc * sizeof(int32_t), hipMemcpyHostToDevice, gs));
+    HIPCHK(hipMemcpyAsync(cb.sg, sg, nc * sizeof(int8_t), hipMemcpyHostToDevice, gs));
+    dei = cb.ei; dej = cb.ej; dsgn = cb.sg;
   }
   int64_t* dptr = st->dptr[ds];
-  int32_t* dcol = st->dcol[ds];
-  int8_t* dsg = st->dsg[ds];
+  int32_t* dcol = cb.dcol[ds];
+  int8_t* dsg = cb.dsg[ds];
   int64_t* maxdeg = st->maxdeg[gn];
   st->marking = st->prof;
   mark(st, 0);
@@ -653,16 +686,15 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   launch_fill_bytes0(maxdeg, sizeof(int64_t), gs);
   launch_fill_i64(st->dcnt, 0, n2 + 1, gs);
   const int kshift = delta_key_shift(n2);
-  launch_delta_keys(dei, dej, dsgn, nc, n, S, kshift, st->dkey_in, st->dsg_tmp, st->dcnt, st->vstat[ds], gs);
+  launch_delta_keys(dei, dej, dsgn, nc, n, S, kshift, cb.kin, cb.sg_tmp, st->dcnt, st->vstat[ds], gs);
   launch_scan_excl(st->dcnt, dptr, n2, st->scan_tmp, gs);
-  if (!launch_delta_sort(st->dkey_in, st->dkey_out, st->dsg_tmp, dsg, 2 * nc, 2 * kshift, st->sort_tmp,
-                         st->sort_tmp_bytes, gs)) {
+  if (!launch_delta_sort(cb.kin, cb.kout, cb.sg_tmp, dsg, 2 * nc, 2 * kshift, cb.sort_tmp, cb.sort_bytes, gs)) {
     snprintf(g_last_error, sizeof(g_last_error), "radix sort of the update could not be launched");
     return GREST_EDEVICE;
   }
-  launch_delta_extract(st->dkey_out, 2 * nc, dptr + n2, kshift, dcol, gs);
+  launch_delta_extract(cb.kout, 2 * nc, dptr + n2, kshift, dcol, gs);
   const bool gfree = st->graph_free;
-  launch_delta_rows(n, S, dptr, dcol, dsg, st->dins, gfree ? nullptr : st->rp[st->gcur],
+  launch_delta_rows(n, S, dptr, dcol, dsg, cb.dins, gfree ? nullptr : st->rp[st->gcur],
                     gfree ? nullptr : st->col[st->gcur], st->newlen, st->vstat[ds], gs);
   if (!gfree) {
     launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, gs);
@@ -710,7 +742,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   if (sparse_dx || lowrank)
     launch_delta1_rows(n, S, dptr, dcol, st->dflag, st->dpos, st->dscan_tmp, st->drows, gs);
   if (!gfree)
-    launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, st->dins, st->rp[gn], st->col[gn],
+    launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, cb.dins, st->rp[gn], st->col[gn],
                      st->cap_m, gs);
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].vstatus, st->vstat[ds], sizeof(int32_t), hipMemcpyDeviceToHost, gs));
   if (!gfree)
@@ -1256,6 +1288,73 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
     return st->es == 8 ? init_impl<double>(st, st->rs_iters, seed) : init_impl<float>(st, st->rs_iters, seed);
   }
   return GREST_OK;
+}
+
+// The change-list buffers of grest_update_noalloc carved out of the static device
+// workspace (fixed layout for kNoAllocMaxChanges changes, 256-byte aligned pieces; the
+// radix sort's temporary storage takes the rest).  False if the layout does not fit.
+bool noalloc_bufs(void* base, ChangeBufs* b) {
+  const int64_t nc = kNoAllocMaxChanges;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = (char*)base + off;
+    off += (bytes + 255) & ~size_t(255);
+    return (void*)p;
+  };
+  b->ei = (int32_t*)take(nc * sizeof(int32_t));
+  b->ej = (int32_t*)take(nc * sizeof(int32_t));
+  b->sg = (int8_t*)take(nc);
+  b->kin = (uint64_t*)take(2 * nc * sizeof(uint64_t));
+  b->kout = (uint64_t*)take(2 * nc * sizeof(uint64_t));
+  for (int k = 0; k < 2; ++k) {
+    b->dcol[k] = (int32_t*)take(2 * nc * sizeof(int32_t));
+    b->dsg[k] = (int8_t*)take(2 * nc);
+  }
+  b->dins = (int32_t*)take(2 * nc * sizeof(int32_t));
+  b->sg_tmp = (int8_t*)take(2 * nc);
+  if (off >= kNoAllocScratchBytes) return false;
+  b->sort_tmp = (char*)base + off;
+  b->sort_bytes = kNoAllocScratchBytes - off;
+  return true;
+}
+
+grest_status grest_update_noalloc(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei,
+                                  const int32_t* ej, const int8_t* sign, const double* omega, int32_t where) {
+  if (!st || !st->has_pairs) return GREST_EINVAL;
+  if (n_new < 0 || n_changes < 0) return GREST_EINVAL;
+  if (st->n + n_new >= INT32_MAX) return GREST_EINVAL;
+  if (n_changes > 0 && (!ei || !ej || !sign)) return GREST_EINVAL;
+  if (st->variant == GREST_G3 && n_new > st->cfg.max_new) return GREST_EINVAL;
+  if (st->variant == GREST_RSVD && n_new > 0 && !omega) return GREST_EINVAL;
+  if (where != GREST_HOST && where != GREST_DEVICE) return GREST_EINVAL;
+  // nothing may grow: every size the update needs must fit what is already allocated
+  auto refuse = [](const char* what) {
+    snprintf(g_last_error, sizeof(g_last_error), "grest_update_noalloc: %s", what);
+    return GREST_EINVAL;
+  };
+  const int64_t n2 = st->n + n_new;
+  if (n_changes > kNoAllocMaxChanges) return refuse("change list longer than the workspace's maximum");
+  if (n2 > st->cap_n) return refuse("node count beyond the state's node capacity");
+  if (!st->graph_free && st->m + 2 * n_changes > st->cap_m)
+    return refuse("stored entries beyond the state's entry capacity");
+  if (st->variant == GREST_RSVD && n_new > st->cap_s)
+    return refuse("appended nodes beyond the state's sketch capacity");
+  if (st->proj == GREST_PROJ_LOWRANK &&
+      std::min<int64_t>(n2, 2 * n_changes) > std::max<int64_t>(1, std::min<int64_t>(2 * st->cap_nc, st->cap_n)))
+    return refuse("rows of Delta beyond the low-rank gather capacity");
+  // the format of the change list is checked on the device alone (the host check sorts a
+  // copy of the keys, which would allocate); a violation still leaves the state unchanged
+  void* base = nullptr;
+  const hipError_t e = noalloc_scratch(st->device, &base);
+  if (e != hipSuccess) {
+    set_err("hipGetSymbolAddress of the no-allocation workspace", e);
+    return GREST_EDEVICE;
+  }
+  ChangeBufs cb;
+  if (!noalloc_bufs(base, &cb)) return refuse("workspace layout does not fit");
+  if (delta_sort_temp_bytes(2 * n_changes) > cb.sort_bytes) return refuse("sort storage beyond the workspace");
+  return st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where, &cb)
+                     : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where, &cb);
 }
 
 grest_status grest_drift(grest_state* st, double* orth, double* resid) {

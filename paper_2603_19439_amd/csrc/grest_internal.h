@@ -205,6 +205,16 @@ void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double
                   hipStream_t s);
 
 // ------------------------------------------------------------------------------------
+// noalloc.hip: the static workspace of the update that allocates nothing
+// ------------------------------------------------------------------------------------
+// largest change list of one grest_update_noalloc call, and the size of the device array
+// that holds its change-list buffers (per device, for the life of the process)
+constexpr int64_t kNoAllocMaxChanges = int64_t(1) << 18;
+constexpr size_t kNoAllocScratchBytes = size_t(28) << 20;
+// device address of that array on `device` (looked up once per device)
+hipError_t noalloc_scratch(int device, void** out);
+
+// ------------------------------------------------------------------------------------
 // api.cpp: state accessors used by the server
 // ------------------------------------------------------------------------------------
 struct grest_state;

@@ -50,6 +50,8 @@ _SIGS = [
     ("grest_init_pairs", C.c_int, [C.c_void_p, C.c_int32, C.c_uint64]),
     ("grest_update", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int32]),
+    ("grest_update_noalloc", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_int32]),
     ("grest_sync", C.c_int, [C.c_void_p]),
     ("grest_get", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
     ("grest_shape", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -211,7 +213,9 @@ class State:
     def init_pairs(self, iterations: int = 30, seed: int = 0):
         _check(lib().grest_init_pairs(self._h, int(iterations), int(seed)), "grest_init_pairs")
 
-    def update(self, n_new: int, i, j, sign, omega=None):
+    def update(self, n_new: int, i, j, sign, omega=None, noalloc: bool = False):
+        """One update (grest_update); noalloc=True calls grest_update_noalloc, which
+        allocates nothing and needs the state's capacities to suffice."""
         ai, pi, w1 = _ptr(i, np.int32)
         aj, pj, w2 = _ptr(j, np.int32)
         asg, ps, w3 = _ptr(sign, np.int8)
@@ -220,11 +224,12 @@ class State:
         where = w1
         if omega is not None and w4 != where:
             raise ValueError("omega must live where the change arrays live")
-        _check(lib().grest_update(self._h, int(n_new), nc, pi, pj, ps, po, where), "grest_update")
+        name = "grest_update_noalloc" if noalloc else "grest_update"
+        _check(getattr(lib(), name)(self._h, int(n_new), nc, pi, pj, ps, po, where), name)
         self._keep = (ai, aj, asg, ao)
 
-    def update_delta(self, d, omega=None):
-        return self.update(d.n_new, d.i, d.j, d.sign, omega)
+    def update_delta(self, d, omega=None, noalloc: bool = False):
+        return self.update(d.n_new, d.i, d.j, d.sign, omega, noalloc=noalloc)
 
     def sync(self):
         _check(lib().grest_sync(self._h), "grest_sync")
