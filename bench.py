@@ -52,10 +52,11 @@ CONFIGS = {
                compare="mixed", lowrank=False, serving=0, oracle_steps=4,
                workload="Chung-Lu n0=1e5, pdf exponent 2.5, mean degree 16, max 2000; +0.5%/-0.2% edges per "
                         "step; normalised Laplacian (2I - L_n), k=32 smallest, G-REST2 (S=0), FP32"),
-    "c5": dict(preset="chunglu_n4e6", op="lap", k=64, variant="g2", L=0, P=0, max_new=0, precision="mixed",
+    "c5": dict(preset="chunglu_n4e6", op="lap", k=65, variant="rsvd", L=64, P=64, max_new=0, precision="mixed",
                compare="", lowrank=False, serving=0, oracle_steps=1,
                workload="Chung-Lu n0=4e6, pdf exponent 2.2, mean degree 16; +1% nodes per step; combinatorial "
-                        "Laplacian (alpha I - L), k=64 smallest, G-REST2 (width 128), mixed"),
+                        "Laplacian (alpha I - L), k=65 smallest (64 non-trivial), G-REST_RSVD L=P=64 (width 194), "
+                        "mixed"),
 }
 
 
@@ -71,7 +72,8 @@ def parse():
     ap.add_argument("--no-lowrank", action="store_true",
                     help="skip timing the low-rank projected matrix (eq. ..._main3) beside the headline")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink node counts (quick runs only)")
-    ap.add_argument("--init-iters", type=int, default=40)
+    ap.add_argument("--init-iters", type=int, default=300,
+                    help="product budget of the device's initial eigensolver (it stops earlier on its residual)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run each update's graph stage on the state's stream (no second stream)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -297,7 +299,7 @@ def main():
         st = G.State(wl.rowptr0, wl.col0, k=K, variant=variant, op=op, precision=prec, L=L, P=P,
                      max_new=cfg["max_new"], stream=torch.cuda.current_stream().cuda_stream,
                      node_capacity=n_final + 1, nnz_capacity=nnz_cap, proj=proj)
-        st.init_pairs(iterations=args.init_iters, seed=7)
+        init_stats.append(st.init_pairs(iterations=args.init_iters, seed=7))
         start = st.get()
         if proj == "lowrank":  # the low-rank form needs Delta and the pairs only
             st.release_graph()
@@ -305,6 +307,7 @@ def main():
         return st, start
 
     final_graph = {}
+    init_stats = []  # (products, residual) of every initial eigensolve
 
     def final_checks(st, prec, lowrank):
         """Properties of a timed state after its updates that hold for any Rayleigh-Ritz
@@ -365,6 +368,7 @@ def main():
         st.close()
         # 3. timed updates on a fresh state
         st, _ = make_state(prec, proj)
+        init = init_stats[-1]
         st.profile(2)
         sizes = []
         torch.cuda.synchronize()
@@ -388,7 +392,8 @@ def main():
         byts = sum(spmm_bytes(n2, nnz, width, elem) for n2, nnz, _ in sizes) if width > 0 else 0.0
         return {"seconds": te - ts, "stages_ms": stages, "stage_updates": stage_n, "spmm_ms": spmm_ms, "updates": nupd,
                 "spmm_bytes": byts, "spmm_width": width, "sizes": sizes, "lambda1": float(vals[0]),
-                "state_gib": dev_bytes / 2**30, "final": checks, "acc_start": acc_start, "acc_outs": acc_outs}
+                "state_gib": dev_bytes / 2**30, "final": checks, "acc_start": acc_start, "acc_outs": acc_outs,
+                "init": init}
 
     log(args, f"timing {args.precision} path: warmup {args.warmup}, steps {args.steps}")
     main_res = run_path(args.precision)
@@ -459,6 +464,10 @@ def main():
         "accuracy": accuracy(main_res, args.precision),
         "stages_ms_per_update": {k: round(v / max(1, main_res["stage_updates"]), 4) for k, v in stages.items()},
         "stages_note": "HIP events around every stage, from the untimed warm-up updates",
+        "initial_pairs": {"method": "device Chebyshev-filtered block iteration with a residual stop",
+                          "products": main_res["init"][0], "residual": main_res["init"][1],
+                          "residual_note": "max_j ||M x_j - lambda_j x_j|| / max_j |lambda_j| of the timed state's "
+                                           "initial pairs"},
         "dominant_stage": dominant,
         "roofline": {"kernel": "spmm (product with the updated operator)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -115,6 +115,9 @@ grest_status grest_validate_changes(int64_t n, int64_t n_new, int64_t n_changes,
  * room for growth (0 = automatic; buffers grow on demand with a device
  * synchronisation).  stream: a hipStream_t of that device, or NULL for a private
  * stream.  The tracked pairs are unset until grest_set_pairs or grest_init_pairs.
+ * Widths: 1 <= k <= 128 and k < n0; the basis width D = k + Dw with Dw = k (G-REST2),
+ * k + max_new (G-REST3) or k + L (RSVD) is at most 196; every block orthonormalised by
+ * CholQR2 is at most 128 wide (G-REST2/3: Dw; RSVD: k and L + P).  Otherwise GREST_EINVAL.
  */
 grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, const int64_t* rowptr,
                           const int32_t* col, int64_t node_capacity, int64_t nnz_capacity,
@@ -128,11 +131,31 @@ grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, con
 grest_status grest_set_pairs(grest_state* st, const double* values, const double* X, int32_t where);
 
 /*
- * Compute initial pairs on the device (Alg. 2 line 3 with a block subspace iteration
- * of width 2k built from the update kernels: product with the operator, CholQR2,
- * Rayleigh-Ritz).  iterations: number of products (>= 1); seed: start block.
+ * Compute initial pairs on the device (Alg. 2 line 3; the paper allows any direct
+ * eigendecomposition method): a Chebyshev-filtered block subspace iteration built from the
+ * update kernels.  The block has min(width, 128, n) columns (width = the basis width of
+ * the state, K + Dw); after a random start orthonormalised by CholQR2, every outer step
+ * runs Rayleigh-Ritz on the block (FP64 small eigensolve of all its pairs), measures
+ * resid = max_{j < k} ||M x_j - lambda_j x_j||_2 / scale (M and scale as for grest_drift),
+ * and, unless resid <= tol or the budget is spent, applies the Chebyshev polynomial of
+ * the operator that damps the interval of the unwanted spectrum (its degree bounded so
+ * that the filtered block stays well conditioned, at most 16) followed by CholQR2.
+ * iterations: largest number of products with the operator (>= 1); seed: start block.
+ * grest_init_pairs uses the precision's default tolerance (1e-12 with FP64 blocks, 4e-6
+ * otherwise); grest_init_pairs_tol takes tol (>= 0; 0 runs the whole budget) and returns
+ * the products used and the final resid (either pointer may be NULL).  The pairs of the
+ * last Rayleigh-Ritz step are kept whether or not tol was reached; GREST_ENUMERIC on a
+ * non-finite value.  EINVAL on a NULL state, iterations < 1, a negative or NaN tol or a
+ * state without its graph.
  */
 grest_status grest_init_pairs(grest_state* st, int32_t iterations, uint64_t seed);
+grest_status grest_init_pairs_tol(grest_state* st, int32_t max_products, double tol, uint64_t seed,
+                                  int32_t* products, double* resid);
+
+/* Products with the operator and final residual of the state's last initial eigensolve
+ * (grest_init_pairs, grest_init_pairs_tol or a restart); 0 and -1 before the first.
+ * Either pointer may be NULL.  EINVAL on a NULL state. */
+grest_status grest_init_stats(const grest_state* st, int32_t* products, double* resid);
 
 /*
  * One G-REST update (Alg. 2 loop body) with n_new appended nodes and n_changes edge
@@ -319,9 +342,14 @@ grest_status grest_memory(const grest_state* st, int64_t* device_bytes);
  * same reduction orders whatever else is queued, so its result does not depend on the
  * mix of graphs.
  *
- * Admission: attach fails with GREST_EAGAIN when the device memory of the attached
- * states would exceed hbm_budget_bytes (0: no limit); submit fails with GREST_EAGAIN
- * when `max_queue` requests are pending.
+ * Admission by device memory (hbm_budget_bytes, 0: no limit): the server reserves for
+ * every attached graph its current footprint (grest_memory) plus the growth its queued
+ * requests will cause (an update that outgrows a capacity reallocates it: node and entry
+ * buffers by 1.5x, change and sketch buffers by 2x).  attach fails with GREST_EAGAIN when
+ * the state's footprint does not fit the budget; submit fails with GREST_EAGAIN when the
+ * request's growth does not fit, or when `max_queue` requests are pending.  Memory frees
+ * up when a graph is detached, and when a graph's requests have all run (its reservation
+ * is then replaced by its actual footprint); a refused submission can be retried then.
  * Time stamps are nanoseconds of the monotonic clock that grest_now_ns reads.
  * While attached, a state must not be used directly (no update, get or sync) except
  * after grest_server_drain has returned; the server restores the state's original
@@ -353,6 +381,15 @@ grest_status grest_submit(grest_server* sv, int32_t graph_id, int64_t n_new, int
  * (never blocks). */
 int32_t grest_poll(grest_server* sv, int32_t max, uint64_t* tags, int32_t* status, int64_t* t_submit_ns,
                    int64_t* t_done_ns);
+
+/* Detaches an idle graph (nothing of it queued or running; else GREST_EAGAIN): its
+ * reservation is released, its state gets its original stream back and may be used
+ * directly again; the id is not reused (submit to it: EINVAL). */
+grest_status grest_server_detach(grest_server* sv, int32_t graph_id);
+
+/* Device bytes reserved by the attached graphs (footprints plus the growth of queued
+ * requests) and the budget; either pointer may be NULL. */
+grest_status grest_server_memory(grest_server* sv, int64_t* reserved, int64_t* budget);
 
 /* Blocks until every queued request has finished (they stay available to grest_poll). */
 grest_status grest_server_drain(grest_server* sv);

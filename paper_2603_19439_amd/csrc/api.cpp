@@ -51,6 +51,7 @@ struct Pinned {
   struct {
     int32_t vstatus;  // validation status of the update that used this slot
     int64_t m_new;
+    int64_t hcount;   // heavy rows of the new graph
   } g[2];
 };
 
@@ -148,6 +149,12 @@ struct grest_state {
   int32_t* ranks = nullptr;
   int32_t* status = nullptr;
   int64_t* maxdeg[2] = {nullptr, nullptr};  // largest degree of CSR buffer b
+  // rows of CSR buffer b with more than HEAVY_DEG entries (multiplied by a workgroup each),
+  // their count on the device and on the host; flag, position and scan workspaces
+  int32_t* hrows[2] = {nullptr, nullptr};
+  int64_t* hcnt[2] = {nullptr, nullptr};
+  int64_t hcnt_host[2] = {0, 0};
+  int64_t *hflag = nullptr, *hpos = nullptr, *hscan = nullptr;
   Pinned* pin = nullptr;
   double* theta_pin = nullptr;
   int32_t deferred = 0;
@@ -167,6 +174,9 @@ struct grest_state {
   int64_t rs_since_check = 0, rs_since_start = 0, rs_count = 0;
   double rs_last_orth = -1.0, rs_last_resid = -1.0;
   int32_t ax_age = 0;  // updates since the last full-width product
+  // the last run of the initial eigensolver: products with the operator, final residual
+  int32_t last_init_products = 0;
+  double last_init_resid = -1.0;
 
   // optional stage timing with HIP events on the state's stream; two sets of events, used
   // by alternate updates, so that an update's events are read (at the next update's
@@ -258,6 +268,10 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   CHK(dalloc(&st->dscan_tmp, scan_tmp_elems(cap_n + 1) + 16));
   CHK(dalloc(&st->srows, cap_n + 1));
   CHK(dalloc(&st->drows, cap_n + 1));
+  for (int b = 0; b < 2; ++b) CHK(dalloc(&st->hrows[b], cap_n + 1));
+  CHK(dalloc(&st->hflag, cap_n + 1));
+  CHK(dalloc(&st->hpos, cap_n + 1));
+  CHK(dalloc(&st->hscan, scan_tmp_elems(cap_n + 1) + 16));
   st->cap_n = cap_n;
   return GREST_OK;
 }
@@ -329,6 +343,8 @@ int64_t device_bytes(const grest_state* st) {
   add(st->d_ei); add(st->d_ej); add(st->d_sg);
   add(st->dcnt); add(st->newlen); add(st->scan_tmp); add(st->srows); add(st->drows);
   add(st->rflag); add(st->rpos); add(st->rscan_tmp); add(st->dflag); add(st->dpos); add(st->dscan_tmp);
+  add(st->hrows[0]); add(st->hrows[1]); add(st->hcnt[0]); add(st->hcnt[1]); add(st->hflag); add(st->hpos);
+  add(st->hscan);
   add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp); add(st->dins); add(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
     add(st->dptr[b]); add(st->dcol[b]); add(st->dsg[b]); add(st->vstat[b]); add(st->maxdeg[b]);
@@ -348,6 +364,8 @@ void free_all(grest_state* st) {
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
   dfree(st->dcnt); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows); dfree(st->drows);
   dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp); dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
+  dfree(st->hrows[0]); dfree(st->hrows[1]); dfree(st->hcnt[0]); dfree(st->hcnt[1]); dfree(st->hflag);
+  dfree(st->hpos); dfree(st->hscan);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp); dfree(st->dins); dfree(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
     dfree(st->dptr[b]); dfree(st->dcol[b]); dfree(st->dsg[b]); dfree(st->vstat[b]); dfree(st->maxdeg[b]);
@@ -365,6 +383,20 @@ void free_all(grest_state* st) {
   st->pin = nullptr;
   st->theta_pin = nullptr;
 }
+
+// the heavy rows of CSR buffer b (its graph in place), with their count copied to the host
+grest_status heavy_rows_sync(grest_state* st, int b) {
+  if (st->graph_free) {
+    st->hcnt_host[b] = 0;
+    return GREST_OK;
+  }
+  launch_heavy_rows(st->n, st->rp[b], st->hflag, st->hpos, st->hscan, st->hrows[b], st->hcnt[b], st->stream);
+  HIPCHK(hipMemcpyAsync(&st->hcnt_host[b], st->hcnt[b], sizeof(int64_t), hipMemcpyDeviceToHost, st->stream));
+  HIPCHK(hipStreamSynchronize(st->stream));
+  return GREST_OK;
+}
+
+HeavyRows heavy_of(const grest_state* st, int b) { return HeavyRows{st->hrows[b], st->hcnt[b], st->hcnt_host[b]}; }
 
 // Grow node-indexed buffers, keeping the current graph and basis.
 grest_status grow_nodes(grest_state* st, int64_t need) {
@@ -386,6 +418,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   dfree(st->newlen); dfree(st->scan_tmp); dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp);
   dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
   dfree(st->srows); dfree(st->drows);
+  dfree(st->hrows[0]); dfree(st->hrows[1]); dfree(st->hflag); dfree(st->hpos); dfree(st->hscan);
   CHK(alloc_node_arrays(st, cap));
   CHK(alloc_gather_arrays(st));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
@@ -393,6 +426,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   HIPCHK(hipMemcpyAsync(st->sc[st->gcur], sc_old, st->n * st->es, hipMemcpyDeviceToDevice, st->stream));
   HIPCHK(hipMemcpyAsync(st->z[st->zcur], z_old, (size_t)st->n * st->ldz * st->es, hipMemcpyDeviceToDevice,
                         st->stream));
+  CHK(heavy_rows_sync(st, st->gcur));
   HIPCHK(hipStreamSynchronize(st->stream));
   for (int b = 0; b < 2; ++b) { dfree(rp_keep[b]); dfree(z_keep[b]); dfree(sc_keep[b]); }
   return GREST_OK;
@@ -561,7 +595,8 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
     // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
     const int c0 = reuse ? st->K : 0;
     mark_spmm(st, 0);
-    launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc + c0, st->ldz, n2, st->D - c0, b.aux + c0, st->D, st->stream);
+    const HeavyRows hv = heavy_of(st, st->gcur ^ 1);  // the updated graph's buffer
+    launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc + c0, st->ldz, n2, st->D - c0, b.aux + c0, st->D, st->stream, &hv);
     mark_spmm(st, 1);
     st->spmm_cols[st->pslot] = st->D - c0;
     mark(st, 5);
@@ -700,6 +735,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     launch_scan_excl(st->newlen, st->rp[gn], n2, st->scan_tmp, gs);
     if (sizeof(T) == 8) launch_degrees(n2, st->rp[gn], (double*)st->sc[gn], nullptr, maxdeg, gs);
     else launch_degrees(n2, st->rp[gn], nullptr, (float*)st->sc[gn], maxdeg, gs);
+    launch_heavy_rows(n2, st->rp[gn], st->hflag, st->hpos, st->hscan, st->hrows[gn], st->hcnt[gn], gs);
   }
   // ---- the work of the update that reads only Delta, the new graph's scales and Omega,
   // and writes only scratch (the sketch and the row lists), goes on the same stream, its
@@ -745,8 +781,10 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     launch_csr_merge(n, S, st->rp[st->gcur], st->col[st->gcur], dptr, dcol, dsg, cb.dins, st->rp[gn], st->col[gn],
                      st->cap_m, gs);
   HIPCHK(hipMemcpyAsync(&st->pin->g[ds].vstatus, st->vstat[ds], sizeof(int32_t), hipMemcpyDeviceToHost, gs));
-  if (!gfree)
+  if (!gfree) {
     HIPCHK(hipMemcpyAsync(&st->pin->g[ds].m_new, st->rp[gn] + n2, sizeof(int64_t), hipMemcpyDeviceToHost, gs));
+    HIPCHK(hipMemcpyAsync(&st->pin->g[ds].hcount, st->hcnt[gn], sizeof(int64_t), hipMemcpyDeviceToHost, gs));
+  }
   if (st->marking && st->stage_marks) (void)hipEventRecord(st->gend[st->pslot], gs);
   HIPCHK(hipEventRecord(st->gev[ds], gs));
   st->dslot ^= 1;
@@ -872,6 +910,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     return GREST_EINVAL;
   }
   const int64_t m_new = gfree ? -1 : st->pin->g[ds].m_new;
+  st->hcnt_host[gn] = gfree ? 0 : st->pin->g[ds].hcount;
 
   if (nlap) {
     launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
@@ -906,48 +945,149 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
 }
 
 
-// Initial pairs (Alg. 2 line 3): block subspace iteration of width b = min(2K, Dw) on the
-// tracked operator (shifted for the Laplacians so that the wanted end of the spectrum
-// dominates), CholQR2 after every product, then Rayleigh-Ritz on the final block.
+// Default residual tolerance of the initial eigensolver: max_j ||M x_j - lambda_j x_j|| /
+// scale (scale as for the drift measure), near what the precision of the blocks can reach.
+double default_init_tol(const grest_state* st) { return st->es == 8 ? 1e-12 : 4e-6; }
+
+// Initial pairs (Alg. 2 line 3, "any direct eigendecomposition method"): a Chebyshev-
+// filtered block subspace iteration on the tracked operator, with Rayleigh-Ritz after
+// every filter and a residual stop.  The block has b = min(D, 128, n) columns (D the
+// basis width, at least K).  Starting from a random block orthonormalised by CholQR2,
+// each outer step
+//  1. runs Rayleigh-Ritz on the orthonormal block Z: (op Z) by the sparse product, H =
+//     Z^T (op Z) with FP64 accumulation, all b Ritz pairs by the small FP64 eigensolver
+//     in the order of the selection (largest magnitude for the adjacency; smallest nu for
+//     the Laplacians, whose products are taken in the L-form), X = Z F and (op X) =
+//     (op Z) F;
+//  2. measures the residual of the K leading pairs, max_j ||(op) x_j - theta_j x_j|| /
+//     scale with scale = max_j |theta_j| (adjacency), 2 d_max (L) or 2 (L_n), and stops
+//     when it is at most tol or the product budget is spent;
+//  3. filters the Ritz block by the Chebyshev polynomial T_m of the operator mapped so
+//     that the interval of the unwanted spectrum becomes [-1, 1]: [-c, c] with c the
+//     smallest magnitude in the block (adjacency), [nu_b, 2 d_max] or [nu_b, 2] with nu_b
+//     the largest nu in the block (Laplacians; both bound the spectrum of L and L_n from
+//     above).  The degree m is the largest whose growth at the block's leading Ritz value
+//     stays below 1e4, so that CholQR2 of the filtered block stays well conditioned (at
+//     most 16, at least 1); T_m comes from the three-term recurrence
+//     Y_{j+1} = (2/e)(op Y_j - center Y_j) - Y_{j-1}; then CholQR2.
+// The pairs of the last Rayleigh-Ritz step are committed; *products and *resid report
+// the products with the operator used and the last residual.
 template <typename T>
-grest_status init_impl(grest_state* st, int iters, uint64_t seed) {
+grest_status init_impl(grest_state* st, int max_products, double tol, uint64_t seed, int32_t* products_out,
+                       double* resid_out) {
   hipStream_t s = st->stream;
   const int64_t n = st->n;
-  int b = std::min(2 * st->K, st->Dw);
+  const int K = st->K;
+  int b = std::min(st->D, 128);
   if (b > n) b = (int)n;
-  T* Z = (T*)st->z[st->zcur];
+  if (b < K || max_products < 1) return GREST_EINVAL;
+  const bool adj = st->op == GREST_OP_ADJ;
+  const int which = adj ? 0 : 1;
+  T* buf[2] = {(T*)st->z[0], (T*)st->z[1]};
+  int cur = st->zcur;  // buffer of the orthonormal block
   T* aux = (T*)st->aux;
   const int64_t* rp = st->rp[st->gcur];
   const int32_t* col = st->col[st->gcur];
   const T* sc = (const T*)st->sc[st->gcur];
-  double shift = 0.0;
+  const HeavyRows hv = heavy_of(st, st->gcur);
+  double hi = 0.0;  // upper bound of the spectrum of L (2 d_max) or L_n (2)
   if (st->op == GREST_OP_LAP) {
     int64_t md = 0;
     HIPCHK(hipMemcpy(&md, st->maxdeg[st->gcur], sizeof(int64_t), hipMemcpyDeviceToHost));
-    shift = 2.0 * (double)md;
+    hi = 2.0 * (double)md;
   } else if (st->op == GREST_OP_NLAP) {
-    shift = 2.0;
+    hi = 2.0;
   }
   launch_fill_bytes0(st->status, sizeof(int32_t), s);
-  launch_fill_rows<T>(Z, st->ldz, 0, n, st->ldz, s);
-  launch_fill_random<T>(Z, st->ldz, n, b, seed, s);
-  cholqr2<T>(st, n, Z, st->ldz, b, 0);
-  for (int it = 0; it < iters; ++it) {
-    launch_spmm<T>(st->op, n, rp, col, sc, Z, st->ldz, n, b, aux, st->D, s);
-    if (st->op != GREST_OP_ADJ) launch_axpby<T>(n, b, shift, Z, st->ldz, -1.0, aux, st->D, s);
-    HIPCHK(hipMemcpy2DAsync(Z, st->ldz * sizeof(T), aux, st->D * sizeof(T), b * sizeof(T), n,
-                            hipMemcpyDeviceToDevice, s));
-    cholqr2<T>(st, n, Z, st->ldz, b, 0);
+  launch_fill_rows<T>(buf[cur], st->ldz, 0, n, st->ldz, s);
+  launch_fill_random<T>(buf[cur], st->ldz, n, b, seed, s);
+  cholqr2<T>(st, n, buf[cur], st->ldz, b, 0);
+  std::vector<double> th((size_t)b), gram((size_t)K * K);
+  int32_t rk[8] = {};
+  int products = 0;
+  double resid = INFINITY;
+  for (;;) {
+    T* Z = buf[cur];
+    T* X = buf[cur ^ 1];
+    // 1. Rayleigh-Ritz on Z (its kept columns)
+    launch_spmm<T>(st->op, n, rp, col, sc, Z, st->ldz, n, b, aux, st->D, s, &hv);
+    ++products;
+    launch_tn<T, true>(n, Z, st->ldz, b, aux, st->D, b, st->partial, st->H, s);
+    launch_symmetrize(b, st->H, s);
+    if (!launch_small_eig(b, 0, st->ranks + 1, st->H, which, b, 0.0, st->theta, st->F, nullptr, st->eigwork,
+                          st->status, s)) {
+      snprintf(g_last_error, sizeof(g_last_error), "initial block width %d outside the small eigensolver's range", b);
+      return GREST_EINVAL;
+    }
+    launch_apply<T>(n, Z, st->ldz, b, st->F, b, 1.0, 0.0, X, st->ldz, s);
+    launch_apply<T>(n, aux, st->D, b, st->F, b, 1.0, 0.0, aux, st->D, s);  // (op X), in place
+    // 2. residual block of the K leading pairs, in Z's buffer (free from here on)
+    launch_lincomb3<T>(n, K, 1.0, aux, st->D, 0.0, aux, st->D, 0.0, nullptr, 0, Z, st->ldz, s);
+    launch_sub_scaled_cols<T>(n, K, st->theta, X, st->ldz, Z, st->ldz, s);
+    launch_tn<T, true>(n, Z, st->ldz, K, Z, st->ldz, K, st->partial, st->Gm, s);
+    HIPCHK(hipMemcpyAsync(gram.data(), st->Gm, gram.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(th.data(), st->theta, th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rk, st->ranks, sizeof(rk), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    cur ^= 1;  // the Ritz block X is the current block
+    if (st->pin->status & ST_NUMERIC) break;
+    double scale = hi;
+    if (adj) {
+      scale = 0.0;
+      for (int j = 0; j < K; ++j) scale = std::max(scale, std::fabs(th[(size_t)j]));
+    }
+    if (!(scale > 0.0)) scale = 1.0;
+    double m2 = 0.0;
+    for (int j = 0; j < K; ++j) m2 = std::max(m2, gram[(size_t)j * K + j]);
+    resid = std::sqrt(m2) / scale;
+    if (resid <= tol || max_products - products < 2) break;
+    // 3. Chebyshev filter of the Ritz block (its nb valid columns, ordered by the selection)
+    const int nb = std::max(1, std::min(b, (int)rk[1]));
+    double center, e, r0;
+    if (adj) {
+      double c = std::fabs(th[(size_t)nb - 1]);
+      if (!(c > 0.0)) c = 0.5 * std::fabs(th[0]);
+      center = 0.0;
+      e = c > 0.0 ? c : 1.0;
+      r0 = std::fabs(th[0]) / e;
+    } else {
+      const double lo = th[(size_t)nb - 1];
+      const double top = std::max(hi, lo + 1e-12 * std::max(1.0, hi));
+      center = 0.5 * (lo + top);
+      e = 0.5 * (top - lo);
+      r0 = (center - th[0]) / e;
+    }
+    int m = 1;
+    if (r0 > 1.0 + 1e-12) m = (int)std::floor(std::acosh(1e4) / std::acosh(r0));
+    m = std::max(1, std::min(m, std::min(16, max_products - products - 1)));
+    T* prev = buf[cur];
+    T* next = buf[cur ^ 1];
+    launch_spmm<T>(st->op, n, rp, col, sc, prev, st->ldz, n, b, aux, st->D, s, &hv);
+    ++products;
+    launch_lincomb3<T>(n, b, 1.0 / e, aux, st->D, -center / e, prev, st->ldz, 0.0, nullptr, 0, next, st->ldz, s);
+    for (int j = 1; j < m; ++j) {
+      launch_spmm<T>(st->op, n, rp, col, sc, next, st->ldz, n, b, aux, st->D, s, &hv);
+      ++products;
+      // T_{j+1} into the buffer of T_{j-1} (element by element, read before written)
+      launch_lincomb3<T>(n, b, 2.0 / e, aux, st->D, -2.0 * center / e, next, st->ldz, -1.0, prev, st->ldz, prev,
+                         st->ldz, s);
+      std::swap(prev, next);
+    }
+    cur = next == buf[0] ? 0 : 1;
+    cholqr2<T>(st, n, buf[cur], st->ldz, b, 0);
   }
-  CHK(rayleigh_ritz<T>(st, n, rp, col, sc, 0, st->ranks + 1, false));
   HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  st->zcur ^= 1;
+  st->zcur = cur;
   st->has_pairs = true;
-  st->ax_valid = st->op == GREST_OP_ADJ && st->proj == GREST_PROJ_EXACT;
+  st->ax_valid = st->op == GREST_OP_ADJ && st->proj == GREST_PROJ_EXACT;  // aux[:, 0:K] = A X
   st->ax_age = 0;
   st->rs_since_check = st->rs_since_start = 0;
+  st->last_init_products = products;
+  st->last_init_resid = resid;
+  if (products_out) *products_out = products;
+  if (resid_out) *resid_out = resid;
   if (st->pin->status & ST_NUMERIC) return GREST_ENUMERIC;
   return GREST_OK;
 }
@@ -971,8 +1111,9 @@ grest_status drift_impl(grest_state* st, double* orth, double* resid) {
   HIPCHK(hipMemcpyAsync(G.data(), st->Gm, G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   int64_t md = 0;
   if (!st->graph_free) {
+    const HeavyRows hv = heavy_of(st, st->gcur);
     launch_spmm<T>(st->op, n, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], U, st->ldz, n, K, R,
-                   st->ldz, s);
+                   st->ldz, s, &hv);
     launch_sub_scaled_cols<T>(n, K, st->theta, U, st->ldz, R, st->ldz, s);
     launch_tn<T, true>(n, R, st->ldz, K, R, st->ldz, K, st->partial, st->H, s);
     HIPCHK(hipMemcpyAsync(RR.data(), st->H, RR.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1087,6 +1228,50 @@ grest_status get_impl(grest_state* st, double* values, void* X, int32_t x_dtype,
 
 }  // namespace
 
+// Device bytes of the capacity-sized buffers at the given capacities (the sizes the
+// allocation functions above request; the small fixed matrices are left out, they never
+// grow).  The allocator may round each request up a little.
+int64_t state_bytes_for(const grest_state* st, const StateCaps& c) {
+  const int64_t es = (int64_t)st->es;
+  const int64_t n1 = c.cap_n + 1;
+  int64_t b = 0;
+  b += 2 * n1 * 8 + 2 * c.cap_n * es + 2 * c.cap_n * st->ldz * es;  // rp, sc, z (two each)
+  if (!st->graph_free) b += c.cap_n * std::max(st->D, st->K) * es;  // (op Z)
+  if (st->variant == GREST_RSVD) b += 2 * c.cap_n * st->ldy * es;    // sketch and its basis
+  b += 8 * n1 * 8;                                                   // counts, offsets, flags, positions
+  b += 3 * (scan_tmp_elems(n1) + 16) * 8;                            // scan workspaces
+  b += 2 * n1 * 4;                                                   // row lists
+  if (!st->graph_free) b += 2 * c.cap_m * 4;                         // column ids (two buffers)
+  const int64_t nc = c.cap_nc;
+  b += nc * (4 + 4 + 1) + 2 * nc * (8 + 8 + 2 * 4 + 2 * 1 + 4 + 1);  // change arrays
+  b += (int64_t)delta_sort_temp_bytes(2 * nc);
+  if (st->proj == GREST_PROJ_LOWRANK)
+    b += 2 * std::max<int64_t>(1, std::min<int64_t>(2 * nc, c.cap_n)) * st->D * es;
+  if (st->variant == GREST_RSVD) b += c.cap_s * st->Ls * (2 * es + 8);
+  return b;
+}
+
+void state_caps(const grest_state* st, StateCaps* c) {
+  c->cap_n = st->cap_n;
+  c->cap_m = st->cap_m;
+  c->cap_nc = st->cap_nc;
+  c->cap_s = st->cap_s;
+  c->n = st->n;
+  c->m = st->m;
+}
+
+// The capacities after one more update of n_new nodes and nc changes, by the growth rule
+// of the update (node and entry buffers by 1.5x, change and sketch buffers by 2x).
+void state_caps_after(const grest_state* st, StateCaps* c, int64_t n_new, int64_t nc, int64_t dm) {
+  const int64_t n2 = c->n + n_new;
+  if (n2 > c->cap_n) c->cap_n = std::max<int64_t>(n2, c->cap_n + c->cap_n / 2);
+  if (!st->graph_free && c->m + 2 * nc > c->cap_m) c->cap_m = std::max<int64_t>(c->m + 2 * nc, c->cap_m + c->cap_m / 2);
+  if (nc > c->cap_nc) c->cap_nc = std::max<int64_t>(nc, c->cap_nc * 2);
+  if (st->variant == GREST_RSVD && n_new > c->cap_s) c->cap_s = std::max<int64_t>(n_new, 2 * c->cap_s);
+  c->n = n2;
+  if (!st->graph_free) c->m += dm;
+}
+
 void* state_user_stream(const grest_state* st) { return st->own_stream ? nullptr : (void*)st->stream; }
 int64_t state_sketch_cols(const grest_state* st) { return st->variant == GREST_RSVD ? st->Ls : 0; }
 void state_rebind_stream(grest_state* st, void* stream) {
@@ -1168,7 +1353,11 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   const int extra = cfg->variant == GREST_G3 ? cfg->max_new : (cfg->variant == GREST_RSVD ? cfg->L : 0);
   st->Dw = st->K + extra;
   st->D = st->K + st->Dw;
-  if (st->Dw > 128 || st->D > 128) { delete st; return GREST_EINVAL; }
+  // widths the kernels hold: every block orthonormalised by CholQR2 at most 128 columns
+  // (the Cholesky factor; RSVD: Delta Xbar and the sketch, else the whole augmentation),
+  // the basis at most 196 (the small eigensolver)
+  const int orth_w = st->variant == GREST_RSVD ? std::max(st->K, st->Ls) : st->Dw;
+  if (orth_w > 128 || st->D > 196) { delete st; return GREST_EINVAL; }
   const int q = (int)(16 / st->es);
   st->ldz = (int)round_up(st->D, q);
   st->ldy = (int)round_up(std::max(st->Ls, 1), q);
@@ -1194,14 +1383,19 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   const int wmax = std::max(st->Dw, std::max(st->Ls, 1));
   if ((rc = dalloc(&st->C1, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->C2, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->Gm, (size_t)wmax * wmax)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->Mchol, (size_t)(st->K + wmax) * wmax + (size_t)(wmax + 1) * (wmax + 1))) != GREST_OK) return fail(rc);
+  // the Gram and the factor also serve the initial eigensolver's blocks of up to D columns
+  const size_t gw = (size_t)std::max(wmax, dmax);
+  if ((rc = dalloc(&st->Gm, gw * gw)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->Mchol, std::max((size_t)(st->K + wmax) * wmax + (size_t)(wmax + 1) * (wmax + 1),
+                                        gw * gw))) != GREST_OK)
+    return fail(rc);
   if ((rc = dalloc(&st->M1buf, (size_t)(st->D + wmax) * wmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Clr, (size_t)st->D * st->K)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->H, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Msk, (size_t)(st->K + wmax) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->F, (size_t)dmax * st->K)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->theta, st->K)) != GREST_OK) return fail(rc);
+  // F and theta hold all the pairs of a block of the initial eigensolver (up to D)
+  if ((rc = dalloc(&st->F, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->theta, dmax)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->Fb, (size_t)std::max(st->Ls, 1) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->thetab, std::max(st->L, 1))) != GREST_OK) return fail(rc);
   st->partial_elems = (int64_t)tn_num_chunks(INT64_MAX / 4) * dmax * dmax;
@@ -1211,6 +1405,7 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   if ((rc = dalloc(&st->ranks, 8)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->status, 1)) != GREST_OK) return fail(rc);
   for (int b = 0; b < 2; ++b) {
+    if ((rc = dalloc(&st->hcnt[b], 1)) != GREST_OK) return fail(rc);
     if ((rc = dalloc(&st->maxdeg[b], 1)) != GREST_OK) return fail(rc);
     if ((rc = dalloc(&st->vstat[b], 1)) != GREST_OK) return fail(rc);
     if (hipEventCreateWithFlags(&st->gev[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
@@ -1231,6 +1426,7 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   launch_fill_bytes0(st->maxdeg[0], sizeof(int64_t), st->stream);
   if (st->es == 8) launch_degrees(n0, st->rp[0], (double*)st->sc[0], nullptr, st->maxdeg[0], st->stream);
   else launch_degrees(n0, st->rp[0], nullptr, (float*)st->sc[0], st->maxdeg[0], st->stream);
+  if ((rc = heavy_rows_sync(st, 0)) != GREST_OK) return fail(rc);
   // symmetry check on the device would need a transpose; the host check above covers format
   if (hipStreamSynchronize(st->stream) != hipSuccess) return fail(GREST_EDEVICE);
   *out = st;
@@ -1250,7 +1446,23 @@ grest_status grest_set_pairs(grest_state* st, const double* values, const double
 
 grest_status grest_init_pairs(grest_state* st, int32_t iterations, uint64_t seed) {
   if (!st || iterations < 1 || st->graph_free) return GREST_EINVAL;
-  return st->es == 8 ? init_impl<double>(st, iterations, seed) : init_impl<float>(st, iterations, seed);
+  const double tol = default_init_tol(st);
+  return st->es == 8 ? init_impl<double>(st, iterations, tol, seed, nullptr, nullptr)
+                     : init_impl<float>(st, iterations, tol, seed, nullptr, nullptr);
+}
+
+grest_status grest_init_pairs_tol(grest_state* st, int32_t max_products, double tol, uint64_t seed,
+                                  int32_t* products, double* resid) {
+  if (!st || max_products < 1 || st->graph_free || !(tol >= 0.0)) return GREST_EINVAL;
+  return st->es == 8 ? init_impl<double>(st, max_products, tol, seed, products, resid)
+                     : init_impl<float>(st, max_products, tol, seed, products, resid);
+}
+
+grest_status grest_init_stats(const grest_state* st, int32_t* products, double* resid) {
+  if (!st) return GREST_EINVAL;
+  if (products) *products = st->last_init_products;
+  if (resid) *resid = st->last_init_resid;
+  return GREST_OK;
 }
 
 grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei, const int32_t* ej,
@@ -1285,7 +1497,9 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
     st->pin->status = 0;
     const uint64_t seed = st->rs_seed + (uint64_t)st->rs_count;
     ++st->rs_count;
-    return st->es == 8 ? init_impl<double>(st, st->rs_iters, seed) : init_impl<float>(st, st->rs_iters, seed);
+    const double tol = default_init_tol(st);
+    return st->es == 8 ? init_impl<double>(st, st->rs_iters, tol, seed, nullptr, nullptr)
+                       : init_impl<float>(st, st->rs_iters, tol, seed, nullptr, nullptr);
   }
   return GREST_OK;
 }

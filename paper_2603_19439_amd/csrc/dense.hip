@@ -143,6 +143,22 @@ __global__ void k_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, 
   }
 }
 
+// Out = a P + b Q + c R on an n x w block (FP64 arithmetic; R may be null).  Out may be
+// P, Q or R itself: each element is read before it is written, at the same position.
+template <typename T>
+__global__ void k_lincomb3(int64_t rows, int w, double a, const T* P, int64_t ldp, double b, const T* Q,
+                           int64_t ldq, double c, const T* R, int64_t ldr, T* Out, int64_t ldo) {
+  const int64_t total = rows * w;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int64_t r = idx / w;
+    const int col = (int)(idx % w);
+    double v = a * (double)P[r * ldp + col] + b * (double)Q[r * ldq + col];
+    if (R) v += c * (double)R[r * ldr + col];
+    Out[r * ldo + col] = (T)v;
+  }
+}
+
 // residual block of tracked pairs: R[:, c] -= values[c] U[:, c] (FP64 arithmetic)
 template <typename T>
 __global__ void k_sub_scaled_cols(int64_t rows, int w, const double* __restrict__ values, const T* __restrict__ U,
@@ -180,6 +196,17 @@ void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double
   if (rows <= 0 || w <= 0) return;
   k_axpby<T><<<grid_cap(rows * w), 256, 0, s>>>(rows, w, a, X, ldx, b, Y, ldy);
 }
+
+template <typename T>
+void launch_lincomb3(int64_t rows, int w, double a, const T* P, int64_t ldp, double b, const T* Q, int64_t ldq,
+                     double c, const T* R, int64_t ldr, T* Out, int64_t ldo, hipStream_t s) {
+  if (rows <= 0 || w <= 0) return;
+  k_lincomb3<T><<<grid_cap(rows * w), 256, 0, s>>>(rows, w, a, P, ldp, b, Q, ldq, c, R, ldr, Out, ldo);
+}
+template void launch_lincomb3<float>(int64_t, int, double, const float*, int64_t, double, const float*, int64_t,
+                                     double, const float*, int64_t, float*, int64_t, hipStream_t);
+template void launch_lincomb3<double>(int64_t, int, double, const double*, int64_t, double, const double*, int64_t,
+                                      double, const double*, int64_t, double*, int64_t, hipStream_t);
 
 template void launch_fill_random<float>(float*, int64_t, int64_t, int, uint64_t, hipStream_t);
 template void launch_fill_random<double>(double*, int64_t, int64_t, int, uint64_t, hipStream_t);

@@ -71,9 +71,22 @@ enum OpKind : int32_t { OPK_ADJ = 0, OPK_LAP = 1, OPK_NLAP = 2 };
 //   lap : sum_c (Z[r] - Z[c])                 (= L Z)
 //   nlap: s_r sum_c (s_r Z[r] - s_c Z[c])      (= L_n Z; isolated rows give Z[r])
 // Z rows beyond nz_rows are treated as zero (padding).
+// Rows with more than HEAVY_DEG entries (the hubs of power-law graphs) go to a kernel that
+// splits each of them by entries over a whole workgroup; the others are row-split.
+constexpr int64_t HEAVY_DEG = 128;
+struct HeavyRows {
+  const int32_t* rows;   // ids of the heavy rows, ascending
+  const int64_t* count;  // their number (device)
+  int64_t bound;         // an upper bound of the count known on the host (0: no heavy rows)
+};
 template <typename T>
 void launch_spmm(int op, int64_t n, const int64_t* rp, const int32_t* col, const T* sc,
-                 const T* Z, int64_t ldz, int64_t nz_rows, int w, T* Y, int64_t ldy, hipStream_t s);
+                 const T* Z, int64_t ldz, int64_t nz_rows, int w, T* Y, int64_t ldy, hipStream_t s,
+                 const HeavyRows* heavy = nullptr);
+// rows[0 .. *count) = the rows of the CSR with more than HEAVY_DEG entries, ascending; flag
+// and pos hold n + 1 entries, scan_tmp scan_tmp_elems(n + 1)
+void launch_heavy_rows(int64_t n, const int64_t* rp, int64_t* flag, int64_t* pos, int64_t* scan_tmp, int32_t* rows,
+                       int64_t* count, hipStream_t s);
 
 // Products with the update Delta of the tracked operator (rows grouped in dptr/dcol/dsg).
 //   mode 0: V = Delta_1 Xbar            (only columns c < n_old, input X rows c)
@@ -199,6 +212,10 @@ void launch_fill_random(T* p, int64_t ld, int64_t rows, int w, uint64_t seed, hi
 template <typename T>
 void launch_sub_scaled_cols(int64_t rows, int w, const double* values, const T* U, int64_t ldu, T* R, int64_t ldr,
                             hipStream_t s);
+// Out = a P + b Q + c R on an n x w block (R may be null; Out may alias P, Q or R)
+template <typename T>
+void launch_lincomb3(int64_t rows, int w, double a, const T* P, int64_t ldp, double b, const T* Q, int64_t ldq,
+                     double c, const T* R, int64_t ldr, T* Out, int64_t ldo, hipStream_t s);
 // Y = a X + b Y on an n x w block
 template <typename T>
 void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double b, T* Y, int64_t ldy,
@@ -218,6 +235,17 @@ hipError_t noalloc_scratch(int device, void** out);
 // api.cpp: state accessors used by the server
 // ------------------------------------------------------------------------------------
 struct grest_state;
+// capacities of a state's growing buffers and its current sizes
+struct StateCaps {
+  int64_t cap_n = 0, cap_m = 0, cap_nc = 0, cap_s = 0;
+  int64_t n = 0, m = 0;
+};
+void state_caps(const grest_state* st, StateCaps* c);
+// device bytes of the growing buffers at capacities c
+int64_t state_bytes_for(const grest_state* st, const StateCaps& c);
+// c advanced by one update of n_new nodes and nc changes that changes the stored entries
+// by dm (the capacities grow as the update would grow them)
+void state_caps_after(const grest_state* st, StateCaps* c, int64_t n_new, int64_t nc, int64_t dm);
 // the caller's stream the state is bound to, or null when the state uses its own
 void* state_user_stream(const grest_state* st);
 // columns of the Gaussian test matrix an update needs (L + P for RSVD, else 0)

@@ -474,6 +474,7 @@ struct RedJob {
   const double* partial;
   double* C;
   int a, b, blocks;
+  int ldc;  // leading dimension of C (b for a whole product, wider for a block of one)
 };
 
 __global__ void __launch_bounds__(RWV * 64) k_tn_reduce(int g, RedJob j0, RedJob j1) {
@@ -502,12 +503,13 @@ __global__ void __launch_bounds__(RWV * 64) k_tn_reduce(int g, RedJob j0, RedJob
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < RWV; ++q) t += red[q][lane];
-    C[idx] = t;
+    const int ldc = second ? j1.ldc : j0.ldc;
+    C[(idx / b) * ldc + idx % b] = t;
   }
 }
 
-inline RedJob red_job(const double* partial, double* C, int a, int b) {
-  return RedJob{partial, C, a, b, (int)(((int64_t)a * b + 63) / 64)};
+inline RedJob red_job(const double* partial, double* C, int a, int b, int ldc = -1) {
+  return RedJob{partial, C, a, b, (int)(((int64_t)a * b + 63) / 64), ldc < 0 ? b : ldc};
 }
 
 inline void launch_reduce(int g, const RedJob& j0, const RedJob& j1, hipStream_t s) {
@@ -865,17 +867,27 @@ int tn_num_chunks(int64_t n) {
   return (int)g;
 }
 
-// kind: 0 = FP32 MFMA, 1 = FP64 MFMA, 2 = split-BF16 MFMA
+// kind: 0 = FP32 MFMA, 1 = FP64 MFMA, 2 = split-BF16 MFMA; C has leading dimension ldc
 template <typename T>
 static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T* B, int64_t ldb, int b,
-                   double* partial, double* C, hipStream_t s) {
+                   double* partial, double* C, hipStream_t s, int ldc = -1) {
   if (a <= 0 || b <= 0) return;
+  if (ldc < 0) ldc = b;
+  if (a > TW || b > TW) {
+    // operands wider than the kernels hold: blocks of at most TW columns of each, one after
+    // the other on the stream (they share the partial sums), each reduced into its block of C
+    for (int a0 = 0; a0 < a; a0 += TW)
+      for (int b0 = 0; b0 < b; b0 += TW)
+        tn_run<T>(kind, n, A + a0, lda, std::min(TW, a - a0), B + b0, ldb, std::min(TW, b - b0), partial,
+                  C + (size_t)a0 * ldc + b0, s, ldc);
+    return;
+  }
   const int g = tn_num_chunks(n);
   const int rb = kind == 2 ? 32 : 16;
   int64_t rpc = (n + g - 1) / g;
   rpc = ((rpc + rb - 1) / rb) * rb;
   if (kind == 2 && ((a + 15) >> 4) * ((b + 15) >> 4) > NW * BT) kind = 0;  // too many tiles: FP32 MFMA
-  bool sym = (A == B && lda == ldb && a == b && kind != 2);
+  bool sym = (A == B && lda == ldb && a == b && kind != 2 && ldc == b);
   if (kind == 2) {
     const int tt = std::max((((a + 15) >> 4) + 1) / 2, (((b + 15) >> 4) + 1) / 2);
     const bool staged = a % 4 == 0 && b % 4 == 0 && aligned16(A, lda) && aligned16(B, ldb);
@@ -893,7 +905,7 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
     if (sym && ((a + 15) >> 4) > 4) sym = false;
     tnw_dispatch<T, float>(n, g, rpc, A, lda, a, B, ldb, b, sym, partial, s);
   }
-  launch_reduce(g, red_job(partial, C, a, b), RedJob{nullptr, nullptr, 0, 0, 0}, s);
+  launch_reduce(g, red_job(partial, C, a, b, ldc), RedJob{nullptr, nullptr, 0, 0, 0, 0}, s);
 }
 
 // one projection round: C = X^T W and G = W^T W (upper tiles; the reduce mirrors them)
@@ -971,9 +983,56 @@ static void apply_launch(int64_t n, const T* In1, int64_t ld1, int a1, const T* 
 }
 
 template <typename T>
+static void apply2_narrow(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
+                          const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s,
+                          const int64_t* flag2, const int32_t* rows, const int64_t* nrows);
+
+// whether columns [p, p + w) and [q, q + v) of row-major blocks with the same leading
+// dimension share memory (the blocks start in the same row)
+template <typename T>
+static bool cols_overlap(const T* p, int w, const T* q, int v, int64_t ld, int64_t ldq) {
+  if (ld != ldq || w <= 0 || v <= 0) return false;
+  const int64_t d = q - p;
+  return d > -(int64_t)v && d < (int64_t)w && d > -ld && d < ld;
+}
+
+template <typename T>
 void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
                    const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s,
                    const int64_t* flag2, const int32_t* rows, const int64_t* nrows) {
+  if (n <= 0 || b <= 0) return;
+  if (a1 + a2 <= TW) {
+    apply2_narrow<T>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, s, flag2, rows, nrows);
+    return;
+  }
+  // A contraction wider than the kernel holds: Out = beta Out + alpha sum over blocks of at
+  // most TW input columns (In1's, then In2's) of In_blk M_blk, the first launch with beta and
+  // the others adding to Out.  A block whose columns Out overwrites (an in-place apply) goes
+  // first, as one launch in place; every other block must not share memory with Out.
+  struct Blk { const T* p; int64_t ld; int w; int row0; bool second; };
+  Blk blk[8];
+  int nb = 0;
+  for (int c0 = 0; c0 < a1 && nb < 8; c0 += TW) blk[nb++] = Blk{In1 + c0, ld1, std::min(TW, a1 - c0), c0, false};
+  for (int c0 = 0; c0 < a2 && nb < 8; c0 += TW) blk[nb++] = Blk{In2 + c0, ld2, std::min(TW, a2 - c0), a1 + c0, true};
+  int first = -1;
+  for (int q = 0; q < nb; ++q)
+    if (cols_overlap(blk[q].p, blk[q].w, (const T*)Out, b, blk[q].ld, ldout)) first = q;
+  double bt = beta;
+  auto run = [&](const Blk& k) {
+    apply2_narrow<T>(n, k.p, k.ld, k.w, k.p, k.ld, 0, M + (size_t)k.row0 * b, b, alpha, bt, Out, ldout, s,
+                     nullptr, rows, nrows);
+    bt = 1.0;
+  };
+  if (first >= 0) run(blk[first]);
+  for (int q = 0; q < nb; ++q)
+    if (q != first) run(blk[q]);
+  (void)flag2;  // an optimisation only (skips reading zero rows of In2): every row is read here
+}
+
+template <typename T>
+static void apply2_narrow(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, int64_t ld2, int a2,
+                          const double* M, int b, double alpha, double beta, T* Out, int64_t ldout, hipStream_t s,
+                          const int64_t* flag2, const int32_t* rows, const int64_t* nrows) {
   if (n <= 0 || b <= 0) return;
   if (!rows) nrows = nullptr;
   const bool vec = aligned16(In1, ld1) && (a2 == 0 || (aligned16(In2, ld2) && a1 % 4 == 0));

@@ -9,6 +9,14 @@
 // request waits behind a long update of another graph, and the lanes overlap on the
 // device.  Requests own copies of their change lists.  Completions are kept until
 // grest_poll hands them out.
+//
+// Admission by device memory: the server reserves, for every attached graph, its current
+// footprint plus the growth its queued requests will cause (the capacities an update
+// grows are known on the host: node and entry buffers by 1.5x, change and sketch buffers
+// by 2x).  A submission whose growth would take the reservations past the budget is
+// refused with GREST_EAGAIN and can be retried once memory frees up: when a graph with
+// nothing queued is detached, and when a graph's requests have all run and its
+// reservation is replaced by its actual footprint.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,12 +57,14 @@ struct Done {
 
 struct Graph {
   grest_state* st;
-  void* user_stream;  // restored on destroy (null: the state had its own stream)
-  int64_t bytes;
+  void* user_stream;  // restored on detach or destroy (null: the state had its own stream)
+  int64_t bytes;      // reserved device bytes: the footprint once its queued requests have run
   int64_t sketch_cols;  // L + P of an RSVD state, else 0
-  int64_t n_proj;       // node count once every queued request of the graph has run
+  StateCaps proj;       // capacities and sizes once every queued request of the graph has run
   int32_t lane;         // lane whose stream the state is on
+  int32_t queued;       // its requests queued or running
   bool running;         // a lane is updating it
+  bool detached;
 };
 
 }  // namespace
@@ -115,8 +125,18 @@ void worker(grest_server* sv, int lane) {
     const int64_t t_done = now_ns();
     {
       std::lock_guard<std::mutex> lk(sv->mu);
-      if (ru != GREST_OK) sv->graphs[rq.gid].n_proj -= rq.n_new;  // rejected: the graph did not grow
-      sv->graphs[rq.gid].running = false;
+      Graph& g = sv->graphs[rq.gid];
+      g.running = false;
+      if (--g.queued == 0) {
+        // nothing else queued for the graph: its reservation becomes its actual footprint
+        // (a rejected request did not grow it; the capacities may have grown by less)
+        int64_t actual = g.bytes;
+        if (grest_memory(st, &actual) == GREST_OK) {
+          sv->used += actual - g.bytes;
+          g.bytes = actual;
+        }
+        state_caps(st, &g.proj);
+      }
       sv->done.push_back(Done{rq.tag, (int32_t)rc, rq.t_submit, t_done});
       --sv->pending;
     }
@@ -167,12 +187,14 @@ grest_status grest_server_attach(grest_server* sv, grest_state* st, int32_t* gra
   if ((rc = grest_shape(st, &n, nullptr, &k, &width)) != GREST_OK) return rc;
   std::lock_guard<std::mutex> lk(sv->mu);
   for (const Graph& g : sv->graphs)
-    if (g.st == st) return GREST_EINVAL;  // already attached
+    if (!g.detached && g.st == st) return GREST_EINVAL;  // already attached
   if (sv->budget > 0 && sv->used + bytes > sv->budget) return GREST_EAGAIN;
   const int32_t id = (int32_t)sv->graphs.size();
   void* user = state_user_stream(st);
   if ((rc = grest_set_stream(st, sv->streams[id % sv->nlanes])) != GREST_OK) return rc;
-  sv->graphs.push_back(Graph{st, user, bytes, state_sketch_cols(st), n, id % sv->nlanes, false});
+  Graph g{st, user, bytes, state_sketch_cols(st), StateCaps{}, id % sv->nlanes, 0, false, false};
+  state_caps(st, &g.proj);
+  sv->graphs.push_back(g);
   sv->used += bytes;
   *graph_id = id;
   return GREST_OK;
@@ -185,12 +207,16 @@ grest_status grest_submit(grest_server* sv, int32_t graph_id, int64_t n_new, int
   Graph g;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (graph_id < 0 || graph_id >= (int32_t)sv->graphs.size()) return GREST_EINVAL;
+    if (graph_id < 0 || graph_id >= (int32_t)sv->graphs.size() || sv->graphs[graph_id].detached)
+      return GREST_EINVAL;
     g = sv->graphs[graph_id];
   }
   if (g.sketch_cols > 0 && n_new > 0 && !omega) return GREST_EINVAL;
   // format, id ranges, no duplicates: against the size the graph will have when this runs
-  if (grest_validate_changes(g.n_proj, n_new, n_changes, ei, ej, sign) != GREST_OK) return GREST_EINVAL;
+  // (its requests are submitted from one thread, so the size cannot change meanwhile)
+  if (grest_validate_changes(g.proj.n, n_new, n_changes, ei, ej, sign) != GREST_OK) return GREST_EINVAL;
+  int64_t dm = 0;  // change of the stored entries: +2 per insertion, -2 per deletion
+  for (int64_t c = 0; c < n_changes; ++c) dm += sign[c] > 0 ? 2 : -2;
   Request rq;
   rq.gid = graph_id;
   rq.tag = tag;
@@ -205,7 +231,18 @@ grest_status grest_submit(grest_server* sv, int32_t graph_id, int64_t n_new, int
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->pending >= sv->max_queue) return GREST_EAGAIN;
-    sv->graphs[graph_id].n_proj += n_new;
+    Graph& gr = sv->graphs[graph_id];
+    if (gr.detached) return GREST_EINVAL;
+    StateCaps after = gr.proj;
+    state_caps_after(gr.st, &after, n_new, n_changes, dm);
+    const int64_t growth = state_bytes_for(gr.st, after) - state_bytes_for(gr.st, gr.proj);
+    if (sv->budget > 0 && growth > 0 && sv->used + growth > sv->budget) return GREST_EAGAIN;
+    if (growth > 0) {
+      sv->used += growth;
+      gr.bytes += growth;
+    }
+    gr.proj = after;
+    ++gr.queued;
     rq.t_submit = now_ns();
     sv->queue.push_back(std::move(rq));
     ++sv->pending;
@@ -231,6 +268,31 @@ int32_t grest_poll(grest_server* sv, int32_t max, uint64_t* tags, int32_t* statu
   return c;
 }
 
+grest_status grest_server_detach(grest_server* sv, int32_t graph_id) {
+  if (!sv) return GREST_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (graph_id < 0 || graph_id >= (int32_t)sv->graphs.size() || sv->graphs[graph_id].detached)
+    return GREST_EINVAL;
+  Graph& g = sv->graphs[graph_id];
+  if (g.queued > 0 || g.running) return GREST_EAGAIN;
+  // the state is idle: its last update ended with grest_sync on its lane's stream
+  grest_status rc = grest_set_stream(g.st, g.user_stream);
+  if (rc != GREST_OK) return rc;
+  sv->used -= g.bytes;
+  g.bytes = 0;
+  g.detached = true;
+  g.st = nullptr;
+  return GREST_OK;
+}
+
+grest_status grest_server_memory(grest_server* sv, int64_t* reserved, int64_t* budget) {
+  if (!sv) return GREST_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (reserved) *reserved = sv->used;
+  if (budget) *budget = sv->budget;
+  return GREST_OK;
+}
+
 grest_status grest_server_drain(grest_server* sv) {
   if (!sv) return GREST_EINVAL;
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -247,7 +309,8 @@ void grest_server_destroy(grest_server* sv) {
   }
   sv->cv_work.notify_all();
   for (std::thread& t : sv->workers) t.join();
-  for (const Graph& g : sv->graphs) (void)grest_set_stream(g.st, g.user_stream);
+  for (const Graph& g : sv->graphs)
+    if (!g.detached) (void)grest_set_stream(g.st, g.user_stream);
   for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
   delete sv;
 }

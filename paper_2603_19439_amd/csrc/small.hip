@@ -18,7 +18,8 @@
 //      selected tridiagonal-basis vectors, y_s <- y_s - (1/2) sum_t (y_t^T y_s) y_t, which
 //      removes the eps ||T|| / gap overlap that independent inverse iterations leave
 //      between neighbours, then the back-transform through the reflectors.
-// Orders up to MAXN = 128 are supported.
+// Orders up to 128 are tridiagonalised with the matrix in registers; larger ones, up to
+// TL_MAX = 196, with the lower triangle of the matrix packed in LDS (k_tridiag_lds).
 #include "grest_internal.h"
 
 #include <math.h>
@@ -27,7 +28,9 @@ namespace {
 
 constexpr int TRI_WAVES = 8;  // waves of the tridiagonalisation workgroup (two per SIMD)
 constexpr int PCH_WAVES = 16;  // waves of the pivoted Cholesky workgroup
-constexpr int MAXN = 128;  // largest order
+constexpr int MAXN = 256;  // order of the work layout (largest order: TL_MAX)
+constexpr int NCOL = MAXN / GREST_WAVE;  // elements of a length-MAXN vector per lane
+constexpr int TL_MAX = 196;              // largest order of the LDS-resident tridiagonalisation
 constexpr double EPS = 2.220446049250313e-16;
 
 // work layout of the eigensolver (doubles)
@@ -38,7 +41,7 @@ constexpr int W_E2 = W_OD + MAXN;      // squared off-diagonal
 constexpr int W_HB = W_E2 + MAXN;      // reflector coefficients beta_k
 constexpr int W_EV = W_HB + MAXN;      // eigenvalues of T, ascending
 constexpr int W_FL = W_EV + MAXN;      // 1 for an output slot that holds a kept pair
-constexpr int W_R = 1024;              // reflector k in row k (MAXN x MAXN), v_{k+1} = 1
+constexpr int W_R = 2048;              // reflector k in row k (MAXN x MAXN), v_{k+1} = 1
 constexpr int W_Y = W_R + MAXN * MAXN;  // tridiagonal-basis vectors of clustered pairs
 constexpr int W_END = W_Y + MAXN * MAXN;
 
@@ -596,6 +599,42 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
 
 // ------------------------------------------------------------------------------------
 // 1. tridiagonalisation T = Q^T A Q, Q = P_0 ... P_{n-3}, P_k = I - beta_k v_k v_k^T
+// The tridiagonal T (diagonal sdg, off-diagonal sod, reflector coefficients shb, all of
+// order n) to the work table with the Gershgorin interval, the norm and the pivot floor of
+// the inertia counts, and the index map of the reduced matrix; run by one wave.
+__device__ void tridiag_finish(int n, int s1, int seg2, const double* sdg, const double* sod, const double* shb,
+                               double* work) {
+  const int lane = threadIdx.x & (GREST_WAVE - 1);
+  double lo = INFINITY, hi = -INFINITY, tn = 0.0, emax = 0.0;
+  for (int i = lane; i < n; i += GREST_WAVE) {
+    const double r = (i > 0 ? fabs(sod[i - 1]) : 0.0) + (i + 1 < n ? fabs(sod[i]) : 0.0);
+    lo = fmin(lo, sdg[i] - r);
+    hi = fmax(hi, sdg[i] + r);
+    tn = fmax(tn, fabs(sdg[i]) + r);
+    const double e2 = (i + 1 < n) ? sod[i] * sod[i] : 0.0;
+    emax = fmax(emax, e2);
+    work[W_DG + i] = sdg[i];
+    work[W_OD + i] = (i + 1 < n) ? sod[i] : 0.0;
+    work[W_E2 + i] = e2;
+    work[W_HB + i] = shb[i];
+  }
+  lo = wave_min_d(lo);
+  hi = wave_max_d(hi);
+  tn = wave_max_d(tn);
+  emax = wave_max_d(emax);
+  if (lane == 0) {
+    if (n == 0) { lo = 0.0; hi = 0.0; }
+    const double pad = 4.0 * EPS * fmax(tn, 1e-300) + 1e-300;
+    work[W_HDR + 0] = (double)n;
+    work[W_HDR + 1] = lo - pad;
+    work[W_HDR + 2] = hi + pad;
+    work[W_HDR + 3] = tn;
+    work[W_HDR + 4] = 1e-290 * fmax(1.0, emax);
+    work[W_HDR + 5] = (double)s1;
+    work[W_HDR + 6] = (double)seg2;
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // A lives in registers (see above).  Iteration k:
 //   every wave holds column k in registers and forms the reflector itself (identical
@@ -695,7 +734,8 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
       const double dk = vec_elem<C>(colk, k);
 #pragma unroll
       for (int c = 0; c < C; ++c) R[(size_t)k * MAXN + lane + GREST_WAVE * c] = v[c];
-      if (C == 1) R[(size_t)k * MAXN + lane + GREST_WAVE] = 0.0;
+#pragma unroll
+      for (int c = C; c < NCOL; ++c) R[(size_t)k * MAXN + lane + GREST_WAVE * c] = 0.0;
       if (lane == 0) { sdg[k] = dk; sod[k] = ek; shb[k] = beta; }
     }
     double vr[RW];
@@ -775,39 +815,139 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
     if (tid == 0) { sdg[0] = d0; sod[0] = 0.0; shb[0] = 0.0; }
   }
   __syncthreads();
-  if (wv == 0) {
-    // Gershgorin interval, norm, pivot floor; T to global memory
-    double lo = INFINITY, hi = -INFINITY, tn = 0.0, emax = 0.0;
-    for (int i = lane; i < MAXN; i += GREST_WAVE) {
-      if (i < n) {
-        const double r = (i > 0 ? fabs(sod[i - 1]) : 0.0) + (i + 1 < n ? fabs(sod[i]) : 0.0);
-        lo = fmin(lo, sdg[i] - r);
-        hi = fmax(hi, sdg[i] + r);
-        tn = fmax(tn, fabs(sdg[i]) + r);
-        const double e2 = (i + 1 < n) ? sod[i] * sod[i] : 0.0;
-        emax = fmax(emax, e2);
-        work[W_DG + i] = sdg[i];
-        work[W_OD + i] = (i + 1 < n) ? sod[i] : 0.0;
-        work[W_E2 + i] = e2;
-        work[W_HB + i] = shb[i];
-      }
-    }
-    lo = wave_min_d(lo);
-    hi = wave_max_d(hi);
-    tn = wave_max_d(tn);
-    emax = wave_max_d(emax);
-    if (lane == 0) {
-      if (n == 0) { lo = 0.0; hi = 0.0; }
-      const double pad = 4.0 * EPS * fmax(tn, 1e-300) + 1e-300;
-      work[W_HDR + 0] = (double)n;
-      work[W_HDR + 1] = lo - pad;
-      work[W_HDR + 2] = hi + pad;
-      work[W_HDR + 3] = tn;
-      work[W_HDR + 4] = 1e-290 * fmax(1.0, emax);
-      work[W_HDR + 5] = (double)s1;
-      work[W_HDR + 6] = (double)seg2;
+  if (wv == 0) tridiag_finish(n, s1, seg2, sdg, sod, shb, work);
+}
+
+// Householder tridiagonalisation of orders above 128 (up to TL_MAX), with the same
+// reflector convention and outputs as k_tridiag: the lower triangle of the matrix lives in
+// LDS, packed by rows (row i holds columns 0..i at offset i (i + 1) / 2), and one
+// workgroup of 1024 threads works on it.  Each step forms the reflector of the column
+// below the diagonal (a block sum of squares), p = beta A v with four threads per row of
+// the trailing block (reading the packed triangle by rows left of the diagonal and by
+// columns right of it), the correction K = beta / 2 (beta p)^T v (a block sum), w = beta p
+// - K v, and the rank-two update A -= v w^T + w v^T of the trailing triangle, again four
+// threads per row.  The block sums add the per-wave sums in a fixed order.
+constexpr int TL_THREADS = 1024;
+constexpr int TL_WAVES = TL_THREADS / GREST_WAVE;
+constexpr size_t TL_LDS = ((size_t)TL_MAX * (TL_MAX + 1) / 2 + 2 * TL_MAX + TL_WAVES) * sizeof(double);
+
+__device__ __forceinline__ int tri_at(int i, int j) { return (i * (i + 1)) / 2 + j; }  // i >= j
+
+// sum of v over the workgroup, the same in every thread (red: TL_WAVES doubles)
+__device__ __forceinline__ double tl_block_sum(double v, double* red) {
+  v = wave_sum_d(v);
+  __syncthreads();  // earlier readers of red are done
+  if ((threadIdx.x & (GREST_WAVE - 1)) == 0) red[threadIdx.x / GREST_WAVE] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < TL_WAVES; ++w) s += red[w];
+  return s;
+}
+
+__global__ void __launch_bounds__(TL_THREADS) k_tridiag_lds(int d_full, int base, const int32_t* rank_p, int seg2,
+                                                            const int32_t* rank2_p, const double* H, double* work,
+                                                            int32_t* status) {
+  extern __shared__ double tl_smem[];
+  double* L = tl_smem;                           // packed lower triangle
+  double* vb = L + TL_MAX * (TL_MAX + 1) / 2;    // v
+  double* wb = vb + TL_MAX;                      // w
+  double* red = wb + TL_MAX;                     // per-wave sums
+  __shared__ double sdg[TL_MAX], sod[TL_MAX], shb[TL_MAX];
+  const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / GREST_WAVE);
+  int s1 = base + (rank_p ? rank_p[0] : 0);
+  s1 = s1 < 0 ? 0 : (s1 > d_full ? d_full : s1);
+  int r2 = rank2_p ? rank2_p[0] : 0;
+  if (!rank2_p) seg2 = s1;
+  if (seg2 < s1) seg2 = s1;
+  r2 = r2 < 0 ? 0 : (r2 > d_full - seg2 ? d_full - seg2 : r2);
+  int n = s1 + r2;
+  if (n > TL_MAX) n = TL_MAX;
+  auto mp = [&](int i) { return i < s1 ? i : seg2 + (i - s1); };
+  double* R = work + W_R;
+  int bad = 0;
+  for (int i = wv; i < n; i += TL_WAVES) {
+    const int mi = mp(i);
+    for (int j = lane; j <= i; j += GREST_WAVE) {
+      const int mj = mp(j);
+      double h = 0.5 * (H[(size_t)mi * d_full + mj] + H[(size_t)mj * d_full + mi]);
+      if (!isfinite(h)) { bad = 1; h = 0.0; }
+      L[tri_at(i, j)] = h;
     }
   }
+  if (bad) atomicOr(status, ST_NONFINITE_H);
+  __syncthreads();
+  const int q = tid & 3;   // quarter of a row
+  const int row = tid >> 2;  // the row of this thread's quad
+  for (int k = 0; k + 2 < n; ++k) {
+    const int j2 = k + 2 + tid;
+    double part = 0.0;
+    if (j2 < n) {
+      const double x = L[tri_at(j2, k)];
+      part = x * x;
+    }
+    const double sigma = tl_block_sum(part, red);
+    const double x0 = L[tri_at(k + 1, k)];
+    double beta = 0.0, v0 = 1.0, ek = x0;
+    if (sigma > 0.0) {
+      const double mu = sqrt(x0 * x0 + sigma);
+      v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma * recip(x0 + mu));
+      beta = 2.0 * v0 * v0 * recip(sigma + v0 * v0);
+      ek = mu;
+    }
+    const double inv = recip(v0);
+    if (tid < MAXN) {
+      const int j = tid;
+      const double vj = (j == k + 1) ? 1.0 : ((j > k + 1 && j < n) ? L[tri_at(j, k)] * inv : 0.0);
+      if (j < TL_MAX) vb[j] = vj;
+      R[(size_t)k * MAXN + j] = vj;
+    }
+    if (tid == 0) { sdg[k] = L[tri_at(k, k)]; sod[k] = ek; shb[k] = beta; }
+    __syncthreads();  // v visible
+    if (beta != 0.0) {
+      const int i = row;
+      const bool act = i > k && i < n;
+      double pp = 0.0;
+      if (act) {
+        for (int j = k + 1 + q; j < n; j += 4) {
+          const double a = j <= i ? L[tri_at(i, j)] : L[tri_at(j, i)];
+          pp = fma(a, vb[j], pp);
+        }
+      }
+      pp += __shfl_xor(pp, 1);
+      pp += __shfl_xor(pp, 2);
+      const double bp = beta * pp;
+      const double pv = tl_block_sum((q == 0 && act) ? bp * vb[i] : 0.0, red);
+      const double Kc = 0.5 * beta * pv;
+      if (q == 0 && i < TL_MAX) wb[i] = act ? fma(-Kc, vb[i], bp) : 0.0;
+      __syncthreads();  // w visible
+      if (act) {
+        const double vi = vb[i], wi = wb[i];
+        for (int j = k + 1 + q; j <= i; j += 4) {
+          const int e = tri_at(i, j);
+          L[e] = fma(-vi, wb[j], fma(-wi, vb[j], L[e]));
+        }
+      }
+    }
+    __syncthreads();  // the step's update is done before the next column is read
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      sdg[n - 2] = L[tri_at(n - 2, n - 2)];
+      sod[n - 2] = L[tri_at(n - 1, n - 2)];
+      shb[n - 2] = 0.0;
+      sdg[n - 1] = L[tri_at(n - 1, n - 1)];
+      sod[n - 1] = 0.0;
+      shb[n - 1] = 0.0;
+    } else if (n == 1) {
+      sdg[0] = L[0];
+      sod[0] = 0.0;
+      shb[0] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (wv == 0) tridiag_finish(n, s1, seg2, sdg, sod, shb, work);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1000,33 +1140,42 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
         }
       }
       __syncthreads();
-      double y0 = lane < n ? yv[lane] : 0.0;
-      double y1 = lane + GREST_WAVE < n ? yv[lane + GREST_WAVE] : 0.0;
+      double y[NCOL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) y[c] = lane + GREST_WAVE * c < n ? yv[lane + GREST_WAVE * c] : 0.0;
       // classical Gram-Schmidt, twice, against the finished members of the cluster
       for (int pass = 0; pass < (nmem > 0 ? 2 : 0); ++pass) {
         for (int q = 0; q < nmem; ++q) {
           const double* yq = Yb + (size_t)mslot[q] * MAXN;
-          const double d = wave_sum_d(y0 * yq[lane] + y1 * yq[lane + GREST_WAVE]);
-          y0 = fma(-d, yq[lane], y0);
-          y1 = fma(-d, yq[lane + GREST_WAVE], y1);
+          double dp = 0.0;
+#pragma unroll
+          for (int c = 0; c < NCOL; ++c) dp = fma(y[c], yq[lane + GREST_WAVE * c], dp);
+          const double d = wave_sum_d(dp);
+#pragma unroll
+          for (int c = 0; c < NCOL; ++c) y[c] = fma(-d, yq[lane + GREST_WAVE * c], y[c]);
         }
       }
-      const double nrm2 = wave_sum_d(y0 * y0 + y1 * y1);
+      double n2p = 0.0;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) n2p = fma(y[c], y[c], n2p);
+      const double nrm2 = wave_sum_d(n2p);
       double s = (nrm2 > 0.0 && isfinite(nrm2)) ? 1.0 / sqrt(nrm2) : 0.0;
       if (s == 0.0) {  // breakdown: fall back to the unit vector of the index
         if (lane == 0) atomicOr(status, ST_NOT_CONVERGED);
-        y0 = (lane == cur) ? 1.0 : 0.0;
-        y1 = (lane + GREST_WAVE == cur) ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) y[c] = (lane + GREST_WAVE * c == cur) ? 1.0 : 0.0;
         s = 1.0;
       }
-      y0 *= s;
-      y1 *= s;
-      if (lane < n) yv[lane] = y0;
-      if (lane + GREST_WAVE < n) yv[lane + GREST_WAVE] = y1;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        y[c] *= s;
+        if (lane + GREST_WAVE * c < n) yv[lane + GREST_WAVE * c] = y[c];
+      }
       __syncthreads();
     }
-    double y0 = lane < n ? yv[lane] : 0.0;
-    double y1 = lane + GREST_WAVE < n ? yv[lane + GREST_WAVE] : 0.0;
+    double y[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) y[c] = lane + GREST_WAVE * c < n ? yv[lane + GREST_WAVE * c] : 0.0;
     // next member of the cluster, if any
     int nxt = -1;
     for (int j = cur + 1; j < n; ++j)
@@ -1034,8 +1183,8 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
     if (nxt >= 0 && !(sev[nxt] - sev[cur] <= ortol)) nxt = -1;
     // the tridiagonal-basis vector, for the later members and for the last launch
     double* yq = Yb + (size_t)cslot * MAXN;
-    yq[lane] = y0;
-    yq[lane + GREST_WAVE] = y1;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) yq[lane + GREST_WAVE * c] = y[c];
     if (lane == 0) { mslot[nmem] = cslot; theta_out[cslot] = sev[cur]; }
     __threadfence_block();
     ++nmem;
@@ -1053,27 +1202,43 @@ __global__ void __launch_bounds__(GREST_WAVE) k_backtr(int d_full, int kk, const
   const double* R = work + W_R;
   const double* hb = work + W_HB;
   const double* Yb = work + W_Y;
-  const double ys0 = Yb[(size_t)slot * MAXN + lane], ys1 = Yb[(size_t)slot * MAXN + lane + GREST_WAVE];
-  double c0 = 0.0, c1 = 0.0;
+  double ys[NCOL], cc[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    ys[c] = Yb[(size_t)slot * MAXN + lane + GREST_WAVE * c];
+    cc[c] = 0.0;
+  }
   for (int t = 0; t < kk; ++t) {
     if (t == slot || work[W_FL + t] == 0.0) continue;
-    const double yt0 = Yb[(size_t)t * MAXN + lane], yt1 = Yb[(size_t)t * MAXN + lane + GREST_WAVE];
-    const double e = wave_sum_d(fma(yt0, ys0, yt1 * ys1));
-    c0 = fma(e, yt0, c0);
-    c1 = fma(e, yt1, c1);
+    double yt[NCOL], ep = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      yt[c] = Yb[(size_t)t * MAXN + lane + GREST_WAVE * c];
+      ep = fma(yt[c], ys[c], ep);
+    }
+    const double e = wave_sum_d(ep);
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) cc[c] = fma(e, yt[c], cc[c]);
   }
-  double y0 = fma(-0.5, c0, ys0), y1 = fma(-0.5, c1, ys1);
+  double y[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) y[c] = fma(-0.5, cc[c], ys[c]);
   // back-transform y <- P_0 ... P_{n-3} y
   for (int k = n - 3; k >= 0; --k) {
     const double beta = hb[k];
-    const double r0 = R[(size_t)k * MAXN + lane], r1 = R[(size_t)k * MAXN + lane + GREST_WAVE];
-    const double d = beta * wave_sum_d(fma(r0, y0, r1 * y1));
-    y0 = fma(-d, r0, y0);
-    y1 = fma(-d, r1, y1);
+    double rk[NCOL], dp = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      rk[c] = R[(size_t)k * MAXN + lane + GREST_WAVE * c];
+      dp = fma(rk[c], y[c], dp);
+    }
+    const double d = beta * wave_sum_d(dp);
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) y[c] = fma(-d, rk[c], y[c]);
   }
   // F row of reduced index i is mp(i); the rows outside the map are zero
-  ysh[lane] = y0;
-  ysh[lane + GREST_WAVE] = y1;
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) ysh[lane + GREST_WAVE * c] = y[c];
   wave_lds_fence();
   for (int r = lane; r < d_full; r += GREST_WAVE) {
     const int i = r < s1 ? r : ((r >= seg2 && r - seg2 < n - s1) ? s1 + (r - seg2) : -1);
@@ -1094,7 +1259,7 @@ __global__ void k_symmetrize(int d, double* H) {
 
 }  // namespace
 
-int64_t eig_work_elems(int d) { return d <= MAXN ? (int64_t)W_END : 0; }
+int64_t eig_work_elems(int d) { return d <= TL_MAX ? (int64_t)W_END : 0; }
 
 int64_t pchol_work_elems(int, int) { return 0; }
 
@@ -1148,12 +1313,20 @@ void launch_pchol2(int m, const double* G, const double* C, int kc, double tol, 
 bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H, int which, int kk,
                       double drop_tol, double* theta, double* F, int32_t* kept, double* work,
                       int32_t* status, hipStream_t s, int seg2, const int32_t* rank2) {
-  if (d_full < 1 || d_full > MAXN || kk < 1 || kk > MAXN) return false;
+  if (d_full < 1 || d_full > TL_MAX || kk < 1 || kk > d_full) return false;
   if (rank2 && (seg2 < base || seg2 > d_full)) return false;
-  if (d_full <= 64)
+  if (d_full <= 64) {
     k_tridiag<64><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, seg2, rank2, H, work, status);
-  else
+  } else if (d_full <= 128) {
     k_tridiag<128><<<1, TRI_WAVES * GREST_WAVE, 0, s>>>(d_full, base, rank, seg2, rank2, H, work, status);
+  } else {
+    static const bool attr = [] {
+      (void)hipFuncSetAttribute((const void*)k_tridiag_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TL_LDS);
+      return true;
+    }();
+    (void)attr;
+    k_tridiag_lds<<<1, TL_THREADS, TL_LDS, s>>>(d_full, base, rank, seg2, rank2, H, work, status);
+  }
   k_bisect<<<d_full, GREST_WAVE, 0, s>>>(work);
   k_eigvec<<<kk, GREST_WAVE, 0, s>>>(d_full, which, kk, drop_tol, work, theta, F, kept, status);
   k_backtr<<<kk, GREST_WAVE, 0, s>>>(d_full, kk, work, F);

@@ -48,6 +48,9 @@ _SIGS = [
                                C.c_int64, C.POINTER(C.c_void_p)]),
     ("grest_set_pairs", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("grest_init_pairs", C.c_int, [C.c_void_p, C.c_int32, C.c_uint64]),
+    ("grest_init_pairs_tol", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_uint64, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double)]),
+    ("grest_init_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("grest_update", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int32]),
     ("grest_update_noalloc", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -80,6 +83,8 @@ _SIGS = [
     ("grest_submit", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_uint64]),
     ("grest_poll", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grest_server_detach", C.c_int, [C.c_void_p, C.c_int32]),
+    ("grest_server_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("grest_server_drain", C.c_int, [C.c_void_p]),
     ("grest_server_destroy", None, [C.c_void_p]),
 ]
@@ -210,8 +215,23 @@ class State:
             raise ValueError("values and X must both be host or both be device arrays")
         _check(lib().grest_set_pairs(self._h, pv, px, wx), "grest_set_pairs")
 
-    def init_pairs(self, iterations: int = 30, seed: int = 0):
-        _check(lib().grest_init_pairs(self._h, int(iterations), int(seed)), "grest_init_pairs")
+    def init_pairs(self, iterations: int = 30, seed: int = 0, tol: Optional[float] = None):
+        """Initial pairs on the device (at most ``iterations`` products with the operator);
+        with ``tol`` the residual target of grest_init_pairs_tol, else the precision's
+        default.  Returns (products used, final residual)."""
+        if tol is None:
+            _check(lib().grest_init_pairs(self._h, int(iterations), int(seed)), "grest_init_pairs")
+            return self.init_stats()
+        p, r = C.c_int32(), C.c_double()
+        _check(lib().grest_init_pairs_tol(self._h, int(iterations), float(tol), int(seed), C.byref(p), C.byref(r)),
+               "grest_init_pairs_tol")
+        return p.value, r.value
+
+    def init_stats(self) -> Tuple[int, float]:
+        """(products, final residual) of the last initial eigensolve."""
+        p, r = C.c_int32(), C.c_double()
+        _check(lib().grest_init_stats(self._h, C.byref(p), C.byref(r)), "grest_init_stats")
+        return p.value, r.value
 
     def update(self, n_new: int, i, j, sign, omega=None, noalloc: bool = False):
         """One update (grest_update); noalloc=True calls grest_update_noalloc, which
@@ -364,6 +384,16 @@ class Server:
                                      st.ctypes.data_as(C.c_void_p), ts.ctypes.data_as(C.c_void_p),
                                      td.ctypes.data_as(C.c_void_p)))
         return tags[:c], st[:c], ts[:c], td[:c]
+
+    def detach(self, graph_id: int) -> int:
+        """Detaches an idle graph; returns the status (OK, EAGAIN while it is busy)."""
+        return int(self._lib.grest_server_detach(self._h, int(graph_id)))
+
+    def memory(self) -> Tuple[int, int]:
+        """(reserved device bytes, budget)."""
+        r, b = C.c_int64(), C.c_int64()
+        _check(self._lib.grest_server_memory(self._h, C.byref(r), C.byref(b)), "grest_server_memory")
+        return r.value, b.value
 
     def drain(self):
         _check(self._lib.grest_server_drain(self._h), "grest_server_drain")

@@ -78,10 +78,11 @@ def test_sbm_n1e6_k32_rsvd_mixed_full_size():
     _run(wl, 32, "rsvd", "adj", 32, 32, 4, 40)
 
 
-def test_chunglu_n4e6_laplacian_k64_full_size():
-    """Chung-Lu n0 = 4e6, mean degree 16, exponent 2.2, combinatorial Laplacian, K = 64
-    smallest, G-REST2 (a 128-wide basis), mixed precision; 2 updates of 1 % node growth."""
+def test_chunglu_n4e6_laplacian_k65_rsvd_full_size():
+    """Chung-Lu n0 = 4e6, mean degree 16, exponent 2.2, combinatorial Laplacian, K = 65
+    smallest (64 non-trivial and the trivial pair), G-REST_RSVD with L = P = 64 (a 194-wide
+    basis), mixed precision; 2 updates of 1 % node growth."""
     t0 = time.time()
     wl = W.preset("chunglu_n4e6", steps=2)
     banner(f"chung-lu n4e6 generated in {time.time() - t0:.1f} s")
-    _run(wl, 64, "g2", "lap", 0, 0, 2, 20)
+    _run(wl, 65, "rsvd", "lap", 64, 64, 2, 20)

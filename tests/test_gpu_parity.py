@@ -347,6 +347,17 @@ def test_laplacian_k64_width_128(prec):
     run_trajectory(wl, 64, "g2", "lap", prec, 2)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_laplacian_k65_rsvd_width_194(prec):
+    """The large Laplacian workload's shape at n0 = 4000: Chung-Lu, combinatorial
+    Laplacian, K = 65 (the 64 smallest non-trivial pairs and the trivial one), G-REST_RSVD
+    with L = P = 64, so the basis is 194 wide (the small eigensolver's LDS-resident
+    tridiagonalisation, the tall products and applies in blocks of 128 columns), 1 % node
+    growth per step."""
+    wl = W.preset("chunglu_n4e6", scale=0.001, steps=3)
+    run_trajectory(wl, 65, "rsvd", "lap", prec, 3, L=64, P=64)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_rsvd_sketch_rank_below_L(prec):
     """Fewer new nodes than L: the sketch keeps fewer than L columns, so the basis
@@ -586,27 +597,67 @@ def test_overlap_mode_matches_one_stream(case):
         assert np.array_equal(a, b)
 
 
-def test_device_init_pairs_match_exact_leading_pairs():
-    banner("device initial eigensolver")
+@pytest.mark.parametrize("op,prec", [("adj", "fp64"), ("lap", "fp64"), ("nlap", "fp64"), ("adj", "fp32")])
+def test_device_init_pairs_match_exact_leading_pairs(op, prec):
+    """The device's initial eigensolver (Chebyshev-filtered block iteration with a residual
+    stop) against dense eigh of the n = 2000 SBM's operator: it stops on its residual
+    before the product budget, and every tracked pair is exact to the precision (FP64:
+    eigenvalues to 1e-10, the separated subspace to 1e-8, the block orthonormal to 1e-12;
+    FP32: 1e-5 and 1e-3)."""
+    banner(f"device initial eigensolver op={op} prec={prec}")
     wl = W.preset("sbm_n2000", steps=0)
     A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
-    st = G.State(wl.rowptr0, wl.col0, k=4, variant="g3", precision="fp64", max_new=8)
-    st.init_pairs(iterations=200, seed=1)
+    k = 8
+    st = G.State(wl.rowptr0, wl.col0, k=k, variant="g3", op=op, precision=prec, max_new=100)
+    tol = 1e-12 if prec == "fp64" else 4e-6
+    products, resid = st.init_pairs(iterations=1500, seed=1, tol=tol)
     vals, X = st.get()
-    th, Xe, _ = O.leading_eigenpairs(A, 4)
-    assert M.eig_rel_error(vals[:1], th[:1]) < 1e-10
-    assert M.eig_rel_error(vals, th) < 1e-3
+    th, Xe, shift = O.leading_eigenpairs(A, k + 1, op)
+    ref = th if op == "adj" else shift - th
+    keys = np.abs(th) if op == "adj" else th
+    kk = M.gap_prefix(keys, k, 1e-3)
+    if op == "adj":
+        e = M.eig_rel_error(vals, ref[:k])
+    else:  # nu relative to the tracked spectrum's scale (nu_1 = 0 for L)
+        e = float(np.abs(vals - ref[:k]).max() / np.abs(ref[:k]).max())
+    sine = M.subspace_sine(X[:, :kk], Xe[:, :kk])
+    orth = M.orthonormality(X)
+    banner(f"  products {products}, resid {resid:.2e}, e_lambda {e:.2e}, sine(k*={kk}) {sine:.2e}, orth {orth:.2e}")
+    assert products < 1500 and resid <= tol
+    assert st.init_stats() == (products, resid)
+    assert e <= TOL_EIG[prec], e
+    assert sine <= TOL_SINE[prec], sine
+    assert orth <= TOL_ORTH[prec], orth
+
+
+def test_device_init_pairs_budget_and_arguments():
+    """With a budget too small to converge the eigensolver keeps the last Rayleigh-Ritz
+    pairs and reports their residual; bad arguments are refused."""
+    banner("device initial eigensolver: budget and arguments")
+    wl = W.preset("sbm_n2000", steps=0)
+    st = G.State(wl.rowptr0, wl.col0, k=4, variant="g3", precision="fp64", max_new=8)
+    products, resid = st.init_pairs(iterations=3, seed=2, tol=1e-14)
+    assert products <= 3 and resid > 1e-14
+    vals, X = st.get()
+    assert np.all(np.isfinite(vals)) and M.orthonormality(X) <= 1e-12
+    for bad in ((0, 1e-12), (10, -1.0), (10, float("nan"))):
+        with pytest.raises(G.GrestError) as e:
+            st.init_pairs(iterations=bad[0], seed=0, tol=bad[1])
+        assert e.value.status == G.EINVAL
 
 
 # ------------------------------------------------------------------------------------
 # full size: the headline workload in the launch configuration the benchmark times
 # ------------------------------------------------------------------------------------
-def test_full_size_single_step_parity():
+def test_full_size_trajectory_parity():
     """n0 = 1e6 SBM, K = 32, RSVD with L = P = 32 (the benchmark's workload and kernel
-    shapes): one update from the same start on the GPU (mixed and FP32) and in the oracle.
-    The start is a few block power iterations on the host (no exact eigensolve at this
-    size); parity is the agreement of the two updates on the same inputs."""
-    wl = W.preset("sbm_n1e6", scale=1.0, steps=1)
+    shapes): a 10-update trajectory from one shared start on the GPU (mixed and FP32) and
+    in the oracle, compared after every update (eigenvalue error, subspace sine and
+    orthonormality at the precision's tolerances).  The start is a few block power
+    iterations on the host (no exact eigensolve at this size); parity is the agreement of
+    the two trajectories on the same inputs."""
+    steps = 10
+    wl = W.preset("sbm_n1e6", scale=1.0, steps=steps)
     A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
     X = W.random_orthonormal(wl.n0, 32, 5)
     for _ in range(6):  # block power iteration with Cholesky QR (host, FP64)
@@ -614,17 +665,26 @@ def test_full_size_single_step_parity():
         R = np.linalg.cholesky(Y.T @ Y).T
         X = np.linalg.solve(R.T, Y.T).T
     th = np.einsum("ij,ij->j", X, A @ X)
-    d = wl.deltas[0]
-    om = W.omega(wl.cfg_id, 0, 1, d.n_new, 64)
-    banner(f"full size: oracle step n0={wl.n0} nnz={A.nnz}")
-    r = O.grest_step(A, X, th, d.n_new, d.i, d.j, d.sign, 32, variant=O.RSVD, L=32, Omega=om)
+    oms = [W.omega(wl.cfg_id, 0, t + 1, d.n_new, 64) for t, d in enumerate(wl.deltas)]
+    ref = []
+    Ao, Xo, tho = A, X, th
+    for t, d in enumerate(wl.deltas):
+        banner(f"full size: oracle step {t + 1} n={Ao.shape[0]} nnz={Ao.nnz}")
+        r = O.grest_step(Ao, Xo, tho, d.n_new, d.i, d.j, d.sign, 32, variant=O.RSVD, L=32, Omega=oms[t])
+        ref.append(r)
+        Ao, Xo, tho = r.A, r.X, r.theta
+    n_fin = wl.n_at(steps) + 1
+    nnz = int(wl.col0.size + 2 * sum(d.n_changes for d in wl.deltas) + 1024)
     for prec in ("mixed", "fp32"):
-        banner(f"full size: GPU step prec={prec}")
-        n_fin = wl.n0 + d.n_new + 1
         st = G.State(wl.rowptr0, wl.col0, k=32, variant="rsvd", precision=prec, L=32, P=32, node_capacity=n_fin,
-                     nnz_capacity=int(wl.col0.size + 2 * d.n_changes + 1024))
+                     nnz_capacity=nnz)
         st.set_pairs(th, X)
-        st.update_delta(d, om)
-        st.sync()
-        check_step(st, r, "adj", prec, 32, f"full size {prec}")
+        st.set_overlap(True)
+        for t, d in enumerate(wl.deltas):
+            banner(f"full size: GPU step {t + 1} prec={prec}")
+            st.update_delta(d, oms[t])
+            st.sync()
+            check_step(st, ref[t], "adj", prec, 32, f"full size {prec} step {t + 1}")
+        rp, col = st.graph()
+        assert np.array_equal(rp, ref[-1].A.indptr) and np.array_equal(col, ref[-1].A.indices)
         st.close()

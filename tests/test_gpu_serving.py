@@ -109,7 +109,11 @@ def test_served_graph_matches_oracle():
                          Omega=_omega(wl, 0, t, d, k))
         A, Xo, tho = r.A, r.X, r.theta
     vals, Xg = st.get()
-    kk = M.gap_prefix(np.abs(tho), k, 1e-3)
+    # the gate covers the prefix separated from the rest of the oracle's Ritz spectrum (all
+    # of its projected matrix's values, not only the K tracked ones)
+    th_all = np.linalg.eigvalsh(r.H)
+    keys = np.abs(th_all[O.select(th_all, th_all.size, O.which_for("adj"))])
+    kk = M.gap_prefix(keys, k, 1e-3)
     assert M.eig_rel_error(vals[:kk], tho[:kk]) <= 1e-10
     if kk > 0:
         assert M.subspace_sine(Xg[:, :kk], Xo[:, :kk]) <= 1e-8
@@ -148,7 +152,7 @@ def test_invalid_request_fails_alone():
 
 def test_admission_limits():
     (wl, k, th, X), = _graphs(1)
-    banner("serving admission")
+    banner("serving admission: budget below one state")
     st = _new_state(wl, k, th, X, "fp64")
     assert st.memory() > 0
     sv = G.Server(lanes=1, hbm_budget_bytes=1)
@@ -156,20 +160,91 @@ def test_admission_limits():
         sv.attach(st)
     assert e.value.status == G.EAGAIN
     sv.close()
-    sv = G.Server(lanes=1, max_queue=1)
-    gid = sv.attach(st)
-    d0, d1 = wl.deltas[0], wl.deltas[1]
-    assert sv.submit(gid, d0.n_new, d0.i, d0.j, d0.sign, _omega(wl, 0, 0, d0, k), tag=1) == G.OK
-    # the first update takes milliseconds; this submission comes microseconds later
-    assert sv.submit(gid, d1.n_new, d1.i, d1.j, d1.sign, _omega(wl, 0, 1, d1, k), tag=2) == G.EAGAIN
+    st.close()
+
+
+def _fresh_insertions(wl, count, seed, avoid=()):
+    """`count` insertions among the initial nodes: pairs that are not edges of the initial
+    graph and do not appear in the change lists `avoid` (so they stay valid whatever of
+    those runs first)."""
+    n = wl.n0
+    taken = set()
+    for r in range(n):
+        for c in wl.col0[wl.rowptr0[r]:wl.rowptr0[r + 1]]:
+            taken.add((r, int(c)))
+    for d in avoid:
+        taken.update(zip(d.i.tolist(), d.j.tolist()))
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        a, b = sorted(rng.integers(0, n, 2).tolist())
+        if a < b and (a, b) not in taken:
+            taken.add((a, b))
+            out.append((a, b))
+    i, j = (np.array(x, dtype=np.int32) for x in zip(*out))
+    return i, j, np.ones(count, dtype=np.int8)
+
+
+def test_admission_by_memory_and_detach():
+    """Admission by device memory, deterministic: the server reserves each graph's
+    footprint plus the growth of its queued requests.  A request that would outgrow the
+    state's node capacity is refused while the budget is tight, a request within the
+    capacities is admitted, and after a detach releases another graph's reservation the
+    growing request is admitted and runs; the reservation then equals the actual
+    footprint of the attached states and never exceeds the budget."""
+    graphs = _graphs(2, n0=600)
+    (wa, ka, tha, Xa), (wb, kb, thb, Xb) = graphs
+    banner("serving admission by memory")
+    # A: node capacity exactly its node count (+1), so appended nodes force a reallocation
+    sa = G.State(wa.rowptr0, wa.col0, k=ka, variant="rsvd", precision="fp64", L=ka, P=ka,
+                 node_capacity=wa.n0 + 1)
+    sa.set_pairs(tha, Xa)
+    sb = G.State(wb.rowptr0, wb.col0, k=kb, variant="rsvd", precision="fp64", L=kb, P=kb,
+                 node_capacity=4 * wb.n0)
+    sb.set_pairs(thb, Xb)
+    ma, mb = sa.memory(), sb.memory()
+    budget = ma + mb + 4096
+    sv = G.Server(lanes=2, hbm_budget_bytes=budget)
+    ga, gb = sv.attach(sa), sv.attach(sb)
+    assert sv.memory() == (ma + mb, budget)
+    d0 = wa.deltas[0]
+    om0 = _omega(wa, 0, 0, d0, ka)
+    assert d0.n_new > 1
+    # growth of A's node buffers does not fit: refused, nothing reserved
+    assert sv.submit(ga, d0.n_new, d0.i, d0.j, d0.sign, om0, tag=1) == G.EAGAIN
+    assert sv.memory()[0] == ma + mb
+    # a request within A's capacities is admitted and runs
+    i1, j1, s1 = _fresh_insertions(wa, 40, 1, avoid=[d0])
+    assert sv.submit(ga, 0, i1, j1, s1, None, tag=2) == G.OK
     sv.drain()
     tags, status, _, _ = sv.poll(16)
-    assert list(tags) == [1] and status[0] == G.OK
+    assert list(tags) == [2] and list(status) == [G.OK]
+    assert sv.memory()[0] == sa.memory() + mb <= budget
+    # detach B: its reservation is released and A's growing request now fits
+    assert sv.detach(gb) == G.OK
+    assert sv.memory()[0] == sa.memory()
+    assert sv.detach(gb) == G.EINVAL
+    assert sv.submit(gb, 0, i1[:1], j1[:1], s1[:1], None, tag=9) == G.EINVAL
+    rc = sv.submit(ga, d0.n_new, d0.i, d0.j, d0.sign, om0, tag=3)
+    assert rc == G.OK, rc
+    assert sv.memory()[0] <= budget
+    sv.drain()
+    tags, status, _, _ = sv.poll(16)
+    assert list(tags) == [3] and list(status) == [G.OK]
+    reserved = sv.memory()[0]
+    assert reserved == sa.memory() and reserved <= budget and sa.memory() > ma
+    assert sa.shape()[0] == wa.n0 + d0.n_new
     sv.close()
-    # the state is usable directly again after the server is gone
-    st.update_delta(d1, _omega(wl, 0, 1, d1, k))
-    st.sync()
-    st.close()
+    # the detached state is usable directly, and so is A after the server is gone
+    db = wb.deltas[0]
+    sb.update_delta(db, _omega(wb, 1, 0, db, kb))
+    sb.sync()
+    class _Pairs:  # the insertions already applied, to be avoided by the last one
+        i, j = i1, j1
+    sa.update(0, *_fresh_insertions(wa, 10, 2, avoid=[d0, _Pairs]))
+    sa.sync()
+    sa.close()
+    sb.close()
 
 
 @pytest.mark.parametrize("graph_id,requests", [(16, 4), (14, 20)])
@@ -236,11 +311,13 @@ def test_restart_policy_inside_served_updates():
 def test_graph_free_lowrank_states_served():
     """Low-rank states that released their graphs (the truncated form keeps Delta alone)
     are admitted with the footprint they have after the release and served with results
-    bitwise those of each graph alone."""
+    bitwise those of each graph alone.  Their node capacity covers every update, so the
+    requests need no growth and fit a budget of exactly the attached footprints."""
     graphs = _graphs(3, steps=3)
 
     def lowrank_state(wl, k, th, X):
-        st = G.State(wl.rowptr0, wl.col0, k=k, variant="rsvd", precision="mixed", L=k, P=k, proj="lowrank")
+        st = G.State(wl.rowptr0, wl.col0, k=k, variant="rsvd", precision="mixed", L=k, P=k, proj="lowrank",
+                     node_capacity=wl.n_at(3) + 1)
         st.set_pairs(th, X)
         before = st.memory()
         st.release_graph()
