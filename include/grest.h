@@ -164,7 +164,8 @@ grest_status grest_init_stats(const grest_state* st, int32_t* products, double* 
  * variant RSVD when n_new > 0, ignored otherwise.  where: GREST_HOST or GREST_DEVICE
  * for all four arrays.
  * The change list is validated before anything is committed: a violation returns
- * GREST_EINVAL and leaves the state exactly as it was.  The rest of the update is
+ * GREST_EINVAL and leaves the state exactly as it was.  One update may change at most
+ * 16,384 edges at any one node (a longer row of Delta is refused as a violation).  The rest of the update is
  * queued on the state's stream; numerical trouble is reported by grest_sync.
  */
 grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei,
@@ -179,8 +180,8 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
  *     stored entries, appended nodes of the sketch, the low-rank gather rows), which
  *     grest_create's node_capacity / nnz_capacity or earlier grest_update calls set;
  *   - n_changes <= 262,144 (2^18).  The buffers sized by the change list (its device
- *     copy, Delta's packed keys, their radix sort, the merge ranks, Delta's columns and
- *     signs) live in one static device array of 28 MiB that every device the library
+ *     copy, Delta's packed keys and their copy grouped by row, the merge ranks, Delta's
+ *     columns and signs) live in one static device array of 20 MiB that every device the library
  *     runs on holds until the process ends;
  *   - the change list's format is checked on the device only (the state is still left
  *     unchanged by a violation, with GREST_EINVAL);

@@ -125,8 +125,6 @@ struct grest_state {
   int8_t* dsg[2] = {nullptr, nullptr};
   int32_t* vstat[2] = {nullptr, nullptr};  // validation bits per slot
   uint64_t *dkey_in = nullptr, *dkey_out = nullptr;  // packed (row, column) keys of Delta
-  char* sort_tmp = nullptr;
-  size_t sort_tmp_bytes = 0;
   int32_t* dins = nullptr;
   int8_t* dsg_tmp = nullptr;
   // row lists of the sparse projection rounds (flags, positions, scan workspace): the
@@ -301,15 +299,13 @@ grest_status alloc_gather_arrays(grest_state* st) {
 grest_status alloc_change_arrays(grest_state* st, int64_t cap_nc) {
   CHK(sync_all(st));  // queued work may still read the old arrays
   dfree(st->d_ei); dfree(st->d_ej); dfree(st->d_sg);
-  dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp);
+  dfree(st->dkey_in); dfree(st->dkey_out);
   dfree(st->dcol[0]); dfree(st->dcol[1]); dfree(st->dins); dfree(st->dsg_tmp); dfree(st->dsg[0]); dfree(st->dsg[1]);
   CHK(dalloc(&st->d_ei, cap_nc));
   CHK(dalloc(&st->d_ej, cap_nc));
   CHK(dalloc(&st->d_sg, cap_nc));
   CHK(dalloc(&st->dkey_in, 2 * cap_nc));
   CHK(dalloc(&st->dkey_out, 2 * cap_nc));
-  st->sort_tmp_bytes = delta_sort_temp_bytes(2 * cap_nc);
-  CHK(dalloc(&st->sort_tmp, st->sort_tmp_bytes));
   for (int b = 0; b < 2; ++b) {
     CHK(dalloc(&st->dcol[b], 2 * cap_nc));
     CHK(dalloc(&st->dsg[b], 2 * cap_nc));
@@ -345,7 +341,7 @@ int64_t device_bytes(const grest_state* st) {
   add(st->rflag); add(st->rpos); add(st->rscan_tmp); add(st->dflag); add(st->dpos); add(st->dscan_tmp);
   add(st->hrows[0]); add(st->hrows[1]); add(st->hcnt[0]); add(st->hcnt[1]); add(st->hflag); add(st->hpos);
   add(st->hscan);
-  add(st->dkey_in); add(st->dkey_out); add(st->sort_tmp); add(st->dins); add(st->dsg_tmp);
+  add(st->dkey_in); add(st->dkey_out); add(st->dins); add(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
     add(st->dptr[b]); add(st->dcol[b]); add(st->dsg[b]); add(st->vstat[b]); add(st->maxdeg[b]);
   }
@@ -366,7 +362,7 @@ void free_all(grest_state* st) {
   dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp); dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
   dfree(st->hrows[0]); dfree(st->hrows[1]); dfree(st->hcnt[0]); dfree(st->hcnt[1]); dfree(st->hflag);
   dfree(st->hpos); dfree(st->hscan);
-  dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->sort_tmp); dfree(st->dins); dfree(st->dsg_tmp);
+  dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->dins); dfree(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
     dfree(st->dptr[b]); dfree(st->dcol[b]); dfree(st->dsg[b]); dfree(st->vstat[b]); dfree(st->maxdeg[b]);
     if (st->gev[b]) (void)hipEventDestroy(st->gev[b]);
@@ -635,16 +631,13 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
 }
 
 // The buffers an update sizes by its change list: the device copies of the change arrays,
-// the packed keys of Delta before and after the sort, the sort's temporary storage, the
-// insertion ranks of the merge, the unsorted signs and the two slots of Delta's columns
-// and signs.  grest_update uses the state's own (grown on demand), grest_update_noalloc
+// the packed keys of Delta before and after they are grouped by row, the insertion ranks
+// of the merge, the ungrouped signs and the two slots of Delta's columns and signs.  grest_update uses the state's own (grown on demand), grest_update_noalloc
 // those carved from the static device workspace.
 struct ChangeBufs {
   int32_t *ei = nullptr, *ej = nullptr;
   int8_t* sg = nullptr;
   uint64_t *kin = nullptr, *kout = nullptr;
-  void* sort_tmp = nullptr;
-  size_t sort_bytes = 0;
   int32_t* dcol[2] = {nullptr, nullptr};
   int8_t* dsg[2] = {nullptr, nullptr};
   int32_t* dins = nullptr;
@@ -655,7 +648,6 @@ ChangeBufs state_change_bufs(const grest_state* st) {
   ChangeBufs b;
   b.ei = st->d_ei; b.ej = st->d_ej; b.sg = st->d_sg;
   b.kin = st->dkey_in; b.kout = st->dkey_out;
-  b.sort_tmp = st->sort_tmp; b.sort_bytes = st->sort_tmp_bytes;
   for (int k = 0; k < 2; ++k) { b.dcol[k] = st->dcol[k]; b.dsg[k] = st->dsg[k]; }
   b.dins = st->dins; b.sg_tmp = st->dsg_tmp;
   return b;
@@ -723,10 +715,10 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   const int kshift = delta_key_shift(n2);
   launch_delta_keys(dei, dej, dsgn, nc, n, S, kshift, cb.kin, cb.sg_tmp, st->dcnt, st->vstat[ds], gs);
   launch_scan_excl(st->dcnt, dptr, n2, st->scan_tmp, gs);
-  if (!launch_delta_sort(cb.kin, cb.kout, cb.sg_tmp, dsg, 2 * nc, 2 * kshift, cb.sort_tmp, cb.sort_bytes, gs)) {
-    snprintf(g_last_error, sizeof(g_last_error), "radix sort of the update could not be launched");
-    return GREST_EDEVICE;
-  }
+  // the keys into their rows, each row sorted by column (the list of long rows uses the
+  // new-length array, which the row pass below fills afterwards)
+  launch_delta_group(cb.kin, cb.sg_tmp, 2 * nc, kshift, n2, dptr, st->dcnt, cb.kout, dsg, st->newlen, st->vstat[ds],
+                     gs);
   launch_delta_extract(cb.kout, 2 * nc, dptr + n2, kshift, dcol, gs);
   const bool gfree = st->graph_free;
   launch_delta_rows(n, S, dptr, dcol, dsg, cb.dins, gfree ? nullptr : st->rp[st->gcur],
@@ -1244,7 +1236,6 @@ int64_t state_bytes_for(const grest_state* st, const StateCaps& c) {
   if (!st->graph_free) b += 2 * c.cap_m * 4;                         // column ids (two buffers)
   const int64_t nc = c.cap_nc;
   b += nc * (4 + 4 + 1) + 2 * nc * (8 + 8 + 2 * 4 + 2 * 1 + 4 + 1);  // change arrays
-  b += (int64_t)delta_sort_temp_bytes(2 * nc);
   if (st->proj == GREST_PROJ_LOWRANK)
     b += 2 * std::max<int64_t>(1, std::min<int64_t>(2 * nc, c.cap_n)) * st->D * es;
   if (st->variant == GREST_RSVD) b += c.cap_s * st->Ls * (2 * es + 8);
@@ -1505,8 +1496,8 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
 }
 
 // The change-list buffers of grest_update_noalloc carved out of the static device
-// workspace (fixed layout for kNoAllocMaxChanges changes, 256-byte aligned pieces; the
-// radix sort's temporary storage takes the rest).  False if the layout does not fit.
+// workspace (fixed layout for kNoAllocMaxChanges changes, 256-byte aligned pieces).
+// False if the layout does not fit.
 bool noalloc_bufs(void* base, ChangeBufs* b) {
   const int64_t nc = kNoAllocMaxChanges;
   size_t off = 0;
@@ -1526,10 +1517,7 @@ bool noalloc_bufs(void* base, ChangeBufs* b) {
   }
   b->dins = (int32_t*)take(2 * nc * sizeof(int32_t));
   b->sg_tmp = (int8_t*)take(2 * nc);
-  if (off >= kNoAllocScratchBytes) return false;
-  b->sort_tmp = (char*)base + off;
-  b->sort_bytes = kNoAllocScratchBytes - off;
-  return true;
+  return off <= kNoAllocScratchBytes;
 }
 
 grest_status grest_update_noalloc(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei,
@@ -1566,7 +1554,6 @@ grest_status grest_update_noalloc(grest_state* st, int64_t n_new, int64_t n_chan
   }
   ChangeBufs cb;
   if (!noalloc_bufs(base, &cb)) return refuse("workspace layout does not fit");
-  if (delta_sort_temp_bytes(2 * n_changes) > cb.sort_bytes) return refuse("sort storage beyond the workspace");
   return st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where, &cb)
                      : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where, &cb);
 }

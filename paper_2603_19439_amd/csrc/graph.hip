@@ -7,8 +7,10 @@
 //   1. the two directed entries of every change become keys (row, column) packed in
 //      64 bits; the entries per row are counted                      (atomics)
 //   2. exclusive scan of the counts -> row offsets of Delta          (3-kernel scan)
-//   3. stable radix sort of the keys (signs carried along), so every row of Delta is
-//      contiguous and sorted by column whatever its length
+//   3. the keys are placed in their rows (each row's slots counted down from its count,
+//      atomics) and every row is sorted by column: a thread per short row (insertion
+//      sort), a workgroup per long row (bitonic sort in LDS), so every row of Delta is
+//      contiguous and sorted whatever its length
 //   4. a group of lanes per row, linear in the row: duplicates, insert/delete checks
 //      against the old row (binary search), per-row prefix counts of insertions and
 //      the new row length
@@ -19,9 +21,9 @@
 // Every write is bounds-checked against the row and the column capacity, so an
 // invalid change list (reported through the status word before anything reads the
 // new graph) can never write out of bounds.
-#include "grest_internal.h"
+#include <algorithm>
 
-#include <hipcub/hipcub.hpp>
+#include "grest_internal.h"
 
 namespace {
 
@@ -417,23 +419,123 @@ void launch_delta_keys(const int32_t* ei, const int32_t* ej, const int8_t* sg, i
   k_delta_keys<<<grid_for(nc), BS, 0, s>>>(ei, ej, sg, nc, n_old, n_old + n_new, shift, keys, vals, cnt, status);
 }
 
-size_t delta_sort_temp_bytes(int64_t items) {
-  size_t bytes = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                           (const int8_t*)nullptr, (int8_t*)nullptr, (int)items, 0, 64);
-  return bytes;
+namespace {
+
+constexpr int SHORT_ROW = 64;      // rows of Delta up to this length are sorted by one thread
+constexpr int LONG_BS = 1024;      // threads of the workgroup that sorts one long row
+
+// Every valid key goes to a slot of its row: the row's count is taken down by one per
+// key, and the slot is the row offset plus the count left (invalid keys, all ones, were
+// never counted and are dropped).  The counts end at zero.
+__global__ void k_delta_bucket(const uint64_t* __restrict__ kin, const int8_t* __restrict__ vin, int64_t items,
+                               int shift, const int64_t* __restrict__ dptr, int64_t* __restrict__ cnt,
+                               uint64_t* __restrict__ kout, int8_t* __restrict__ vout) {
+  const int64_t stride = (int64_t)gridDim.x * BS;
+  for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < items; t += stride) {
+    const uint64_t key = kin[t];
+    if (key == ~0ull) continue;
+    const int64_t row = (int64_t)(key >> shift);
+    const int64_t slot = (int64_t)atomicAdd((unsigned long long*)&cnt[row], (unsigned long long)-1) - 1;
+    const int64_t pos = dptr[row] + slot;
+    kout[pos] = key;
+    vout[pos] = vin[t];
+  }
 }
 
-bool launch_delta_sort(const uint64_t* kin, uint64_t* kout, const int8_t* vin, int8_t* vout, int64_t items,
-                       int end_bit, void* tmp, size_t tmp_bytes, hipStream_t s) {
-  if (items <= 0) return true;
-  size_t need = 0;
-  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)items, 0, end_bit, s) !=
-          hipSuccess ||
-      need > tmp_bytes)
-    return false;
-  return hipcub::DeviceRadixSort::SortPairs(tmp, need, kin, kout, vin, vout, (int)items, 0, end_bit, s) ==
-         hipSuccess;
+// Rows up to SHORT_ROW entries: insertion sort by key in place.  Longer rows go to the
+// list (list[0 .. list[n2])) for k_delta_sort_long; rows longer than LONG_MAX are refused.
+__global__ void k_delta_sort_short(int64_t n2, const int64_t* __restrict__ dptr, uint64_t* __restrict__ keys,
+                                   int8_t* __restrict__ vals, int64_t* __restrict__ list, int32_t* status) {
+  const int64_t stride = (int64_t)gridDim.x * BS;
+  for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n2; r += stride) {
+    const int64_t b = dptr[r], len = dptr[r + 1] - b;
+    if (len <= 1) continue;
+    if (len > SHORT_ROW) {
+      if (len > DELTA_LONG_MAX) {
+        atomicOr(status, ST_BAD_FORMAT);
+      } else {
+        const int64_t q = (int64_t)atomicAdd((unsigned long long*)&list[n2], 1ull);
+        list[q] = r;
+      }
+      continue;
+    }
+    for (int64_t i = 1; i < len; ++i) {
+      const uint64_t k = keys[b + i];
+      const int8_t v = vals[b + i];
+      int64_t j = i - 1;
+      while (j >= 0 && keys[b + j] > k) {
+        keys[b + j + 1] = keys[b + j];
+        vals[b + j + 1] = vals[b + j];
+        --j;
+      }
+      keys[b + j + 1] = k;
+      vals[b + j + 1] = v;
+    }
+  }
+}
+
+// One listed long row per workgroup: bitonic sort of its keys (signs carried) in LDS,
+// padded with all-ones keys to a power of two.
+__global__ void __launch_bounds__(LONG_BS) k_delta_sort_long(int64_t n2, const int64_t* __restrict__ dptr,
+                                                             const int64_t* __restrict__ list,
+                                                             uint64_t* __restrict__ keys, int8_t* __restrict__ vals) {
+  extern __shared__ char sort_smem[];
+  uint64_t* sk = reinterpret_cast<uint64_t*>(sort_smem);
+  int8_t* sv = reinterpret_cast<int8_t*>(sk + DELTA_LONG_MAX);
+  if ((int64_t)blockIdx.x >= list[n2]) return;
+  const int64_t r = list[blockIdx.x];
+  const int64_t b = dptr[r];
+  const int len = (int)(dptr[r + 1] - b);
+  int P = 1;
+  while (P < len) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += LONG_BS) {
+    sk[i] = i < len ? keys[b + i] : ~0ull;
+    sv[i] = i < len ? vals[b + i] : (int8_t)0;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += LONG_BS) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & k) == 0;
+          const uint64_t a = sk[i], c = sk[ixj];
+          if ((a > c) == up) {
+            sk[i] = c;
+            sk[ixj] = a;
+            const int8_t t = sv[i];
+            sv[i] = sv[ixj];
+            sv[ixj] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < len; i += LONG_BS) {
+    keys[b + i] = sk[i];
+    vals[b + i] = sv[i];
+  }
+}
+
+}  // namespace
+
+void launch_delta_group(const uint64_t* kin, const int8_t* vin, int64_t items, int shift, int64_t n2,
+                        const int64_t* dptr, int64_t* cnt, uint64_t* kout, int8_t* vout, int64_t* list,
+                        int32_t* status, hipStream_t s) {
+  if (items <= 0 || n2 <= 0) return;
+  k_delta_bucket<<<grid_for(items), BS, 0, s>>>(kin, vin, items, shift, dptr, cnt, kout, vout);
+  launch_fill_i64(list + n2, 0, 1, s);
+  k_delta_sort_short<<<grid_for(n2), BS, 0, s>>>(n2, dptr, kout, vout, list, status);
+  // rows longer than SHORT_ROW hold more than SHORT_ROW of the items each
+  const int64_t bound = std::min<int64_t>(n2, items / (SHORT_ROW + 1) + 1);
+  const size_t lds = (size_t)DELTA_LONG_MAX * (sizeof(uint64_t) + sizeof(int8_t));
+  static const bool attr = [lds] {
+    (void)hipFuncSetAttribute((const void*)k_delta_sort_long, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return true;
+  }();
+  (void)attr;
+  k_delta_sort_long<<<(unsigned)bound, LONG_BS, lds, s>>>(n2, dptr, list, kout, vout);
 }
 
 void launch_delta_extract(const uint64_t* keys, int64_t items, const int64_t* total, int shift, int32_t* dcol,

@@ -43,11 +43,15 @@ int delta_key_shift(int64_t n2);
 void launch_delta_keys(const int32_t* ei, const int32_t* ej, const int8_t* sg, int64_t nc, int64_t n_old,
                        int64_t n_new, int shift, uint64_t* keys, int8_t* vals, int64_t* cnt, int32_t* status,
                        hipStream_t s);
-// stable radix sort of items keys (bits [0, end_bit)) with their signs; false when the
-// temporary storage is too small or the sort cannot be launched
-size_t delta_sort_temp_bytes(int64_t items);
-bool launch_delta_sort(const uint64_t* kin, uint64_t* kout, const int8_t* vin, int8_t* vout, int64_t items,
-                       int end_bit, void* tmp, size_t tmp_bytes, hipStream_t s);
+// longest row of Delta (changes at one node in one update) the grouping sorts; a longer
+// row marks the update ST_BAD_FORMAT
+constexpr int DELTA_LONG_MAX = 16384;
+// The valid keys of kin (items entries; invalid ones are all ones) placed by row at the
+// offsets dptr (cnt: the per-row counts, taken down to zero) into kout / vout with their
+// signs, each row sorted by column.  list: n2 + 1 entries of scratch.
+void launch_delta_group(const uint64_t* kin, const int8_t* vin, int64_t items, int shift, int64_t n2,
+                        const int64_t* dptr, int64_t* cnt, uint64_t* kout, int8_t* vout, int64_t* list,
+                        int32_t* status, hipStream_t s);
 // column ids of the first *total sorted keys
 void launch_delta_extract(const uint64_t* keys, int64_t items, const int64_t* total, int shift, int32_t* dcol,
                           hipStream_t s);
@@ -227,7 +231,7 @@ void launch_axpby(int64_t rows, int w, double a, const T* X, int64_t ldx, double
 // largest change list of one grest_update_noalloc call, and the size of the device array
 // that holds its change-list buffers (per device, for the life of the process)
 constexpr int64_t kNoAllocMaxChanges = int64_t(1) << 18;
-constexpr size_t kNoAllocScratchBytes = size_t(28) << 20;
+constexpr size_t kNoAllocScratchBytes = size_t(20) << 20;
 // device address of that array on `device` (looked up once per device)
 hipError_t noalloc_scratch(int device, void** out);
 

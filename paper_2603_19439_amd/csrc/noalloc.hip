@@ -1,8 +1,8 @@
 // Static device workspace of grest_update_noalloc, the update that allocates nothing.
 //
 // The buffers an update sizes by its change list -- the copied change arrays, the packed
-// (row, column) keys of Delta and their sorted copy, the radix sort's temporary storage,
-// the insertion ranks of the merge and the two slots of Delta's columns and signs -- are
+// (row, column) keys of Delta and their copy grouped by row, the insertion ranks of the
+// merge and the two slots of Delta's columns and signs -- are
 // allocated by grest_update on demand (they grow with the largest change list seen).  The
 // no-allocation variant takes them from one file-scope device array instead, of a fixed
 // size that every device the library runs on holds until the process ends.  Every call on

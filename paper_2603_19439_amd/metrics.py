@@ -20,13 +20,15 @@ def eig_rel_error(theta: np.ndarray, ref: np.ndarray) -> float:
     return float(np.max(np.abs(theta - ref) / den))
 
 
-def gap_prefix(ref_all: np.ndarray, k: int, rel_gap: float = 1e-3) -> int:
-    """Largest k* <= k whose cut is separated: |ref_{k*} - ref_{k*+1}| >= rel_gap * |ref_1|.
+def gap_prefix(ref_all: np.ndarray, k: int, rel_gap: float = 1e-3, scale: float = None) -> int:
+    """Largest k* <= k whose cut is separated: |ref_{k*} - ref_{k*+1}| >= rel_gap * scale,
+    with scale = |ref_1| unless given.
 
     ``ref_all`` lists the reference values in output order (at least k+1 of them if a
     (k+1)-th value is known)."""
     ref_all = np.asarray(ref_all, dtype=np.float64)
-    scale = max(abs(ref_all[0]), 1e-300) if ref_all.size else 1.0
+    if scale is None:
+        scale = max(abs(ref_all[0]), 1e-300) if ref_all.size else 1.0
     for kk in range(min(k, ref_all.size - 1), 0, -1):
         if abs(ref_all[kk - 1] - ref_all[kk]) >= rel_gap * scale:
             return kk

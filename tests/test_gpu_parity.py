@@ -37,11 +37,15 @@ def check_step(st, r, op, prec, k, label):
     vals, X = st.get()
     ref = oracle_values(r, op)
     # the gate covers the prefix k* <= K of the tracked set that is separated from the
-    # rest by a relative gap >= 1e-3 in the selection key (|theta| for the adjacency)
+    # rest by a gap >= 1e-3 of the scale: |theta_1| for the adjacency, the largest tracked
+    # nu for the Laplacians
     th_all = np.linalg.eigvalsh(r.H)
     order = O.select(th_all, th_all.size, O.which_for(op))
-    keys = np.abs(th_all[order]) if op == "adj" else th_all[order]
-    kk = M.gap_prefix(keys, k, 1e-3)
+    if op == "adj":
+        kk = M.gap_prefix(np.abs(th_all[order]), k, 1e-3)
+    else:  # gaps between the nu = shift - theta, relative to the tracked nu's scale (not the shift)
+        nu = r.shift - th_all[order]
+        kk = M.gap_prefix(nu, k, 1e-3, scale=max(float(np.abs(nu[:k]).max()), 1e-300))
     if op == "adj":
         e = M.eig_rel_error(vals[:kk], ref[:kk])
     else:
@@ -614,8 +618,10 @@ def test_device_init_pairs_match_exact_leading_pairs(op, prec):
     vals, X = st.get()
     th, Xe, shift = O.leading_eigenpairs(A, k + 1, op)
     ref = th if op == "adj" else shift - th
-    keys = np.abs(th) if op == "adj" else th
-    kk = M.gap_prefix(keys, k, 1e-3)
+    if op == "adj":
+        kk = M.gap_prefix(np.abs(th), k, 1e-3)
+    else:
+        kk = M.gap_prefix(ref, k, 1e-3, scale=float(np.abs(ref[:k]).max()))
     if op == "adj":
         e = M.eig_rel_error(vals, ref[:k])
     else:  # nu relative to the tracked spectrum's scale (nu_1 = 0 for L)
