@@ -905,8 +905,9 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   st->hcnt_host[gn] = gfree ? 0 : st->pin->g[ds].hcount;
 
   if (nlap) {
+    const HeavyRows hv = heavy_of(st, gn);
     launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
-                           st->col[gn], sc_new, b.Zc, st->ldz, K, dX, st->ldz, s);
+                           st->col[gn], sc_new, b.Zc, st->ldz, K, dX, st->ldz, s, &hv);
     project();
   }
   mark(st, 4);

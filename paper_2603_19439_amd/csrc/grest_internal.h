@@ -107,11 +107,13 @@ void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int6
                       const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
                       const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s,
                       T* acc_io = nullptr, int64_t ldacc = 0);
-// nlap: V = S'A'S' Xbar - [S A S X; 0] computed row by row from both graphs
+// nlap: V = S'A'S' Xbar - [S A S X; 0] computed row by row from both graphs; with heavy
+// (the new graph's heavy rows) those rows go to a workgroup each
 template <typename T>
 void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
                          const T* s_old, const int64_t* rp_new, const int32_t* col_new, const T* s_new,
-                         const T* X, int64_t ldx, int k, T* V, int64_t ldv, hipStream_t s);
+                         const T* X, int64_t ldx, int k, T* V, int64_t ldv, hipStream_t s,
+                         const HeavyRows* heavy = nullptr);
 
 // ------------------------------------------------------------------------------------
 // dense.hip: tall-skinny dense kernels (row-major blocks, n rows)

@@ -508,6 +508,14 @@ __global__ void __launch_bounds__(RWV * 64) k_tn_reduce(int g, RedJob j0, RedJob
   }
 }
 
+// C[j0 + c][i0 + r] = C[i0 + r][j0 + c] for the wi x wj block at (i0, j0) (leading dimension ldc)
+__global__ void k_mirror_block(double* C, int ldc, int i0, int j0, int wi, int wj) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= wi * wj) return;
+  const int r = idx / wj, c = idx % wj;
+  C[(size_t)(j0 + c) * ldc + i0 + r] = C[(size_t)(i0 + r) * ldc + j0 + c];
+}
+
 inline RedJob red_job(const double* partial, double* C, int a, int b, int ldc = -1) {
   return RedJob{partial, C, a, b, (int)(((int64_t)a * b + 63) / 64), ldc < 0 ? b : ldc};
 }
@@ -873,6 +881,18 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
                    double* partial, double* C, hipStream_t s, int ldc = -1) {
   if (a <= 0 || b <= 0) return;
   if (ldc < 0) ldc = b;
+  if (A == B && lda == ldb && a == b && kind != 2 && ((a + 15) >> 4) > 4) {
+    // a Gram wider than the symmetric kernel's 64 columns: its upper blocks of 64 columns
+    // (the diagonal ones by the symmetric kernel), the lower blocks as their mirrors
+    constexpr int SB = 64;
+    for (int i0 = 0; i0 < a; i0 += SB)
+      for (int j0 = i0; j0 < a; j0 += SB) {
+        const int wi = std::min(SB, a - i0), wj = std::min(SB, a - j0);
+        tn_run<T>(kind, n, A + i0, lda, wi, A + j0, lda, wj, partial, C + (size_t)i0 * ldc + j0, s, ldc);
+        if (j0 > i0) k_mirror_block<<<(wi * wj + 255) / 256, 256, 0, s>>>(C, ldc, i0, j0, wi, wj);
+      }
+    return;
+  }
   if (a > TW || b > TW) {
     // operands wider than the kernels hold: blocks of at most TW columns of each, one after
     // the other on the stream (they share the partial sums), each reduced into its block of C
@@ -887,7 +907,7 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
   int64_t rpc = (n + g - 1) / g;
   rpc = ((rpc + rb - 1) / rb) * rb;
   if (kind == 2 && ((a + 15) >> 4) * ((b + 15) >> 4) > NW * BT) kind = 0;  // too many tiles: FP32 MFMA
-  bool sym = (A == B && lda == ldb && a == b && kind != 2 && ldc == b);
+  bool sym = (A == B && lda == ldb && a == b && kind != 2);
   if (kind == 2) {
     const int tt = std::max((((a + 15) >> 4) + 1) / 2, (((b + 15) >> 4) + 1) / 2);
     const bool staged = a % 4 == 0 && b % 4 == 0 && aligned16(A, lda) && aligned16(B, ldb);

@@ -65,6 +65,16 @@ inline int pick_vec(int w, int64_t ld1, int64_t ld2, const void* p1, const void*
   return 1;
 }
 
+// 8-byte slices for FP32 blocks whose width or offsets are even but not multiples of four
+// (a basis of odd K, e.g. 65 tracked pairs and a 194-wide basis)
+template <typename T>
+inline int pick_vec2(int w, int64_t ld1, int64_t ld2, const void* p1, const void* p2) {
+  const int v = pick_vec<T>(w, ld1, ld2, p1, p2);
+  if (v > 1 || sizeof(T) != 4) return v;
+  if (w % 2 == 0 && ld1 % 2 == 0 && ld2 % 2 == 0 && ((uintptr_t)p1 % 8) == 0 && ((uintptr_t)p2 % 8) == 0) return 2;
+  return 1;
+}
+
 // ---------------------------------------------------------------------------------
 // (op Z) for the stored graph
 // ---------------------------------------------------------------------------------
@@ -198,6 +208,8 @@ void spmm_dispatch(int vec, int64_t n, const int64_t* rp, const int32_t* col, co
   const int64_t skip = hv ? HEAVY_DEG : INT64_MAX;
   if (vec == 16 / (int)sizeof(T))
     k_spmm<T, 16 / sizeof(T), OP><<<g, BS, 0, s>>>(n, rp, col, sc, Z, ldz, w, Y, ldy, ilog2(lpr), skip);
+  else if (vec == 2)
+    k_spmm<T, 2, OP><<<g, BS, 0, s>>>(n, rp, col, sc, Z, ldz, w, Y, ldy, ilog2(lpr), skip);
   else
     k_spmm<T, 1, OP><<<g, BS, 0, s>>>(n, rp, col, sc, Z, ldz, w, Y, ldy, ilog2(lpr), skip);
   if (!hv) return;
@@ -207,6 +219,9 @@ void spmm_dispatch(int vec, int64_t n, const int64_t* rp, const int32_t* col, co
   if (vec == 16 / (int)sizeof(T))
     k_spmm_heavy<T, 16 / sizeof(T), OP><<<hg, HEAVY_BS, lds, s>>>(heavy->rows, heavy->count, rp, col, sc, Z, ldz,
                                                                   w, Y, ldy, ilog2(lpr));
+  else if (vec == 2)
+    k_spmm_heavy<T, 2, OP><<<hg, HEAVY_BS, lds, s>>>(heavy->rows, heavy->count, rp, col, sc, Z, ldz, w, Y, ldy,
+                                                     ilog2(lpr));
   else
     k_spmm_heavy<T, 1, OP><<<hg, HEAVY_BS, lds, s>>>(heavy->rows, heavy->count, rp, col, sc, Z, ldz, w, Y, ldy,
                                                      ilog2(lpr));
@@ -359,41 +374,87 @@ __global__ void __launch_bounds__(BS) k_delta_dense2(DeltaArgs a, const T* __res
   }
 }
 
+// One row of Delta_Tn Xbar for the normalised Laplacian, columns c0 .. c0 + VEC, over the
+// entries [e0, e1) of the new row and [f0, f1) of the old one: the sums of s'_c x_c over
+// the new row's old columns and of s_c x_c over the old row (four gathers in flight).
+template <typename T, int VEC>
+__device__ inline void nlap_dx_range(int64_t n_old, int64_t e0, int64_t e1, const int32_t* __restrict__ coln,
+                                     const T* __restrict__ sn, int64_t f0, int64_t f1,
+                                     const int32_t* __restrict__ colo, const T* __restrict__ so,
+                                     const T* __restrict__ X, int64_t ldx, int c0, T (&a1)[VEC], T (&a0)[VEC]) {
+  int64_t e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    int32_t c[4];
+    T z[4][VEC];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = coln[e + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (c[u] < n_old) vload<T, VEC>(X + (int64_t)c[u] * ldx + c0, z[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (c[u] >= n_old) continue;
+      const T scu = sn[c[u]];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) a1[i] += scu * z[u][i];
+    }
+  }
+  for (; e < e1; ++e) {
+    const int32_t c = coln[e];
+    if (c >= n_old) continue;
+    T z[VEC];
+    vload<T, VEC>(X + (int64_t)c * ldx + c0, z);
+    const T scu = sn[c];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) a1[i] += scu * z[i];
+  }
+  int64_t f = f0;
+  for (; f + 4 <= f1; f += 4) {
+    int32_t c[4];
+    T z[4][VEC];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = colo[f + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vload<T, VEC>(X + (int64_t)c[u] * ldx + c0, z[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T scu = so[c[u]];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) a0[i] += scu * z[u][i];
+    }
+  }
+  for (; f < f1; ++f) {
+    const int32_t c = colo[f];
+    T z[VEC];
+    vload<T, VEC>(X + (int64_t)c * ldx + c0, z);
+    const T scu = so[c];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) a0[i] += scu * z[i];
+  }
+}
+
+// Rows whose new row has more than skip_deg entries are left to k_nlap_dx_heavy.
 template <typename T, int VEC>
 __global__ void __launch_bounds__(BS) k_nlap_dx(int64_t n_old, int64_t n2, const int64_t* __restrict__ rpo,
                                                 const int32_t* __restrict__ colo, const T* __restrict__ so,
                                                 const int64_t* __restrict__ rpn,
                                                 const int32_t* __restrict__ coln, const T* __restrict__ sn,
                                                 const T* __restrict__ X, int64_t ldx, int w,
-                                                T* __restrict__ V, int64_t ldv, int lpr_shift) {
+                                                T* __restrict__ V, int64_t ldv, int lpr_shift, int64_t skip_deg) {
   const int lpr = 1 << lpr_shift;
   const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int gl = (int)(gid & (lpr - 1));
   const int64_t ngroups = ((int64_t)gridDim.x * BS) >> lpr_shift;
   for (int64_t r = gid >> lpr_shift; r < n2; r += ngroups) {
+    const int64_t e0 = rpn[r], e1 = rpn[r + 1];
+    if (e1 - e0 > skip_deg) continue;
+    const int64_t f0 = r < n_old ? rpo[r] : 0, f1 = r < n_old ? rpo[r + 1] : 0;
     for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
       T a1[VEC], a0[VEC];
 #pragma unroll
       for (int i = 0; i < VEC; ++i) { a1[i] = T(0); a0[i] = T(0); }
-      for (int64_t e = rpn[r]; e < rpn[r + 1]; ++e) {
-        const int64_t c = coln[e];
-        if (c >= n_old) continue;
-        T z[VEC];
-        vload<T, VEC>(X + c * ldx + c0, z);
-        const T sc = sn[c];
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) a1[i] += sc * z[i];
-      }
-      if (r < n_old) {
-        for (int64_t e = rpo[r]; e < rpo[r + 1]; ++e) {
-          const int64_t c = colo[e];
-          T z[VEC];
-          vload<T, VEC>(X + c * ldx + c0, z);
-          const T sc = so[c];
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) a0[i] += sc * z[i];
-        }
-      }
+      nlap_dx_range<T, VEC>(n_old, e0, e1, coln, sn, f0, f1, colo, so, X, ldx, c0, a1, a0);
       const T s1 = sn[r];
       const T s0 = r < n_old ? so[r] : T(0);
       T o[VEC];
@@ -404,6 +465,56 @@ __global__ void __launch_bounds__(BS) k_nlap_dx(int64_t n_old, int64_t n2, const
   }
 }
 
+// The heavy rows (of the new graph) of Delta_Tn Xbar: a workgroup per row, its lane groups
+// taking equal shares of the new row's and of the old row's entries, partial sums added in
+// LDS in a fixed order (as k_spmm_heavy).
+template <typename T, int VEC>
+__global__ void __launch_bounds__(HEAVY_BS) k_nlap_dx_heavy(const int32_t* __restrict__ hrows,
+                                                            const int64_t* __restrict__ hcount, int64_t n_old,
+                                                            const int64_t* __restrict__ rpo,
+                                                            const int32_t* __restrict__ colo,
+                                                            const T* __restrict__ so, const int64_t* __restrict__ rpn,
+                                                            const int32_t* __restrict__ coln,
+                                                            const T* __restrict__ sn, const T* __restrict__ X,
+                                                            int64_t ldx, int w, T* __restrict__ V, int64_t ldv,
+                                                            int lpr_shift) {
+  extern __shared__ char nlap_smem[];
+  T* p1 = reinterpret_cast<T*>(nlap_smem);  // [groups][w], then the old row's [groups][w]
+  if ((int64_t)blockIdx.x >= *hcount) return;
+  const int64_t r = hrows[blockIdx.x];
+  const int lpr = 1 << lpr_shift;
+  const int groups = HEAVY_BS >> lpr_shift;
+  T* p0 = p1 + (size_t)groups * w;
+  const int grp = threadIdx.x >> lpr_shift, gl = threadIdx.x & (lpr - 1);
+  const int64_t b1 = rpn[r], l1 = rpn[r + 1] - b1;
+  const int64_t b0 = r < n_old ? rpo[r] : 0, l0 = r < n_old ? rpo[r + 1] - b0 : 0;
+  const int64_t sh1 = (l1 + groups - 1) / groups, sh0 = (l0 + groups - 1) / groups;
+  const int64_t e0 = b1 + min(l1, grp * sh1), e1 = b1 + min(l1, (grp + 1) * sh1);
+  const int64_t f0 = b0 + min(l0, grp * sh0), f1 = b0 + min(l0, (grp + 1) * sh0);
+  for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
+    T a1[VEC], a0[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) { a1[i] = T(0); a0[i] = T(0); }
+    nlap_dx_range<T, VEC>(n_old, e0, e1, coln, sn, f0, f1, colo, so, X, ldx, c0, a1, a0);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      p1[(size_t)grp * w + c0 + i] = a1[i];
+      p0[(size_t)grp * w + c0 + i] = a0[i];
+    }
+  }
+  __syncthreads();
+  const T s1 = sn[r];
+  const T s0 = r < n_old ? so[r] : T(0);
+  for (int c = threadIdx.x; c < w; c += HEAVY_BS) {
+    T t1 = T(0), t0 = T(0);
+    for (int g = 0; g < groups; ++g) {
+      t1 += p1[(size_t)g * w + c];
+      t0 += p0[(size_t)g * w + c];
+    }
+    V[r * ldv + c] = s1 * t1 - s0 * t0;
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -411,7 +522,7 @@ void launch_spmm(int op, int64_t n, const int64_t* rp, const int32_t* col, const
                  int64_t ldz, int64_t nz_rows, int w, T* Y, int64_t ldy, hipStream_t s, const HeavyRows* heavy) {
   (void)nz_rows;
   if (n <= 0 || w <= 0) return;
-  const int vec = pick_vec<T>(w, ldz, ldy, Z, Y);
+  const int vec = pick_vec2<T>(w, ldz, ldy, Z, Y);
   if (op == OPK_ADJ) spmm_dispatch<T, OPK_ADJ>(vec, n, rp, col, sc, Z, ldz, w, Y, ldy, heavy, s);
   else if (op == OPK_LAP) spmm_dispatch<T, OPK_LAP>(vec, n, rp, col, sc, Z, ldz, w, Y, ldy, heavy, s);
   else spmm_dispatch<T, OPK_NLAP>(vec, n, rp, col, sc, Z, ldz, w, Y, ldy, heavy, s);
@@ -467,18 +578,31 @@ void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int6
 template <typename T>
 void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, const int32_t* col_old,
                          const T* s_old, const int64_t* rp_new, const int32_t* col_new, const T* s_new,
-                         const T* X, int64_t ldx, int k, T* V, int64_t ldv, hipStream_t s) {
+                         const T* X, int64_t ldx, int k, T* V, int64_t ldv, hipStream_t s, const HeavyRows* heavy) {
   const int64_t n2 = n_old + n_new;
   if (n2 <= 0 || k <= 0) return;
   const int vec = pick_vec<T>(k, ldx, ldv, X, V);
   const int lpr = lanes_per_row(k, vec);
   const int g = grid_for(n2 * lpr);
+  const bool hv = heavy && heavy->bound > 0;
+  const int64_t skip = hv ? HEAVY_DEG : INT64_MAX;
   if (vec == 16 / (int)sizeof(T))
     k_nlap_dx<T, 16 / sizeof(T)><<<g, BS, 0, s>>>(n_old, n2, rp_old, col_old, s_old, rp_new, col_new,
-                                                  s_new, X, ldx, k, V, ldv, ilog2(lpr));
+                                                  s_new, X, ldx, k, V, ldv, ilog2(lpr), skip);
   else
     k_nlap_dx<T, 1><<<g, BS, 0, s>>>(n_old, n2, rp_old, col_old, s_old, rp_new, col_new, s_new, X, ldx,
-                                     k, V, ldv, ilog2(lpr));
+                                     k, V, ldv, ilog2(lpr), skip);
+  if (!hv) return;
+  const int groups = HEAVY_BS / lpr;
+  const size_t lds = 2 * (size_t)groups * k * sizeof(T);
+  const unsigned hg = (unsigned)std::min<int64_t>(heavy->bound, n2);
+  if (vec == 16 / (int)sizeof(T))
+    k_nlap_dx_heavy<T, 16 / sizeof(T)><<<hg, HEAVY_BS, lds, s>>>(heavy->rows, heavy->count, n_old, rp_old, col_old,
+                                                                 s_old, rp_new, col_new, s_new, X, ldx, k, V, ldv,
+                                                                 ilog2(lpr));
+  else
+    k_nlap_dx_heavy<T, 1><<<hg, HEAVY_BS, lds, s>>>(heavy->rows, heavy->count, n_old, rp_old, col_old, s_old,
+                                                    rp_new, col_new, s_new, X, ldx, k, V, ldv, ilog2(lpr));
 }
 
 #define INST(T)                                                                                       \
@@ -489,7 +613,7 @@ void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, co
                                     T*, int64_t, hipStream_t, T*, int64_t);                           \
   template void launch_nlap_delta_x<T>(int64_t, int64_t, const int64_t*, const int32_t*, const T*,     \
                                        const int64_t*, const int32_t*, const T*, const T*, int64_t,   \
-                                       int, T*, int64_t, hipStream_t);
+                                       int, T*, int64_t, hipStream_t, const HeavyRows*);
 INST(float)
 INST(double)
 #undef INST
