@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--serving-rates", default="50,100,200,500,1000,2000", help="Poisson arrival rates, requests/s")
     ap.add_argument("--serving-requests", default="200,300,500,1000,2000,3000", help="requests per rate")
     ap.add_argument("--serving-lanes", type=int, default=8)
+    ap.add_argument("--serving-batch", type=int, default=1,
+                    help="requests of distinct graphs a lane runs as one batched update (1: one at a time)")
     ap.add_argument("--serving-burst", type=int, default=512,
                     help="requests of the saturation burst (served path vs plain FP32 per-graph path)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -585,7 +587,7 @@ def serving_leg(args):
         states.append(st)
     torch.cuda.synchronize()
     mem = [st.memory() for st in states]
-    sv = G.Server(lanes=args.serving_lanes, max_queue=1 << 16)
+    sv = G.Server(lanes=args.serving_lanes, max_queue=1 << 16, batch=args.serving_batch)
     ids = [sv.attach(st) for st in states]
     nxt = [0] * ng
     results = []
@@ -686,7 +688,8 @@ def serving_leg(args):
         sat = {"requests": len(burst), "served_req_s": round(served, 1), "plain_fp32_per_graph_req_s": round(plain, 1),
                "speedup": round(served / plain, 2)}
         log(args, f"serving burst of {len(burst)}: {served:.0f} req/s served ({args.precision}, "
-                  f"{args.serving_lanes} lanes) vs {plain:.0f} req/s plain FP32 per graph")
+                  f"{args.serving_lanes} lanes, batches of up to {args.serving_batch}) vs {plain:.0f} req/s plain "
+                  f"FP32 per graph")
     else:
         sv.close()
     # accuracy of the probe graphs: graph, and the oracle's replay of all their updates
@@ -718,7 +721,7 @@ def serving_leg(args):
     return {"workload": f"{ng} graphs (SBM or Chung-Lu, n0 {min(g.workload.n0 for g in graphs)}.."
                         f"{max(g.workload.n0 for g in graphs)}, mean degree 8-32, K in {{8,16,32}}, "
                         f"G-REST_RSVD L=P=K), requests of 0.1-1 % new nodes + 0.1-1 % insertions",
-            "lanes": args.serving_lanes, "precision": args.precision,
+            "lanes": args.serving_lanes, "batch": args.serving_batch, "precision": args.precision,
             "device_gib_of_states": round(sum(mem) / 2**30, 2), "rates": results, "saturation": sat,
             "accuracy_probes": acc, "accuracy_gate_passed": passed}
 
@@ -760,6 +763,16 @@ def cpu_baseline(wl, cfg, args, replays, start):
     return out
 
 
+def kernel_source_sha1(csrc):
+    """Short hash of the product kernel's source: spmm.hip and the row-slice helpers it
+    includes (rowvec.h)."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in ("spmm.hip", "rowvec.h"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:12]
+
+
 def measured_traffic(config, width):
     """HBM bytes per launch of the product kernel at this workload, from the committed
     byte-counter summary: measured at two widths and linear in the width in between (a
@@ -767,19 +780,18 @@ def measured_traffic(config, width):
     of the timed updates picks its point on that line.  None when there is no summary for
     the configuration, the kernel source changed since the counters were taken or the
     width lies outside the measured range."""
-    import hashlib
     names = {"c3": "spmm_traffic_sbm_n1e6_k32.txt"}
     if config not in names:
         return None
     path = os.path.join(ROOT, "profiles", names[config])
-    src = os.path.join(ROOT, "paper_2603_19439_amd", "csrc", "spmm.hip")
+    csrc = os.path.join(ROOT, "paper_2603_19439_amd", "csrc")
     try:
         rec = {}
         for line in open(path):
             if "=" in line and not line.startswith(" "):
                 k, v = line.split("=", 1)
                 rec[k.strip()] = v.split()[0]
-        cur = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+        cur = kernel_source_sha1(csrc)
         if rec.get("kernel_source_sha1") != cur:
             return None
         pts = sorted((float(w), float(t)) for w, t in (p.split(":") for p in rec["traffic_points"].split(",")))

@@ -195,6 +195,38 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
 grest_status grest_update_noalloc(grest_state* st, int64_t n_new, int64_t n_changes, const int32_t* ei,
                                   const int32_t* ej, const int8_t* sign, const double* omega, int32_t where);
 
+/*
+ * Updates of several graphs at once (Alg. 2 loop body for each): items[i] names a state
+ * and its update, with the arguments of grest_update.  The updates run in lockstep, each
+ * on its own state's stream: the one-workgroup stages of the method (the Cholesky factors
+ * of CholQR2, Sec. 3.5 step S.2 and the projection of Sec. 4; the small symmetric
+ * eigensolves of Alg. 1 and step S.3) are launched once for all graphs, one workgroup per
+ * graph, each reading its graph's arguments from a descriptor array in device memory,
+ * instead of once per graph.  Every graph gets exactly the computation of its own
+ * grest_update (the same kernels with the same arguments), so its results do not depend
+ * on the other members.
+ *   - 1 <= count <= GREST_BATCH_MAX; the states must be distinct, on one device, and not
+ *     updated by another thread meanwhile.  For the graphs' work to overlap, give the
+ *     states streams of their own (the default).
+ *   - items[i].status receives that member's grest_update status; the call returns
+ *     GREST_OK when every member succeeded, else the first member's failure (the others
+ *     are applied or refused as their own statuses say; grest_last_error names the
+ *     member).  EINVAL with nothing done for a bad count, a NULL or repeated state.
+ * Like grest_update, the call returns once the work is queued; grest_sync each state.
+ */
+#define GREST_BATCH_MAX 64
+typedef struct {
+  grest_state* state;
+  int64_t n_new, n_changes;
+  const int32_t* ei;
+  const int32_t* ej;
+  const int8_t* sign;
+  const double* omega;
+  int32_t where;
+  int32_t status; /* out */
+} grest_batch_item;
+grest_status grest_update_batch(grest_batch_item* items, int32_t count);
+
 /* Wait for queued work and return (then clear) deferred numerical status bits. */
 grest_status grest_sync(grest_state* st);
 
@@ -364,6 +396,15 @@ int64_t grest_now_ns(void);
 /* lanes in [1, 64]; max_queue >= 1. */
 grest_status grest_server_create(int64_t hbm_budget_bytes, int32_t lanes, int32_t max_queue,
                                  grest_server** out);
+
+/* The same server whose lanes run batches: a free lane takes up to max_batch runnable
+ * requests of distinct graphs (oldest first) and runs them as one grest_update_batch, each
+ * graph on one of the lane's max_batch streams, so the one-workgroup stages of up to
+ * max_batch updates go out as single launches.  Order, admission and results are as
+ * above (a graph's result is the same alone or in any batch).  max_batch in [1,
+ * GREST_BATCH_MAX], lanes * max_batch <= 256; max_batch = 1 is grest_server_create. */
+grest_status grest_server_create_batched(int64_t hbm_budget_bytes, int32_t lanes, int32_t max_queue,
+                                         int32_t max_batch, grest_server** out);
 
 /* Attaches a state that already holds its pairs; *graph_id receives its id. */
 grest_status grest_server_attach(grest_server* sv, grest_state* st, int32_t* graph_id);

@@ -12,9 +12,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/grest.h"
@@ -76,6 +80,10 @@ struct grest_state {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
+  // set while the state's update is a member of a batch (grest_update_batch): its
+  // one-workgroup stages are then launched with the other members'
+  BatchCtx* batch = nullptr;
+  int batch_err = 0;  // a failed device call of a batch round
 
   int prec = GREST_FP64;
   size_t es = 8;  // element size of the dense blocks
@@ -465,6 +473,33 @@ Blocks<T> blocks(grest_state* st) {
   return b;
 }
 
+// The one-workgroup stages of an update: launched on the state's stream, or, while the
+// update is a member of a batch, handed to the batch, which launches them with the other
+// members' (the same kernels with the same arguments).
+void pchol2_stage(grest_state* st, int m, const double* G, const double* C, int kc, double* Mout, int32_t* rank) {
+  if (!st->batch) {
+    launch_pchol2(m, G, C, kc, st->tol, Mout, rank, st->status, st->eigwork, st->stream);
+    return;
+  }
+  const CholJob j{m, kc, G, C, st->tol, Mout, rank, st->status, st->eigwork};
+  if (int rc = batch_chol(st->batch, st->stream, j)) st->batch_err = rc;
+}
+
+bool small_eig_stage(grest_state* st, int d_full, int base, const int32_t* rank, const double* H, int which, int kk,
+                     double drop_tol, double* theta, double* F, int32_t* kept, int seg2 = 0,
+                     const int32_t* rank2 = nullptr) {
+  if (!st->batch)
+    return launch_small_eig(d_full, base, rank, H, which, kk, drop_tol, theta, F, kept, st->eigwork, st->status,
+                            st->stream, seg2, rank2);
+  EigJob j{};
+  j.d_full = d_full; j.base = base; j.seg2 = seg2; j.which = which; j.kk = kk;
+  j.rank = rank; j.rank2 = rank2; j.H = H; j.drop_tol = drop_tol;
+  j.theta = theta; j.F = F; j.kept = kept; j.work = st->eigwork; j.status = st->status;
+  if (!small_eig_job_ok(j)) return false;
+  if (int rc = batch_small_eig(st->batch, st->stream, j)) st->batch_err = rc;
+  return true;
+}
+
 // Orthonormal basis of (I - Xbar Xbar^T) W in place (W: n x w, ld), two rounds of block
 // Gram-Schmidt with the Pythagorean Gram (CholQR2 against Xbar): each round reads
 // [Xbar W] once for C = Xbar^T W and the FP64 Gram G = W^T W, factors G - C^T C by
@@ -493,9 +528,9 @@ void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T
         launch_tn<T, false>(n, X, ldx, kx, W, ldw, w, st->partial, st->C1, s);
         launch_tn<T, true>(n, W, ldw, w, W, ldw, w, st->partial, st->Gm, s);
       }
-      launch_pchol2(w, st->Gm, st->C1, kx, st->tol, st->M1buf, st->ranks + slot, st->status, st->eigwork, s);
+      pchol2_stage(st, w, st->Gm, st->C1, kx, st->M1buf, st->ranks + slot);
       launch_apply_pip(n, X, ldx, kx, W, ldw, w, flag2, st->M1buf, Wo, ldw, st->partial, st->C1, st->Gm, s);
-      launch_pchol2(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + 1, st->status, st->eigwork, s);
+      pchol2_stage(st, w, st->Gm, st->C1, kx, st->Mchol, st->ranks + slot + 1);
       if (last_apply) launch_apply2<T>(n, X, ldx, kx, Wo, ldw, w, st->Mchol, w, 1.0, 0.0, Wo, ldw, s);
       return;
     }
@@ -510,7 +545,7 @@ void orth_against(grest_state* st, int64_t n, const T* X, int64_t ldx, int kx, T
       else launch_tn<T, false>(n, X, ldx, kx, Win, ldw, w, st->partial, st->C1, s);
       launch_tn<T, true>(n, Win, ldw, w, Win, ldw, w, st->partial, st->Gm, s);
     }
-    launch_pchol2(w, st->Gm, st->C1, kx, st->tol, st->Mchol, st->ranks + slot + round, st->status, st->eigwork, s);
+    pchol2_stage(st, w, st->Gm, st->C1, kx, st->Mchol, st->ranks + slot + round);
     if (round == 1 && !last_apply) break;
     if (round == 0 && rows && Wout) {
       // W is zero off the listed rows and goes to another buffer: Wout = X (-C M) over
@@ -613,8 +648,8 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   if (gate_slot >= 0 && st->overlap && hipEventRecord(st->gate[gate_slot], st->stream) == hipSuccess)
     st->gate_recorded[gate_slot] = true;
   const int which = st->op == GREST_OP_ADJ ? 0 : 1;
-  if (!launch_small_eig(st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, st->eigwork,
-                        st->status, st->stream, seg2, rank2)) {
+  if (!small_eig_stage(st, st->D, base, rank_slot, st->H, which, st->K, 0.0, st->theta, st->F, nullptr, seg2,
+                       rank2)) {
     snprintf(g_last_error, sizeof(g_last_error), "projected order %d outside the small eigensolver's range", st->D);
     return GREST_EINVAL;
   }
@@ -764,7 +799,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     st->srows_bound = sk_bound;
     st->y_clean = true;
     launch_delta_mul<T>(1, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, (const T*)st->omega_t, Ls, Ls, Y,
-                        st->ldy, gs);
+                        st->ldy, gs, nullptr, 0, st->srows, st->rpos + n2, sk_bound);
   }
   // rows where Delta_1 X can be nonzero (the adjacency's and the Laplacian's form)
   if (sparse_dx || lowrank)
@@ -832,9 +867,16 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   mark(st, 1);
   launch_fill_rows<T>(b.Zc, st->ldz, n, S, st->ldz, s);
   // ---- Delta Xbar = Delta_1 X (Prop. 3) ----
-  if (!nlap)
+  if (sparse_dx) {
+    // zero the block, then visit only the rows of Delta (the row list of the graph stage)
+    launch_fill_rows<T>(dX, st->ldz, 0, n2, K, s);
+    if (reuse) launch_fill_rows<T>(b.aux, st->D, n, S, K, s);
+    launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX, st->ldz, s,
+                        reuse ? b.aux : nullptr, st->D, st->drows, st->dpos + n2, std::min<int64_t>(n2, 2 * nc));
+  } else if (!nlap) {
     launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX,
                         st->ldz, s, reuse ? b.aux : nullptr, st->D);
+  }
   st->ax_valid = false;  // valid again only once this update commits
   mark(st, 2);
   // ---- augmentation block ----
@@ -870,8 +912,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       launch_delta_mul<T>(2, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, Mrows, st->ldy, Ls,
                           (T*)st->bt, Ls, s);
       launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
-      if (!launch_small_eig(Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb, st->ranks + 4,
-                            st->eigwork, st->status, s)) {
+      if (!small_eig_stage(st, Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb,
+                           st->ranks + 4)) {
         (void)hipEventSynchronize(st->gev[ds]);
         st->prev_rejected = true;  // nothing committed; queued work may still read slot ds
         st->marking = false;
@@ -1471,6 +1513,10 @@ grest_status grest_update(grest_state* st, int64_t n_new, int64_t n_changes, con
   // collected at this update's validation wait
   grest_status rc = st->es == 8 ? update_impl<double>(st, n_new, n_changes, ei, ej, sign, omega, where)
                                 : update_impl<float>(st, n_new, n_changes, ei, ej, sign, omega, where);
+  if (st->batch) {  // a batch member: its stages are all queued, the others need not wait for it
+    batch_leave(st->batch);
+    st->batch = nullptr;
+  }
   if (rc != GREST_OK || st->rs_every <= 0) return rc;
   // restart policy: the drift is measured once every rs_every updates (this call then
   // waits for the update); past a threshold the pairs are recomputed from scratch, at
@@ -1878,3 +1924,141 @@ void grest_destroy(grest_state* st) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Batched updates of many graphs (lockstep one-workgroup stages)
+// ---------------------------------------------------------------------------------
+namespace {
+
+// Helper threads for the members of a batch beyond the caller's own, kept for reuse.
+struct BatchRunner {
+  BatchCtx* bc = nullptr;
+  int device = 0;
+  int size = 0;  // members it can run
+  std::vector<std::thread> helpers;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  uint64_t gen = 0;
+  int count = 0, remaining = 0;
+  bool stop = false;
+  const std::function<void(int)>* task = nullptr;
+
+  void helper(int idx) {
+    (void)hipSetDevice(device);
+    uint64_t seen = 0;
+    for (;;) {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop || gen != seen; });
+      if (stop) return;
+      seen = gen;
+      if (idx >= count) continue;
+      const std::function<void(int)>* f = task;
+      lk.unlock();
+      (*f)(idx);
+      lk.lock();
+      if (--remaining == 0) cv_done.notify_all();
+    }
+  }
+  // runs f(0) on the calling thread and f(1 .. count - 1) on the helpers, then returns
+  void run(int n, const std::function<void(int)>& f) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      task = &f;
+      count = n;
+      remaining = n - 1;
+      ++gen;
+    }
+    cv.notify_all();
+    f(0);
+    std::unique_lock<std::mutex> lk(mu);
+    cv_done.wait(lk, [&] { return remaining == 0; });
+  }
+  ~BatchRunner() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto& t : helpers) t.join();
+    batch_destroy(bc);
+  }
+};
+
+std::mutex g_runner_mu;
+std::vector<BatchRunner*> g_runners_free;  // idle runners (any device, any size)
+
+BatchRunner* runner_take(int device, int size) {
+  {
+    std::lock_guard<std::mutex> lk(g_runner_mu);
+    for (size_t i = 0; i < g_runners_free.size(); ++i)
+      if (g_runners_free[i]->device == device && g_runners_free[i]->size >= size) {
+        BatchRunner* r = g_runners_free[i];
+        g_runners_free.erase(g_runners_free.begin() + i);
+        return r;
+      }
+  }
+  BatchRunner* r = new BatchRunner;
+  r->device = device;
+  r->size = std::max(size, 8);
+  r->bc = batch_create(device, r->size);
+  if (!r->bc) {
+    delete r;
+    return nullptr;
+  }
+  for (int i = 1; i < r->size; ++i) r->helpers.emplace_back(&BatchRunner::helper, r, i);
+  return r;
+}
+
+void runner_give(BatchRunner* r) {
+  std::lock_guard<std::mutex> lk(g_runner_mu);
+  g_runners_free.push_back(r);
+}
+
+}  // namespace
+
+grest_status grest_update_batch(grest_batch_item* items, int32_t count) {
+  if (!items || count < 1 || count > GREST_BATCH_MAX) return GREST_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    items[i].status = GREST_EINVAL;
+    if (!items[i].state) return GREST_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (items[j].state == items[i].state) return GREST_EINVAL;
+    if (items[i].state->device != items[0].state->device || items[i].state->batch) return GREST_EINVAL;
+  }
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  const int device = items[0].state->device;
+  if (cur != device) HIPCHK(hipSetDevice(device));
+  BatchRunner* r = runner_take(device, count);
+  if (!r) {
+    for (int i = 0; i < count; ++i) items[i].status = GREST_ENOMEM;
+    if (cur != device) (void)hipSetDevice(cur);
+    snprintf(g_last_error, sizeof(g_last_error), "could not set up a batch of %d", count);
+    return GREST_ENOMEM;
+  }
+  batch_begin(r->bc, count);
+  std::vector<std::string> errs(count);
+  const std::function<void(int)> member = [&](int i) {
+    grest_batch_item& it = items[i];
+    grest_state* st = it.state;
+    st->batch = r->bc;
+    st->batch_err = 0;
+    grest_status rc = grest_update(st, it.n_new, it.n_changes, it.ei, it.ej, it.sign, it.omega, it.where);
+    if (st->batch) {  // returned before its update was queued
+      batch_leave(st->batch);
+      st->batch = nullptr;
+    }
+    if (rc == GREST_OK && st->batch_err) rc = (grest_status)st->batch_err;
+    if (rc != GREST_OK) errs[i] = g_last_error;
+    it.status = rc;
+  };
+  r->run(count, member);
+  runner_give(r);
+  if (cur != device) (void)hipSetDevice(cur);
+  for (int i = 0; i < count; ++i)
+    if (items[i].status != GREST_OK) {
+      snprintf(g_last_error, sizeof(g_last_error), "batch member %d: %s", i, errs[i].c_str());
+      return (grest_status)items[i].status;
+    }
+  return GREST_OK;
+}

@@ -66,7 +66,7 @@ void launch_degrees(int64_t n, const int64_t* rp, double* dinv_sqrt64, float* di
                     int64_t* maxdeg, hipStream_t s);
 
 // ------------------------------------------------------------------------------------
-// spmm.hip: products with the stored graph and with the update
+// spmm.hip: the product with the stored graph; delta.hip: products with the update
 // ------------------------------------------------------------------------------------
 enum OpKind : int32_t { OPK_ADJ = 0, OPK_LAP = 1, OPK_NLAP = 2 };
 
@@ -98,15 +98,18 @@ void launch_heavy_rows(int64_t n, const int64_t* rp, int64_t* flag, int64_t* pos
 //           the rows that can be nonzero are written, the others must be zero already)
 //   mode 2: B = Delta_2^T M              (rows n_old.., all columns, input rows c)
 //   mode 3: write Delta_2 densely into out[:, 0:S] (G-REST3)
-// For lap/nlap the degree and scaling changes are included (see spmm.hip).
+// For lap/nlap the degree and scaling changes are included (see delta.hip).
 // Mode 0 with acc_io: also acc_io[r] += V[r] on old rows with entries, acc_io[r] = V[r] on
 // appended rows (turns a kept product of the old operator with X into the updated
-// operator's product with the padded block).
+// operator's product with the padded block).  Modes 0 and 1 with a row list (rows, *rcount
+// <= bound on the device): only those rows are computed.  Mode 0: out must be zero elsewhere
+// already, and acc_io's appended rows too; mode 1: the list must hold every row it writes.
 template <typename T>
 void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
                       const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
                       const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s,
-                      T* acc_io = nullptr, int64_t ldacc = 0);
+                      T* acc_io = nullptr, int64_t ldacc = 0, const int32_t* rows = nullptr,
+                      const int64_t* rcount = nullptr, int64_t bound = 0);
 // nlap: V = S'A'S' Xbar - [S A S X; 0] computed row by row from both graphs; with heavy
 // (the new graph's heavy rows) those rows go to a workgroup each
 template <typename T>
@@ -210,6 +213,54 @@ bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H
                       int kk, double drop_tol, double* theta, double* F, int32_t* kept,
                       double* work, int32_t* status, hipStream_t s, int seg2 = 0,
                       const int32_t* rank2 = nullptr);
+// One graph's arguments of a CholQR factor (as launch_pchol2) or of a small eigensolve (as
+// launch_small_eig), for the batched launches that serve many graphs at once.
+struct CholJob {
+  int m, kc;
+  const double* G;
+  const double* C;
+  double tol;
+  double* Mout;
+  int32_t* rank;
+  int32_t* status;
+  double* work;
+};
+struct EigJob {
+  int d_full, base, seg2, which, kk;
+  const int32_t* rank;
+  const int32_t* rank2;
+  const double* H;
+  double drop_tol;
+  double* theta;
+  double* F;
+  int32_t* kept;
+  double* work;
+  int32_t* status;
+  int b0_bisect, b0_vec;  // first block of the job in the batched grids (set by the prepare step)
+};
+bool small_eig_job_ok(const EigJob& j);  // the range launch_small_eig accepts
+// Batched launches over nj jobs of different graphs: *_prepare orders the host array by
+// kernel instance (and sets the block offsets); the caller copies it to dev (same layout,
+// device memory) and calls *_launch with both on one stream.  Each job gets exactly the
+// computation of its single-graph launch.
+void chol_batch_prepare(CholJob* jobs, int nj);
+void chol_batch_launch(const CholJob* jobs, const CholJob* dev, int nj, hipStream_t s);
+void small_eig_batch_prepare(EigJob* jobs, int nj);
+void small_eig_batch_launch(const EigJob* jobs, const EigJob* dev, int nj, hipStream_t s);
+
+// Many graphs' updates in lockstep (grest_update_batch): member threads meet at each
+// one-workgroup stage and the last one to arrive launches that stage for all of them on
+// the batch stream, which waits for the members' streams and which they wait for in turn.
+struct BatchCtx;
+BatchCtx* batch_create(int device, int max_members);
+void batch_destroy(BatchCtx* bc);
+void batch_begin(BatchCtx* bc, int members);
+// called by a member at a stage; returns once that stage is queued for every member, with 0
+// or the grest_status of a failed device call
+int batch_chol(BatchCtx* bc, hipStream_t s, const CholJob& job);
+int batch_small_eig(BatchCtx* bc, hipStream_t s, const EigJob& job);
+void batch_leave(BatchCtx* bc);  // a member that has no stage left
+
 // H = 0.5 (H + H^T) of a d x d matrix in place
 void launch_symmetrize(int d, double* H, hipStream_t s);
 template <typename T>

@@ -1,10 +1,13 @@
 // Batched execution of many independent graphs on one device (the serving loop).
 //
-// A server runs `lanes` worker threads, each with its own HIP stream (default priority).
+// A server runs `lanes` worker threads, each with its own HIP streams (default priority).
 // Requests wait in one queue in submission order.  A free lane takes the oldest request
 // whose graph is not being updated by another lane, moves that graph's state onto its
 // own stream (the state is idle then, so the move costs no wait) and runs the request as
 // a complete single-graph update (grest_update, then grest_sync for the deferred status).
+// With batches (max_batch > 1) a free lane takes up to max_batch such requests, of
+// distinct graphs, oldest first, puts each graph on one of its max_batch streams and runs
+// them as one grest_update_batch: their one-workgroup stages are launched together.
 // So one graph's updates stay ordered and never overlap, no lane idles while a runnable
 // request waits behind a long update of another graph, and the lanes overlap on the
 // device.  Requests own copies of their change lists.  Completions are kept until
@@ -61,7 +64,7 @@ struct Graph {
   int64_t bytes;      // reserved device bytes: the footprint once its queued requests have run
   int64_t sketch_cols;  // L + P of an RSVD state, else 0
   StateCaps proj;       // capacities and sizes once every queued request of the graph has run
-  int32_t lane;         // lane whose stream the state is on
+  int32_t slot;         // server stream the state is on (lane * max_batch + member)
   int32_t queued;       // its requests queued or running
   bool running;         // a lane is updating it
   bool detached;
@@ -72,8 +75,8 @@ struct Graph {
 struct grest_server {
   int device = 0;
   int64_t budget = 0, used = 0;
-  int32_t nlanes = 0, max_queue = 0;
-  std::vector<hipStream_t> streams;
+  int32_t nlanes = 0, max_queue = 0, max_batch = 1;
+  std::vector<hipStream_t> streams;  // lane l's streams: [l * max_batch, (l + 1) * max_batch)
   std::deque<Request> queue;  // submission order
   std::vector<std::thread> workers;
   std::vector<Graph> graphs;
@@ -88,60 +91,92 @@ namespace {
 
 void worker(grest_server* sv, int lane) {
   (void)hipSetDevice(sv->device);
+  const int nb = sv->max_batch;
+  std::vector<Request> rqs;
+  std::vector<grest_state*> sts;
+  std::vector<bool> moves;
+  std::vector<grest_batch_item> items;
   for (;;) {
-    Request rq;
-    grest_state* st = nullptr;
-    bool move = false;
+    rqs.clear();
+    sts.clear();
+    moves.clear();
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      // the oldest request whose graph is idle (the graph's own requests are in order)
+      // the oldest requests whose graphs are idle (a graph's own requests are in order),
+      // at most one per graph
       auto runnable = [&] {
         for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
-          if (!sv->graphs[it->gid].running) return it;
-        return sv->queue.end();
+          if (!sv->graphs[it->gid].running) return true;
+        return false;
       };
-      auto it = sv->queue.end();
-      sv->cv_work.wait(lk, [&] { return (it = runnable()) != sv->queue.end() || (sv->stop && sv->queue.empty()); });
-      if (it == sv->queue.end()) return;  // stop requested and nothing left
-      rq = std::move(*it);
-      sv->queue.erase(it);
-      Graph& g = sv->graphs[rq.gid];  // under the lock: attach may grow the table
-      g.running = true;
-      st = g.st;
-      move = g.lane != lane;
-      g.lane = lane;
-    }
-    // the state is idle (its last update ended with grest_sync), while its old stream may
-    // be running another graph's update: no wait on that stream
-    if (move) state_rebind_stream(st, sv->streams[lane]);
-    const int64_t nc = (int64_t)rq.ei.size();
-    const grest_status ru = grest_update(st, rq.n_new, nc, nc ? rq.ei.data() : nullptr,
-                                         nc ? rq.ej.data() : nullptr, nc ? rq.sg.data() : nullptr,
-                                         rq.has_omega ? rq.omega.data() : nullptr, GREST_HOST);
-    // waits for the update and reads its deferred numerical status (the update has
-    // committed even when that status is not OK)
-    const grest_status rs = grest_sync(st);
-    const grest_status rc = ru != GREST_OK ? ru : rs;
-    const int64_t t_done = now_ns();
-    {
-      std::lock_guard<std::mutex> lk(sv->mu);
-      Graph& g = sv->graphs[rq.gid];
-      g.running = false;
-      if (--g.queued == 0) {
-        // nothing else queued for the graph: its reservation becomes its actual footprint
-        // (a rejected request did not grow it; the capacities may have grown by less)
-        int64_t actual = g.bytes;
-        if (grest_memory(st, &actual) == GREST_OK) {
-          sv->used += actual - g.bytes;
-          g.bytes = actual;
+      sv->cv_work.wait(lk, [&] { return runnable() || (sv->stop && sv->queue.empty()); });
+      if (!runnable()) return;  // stop requested and nothing left
+      for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)rqs.size() < nb;) {
+        Graph& g = sv->graphs[it->gid];  // under the lock: attach may grow the table
+        if (g.running) {
+          ++it;
+          continue;
         }
-        state_caps(st, &g.proj);
+        g.running = true;
+        const int32_t slot = lane * nb + (int32_t)rqs.size();
+        moves.push_back(g.slot != slot);
+        g.slot = slot;
+        sts.push_back(g.st);
+        rqs.push_back(std::move(*it));
+        it = sv->queue.erase(it);
       }
-      sv->done.push_back(Done{rq.tag, (int32_t)rc, rq.t_submit, t_done});
-      --sv->pending;
     }
-    sv->cv_idle.notify_all();
-    sv->cv_work.notify_all();  // the graph's next request may be runnable now
+    // each state is idle (its last update ended with grest_sync), while its old stream may
+    // be running another graph's update: no wait on that stream
+    const int cnt = (int)rqs.size();
+    for (int i = 0; i < cnt; ++i)
+      if (moves[i]) state_rebind_stream(sts[i], sv->streams[lane * nb + i]);
+    std::vector<grest_status> ru(cnt, GREST_OK);
+    if (cnt == 1) {
+      const Request& rq = rqs[0];
+      const int64_t nc = (int64_t)rq.ei.size();
+      ru[0] = grest_update(sts[0], rq.n_new, nc, nc ? rq.ei.data() : nullptr, nc ? rq.ej.data() : nullptr,
+                           nc ? rq.sg.data() : nullptr, rq.has_omega ? rq.omega.data() : nullptr, GREST_HOST);
+    } else {
+      items.assign(cnt, grest_batch_item{});
+      for (int i = 0; i < cnt; ++i) {
+        const Request& rq = rqs[i];
+        const int64_t nc = (int64_t)rq.ei.size();
+        items[i] = grest_batch_item{sts[i], rq.n_new, nc, nc ? rq.ei.data() : nullptr, nc ? rq.ej.data() : nullptr,
+                                    nc ? rq.sg.data() : nullptr, rq.has_omega ? rq.omega.data() : nullptr,
+                                    GREST_HOST, GREST_OK};
+      }
+      (void)grest_update_batch(items.data(), cnt);  // every member's own status is in its item
+      for (int i = 0; i < cnt; ++i) ru[i] = (grest_status)items[i].status;
+    }
+    for (int i = 0; i < cnt; ++i) {
+      const Request& rq = rqs[i];
+      grest_state* st = sts[i];
+      // waits for the update and reads its deferred numerical status (the update has
+      // committed even when that status is not OK)
+      const grest_status rs = grest_sync(st);
+      const grest_status rc = ru[i] != GREST_OK ? ru[i] : rs;
+      const int64_t t_done = now_ns();
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        Graph& g = sv->graphs[rq.gid];
+        g.running = false;
+        if (--g.queued == 0) {
+          // nothing else queued for the graph: its reservation becomes its actual footprint
+          // (a rejected request did not grow it; the capacities may have grown by less)
+          int64_t actual = g.bytes;
+          if (grest_memory(st, &actual) == GREST_OK) {
+            sv->used += actual - g.bytes;
+            g.bytes = actual;
+          }
+          state_caps(st, &g.proj);
+        }
+        sv->done.push_back(Done{rq.tag, (int32_t)rc, rq.t_submit, t_done});
+        --sv->pending;
+      }
+      sv->cv_idle.notify_all();
+      sv->cv_work.notify_all();  // the graph's next request may be runnable now
+    }
   }
 }
 
@@ -152,9 +187,15 @@ extern "C" {
 int64_t grest_now_ns(void) { return now_ns(); }
 
 grest_status grest_server_create(int64_t hbm_budget_bytes, int32_t lanes, int32_t max_queue, grest_server** out) {
+  return grest_server_create_batched(hbm_budget_bytes, lanes, max_queue, 1, out);
+}
+
+grest_status grest_server_create_batched(int64_t hbm_budget_bytes, int32_t lanes, int32_t max_queue,
+                                         int32_t max_batch, grest_server** out) {
   if (!out) return GREST_EINVAL;
   *out = nullptr;
   if (lanes < 1 || lanes > 64 || max_queue < 1 || hbm_budget_bytes < 0) return GREST_EINVAL;
+  if (max_batch < 1 || max_batch > GREST_BATCH_MAX || lanes * max_batch > 256) return GREST_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GREST_ENODEV;
   grest_server* sv = new (std::nothrow) grest_server();
@@ -163,7 +204,8 @@ grest_status grest_server_create(int64_t hbm_budget_bytes, int32_t lanes, int32_
   sv->budget = hbm_budget_bytes;
   sv->nlanes = lanes;
   sv->max_queue = max_queue;
-  for (int l = 0; l < lanes; ++l) {
+  sv->max_batch = max_batch;
+  for (int l = 0; l < lanes * max_batch; ++l) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       for (hipStream_t t : sv->streams) (void)hipStreamDestroy(t);
@@ -191,8 +233,9 @@ grest_status grest_server_attach(grest_server* sv, grest_state* st, int32_t* gra
   if (sv->budget > 0 && sv->used + bytes > sv->budget) return GREST_EAGAIN;
   const int32_t id = (int32_t)sv->graphs.size();
   void* user = state_user_stream(st);
-  if ((rc = grest_set_stream(st, sv->streams[id % sv->nlanes])) != GREST_OK) return rc;
-  Graph g{st, user, bytes, state_sketch_cols(st), StateCaps{}, id % sv->nlanes, 0, false, false};
+  const int32_t slot = (id % sv->nlanes) * sv->max_batch;
+  if ((rc = grest_set_stream(st, sv->streams[slot])) != GREST_OK) return rc;
+  Graph g{st, user, bytes, state_sketch_cols(st), StateCaps{}, slot, 0, false, false};
   state_caps(st, &g.proj);
   sv->graphs.push_back(g);
   sv->used += bytes;

@@ -20,6 +20,8 @@
 //      between neighbours, then the back-transform through the reflectors.
 // Orders up to 128 are tridiagonalised with the matrix in registers; larger ones, up to
 // TL_MAX = 196, with the lower triangle of the matrix packed in LDS (k_tridiag_lds).
+#include <algorithm>
+
 #include "grest_internal.h"
 
 #include <math.h>
@@ -149,9 +151,9 @@ __device__ __forceinline__ bool chosen_bit(uint64_t c0, uint64_t c1, int j) {
 }
 
 template <int M, bool CL>
-__global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const double* G, const double* Cg, int kc, double tol,
+__device__ __forceinline__ void pchol_body(int m, const double* G, const double* Cg, int kc, double tol,
                                               double* Mout, int32_t* rank_out, int32_t* status,
-                                              const int32_t* done) {
+                                              const int32_t* done, const int bx) {
   constexpr int NW = PCH_WAVES, EB = PCH_WAVES * GREST_WAVE;
   if (done && *done) return;  // the factor is already there (k_chol_np)
   constexpr int CC = M / GREST_WAVE, RW = M / NW, LP = M + 1;
@@ -326,6 +328,13 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
   if (tid == 0) *rank_out = r;
 }
 
+template <int M, bool CL>
+__global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const double* G, const double* Cg, int kc, double tol,
+                                              double* Mout, int32_t* rank_out, int32_t* status,
+                                              const int32_t* done) {
+  pchol_body<M, CL>(m, G, Cg, kc, tol, Mout, rank_out, status, done, (int)blockIdx.x);
+}
+
 // ------------------------------------------------------------------------------------
 // Cholesky factor without pivoting, tried first in every CholQR round: the Gram matrix of
 // a full-rank block (and of the second round, close to the identity on the columns the
@@ -343,9 +352,9 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
 constexpr int CNP_M = 64, CNP_T = 256, CNP_P = CNP_M + 1;
 constexpr size_t kCnpDynMax = (size_t)CNP_M * CNP_M * sizeof(double);  // the block C (kc <= 64)
 
-__global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restrict__ G, const double* __restrict__ Cg,
+__device__ __forceinline__ void chol_np_body(int m, const double* __restrict__ G, const double* __restrict__ Cg,
                                                   int kc, double tol, double* __restrict__ Mout,
-                                                  int32_t* rank_out, int32_t* done) {
+                                                  int32_t* rank_out, int32_t* done, const int bx) {
   constexpr int NB = CNP_M / 16;  // a thread's rows (and columns) on a 16 x 16 thread grid
   // Each thread keeps its 4 x 4 entries (rows ty + 16 a, columns tx + 16 b) of S, later of
   // X = R^{-1}, in registers; what the other threads need goes through LDS one row at a
@@ -597,6 +606,12 @@ __global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restri
   }
 }
 
+__global__ void __launch_bounds__(CNP_T) k_chol_np(int m, const double* __restrict__ G, const double* __restrict__ Cg,
+                                                  int kc, double tol, double* __restrict__ Mout,
+                                                  int32_t* rank_out, int32_t* done) {
+  chol_np_body(m, G, Cg, kc, tol, Mout, rank_out, done, (int)blockIdx.x);
+}
+
 // ------------------------------------------------------------------------------------
 // 1. tridiagonalisation T = Q^T A Q, Q = P_0 ... P_{n-3}, P_k = I - beta_k v_k v_k^T
 // The tridiagonal T (diagonal sdg, off-diagonal sod, reflector coefficients shb, all of
@@ -652,10 +667,10 @@ __device__ void tridiag_finish(int n, int s1, int seg2, const double* sdg, const
 // packed blocks); index i of the reduced matrix is H index i for i < s1, else
 // seg2 + i - s1.  The back-transform writes F through the same map.
 template <int M>
-__global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, int base, const int32_t* rank_p,
+__device__ __forceinline__ void tridiag_body(int d_full, int base, const int32_t* rank_p,
                                                                     int seg2, const int32_t* rank2_p,
                                                                     const double* H, double* work,
-                                                                    int32_t* status) {
+                                                                    int32_t* status, const int bx) {
   constexpr int NW = TRI_WAVES;
   constexpr int C = M / GREST_WAVE, RW = M / NW;
   __shared__ double pwv[2][NW][M];
@@ -818,6 +833,14 @@ __global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, 
   if (wv == 0) tridiag_finish(n, s1, seg2, sdg, sod, shb, work);
 }
 
+template <int M>
+__global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag(int d_full, int base, const int32_t* rank_p,
+                                                                    int seg2, const int32_t* rank2_p,
+                                                                    const double* H, double* work,
+                                                                    int32_t* status) {
+  tridiag_body<M>(d_full, base, rank_p, seg2, rank2_p, H, work, status, (int)blockIdx.x);
+}
+
 // Householder tridiagonalisation of orders above 128 (up to TL_MAX), with the same
 // reflector convention and outputs as k_tridiag: the lower triangle of the matrix lives in
 // LDS, packed by rows (row i holds columns 0..i at offset i (i + 1) / 2), and one
@@ -845,9 +868,9 @@ __device__ __forceinline__ double tl_block_sum(double v, double* red) {
   return s;
 }
 
-__global__ void __launch_bounds__(TL_THREADS) k_tridiag_lds(int d_full, int base, const int32_t* rank_p, int seg2,
+__device__ __forceinline__ void tridiag_lds_body(int d_full, int base, const int32_t* rank_p, int seg2,
                                                             const int32_t* rank2_p, const double* H, double* work,
-                                                            int32_t* status) {
+                                                            int32_t* status, const int bx) {
   extern __shared__ double tl_smem[];
   double* L = tl_smem;                           // packed lower triangle
   double* vb = L + TL_MAX * (TL_MAX + 1) / 2;    // v
@@ -950,6 +973,12 @@ __global__ void __launch_bounds__(TL_THREADS) k_tridiag_lds(int d_full, int base
   if (wv == 0) tridiag_finish(n, s1, seg2, sdg, sod, shb, work);
 }
 
+__global__ void __launch_bounds__(TL_THREADS) k_tridiag_lds(int d_full, int base, const int32_t* rank_p, int seg2,
+                                                            const int32_t* rank2_p, const double* H, double* work,
+                                                            int32_t* status) {
+  tridiag_lds_body(d_full, base, rank_p, seg2, rank2_p, H, work, status, (int)blockIdx.x);
+}
+
 // ------------------------------------------------------------------------------------
 // 2. eigenvalues: one wave per index t, 64-way multisection on the inertia count
 // ------------------------------------------------------------------------------------
@@ -970,9 +999,9 @@ __device__ __forceinline__ int sturm_count(const double* dg, const double* e2, i
 
 __device__ __forceinline__ double probe_at(double lo, double w, int s) { return lo + w * ((double)s * (1.0 / 65.0)); }
 
-__global__ void __launch_bounds__(GREST_WAVE) k_bisect(double* work) {
+__device__ __forceinline__ void bisect_body(double* work, const int bx) {
   __shared__ double sdg[MAXN], se2[MAXN];
-  const int t = blockIdx.x, lane = threadIdx.x;
+  const int t = bx, lane = threadIdx.x;
   const int n = (int)work[W_HDR];
   if (t >= n) return;
   for (int i = lane; i < n; i += GREST_WAVE) { sdg[i] = work[W_DG + i]; se2[i] = work[W_E2 + i]; }
@@ -993,6 +1022,10 @@ __global__ void __launch_bounds__(GREST_WAVE) k_bisect(double* work) {
     hi = nhi;
   }
   if (lane == 0) work[W_EV + t] = 0.5 * (lo + hi);
+}
+
+__global__ void __launch_bounds__(GREST_WAVE) k_bisect(double* work) {
+  bisect_body(work, (int)blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1020,14 +1053,14 @@ __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
   return ((double)(h & 0xFFFFFF) / 16777216.0) - 0.5;
 }
 
-__global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, int kk, double drop_tol,
+__device__ __forceinline__ void eigvec_body(int d_full, int which, int kk, double drop_tol,
                                                        double* work, double* theta_out, double* F,
-                                                       int32_t* kept_out, int32_t* status) {
+                                                       int32_t* kept_out, int32_t* status, const int bx) {
   __shared__ double sev[MAXN], sdg[MAXN], sod[MAXN];
   __shared__ double u0i[MAXN], u1[MAXN], u2[MAXN], lm[MAXN], yv[MAXN];
   __shared__ unsigned char pv[MAXN];
   __shared__ int ssel[MAXN], sslot[MAXN], mslot[MAXN];
-  const int slot = blockIdx.x, lane = threadIdx.x;
+  const int slot = bx, lane = threadIdx.x;
   const int n = (int)work[W_HDR];
   const double tnorm = work[W_HDR + 3];
   double* Yb = work + W_Y;
@@ -1193,9 +1226,15 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
   }
 }
 
-__global__ void __launch_bounds__(GREST_WAVE) k_backtr(int d_full, int kk, const double* work, double* F) {
+__global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, int kk, double drop_tol,
+                                                       double* work, double* theta_out, double* F,
+                                                       int32_t* kept_out, int32_t* status) {
+  eigvec_body(d_full, which, kk, drop_tol, work, theta_out, F, kept_out, status, (int)blockIdx.x);
+}
+
+__device__ __forceinline__ void backtr_body(int d_full, int kk, const double* work, double* F, const int bx) {
   __shared__ double ysh[MAXN];
-  const int slot = blockIdx.x, lane = threadIdx.x;
+  const int slot = bx, lane = threadIdx.x;
   if (work[W_FL + slot] == 0.0) return;
   const int n = (int)work[W_HDR];
   const int s1 = (int)work[W_HDR + 5], seg2 = (int)work[W_HDR + 6];
@@ -1244,6 +1283,10 @@ __global__ void __launch_bounds__(GREST_WAVE) k_backtr(int d_full, int kk, const
     const int i = r < s1 ? r : ((r >= seg2 && r - seg2 < n - s1) ? s1 + (r - seg2) : -1);
     F[(size_t)r * kk + slot] = i >= 0 ? ysh[i] : 0.0;
   }
+}
+
+__global__ void __launch_bounds__(GREST_WAVE) k_backtr(int d_full, int kk, const double* work, double* F) {
+  backtr_body(d_full, kk, work, F, (int)blockIdx.x);
 }
 
 __global__ void k_symmetrize(int d, double* H) {
@@ -1336,4 +1379,172 @@ bool launch_small_eig(int d_full, int base, const int32_t* rank, const double* H
 void launch_symmetrize(int d, double* H, hipStream_t s) {
   int nthr = d * d;
   k_symmetrize<<<(nthr + 255) / 256, 256, 0, s>>>(d, H);
+}
+
+// ------------------------------------------------------------------------------------
+// Batched launches: the same factor and eigensolve kernels for many graphs at once, one
+// workgroup per graph (or per graph and pair), each reading its graph's arguments from a
+// descriptor array in device memory.  Every workgroup runs the code of the single-graph
+// kernel on its own graph's data, so a graph's results do not depend on the others.
+// ------------------------------------------------------------------------------------
+namespace {
+
+// instance of the factor kernels a job needs: k_chol_np first (np), then k_pchol<M, CL>
+struct CholPlan {
+  bool np;
+  int M;
+  bool cl;
+  size_t dyn_np, dyn_p;
+};
+
+template <int M>
+constexpr size_t pchol_dyn_max() {
+  return 160 * 1024 - ((size_t)M * (M + 1) * 8 + (size_t)M * 24) - 1024;
+}
+
+CholPlan chol_plan(const CholJob& j) {
+  CholPlan p{};
+  const int kc = j.C ? j.kc : 0;
+  p.dyn_np = (size_t)kc * CNP_M * sizeof(double);
+  p.np = j.m <= CNP_M && p.dyn_np <= kCnpDynMax;
+  p.M = j.m <= 64 ? 64 : 128;
+  p.dyn_p = (size_t)kc * j.m * sizeof(double);
+  p.cl = kc > 0 && p.dyn_p <= (p.M == 64 ? pchol_dyn_max<64>() : pchol_dyn_max<128>());
+  if (!p.cl) p.dyn_p = 0;
+  return p;
+}
+
+int chol_key(const CholJob& j) {
+  const CholPlan p = chol_plan(j);
+  return (p.np ? 0 : 4) + (p.M == 64 ? 0 : 2) + (p.cl ? 1 : 0);
+}
+
+int eig_key(const EigJob& j) { return j.d_full <= 64 ? 0 : (j.d_full <= 128 ? 1 : 2); }
+
+__global__ void __launch_bounds__(CNP_T) k_chol_np_batch(const CholJob* J) {
+  const CholJob& j = J[blockIdx.x];
+  chol_np_body(j.m, j.G, j.C, j.C ? j.kc : 0, j.tol, j.Mout, j.rank, reinterpret_cast<int32_t*>(j.work), 0);
+}
+
+template <int M, bool CL>
+__global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol_batch(const CholJob* J, int after_np) {
+  const CholJob& j = J[blockIdx.x];
+  pchol_body<M, CL>(j.m, j.G, j.C, j.C ? j.kc : 0, j.tol, j.Mout, j.rank, j.status,
+                    after_np ? reinterpret_cast<const int32_t*>(j.work) : nullptr, 0);
+}
+
+template <int M>
+__global__ void __launch_bounds__(TRI_WAVES * GREST_WAVE) k_tridiag_batch(const EigJob* J) {
+  const EigJob& j = J[blockIdx.x];
+  tridiag_body<M>(j.d_full, j.base, j.rank, j.seg2, j.rank2, j.H, j.work, j.status, 0);
+}
+
+__global__ void __launch_bounds__(TL_THREADS) k_tridiag_lds_batch(const EigJob* J) {
+  const EigJob& j = J[blockIdx.x];
+  tridiag_lds_body(j.d_full, j.base, j.rank, j.seg2, j.rank2, j.H, j.work, j.status, 0);
+}
+
+// the job whose block range [b0, b0 + count) holds block b (jobs in ascending b0)
+__device__ __forceinline__ int job_of(const EigJob* J, int nj, int b, bool vec) {
+  int g = 0;
+  for (int i = 1; i < nj; ++i)
+    if ((vec ? J[i].b0_vec : J[i].b0_bisect) <= b) g = i;
+  return g;
+}
+
+__global__ void __launch_bounds__(GREST_WAVE) k_bisect_batch(const EigJob* J, int nj) {
+  const int b = blockIdx.x;
+  const EigJob& j = J[job_of(J, nj, b, false)];
+  bisect_body(j.work, b - j.b0_bisect);
+}
+
+__global__ void __launch_bounds__(GREST_WAVE) k_eigvec_batch(const EigJob* J, int nj) {
+  const int b = blockIdx.x;
+  const EigJob& j = J[job_of(J, nj, b, true)];
+  eigvec_body(j.d_full, j.which, j.kk, j.drop_tol, j.work, j.theta, j.F, j.kept, j.status, b - j.b0_vec);
+}
+
+__global__ void __launch_bounds__(GREST_WAVE) k_backtr_batch(const EigJob* J, int nj) {
+  const int b = blockIdx.x;
+  const EigJob& j = J[job_of(J, nj, b, true)];
+  backtr_body(j.d_full, j.kk, j.work, j.F, b - j.b0_vec);
+}
+
+template <typename K>
+void set_dyn_max(K kernel, size_t bytes) {
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+bool small_eig_job_ok(const EigJob& j) {
+  if (j.d_full < 1 || j.d_full > TL_MAX || j.kk < 1 || j.kk > j.d_full) return false;
+  if (j.rank2 && (j.seg2 < j.base || j.seg2 > j.d_full)) return false;
+  return true;
+}
+
+void chol_batch_prepare(CholJob* jobs, int nj) {
+  std::stable_sort(jobs, jobs + nj, [](const CholJob& a, const CholJob& b) { return chol_key(a) < chol_key(b); });
+}
+
+void chol_batch_launch(const CholJob* jobs, const CholJob* dev, int nj, hipStream_t s) {
+  static const bool attr = [] {
+    set_dyn_max(k_chol_np_batch, kCnpDynMax);
+    set_dyn_max(k_pchol_batch<64, true>, pchol_dyn_max<64>());
+    set_dyn_max(k_pchol_batch<128, true>, pchol_dyn_max<128>());
+    return true;
+  }();
+  (void)attr;
+  // k_chol_np over the leading jobs that take it (sorted first), then k_pchol per instance
+  int np = 0;
+  size_t dyn = 0;
+  while (np < nj && chol_plan(jobs[np]).np) dyn = std::max(dyn, chol_plan(jobs[np++]).dyn_np);
+  if (np > 0) k_chol_np_batch<<<np, CNP_T, dyn, s>>>(dev);
+  for (int a = 0; a < nj;) {
+    const int key = chol_key(jobs[a]);
+    int b = a;
+    size_t d = 0;
+    while (b < nj && chol_key(jobs[b]) == key) d = std::max(d, chol_plan(jobs[b++]).dyn_p);
+    const CholPlan p = chol_plan(jobs[a]);
+    const int after_np = p.np ? 1 : 0;
+    const unsigned g = (unsigned)(b - a);
+    if (p.M == 64 && p.cl) k_pchol_batch<64, true><<<g, PCH_WAVES * GREST_WAVE, d, s>>>(dev + a, after_np);
+    else if (p.M == 64) k_pchol_batch<64, false><<<g, PCH_WAVES * GREST_WAVE, 0, s>>>(dev + a, after_np);
+    else if (p.cl) k_pchol_batch<128, true><<<g, PCH_WAVES * GREST_WAVE, d, s>>>(dev + a, after_np);
+    else k_pchol_batch<128, false><<<g, PCH_WAVES * GREST_WAVE, 0, s>>>(dev + a, after_np);
+    a = b;
+  }
+}
+
+void small_eig_batch_prepare(EigJob* jobs, int nj) {
+  std::stable_sort(jobs, jobs + nj, [](const EigJob& a, const EigJob& b) { return eig_key(a) < eig_key(b); });
+  int bb = 0, bv = 0;
+  for (int i = 0; i < nj; ++i) {
+    jobs[i].b0_bisect = bb;
+    jobs[i].b0_vec = bv;
+    bb += jobs[i].d_full;
+    bv += jobs[i].kk;
+  }
+}
+
+void small_eig_batch_launch(const EigJob* jobs, const EigJob* dev, int nj, hipStream_t s) {
+  static const bool attr = [] {
+    set_dyn_max(k_tridiag_lds_batch, TL_LDS);
+    return true;
+  }();
+  (void)attr;
+  for (int a = 0; a < nj;) {
+    const int key = eig_key(jobs[a]);
+    int b = a;
+    while (b < nj && eig_key(jobs[b]) == key) ++b;
+    const unsigned g = (unsigned)(b - a);
+    if (key == 0) k_tridiag_batch<64><<<g, TRI_WAVES * GREST_WAVE, 0, s>>>(dev + a);
+    else if (key == 1) k_tridiag_batch<128><<<g, TRI_WAVES * GREST_WAVE, 0, s>>>(dev + a);
+    else k_tridiag_lds_batch<<<g, TL_THREADS, TL_LDS, s>>>(dev + a);
+    a = b;
+  }
+  const EigJob& last = jobs[nj - 1];
+  k_bisect_batch<<<last.b0_bisect + last.d_full, GREST_WAVE, 0, s>>>(dev, nj);
+  k_eigvec_batch<<<last.b0_vec + last.kk, GREST_WAVE, 0, s>>>(dev, nj);
+  k_backtr_batch<<<last.b0_vec + last.kk, GREST_WAVE, 0, s>>>(dev, nj);
 }

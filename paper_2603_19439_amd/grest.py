@@ -38,6 +38,15 @@ class Config(C.Structure):
 
 _lib = None
 
+BATCH_MAX = 64
+
+
+class BatchItem(C.Structure):
+    """grest_batch_item of include/grest.h."""
+    _fields_ = [("state", C.c_void_p), ("n_new", C.c_int64), ("n_changes", C.c_int64), ("ei", C.c_void_p),
+                ("ej", C.c_void_p), ("sign", C.c_void_p), ("omega", C.c_void_p), ("where", C.c_int32),
+                ("status", C.c_int32)]
+
 # (name, restype, argtypes) of every entry point of include/grest.h
 _SIGS = [
     ("grest_abi_version", C.c_int32, []),
@@ -55,6 +64,7 @@ _SIGS = [
                                C.c_int32]),
     ("grest_update_noalloc", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_int32]),
+    ("grest_update_batch", C.c_int, [C.c_void_p, C.c_int32]),
     ("grest_sync", C.c_int, [C.c_void_p]),
     ("grest_get", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
     ("grest_shape", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
@@ -79,6 +89,7 @@ _SIGS = [
                                       C.POINTER(C.c_double)]),
     ("grest_now_ns", C.c_int64, []),
     ("grest_server_create", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    ("grest_server_create_batched", C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
     ("grest_server_attach", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     ("grest_submit", C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_uint64]),
@@ -147,6 +158,33 @@ def validate_changes(n: int, n_new: int, i, j, sign) -> bool:
     j, pj = _host(j, np.int32)
     s, ps = _host(sign, np.int8)
     return lib().grest_validate_changes(int(n), int(n_new), int(i.size), pi, pj, ps) == OK
+
+
+def update_batch(updates):
+    """Updates of several states at once (grest_update_batch): updates is a list of
+    (state, n_new, i, j, sign, omega) with distinct states; returns the per-member statuses
+    and raises on the first failure."""
+    items = (BatchItem * len(updates))()
+    keep = []
+    for it, (st, n_new, i, j, sign, omega) in zip(items, updates):
+        ai, pi, w1 = _ptr(i, np.int32)
+        aj, pj, _ = _ptr(j, np.int32)
+        asg, ps, _ = _ptr(sign, np.int8)
+        ao, po, w4 = _ptr(omega, np.float64)
+        if omega is not None and w4 != w1:
+            raise ValueError("omega must live where the change arrays live")
+        nc = int(ai.numel() if hasattr(ai, "numel") else np.asarray(ai).size)
+        it.state = st._h.value
+        it.n_new = int(n_new)
+        it.n_changes = nc
+        it.ei, it.ej, it.sign, it.omega = (None if p is None else p.value for p in (pi, pj, ps, po))
+        it.where = w1
+        keep.append((ai, aj, asg, ao))
+    rc = lib().grest_update_batch(items, len(updates))
+    for (st, *_), k in zip(updates, keep):
+        st._keep = k
+    _check(rc, "grest_update_batch")
+    return [it.status for it in items]
 
 
 class State:
@@ -352,11 +390,13 @@ def now_ns() -> int:
 class Server:
     """Batched execution of many graphs on the current device (grest_server_* in grest.h)."""
 
-    def __init__(self, lanes: int = 4, max_queue: int = 1 << 16, hbm_budget_bytes: int = 0):
+    def __init__(self, lanes: int = 4, max_queue: int = 1 << 16, hbm_budget_bytes: int = 0, batch: int = 1):
+        """batch > 1: each lane runs up to `batch` requests of distinct graphs as one
+        grest_update_batch (grest_server_create_batched)."""
         self._lib = lib()
         self._h = C.c_void_p()
-        _check(self._lib.grest_server_create(int(hbm_budget_bytes), int(lanes), int(max_queue),
-                                             C.byref(self._h)), "grest_server_create")
+        _check(self._lib.grest_server_create_batched(int(hbm_budget_bytes), int(lanes), int(max_queue), int(batch),
+                                                     C.byref(self._h)), "grest_server_create_batched")
         self._states = []
 
     def attach(self, state: "State") -> int:

@@ -50,9 +50,11 @@ def _omega(wl, g, t, d, k):
     return W.omega(wl.cfg_id, g, t + 1, d.n_new, 2 * k) if d.n_new > 0 else None
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_results_do_not_depend_on_the_mix(prec):
-    graphs = _graphs(3)
+@pytest.mark.parametrize("prec,batch", [("fp64", 1), ("mixed", 1), ("mixed", 3), ("fp64", 2)])
+def test_results_do_not_depend_on_the_mix(prec, batch):
+    """Also with lanes that run batches (grest_server_create_batched): a graph's updates
+    go through grest_update_batch with whatever other graphs were runnable."""
+    graphs = _graphs(3 if batch == 1 else 5)
     # reference: every graph alone, updates driven directly
     ref = []
     for g, (wl, k, th, X) in enumerate(graphs):
@@ -64,8 +66,8 @@ def test_results_do_not_depend_on_the_mix(prec):
         ref.append(st.get())
         st.close()
     # the same updates interleaved over two lanes
-    banner(f"serving mix prec={prec}")
-    sv = G.Server(lanes=2)
+    banner(f"serving mix prec={prec} batch={batch}")
+    sv = G.Server(lanes=2, batch=batch)
     states = [_new_state(wl, k, th, X, prec) for (wl, k, th, X) in graphs]
     ids = [sv.attach(st) for st in states]
     tag = 0
