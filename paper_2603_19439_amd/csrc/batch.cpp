@@ -14,11 +14,20 @@
 // Nothing is reordered on the device but the one-workgroup kernels, which run with exactly
 // the arguments of their single-graph launch: the members' results are those of the same
 // updates run one at a time.
+//
+// The launches of a round depend only on its shape: which kernel instances, how many jobs
+// each, and the block counts of the per-pair kernels.  The first round of a shape is
+// captured from the batch stream into a HIP graph whose kernels read a descriptor array of
+// their own; a later round of the same shape copies its descriptors there and replays the
+// graph, one launch instead of up to ten (GREST_BATCH_GRAPHS=0 in the environment launches
+// every round directly instead).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -28,6 +37,14 @@
 namespace {
 
 constexpr size_t kRingBytes = 1 << 20;  // descriptor staging, reused once the stream has drained
+constexpr size_t kMaxGraphs = 256;       // captured round shapes kept per batch context
+
+// A captured round: its graph and the descriptor arrays its kernels read.
+struct RoundGraph {
+  hipGraphExec_t exec = nullptr;
+  void* chol = nullptr;  // device arrays, as many jobs as the shape has
+  void* eig = nullptr;
+};
 
 struct Pending {
   int kind;  // 0: factor, 1: eigensolve
@@ -54,6 +71,8 @@ struct BatchCtx {
   unsigned char* host_ring = nullptr;  // pinned
   unsigned char* dev_ring = nullptr;
   size_t ring_off = 0;
+  bool graphs = true;
+  std::map<std::vector<int>, RoundGraph> cache;  // by round shape
 };
 
 namespace {
@@ -84,6 +103,79 @@ int stage_jobs(BatchCtx* bc, std::vector<J>& jobs, J** dev) {
   return hip_fail(hipMemcpyAsync(*dev, bc->host_ring + off, bytes, hipMemcpyHostToDevice, bc->bs));
 }
 
+// shape of a round: per job its kernel instance, its block counts and the sizes its dynamic
+// LDS depends on, in launch order
+std::vector<int> round_shape(const std::vector<CholJob>& cj, const std::vector<EigJob>& ej) {
+  std::vector<int> k;
+  k.push_back((int)cj.size());
+  for (const CholJob& j : cj) {  // the instance, and the order and coefficient rows that size its LDS
+    k.push_back(chol_job_key(j));
+    k.push_back(j.m);
+    k.push_back(j.C ? j.kc : 0);
+  }
+  k.push_back((int)ej.size());
+  for (const EigJob& j : ej) {
+    k.push_back(eig_job_key(j));
+    k.push_back(j.d_full);
+    k.push_back(j.kk);
+  }
+  return k;
+}
+
+// staging copy of a round's descriptors into device memory at dst, on the batch stream
+template <typename J>
+int copy_jobs(BatchCtx* bc, const std::vector<J>& jobs, void* dst) {
+  if (jobs.empty()) return 0;
+  size_t off = 0;
+  const size_t bytes = jobs.size() * sizeof(J);
+  if (int rc = ring_take(bc, bytes, &off)) return rc;
+  std::memcpy(bc->host_ring + off, jobs.data(), bytes);
+  return hip_fail(hipMemcpyAsync(dst, bc->host_ring + off, bytes, hipMemcpyHostToDevice, bc->bs));
+}
+
+void launch_sets(std::vector<CholJob>& cj, std::vector<EigJob>& ej, void* dchol, void* deig, hipStream_t s) {
+  if (!cj.empty()) chol_batch_launch(cj.data(), (const CholJob*)dchol, (int)cj.size(), s);
+  if (!ej.empty()) small_eig_batch_launch(ej.data(), (const EigJob*)deig, (int)ej.size(), s);
+}
+
+// the round's launches through its captured graph (captured now if its shape is new)
+int replay_round(BatchCtx* bc, std::vector<CholJob>& cj, std::vector<EigJob>& ej) {
+  const std::vector<int> key = round_shape(cj, ej);
+  auto it = bc->cache.find(key);
+  if (it == bc->cache.end()) {
+    if (bc->cache.size() >= kMaxGraphs) {  // drop every shape kept so far
+      if (int rc = hip_fail(hipStreamSynchronize(bc->bs))) return rc;
+      for (auto& kv : bc->cache) {
+        (void)hipGraphExecDestroy(kv.second.exec);
+        (void)hipFree(kv.second.chol);
+        (void)hipFree(kv.second.eig);
+      }
+      bc->cache.clear();
+    }
+    RoundGraph g;
+    int rc = 0;
+    if (!cj.empty()) rc = hip_fail(hipMalloc(&g.chol, cj.size() * sizeof(CholJob)));
+    if (!rc && !ej.empty()) rc = hip_fail(hipMalloc(&g.eig, ej.size() * sizeof(EigJob)));
+    hipGraph_t graph = nullptr;
+    if (!rc) rc = hip_fail(hipStreamBeginCapture(bc->bs, hipStreamCaptureModeRelaxed));
+    if (!rc) {
+      launch_sets(cj, ej, g.chol, g.eig, bc->bs);
+      rc = hip_fail(hipStreamEndCapture(bc->bs, &graph));
+    }
+    if (!rc) rc = hip_fail(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) {
+      (void)hipFree(g.chol);
+      (void)hipFree(g.eig);
+      return rc;
+    }
+    it = bc->cache.emplace(key, g).first;
+  }
+  if (int rc = copy_jobs(bc, cj, it->second.chol)) return rc;
+  if (int rc = copy_jobs(bc, ej, it->second.eig)) return rc;
+  return hip_fail(hipGraphLaunch(it->second.exec, bc->bs));
+}
+
 // under the lock, by the last member to arrive: one launch set for the whole round
 void launch_round(BatchCtx* bc) {
   int rc = 0;
@@ -95,17 +187,16 @@ void launch_round(BatchCtx* bc) {
     if (p.kind == 0) cj.push_back(p.chol);
     else ej.push_back(p.eig);
   }
-  if (!rc && !cj.empty()) {
-    chol_batch_prepare(cj.data(), (int)cj.size());
-    CholJob* dev = nullptr;
-    rc = stage_jobs(bc, cj, &dev);
-    if (!rc) chol_batch_launch(cj.data(), dev, (int)cj.size(), bc->bs);
-  }
-  if (!rc && !ej.empty()) {
-    small_eig_batch_prepare(ej.data(), (int)ej.size());
-    EigJob* dev = nullptr;
-    rc = stage_jobs(bc, ej, &dev);
-    if (!rc) small_eig_batch_launch(ej.data(), dev, (int)ej.size(), bc->bs);
+  if (!cj.empty()) chol_batch_prepare(cj.data(), (int)cj.size());
+  if (!ej.empty()) small_eig_batch_prepare(ej.data(), (int)ej.size());
+  if (!rc && bc->graphs) {
+    rc = replay_round(bc, cj, ej);
+  } else if (!rc) {
+    CholJob* dc = nullptr;
+    EigJob* de = nullptr;
+    if (!cj.empty()) rc = stage_jobs(bc, cj, &dc);
+    if (!rc && !ej.empty()) rc = stage_jobs(bc, ej, &de);
+    if (!rc) launch_sets(cj, ej, dc, de, bc->bs);
   }
   if (!rc) rc = hip_fail(hipGetLastError());
   if (!rc) rc = hip_fail(hipEventRecord(bc->done, bc->bs));
@@ -143,6 +234,9 @@ BatchCtx* batch_create(int device, int max_members) {
     ok = hipEventCreateWithFlags(&bc->ev[i], hipEventDisableTiming) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&bc->host_ring, kRingBytes, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMalloc((void**)&bc->dev_ring, kRingBytes) == hipSuccess;
+  const char* env = std::getenv("GREST_BATCH_GRAPHS");
+  bc->graphs = !(env && env[0] == '0');
+  batch_kernels_init();  // kernel attributes, before any capture
   if (!ok) {
     batch_destroy(bc);
     return nullptr;
@@ -153,6 +247,11 @@ BatchCtx* batch_create(int device, int max_members) {
 void batch_destroy(BatchCtx* bc) {
   if (!bc) return;
   if (bc->bs) (void)hipStreamSynchronize(bc->bs);
+  for (auto& kv : bc->cache) {
+    (void)hipGraphExecDestroy(kv.second.exec);
+    (void)hipFree(kv.second.chol);
+    (void)hipFree(kv.second.eig);
+  }
   for (hipEvent_t e : bc->ev)
     if (e) (void)hipEventDestroy(e);
   if (bc->done) (void)hipEventDestroy(bc->done);

@@ -247,6 +247,9 @@ void chol_batch_prepare(CholJob* jobs, int nj);
 void chol_batch_launch(const CholJob* jobs, const CholJob* dev, int nj, hipStream_t s);
 void small_eig_batch_prepare(EigJob* jobs, int nj);
 void small_eig_batch_launch(const EigJob* jobs, const EigJob* dev, int nj, hipStream_t s);
+void batch_kernels_init();             // kernel attributes of the batched launches (idempotent)
+int chol_job_key(const CholJob& j);    // kernel instances a job takes (the launch order key)
+int eig_job_key(const EigJob& j);
 
 // Many graphs' updates in lockstep (grest_update_batch): member threads meet at each
 // one-workgroup stage and the last one to arrive launches that stage for all of them on

@@ -65,6 +65,7 @@ struct Graph {
   int64_t sketch_cols;  // L + P of an RSVD state, else 0
   StateCaps proj;       // capacities and sizes once every queued request of the graph has run
   int32_t slot;         // server stream the state is on (lane * max_batch + member)
+  int32_t k;            // tracked pairs
   int32_t queued;       // its requests queued or running
   bool running;         // a lane is updating it
   bool detached;
@@ -89,6 +90,13 @@ struct grest_server {
 
 namespace {
 
+// size class of a graph for batching: its K and the octave of its node count
+int size_class(const Graph& g) {
+  int oct = 0;
+  for (int64_t n = std::max<int64_t>(g.proj.n, 1); n > 1; n >>= 1) ++oct;
+  return g.k * 64 + oct;
+}
+
 void worker(grest_server* sv, int lane) {
   (void)hipSetDevice(sv->device);
   const int nb = sv->max_batch;
@@ -111,12 +119,17 @@ void worker(grest_server* sv, int lane) {
       };
       sv->cv_work.wait(lk, [&] { return runnable() || (sv->stop && sv->queue.empty()); });
       if (!runnable()) return;  // stop requested and nothing left
+      // a batch holds graphs of one size class (the oldest runnable request's): members in
+      // lockstep wait for each other at every one-workgroup stage
+      int cls = -1;
       for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)rqs.size() < nb;) {
         Graph& g = sv->graphs[it->gid];  // under the lock: attach may grow the table
-        if (g.running) {
+        const int c = size_class(g);
+        if (g.running || (cls >= 0 && c != cls)) {
           ++it;
           continue;
         }
+        cls = c;
         g.running = true;
         const int32_t slot = lane * nb + (int32_t)rqs.size();
         moves.push_back(g.slot != slot);
@@ -235,7 +248,7 @@ grest_status grest_server_attach(grest_server* sv, grest_state* st, int32_t* gra
   void* user = state_user_stream(st);
   const int32_t slot = (id % sv->nlanes) * sv->max_batch;
   if ((rc = grest_set_stream(st, sv->streams[slot])) != GREST_OK) return rc;
-  Graph g{st, user, bytes, state_sketch_cols(st), StateCaps{}, slot, 0, false, false};
+  Graph g{st, user, bytes, state_sketch_cols(st), StateCaps{}, slot, k, 0, false, false};
   state_caps(st, &g.proj);
   sv->graphs.push_back(g);
   sv->used += bytes;

@@ -1487,14 +1487,23 @@ void chol_batch_prepare(CholJob* jobs, int nj) {
   std::stable_sort(jobs, jobs + nj, [](const CholJob& a, const CholJob& b) { return chol_key(a) < chol_key(b); });
 }
 
-void chol_batch_launch(const CholJob* jobs, const CholJob* dev, int nj, hipStream_t s) {
+void batch_kernels_init() {
   static const bool attr = [] {
     set_dyn_max(k_chol_np_batch, kCnpDynMax);
     set_dyn_max(k_pchol_batch<64, true>, pchol_dyn_max<64>());
     set_dyn_max(k_pchol_batch<128, true>, pchol_dyn_max<128>());
+    set_dyn_max(k_tridiag_lds_batch, TL_LDS);
     return true;
   }();
   (void)attr;
+}
+
+int chol_job_key(const CholJob& j) { return chol_key(j); }
+
+int eig_job_key(const EigJob& j) { return eig_key(j); }
+
+void chol_batch_launch(const CholJob* jobs, const CholJob* dev, int nj, hipStream_t s) {
+  batch_kernels_init();
   // k_chol_np over the leading jobs that take it (sorted first), then k_pchol per instance
   int np = 0;
   size_t dyn = 0;
@@ -1528,11 +1537,7 @@ void small_eig_batch_prepare(EigJob* jobs, int nj) {
 }
 
 void small_eig_batch_launch(const EigJob* jobs, const EigJob* dev, int nj, hipStream_t s) {
-  static const bool attr = [] {
-    set_dyn_max(k_tridiag_lds_batch, TL_LDS);
-    return true;
-  }();
-  (void)attr;
+  batch_kernels_init();
   for (int a = 0; a < nj;) {
     const int key = eig_key(jobs[a]);
     int b = a;
