@@ -88,6 +88,7 @@ struct grest_state {
   int prec = GREST_FP64;
   size_t es = 8;  // element size of the dense blocks
   int K = 0, op = 0, variant = 0, L = 0, Ls = 0, Dw = 0, D = 0, ldz = 0, ldy = 0;
+  int ldq = 0;  // leading dimension of (op Z): D rounded up to 16 bytes, like ldz
   double tol = 1e-7;
   bool has_pairs = false;
 
@@ -101,7 +102,7 @@ struct grest_state {
 
   void* z[2] = {nullptr, nullptr};
   int zcur = 0;
-  void* aux = nullptr;   // (op Z), cap_n x D
+  void* aux = nullptr;   // (op Z), cap_n x D with leading dimension ldq
   void* ybuf = nullptr;  // sketch Y = Delta_2 Omega, cap_n x ldy, zero outside the listed rows
   void* mbuf = nullptr;  // its orthonormal basis M, cap_n x ldy
   bool y_clean = false;  // ybuf is zero outside srows[0 .. *srows_cnt)
@@ -255,7 +256,7 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
     CHK(dalloc((char**)&st->sc[b], cap_n * es));
     CHK(dalloc((char**)&st->z[b], (size_t)cap_n * st->ldz * es));
   }
-  if (!st->graph_free) CHK(dalloc((char**)&st->aux, (size_t)cap_n * std::max(st->D, st->K) * es));
+  if (!st->graph_free) CHK(dalloc((char**)&st->aux, (size_t)cap_n * st->ldq * es));
   if (st->variant == GREST_RSVD) {
     CHK(dalloc((char**)&st->ybuf, (size_t)cap_n * st->ldy * es));
     CHK(dalloc((char**)&st->mbuf, (size_t)cap_n * st->ldy * es));
@@ -627,18 +628,22 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
     const int c0 = reuse ? st->K : 0;
     mark_spmm(st, 0);
     const HeavyRows hv = heavy_of(st, st->gcur ^ 1);  // the updated graph's buffer
-    launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc + c0, st->ldz, n2, st->D - c0, b.aux + c0, st->D, st->stream, &hv);
+    // the product covers the basis columns up to the padding of the row (columns the rest of
+    // the update never reads), so that an odd width keeps 16-byte slices
+    int wsp = st->D - c0;
+    if (c0 % 4 == 0 && st->ldz % 4 == 0 && st->ldq == st->ldz) wsp = std::min(st->ldz - c0, (wsp + 3) / 4 * 4);
+    launch_spmm<T>(st->op, n2, rp, col, sc, b.Zc + c0, st->ldz, n2, wsp, b.aux + c0, st->ldq, st->stream, &hv);
     mark_spmm(st, 1);
     st->spmm_cols[st->pslot] = st->D - c0;
     mark(st, 5);
     // H = Z^T (op Z)
     if constexpr (sizeof(T) == 4) {
       if (st->prec == GREST_MIXED)
-        launch_tn_bf16(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+        launch_tn_bf16(n2, b.Zc, st->ldz, st->D, b.aux, st->ldq, st->D, st->partial, st->H, st->stream);
       else
-        launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+        launch_tn<T, false>(n2, b.Zc, st->ldz, st->D, b.aux, st->ldq, st->D, st->partial, st->H, st->stream);
     } else {
-      launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->D, st->D, st->partial, st->H, st->stream);
+      launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.aux, st->ldq, st->D, st->partial, st->H, st->stream);
     }
   }
   // small FP64 eigensolve on the leading K + rank block, selection of K pairs
@@ -660,7 +665,7 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
   // A X' = (A Z) F, kept in aux[:, 0:K] for the next update (in place: every row of aux is
   // read before its first K entries are written)
   if (st->op == GREST_OP_ADJ && !lr)
-    launch_apply<T>(n2, b.aux, st->D, st->D, st->F, st->K, 1.0, 0.0, b.aux, st->D, st->stream);
+    launch_apply<T>(n2, b.aux, st->ldq, st->D, st->F, st->K, 1.0, 0.0, b.aux, st->ldq, st->stream);
   mark(st, 8);
   return GREST_OK;
 }
@@ -870,12 +875,12 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   if (sparse_dx) {
     // zero the block, then visit only the rows of Delta (the row list of the graph stage)
     launch_fill_rows<T>(dX, st->ldz, 0, n2, K, s);
-    if (reuse) launch_fill_rows<T>(b.aux, st->D, n, S, K, s);
+    if (reuse) launch_fill_rows<T>(b.aux, st->ldq, n, S, K, s);
     launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX, st->ldz, s,
-                        reuse ? b.aux : nullptr, st->D, st->drows, st->dpos + n2, std::min<int64_t>(n2, 2 * nc));
+                        reuse ? b.aux : nullptr, st->ldq, st->drows, st->dpos + n2, std::min<int64_t>(n2, 2 * nc));
   } else if (!nlap) {
     launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX,
-                        st->ldz, s, reuse ? b.aux : nullptr, st->D);
+                        st->ldz, s, reuse ? b.aux : nullptr, st->ldq);
   }
   st->ax_valid = false;  // valid again only once this update commits
   mark(st, 2);
@@ -1045,9 +1050,9 @@ grest_status init_impl(grest_state* st, int max_products, double tol, uint64_t s
     T* Z = buf[cur];
     T* X = buf[cur ^ 1];
     // 1. Rayleigh-Ritz on Z (its kept columns)
-    launch_spmm<T>(st->op, n, rp, col, sc, Z, st->ldz, n, b, aux, st->D, s, &hv);
+    launch_spmm<T>(st->op, n, rp, col, sc, Z, st->ldz, n, b, aux, st->ldq, s, &hv);
     ++products;
-    launch_tn<T, true>(n, Z, st->ldz, b, aux, st->D, b, st->partial, st->H, s);
+    launch_tn<T, true>(n, Z, st->ldz, b, aux, st->ldq, b, st->partial, st->H, s);
     launch_symmetrize(b, st->H, s);
     if (!launch_small_eig(b, 0, st->ranks + 1, st->H, which, b, 0.0, st->theta, st->F, nullptr, st->eigwork,
                           st->status, s)) {
@@ -1055,9 +1060,9 @@ grest_status init_impl(grest_state* st, int max_products, double tol, uint64_t s
       return GREST_EINVAL;
     }
     launch_apply<T>(n, Z, st->ldz, b, st->F, b, 1.0, 0.0, X, st->ldz, s);
-    launch_apply<T>(n, aux, st->D, b, st->F, b, 1.0, 0.0, aux, st->D, s);  // (op X), in place
+    launch_apply<T>(n, aux, st->ldq, b, st->F, b, 1.0, 0.0, aux, st->ldq, s);  // (op X), in place
     // 2. residual block of the K leading pairs, in Z's buffer (free from here on)
-    launch_lincomb3<T>(n, K, 1.0, aux, st->D, 0.0, aux, st->D, 0.0, nullptr, 0, Z, st->ldz, s);
+    launch_lincomb3<T>(n, K, 1.0, aux, st->ldq, 0.0, aux, st->ldq, 0.0, nullptr, 0, Z, st->ldz, s);
     launch_sub_scaled_cols<T>(n, K, st->theta, X, st->ldz, Z, st->ldz, s);
     launch_tn<T, true>(n, Z, st->ldz, K, Z, st->ldz, K, st->partial, st->Gm, s);
     HIPCHK(hipMemcpyAsync(gram.data(), st->Gm, gram.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1098,14 +1103,14 @@ grest_status init_impl(grest_state* st, int max_products, double tol, uint64_t s
     m = std::max(1, std::min(m, std::min(16, max_products - products - 1)));
     T* prev = buf[cur];
     T* next = buf[cur ^ 1];
-    launch_spmm<T>(st->op, n, rp, col, sc, prev, st->ldz, n, b, aux, st->D, s, &hv);
+    launch_spmm<T>(st->op, n, rp, col, sc, prev, st->ldz, n, b, aux, st->ldq, s, &hv);
     ++products;
-    launch_lincomb3<T>(n, b, 1.0 / e, aux, st->D, -center / e, prev, st->ldz, 0.0, nullptr, 0, next, st->ldz, s);
+    launch_lincomb3<T>(n, b, 1.0 / e, aux, st->ldq, -center / e, prev, st->ldz, 0.0, nullptr, 0, next, st->ldz, s);
     for (int j = 1; j < m; ++j) {
-      launch_spmm<T>(st->op, n, rp, col, sc, next, st->ldz, n, b, aux, st->D, s, &hv);
+      launch_spmm<T>(st->op, n, rp, col, sc, next, st->ldz, n, b, aux, st->ldq, s, &hv);
       ++products;
       // T_{j+1} into the buffer of T_{j-1} (element by element, read before written)
-      launch_lincomb3<T>(n, b, 2.0 / e, aux, st->D, -2.0 * center / e, next, st->ldz, -1.0, prev, st->ldz, prev,
+      launch_lincomb3<T>(n, b, 2.0 / e, aux, st->ldq, -2.0 * center / e, next, st->ldz, -1.0, prev, st->ldz, prev,
                          st->ldz, s);
       std::swap(prev, next);
     }
@@ -1271,7 +1276,7 @@ int64_t state_bytes_for(const grest_state* st, const StateCaps& c) {
   const int64_t n1 = c.cap_n + 1;
   int64_t b = 0;
   b += 2 * n1 * 8 + 2 * c.cap_n * es + 2 * c.cap_n * st->ldz * es;  // rp, sc, z (two each)
-  if (!st->graph_free) b += c.cap_n * std::max(st->D, st->K) * es;  // (op Z)
+  if (!st->graph_free) b += c.cap_n * st->ldq * es;  // (op Z)
   if (st->variant == GREST_RSVD) b += 2 * c.cap_n * st->ldy * es;    // sketch and its basis
   b += 8 * n1 * 8;                                                   // counts, offsets, flags, positions
   b += 3 * (scan_tmp_elems(n1) + 16) * 8;                            // scan workspaces
@@ -1394,6 +1399,7 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   if (orth_w > 128 || st->D > 196) { delete st; return GREST_EINVAL; }
   const int q = (int)(16 / st->es);
   st->ldz = (int)round_up(st->D, q);
+  st->ldq = st->ldz;
   st->ldy = (int)round_up(std::max(st->Ls, 1), q);
   st->tol = cfg->rank_tol > 0 ? cfg->rank_tol : (cfg->precision == GREST_FP64 ? 1e-7 : 1e-5);
   if (stream) {
@@ -1833,7 +1839,7 @@ grest_status grest_save(grest_state* st, void* buf, size_t* bytes) {
     p += (size_t)h.cfg.k * sizeof(double) + (size_t)h.n * h.cfg.k * sizeof(double);
   }
   if (h.ax_valid) {
-    HIPCHK(hipMemcpy2D(p, (size_t)h.cfg.k * h.es, st->aux, (size_t)st->D * h.es, (size_t)h.cfg.k * h.es, h.n,
+    HIPCHK(hipMemcpy2D(p, (size_t)h.cfg.k * h.es, st->aux, (size_t)st->ldq * h.es, (size_t)h.cfg.k * h.es, h.n,
                        hipMemcpyDeviceToHost));
   }
   *bytes = need;
@@ -1882,7 +1888,7 @@ grest_status grest_load(const void* buf, size_t bytes, void* stream, grest_state
     p += (size_t)h.cfg.k * sizeof(double) + (size_t)h.n * h.cfg.k * sizeof(double);
   }
   if (rc == GREST_OK && h.ax_valid) {
-    if (hipMemcpy2D(st->aux, (size_t)st->D * h.es, p, (size_t)h.cfg.k * h.es, (size_t)h.cfg.k * h.es, h.n,
+    if (hipMemcpy2D(st->aux, (size_t)st->ldq * h.es, p, (size_t)h.cfg.k * h.es, (size_t)h.cfg.k * h.es, h.n,
                     hipMemcpyHostToDevice) != hipSuccess) {
       rc = GREST_EDEVICE;
     } else {
