@@ -162,6 +162,9 @@ struct grest_state {
   int64_t* hcnt[2] = {nullptr, nullptr};
   int64_t hcnt_host[2] = {0, 0};
   int64_t *hflag = nullptr, *hpos = nullptr, *hscan = nullptr;
+  // rows of the current Delta with more than HEAVY_DEG entries (count on the device)
+  int32_t* dhrows = nullptr;
+  int64_t* dhcnt = nullptr;
   Pinned* pin = nullptr;
   double* theta_pin = nullptr;
   int32_t deferred = 0;
@@ -276,6 +279,7 @@ grest_status alloc_node_arrays(grest_state* st, int64_t cap_n) {
   CHK(dalloc(&st->srows, cap_n + 1));
   CHK(dalloc(&st->drows, cap_n + 1));
   for (int b = 0; b < 2; ++b) CHK(dalloc(&st->hrows[b], cap_n + 1));
+  CHK(dalloc(&st->dhrows, cap_n + 1));
   CHK(dalloc(&st->hflag, cap_n + 1));
   CHK(dalloc(&st->hpos, cap_n + 1));
   CHK(dalloc(&st->hscan, scan_tmp_elems(cap_n + 1) + 16));
@@ -349,6 +353,7 @@ int64_t device_bytes(const grest_state* st) {
   add(st->dcnt); add(st->newlen); add(st->scan_tmp); add(st->srows); add(st->drows);
   add(st->rflag); add(st->rpos); add(st->rscan_tmp); add(st->dflag); add(st->dpos); add(st->dscan_tmp);
   add(st->hrows[0]); add(st->hrows[1]); add(st->hcnt[0]); add(st->hcnt[1]); add(st->hflag); add(st->hpos);
+  add(st->dhrows); add(st->dhcnt);
   add(st->hscan);
   add(st->dkey_in); add(st->dkey_out); add(st->dins); add(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
@@ -370,6 +375,7 @@ void free_all(grest_state* st) {
   dfree(st->dcnt); dfree(st->newlen); dfree(st->scan_tmp); dfree(st->srows); dfree(st->drows);
   dfree(st->rflag); dfree(st->rpos); dfree(st->rscan_tmp); dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
   dfree(st->hrows[0]); dfree(st->hrows[1]); dfree(st->hcnt[0]); dfree(st->hcnt[1]); dfree(st->hflag);
+  dfree(st->dhrows); dfree(st->dhcnt);
   dfree(st->hpos); dfree(st->hscan);
   dfree(st->dkey_in); dfree(st->dkey_out); dfree(st->dins); dfree(st->dsg_tmp);
   for (int b = 0; b < 2; ++b) {
@@ -424,6 +430,7 @@ grest_status grow_nodes(grest_state* st, int64_t need) {
   dfree(st->dflag); dfree(st->dpos); dfree(st->dscan_tmp);
   dfree(st->srows); dfree(st->drows);
   dfree(st->hrows[0]); dfree(st->hrows[1]); dfree(st->hflag); dfree(st->hpos); dfree(st->hscan);
+  dfree(st->dhrows);
   CHK(alloc_node_arrays(st, cap));
   CHK(alloc_gather_arrays(st));
   HIPCHK(hipMemcpyAsync(st->rp[st->gcur], rp_old, (st->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
@@ -755,6 +762,9 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   const int kshift = delta_key_shift(n2);
   launch_delta_keys(dei, dej, dsgn, nc, n, S, kshift, cb.kin, cb.sg_tmp, st->dcnt, st->vstat[ds], gs);
   launch_scan_excl(st->dcnt, dptr, n2, st->scan_tmp, gs);
+  // Delta's rows with more than HEAVY_DEG entries (only possible beyond HEAVY_DEG changes)
+  const int64_t dh_bound = nc > HEAVY_DEG ? std::min<int64_t>(n2, 2 * nc / (HEAVY_DEG + 1) + 1) : 0;
+  if (dh_bound > 0) launch_heavy_rows(n2, dptr, st->hflag, st->hpos, st->hscan, st->dhrows, st->dhcnt, gs);
   // the keys into their rows, each row sorted by column (the list of long rows uses the
   // new-length array, which the row pass below fills afterwards)
   launch_delta_group(cb.kin, cb.sg_tmp, 2 * nc, kshift, n2, dptr, st->dcnt, cb.kout, dsg, st->newlen, st->vstat[ds],
@@ -872,15 +882,17 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   mark(st, 1);
   launch_fill_rows<T>(b.Zc, st->ldz, n, S, st->ldz, s);
   // ---- Delta Xbar = Delta_1 X (Prop. 3) ----
+  const HeavyRows dheavy{st->dhrows, st->dhcnt, dh_bound};
   if (sparse_dx) {
     // zero the block, then visit only the rows of Delta (the row list of the graph stage)
     launch_fill_rows<T>(dX, st->ldz, 0, n2, K, s);
     if (reuse) launch_fill_rows<T>(b.aux, st->ldq, n, S, K, s);
     launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX, st->ldz, s,
-                        reuse ? b.aux : nullptr, st->ldq, st->drows, st->dpos + n2, std::min<int64_t>(n2, 2 * nc));
+                        reuse ? b.aux : nullptr, st->ldq, st->drows, st->dpos + n2, std::min<int64_t>(n2, 2 * nc),
+                        &dheavy);
   } else if (!nlap) {
     launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX,
-                        st->ldz, s, reuse ? b.aux : nullptr, st->ldq);
+                        st->ldz, s, reuse ? b.aux : nullptr, st->ldq, nullptr, nullptr, 0, &dheavy);
   }
   st->ax_valid = false;  // valid again only once this update commits
   mark(st, 2);
@@ -1278,9 +1290,9 @@ int64_t state_bytes_for(const grest_state* st, const StateCaps& c) {
   b += 2 * n1 * 8 + 2 * c.cap_n * es + 2 * c.cap_n * st->ldz * es;  // rp, sc, z (two each)
   if (!st->graph_free) b += c.cap_n * st->ldq * es;  // (op Z)
   if (st->variant == GREST_RSVD) b += 2 * c.cap_n * st->ldy * es;    // sketch and its basis
-  b += 8 * n1 * 8;                                                   // counts, offsets, flags, positions
-  b += 3 * (scan_tmp_elems(n1) + 16) * 8;                            // scan workspaces
-  b += 2 * n1 * 4;                                                   // row lists
+  b += 10 * n1 * 8;                                                  // counts, offsets, flags, positions
+  b += 4 * (scan_tmp_elems(n1) + 16) * 8;                            // scan workspaces
+  b += 5 * n1 * 4;                                                   // row lists
   if (!st->graph_free) b += 2 * c.cap_m * 4;                         // column ids (two buffers)
   const int64_t nc = c.cap_nc;
   b += nc * (4 + 4 + 1) + 2 * nc * (8 + 8 + 2 * 4 + 2 * 1 + 4 + 1);  // change arrays
@@ -1444,6 +1456,7 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   if ((rc = dalloc(&st->eigwork, ework)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->ranks, 8)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->status, 1)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc(&st->dhcnt, 1)) != GREST_OK) return fail(rc);
   for (int b = 0; b < 2; ++b) {
     if ((rc = dalloc(&st->hcnt[b], 1)) != GREST_OK) return fail(rc);
     if ((rc = dalloc(&st->maxdeg[b], 1)) != GREST_OK) return fail(rc);

@@ -54,7 +54,7 @@ template <typename T, int VEC, int OP, int MODE>
 __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__ snew,
                                               const T* __restrict__ in, int64_t ldin, int w,
                                               T* __restrict__ out, int64_t ldout, T* __restrict__ acc_io,
-                                              int64_t ldacc, int lpr_shift) {
+                                              int64_t ldacc, int lpr_shift, int64_t skip_deg) {
   const int lpr = 1 << lpr_shift;
   const int64_t gid = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int gl = (int)(gid & (lpr - 1));
@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
     const int64_t r = listed ? (int64_t)a.rows[q] : (MODE == 2) ? a.n_old + q : q;
     const int64_t orow = (MODE == 2) ? q : r;
     const int64_t beg = a.dptr[r], end = a.dptr[r + 1];
+    if (MODE == 0 && end - beg > skip_deg) continue;  // a heavy row: k_delta0_heavy
     for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
       T acc[VEC];
 #pragma unroll
@@ -127,6 +128,65 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
           vstore<T, VEC>(pa, old);
         }
       }
+    }
+  }
+}
+
+// Mode 0 on the heavy rows of Delta (more than HEAVY_DEG entries: hubs of a power-law graph
+// that gain or lose many edges in one update), one workgroup of HEAVY_BS threads per row:
+// its lane groups take contiguous, equal shares of the row's entries and keep their partial
+// sums (and partial sign sums) in LDS, the workgroup adds them in a fixed order and applies
+// mode 0's epilogue (the Laplacian's degree term, the kept product).  The row-split kernel
+// would leave a row of thousands of entries to one lane group.
+template <typename T, int VEC, int OP>
+__global__ void __launch_bounds__(HEAVY_BS) k_delta0_heavy(DeltaArgs a, const int32_t* __restrict__ hrows,
+                                                           const int64_t* __restrict__ hcount,
+                                                           const T* __restrict__ in, int64_t ldin, int w,
+                                                           T* __restrict__ out, int64_t ldout, T* __restrict__ acc_io,
+                                                           int64_t ldacc, int lpr_shift) {
+  extern __shared__ char delta_smem[];
+  T* part = reinterpret_cast<T*>(delta_smem);  // [groups][w]
+  __shared__ int32_t gsum[HEAVY_BS];           // sign sum of each group's share
+  if ((int64_t)blockIdx.x >= *hcount) return;
+  const int64_t r = hrows[blockIdx.x];
+  const int lpr = 1 << lpr_shift;
+  const int groups = HEAVY_BS >> lpr_shift;
+  const int grp = threadIdx.x >> lpr_shift, gl = threadIdx.x & (lpr - 1);
+  const int64_t beg = a.dptr[r], end = a.dptr[r + 1];
+  const int64_t share = (end - beg + groups - 1) / groups;
+  const int64_t e0 = min(end, beg + grp * share), e1 = min(end, e0 + share);
+  if (gl == 0) {
+    int32_t ss = 0;
+    for (int64_t e = e0; e < e1; ++e) ss += a.dsg[e];
+    gsum[grp] = ss;
+  }
+  for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
+    T acc[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) acc[i] = T(0);
+    for (int64_t e = e0; e < e1; ++e) {
+      const int64_t c = a.dcol[e];
+      if (c >= a.n_old) continue;
+      const T wgt = T(a.dsg[e]);
+      T z[VEC];
+      vload<T, VEC>(in + c * ldin + c0, z);
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) acc[i] += wgt * z[i];
+    }
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) part[(size_t)grp * w + c0 + i] = acc[i];
+  }
+  __syncthreads();
+  int32_t ssum = 0;
+  for (int g = 0; g < groups; ++g) ssum += gsum[g];
+  for (int c = threadIdx.x; c < w; c += HEAVY_BS) {
+    T sum = T(0);
+    for (int g = 0; g < groups; ++g) sum += part[(size_t)g * w + c];
+    if (OP == OPK_LAP && r < a.n_old && ssum != 0) sum -= T(ssum) * in[r * ldin + c];
+    out[r * ldout + c] = sum;
+    if (acc_io) {
+      if (r >= a.n_old) acc_io[r * ldacc + c] = sum;
+      else acc_io[r * ldacc + c] += sum;
     }
   }
 }
@@ -293,24 +353,39 @@ __global__ void __launch_bounds__(HEAVY_BS) k_nlap_dx_heavy(const int32_t* __res
 
 template <typename T, int OP, int MODE>
 static void delta_dispatch(int vec, const DeltaArgs& a, const T* snew, const T* in, int64_t ldin, int w,
-                           T* out, int64_t ldout, T* acc_io, int64_t ldacc, hipStream_t s, int64_t bound) {
+                           T* out, int64_t ldout, T* acc_io, int64_t ldacc, hipStream_t s, int64_t bound,
+                           const HeavyRows* heavy) {
   const int64_t rows = (MODE <= 1 && a.rows) ? bound : (MODE == 2) ? a.n_new : a.n_old + a.n_new;
   if (rows <= 0 || w <= 0) return;
   const int lpr = lanes_per_row(w, vec);
   const int g = grid_for(rows * lpr);
-  if (vec == 16 / (int)sizeof(T))
-    k_delta<T, 16 / sizeof(T), OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc,
-                                                          ilog2(lpr));
+  const bool hv = MODE == 0 && heavy && heavy->bound > 0;
+  const int64_t skip = hv ? HEAVY_DEG : INT64_MAX;
+  constexpr int V = 16 / sizeof(T);
+  if (vec == V)
+    k_delta<T, V, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc, ilog2(lpr), skip);
   else
-    k_delta<T, 1, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc, ilog2(lpr));
+    k_delta<T, 1, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc, ilog2(lpr), skip);
+  if constexpr (MODE == 0) {
+    if (!hv) return;
+    const size_t lds = (size_t)(HEAVY_BS / lpr) * w * sizeof(T);
+    const unsigned hg = (unsigned)std::min<int64_t>(heavy->bound, a.n_old + a.n_new);
+    if (vec == V)
+      k_delta0_heavy<T, V, OP><<<hg, HEAVY_BS, lds, s>>>(a, heavy->rows, heavy->count, in, ldin, w, out, ldout,
+                                                         acc_io, ldacc, ilog2(lpr));
+    else
+      k_delta0_heavy<T, 1, OP><<<hg, HEAVY_BS, lds, s>>>(a, heavy->rows, heavy->count, in, ldin, w, out, ldout,
+                                                         acc_io, ldacc, ilog2(lpr));
+  }
 }
 
 template <typename T, int OP>
 static void delta_mode(int mode, int vec, const DeltaArgs& a, const T* snew, const T* in, int64_t ldin,
-                       int w, T* out, int64_t ldout, T* acc_io, int64_t ldacc, hipStream_t s, int64_t bound) {
-  if (mode == 0) delta_dispatch<T, OP, 0>(vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound);
-  else if (mode == 1) delta_dispatch<T, OP, 1>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s, bound);
-  else if (mode == 2) delta_dispatch<T, OP, 2>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s, 0);
+                       int w, T* out, int64_t ldout, T* acc_io, int64_t ldacc, hipStream_t s, int64_t bound,
+                       const HeavyRows* heavy) {
+  if (mode == 0) delta_dispatch<T, OP, 0>(vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound, heavy);
+  else if (mode == 1) delta_dispatch<T, OP, 1>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s, bound, nullptr);
+  else if (mode == 2) delta_dispatch<T, OP, 2>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s, 0, nullptr);
   else if (a.n_new > 0) k_delta_dense2<T, OP><<<grid_for(a.n_new), BS, 0, s>>>(a, snew, out, ldout);
 }
 
@@ -318,15 +393,17 @@ template <typename T>
 void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
                       const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
                       const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s, T* acc_io,
-                      int64_t ldacc, const int32_t* rows, const int64_t* rcount, int64_t bound) {
+                      int64_t ldacc, const int32_t* rows, const int64_t* rcount, int64_t bound,
+                      const HeavyRows* heavy) {
   if (mode > 1 || bound <= 0) rows = nullptr;
   DeltaArgs a{n_old, n_new, dptr, dcol, dsg, maxdeg, rows, rows ? rcount : nullptr};
   int vec = (mode == 3) ? 1 : pick_vec<T>(w, ldin, ldout, in, out);
   if (acc_io && vec > 1 && (ldacc % vec != 0 || ((uintptr_t)acc_io % 16) != 0)) vec = 1;
-  if (op == OPK_ADJ) delta_mode<T, OPK_ADJ>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound);
+  if (op == OPK_ADJ)
+    delta_mode<T, OPK_ADJ>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound, heavy);
   else if (op == OPK_LAP)
-    delta_mode<T, OPK_LAP>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound);
-  else delta_mode<T, OPK_NLAP>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound);
+    delta_mode<T, OPK_LAP>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound, heavy);
+  else delta_mode<T, OPK_NLAP>(mode, vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound, heavy);
 }
 
 template <typename T>
@@ -363,7 +440,7 @@ void launch_nlap_delta_x(int64_t n_old, int64_t n_new, const int64_t* rp_old, co
   template void launch_delta_mul<T>(int, int, int64_t, int64_t, const int64_t*, const int32_t*,        \
                                     const int8_t*, const int64_t*, const T*, const T*, int64_t, int,  \
                                     T*, int64_t, hipStream_t, T*, int64_t, const int32_t*,            \
-                                    const int64_t*, int64_t);                                         \
+                                    const int64_t*, int64_t, const HeavyRows*);                       \
   template void launch_nlap_delta_x<T>(int64_t, int64_t, const int64_t*, const int32_t*, const T*,     \
                                        const int64_t*, const int32_t*, const T*, const T*, int64_t,   \
                                        int, T*, int64_t, hipStream_t, const HeavyRows*);

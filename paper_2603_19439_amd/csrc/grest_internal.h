@@ -104,12 +104,14 @@ void launch_heavy_rows(int64_t n, const int64_t* rp, int64_t* flag, int64_t* pos
 // operator's product with the padded block).  Modes 0 and 1 with a row list (rows, *rcount
 // <= bound on the device): only those rows are computed.  Mode 0: out must be zero elsewhere
 // already, and acc_io's appended rows too; mode 1: the list must hold every row it writes.
+// Mode 0 with heavy (the rows of Delta with more than HEAVY_DEG entries): those rows go to a
+// workgroup each.
 template <typename T>
 void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
                       const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
                       const T* in, int64_t ldin, int w, T* out, int64_t ldout, hipStream_t s,
                       T* acc_io = nullptr, int64_t ldacc = 0, const int32_t* rows = nullptr,
-                      const int64_t* rcount = nullptr, int64_t bound = 0);
+                      const int64_t* rcount = nullptr, int64_t bound = 0, const HeavyRows* heavy = nullptr);
 // nlap: V = S'A'S' Xbar - [S A S X; 0] computed row by row from both graphs; with heavy
 // (the new graph's heavy rows) those rows go to a workgroup each
 template <typename T>

@@ -141,6 +141,104 @@ __global__ void __launch_bounds__(WG) k_tnw(int64_t n, int64_t rpc, const Tin* _
 }
 
 // ---------------------------------------------------------------------------------
+// C = A^T B for wide FP32 operands (more than 64 columns, up to TNL_MAXW): every output
+// tile is owned by one wave for the workgroup's whole row chunk (tiles dealt out round-
+// robin, upper tiles only for a Gram), rows are staged 16 at a time through LDS (the
+// threads of the workgroup on consecutive columns of a row, the next stage's loads in
+// flight during the MFMAs), and each lane feeds the matrix core from LDS.  So every row of
+// A and B is read once per product, where the register-tiled kernel re-reads B once per
+// slice of two tile-rows.  FP32 MFMA (Tc = float) or FP64 MFMA (Tc = double)
+// accumulation; the workgroup's partial is written tile by tile by the owning waves (a
+// Gram's lower tiles as the mirrors of the upper ones), so no two waves add into one value.
+// ---------------------------------------------------------------------------------
+constexpr int TNL_W = 8;         // waves of a workgroup
+constexpr int TNL_MAXW = 208;    // widest operand (13 tiles); also the LDS pitch of a staged row
+static_assert(TNL_MAXW % 64 == 16, "the four 16-lane groups of a fragment read hit disjoint banks");
+
+template <typename Tc, int MT>
+__global__ void __launch_bounds__(TNL_W * 64) k_tnl(int64_t n, int64_t rpc, const float* __restrict__ A, int64_t lda,
+                                                    int a, const float* __restrict__ B, int64_t ldb, int b, int sym,
+                                                    double* __restrict__ partial) {
+  using M = Mma<Tc>;
+  using acc_t = typename M::acc_t;
+  __shared__ float sA[16 * TNL_MAXW];
+  __shared__ float sB[16 * TNL_MAXW];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int TA = (a + 15) >> 4, TB = (b + 15) >> 4;
+  // this wave's tiles: t = wid, wid + TNL_W, ... in row-major order of the (upper) tile grid
+  int ti[MT], tj[MT];
+  acc_t acc[MT];
+  {
+    int i = 0, j = 0, t = 0;  // the tile with index t
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      const int want = wid + TNL_W * q;
+      while (i < TA && t < want) {
+        ++t;
+        if (++j == TB) {
+          ++i;
+          j = sym ? i : 0;
+        }
+      }
+      const bool ok = i < TA && t == want;
+      ti[q] = ok ? i : -1;
+      tj[q] = ok ? j : -1;
+      acc[q] = acc_t{0, 0, 0, 0};
+    }
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rpc;
+  const int64_t r1 = min(n, r0 + rpc);
+  const int wcols = sym ? a : a + b;  // staged columns per row
+  // loader: thread tid takes column tid of each of the 16 rows (wcols <= 2 TNL_MAXW <= 512)
+  const bool lc = tid < wcols;
+  const bool inA = tid < a;
+  const float* src = inA ? A + tid : B + (tid - a);
+  const int64_t lds = inA ? lda : ldb;
+  float* dst = (inA ? sA : sB) + (inA ? tid : tid - a);
+  float pre[16];
+  auto fetch = [&](int64_t rb) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) pre[r] = (lc && rb + r < r1) ? src[(rb + r) * lds] : 0.f;
+  };
+  const float* sBr = sym ? sA : sB;
+  if (r0 < r1) fetch(r0);
+  for (int64_t rb = r0; rb < r1; rb += 16) {
+    __syncthreads();  // the previous stage's fragments have been read
+    if (lc) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dst[r * TNL_MAXW] = pre[r];
+    }
+    __syncthreads();
+    if (rb + 16 < r1) fetch(rb + 16);  // in flight during the MFMAs below
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int rowoff = (4 * s + g) * TNL_MAXW + c16;
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        if (ti[q] < 0) continue;
+        const Tc fa = (Tc)sA[rowoff + ti[q] * 16];
+        const Tc fb = (Tc)sBr[rowoff + tj[q] * 16];
+        acc[q] = M::run(fa, fb, acc[q]);
+      }
+    }
+  }
+  double* out = partial + (size_t)blockIdx.x * a * b;
+#pragma unroll
+  for (int q = 0; q < MT; ++q) {
+    if (ti[q] < 0) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = ti[q] * 16 + M::row(lane, r), j = tj[q] * 16 + c16;
+      if (i < a && j < b) {
+        out[(size_t)i * b + j] = (double)acc[q][r];
+        if (sym && ti[q] != tj[q]) out[(size_t)j * b + i] = (double)acc[q][r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // C = A^T B with split-BF16 MFMA (FP32 accumulation); 32 rows per stage, prefetched
 // ---------------------------------------------------------------------------------
 constexpr int BT = 10;  // output tiles per wave (<= 40 tiles per workgroup)
@@ -881,6 +979,35 @@ static void tn_run(int kind, int64_t n, const T* A, int64_t lda, int a, const T*
                    double* partial, double* C, hipStream_t s, int ldc = -1) {
   if (a <= 0 || b <= 0) return;
   if (ldc < 0) ldc = b;
+  if constexpr (std::is_same<T, float>::value) {
+    // wide FP32 operands: one pass over the rows with LDS staging (split BF16 has no such
+    // form; its wide products take FP32 MFMA here, as they do below)
+    const int TA = (a + 15) >> 4, TB = (b + 15) >> 4;
+    const bool sym = A == B && lda == ldb && a == b && kind != 2;
+    const bool bf16_fits = kind == 2 && a <= TW && b <= TW && TA * TB <= NW * BT;
+    if ((a > 64 || b > 64) && a <= TNL_MAXW && b <= TNL_MAXW && !bf16_fits) {
+      const int ntile = sym ? TA * (TA + 1) / 2 : TA * TB;
+      const int per = (ntile + TNL_W - 1) / TNL_W;
+      const bool f64 = kind == 1;
+      if ((!f64 && per <= 24) || (f64 && per <= 12)) {
+        const int g = tn_num_chunks(n);
+        int64_t rpc = (n + g - 1) / g;
+        rpc = ((rpc + 15) / 16) * 16;
+        const float* fA = (const float*)A;
+        const float* fB = (const float*)B;
+        const int sy = sym ? 1 : 0;
+        // the smallest register tile that holds the wave's tiles: fewer registers, more
+        // resident waves to cover the loads of the next stage
+        if (f64 && per <= 6) k_tnl<double, 6><<<g, TNL_W * 64, 0, s>>>(n, rpc, fA, lda, a, fB, ldb, b, sy, partial);
+        else if (f64) k_tnl<double, 12><<<g, TNL_W * 64, 0, s>>>(n, rpc, fA, lda, a, fB, ldb, b, sy, partial);
+        else if (per <= 6) k_tnl<float, 6><<<g, TNL_W * 64, 0, s>>>(n, rpc, fA, lda, a, fB, ldb, b, sy, partial);
+        else if (per <= 12) k_tnl<float, 12><<<g, TNL_W * 64, 0, s>>>(n, rpc, fA, lda, a, fB, ldb, b, sy, partial);
+        else k_tnl<float, 24><<<g, TNL_W * 64, 0, s>>>(n, rpc, fA, lda, a, fB, ldb, b, sy, partial);
+        launch_reduce(g, red_job(partial, C, a, b, ldc), RedJob{nullptr, nullptr, 0, 0, 0, 0}, s);
+        return;
+      }
+    }
+  }
   if (A == B && lda == ldb && a == b && kind != 2 && ((a + 15) >> 4) > 4) {
     // a Gram wider than the symmetric kernel's 64 columns: its upper blocks of 64 columns
     // (the diagonal ones by the symmetric kernel), the lower blocks as their mirrors
@@ -1032,8 +1159,18 @@ void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, i
   struct Blk { const T* p; int64_t ld; int w; int row0; bool second; };
   Blk blk[8];
   int nb = 0;
-  for (int c0 = 0; c0 < a1 && nb < 8; c0 += TW) blk[nb++] = Blk{In1 + c0, ld1, std::min(TW, a1 - c0), c0, false};
-  for (int c0 = 0; c0 < a2 && nb < 8; c0 += TW) blk[nb++] = Blk{In2 + c0, ld2, std::min(TW, a2 - c0), a1 + c0, true};
+  const int a = a1 + a2;
+  if (a2 > 0 && In2 == In1 + a1 && ld2 == ld1 && a <= 2 * TW && cols_overlap(In1 + (a - TW), TW, (const T*)Out, b, ld1, ldout) &&
+      !cols_overlap(In1, a - TW, (const T*)Out, b, ld1, ldout)) {
+    // In2 continues In1 in memory and Out lies in its last TW columns: two blocks, the last
+    // TW columns (in place) and the rest, so that no block is a sliver that costs a whole
+    // read-modify-write pass over Out
+    blk[nb++] = Blk{In1 + (a - TW), ld1, TW, a - TW, false};
+    blk[nb++] = Blk{In1, ld1, a - TW, 0, false};
+  } else {
+    for (int c0 = 0; c0 < a1 && nb < 8; c0 += TW) blk[nb++] = Blk{In1 + c0, ld1, std::min(TW, a1 - c0), c0, false};
+    for (int c0 = 0; c0 < a2 && nb < 8; c0 += TW) blk[nb++] = Blk{In2 + c0, ld2, std::min(TW, a2 - c0), a1 + c0, true};
+  }
   int first = -1;
   for (int q = 0; q < nb; ++q)
     if (cols_overlap(blk[q].p, blk[q].w, (const T*)Out, b, blk[q].ld, ldout)) first = q;

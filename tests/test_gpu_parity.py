@@ -144,6 +144,44 @@ def test_laplacians_with_growth_fp64(op):
     run_trajectory(wl, 8, "rsvd", op, "fp64", 2, L=8, P=8)
 
 
+def _hub_workload(n0=3000, steps=2, hub_ins=400, hub_del=150, seed=5):
+    """SBM graph whose updates give one node hundreds of changes at once (a row of Delta
+    longer than the 128 entries the row-split product takes), besides appended nodes and
+    scattered changes: the shape of a power-law graph whose hub gains and loses many edges
+    in one update."""
+    wl = W.sbm_small(n0=n0, new_per_step=30, insertions=200, deletions=60, steps=steps, cfg_id=1, graph_id=77)
+    rng = np.random.default_rng(seed)
+    A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
+    deltas = []
+    for d in wl.deltas:
+        n = A.shape[0]
+        taken = set(zip(d.i.tolist(), d.j.tolist()))
+        hub = int(rng.integers(0, n))
+        nbrs = set(A.indices[A.indptr[hub]:A.indptr[hub + 1]].tolist())
+        pair = lambda v: (min(hub, v), max(hub, v))  # noqa: E731
+        ins = [v for v in rng.permutation(n).tolist() if v != hub and v not in nbrs and pair(v) not in taken]
+        dels = [v for v in rng.permutation(sorted(nbrs)).tolist() if pair(v) not in taken]
+        ins, dels = ins[:hub_ins], dels[:hub_del]
+        ei = np.concatenate([d.i, [pair(v)[0] for v in ins + dels]]).astype(np.int64)
+        ej = np.concatenate([d.j, [pair(v)[1] for v in ins + dels]]).astype(np.int64)
+        sg = np.concatenate([d.sign, np.r_[np.ones(len(ins)), -np.ones(len(dels))]]).astype(np.int8)
+        nd = W.Delta(n_old=n, n_new=d.n_new, i=ei, j=ej, sign=sg)
+        deltas.append(nd)
+        A = O.updated_adjacency(A, O.assemble_delta(A, nd.n_new, nd.i, nd.j, nd.sign))
+    return W.Workload(name="sbm_hub", cfg_id=1, n0=wl.n0, rowptr0=wl.rowptr0, col0=wl.col0, deltas=deltas)
+
+
+@pytest.mark.parametrize("op,variant,prec", [("adj", "rsvd", "mixed"), ("lap", "rsvd", "fp64"), ("adj", "g2", "fp32")])
+def test_heavy_delta_rows(op, variant, prec):
+    """A node gains 400 edges and loses some of its own in one update: its row of Delta (over
+    450 entries) goes to the workgroup-per-row path of Delta_1 Xbar (Prop. 3); the trajectory
+    against the oracle's."""
+    wl = _hub_workload()
+    assert max(np.bincount(np.concatenate([d.i, d.j])).max() for d in wl.deltas) > 128
+    kw = dict(L=8, P=8) if variant == "rsvd" else {}
+    run_trajectory(wl, 8, variant, op, prec, 2, **kw)
+
+
 def test_lowrank_projection_sbm_n2000_fp64_g3():
     """The paper's own form of the projected matrix (eq. RR_eigen_graph_upd_main3):
     H = Z^T Xbar Theta Xbar^T Z + Z^T Delta Z with the previous Ritz values, no product with
