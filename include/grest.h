@@ -72,7 +72,9 @@ enum { GREST_F64 = 0, GREST_F32 = 1 };
 /* projected matrix of the Rayleigh-Ritz step: EXACT, H = Z^T A' Z with the stored updated
  * graph (eq. RR_eigen_graph_upd_main2); LOWRANK, H = Z^T (Xbar Theta Xbar^T + Delta) Z
  * with the previous Ritz values Theta (eq. RR_eigen_graph_upd_main3, the form of Alg. 2),
- * which needs no product with the whole graph (adjacency only) */
+ * which needs no product with the whole graph (adjacency and combinatorial Laplacian: for
+ * T = alpha I - L the change of T is Delta minus the degree changes on the rows of Delta,
+ * plus (alpha' - alpha) I on the old nodes and alpha' I on the appended ones) */
 enum { GREST_PROJ_EXACT = 0, GREST_PROJ_LOWRANK = 1 };
 
 typedef struct grest_config {
@@ -83,7 +85,7 @@ typedef struct grest_config {
   int32_t op;         /* GREST_OP_* */
   int32_t precision;  /* GREST_FP64 / GREST_FP32 / GREST_MIXED */
   int32_t max_new;    /* largest S per update for G-REST3 (sizes the basis block) */
-  int32_t proj;       /* GREST_PROJ_EXACT (0) or GREST_PROJ_LOWRANK (op GREST_OP_ADJ only) */
+  int32_t proj;       /* GREST_PROJ_EXACT (0) or GREST_PROJ_LOWRANK (op ADJ or LAP) */
   double rank_tol;    /* relative rank threshold of the orthonormalisation; 0 = default
                          (1e-7 in FP64, 1e-5 otherwise) */
 } grest_config;
@@ -326,7 +328,8 @@ grest_status grest_set_overlap(grest_state* st, int32_t enable);
  * those (the results of an update that breaks them are undefined, not an error).
  * grest_init_pairs and grest_get_graph then return EINVAL and grest_shape reports nnz = -1.
  * Waits for the queued work first.  EINVAL on a NULL state, one with the exact
- * projection or one with a restart policy; calling it again is a no-op.
+ * projection, a Laplacian state (its shift 2 d_max comes from the stored graph) or one with
+ * a restart policy; calling it again is a no-op.
  */
 grest_status grest_release_graph(grest_state* st);
 

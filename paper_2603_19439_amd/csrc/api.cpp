@@ -621,15 +621,37 @@ grest_status rayleigh_ritz(grest_state* st, int64_t n2, const int64_t* rp, const
         launch_tn<T, true>(rows, A, lda, a, B, ldb, bw, st->partial, out, st->stream);
       }
     };
-    product(n2, b.Zc, st->ldz, st->D, b.Zc, st->ldz, st->K, st->Clr);
+    const bool lap = st->op == GREST_OP_LAP;
+    // the Laplacian's form below multiplies I - C C^T - Z_new^T Z_new by the shift alpha =
+    // 2 d_max, which would scale the error of a split-BF16 product up to alpha times itself:
+    // there C and the Gram of the appended rows take FP64 accumulation
+    if (lap)
+      launch_tn<T, true>(n2, b.Zc, st->ldz, st->D, b.Zc, st->ldz, st->K, st->partial, st->Clr, st->stream);
+    else
+      product(n2, b.Zc, st->ldz, st->D, b.Zc, st->ldz, st->K, st->Clr);
     launch_delta_gather<T>(lr->bound, lr->rows, lr->count, lr->dptr, lr->dcol, lr->dsg, b.Zc, st->ldz, st->D, Zg,
-                           Dz, st->stream);
+                           Dz, st->stream, lap);
     if (lr->bound > 0) {
       product(lr->bound, Zg, st->D, st->D, Dz, st->D, st->D, st->H);
     } else {
       launch_fill_rows<double>(st->H, st->D, 0, st->D, st->D, st->stream);
     }
-    launch_lowrank_h(st->D, st->K, st->Clr, st->theta, st->H, st->stream);
+    if (lap) {
+      // The truncated form approximates the shifted operator T = alpha I - L by Xbar Theta
+      // Xbar^T, Theta = alpha - nu.  The pairs are tracked in the L form, and alpha' I - H_T
+      // with H_T = C Theta C^T + Z^T Delta_T Z, Delta_T = T' - pad(T), works out (Z^T Z = I) to
+      //   C nu C^T + Z^T Delta_L Z + alpha (I - C C^T - Z_new^T Z_new),
+      // Delta_L = L' - pad(L) the gathered product and Z_new the appended rows of Z: same
+      // Ritz vectors, nu' = alpha' - theta.  F is free until the eigensolve: it holds the Gram.
+      const int64_t s_new = n2 - st->n;
+      if (s_new > 0)
+        launch_tn<T, true>(s_new, b.Zc + (size_t)st->n * st->ldz, st->ldz, st->D, b.Zc + (size_t)st->n * st->ldz,
+                           st->ldz, st->D, st->partial, st->F, st->stream);
+      launch_lowrank_h(st->D, st->K, st->Clr, st->theta, st->H, st->stream, s_new > 0 ? st->F : nullptr,
+                       st->maxdeg[st->gcur]);
+    } else {
+      launch_lowrank_h(st->D, st->K, st->Clr, st->theta, st->H, st->stream);
+    }
   } else {
     // (op Z) with the updated operator (eq. RR_eigen_graph_upd_main2), L-form for Laplacians
     const int c0 = reuse ? st->K : 0;
@@ -927,7 +949,7 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
       const T* Mrows = b.Y;
       // B^T = Delta_2^T M; B B^T (FP64) and its leading eigenvectors U_L
       launch_delta_mul<T>(2, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, Mrows, st->ldy, Ls,
-                          (T*)st->bt, Ls, s);
+                          (T*)st->bt, Ls, s, nullptr, 0, nullptr, nullptr, 0, &dheavy);
       launch_tn<T, true>(S, (const T*)st->bt, Ls, Ls, (const T*)st->bt, Ls, Ls, st->partial, st->Gm, s);
       if (!small_eig_stage(st, Ls, 0, st->ranks + 3, st->Gm, 2, st->L, st->tol, st->thetab, st->Fb,
                            st->ranks + 4)) {
@@ -1375,7 +1397,7 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   if (cfg->variant == GREST_RSVD && (cfg->L < 1 || cfg->P < 0 || cfg->L + cfg->P > 128)) return GREST_EINVAL;
   if (cfg->variant == GREST_G3 && cfg->max_new < 0) return GREST_EINVAL;
   if (cfg->proj != GREST_PROJ_EXACT && cfg->proj != GREST_PROJ_LOWRANK) return GREST_EINVAL;
-  if (cfg->proj == GREST_PROJ_LOWRANK && cfg->op != GREST_OP_ADJ) return GREST_EINVAL;
+  if (cfg->proj == GREST_PROJ_LOWRANK && cfg->op == GREST_OP_NLAP) return GREST_EINVAL;
   const int64_t m0 = rowptr[n0];
   if (m0 < 0 || (m0 > 0 && !col)) return GREST_EINVAL;
   // host check of the initial CSR: monotone offsets, ids in range, sorted, no self-loops
@@ -1730,6 +1752,10 @@ grest_status grest_release_graph(grest_state* st) {
     return GREST_EINVAL;
   }
   if (st->graph_free) return GREST_OK;
+  if (st->op != GREST_OP_ADJ) {
+    snprintf(g_last_error, sizeof(g_last_error), "a Laplacian state keeps its graph: the shift 2 d_max comes from it");
+    return GREST_EINVAL;
+  }
   if (st->rs_every > 0) {
     snprintf(g_last_error, sizeof(g_last_error), "a state with a restart policy needs its graph");
     return GREST_EINVAL;

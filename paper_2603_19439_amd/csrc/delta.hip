@@ -65,8 +65,18 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
   for (int64_t q = gid >> lpr_shift; q < nrows; q += ngroups) {
     const int64_t r = listed ? (int64_t)a.rows[q] : (MODE == 2) ? a.n_old + q : q;
     const int64_t orow = (MODE == 2) ? q : r;
-    const int64_t beg = a.dptr[r], end = a.dptr[r + 1];
-    if (MODE == 0 && end - beg > skip_deg) continue;  // a heavy row: k_delta0_heavy
+    int64_t beg = a.dptr[r];
+    const int64_t end = a.dptr[r + 1];
+    if (MODE != 1 && end - beg > skip_deg) continue;  // a heavy row: k_delta_heavy
+    if (MODE == 1) {  // the row is sorted by column: start at its first appended column
+      int64_t lo = beg, hi = end;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)a.dcol[mid] < a.n_old) lo = mid + 1;
+        else hi = mid;
+      }
+      beg = lo;
+    }
     for (int c0 = gl * VEC; c0 < w; c0 += lpr * VEC) {
       T acc[VEC];
 #pragma unroll
@@ -132,30 +142,33 @@ __global__ void __launch_bounds__(BS) k_delta(DeltaArgs a, const T* __restrict__
   }
 }
 
-// Mode 0 on the heavy rows of Delta (more than HEAVY_DEG entries: hubs of a power-law graph
-// that gain or lose many edges in one update), one workgroup of HEAVY_BS threads per row:
-// its lane groups take contiguous, equal shares of the row's entries and keep their partial
-// sums (and partial sign sums) in LDS, the workgroup adds them in a fixed order and applies
-// mode 0's epilogue (the Laplacian's degree term, the kept product).  The row-split kernel
-// would leave a row of thousands of entries to one lane group.
-template <typename T, int VEC, int OP>
-__global__ void __launch_bounds__(HEAVY_BS) k_delta0_heavy(DeltaArgs a, const int32_t* __restrict__ hrows,
-                                                           const int64_t* __restrict__ hcount,
-                                                           const T* __restrict__ in, int64_t ldin, int w,
-                                                           T* __restrict__ out, int64_t ldout, T* __restrict__ acc_io,
-                                                           int64_t ldacc, int lpr_shift) {
+// Modes 0 and 2 on the heavy rows of Delta (more than HEAVY_DEG entries: a hub that gains
+// or loses many edges in one update, or an appended node with many edges), one workgroup of
+// HEAVY_BS threads per row: its lane groups take contiguous, equal shares of the row's
+// entries and keep their partial sums (and partial sign sums) in LDS, the workgroup adds
+// them in a fixed order and applies the mode's epilogue (mode 0: the Laplacian's degree term
+// and the kept product; mode 2: the diagonal of the appended block, rows of appended nodes
+// only).  The row-split kernel would leave a row of thousands of entries to one lane group.
+template <typename T, int VEC, int OP, int MODE>
+__global__ void __launch_bounds__(HEAVY_BS) k_delta_heavy(DeltaArgs a, const T* __restrict__ snew,
+                                                          const int32_t* __restrict__ hrows,
+                                                          const int64_t* __restrict__ hcount,
+                                                          const T* __restrict__ in, int64_t ldin, int w,
+                                                          T* __restrict__ out, int64_t ldout, T* __restrict__ acc_io,
+                                                          int64_t ldacc, int lpr_shift) {
   extern __shared__ char delta_smem[];
   T* part = reinterpret_cast<T*>(delta_smem);  // [groups][w]
   __shared__ int32_t gsum[HEAVY_BS];           // sign sum of each group's share
   if ((int64_t)blockIdx.x >= *hcount) return;
   const int64_t r = hrows[blockIdx.x];
+  if (MODE == 2 && r < a.n_old) return;  // mode 2 covers the appended rows only
   const int lpr = 1 << lpr_shift;
   const int groups = HEAVY_BS >> lpr_shift;
   const int grp = threadIdx.x >> lpr_shift, gl = threadIdx.x & (lpr - 1);
   const int64_t beg = a.dptr[r], end = a.dptr[r + 1];
   const int64_t share = (end - beg + groups - 1) / groups;
   const int64_t e0 = min(end, beg + grp * share), e1 = min(end, e0 + share);
-  if (gl == 0) {
+  if (MODE == 0 && gl == 0) {
     int32_t ss = 0;
     for (int64_t e = e0; e < e1; ++e) ss += a.dsg[e];
     gsum[grp] = ss;
@@ -166,8 +179,8 @@ __global__ void __launch_bounds__(HEAVY_BS) k_delta0_heavy(DeltaArgs a, const in
     for (int i = 0; i < VEC; ++i) acc[i] = T(0);
     for (int64_t e = e0; e < e1; ++e) {
       const int64_t c = a.dcol[e];
-      if (c >= a.n_old) continue;
-      const T wgt = T(a.dsg[e]);
+      if (MODE == 0 && c >= a.n_old) continue;
+      const T wgt = MODE == 0 ? T(a.dsg[e]) : d2_weight<T, OP>(a.dsg[e], snew, r, c);
       T z[VEC];
       vload<T, VEC>(in + c * ldin + c0, z);
 #pragma unroll
@@ -178,15 +191,22 @@ __global__ void __launch_bounds__(HEAVY_BS) k_delta0_heavy(DeltaArgs a, const in
   }
   __syncthreads();
   int32_t ssum = 0;
-  for (int g = 0; g < groups; ++g) ssum += gsum[g];
+  if (MODE == 0)
+    for (int g = 0; g < groups; ++g) ssum += gsum[g];
+  const T dgl = MODE == 2 ? d2_diag<T, OP>(a, r) : T(0);
   for (int c = threadIdx.x; c < w; c += HEAVY_BS) {
     T sum = T(0);
     for (int g = 0; g < groups; ++g) sum += part[(size_t)g * w + c];
-    if (OP == OPK_LAP && r < a.n_old && ssum != 0) sum -= T(ssum) * in[r * ldin + c];
-    out[r * ldout + c] = sum;
-    if (acc_io) {
-      if (r >= a.n_old) acc_io[r * ldacc + c] = sum;
-      else acc_io[r * ldacc + c] += sum;
+    if (MODE == 0) {
+      if (OP == OPK_LAP && r < a.n_old && ssum != 0) sum -= T(ssum) * in[r * ldin + c];
+      out[r * ldout + c] = sum;
+      if (acc_io) {
+        if (r >= a.n_old) acc_io[r * ldacc + c] = sum;
+        else acc_io[r * ldacc + c] += sum;
+      }
+    } else {
+      if (dgl != T(0)) sum += dgl * in[r * ldin + c];
+      out[(r - a.n_old) * ldout + c] = sum;
     }
   }
 }
@@ -359,23 +379,23 @@ static void delta_dispatch(int vec, const DeltaArgs& a, const T* snew, const T* 
   if (rows <= 0 || w <= 0) return;
   const int lpr = lanes_per_row(w, vec);
   const int g = grid_for(rows * lpr);
-  const bool hv = MODE == 0 && heavy && heavy->bound > 0;
+  const bool hv = MODE != 1 && heavy && heavy->bound > 0;
   const int64_t skip = hv ? HEAVY_DEG : INT64_MAX;
   constexpr int V = 16 / sizeof(T);
   if (vec == V)
     k_delta<T, V, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc, ilog2(lpr), skip);
   else
     k_delta<T, 1, OP, MODE><<<g, BS, 0, s>>>(a, snew, in, ldin, w, out, ldout, acc_io, ldacc, ilog2(lpr), skip);
-  if constexpr (MODE == 0) {
+  if constexpr (MODE != 1) {
     if (!hv) return;
     const size_t lds = (size_t)(HEAVY_BS / lpr) * w * sizeof(T);
     const unsigned hg = (unsigned)std::min<int64_t>(heavy->bound, a.n_old + a.n_new);
     if (vec == V)
-      k_delta0_heavy<T, V, OP><<<hg, HEAVY_BS, lds, s>>>(a, heavy->rows, heavy->count, in, ldin, w, out, ldout,
-                                                         acc_io, ldacc, ilog2(lpr));
+      k_delta_heavy<T, V, OP, MODE><<<hg, HEAVY_BS, lds, s>>>(a, snew, heavy->rows, heavy->count, in, ldin, w, out,
+                                                              ldout, acc_io, ldacc, ilog2(lpr));
     else
-      k_delta0_heavy<T, 1, OP><<<hg, HEAVY_BS, lds, s>>>(a, heavy->rows, heavy->count, in, ldin, w, out, ldout,
-                                                         acc_io, ldacc, ilog2(lpr));
+      k_delta_heavy<T, 1, OP, MODE><<<hg, HEAVY_BS, lds, s>>>(a, snew, heavy->rows, heavy->count, in, ldin, w, out,
+                                                              ldout, acc_io, ldacc, ilog2(lpr));
   }
 }
 
@@ -385,7 +405,7 @@ static void delta_mode(int mode, int vec, const DeltaArgs& a, const T* snew, con
                        const HeavyRows* heavy) {
   if (mode == 0) delta_dispatch<T, OP, 0>(vec, a, snew, in, ldin, w, out, ldout, acc_io, ldacc, s, bound, heavy);
   else if (mode == 1) delta_dispatch<T, OP, 1>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s, bound, nullptr);
-  else if (mode == 2) delta_dispatch<T, OP, 2>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s, 0, nullptr);
+  else if (mode == 2) delta_dispatch<T, OP, 2>(vec, a, snew, in, ldin, w, out, ldout, nullptr, 0, s, 0, heavy);
   else if (a.n_new > 0) k_delta_dense2<T, OP><<<grid_for(a.n_new), BS, 0, s>>>(a, snew, out, ldout);
 }
 

@@ -37,13 +37,26 @@ __global__ void k_convert(const Ts* s, Td* d, int64_t count) {
 
 // H (d x d) += C diag(theta) C^T, C d x k row-major (the low-rank term of the projected
 // matrix), one entry per thread
+// H += C diag(theta) C^T; with md_old (the combinatorial Laplacian, whose pairs are tracked
+// as the eigenpairs nu of L) also alpha (I - C C^T - Gn) with alpha = 2 md_old and Gn the Gram
+// of the appended rows of the basis (null when there are none)
 __global__ void __launch_bounds__(256) k_lowrank_h(int d, int k, const double* __restrict__ Cm,
-                                                   const double* __restrict__ theta, double* __restrict__ H) {
+                                                   const double* __restrict__ theta, double* __restrict__ H,
+                                                   const double* __restrict__ Gn, const int64_t* md_old) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d * d) return;
   const int i = idx / d, j = idx % d;
-  double acc = H[idx];
-  for (int q = 0; q < k; ++q) acc = fma(Cm[(size_t)i * k + q] * theta[q], Cm[(size_t)j * k + q], acc);
+  double acc = H[idx], cc = 0.0;
+  for (int q = 0; q < k; ++q) {
+    const double ci = Cm[(size_t)i * k + q], cj = Cm[(size_t)j * k + q];
+    acc = fma(ci * theta[q], cj, acc);
+    cc = fma(ci, cj, cc);
+  }
+  if (md_old) {
+    const double alpha = 2.0 * (double)md_old[0];
+    const double p = (i == j ? 1.0 : 0.0) - cc - (Gn ? Gn[idx] : 0.0);
+    acc = fma(alpha, p, acc);
+  }
   H[idx] = acc;
 }
 
@@ -83,9 +96,10 @@ void launch_zero_listed_rows(T* p, int64_t ld, int w, const int32_t* rows, const
 
 void launch_copy_i64(const int64_t* src, int64_t* dst, hipStream_t s) { k_copy_i64<<<1, 64, 0, s>>>(src, dst); }
 
-void launch_lowrank_h(int d, int k, const double* Cm, const double* theta, double* H, hipStream_t s) {
+void launch_lowrank_h(int d, int k, const double* Cm, const double* theta, double* H, hipStream_t s,
+                      const double* Gn, const int64_t* md_old) {
   if (d <= 0) return;
-  k_lowrank_h<<<(d * d + 255) / 256, 256, 0, s>>>(d, k, Cm, theta, H);
+  k_lowrank_h<<<(d * d + 255) / 256, 256, 0, s>>>(d, k, Cm, theta, H, Gn, md_old);
 }
 
 void launch_small_gemm(int m, int p, int q, const double* A, const double* B, double* C, hipStream_t s) {

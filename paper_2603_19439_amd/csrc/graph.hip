@@ -601,7 +601,8 @@ __global__ void __launch_bounds__(256) k_delta_gather(int64_t bound, const int32
                                                       const int64_t* count, const int64_t* __restrict__ dptr,
                                                       const int32_t* __restrict__ dcol,
                                                       const int8_t* __restrict__ dsg, const T* __restrict__ Z,
-                                                      int64_t ldz, int w, T* __restrict__ Zg, T* __restrict__ Dz) {
+                                                      int64_t ldz, int w, T* __restrict__ Zg, T* __restrict__ Dz,
+                                                      int lap) {
   const int lane = threadIdx.x & 63;
   const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (slot >= bound) return;
@@ -611,8 +612,13 @@ __global__ void __launch_bounds__(256) k_delta_gather(int64_t bound, const int32
     if (slot < cnt) {
       const int64_t r = rows[slot];
       double acc = 0.0;
-      for (int64_t e = dptr[r]; e < dptr[r + 1]; ++e) acc += (double)dsg[e] * (double)Z[(int64_t)dcol[e] * ldz + c];
+      int64_t ssum = 0;
+      for (int64_t e = dptr[r]; e < dptr[r + 1]; ++e) {
+        acc += (double)dsg[e] * (double)Z[(int64_t)dcol[e] * ldz + c];
+        ssum += dsg[e];
+      }
       zg = Z[r * ldz + c];
+      if (lap) acc = (double)ssum * (double)zg - acc;  // Delta_L = diag(degree changes) - Delta
       dz = (T)acc;
     }
     Zg[slot * w + c] = zg;
@@ -624,13 +630,15 @@ __global__ void __launch_bounds__(256) k_delta_gather(int64_t bound, const int32
 template <typename T>
 void launch_delta_gather(int64_t bound, const int32_t* rows, const int64_t* count, const int64_t* dptr,
                          const int32_t* dcol, const int8_t* dsg, const T* Z, int64_t ldz, int w, T* Zg, T* Dz,
-                         hipStream_t s) {
+                         hipStream_t s, bool lap) {
   if (bound <= 0 || w <= 0) return;
   k_delta_gather<T><<<(unsigned)((bound + 3) / 4), 256, 0, s>>>(bound, rows, count, dptr, dcol, dsg, Z, ldz, w, Zg,
-                                                                 Dz);
+                                                                 Dz, lap ? 1 : 0);
 }
 
 template void launch_delta_gather<float>(int64_t, const int32_t*, const int64_t*, const int64_t*, const int32_t*,
-                                        const int8_t*, const float*, int64_t, int, float*, float*, hipStream_t);
+                                        const int8_t*, const float*, int64_t, int, float*, float*, hipStream_t,
+                                        bool);
 template void launch_delta_gather<double>(int64_t, const int32_t*, const int64_t*, const int64_t*, const int32_t*,
-                                         const int8_t*, const double*, int64_t, int, double*, double*, hipStream_t);
+                                         const int8_t*, const double*, int64_t, int, double*, double*, hipStream_t,
+                                         bool);

@@ -104,8 +104,8 @@ void launch_heavy_rows(int64_t n, const int64_t* rp, int64_t* flag, int64_t* pos
 // operator's product with the padded block).  Modes 0 and 1 with a row list (rows, *rcount
 // <= bound on the device): only those rows are computed.  Mode 0: out must be zero elsewhere
 // already, and acc_io's appended rows too; mode 1: the list must hold every row it writes.
-// Mode 0 with heavy (the rows of Delta with more than HEAVY_DEG entries): those rows go to a
-// workgroup each.
+// Modes 0 and 2 with heavy (the rows of Delta with more than HEAVY_DEG entries): those rows
+// go to a workgroup each.
 template <typename T>
 void launch_delta_mul(int mode, int op, int64_t n_old, int64_t n_new, const int64_t* dptr,
                       const int32_t* dcol, const int8_t* dsg, const int64_t* maxdeg, const T* snew,
@@ -154,14 +154,18 @@ bool apply_pip_ok(const float* X, int64_t ldx, int kx, const float* W, int64_t l
 bool launch_apply_pip(int64_t n, const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w,
                       const int64_t* flag2, const double* M1, float* Out, int64_t ldout, double* partial, double* C,
                       double* G, hipStream_t s);
-// H (d x d) += C diag(theta) C^T, C d x k row-major FP64
-void launch_lowrank_h(int d, int k, const double* Cm, const double* theta, double* H, hipStream_t s);
+// H (d x d) += C diag(theta) C^T, C d x k row-major FP64; with md_old (the maximum degree of
+// the old graph, device) also alpha (I - C C^T - Gn), alpha = 2 md_old, for the combinatorial
+// Laplacian tracked in the L form (Gn d x d, may be null)
+void launch_lowrank_h(int d, int k, const double* Cm, const double* theta, double* H, hipStream_t s,
+                      const double* Gn = nullptr, const int64_t* md_old = nullptr);
 // Zg[i] = Z[rows[i]], Dz[i] = (Delta Z)[rows[i]] for slots i < *count, zero rows up to bound
-// (outputs bound x w, row-major, ld w)
+// (outputs bound x w, row-major, ld w); with lap, Dz[i] = (Delta_L Z)[rows[i]] instead, Delta_L
+// = diag(degree changes) - Delta the change of the combinatorial Laplacian
 template <typename T>
 void launch_delta_gather(int64_t bound, const int32_t* rows, const int64_t* count, const int64_t* dptr,
                          const int32_t* dcol, const int8_t* dsg, const T* Z, int64_t ldz, int w, T* Zg, T* Dz,
-                         hipStream_t s);
+                         hipStream_t s, bool lap = false);
 // C (m x q) = A (m x p) B (p x q), row-major FP64
 void launch_small_gemm(int m, int p, int q, const double* A, const double* B, double* C, hipStream_t s);
 template <typename Tsrc, typename Tdst>

@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(WG) k_apply(int64_t n, const T* In1, int64_t l
 // outputs are written, so Out may alias In2 (in-place update of a column block).
 // With flag2, the In2 part of row r is read only where flag2[r] != 0 (zero elsewhere).
 // With rows, only the listed rows rows[0 .. min(n, *nrows)) are covered.
-template <int KB, bool VEC>
+template <int KB, bool VEC, bool VOUT>
 __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, int64_t ld1, int a1,
                                                   const float* In2, int64_t ld2, int a2,
                                                   const double* __restrict__ Mg, int b, double alpha, double beta,
@@ -773,8 +773,10 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
   auto row_of = [&](int64_t idx) __attribute__((always_inline)) {
     return rows ? (idx < nl ? (int64_t)rows[idx] : (int64_t)0) : idx;
   };
-  // VEC: a1, a and b are multiples of four and every row start is 16-byte aligned, so a
-  // lane's four columns are either all inside one input block or all past the end
+  // VEC: every input row starts 16 bytes aligned and a1 is a multiple of four (or In2 is
+  // empty), so a lane's four columns lie in one input block; the last group of a block may
+  // pass its end, which stays inside the row (rows are whole multiples of 16 bytes), and is
+  // masked to zero there
   auto load = [&](int64_t t, f32x4(&f)[KB]) __attribute__((always_inline)) {
     const int64_t idx = t * 16 + c16;
     const bool ok = idx < nl;
@@ -789,6 +791,10 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
         f[kb] = (ok && k0 < a && (k0 < a1 || use2))
                     ? *reinterpret_cast<const f32x4*>((k0 < a1 ? b1 : b2) + k0)
                     : f32x4{0.f, 0.f, 0.f, 0.f};
+        const int lim = k0 < a1 ? a1 : a;  // the end of the block the group starts in
+#pragma unroll
+        for (int m = 1; m < 4; ++m)
+          if (k0 + m >= lim) f[kb][m] = 0.f;
       }
     } else {
 #pragma unroll
@@ -810,8 +816,7 @@ __global__ void __launch_bounds__(WG) k_apply_f32(int64_t n, const float* In1, i
     const int col0 = jt * 16 + 4 * g;
     if (!ok || jt >= TB) return;
     float* o = Out + row * ldout + col0;
-    if (VEC) {
-      if (col0 >= b) return;
+    if (VOUT && col0 + 4 <= b) {  // a whole 16-byte group of an aligned output row
       if (beta != 0.0) {
         const f32x4 old = *reinterpret_cast<const f32x4*>(o);
 #pragma unroll
@@ -870,7 +875,7 @@ int device_cus() {
   return cus;
 }
 
-template <int KB, bool VEC>
+template <int KB, bool VEC, bool VOUT>
 void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
                       const double* M, int b, double alpha, double beta, float* Out, int64_t ldout,
                       const int64_t* flag2, const int32_t* rows, const int64_t* nrows, hipStream_t s) {
@@ -882,13 +887,13 @@ void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const fl
   int occ = occ_cache[TB - 1].load(std::memory_order_relaxed);
   if (occ <= 0) {
     static const bool attr = [] {
-      (void)hipFuncSetAttribute((const void*)k_apply_f32<KB, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (void)hipFuncSetAttribute((const void*)k_apply_f32<KB, VEC, VOUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(KB * 8 * 64 * sizeof(f32x4)));
       return true;
     }();
     (void)attr;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_apply_f32<KB, VEC>, WG, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_apply_f32<KB, VEC, VOUT>, WG, lds) != hipSuccess ||
         nb < 1)
       nb = 1;
     occ = nb;
@@ -897,23 +902,23 @@ void apply_f32_launch(int64_t n, const float* In1, int64_t ld1, int a1, const fl
   const int64_t tiles = (n + 15) / 16;
   int64_t g = std::min<int64_t>((tiles + NW - 1) / NW, (int64_t)device_cus() * occ);
   if (g < 1) g = 1;
-  k_apply_f32<KB, VEC><<<(unsigned)g, WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout,
+  k_apply_f32<KB, VEC, VOUT><<<(unsigned)g, WG, lds, s>>>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout,
                                                      flag2, rows, nrows);
 }
 
-template <bool VEC>
+template <bool VEC, bool VOUT>
 void apply_f32_dispatch(int64_t n, const float* In1, int64_t ld1, int a1, const float* In2, int64_t ld2, int a2,
                         const double* M, int b, double alpha, double beta, float* Out, int64_t ldout,
                         const int64_t* flag2, const int32_t* rows, const int64_t* nrows, hipStream_t s) {
   switch ((a1 + a2 + 15) >> 4) {
-    case 1: apply_f32_launch<1, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
-    case 2: apply_f32_launch<2, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
-    case 3: apply_f32_launch<3, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
-    case 4: apply_f32_launch<4, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
-    case 5: apply_f32_launch<5, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
-    case 6: apply_f32_launch<6, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
-    case 7: apply_f32_launch<7, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
-    default: apply_f32_launch<8, VEC>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 1: apply_f32_launch<1, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 2: apply_f32_launch<2, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 3: apply_f32_launch<3, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 4: apply_f32_launch<4, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 5: apply_f32_launch<5, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 6: apply_f32_launch<6, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    case 7: apply_f32_launch<7, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
+    default: apply_f32_launch<8, VEC, VOUT>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s); break;
   }
 }
 
@@ -1160,13 +1165,15 @@ void launch_apply2(int64_t n, const T* In1, int64_t ld1, int a1, const T* In2, i
   Blk blk[8];
   int nb = 0;
   const int a = a1 + a2;
-  if (a2 > 0 && In2 == In1 + a1 && ld2 == ld1 && a <= 2 * TW && cols_overlap(In1 + (a - TW), TW, (const T*)Out, b, ld1, ldout) &&
-      !cols_overlap(In1, a - TW, (const T*)Out, b, ld1, ldout)) {
+  const int c1s = (a - TW + 3) / 4 * 4;
+  if (a2 > 0 && In2 == In1 + a1 && ld2 == ld1 && a <= 2 * TW && c1s < a && c1s <= TW &&
+      cols_overlap(In1 + c1s, a - c1s, (const T*)Out, b, ld1, ldout) && !cols_overlap(In1, c1s, (const T*)Out, b, ld1, ldout)) {
     // In2 continues In1 in memory and Out lies in its last TW columns: two blocks, the last
     // TW columns (in place) and the rest, so that no block is a sliver that costs a whole
     // read-modify-write pass over Out
-    blk[nb++] = Blk{In1 + (a - TW), ld1, TW, a - TW, false};
-    blk[nb++] = Blk{In1, ld1, a - TW, 0, false};
+    const int c1 = (a - TW + 3) / 4 * 4;  // a multiple of four: both blocks keep 16-byte groups
+    blk[nb++] = Blk{In1 + c1, ld1, a - c1, c1, false};
+    blk[nb++] = Blk{In1, ld1, c1, 0, false};
   } else {
     for (int c0 = 0; c0 < a1 && nb < 8; c0 += TW) blk[nb++] = Blk{In1 + c0, ld1, std::min(TW, a1 - c0), c0, false};
     for (int c0 = 0; c0 < a2 && nb < 8; c0 += TW) blk[nb++] = Blk{In2 + c0, ld2, std::min(TW, a2 - c0), a1 + c0, true};
@@ -1197,10 +1204,18 @@ static void apply2_narrow(int64_t n, const T* In1, int64_t ld1, int a1, const T*
     if (vec) apply_launch<T, double, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, rows, nrows, s);
     else apply_launch<T, double, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, rows, nrows, s);
   } else {
-    if (vec && aligned16(Out, ldout) && a1 % 4 == 0 && (a1 + a2) % 4 == 0 && b % 4 == 0)
-      apply_f32_dispatch<true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
+    // 16-byte input groups wherever the input rows are aligned (a block's last group masked
+    // past its end), 16-byte stores wherever the output rows are
+    const bool vin = aligned16(In1, ld1) && (a2 == 0 || (aligned16(In2, ld2) && a1 % 4 == 0));
+    const bool vout = aligned16(Out, ldout);
+    if (vin && vout)
+      apply_f32_dispatch<true, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
+    else if (vin)
+      apply_f32_dispatch<true, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
+    else if (vout)
+      apply_f32_dispatch<false, true>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
     else
-      apply_f32_dispatch<false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
+      apply_f32_dispatch<false, false>(n, In1, ld1, a1, In2, ld2, a2, M, b, alpha, beta, Out, ldout, flag2, rows, nrows, s);
   }
 }
 

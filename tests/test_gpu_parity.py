@@ -29,13 +29,20 @@ def banner(msg):
     sys.stdout.flush()
 
 
-def oracle_values(r: O.StepResult, op: str):
-    return r.theta if op == "adj" else r.nu_rq
+def oracle_values(r: O.StepResult, op: str, proj: str = "exact"):
+    """The values the method reports: Ritz values of the projected matrix.  For the
+    Laplacians nu = shift - theta, evaluated as the quadratic form x^T L x of the Ritz
+    vectors for the exact form (the same number, without cancellation against the shift);
+    the truncated form's Ritz values are those of its own projected matrix, which the
+    quadratic form on the true L does not give."""
+    if op == "adj":
+        return r.theta
+    return r.nu if proj == "lowrank" else r.nu_rq
 
 
-def check_step(st, r, op, prec, k, label):
+def check_step(st, r, op, prec, k, label, proj="exact"):
     vals, X = st.get()
-    ref = oracle_values(r, op)
+    ref = oracle_values(r, op, proj)
     # the gate covers the prefix k* <= K of the tracked set that is separated from the
     # rest by a gap >= 1e-3 of the scale: |theta_1| for the adjacency, the largest tracked
     # nu for the Laplacians
@@ -82,10 +89,10 @@ def run_trajectory(wl, k, variant, op, prec, steps, L=0, P=0, max_new=0, single_
         if check_graph:
             rp, col = st.graph()
             assert np.array_equal(rp, r.A.indptr) and np.array_equal(col, r.A.indices), "graph update differs"
-        vals, X = check_step(st, r, op, prec, k, f"step {t + 1}")
+        vals, X = check_step(st, r, op, prec, k, f"step {t + 1}", proj)
         A = r.A
         if single_step:  # feed the oracle's state back to the GPU
-            st.set_pairs(oracle_values(r, op), r.X)
+            st.set_pairs(oracle_values(r, op, proj), r.X)
         Xo, tho = r.X, r.theta
     st.close()
 
@@ -144,11 +151,11 @@ def test_laplacians_with_growth_fp64(op):
     run_trajectory(wl, 8, "rsvd", op, "fp64", 2, L=8, P=8)
 
 
-def _hub_workload(n0=3000, steps=2, hub_ins=400, hub_del=150, seed=5):
+def _hub_workload(n0=3000, steps=2, hub_ins=400, hub_del=150, seed=5, new_hub=False):
     """SBM graph whose updates give one node hundreds of changes at once (a row of Delta
     longer than the 128 entries the row-split product takes), besides appended nodes and
     scattered changes: the shape of a power-law graph whose hub gains and loses many edges
-    in one update."""
+    in one update.  With new_hub the node is the first appended one (insertions only)."""
     wl = W.sbm_small(n0=n0, new_per_step=30, insertions=200, deletions=60, steps=steps, cfg_id=1, graph_id=77)
     rng = np.random.default_rng(seed)
     A = O.adjacency_from_csr(wl.rowptr0, wl.col0)
@@ -156,12 +163,12 @@ def _hub_workload(n0=3000, steps=2, hub_ins=400, hub_del=150, seed=5):
     for d in wl.deltas:
         n = A.shape[0]
         taken = set(zip(d.i.tolist(), d.j.tolist()))
-        hub = int(rng.integers(0, n))
-        nbrs = set(A.indices[A.indptr[hub]:A.indptr[hub + 1]].tolist())
+        hub = n if new_hub else int(rng.integers(0, n))
+        nbrs = set() if new_hub else set(A.indices[A.indptr[hub]:A.indptr[hub + 1]].tolist())
         pair = lambda v: (min(hub, v), max(hub, v))  # noqa: E731
         ins = [v for v in rng.permutation(n).tolist() if v != hub and v not in nbrs and pair(v) not in taken]
         dels = [v for v in rng.permutation(sorted(nbrs)).tolist() if pair(v) not in taken]
-        ins, dels = ins[:hub_ins], dels[:hub_del]
+        ins, dels = ins[:hub_ins], ([] if new_hub else dels[:hub_del])
         ei = np.concatenate([d.i, [pair(v)[0] for v in ins + dels]]).astype(np.int64)
         ej = np.concatenate([d.j, [pair(v)[1] for v in ins + dels]]).astype(np.int64)
         sg = np.concatenate([d.sign, np.r_[np.ones(len(ins)), -np.ones(len(dels))]]).astype(np.int8)
@@ -171,12 +178,15 @@ def _hub_workload(n0=3000, steps=2, hub_ins=400, hub_del=150, seed=5):
     return W.Workload(name="sbm_hub", cfg_id=1, n0=wl.n0, rowptr0=wl.rowptr0, col0=wl.col0, deltas=deltas)
 
 
-@pytest.mark.parametrize("op,variant,prec", [("adj", "rsvd", "mixed"), ("lap", "rsvd", "fp64"), ("adj", "g2", "fp32")])
-def test_heavy_delta_rows(op, variant, prec):
-    """A node gains 400 edges and loses some of its own in one update: its row of Delta (over
-    450 entries) goes to the workgroup-per-row path of Delta_1 Xbar (Prop. 3); the trajectory
+@pytest.mark.parametrize("op,variant,prec,new_hub", [("adj", "rsvd", "mixed", False), ("lap", "rsvd", "fp64", False),
+                                                     ("adj", "g2", "fp32", False), ("adj", "rsvd", "fp64", True),
+                                                     ("lap", "rsvd", "mixed", True)])
+def test_heavy_delta_rows(op, variant, prec, new_hub):
+    """A node gains 400 edges (and, if it is an old node, loses some of its own) in one
+    update: its row of Delta goes to the workgroup-per-row path of Delta_1 Xbar (Prop. 3)
+    and, for an appended node, of the sketch's Delta_2^T M (Sec. 3.5); the trajectory
     against the oracle's."""
-    wl = _hub_workload()
+    wl = _hub_workload(new_hub=new_hub)
     assert max(np.bincount(np.concatenate([d.i, d.j])).max() for d in wl.deltas) > 128
     kw = dict(L=8, P=8) if variant == "rsvd" else {}
     run_trajectory(wl, 8, variant, op, prec, 2, **kw)
@@ -189,6 +199,16 @@ def test_lowrank_projection_sbm_n2000_fp64_g3():
     form on the same inputs."""
     wl = W.preset("sbm_n2000", steps=5)
     run_trajectory(wl, 8, "g3", "adj", "fp64", 5, max_new=100, proj="lowrank")
+
+
+@pytest.mark.parametrize("variant,prec", [("g3", "fp64"), ("rsvd", "fp64"), ("rsvd", "mixed")])
+def test_lowrank_projection_laplacian(variant, prec):
+    """The low-rank form for the shifted combinatorial Laplacian T = alpha I - L (Sec. 4.2
+    with eq. RR_eigen_graph_upd_main3): Chung-Lu with node growth and a hub, 2 steps,
+    against the oracle's low-rank form (T's change from the degree changes and the shift)."""
+    wl = W.preset("chunglu_n4e6", scale=0.001, steps=2)
+    kw = dict(max_new=64) if variant == "g3" else dict(L=8, P=8)
+    run_trajectory(wl, 8, variant, "lap", prec, 2, proj="lowrank", **kw)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
@@ -366,12 +386,19 @@ def test_restart_policy_argument_checks():
     st.close()
 
 
-def test_lowrank_projection_needs_the_adjacency():
-    banner("lowrank with a Laplacian")
+def test_lowrank_projection_limits():
+    """The low-rank form is refused for the normalised Laplacian (its change rescales every
+    row next to a node whose degree changed), and a Laplacian state keeps its graph."""
+    banner("lowrank limits")
     wl = W.preset("sbm_n2000", scale=0.05, steps=1)
     with pytest.raises(G.GrestError) as e:
-        G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="lap", proj="lowrank")
+        G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="nlap", proj="lowrank")
     assert e.value.status == G.EINVAL
+    st = G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="lap", proj="lowrank")
+    with pytest.raises(G.GrestError) as e:
+        st.release_graph()
+    assert e.value.status == G.EINVAL
+    st.close()
     st = G.State(wl.rowptr0, wl.col0, k=4, variant="g2", op="adj")
     with pytest.raises(G.GrestError) as e:  # the exact form needs its graph
         st.release_graph()

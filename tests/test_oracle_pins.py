@@ -618,3 +618,24 @@ def test_lowrank_equals_exact_on_a_rank_k_graph(variant):
     assert np.allclose(lr.theta, ex.theta, atol=1e-12, rtol=0), (lr.theta, ex.theta)
     # same Ritz subspace (signs aside)
     assert np.abs(np.abs(np.diag(lr.X.T @ ex.X)) - 1.0).max() <= 1e-10
+
+
+# the truncated form for the shifted Laplacians (Sec. 4.2 with eq. RR_eigen_graph_upd_main3):
+# when Xbar holds every pair of the old operator T, pad(T) = Xbar Theta Xbar^T exactly, so
+# the truncated and the exact projected matrices coincide for any update
+@pytest.mark.parametrize("op", ["lap", "nlap"])
+def test_lowrank_equals_exact_for_laplacians_with_all_pairs(op):
+    rng = np.random.default_rng(11)
+    n = 14
+    up = np.triu(rng.random((n, n)) < 0.3, 1)
+    A = sp.csr_matrix((up | up.T).astype(float))
+    th0, X0, _ = O.leading_eigenpairs(A, n, op)
+    assert X0.shape == (n, n)
+    s_new = 2
+    ei = np.array([0, 2, 5, 1, 7], dtype=np.int64)
+    ej = np.array([14, 15, 15, 3, 9], dtype=np.int64)
+    Ad = A.toarray()
+    sg = np.array([1, 1, 1, -1 if Ad[1, 3] else 1, -1 if Ad[7, 9] else 1], dtype=np.int8)
+    ex = O.grest_step(A, X0, th0, s_new, ei, ej, sg, n, variant=O.G2, op=op, proj=O.EXACT)
+    lr = O.grest_step(A, X0, th0, s_new, ei, ej, sg, n, variant=O.G2, op=op, proj=O.LOWRANK)
+    assert np.allclose(lr.theta, ex.theta, atol=1e-10, rtol=0), (lr.theta, ex.theta)
