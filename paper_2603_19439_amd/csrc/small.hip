@@ -347,7 +347,8 @@ __global__ void __launch_bounds__(PCH_WAVES * GREST_WAVE) k_pchol(int m, const d
 // is at most thr (the truncation rule of the pivoted factor holds); otherwise it is
 // cleared and the pivoted kernel runs.  S lives in LDS (upper triangle updated in place,
 // one barrier per column), the inverse is formed row by row from the bottom (one barrier
-// per row).
+// per row).  When S is within 1e-4 of the identity (Frobenius norm) M is instead the
+// third-order polynomial approximation of S^(-1/2) (full rank; see the body).
 // ------------------------------------------------------------------------------------
 constexpr int CNP_M = 64, CNP_T = 256, CNP_P = CNP_M + 1;
 constexpr size_t kCnpDynMax = (size_t)CNP_M * CNP_M * sizeof(double);  // the block C (kc <= 64)
@@ -363,7 +364,7 @@ __device__ __forceinline__ void chol_np_body(int m, const double* __restrict__ G
   __shared__ double Rr[CNP_M * CNP_P];
   __shared__ double Xr[CNP_M * CNP_P];
   __shared__ double rdi[CNP_M];
-  __shared__ double red[CNP_T / GREST_WAVE];
+  __shared__ double red[CNP_T / GREST_WAVE], red2[CNP_T / GREST_WAVE];
   __shared__ int s_bad;
   extern __shared__ double Cs[];  // C (kc x m)
   const int tid = threadIdx.x, lane = tid & (GREST_WAVE - 1), wv = tid / GREST_WAVE;
@@ -396,7 +397,7 @@ __device__ __forceinline__ void chol_np_body(int m, const double* __restrict__ G
   }
   {
     int bad = 0;
-    double mx = 0.0;
+    double mx = 0.0, e2 = 0.0;
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -405,21 +406,131 @@ __device__ __forceinline__ void chol_np_body(int m, const double* __restrict__ G
         if (i < m && j < m) {
           if (!isfinite(v[a][b])) bad = 1;
           if (i == j) mx = fmax(mx, G[(size_t)i * m + i]);
+          const double e = v[a][b] - (i == j ? 1.0 : 0.0);
+          e2 = fma(e, e, e2);
         }
       }
     mx = wave_max_d(mx);
-    if (lane == 0) red[wv] = mx;
+    e2 = wave_sum_d(e2);
+    if (lane == 0) { red[wv] = mx; red2[wv] = e2; }
     if (bad) s_bad = 1;
     if (ty < 2)  // rows 0 and 1, the first pair's
 #pragma unroll
       for (int b = 0; b < NB; ++b) Rr[ty * CNP_P + tx + 16 * b] = v[0][b];
   }
   __syncthreads();
-  double gmx = 0.0;
-  for (int q = 0; q < CNP_T / GREST_WAVE; ++q) gmx = fmax(gmx, red[q]);
+  double gmx = 0.0, ef2 = 0.0;
+  for (int q = 0; q < CNP_T / GREST_WAVE; ++q) {
+    gmx = fmax(gmx, red[q]);
+    ef2 += red2[q];
+  }
   const double thr = tol * tol * fmax(1.0, gmx);
   if (s_bad) {  // leave the non-finite report to the pivoted kernel
     if (tid == 0) *done = 0;
+    return;
+  }
+  // A block that is already orthonormal to within ||S - I||_F <= 1e-4 (the second round of
+  // CholQR2, whose input the first round has orthonormalised; then every eigenvalue of S
+  // lies in 1 +- 1e-4 and no column is dropped) takes M = p(S), the Taylor polynomial of
+  // S^(-1/2) about I to third order: p(S) = I - E/2 + 3E^2/8 - 5E^3/16 with E = S - I.  M
+  // is a polynomial in S, so M^T S M = S p(S)^2 = I - (35/64) E^4 + O(E^5), within 6e-17
+  // of I, and W M spans what W spans; two products of order m replace the factor and
+  // the triangular inverse with their one barrier per row.
+  if (m > 0 && ef2 <= 1e-8) {
+    // E to Rr, E^2 to Xr, then E^3 from both
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = ty + 16 * a, j = tx + 16 * b;
+        Rr[i * CNP_P + j] = (i < m && j < m) ? v[a][b] - (i == j ? 1.0 : 0.0) : 0.0;
+      }
+    __syncthreads();
+    double e2m[NB][NB], e3m[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) { e2m[a][b] = 0.0; e3m[a][b] = 0.0; }
+    for (int q = 0; q < m; ++q) {
+      double ei[NB], eq[NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        ei[a] = Rr[(ty + 16 * a) * CNP_P + q];
+        eq[a] = Rr[q * CNP_P + tx + 16 * a];
+      }
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) e2m[a][b] = fma(ei[a], eq[b], e2m[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) Xr[(ty + 16 * a) * CNP_P + tx + 16 * b] = e2m[a][b];
+    __syncthreads();
+    for (int q = 0; q < m; ++q) {
+      double ei[NB], xq[NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        ei[a] = Rr[(ty + 16 * a) * CNP_P + q];
+        xq[a] = Xr[q * CNP_P + tx + 16 * a];
+      }
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) e3m[a][b] = fma(ei[a], xq[b], e3m[a][b]);
+    }
+    double* Mblk = Mout + (size_t)kc * m;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = ty + 16 * a, j = tx + 16 * b;
+        const double e = Rr[i * CNP_P + j];
+        double mij = fma(-0.3125, e3m[a][b], 0.375 * e2m[a][b]);
+        mij = fma(-0.5, e, mij) + (i == j ? 1.0 : 0.0);
+        v[a][b] = (i < m && j < m) ? mij : 0.0;
+        if (i < m && j < m) Mblk[(size_t)i * m + j] = v[a][b];
+      }
+    __syncthreads();  // every read of E^2 is done
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) Xr[(ty + 16 * a) * CNP_P + tx + 16 * b] = v[a][b];
+    __syncthreads();
+    // rows of -C M
+    for (int l0 = 0; l0 < kc; l0 += CNP_M) {
+      double acc[NB][NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = 0.0;
+      for (int q = 0; q < m; ++q) {
+        double cl[NB], xq[NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const int l = l0 + ty + 16 * a;
+          cl[a] = Cs[(l < kc ? l : 0) * m + q];
+          cl[a] = l < kc ? cl[a] : 0.0;
+          xq[a] = Xr[q * CNP_P + tx + 16 * a];
+        }
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[a][b] = fma(cl[a], xq[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int l = l0 + ty + 16 * a, j = tx + 16 * b;
+          if (l < kc && j < m) Mout[(size_t)l * m + j] = -acc[a][b];
+        }
+    }
+    if (tid == 0) {
+      *rank_out = m;
+      *done = 1;
+    }
     return;
   }
   // right-looking factor: step j subtracts S[i][j] S[j][k] / S[j][j] (i, k > j), with
