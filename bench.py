@@ -122,6 +122,48 @@ def spmm_bytes(n2: int, nnz: int, width: int, elem: int) -> float:
     return 4.0 * nnz + 8.0 * (n2 + 1) + 2.0 * elem * n2 * width
 
 
+def gather_ceiling(res, K):
+    """Average time of grest_calib_gather (random gathers of whole rows, the column ids from
+    a hash) at the timed updates' mean row and entry counts, the entries spread evenly over
+    the rows, and their mix of product widths: the ceiling of the sparse product's own
+    access pattern."""
+    import torch
+    from paper_2603_19439_amd import grest as G
+    sizes, wm = res["sizes"], res["spmm_width"]
+    if not sizes or wm <= 0:
+        return None
+    n2 = int(round(sum(s[0] for s in sizes) / len(sizes)))
+    nnz = int(round(sum(s[1] for s in sizes) / len(sizes)))
+    D = int(sizes[0][2])
+    if D - K + 1e-6 < wm < D - 1e-6:  # the kept product: D - K new columns, all D on a refresh
+        f_full = (wm - (D - K)) / K
+        mix = {D - K: 1.0 - f_full, D: f_full}
+    else:
+        mix = {int(round(wm)): 1.0}
+    ld = (D + 3) // 4 * 4
+    Z = torch.randn(n2, ld, device="cuda")
+    Y = torch.empty(n2, ld, device="cuda")
+    rp = torch.arange(n2 + 1, dtype=torch.int64, device="cuda") * nnz // n2  # entries spread evenly
+    t = 0.0
+    per_width = {}
+    for w, f in mix.items():
+        wp = (w + 3) // 4 * 4
+        for _ in range(40):  # warm-up: the chip's clocks ramp up after the host-side checks
+            G.calib_gather(rp, Z, wp, Y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            G.calib_gather(rp, Z, wp, Y)
+        e1.record()
+        e1.synchronize()
+        per_width[wp] = e0.elapsed_time(e1) / 20
+        t += f * per_width[wp]
+    print(f"[bench] gather ceiling (ms per launch by width): {per_width}", file=sys.stderr, flush=True)
+    del Z, Y, rp
+    torch.cuda.empty_cache()
+    return t
+
+
 def cpu_info():
     """Host CPU model and logical core count (from /proc/cpuinfo)."""
     model, count = "unknown", os.cpu_count()
@@ -460,6 +502,7 @@ def main():
     dominant = max(stages, key=stages.get)
     spmm_avg_ms = main_res["spmm_ms"] / max(1, main_res["updates"])
     achieved = main_res["spmm_bytes"] / (main_res["spmm_ms"] * 1e-3) / 1e9 if main_res["spmm_ms"] > 0 else 0.0
+    ceil_ms = gather_ceiling(main_res, K) if args.precision != "fp64" and spmm_avg_ms > 0 else None
     n0_main = wl.n0
     del wl, dev_steps, replays, exact_oracle
     serve = serving_leg(args) if args.serving_graphs > 0 else None
@@ -504,7 +547,13 @@ def main():
                      "traffic_unit": "GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                      "algorithmic_gb_per_launch": round(main_res["spmm_bytes"] / max(1, len(main_res["sizes"])) / 1e9, 4),
                      "avg_launch_ms": round(spmm_avg_ms, 4),
-                     "width": round(main_res["spmm_width"], 2)},
+                     "width": round(main_res["spmm_width"], 2),
+                     "gather_ceiling": None if ceil_ms is None else {
+                         "avg_launch_ms": round(ceil_ms, 4),
+                         "frac": round(ceil_ms / spmm_avg_ms, 3),
+                         "note": "grest_calib_gather: the same count of whole-row gathers at the same widths, "
+                                 "from uniformly random rows (column ids from a hash instead of memory); "
+                                 "frac = its time / the product's"}},
     }
     if host_res is not None:
         out["host_inputs"] = {"value": round(host_res, 3), "unit": "updates/s",

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgrest.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["graph.hip", "spmm.hip", "delta.hip", "dense.hip", "small.hip", "mfma.hip", "noalloc.hip", "api.cpp", "batch.cpp",
-           "server.cpp"]
+SOURCES = ["graph.hip", "spmm.hip", "delta.hip", "dense.hip", "small.hip", "mfma.hip", "noalloc.hip", "calib.hip",
+           "api.cpp", "batch.cpp", "server.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed FP32 instructions are disabled for all device code

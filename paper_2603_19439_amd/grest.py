@@ -98,6 +98,9 @@ _SIGS = [
     ("grest_server_memory", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     ("grest_server_drain", C.c_int, [C.c_void_p]),
     ("grest_server_destroy", None, [C.c_void_p]),
+    # measurement aid (grest_calib.h)
+    ("grest_calib_gather", C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64,
+                                     C.c_uint64, C.c_void_p]),
 ]
 
 
@@ -158,6 +161,21 @@ def validate_changes(n: int, n_new: int, i, j, sign) -> bool:
     j, pj = _host(j, np.int32)
     s, ps = _host(sign, np.int8)
     return lib().grest_validate_changes(int(n), int(n_new), int(i.size), pi, pj, ps) == OK
+
+
+def calib_gather(rp, Z, w: int, Y, seed: int = 1, stream=None):
+    """Random-gather ceiling (grest_calib_gather): rp a device int64 tensor of n + 1 row
+    pointers, Z and Y device FP32 tensors of n rows whose strides meet the call's rules;
+    the call only enqueues on `stream` (a torch stream, default the current one)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(Z.device)
+    n = int(rp.numel()) - 1
+    if rp.dtype != torch.int64 or not rp.is_cuda or not rp.is_contiguous() or Z.shape[0] != n or Y.shape[0] != n:
+        raise GrestError(1, "calib_gather: rp must be a contiguous device int64 tensor of n + 1 entries, Z and Y n rows")
+    _check(lib().grest_calib_gather(n, C.c_void_p(rp.data_ptr()), C.c_void_p(Z.data_ptr()), int(Z.stride(0)), int(w),
+                                    C.c_void_p(Y.data_ptr()), int(Y.stride(0)), int(seed),
+                                    C.c_void_p(stream.cuda_stream)), "grest_calib_gather")
 
 
 def update_batch(updates):

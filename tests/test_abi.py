@@ -1,5 +1,6 @@
 """The C interface: the library loads without a GPU, exports every entry point that
-include/grest.h declares, and its host-side checks behave as documented."""
+include/*.h declares, and its host-side checks behave as documented."""
+import glob
 import os
 import re
 
@@ -10,16 +11,19 @@ from paper_2603_19439_amd import grest as G
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "grest.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(grest_[a-z_]+)\s*\(", text)))
+def declared_functions(headers=HEADERS):
+    names = set()
+    for h in headers:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(grest_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
-    names = declared_functions()
+    names = declared_functions([HEADER])
     for required in ["grest_create", "grest_set_pairs", "grest_init_pairs", "grest_update", "grest_sync",
                      "grest_get", "grest_destroy", "grest_validate_changes", "grest_strerror"]:
         assert required in names
@@ -108,3 +112,11 @@ def test_checkpoint_header_checks_on_the_host(kw, valid):
             lib.grest_destroy(out)
     else:
         assert rc == G.EINVAL, rc
+
+
+@pytest.mark.parametrize("n,w,ldz,ldy", [(0, 8, 8, 8), (2**31, 8, 8, 8), (10, 6, 8, 8), (10, 8, 6, 8),
+                                         (10, 8, 8, 10), (10, 8, 8, 8)])
+def test_calib_gather_rejects_bad_arguments_on_the_host(n, w, ldz, ldy):
+    # every case is refused before a launch (the last for its null buffers)
+    rc = G.lib().grest_calib_gather(n, None, None, ldz, w, None, ldy, 1, None)
+    assert rc == 1
