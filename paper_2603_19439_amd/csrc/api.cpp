@@ -906,8 +906,15 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // ---- Delta Xbar = Delta_1 X (Prop. 3) ----
   const HeavyRows dheavy{st->dhrows, st->dhcnt, dh_bound};
   if (sparse_dx) {
-    // zero the block, then visit only the rows of Delta (the row list of the graph stage)
-    launch_fill_rows<T>(dX, st->ldz, 0, n2, K, s);
+    // visit only the rows of Delta (the row list of the graph stage); the rest of the block
+    // is zeroed first unless the projection's first round reads the listed rows alone (it
+    // then writes the whole block)
+    bool listed_only = false;
+    if constexpr (sizeof(T) == 4) {
+      listed_only = rsvd ? orth_reads_listed_rows_only(b.Zc, st->ldz, K + st->L, dX, st->ldz, K)
+                         : orth_reads_listed_rows_only(b.Zc, st->ldz, K, b.W, st->ldz, st->Dw);
+    }
+    if (!listed_only) launch_fill_rows<T>(dX, st->ldz, 0, n2, K, s);
     if (reuse) launch_fill_rows<T>(b.aux, st->ldq, n, S, K, s);
     launch_delta_mul<T>(0, st->op, n, S, dptr, dcol, dsg, maxdeg, sc_new, b.Zc, st->ldz, K, dX, st->ldz, s,
                         reuse ? b.aux : nullptr, st->ldq, st->drows, st->dpos + n2, std::min<int64_t>(n2, 2 * nc),

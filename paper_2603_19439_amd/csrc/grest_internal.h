@@ -154,6 +154,10 @@ bool apply_pip_ok(const float* X, int64_t ldx, int kx, const float* W, int64_t l
 bool launch_apply_pip(int64_t n, const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w,
                       const int64_t* flag2, const double* M1, float* Out, int64_t ldout, double* partial, double* C,
                       double* G, hipStream_t s);
+// Whether the fused FP32 CholQR2 against X of a block W in place (apply_pip_ok and a read
+// pass launch_pip covers) reads W on the listed (flagged) rows alone in its first round:
+// then W need not be zero elsewhere beforehand.
+bool orth_reads_listed_rows_only(const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w);
 // H (d x d) += C diag(theta) C^T, C d x k row-major FP64; with md_old (the maximum degree of
 // the old graph, device) also alpha (I - C C^T - Gn), alpha = 2 md_old, for the combinatorial
 // Laplacian tracked in the L form (Gn d x d, may be null)

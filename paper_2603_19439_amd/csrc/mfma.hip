@@ -1078,6 +1078,12 @@ static void pip_launch(int g, int64_t n, int64_t rpc, const T* X, int64_t ldx, i
   k_pip<T, Tcx, TXC, TWC><<<g, WG, lds, s>>>(n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows);
 }
 
+// the (kx / 16, w / 16) block shapes of the read pass
+inline bool pip_shape(int tx, int tw) {
+  return (tx == 2 && tw == 4) || (tx == 4 && tw == 2) || (tx == 3 && tw == 2) || (tx == 2 && tw == 1) ||
+         (tx == 2 && tw == 2) || (tx == 1 && tw == 4) || (tx == 1 && tw == 2) || (tx == 1 && tw == 1);
+}
+
 template <typename T>
 bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t ldw, int w, double* partial,
                 double* C, double* G, hipStream_t s, const int32_t* rows, const int64_t* nrows) {
@@ -1089,6 +1095,7 @@ bool launch_pip(int64_t n, const T* X, int64_t ldx, int kx, const T* W, int64_t 
   double* partC = partial;
   double* partG = partial + (size_t)g * kx * w;
   using Tcx = typename std::conditional<sizeof(T) == 8, double, float>::type;
+  if (!pip_shape(TX, TWt)) return false;
   if (TX == 2 && TWt == 4) pip_launch<T, Tcx, 2, 4>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
   else if (TX == 4 && TWt == 2) pip_launch<T, Tcx, 4, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
   else if (TX == 3 && TWt == 2) pip_launch<T, Tcx, 3, 2>(g, n, rpc, X, ldx, kx, W, ldw, w, partC, partG, rows, nrows, s);
@@ -1440,6 +1447,10 @@ bool apply_pip_ok(const float* X, int64_t ldx, int kx, const float* W, int64_t l
                   int64_t ldout) {
   return kx > 0 && w > 0 && kx % 16 == 0 && w % 16 == 0 && apply_pip_shape(kx / 16, w / 16) && aligned16(X, ldx) &&
          aligned16(W, ldw) && aligned16(Out, ldout);
+}
+
+bool orth_reads_listed_rows_only(const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w) {
+  return apply_pip_ok(X, ldx, kx, W, ldw, w, W, ldw) && pip_shape((kx + 15) >> 4, (w + 15) >> 4);
 }
 
 bool launch_apply_pip(int64_t n, const float* X, int64_t ldx, int kx, const float* W, int64_t ldw, int w,
