@@ -1142,20 +1142,46 @@ __global__ void __launch_bounds__(GREST_WAVE) k_bisect(double* work) {
 // ------------------------------------------------------------------------------------
 // 3. selection, inverse iteration and back-transform: one wave per output slot
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ bool sel_less(int which, double ta, int ia, double tb, int ib) {
-  // true if (ta, ia) comes before (tb, ib) in output order
-  if (which == 0) {  // largest magnitude, then larger algebraic, then lower index
-    const double aa = fabs(ta), ab = fabs(tb);
-    if (aa != ab) return aa > ab;
-    if (ta != tb) return ta > tb;
-    return ia < ib;
+// true if (ta, ia) comes before (tb, ib) in output order; WHICH 0: largest magnitude, then
+// larger algebraic, then lower index; 1: smallest algebraic, then lower index; 2: largest
+// algebraic, then lower index.  Written without branches (it runs in the inner loop of
+// the ranking).
+template <int WHICH>
+__device__ __forceinline__ bool sel_before(double ta, int ia, double tb, int ib) {
+  const bool tie = (ta == tb) & (ia < ib);
+  if (WHICH == 1) return (ta < tb) | tie;
+  if (WHICH == 2) return (ta > tb) | tie;
+  const double aa = fabs(ta), ab = fabs(tb);
+  return (aa > ab) | ((aa == ab) & ((ta > tb) | tie));
+}
+
+// rank of every entry of sev[0, n) in output order, each lane ranking its own entries
+// against all n values, which are broadcast from the lanes' registers one at a time
+template <int WHICH>
+__device__ __forceinline__ void rank_values(const double* sev, int n, int (&rk)[NCOL]) {
+  const int lane = threadIdx.x & (GREST_WAVE - 1);
+  double tv[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    const int i = lane + GREST_WAVE * c;
+    tv[c] = i < n ? sev[i] : 0.0;
+    rk[c] = 0;
   }
-  if (which == 1) {  // smallest algebraic
-    if (ta != tb) return ta < tb;
-    return ia < ib;
+#pragma unroll
+  for (int cj = 0; cj < NCOL; ++cj) {
+    const int lmax = n - GREST_WAVE * cj < GREST_WAVE ? n - GREST_WAVE * cj : GREST_WAVE;
+#pragma unroll 4
+    for (int l = 0; l < lmax; ++l) {
+      const int j = GREST_WAVE * cj + l;
+      const double tj = readlane_d(tv[cj], l);
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c)
+        if (GREST_WAVE * c < n) {
+          const int i = lane + GREST_WAVE * c;
+          rk[c] += (int)((i < n) & (j != i) & sel_before<WHICH>(tj, j, tv[c], i));
+        }
+    }
   }
-  if (ta != tb) return ta > tb;  // largest algebraic
-  return ia < ib;
 }
 
 __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
@@ -1183,12 +1209,19 @@ __device__ __forceinline__ void eigvec_body(int d_full, int which, int kk, doubl
   }
   __syncthreads();
   // rank of every eigenvalue in output order
-  for (int i = lane; i < n; i += GREST_WAVE) {
-    int rk = 0;
-    const double ti = sev[i];
-    for (int j = 0; j < n; ++j) rk += (j != i) && sel_less(which, sev[j], j, ti, i);
-    sslot[i] = rk < kk ? rk : -1;
-    if (rk < kk) ssel[rk] = i;
+  {
+    int rk[NCOL];
+    if (which == 0) rank_values<0>(sev, n, rk);
+    else if (which == 1) rank_values<1>(sev, n, rk);
+    else rank_values<2>(sev, n, rk);
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      const int i = lane + GREST_WAVE * c;
+      if (i < n) {
+        sslot[i] = rk[c] < kk ? rk[c] : -1;
+        if (rk[c] < kk) ssel[rk[c]] = i;
+      }
+    }
   }
   double tmax = -INFINITY;
   for (int i = lane; i < n; i += GREST_WAVE) tmax = fmax(tmax, sev[i]);
@@ -1231,26 +1264,27 @@ __device__ __forceinline__ void eigvec_body(int d_full, int which, int kk, doubl
     shift_prev = lam;
     // LU with partial pivoting of T - lam I (U has three diagonals; 1/U_ii is stored),
     // pivots below tiny are raised to tiny
+    // The sequential loops below (lane 0) are written without branches but the rare
+    // rescaling, so that consecutive steps can be unrolled and their LDS reads issued early.
     if (lane == 0) {
       double a = sdg[0] - lam, bsup = n > 1 ? sod[0] : 0.0;
+#pragma unroll 4
       for (int i = 0; i + 1 < n; ++i) {
         const double c = sod[i];
         const double an = sdg[i + 1] - lam;
         const double bn = i + 2 < n ? sod[i + 1] : 0.0;
-        if (fabs(a) >= fabs(c)) {
-          const double pa = fabs(a) < tiny ? (a < 0.0 ? -tiny : tiny) : a;
-          const double ia = recip(pa);
-          const double l = c * ia;
-          u0i[i] = ia; u1[i] = bsup; u2[i] = 0.0; lm[i] = l; pv[i] = 0;
-          a = fma(-l, bsup, an);
-          bsup = bn;
-        } else {
-          const double ic = recip(c);
-          const double l = a * ic;
-          u0i[i] = ic; u1[i] = an; u2[i] = bn; lm[i] = l; pv[i] = 1;
-          a = fma(-l, an, bsup);
-          bsup = -l * bn;
-        }
+        const bool sw = !(fabs(a) >= fabs(c));  // row interchange
+        const double pa = fabs(a) < tiny ? (a < 0.0 ? -tiny : tiny) : a;
+        const double ip = recip(sw ? c : pa);
+        const double l = (sw ? a : c) * ip;
+        u0i[i] = ip;
+        u1[i] = sw ? an : bsup;
+        u2[i] = sw ? bn : 0.0;
+        lm[i] = l;
+        pv[i] = sw ? 1 : 0;
+        const double a_next = sw ? fma(-l, an, bsup) : fma(-l, bsup, an);
+        bsup = sw ? -l * bn : bn;
+        a = a_next;
       }
       const double pa = fabs(a) < tiny ? (a < 0.0 ? -tiny : tiny) : a;
       u0i[n - 1] = recip(pa);
@@ -1262,11 +1296,13 @@ __device__ __forceinline__ void eigvec_body(int d_full, int which, int kk, doubl
     for (int it = 0; it < 2; ++it) {
       if (lane == 0) {
         double x = yv[0];
+#pragma unroll 4
         for (int i = 0; i + 1 < n; ++i) {  // L^{-1} with the row interchanges
-          double xn = yv[i + 1];
-          if (pv[i]) { const double t = x; x = xn; xn = t; }
-          yv[i] = x;
-          x = fma(-lm[i], x, xn);
+          const double xn = yv[i + 1];
+          const bool sw = pv[i] != 0;
+          const double xa = sw ? xn : x, xb = sw ? x : xn;
+          yv[i] = xa;
+          x = fma(-lm[i], xa, xb);
         }
         yv[n - 1] = x;
         double x1 = 0.0, x2 = 0.0;  // U^{-1}; rescaled when it grows (tiny pivots)
@@ -1343,48 +1379,91 @@ __global__ void __launch_bounds__(GREST_WAVE) k_eigvec(int d_full, int which, in
   eigvec_body(d_full, which, kk, drop_tol, work, theta_out, F, kept_out, status, (int)blockIdx.x);
 }
 
+// The loops of the back-transform walk rows of the work table (the other slots' vectors,
+// then the reflectors) whose loads do not depend on the running vector: each keeps the
+// next PF rows in flight in a ring of registers, refilled as soon as a row is consumed, so
+// that a step waits for its dot product and not for a round trip to memory (PF steps of a
+// few hundred cycles cover it; the workgroup is one wave, so registers are plentiful).
+// Entries past n are zero in every row and are left out.
+constexpr int BT_PF = 16;
+
 __device__ __forceinline__ void backtr_body(int d_full, int kk, const double* work, double* F, const int bx) {
   __shared__ double ysh[MAXN];
+  __shared__ unsigned char sfl[MAXN];
   const int slot = bx, lane = threadIdx.x;
   if (work[W_FL + slot] == 0.0) return;
   const int n = (int)work[W_HDR];
   const int s1 = (int)work[W_HDR + 5], seg2 = (int)work[W_HDR + 6];
+  const int nc = (n + GREST_WAVE - 1) / GREST_WAVE;  // elements of a length-n vector per lane
   const double* R = work + W_R;
   const double* hb = work + W_HB;
   const double* Yb = work + W_Y;
+  for (int t = lane; t < kk; t += GREST_WAVE) sfl[t] = work[W_FL + t] != 0.0;
+  wave_lds_fence();
+  auto get_y = [&](int t, double(&o)[NCOL]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) o[c] = (t < kk && c < nc) ? Yb[(size_t)t * MAXN + lane + GREST_WAVE * c] : 0.0;
+  };
+  auto get_r = [&](int k, double(&o)[NCOL], double& b) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) o[c] = (k >= 0 && c < nc) ? R[(size_t)k * MAXN + lane + GREST_WAVE * c] : 0.0;
+    b = k >= 0 ? hb[k] : 0.0;
+  };
+  constexpr int PF = BT_PF;
   double ys[NCOL], cc[NCOL];
+  get_y(slot, ys);
 #pragma unroll
-  for (int c = 0; c < NCOL; ++c) {
-    ys[c] = Yb[(size_t)slot * MAXN + lane + GREST_WAVE * c];
-    cc[c] = 0.0;
-  }
-  for (int t = 0; t < kk; ++t) {
-    if (t == slot || work[W_FL + t] == 0.0) continue;
-    double yt[NCOL], ep = 0.0;
+  for (int c = 0; c < NCOL; ++c) cc[c] = 0.0;
+  double ring[PF][NCOL];
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) {
-      yt[c] = Yb[(size_t)t * MAXN + lane + GREST_WAVE * c];
-      ep = fma(yt[c], ys[c], ep);
+  for (int p = 0; p < PF; ++p) get_y(p, ring[p]);
+  for (int t0 = 0; t0 < kk; t0 += PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int t = t0 + p;
+      double yt[NCOL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) yt[c] = ring[p][c];
+      get_y(t + PF, ring[p]);
+      if (t < kk && t != slot && sfl[t]) {
+        double ep = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c)
+          if (c < nc) ep = fma(yt[c], ys[c], ep);
+        const double e = wave_sum_d(ep);
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c)
+          if (c < nc) cc[c] = fma(e, yt[c], cc[c]);
+      }
     }
-    const double e = wave_sum_d(ep);
-#pragma unroll
-    for (int c = 0; c < NCOL; ++c) cc[c] = fma(e, yt[c], cc[c]);
   }
   double y[NCOL];
 #pragma unroll
   for (int c = 0; c < NCOL; ++c) y[c] = fma(-0.5, cc[c], ys[c]);
   // back-transform y <- P_0 ... P_{n-3} y
-  for (int k = n - 3; k >= 0; --k) {
-    const double beta = hb[k];
-    double rk[NCOL], dp = 0.0;
+  double bring[PF];
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) {
-      rk[c] = R[(size_t)k * MAXN + lane + GREST_WAVE * c];
-      dp = fma(rk[c], y[c], dp);
+  for (int p = 0; p < PF; ++p) get_r(n - 3 - p, ring[p], bring[p]);
+  for (int k0 = n - 3; k0 >= 0; k0 -= PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int k = k0 - p;
+      double rk[NCOL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) rk[c] = ring[p][c];
+      const double beta = bring[p];
+      get_r(k - PF, ring[p], bring[p]);
+      if (k >= 0) {
+        double dp = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c)
+          if (c < nc) dp = fma(rk[c], y[c], dp);
+        const double d = beta * wave_sum_d(dp);
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c)
+          if (c < nc) y[c] = fma(-d, rk[c], y[c]);
+      }
     }
-    const double d = beta * wave_sum_d(dp);
-#pragma unroll
-    for (int c = 0; c < NCOL; ++c) y[c] = fma(-d, rk[c], y[c]);
   }
   // F row of reduced index i is mp(i); the rows outside the map are zero
 #pragma unroll
