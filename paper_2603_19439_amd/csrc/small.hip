@@ -131,6 +131,18 @@ __device__ __forceinline__ void column_to_lds(const double (&A)[RW][C], int j, i
     }
   }
 }
+// The same for a buffer of NWV * RW entries whose entries past n are never used: every row
+// is written (the rows past n hold zeros), so the writing lane issues its stores back to
+// back instead of one branch per row.
+template <int RW, int C, int NWV>
+__device__ __forceinline__ void column_to_lds_full(const double (&A)[RW][C], int j, int wv, double* buf) {
+  const int lane = threadIdx.x & (GREST_WAVE - 1);
+  if (lane == (j & (GREST_WAVE - 1))) {
+    const int cj = j >> 6;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) buf[wv + NWV * r] = pick<C>(A[r], cj);
+  }
+}
 
 // ------------------------------------------------------------------------------------
 // pivoted Cholesky:  G(P) = R^T R  truncated at the first pivot <= (tol*scale)^2
@@ -821,7 +833,7 @@ __device__ __forceinline__ void tridiag_body(int d_full, int base, const int32_t
   if (bad) atomicOr(status, ST_NONFINITE_H);
   // column k of the current matrix is kept in registers by every wave (colk); column 0 is
   // gathered through LDS once
-  if (n >= 1) column_to_lds<RW, C, NW>(A, 0, wv, n, colb[1]);
+  if (n >= 1) column_to_lds_full<RW, C, NW>(A, 0, wv, colb[1]);
   __syncthreads();
   double colk[C];
 #pragma unroll
@@ -883,7 +895,7 @@ __device__ __forceinline__ void tridiag_body(int d_full, int base, const int32_t
       for (int c = 0; c < C; ++c) pwv[pb][wv][lane + GREST_WAVE * c] = pp[c];
     }
     // column k+1 before this reflection, for the next reflector
-    column_to_lds<RW, C, NW>(A, k + 1, wv, n, colb[pb]);
+    column_to_lds_full<RW, C, NW>(A, k + 1, wv, colb[pb]);
     __syncthreads();  // the only barrier of the step (buffers alternate with k)
     if (beta != 0.0) {
       double w[C];  // first p = beta A v, then w = p - K v
@@ -933,7 +945,7 @@ __device__ __forceinline__ void tridiag_body(int d_full, int base, const int32_t
   if (n >= 2) {
     const double d2 = vec_elem<C>(colk, n - 2), e2 = vec_elem<C>(colk, n - 1);
     if (tid == 0) { sdg[n - 2] = d2; sod[n - 2] = e2; shb[n - 2] = 0.0; }
-    column_to_lds<RW, C, NW>(A, n - 1, wv, n, colb[0]);
+    column_to_lds_full<RW, C, NW>(A, n - 1, wv, colb[0]);
     __syncthreads();
     if (tid == 0) { sdg[n - 1] = colb[0][n - 1]; sod[n - 1] = 0.0; shb[n - 1] = 0.0; }
   } else if (n == 1) {
