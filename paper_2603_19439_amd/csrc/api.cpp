@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
@@ -49,15 +50,22 @@ void set_err(const char* what, hipError_t e) {
 
 constexpr int32_t VALIDATION_BITS = ST_BAD_FORMAT | ST_DUPLICATE | ST_INSERT_EXISTING | ST_DELETE_MISSING;
 
+// Host-pinned results.  status, ranks and the Ritz values (which follow the struct in the
+// same allocation, theta_pin) mirror the device block outbox, [status | ranks | pad | theta],
+// so that the end of an update copies them back in one transfer.
 struct Pinned {
-  int32_t status;  // numerical status of the last update (copied at its end)
-  int32_t ranks[8];
   struct {
     int32_t vstatus;  // validation status of the update that used this slot
     int64_t m_new;
     int64_t hcount;   // heavy rows of the new graph
   } g[2];
+  int32_t status;  // numerical status of the last update (copied at its end)
+  int32_t ranks[8];
+  int32_t pad;
 };
+constexpr size_t OUT_HDR = sizeof(int32_t) * 10;  // status, ranks, pad: theta starts here
+static_assert(offsetof(Pinned, status) + OUT_HDR == sizeof(Pinned), "theta_pin follows Pinned::status at OUT_HDR");
+static_assert(sizeof(Pinned) % sizeof(double) == 0, "theta_pin is 8-byte aligned");
 
 template <typename P>
 grest_status dalloc(P** p, size_t count) {
@@ -152,7 +160,11 @@ struct grest_state {
   void* zg = nullptr;
   void* dz = nullptr;
   double* Clr = nullptr;
-  double *theta = nullptr, *Fb = nullptr, *thetab = nullptr, *partial = nullptr, *eigwork = nullptr;
+  double *Fb = nullptr, *thetab = nullptr, *partial = nullptr, *eigwork = nullptr;
+  // outbox: status word, kept column counts and Ritz values in one device block (the
+  // layout of Pinned from status on), carved into status, ranks and theta
+  void* outbox = nullptr;
+  double* theta = nullptr;
   int32_t* ranks = nullptr;
   int32_t* status = nullptr;
   int64_t* maxdeg[2] = {nullptr, nullptr};  // largest degree of CSR buffer b
@@ -361,8 +373,7 @@ int64_t device_bytes(const grest_state* st) {
   }
   add(st->C1); add(st->C2); add(st->Gm); add(st->Mchol); add(st->H); add(st->F); add(st->Msk); add(st->M1buf);
   add(st->zg); add(st->dz); add(st->Clr);
-  add(st->theta); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
-  add(st->ranks); add(st->status);
+  add(st->outbox); add(st->Fb); add(st->thetab); add(st->partial); add(st->eigwork);
   return total;
 }
 
@@ -387,10 +398,11 @@ void free_all(grest_state* st) {
   }
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F); dfree(st->Msk); dfree(st->M1buf);
   dfree(st->zg); dfree(st->dz); dfree(st->Clr);
-  dfree(st->theta); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
-  dfree(st->ranks); dfree(st->status);
-  if (st->pin) (void)hipHostFree(st->pin);
-  if (st->theta_pin) (void)hipHostFree(st->theta_pin);
+  dfree(st->outbox); dfree(st->Fb); dfree(st->thetab); dfree(st->partial); dfree(st->eigwork);
+  st->theta = nullptr;
+  st->ranks = nullptr;
+  st->status = nullptr;
+  if (st->pin) (void)hipHostFree(st->pin);  // theta_pin lives in the same allocation
   st->pin = nullptr;
   st->theta_pin = nullptr;
 }
@@ -1007,9 +1019,8 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
                          ds, lr));
   else
     CHK(rayleigh_ritz<T>(st, n2, st->rp[gn], st->col[gn], sc_new, K, st->ranks + 1, reuse, 0, nullptr, ds, lr));
-  HIPCHK(hipMemcpyAsync(st->theta_pin, st->theta, st->K * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&st->pin->status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(st->pin->ranks, st->ranks, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // status, ranks and the K Ritz values in one transfer (outbox mirrors Pinned from status on)
+  HIPCHK(hipMemcpyAsync(&st->pin->status, st->outbox, OUT_HDR + st->K * sizeof(double), hipMemcpyDeviceToHost, s));
   // ---- commit ----
   if (st->marking) {  // the next update records into the other set
     st->prof_pending[st->pslot] = true;
@@ -1476,15 +1487,16 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   if ((rc = dalloc(&st->Msk, (size_t)(st->K + wmax) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
   // F and theta hold all the pairs of a block of the initial eigensolver (up to D)
   if ((rc = dalloc(&st->F, (size_t)dmax * dmax)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->theta, dmax)) != GREST_OK) return fail(rc);
+  if ((rc = dalloc((char**)&st->outbox, OUT_HDR + (size_t)dmax * sizeof(double))) != GREST_OK) return fail(rc);
+  st->status = reinterpret_cast<int32_t*>(st->outbox);
+  st->ranks = st->status + 1;
+  st->theta = reinterpret_cast<double*>(static_cast<char*>(st->outbox) + OUT_HDR);
   if ((rc = dalloc(&st->Fb, (size_t)std::max(st->Ls, 1) * std::max(st->L, 1))) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->thetab, std::max(st->L, 1))) != GREST_OK) return fail(rc);
   st->partial_elems = (int64_t)tn_num_chunks(INT64_MAX / 4) * dmax * dmax;
   if ((rc = dalloc(&st->partial, st->partial_elems)) != GREST_OK) return fail(rc);
   const int64_t ework = std::max(eig_work_elems(std::max(dmax, std::max(st->Ls, 1))), pchol_work_elems(wmax, st->K));
   if ((rc = dalloc(&st->eigwork, ework)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->ranks, 8)) != GREST_OK) return fail(rc);
-  if ((rc = dalloc(&st->status, 1)) != GREST_OK) return fail(rc);
   if ((rc = dalloc(&st->dhcnt, 1)) != GREST_OK) return fail(rc);
   for (int b = 0; b < 2; ++b) {
     if ((rc = dalloc(&st->hcnt[b], 1)) != GREST_OK) return fail(rc);
@@ -1495,9 +1507,10 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
     if (hipEventCreateWithFlags(&st->gate[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
   }
   if ((rc = dalloc(&st->srows_cnt, 1)) != GREST_OK) return fail(rc);
-  if (hipHostMalloc((void**)&st->pin, sizeof(Pinned)) != hipSuccess) return fail(GREST_ENOMEM);
-  if (hipHostMalloc((void**)&st->theta_pin, st->K * sizeof(double)) != hipSuccess) return fail(GREST_ENOMEM);
-  memset(st->pin, 0, sizeof(Pinned));
+  if (hipHostMalloc((void**)&st->pin, sizeof(Pinned) + (size_t)st->K * sizeof(double)) != hipSuccess)
+    return fail(GREST_ENOMEM);
+  st->theta_pin = reinterpret_cast<double*>(st->pin + 1);
+  memset(st->pin, 0, sizeof(Pinned) + (size_t)st->K * sizeof(double));
   // upload the graph
   st->n = n0;
   st->m = m0;
