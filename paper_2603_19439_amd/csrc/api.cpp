@@ -762,18 +762,23 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // It writes CSR buffer gn and Delta slot ds.  Without the overlap mode it simply
   // follows the earlier work on the one stream.  With it, it waits only for the last
   // readers of what it overwrites: the update two calls back, which used slot ds and
-  // read buffer gn as its new graph; and the previous update as well when that one read
-  // buffer gn too (the normalised Laplacian's Delta Xbar reads the old graph, and a
-  // rejected update's queued work reads the scales of buffer gn).  It also starts no
-  // earlier than the previous update's small eigensolve, so that its many short kernels
-  // do not queue behind the wide ones before it.
+  // read buffer gn as its new graph; and the previous update, which read buffer gn as its
+  // old graph in its own graph stage and, for the normalised Laplacian, in its Delta Xbar.
+  // The previous update's gate (recorded before its small eigensolve, after every such
+  // read) is enough for that, and it also keeps this stage's many short kernels from
+  // queueing behind the wide ones before it.  Without a gate from the previous update
+  // (it stopped early) the stage waits for that update's end, as it does after a rejected
+  // update, whose queued work reads the scales of buffer gn.
   hipStream_t gs = st->gstream;
+  st->gate_recorded[ds] = false;  // this update's gate, once it is recorded
   if (gs != s) {
     if (st->end_recorded[ds]) HIPCHK(hipStreamWaitEvent(gs, st->endev[ds], 0));
-    if ((st->op == GREST_OP_NLAP || st->prev_rejected) && st->end_recorded[ds ^ 1])
+    if (st->prev_rejected && st->end_recorded[ds ^ 1])
       HIPCHK(hipStreamWaitEvent(gs, st->endev[ds ^ 1], 0));
     else if (st->gate_recorded[ds ^ 1])
       HIPCHK(hipStreamWaitEvent(gs, st->gate[ds ^ 1], 0));
+    else if (st->end_recorded[ds ^ 1])
+      HIPCHK(hipStreamWaitEvent(gs, st->endev[ds ^ 1], 0));
   }
   const int32_t* dei = ei;
   const int32_t* dej = ej;
