@@ -133,6 +133,8 @@ struct grest_state {
   hipEvent_t gev[2] = {};      // graph stage of the slot's update done (results on the host)
   hipEvent_t endev[2] = {};    // every kernel of the slot's update done
   hipEvent_t gate[2] = {};     // the slot's update has reached its small eigensolve
+  hipEvent_t ogate[2] = {};    // the slot's update has read its old graph for the last time
+  bool ogate_recorded[2] = {false, false};
   bool end_recorded[2] = {false, false}, gate_recorded[2] = {false, false};
   int32_t *d_ei = nullptr, *d_ej = nullptr;
   int8_t* d_sg = nullptr;
@@ -394,7 +396,8 @@ void free_all(grest_state* st) {
     if (st->gev[b]) (void)hipEventDestroy(st->gev[b]);
     if (st->endev[b]) (void)hipEventDestroy(st->endev[b]);
     if (st->gate[b]) (void)hipEventDestroy(st->gate[b]);
-    st->gev[b] = st->endev[b] = st->gate[b] = nullptr;
+    if (st->ogate[b]) (void)hipEventDestroy(st->ogate[b]);
+    st->gev[b] = st->endev[b] = st->gate[b] = st->ogate[b] = nullptr;
   }
   dfree(st->C1); dfree(st->C2); dfree(st->Gm); dfree(st->Mchol); dfree(st->H); dfree(st->F); dfree(st->Msk); dfree(st->M1buf);
   dfree(st->zg); dfree(st->dz); dfree(st->Clr);
@@ -764,17 +767,21 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
   // readers of what it overwrites: the update two calls back, which used slot ds and
   // read buffer gn as its new graph; and the previous update, which read buffer gn as its
   // old graph in its own graph stage and, for the normalised Laplacian, in its Delta Xbar.
-  // The previous update's gate (recorded before its small eigensolve, after every such
-  // read) is enough for that, and it also keeps this stage's many short kernels from
-  // queueing behind the wide ones before it.  Without a gate from the previous update
-  // (it stopped early) the stage waits for that update's end, as it does after a rejected
-  // update, whose queued work reads the scales of buffer gn.
+  // For the normalised Laplacian the stage starts once that Delta Xbar is done (ogate);
+  // otherwise at the previous update's gate, recorded before its small eigensolve, which
+  // also keeps this stage's many short kernels from queueing behind the wide ones before
+  // it.  Without either event from the previous update (it stopped early) the stage waits
+  // for that update's end, as it does after a rejected update, whose queued work reads the
+  // scales of buffer gn.
   hipStream_t gs = st->gstream;
-  st->gate_recorded[ds] = false;  // this update's gate, once it is recorded
+  st->gate_recorded[ds] = false;  // this update's events, once they are recorded
+  st->ogate_recorded[ds] = false;
   if (gs != s) {
     if (st->end_recorded[ds]) HIPCHK(hipStreamWaitEvent(gs, st->endev[ds], 0));
     if (st->prev_rejected && st->end_recorded[ds ^ 1])
       HIPCHK(hipStreamWaitEvent(gs, st->endev[ds ^ 1], 0));
+    else if (st->ogate_recorded[ds ^ 1])
+      HIPCHK(hipStreamWaitEvent(gs, st->ogate[ds ^ 1], 0));
     else if (st->gate_recorded[ds ^ 1])
       HIPCHK(hipStreamWaitEvent(gs, st->gate[ds ^ 1], 0));
     else if (st->end_recorded[ds ^ 1])
@@ -1013,6 +1020,9 @@ grest_status update_impl(grest_state* st, int64_t S, int64_t nc, const int32_t* 
     const HeavyRows hv = heavy_of(st, gn);
     launch_nlap_delta_x<T>(n, S, st->rp[st->gcur], st->col[st->gcur], (const T*)st->sc[st->gcur], st->rp[gn],
                            st->col[gn], sc_new, b.Zc, st->ldz, K, dX, st->ldz, s, &hv);
+    // the last read of the old graph (buffer gcur, which the next update's graph stage
+    // overwrites); the rest of this update reads the new graph alone
+    if (gs != s && hipEventRecord(st->ogate[ds], s) == hipSuccess) st->ogate_recorded[ds] = true;
     project();
   }
   mark(st, 4);
@@ -1510,6 +1520,7 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
     if (hipEventCreateWithFlags(&st->gev[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
     if (hipEventCreateWithFlags(&st->endev[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
     if (hipEventCreateWithFlags(&st->gate[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
+    if (hipEventCreateWithFlags(&st->ogate[b], hipEventDisableTiming) != hipSuccess) return fail(GREST_EDEVICE);
   }
   if ((rc = dalloc(&st->srows_cnt, 1)) != GREST_OK) return fail(rc);
   if (hipHostMalloc((void**)&st->pin, sizeof(Pinned) + (size_t)st->K * sizeof(double)) != hipSuccess)
