@@ -119,7 +119,8 @@ grest_status grest_validate_changes(int64_t n, int64_t n_new, int64_t n_changes,
  * stream.  The tracked pairs are unset until grest_set_pairs or grest_init_pairs.
  * Widths: 1 <= k <= 128 and k < n0; the basis width D = k + Dw with Dw = k (G-REST2),
  * k + max_new (G-REST3) or k + L (RSVD) is at most 196; every block orthonormalised by
- * CholQR2 is at most 128 wide (G-REST2/3: Dw; RSVD: k and L + P).  Otherwise GREST_EINVAL.
+ * CholQR2 is at most 128 wide (G-REST2/3: Dw; RSVD: k and L + P).  Node counts and
+ * node_capacity stay below 2^31 - 1 (node ids are int32).  Otherwise GREST_EINVAL.
  */
 grest_status grest_create(const grest_config* cfg, void* stream, int64_t n0, const int64_t* rowptr,
                           const int32_t* col, int64_t node_capacity, int64_t nnz_capacity,

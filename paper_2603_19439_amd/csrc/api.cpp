@@ -427,8 +427,8 @@ HeavyRows heavy_of(const grest_state* st, int b) { return HeavyRows{st->hrows[b]
 // Grow node-indexed buffers, keeping the current graph and basis.
 grest_status grow_nodes(grest_state* st, int64_t need) {
   int64_t cap = std::max<int64_t>(need, st->cap_n + st->cap_n / 2);
-  if (cap + 1 > (int64_t)4096 * 2048) cap = (int64_t)4096 * 2048 - 1;
-  if (cap < need) return GREST_EINVAL;  // device scan limit
+  if (cap >= INT32_MAX) cap = INT32_MAX - 1;  // node ids are int32
+  if (cap < need) return GREST_EINVAL;
   CHK(sync_all(st));
   st->ax_valid = false;  // the product buffer is reallocated below
   int64_t* rp_old = st->rp[st->gcur];
@@ -1479,7 +1479,7 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   grest_status rc = GREST_OK;
   auto fail = [&](grest_status e) { free_all(st); if (st->own_stream) (void)hipStreamDestroy(st->stream); delete st; return e; };
   int64_t capn = exact_caps ? node_capacity : std::max<int64_t>(node_capacity, n0 + 1);
-  if (capn < n0 || capn + 1 > (int64_t)4096 * 2048) return fail(GREST_EINVAL);  // device scan limit
+  if (capn < n0 || capn >= INT32_MAX) return fail(GREST_EINVAL);  // node ids are int32
   int64_t capm = exact_caps ? std::max<int64_t>(nnz_capacity, 1) : std::max<int64_t>(nnz_capacity, m0 + 1024);
   if (capm < m0) return fail(GREST_EINVAL);
   if ((rc = alloc_node_arrays(st, capn)) != GREST_OK) return fail(rc);

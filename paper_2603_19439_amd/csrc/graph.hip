@@ -90,25 +90,30 @@ __global__ void __launch_bounds__(BS) k_scan_reduce(const int64_t* in, int64_t n
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// single workgroup: exclusive scan of nb block sums (nb <= BS * 16), writes out[n] = total
+// single workgroup: exclusive scan of nb block sums in chunks of BS * 16 with a running
+// carry (one chunk up to 8.4M scanned entries), writes out[n] = total
 __global__ void __launch_bounds__(BS) k_scan_blocks(int64_t* bsum, int64_t nb, int64_t* out_total) {
   __shared__ int64_t lds[BS / GREST_WAVE];
   constexpr int IPT = 16;
-  int64_t vals[IPT];
-  int64_t acc = 0;
-  for (int q = 0; q < IPT; ++q) {
-    int64_t i = (int64_t)threadIdx.x * IPT + q;
-    vals[q] = i < nb ? bsum[i] : 0;
-    acc += vals[q];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += (int64_t)BS * IPT) {
+    int64_t vals[IPT];
+    int64_t acc = 0;
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * IPT + q;
+      vals[q] = i < nb ? bsum[i] : 0;
+      acc += vals[q];
+    }
+    int64_t tot;
+    int64_t off = carry + block_excl_scan(acc, lds, &tot);
+    for (int q = 0; q < IPT; ++q) {
+      const int64_t i = c0 + (int64_t)threadIdx.x * IPT + q;
+      if (i < nb) bsum[i] = off;
+      off += vals[q];
+    }
+    carry += tot;
   }
-  int64_t tot;
-  int64_t off = block_excl_scan(acc, lds, &tot);
-  for (int q = 0; q < IPT; ++q) {
-    int64_t i = (int64_t)threadIdx.x * IPT + q;
-    if (i < nb) bsum[i] = off;
-    off += vals[q];
-  }
-  if (threadIdx.x == 0) *out_total = tot;
+  if (threadIdx.x == 0) *out_total = carry;
 }
 
 __global__ void __launch_bounds__(BS) k_scan_final(const int64_t* in, int64_t n, const int64_t* boff,
