@@ -97,9 +97,51 @@ int size_class(const Graph& g) {
   return g.k * 64 + oct;
 }
 
+// Pinned host staging of one request's change list and test matrix: the update's copies to
+// the device then run asynchronously instead of through the runtime's staging of pageable
+// memory.  A worker reuses its buffers once the updates that read them have been synced.
+struct PinnedStage {
+  unsigned char* p = nullptr;
+  size_t cap = 0;
+  PinnedStage() = default;
+  PinnedStage(const PinnedStage&) = delete;
+  PinnedStage& operator=(const PinnedStage&) = delete;
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+  // the request's arrays in pinned memory (null where the request has none); false if the
+  // buffer cannot be grown, in which case the caller passes the request's own arrays
+  bool stage(const Request& rq, const int32_t** ei, const int32_t** ej, const int8_t** sg, const double** om) {
+    const size_t nc = rq.ei.size();
+    const size_t o_ej = nc * sizeof(int32_t), o_sg = 2 * o_ej;
+    const size_t o_om = (o_sg + nc + 7) & ~(size_t)7;
+    const size_t bytes = o_om + (rq.has_omega ? rq.omega.size() * sizeof(double) : 0);
+    if (bytes > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      const size_t want = std::max<size_t>(bytes, 2 * bytes);
+      if (hipHostMalloc((void**)&p, want) != hipSuccess) { p = nullptr; return false; }
+      cap = want;
+    }
+    if (nc) {
+      std::memcpy(p, rq.ei.data(), o_ej);
+      std::memcpy(p + o_ej, rq.ej.data(), o_ej);
+      std::memcpy(p + o_sg, rq.sg.data(), nc);
+    }
+    if (rq.has_omega) std::memcpy(p + o_om, rq.omega.data(), rq.omega.size() * sizeof(double));
+    *ei = nc ? reinterpret_cast<const int32_t*>(p) : nullptr;
+    *ej = nc ? reinterpret_cast<const int32_t*>(p + o_ej) : nullptr;
+    *sg = nc ? reinterpret_cast<const int8_t*>(p + o_sg) : nullptr;
+    *om = rq.has_omega ? reinterpret_cast<const double*>(p + o_om) : nullptr;
+    return true;
+  }
+};
+
 void worker(grest_server* sv, int lane) {
   (void)hipSetDevice(sv->device);
   const int nb = sv->max_batch;
+  std::vector<PinnedStage> pins(nb);
   std::vector<Request> rqs;
   std::vector<grest_state*> sts;
   std::vector<bool> moves;
@@ -145,18 +187,32 @@ void worker(grest_server* sv, int lane) {
     for (int i = 0; i < cnt; ++i)
       if (moves[i]) state_rebind_stream(sts[i], sv->streams[lane * nb + i]);
     std::vector<grest_status> ru(cnt, GREST_OK);
+    // each member's arrays, staged in pinned memory (the request's own arrays if staging fails)
+    struct Args {
+      const int32_t *ei, *ej;
+      const int8_t* sg;
+      const double* om;
+    };
+    std::vector<Args> args(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      const Request& rq = rqs[i];
+      Args& a = args[i];
+      if (!pins[i].stage(rq, &a.ei, &a.ej, &a.sg, &a.om)) {
+        const bool has = !rq.ei.empty();
+        a = Args{has ? rq.ei.data() : nullptr, has ? rq.ej.data() : nullptr, has ? rq.sg.data() : nullptr,
+                 rq.has_omega ? rq.omega.data() : nullptr};
+      }
+    }
     if (cnt == 1) {
       const Request& rq = rqs[0];
       const int64_t nc = (int64_t)rq.ei.size();
-      ru[0] = grest_update(sts[0], rq.n_new, nc, nc ? rq.ei.data() : nullptr, nc ? rq.ej.data() : nullptr,
-                           nc ? rq.sg.data() : nullptr, rq.has_omega ? rq.omega.data() : nullptr, GREST_HOST);
+      ru[0] = grest_update(sts[0], rq.n_new, nc, args[0].ei, args[0].ej, args[0].sg, args[0].om, GREST_HOST);
     } else {
       items.assign(cnt, grest_batch_item{});
       for (int i = 0; i < cnt; ++i) {
         const Request& rq = rqs[i];
         const int64_t nc = (int64_t)rq.ei.size();
-        items[i] = grest_batch_item{sts[i], rq.n_new, nc, nc ? rq.ei.data() : nullptr, nc ? rq.ej.data() : nullptr,
-                                    nc ? rq.sg.data() : nullptr, rq.has_omega ? rq.omega.data() : nullptr,
+        items[i] = grest_batch_item{sts[i], rq.n_new, nc, args[i].ei, args[i].ej, args[i].sg, args[i].om,
                                     GREST_HOST, GREST_OK};
       }
       (void)grest_update_batch(items.data(), cnt);  // every member's own status is in its item
