@@ -1484,8 +1484,15 @@ grest_status create_impl(const grest_config* cfg, void* stream, int64_t n0, cons
   if (capm < m0) return fail(GREST_EINVAL);
   if ((rc = alloc_node_arrays(st, capn)) != GREST_OK) return fail(rc);
   if ((rc = alloc_edge_arrays(st, capm)) != GREST_OK) return fail(rc);
-  if ((rc = alloc_change_arrays(st, 4096)) != GREST_OK) return fail(rc);
-  if ((rc = alloc_sketch_arrays(st, 1024)) != GREST_OK) return fail(rc);
+  // Room for a change list of 1/32 of the stored entries and for n0/64 nodes appended at
+  // once, so that the first updates of a stream do not reallocate these arrays (each
+  // reallocation drains the state's streams).  A low-rank state keeps two gathered basis
+  // rows per change, so it starts small and grows on demand.
+  const bool small_caps = exact_caps || cfg->proj == GREST_PROJ_LOWRANK;
+  const int64_t cap_nc0 = small_caps ? 4096 : std::max<int64_t>(4096, m0 / 32);
+  const int64_t cap_s0 = exact_caps ? 1024 : std::max<int64_t>(1024, n0 / 64);
+  if ((rc = alloc_change_arrays(st, cap_nc0)) != GREST_OK) return fail(rc);
+  if ((rc = alloc_sketch_arrays(st, cap_s0)) != GREST_OK) return fail(rc);
   const int dmax = st->D;
   const int wmax = std::max(st->Dw, std::max(st->Ls, 1));
   if ((rc = dalloc(&st->C1, (size_t)st->K * wmax)) != GREST_OK) return fail(rc);
