@@ -122,6 +122,18 @@ def spmm_bytes(n2: int, nnz: int, width: int, elem: int) -> float:
     return 4.0 * nnz + 8.0 * (n2 + 1) + 2.0 * elem * n2 * width
 
 
+def width_mix(wm: float, D: int, K: int) -> dict:
+    """Widths of the timed sparse products and their shares, from their mean width wm: with
+    the kept product of the tracked block (adjacency) an update multiplies the D - K new
+    columns and a refresh all D, so a mean strictly between the two is that mix (a mean of
+    66 at D = 96, K = 32 is 15 updates at 64 and one at 96, not 16 at 66); otherwise every
+    product has the mean width."""
+    if D - K + 1e-6 < wm < D - 1e-6:
+        f_full = (wm - (D - K)) / K
+        return {D - K: 1.0 - f_full, D: f_full}
+    return {int(round(wm)): 1.0}
+
+
 def gather_ceiling(res, K):
     """Average time of grest_calib_gather (random gathers of whole rows, the column ids from
     a hash) at the timed updates' mean row and entry counts, the entries spread evenly over
@@ -135,11 +147,7 @@ def gather_ceiling(res, K):
     n2 = int(round(sum(s[0] for s in sizes) / len(sizes)))
     nnz = int(round(sum(s[1] for s in sizes) / len(sizes)))
     D = int(sizes[0][2])
-    if D - K + 1e-6 < wm < D - 1e-6:  # the kept product: D - K new columns, all D on a refresh
-        f_full = (wm - (D - K)) / K
-        mix = {D - K: 1.0 - f_full, D: f_full}
-    else:
-        mix = {int(round(wm)): 1.0}
+    mix = width_mix(wm, D, K)
     ld = (D + 3) // 4 * 4
     Z = torch.randn(n2, ld, device="cuda")
     Y = torch.empty(n2, ld, device="cuda")
