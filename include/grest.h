@@ -115,7 +115,9 @@ grest_status grest_validate_changes(int64_t n, int64_t n_new, int64_t n_changes,
  * host pointers to a symmetric CSR with both triangles, sorted columns, no self-loops
  * and no duplicates (checked: GREST_EINVAL).  node_capacity / nnz_capacity reserve
  * room for growth (0 = automatic; buffers grow on demand with a device
- * synchronisation).  stream: a hipStream_t of that device, or NULL for a private
+ * synchronisation).  The change-list buffers start sized for a change list of 1/32 of
+ * the stored entries (4,096 changes for a low-rank state) and the sketch buffers for
+ * n0/64 appended nodes; they too grow on demand.  stream: a hipStream_t of that device, or NULL for a private
  * stream.  The tracked pairs are unset until grest_set_pairs or grest_init_pairs.
  * Widths: 1 <= k <= 128 and k < n0; the basis width D = k + Dw with Dw = k (G-REST2),
  * k + max_new (G-REST3) or k + L (RSVD) is at most 196; every block orthonormalised by
