@@ -534,8 +534,8 @@ void launch_delta_group(const uint64_t* kin, const int8_t* vin, int64_t items, i
   k_delta_sort_short<<<grid_for(n2), BS, 0, s>>>(n2, dptr, kout, vout, list, status);
   // rows longer than SHORT_ROW hold more than SHORT_ROW of the items each
   const int64_t bound = std::min<int64_t>(n2, items / (SHORT_ROW + 1) + 1);
-  const size_t lds = (size_t)DELTA_LONG_MAX * (sizeof(uint64_t) + sizeof(int8_t));
-  static const bool attr = [lds] {
+  constexpr size_t lds = (size_t)DELTA_LONG_MAX * (sizeof(uint64_t) + sizeof(int8_t));
+  static const bool attr = [] {
     (void)hipFuncSetAttribute((const void*)k_delta_sort_long, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return true;
   }();

@@ -938,9 +938,9 @@ bool aligned16(const T* p, int64_t ld) {
 template <typename Tin, typename Tc, bool SYM, int PA, int PB>
 void tnw_launch(dim3 grid, hipStream_t s, int64_t n, int64_t rpc, const Tin* A, int64_t lda, int a, const Tin* B,
                 int64_t ldb, int b, double* partial) {
-  const size_t lds = (size_t)PA * PB * 256 * sizeof(double);
+  constexpr size_t lds = (size_t)PA * PB * 256 * sizeof(double);
   if (lds > 65536) {  // once per instance; function-local statics initialise thread-safely
-    static const bool attr = [lds] {
+    static const bool attr = [] {
       (void)hipFuncSetAttribute((const void*)k_tnw<Tin, Tc, SYM, PA, PB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       return true;
@@ -1066,9 +1066,9 @@ static void pip_launch(int g, int64_t n, int64_t rpc, const T* X, int64_t ldx, i
                        int w, double* partC, double* partG, const int32_t* rows, const int64_t* nrows,
                        hipStream_t s) {
   constexpr int NTG = TWC * (TWC + 1) / 2;
-  const size_t lds = (size_t)(TXC * TWC + NTG) * 256 * sizeof(double);
+  constexpr size_t lds = (size_t)(TXC * TWC + NTG) * 256 * sizeof(double);
   if (lds > 65536) {
-    static const bool attr = [lds] {
+    static const bool attr = [] {
       (void)hipFuncSetAttribute((const void*)k_pip<T, Tcx, TXC, TWC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
       return true;

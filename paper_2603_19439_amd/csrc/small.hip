@@ -1182,7 +1182,6 @@ __device__ __forceinline__ void rank_values(const double* sev, int n, int (&rk)[
 #pragma unroll
   for (int cj = 0; cj < NCOL; ++cj) {
     const int lmax = n - GREST_WAVE * cj < GREST_WAVE ? n - GREST_WAVE * cj : GREST_WAVE;
-#pragma unroll 4
     for (int l = 0; l < lmax; ++l) {
       const int j = GREST_WAVE * cj + l;
       const double tj = readlane_d(tv[cj], l);
